@@ -79,6 +79,8 @@ def _declare(L):
     L.or_rpy_blocks.argtypes = [_dp, C.c_int, C.c_double, C.c_double, _dp, _dp, _dp, _dp]
     L.or_rpy_apply.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, _dp, _dp, C.c_int64]
     L.or_rpy_matrix.argtypes = [C.c_int64, _dp, C.c_double, C.c_double, _dp]
+    L.or_rpy_apply_targets.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_int64, _i64p, _dp,
+                                       _dp, C.c_int64]
     L.or_steric.argtypes = [C.c_int64, _dp, _i64p, C.c_double, C.c_double, C.c_double, _dp]
     L.or_moment.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
     L.or_internal_forces.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp, _dp]
@@ -159,6 +161,16 @@ def rpy_apply(Y, F, T, a, eta, nthreads=0):
     S = Y.shape[0]
     V, W = np.zeros((S, 3)), np.zeros((S, 3))
     lib().or_rpy_apply(S, _p(Y), _p(F), _p(T), a, eta, _p(V), _p(W), int(nthreads))
+    return V, W
+
+
+def rpy_apply_targets(Y, F, T, a, eta, idx, nthreads=0):
+    """(V, Omega) at the targets idx only; arrays [S, 3], result [len(idx), 3]."""
+    Y, F, T = _f64(Y), _f64(F), _f64(T)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    V, W = np.zeros((len(idx), 3)), np.zeros((len(idx), 3))
+    lib().or_rpy_apply_targets(Y.shape[0], _p(Y), _p(F), _p(T), a, eta, len(idx), idx.ctypes.data_as(_i64p),
+                               _p(V), _p(W), int(nthreads))
     return V, W
 
 

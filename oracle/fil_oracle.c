@@ -221,6 +221,31 @@ void or_rpy_apply(int64_t S, const double* Y, const double* F, const double* T, 
     }
 }
 
+/* The same sum for a subset of targets idx[0..ntgt) only (sampled checks at full size);
+ * V, W are [ntgt][3]. */
+void or_rpy_apply_targets(int64_t S, const double* Y, const double* F, const double* T, double a, double eta,
+                          int64_t ntgt, const int64_t* idx, double* V, double* W, int64_t nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads((int)nthreads);
+#pragma omp parallel for schedule(static)
+#endif
+    for (int64_t i = 0; i < ntgt; i++) {
+        int64_t n = idx[i];
+        double v[3] = {0, 0, 0}, w[3] = {0, 0, 0};
+        for (int64_t m = 0; m < S; m++) {
+            double r[3] = {Y[3 * n] - Y[3 * m], Y[3 * n + 1] - Y[3 * m + 1], Y[3 * n + 2] - Y[3 * m + 2]};
+            double Mtt[9], Mtr[9], Mrt[9], Mrr[9], y1[3], y2[3], y3[3], y4[3];
+            or_rpy_blocks(r, n == m, a, eta, Mtt, Mtr, Mrt, Mrr);
+            mat_vec(Mtt, F + 3 * m, y1);
+            mat_vec(Mtr, T + 3 * m, y2);
+            mat_vec(Mrt, F + 3 * m, y3);
+            mat_vec(Mrr, T + 3 * m, y4);
+            for (int k = 0; k < 3; k++) { v[k] += y1[k] + y2[k]; w[k] += y3[k] + y4[k]; }
+        }
+        for (int k = 0; k < 3; k++) { V[3 * i + k] = v[k]; W[3 * i + k] = w[k]; }
+    }
+}
+
 /* Assembled 6S x 6S grand mobility (row-major), unknowns ordered (F_1..F_S, T_1..T_S). */
 void or_rpy_matrix(int64_t S, const double* Y, double a, double eta, double* Mg) {
     int64_t n6 = 6 * S;

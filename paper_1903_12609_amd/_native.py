@@ -1,0 +1,84 @@
+"""ctypes binding of libfil.so (argument marshalling only).
+
+Every numerical step runs in the HIP library.  If the library has not been
+built this module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfil.so")
+
+FIL_OK = 0
+STATUS = {0: "FIL_OK", -1: "FIL_EINVAL", -2: "FIL_EHIP", -3: "FIL_ENOCONV", -4: "FIL_ENONFINITE", -5: "FIL_ENOMEM"}
+PREC = {"f64": 0, "f32tile": 1}
+
+
+class FilError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+_lib = None
+_vp = C.c_void_p
+_i64 = C.c_int64
+_d = C.c_double
+_i = C.c_int
+
+
+class Params(C.Structure):
+    _fields_ = [("a", _d), ("eta", _d), ("dL", _d), ("KB", _d), ("KT", _d), ("chi", _d), ("FS", _d),
+                ("grav", _d * 3), ("dt", _d), ("tol", _d), ("kmax", C.c_int32), ("prec", C.c_int32),
+                ("K0", _d), ("kw", _d), ("omega", _d)]
+
+
+class StepReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("mobility_applies", C.c_int32), ("converged", C.c_int32),
+                ("pad", C.c_int32), ("resid", _d)]
+
+
+def _declare(L):
+    L.fil_last_error.restype = C.c_char_p
+    L.fil_rpy_workspace_bytes.argtypes = [_i64, _i]
+    L.fil_rpy_workspace_bytes.restype = _i64
+    L.fil_rpy_mobility_apply.argtypes = [_i64, _vp, _vp, _vp, _d, _d, _i, _vp, _vp, _vp, _i64, _vp]
+    L.fil_filament_internal_forces.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _d, _d, _d, _vp, _vp, _vp]
+    for name in ("fil_rpy_batched_workspace_bytes",):
+        if hasattr(L, name):
+            getattr(L, name).argtypes = [_i64, _vp, _i]
+            getattr(L, name).restype = _i64
+    if hasattr(L, "fil_rpy_mobility_apply_batched"):
+        L.fil_rpy_mobility_apply_batched.argtypes = [_i64, _vp, _vp, _vp, _vp, _d, _d, _i, _vp, _vp, _vp, _i64,
+                                                     _vp]
+    if hasattr(L, "fil_create"):
+        L.fil_create.argtypes = [C.POINTER(Params), _i64, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)]
+        L.fil_destroy.argtypes = [_vp]
+        L.fil_destroy.restype = None
+        L.fil_bdf2_step.argtypes = [_vp, _vp]
+        L.fil_broyden_begin.argtypes = [_vp, _vp, _vp]
+        L.fil_broyden_update.argtypes = [_vp, _vp, _vp]
+        L.fil_residual.argtypes = [_vp, _vp, _vp]
+        L.fil_get_state.argtypes = [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_i64),
+                                    C.POINTER(_d), C.POINTER(_i64)]
+        L.fil_set_stream.argtypes = [_vp, _vp]
+
+
+def lib():
+    """Load libfil.so; raises if it is missing (build it with paper_1903_12609_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfil.so is not built (run `python -m paper_1903_12609_amd.build`); "
+                               "there is no fallback path")
+        _lib = C.CDLL(LIB_PATH)
+        _declare(_lib)
+    return _lib
+
+
+def check(rc):
+    if rc != FIL_OK:
+        raise FilError(rc, lib().fil_last_error().decode())
+    return rc

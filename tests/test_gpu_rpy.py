@@ -1,0 +1,87 @@
+"""GPU parity of the RPY mobility apply against the FP64 oracle (Sec. 2.7.1)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_12609_amd import synth
+
+from gpu_util import dev, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12      # relative L2, FP64 pair math
+F32_TOL = 1e-5       # relative L2 bound for the FP32-tile path (error is reported, not tuned)
+
+
+def _apply(Y, F, T, prec, a=1.0, eta=1.0):
+    import paper_1903_12609_amd as fil
+    V, W = fil.rpy_mobility_apply(dev(Y), dev(F), dev(T), a, eta, prec)
+    return host(V), host(W)
+
+
+def _cases():
+    rng = np.random.default_rng(0)
+    yield "single", np.zeros((1, 3)), rng.standard_normal((1, 3)), rng.standard_normal((1, 3)), 1.0, 1.0
+    Y = np.array([[0, 0, 0], [2.2, 0, 0.0]])
+    yield "pair", Y, rng.standard_normal((2, 3)), rng.standard_normal((2, 3)), 1.0, 1.0
+    for S in (37, 300, 1037):
+        Y, F, T = synth.rpy_throughput_inputs(S, seed=S)
+        yield "structured%d" % S, Y, F, T, 1.0, 1.0
+    Y = rng.uniform(0, 9.0, (257, 3))                 # dense cloud: many overlapping pairs
+    yield "overlapping257", Y, rng.standard_normal((257, 3)), rng.standard_normal((257, 3)), 1.0, 1.0
+    Y = rng.uniform(0, 60.0, (777, 3))
+    yield "cloud777_a0.7_eta2.5", Y, rng.standard_normal((777, 3)), rng.standard_normal((777, 3)), 0.7, 2.5
+    w = synth.sediment_suspension()
+    rng2 = np.random.default_rng(3)
+    yield "sediment2000", w.Y, rng2.standard_normal((w.S, 3)), rng2.standard_normal((w.S, 3)), 1.0, 1.0
+
+
+@pytest.mark.parametrize("case", list(_cases()), ids=lambda c: c[0])
+def test_rpy_f64_parity(case):
+    name, Y, F, T, a, eta = case
+    print("case", name, Y.shape[0], flush=True)
+    V0, W0 = oracle.rpy_apply(Y, F, T, a, eta, nthreads=8)
+    V, W = _apply(Y, F, T, "f64", a, eta)
+    assert rel_l2(V, V0) <= F64_TOL and rel_l2(W, W0) <= F64_TOL, (rel_l2(V, V0), rel_l2(W, W0))
+
+
+@pytest.mark.parametrize("case", list(_cases()), ids=lambda c: c[0])
+def test_rpy_f32tile_error_bound(case):
+    name, Y, F, T, a, eta = case
+    print("case", name, Y.shape[0], flush=True)
+    V0, W0 = oracle.rpy_apply(Y, F, T, a, eta, nthreads=8)
+    V, W = _apply(Y, F, T, "f32tile", a, eta)
+    ev, ew = rel_l2(V, V0), rel_l2(W, W0)
+    print("f32tile rel L2 V %.3e W %.3e" % (ev, ew))
+    assert np.isfinite(V).all() and np.isfinite(W).all()
+    assert ev <= F32_TOL and ew <= F32_TOL
+
+
+@pytest.mark.parametrize("S", [16000, 32000])
+def test_rpy_full_size_sampled(S):
+    """Full-size applies (the launch configuration the benchmark times) checked
+    on sampled targets the oracle computes one by one."""
+    print("full size", S, flush=True)
+    Y, F, T = synth.rpy_throughput_inputs(S, seed=7)
+    idx = np.unique(np.concatenate([[0, 1, S // 2, S - 2, S - 1], np.random.default_rng(1).integers(0, S, 59)]))
+    v0, w0 = oracle.rpy_apply_targets(Y, F, T, 1.0, 1.0, idx, nthreads=8)
+    V, W = _apply(Y, F, T, "f64")
+    assert rel_l2(V[idx], v0) <= F64_TOL and rel_l2(W[idx], w0) <= F64_TOL
+    V, W = _apply(Y, F, T, "f32tile")
+    print("f32tile sampled rel L2 V %.3e W %.3e" % (rel_l2(V[idx], v0), rel_l2(W[idx], w0)))
+    assert rel_l2(V[idx], v0) <= F32_TOL and rel_l2(W[idx], w0) <= F32_TOL
+
+
+def test_rpy_deterministic_and_empty():
+    import torch
+    import paper_1903_12609_amd as fil
+    Y, F, T = synth.rpy_throughput_inputs(5000, seed=9)
+    Yd, Fd, Td = dev(Y), dev(F), dev(T)
+    for prec in ("f64", "f32tile"):
+        V1, W1 = fil.rpy_mobility_apply(Yd, Fd, Td, 1.0, 1.0, prec)
+        V2, W2 = fil.rpy_mobility_apply(Yd, Fd, Td, 1.0, 1.0, prec)
+        torch.cuda.synchronize()
+        assert torch.equal(V1, V2) and torch.equal(W1, W2)
+    z = torch.zeros((3, 0), dtype=torch.float64, device="cuda")
+    V, W = fil.rpy_mobility_apply(z, z, z)
+    assert V.shape == (3, 0)

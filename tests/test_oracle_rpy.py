@@ -216,3 +216,11 @@ def test_steric_quartic_profile_and_neighbour_exclusion():
     x = lambda r: (r * r - 4 * a * a) / (4 * a * a * (chi * chi - 1))
     assert math.isclose(f1 / f2, ((1 - x(d)) ** 4 * d) / ((1 - x(2.15)) ** 4 * 2.15), rel_tol=1e-13)
     assert np.allclose(FB.sum(axis=0), 0, atol=1e-14)   # pairwise equal and opposite
+
+
+def test_sampled_targets_match_full_apply():
+    Y, F, T = synth.rpy_throughput_inputs(400, seed=5)
+    V, W = oracle.rpy_apply(Y, F, T, 1.0, 1.0)
+    idx = np.array([0, 3, 17, 399, 200])
+    v, w = oracle.rpy_apply_targets(Y, F, T, 1.0, 1.0, idx)
+    assert np.array_equal(v, V[idx]) and np.array_equal(w, W[idx])
