@@ -70,6 +70,15 @@ int64_t fil_rpy_workspace_bytes(int64_t S, int prec);
 int fil_rpy_mobility_apply(int64_t S, const double* Y, const double* F, const double* T, double a, double eta,
                            int prec, double* V, double* Omega, void* work, int64_t work_bytes, void* stream);
 
+/* Batched form: nsusp independent suspensions in one launch; suspension i owns
+ * segments susp_off[i] .. susp_off[i+1]-1 and interacts only with itself.
+ * susp_off is a HOST int64[nsusp+1] (non-decreasing, susp_off[0] = 0);
+ * arrays as above over S = susp_off[nsusp] segments. */
+int64_t fil_rpy_batched_workspace_bytes(int64_t nsusp, const int64_t* susp_off, int prec);
+int fil_rpy_mobility_apply_batched(int64_t nsusp, const int64_t* susp_off, const double* Y, const double* F,
+                                   const double* T, double a, double eta, int prec, double* V, double* Omega,
+                                   void* work, int64_t work_bytes, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Filament mechanics                                                        */
 /* ------------------------------------------------------------------------ */
@@ -88,6 +97,87 @@ int fil_rpy_mobility_apply(int64_t S, const double* Y, const double* F, const do
 int fil_filament_internal_forces(int64_t M, int64_t S, const int64_t* fil_off, const double* q,
                                  const double* Lambda, const double* kappa, double dL, double KB, double KT,
                                  double* F, double* T, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* The implicit step (Sec. 2.9.3 system, Alg. 2 bad Broyden with the explicit */
+/* block-diagonal J0 of Sec. 3.2.2 / Appendix B.2).                           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double a, eta, dL, KB, KT;
+    double chi, FS;             /* steric barrier (Sec. 2.6); FS = 0 switches it off */
+    double grav[3];             /* external force on every segment */
+    double dt, tol;             /* time step; stop when max|f| / a <= tol */
+    int32_t kmax;               /* Broyden iteration cap per step (<= 256) */
+    int32_t prec;               /* fil_prec of the mobility apply */
+    double K0, kw, omega;       /* kappa_nu(s,t) = K0 sin(kw s - omega t + phase_f) */
+} fil_params;
+
+typedef struct {
+    int32_t iters;              /* Broyden updates taken */
+    int32_t mobility_applies;   /* residual evaluations (one mobility apply each) */
+    int32_t converged;          /* 1 if max|f|/a <= tol */
+    int32_t pad;
+    double resid;               /* final max|f| / a */
+} fil_step_report;
+
+typedef struct fil_sim fil_sim;
+
+/* Creates a simulation of nsusp independent suspensions on the current device.
+ * All arrays here are HOST pointers, copied in:
+ *   susp_fil_off int64[nsusp+1]   filaments of suspension i: susp_fil_off[i] .. [i+1]-1
+ *   fil_seg_off  int64[M+1]       segments of filament f (M = susp_fil_off[nsusp])
+ *   Y0  double[S][3], q0 double[S][4]   initial positions (constraints met) and unit quaternions
+ *   phase  double[M] or NULL      per-filament phase of the preferred curvature
+ *   tether int32[M] or NULL       1 = base clamped at its initial Y_1 and q_1
+ * The library allocates all device state and workspace here (FIL_ENOMEM on failure). */
+int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, const int64_t* fil_seg_off,
+               const double* Y0, const double* q0, const double* phase, const int32_t* tether, fil_sim** out);
+void fil_destroy(fil_sim* sim);
+
+/* One time step: warm start, J0 and its inverse, Broyden iterations on the
+ * device (one mobility apply each), then q^{j+1} = exp(u) . q^j, the robot-arm
+ * positions and the history shift.  The first step is BDF1, later ones BDF2.
+ * report: HOST fil_step_report[nsusp] (may be NULL).  Synchronises the stream
+ * once per Broyden iteration to test convergence.  Returns FIL_ENOCONV or
+ * FIL_ENONFINITE if a suspension failed; its state is then left at step j. */
+int fil_bdf2_step(fil_sim* sim, fil_step_report* report);
+
+/* One bad-Broyden update (Alg. 2) on the simulation's current iterate, given
+ * the residual f_new = f(X_{k+1}) (device double[6S]):
+ *   c_{k+1} = -H_k f_new / |f_new - f_k|,  d_{k+1} = (f_new - f_k) / |f_new - f_k|,
+ *   dX_out = -H_{k+1} f_new,  X += dX_out
+ * with H_k = J0^{-1} + sum_i c_i d_i^T.  Call fil_broyden_begin first (it
+ * evaluates J0 at X0, inverts it and sets f_0). */
+/* fil_broyden_begin: X <- X0 (device double[6S]), f_0 = f(X0) (copied to f0_out
+ * if not NULL), J0 at X0 and its inverse, then the first step X <- X0 - J0^{-1} f_0.
+ * fil_broyden_update: the caller evaluates f_new = f(X) at the current iterate
+ * (fil_residual with X from fil_get_state) and passes it in; dX_out (device
+ * double[6S]) may be NULL.  At most kmax - 1 updates follow one begin. */
+int fil_broyden_begin(fil_sim* sim, const double* X0, double* f0_out);
+int fil_broyden_update(fil_sim* sim, const double* f_new, double* dX_out);
+/* Residual f(X) of the reduced system at the current step (device arrays). */
+int fil_residual(fil_sim* sim, const double* X, double* f_out);
+
+/* Device pointers to the committed state of step j (Y^j [3][S], q^j [4][S],
+ * X^j [6S]) and to the current Broyden iterate X [6S]; valid until fil_destroy.
+ * Any pointer argument may be NULL. */
+int fil_get_state(fil_sim* sim, const double** Y, const double** q, const double** Xj, const double** X, int64_t* S,
+                  double* t, int64_t* step);
+
+/* Synchronising copy of the committed state to HOST buffers in the caller's
+ * array-of-structures layout: Y double[S][3], q double[S][4], Xj double[6S];
+ * any may be NULL. */
+int fil_read_state(fil_sim* sim, double* Y, double* q, double* Xj);
+
+/* Timing of the mobility pair kernel inside fil_bdf2_step: when enabled, HIP
+ * events on the simulation's stream bracket every launch of the main pair
+ * kernel; fil_get_timing returns the summed duration (ms) and the launch count
+ * since the last fil_set_timing call.  Enabling resets both counters. */
+int fil_set_timing(fil_sim* sim, int enable);
+int fil_get_timing(fil_sim* sim, double* rpy_ms, int64_t* rpy_launches);
+
+/* Stream the simulation enqueues on (set before stepping). */
+int fil_set_stream(fil_sim* sim, void* stream);
 
 #ifdef __cplusplus
 }

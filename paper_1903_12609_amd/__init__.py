@@ -9,7 +9,8 @@ from __future__ import annotations
 
 from ._native import FilError, PREC, check, lib  # noqa: F401
 
-__all__ = ["FilError", "rpy_mobility_apply", "rpy_workspace_bytes", "filament_internal_forces"]
+__all__ = ["FilError", "Sim", "rpy_mobility_apply", "rpy_mobility_apply_batched", "rpy_workspace_bytes",
+           "filament_internal_forces"]
 
 
 def _stream():
@@ -66,3 +67,147 @@ def filament_internal_forces(fil_off, q, Lam, kappa, dL, KB, KT, F, T):
     check(lib().fil_filament_internal_forces(M, S, _ptr(fil_off), _ptr(q), _ptr(Lam), _ptr(kappa), float(dL),
                                              float(KB), float(KT), _ptr(F), _ptr(T), _stream()))
     return F, T
+
+
+def rpy_mobility_apply_batched(susp_off, Y, F, T, a=1.0, eta=1.0, prec="f64", V=None, W=None):
+    """Independent suspensions in one persistent launch; susp_off: host int sequence [nsusp+1]."""
+    import ctypes
+    import numpy as np
+    import torch
+    off = np.ascontiguousarray(susp_off, dtype=np.int64)
+    S = int(off[-1])
+    for n, t in (("Y", Y), ("F", F), ("T", T)):
+        _check_soa(n, t, 3, S)
+    V = torch.empty_like(Y) if V is None else V
+    W = torch.empty_like(Y) if W is None else W
+    nb = int(lib().fil_rpy_batched_workspace_bytes(len(off) - 1, off.ctypes.data_as(ctypes.c_void_p), PREC[prec]))
+    work = torch.empty(max(nb, 1), dtype=torch.uint8, device=Y.device)
+    check(lib().fil_rpy_mobility_apply_batched(len(off) - 1, off.ctypes.data_as(ctypes.c_void_p), _ptr(Y), _ptr(F),
+                                               _ptr(T), float(a), float(eta), PREC[prec], _ptr(V), _ptr(W),
+                                               _ptr(work), work.numel(), _stream()))
+    return V, W
+
+
+class _DevView:
+    """Zero-copy torch view of a library-owned device array."""
+
+    def __init__(self, ptr, shape):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": "<f8", "data": (int(ptr), False),
+                                         "version": 2, "strides": None}
+
+
+class Sim:
+    """A simulation of one or more independent suspensions on the GPU.
+
+    fil_off [M+1] segment offsets; Y0 [S,3], q0 [S,4] the initial configuration;
+    params: a, eta, dL, KB, KT, chi, FS, grav, dt, tol, kmax, K0, kw, omega and
+    optional phase [M], tether [M]; susp_fil_off [nsusp+1] groups filaments
+    into suspensions (default: one suspension).  prec: "f64" or "f32tile".
+    """
+
+    def __init__(self, fil_off, Y0, q0, params, susp_fil_off=None, prec="f64"):
+        import ctypes
+        import numpy as np
+        from ._native import Params
+        self.fil_off = np.ascontiguousarray(fil_off, dtype=np.int64)
+        M = len(self.fil_off) - 1
+        self.M, self.S = M, int(self.fil_off[-1])
+        sfo = np.ascontiguousarray([0, M] if susp_fil_off is None else susp_fil_off, dtype=np.int64)
+        self.susp_fil_off = sfo
+        self.nsusp = len(sfo) - 1
+        P = Params()
+        P.a, P.eta, P.dL = params.get("a", 1.0), params.get("eta", 1.0), params.get("dL", 2.2)
+        P.KB, P.KT = params.get("KB", 1.0), params.get("KT", params.get("KB", 1.0))
+        P.chi, P.FS = params.get("chi", 1.1), params.get("FS", 0.0)
+        g = params.get("grav", (0.0, 0.0, 0.0))
+        P.grav[0], P.grav[1], P.grav[2] = g
+        P.dt, P.tol, P.kmax = params["dt"], params.get("tol", 1e-6), int(params.get("kmax", 100))
+        P.prec = PREC[prec]
+        P.K0, P.kw, P.omega = params.get("K0", 0.0), params.get("kw", 0.0), params.get("omega", 0.0)
+        self.params = P
+        Y0 = np.ascontiguousarray(Y0, dtype=np.float64).reshape(self.S, 3)
+        q0 = np.ascontiguousarray(q0, dtype=np.float64).reshape(self.S, 4)
+        ph = params.get("phase")
+        ph = None if ph is None else np.ascontiguousarray(ph, dtype=np.float64)
+        th = params.get("tether")
+        th = None if th is None else np.ascontiguousarray(th, dtype=np.int32)
+        vp = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        check(lib().fil_create(ctypes.byref(P), self.nsusp, vp(sfo), vp(self.fil_off), vp(Y0), vp(q0), vp(ph),
+                               vp(th), ctypes.byref(h)))
+        self._h = h
+        check(lib().fil_set_stream(h, _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fil_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, raise_on_fail=True):
+        """One implicit step; returns per-suspension reports (dicts)."""
+        import ctypes
+        from ._native import StepReport
+        reps = (StepReport * self.nsusp)()
+        rc = lib().fil_bdf2_step(self._h, reps)
+        out = [dict(iters=r.iters, applies=r.mobility_applies, converged=bool(r.converged), resid=r.resid)
+               for r in reps]
+        if rc != 0 and raise_on_fail:
+            check(rc)
+        return out if rc == 0 else (rc, out)
+
+    def read_state(self):
+        """(Y [S,3], q [S,4], X^j [6S]) as numpy arrays (synchronising)."""
+        import ctypes
+        import numpy as np
+        Y, q, X = np.zeros((self.S, 3)), np.zeros((self.S, 4)), np.zeros(6 * self.S)
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        check(lib().fil_read_state(self._h, vp(Y), vp(q), vp(X)))
+        return Y, q, X
+
+    def time_step(self):
+        import ctypes
+        t, st = ctypes.c_double(), ctypes.c_int64()
+        check(lib().fil_get_state(self._h, None, None, None, None, None, ctypes.byref(t), ctypes.byref(st)))
+        return t.value, st.value
+
+    def iterate(self):
+        """Zero-copy view (torch, [6S]) of the current Broyden iterate X."""
+        import ctypes
+        import torch
+        x = ctypes.c_void_p()
+        check(lib().fil_get_state(self._h, None, None, None, ctypes.byref(x), None, None, None))
+        return torch.as_tensor(_DevView(x.value, (6 * self.S,)), device="cuda")
+
+    def set_timing(self, enable=True):
+        check(lib().fil_set_timing(self._h, int(enable)))
+
+    def timing(self):
+        """(summed ms, launches) of the mobility pair kernel since set_timing."""
+        import ctypes
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        check(lib().fil_get_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def residual(self, X):
+        import torch
+        f = torch.empty(6 * self.S, dtype=torch.float64, device="cuda")
+        check(lib().fil_residual(self._h, _ptr(X), _ptr(f)))
+        return f
+
+    def broyden_begin(self, X0):
+        import torch
+        f0 = torch.empty(6 * self.S, dtype=torch.float64, device="cuda")
+        check(lib().fil_broyden_begin(self._h, _ptr(X0), _ptr(f0)))
+        return f0
+
+    def broyden_update(self, f_new):
+        import torch
+        dX = torch.empty(6 * self.S, dtype=torch.float64, device="cuda")
+        check(lib().fil_broyden_update(self._h, _ptr(f_new), _ptr(dX)))
+        return dX

@@ -61,9 +61,12 @@ def _declare(L):
         L.fil_broyden_begin.argtypes = [_vp, _vp, _vp]
         L.fil_broyden_update.argtypes = [_vp, _vp, _vp]
         L.fil_residual.argtypes = [_vp, _vp, _vp]
-        L.fil_get_state.argtypes = [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_i64),
-                                    C.POINTER(_d), C.POINTER(_i64)]
+        L.fil_get_state.argtypes = [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
+                                    C.POINTER(_i64), C.POINTER(_d), C.POINTER(_i64)]
+        L.fil_read_state.argtypes = [_vp, _vp, _vp, _vp]
         L.fil_set_stream.argtypes = [_vp, _vp]
+        L.fil_set_timing.argtypes = [_vp, _i]
+        L.fil_get_timing.argtypes = [_vp, C.POINTER(_d), C.POINTER(_i64)]
 
 
 def lib():

@@ -40,6 +40,40 @@ int fil_rpy_mobility_apply(int64_t S, const double* Y, const double* F, const do
     return rpy_launch(p, Y, F, T, a, eta, V, Omega, work, (hipStream_t)stream);
 }
 
+int64_t fil_rpy_batched_workspace_bytes(int64_t nsusp, const int64_t* susp_off, int prec) {
+    if (nsusp < 1 || !susp_off || susp_off[0] != 0 || (prec != FIL_PREC_F64 && prec != FIL_PREC_F32TILE)) return -1;
+    for (int64_t i = 0; i < nsusp; i++)
+        if (susp_off[i + 1] < susp_off[i]) return -1;
+    return (int64_t)rpy_batch_plan(nsusp, susp_off, prec).total();
+}
+
+int fil_rpy_mobility_apply_batched(int64_t nsusp, const int64_t* susp_off, const double* Y, const double* F,
+                                   const double* T, double a, double eta, int prec, double* V, double* Omega,
+                                   void* work, int64_t work_bytes, void* stream) {
+    FIL_CHECK_ARG(nsusp >= 1 && susp_off && susp_off[0] == 0, "fil_rpy_mobility_apply_batched: bad offsets");
+    for (int64_t i = 0; i < nsusp; i++)
+        FIL_CHECK_ARG(susp_off[i + 1] >= susp_off[i], "fil_rpy_mobility_apply_batched: offsets must not decrease");
+    FIL_CHECK_ARG(prec == FIL_PREC_F64 || prec == FIL_PREC_F32TILE,
+                  "fil_rpy_mobility_apply_batched: unknown precision");
+    FIL_CHECK_ARG(std::isfinite(a) && a > 0 && std::isfinite(eta) && eta > 0,
+                  "fil_rpy_mobility_apply_batched: a and eta must be finite and > 0");
+    const int64_t S = susp_off[nsusp];
+    if (S == 0) return FIL_OK;
+    FIL_CHECK_ARG(Y && F && T && V && Omega, "fil_rpy_mobility_apply_batched: null array");
+    FIL_CHECK_ARG(V != Omega && V != Y && V != F && V != T && Omega != Y && Omega != F && Omega != T,
+                  "fil_rpy_mobility_apply_batched: outputs alias inputs");
+    const RpyBatchPlan p = rpy_batch_plan(nsusp, susp_off, prec);
+    FIL_CHECK_ARG(work && work_bytes >= (int64_t)p.total(),
+                  "fil_rpy_mobility_apply_batched: workspace smaller than fil_rpy_batched_workspace_bytes()");
+    int rc = rpy_batch_upload(p, work, (hipStream_t)stream);
+    if (rc) return rc;
+    rc = rpy_batch_launch(p, Y, F, T, a, eta, V, Omega, work, (hipStream_t)stream);
+    if (rc) return rc;
+    // the host-side lists must outlive the asynchronous upload
+    FIL_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    return FIL_OK;
+}
+
 int fil_filament_internal_forces(int64_t M, int64_t S, const int64_t* fil_off, const double* q,
                                  const double* Lambda, const double* kappa, double dL, double KB, double KT,
                                  double* F, double* T, void* stream) {

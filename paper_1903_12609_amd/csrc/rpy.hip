@@ -20,56 +20,24 @@
 //     float and then added into double accumulators.
 //   * Overlapping pairs (r < 2a, the self pair included) take a rarely executed
 //     branch with the regularised forms; the far-field weights are zeroed there.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace fil {
 
 constexpr int kRpyBlock = 256;
+constexpr int kLdsSources = 256;  // source records staged in LDS per block on the small-size path
 
 // ------------------------------------------------------------------ packing
-// FP64 source record: Y(3) F(3) T(3) TxY(3) FxY(3) pad -> 16 doubles (128 B)
-__global__ void __launch_bounds__(256) rpy_pack_f64(int64_t S, const double* __restrict__ Y,
-                                                   const double* __restrict__ F, const double* __restrict__ T,
-                                                   double* __restrict__ pk) {
+__global__ void __launch_bounds__(256) rpy_pack(int64_t S, int prec, const double* __restrict__ Y,
+                                               const double* __restrict__ F, const double* __restrict__ T,
+                                               void* __restrict__ pk) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= S) return;
-    const double y0 = Y[m], y1 = Y[S + m], y2 = Y[2 * S + m];
-    const double f0 = F[m], f1 = F[S + m], f2 = F[2 * S + m];
-    const double t0 = T[m], t1 = T[S + m], t2 = T[2 * S + m];
-    double2* o = reinterpret_cast<double2*>(pk + 16 * m);
-    o[0] = make_double2(y0, y1);
-    o[1] = make_double2(y2, f0);
-    o[2] = make_double2(f1, f2);
-    o[3] = make_double2(t0, t1);
-    o[4] = make_double2(t2, t1 * y2 - t2 * y1);
-    o[5] = make_double2(t2 * y0 - t0 * y2, t0 * y1 - t1 * y0);
-    o[6] = make_double2(f1 * y2 - f2 * y1, f2 * y0 - f0 * y2);
-    o[7] = make_double2(f0 * y1 - f1 * y0, 0.0);
-}
-
-// FP32-tile source record: position in double, force and torque in float (64 B)
-struct alignas(16) SrcF32 {
-    double y[3];
-    float f[3];
-    float t[3];
-    float pad[4];
-};
-static_assert(sizeof(SrcF32) == 64, "SrcF32 must be 64 bytes");
-
-__global__ void __launch_bounds__(256) rpy_pack_f32(int64_t S, const double* __restrict__ Y,
-                                                   const double* __restrict__ F, const double* __restrict__ T,
-                                                   SrcF32* __restrict__ pk) {
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= S) return;
-    SrcF32 s;
-    for (int i = 0; i < 3; i++) {
-        s.y[i] = Y[i * S + m];
-        s.f[i] = (float)F[i * S + m];
-        s.t[i] = (float)T[i * S + m];
-    }
-    s.pad[0] = s.pad[1] = s.pad[2] = s.pad[3] = 0.f;
-    pk[m] = s;
+    rpy_pack_record(prec, pk, m, Y[m], Y[S + m], Y[2 * S + m], F[m], F[S + m], F[2 * S + m], T[m], T[S + m],
+                    T[2 * S + m]);
 }
 
 // ------------------------------------------------------------------ FP64 pair
@@ -115,8 +83,8 @@ __device__ __forceinline__ Ovl<R> rpy_overlap(R rx, R ry, R rz, R r2, R Fx, R Fy
     return o;
 }
 
-__device__ __forceinline__ void rpy_pair_f64(const double y[3], const double* __restrict__ s, double a,
-                                             double four_a2, double two_a2, AccF64& A) {
+__device__ __forceinline__ void rpy_pair_f64(const double y[3], const double (&s)[15], double a, double four_a2,
+                                             double two_a2, AccF64& A) {
     const double rx = y[0] - s[0], ry = y[1] - s[1], rz = y[2] - s[2];
     const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
     const bool near = r2 < four_a2;
@@ -167,12 +135,12 @@ struct RpyOut {
     double* W;
 };
 
-__device__ __forceinline__ void rpy_store(const RpyOut& o, int64_t S, int K, int k, int64_t n, const double v[3],
-                                          const double w[3]) {
+__device__ __forceinline__ void rpy_store(const RpyOut& o, int64_t base, int64_t S, int64_t Sg, int K, int k,
+                                          int64_t n, const double v[3], const double w[3]) {
     if (K == 1) {
         for (int i = 0; i < 3; i++) {
-            o.V[i * S + n] = v[i];
-            o.W[i * S + n] = w[i];
+            o.V[i * Sg + base + n] = v[i];
+            o.W[i * Sg + base + n] = w[i];
         }
     } else {
         double* p = o.part + (int64_t)k * 6 * S + n;
@@ -183,51 +151,143 @@ __device__ __forceinline__ void rpy_store(const RpyOut& o, int64_t S, int K, int
     }
 }
 
-// blockIdx.x -> (target block tb = bid / K, source chunk k = bid % K); chunks
-// adjacent in k land on different XCDs, so each XCD's L2 holds ~K/8 chunks.
-template <int TPL>
-__global__ void __launch_bounds__(kRpyBlock) rpy_f64_kernel(int64_t S, int64_t chunk, int K,
-                                                          const double* __restrict__ pk,
-                                                          const double* __restrict__ Y, double a, double c,
-                                                          RpyOut out) {
-    const int k = (int)(blockIdx.x % (unsigned)K);
-    const int64_t tb = blockIdx.x / (unsigned)K;
-    const int64_t m0 = (int64_t)k * chunk;
-    const int64_t m1 = min(S, m0 + chunk);
+// Writes the per-target results; with WS > 1 the waves' sums are combined in LDS
+// (wave 0 adds waves 1..WS-1 in order) before the store.
+template <int TPL, int WS>
+__device__ __forceinline__ void rpy_finish(const RpyOut& out, int64_t base, int64_t S, int64_t Sg, int K, int k,
+                                           const int64_t (&n)[TPL], double (&vw)[TPL][6]) {
+    if (WS > 1) {
+        __shared__ double red[WS > 1 ? WS - 1 : 1][TPL * 6][64];
+        const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+        if (wave > 0)
+#pragma unroll
+            for (int j = 0; j < TPL; j++)
+                for (int q = 0; q < 6; q++) red[wave - 1][j * 6 + q][lane] = vw[j][q];
+        __syncthreads();
+        if (wave > 0) return;
+#pragma unroll
+        for (int j = 0; j < TPL; j++)
+            for (int q = 0; q < 6; q++)
+                for (int w2 = 0; w2 < WS - 1; w2++) vw[j][q] += red[w2][j * 6 + q][lane];
+    }
+#pragma unroll
+    for (int j = 0; j < TPL; j++) {
+        if (n[j] >= S) continue;
+        const double v[3] = {vw[j][0], vw[j][1], vw[j][2]}, w[3] = {vw[j][3], vw[j][4], vw[j][5]};
+        rpy_store(out, base, S, Sg, K, k, n[j], v, w);
+    }
+}
+
+// One work item: targets [tb*256*TPL, +256*TPL) x sources [k*chunk, +chunk) of one
+// suspension whose segments start at global index `base` (S of them).  Partial
+// results go to part[(k*6 + c) * S + n] (suspension-local n) when K > 1.
+// WS = 1: the block's four waves own 4 x 64 x TPL different targets.  WS = 4 (small
+// sizes): the four waves share 64 x TPL targets and split the chunk's sources
+// four ways; their results are combined through LDS in wave order.
+template <int TPL, int WS>
+__device__ __forceinline__ void rpy_item_f64(int64_t base, int64_t S, int64_t Sg, int64_t tb, int k, int K,
+                                             int64_t chunk, const double* __restrict__ pk,
+                                             const double* __restrict__ Y, double a, double c, const RpyOut& out) {
+    constexpr int kTgtPerBlock = kRpyBlock / WS;  // targets per j-slice
+    const int wave = threadIdx.x / 64;
+    const int tid = WS == 1 ? (int)threadIdx.x : (int)(threadIdx.x % 64);
+    int64_t m0 = (int64_t)k * chunk;
+    int64_t m1 = min(S, m0 + chunk);
+    if (WS > 1) {
+        const int64_t sub = (m1 - m0 + WS - 1) / WS;
+        const int64_t a0 = m0 + wave * sub;
+        m1 = min(m1, a0 + sub);
+        m0 = min(a0, m1);
+    }
     const double four_a2 = 4.0 * a * a, two_a2 = 2.0 * a * a;
     int64_t n[TPL];
     double y[TPL][3];
     AccF64 A[TPL];
 #pragma unroll
     for (int j = 0; j < TPL; j++) {
-        n[j] = tb * (kRpyBlock * TPL) + j * kRpyBlock + threadIdx.x;
-        const int64_t nn = n[j] < S ? n[j] : S - 1;
+        n[j] = tb * (kTgtPerBlock * TPL) + j * kTgtPerBlock + tid;
+        const int64_t nn = base + (n[j] < S ? n[j] : S - 1);
         y[j][0] = Y[nn];
-        y[j][1] = Y[S + nn];
-        y[j][2] = Y[2 * S + nn];
+        y[j][1] = Y[Sg + nn];
+        y[j][2] = Y[2 * Sg + nn];
         for (int i = 0; i < 3; i++)
             A[j].G[i] = A[j].R[i] = A[j].P[i] = A[j].Q[i] = A[j].U[i] = A[j].Hv[i] = A[j].Hw[i] = 0.0;
     }
-    for (int64_t m = m0; m < m1; ++m) {
-        const double* s = pk + 16 * m;
+    if constexpr (WS > 1) {
+        // small sizes: the block's whole source chunk is copied to LDS with
+        // coalesced loads, and each wave reads its quarter from there
+        __shared__ double lsrc[kLdsSources * 16];
+        const int64_t cb0 = (int64_t)k * chunk, cb1 = min(S, cb0 + chunk);
+        const double* g = pk + 16 * (base + cb0);
+#pragma unroll 8
+        for (int64_t e = threadIdx.x; e < (cb1 - cb0) * 16; e += kRpyBlock) lsrc[e] = g[e];
+        __syncthreads();
+        for (int64_t m = m0; m < m1; ++m) {
+            const double* sp = lsrc + 16 * (m - cb0);
+            double cur[15];
+            for (int i = 0; i < 15; i++) cur[i] = sp[i];
 #pragma unroll
-        for (int j = 0; j < TPL; j++) rpy_pair_f64(y[j], s, a, four_a2, two_a2, A[j]);
+            for (int j = 0; j < TPL; j++) rpy_pair_f64(y[j], cur, a, four_a2, two_a2, A[j]);
+        }
+    } else {
+        // the next source record is requested before the current one is used, so
+        // the scalar-load latency overlaps the pair arithmetic
+        const double* src = pk + 16 * base;
+        double cur[15];
+        if (m0 < m1) {
+            for (int i = 0; i < 15; i++) cur[i] = src[16 * m0 + i];
+        }
+        for (int64_t m = m0; m < m1; ++m) {
+            const int64_t mn = m + 1 < m1 ? m + 1 : m;
+            double nxt[15];
+            for (int i = 0; i < 15; i++) nxt[i] = src[16 * mn + i];
+#pragma unroll
+            for (int j = 0; j < TPL; j++) rpy_pair_f64(y[j], cur, a, four_a2, two_a2, A[j]);
+            for (int i = 0; i < 15; i++) cur[i] = nxt[i];
+        }
     }
     const double c23 = 2.0 * a * a / 3.0;
+    double vw[TPL][6];
 #pragma unroll
     for (int j = 0; j < TPL; j++) {
-        if (n[j] >= S) continue;
         const AccF64& B = A[j];
         const double* yy = y[j];
-        double v[3], w[3];
         // V = c [G + 2a^2/3 R + Hv + P x y - Q];  Omega = c [R x y - U + 3/2 Hw - 1/2 P]
-        v[0] = c * (B.G[0] + c23 * B.R[0] + B.Hv[0] + (B.P[1] * yy[2] - B.P[2] * yy[1]) - B.Q[0]);
-        v[1] = c * (B.G[1] + c23 * B.R[1] + B.Hv[1] + (B.P[2] * yy[0] - B.P[0] * yy[2]) - B.Q[1]);
-        v[2] = c * (B.G[2] + c23 * B.R[2] + B.Hv[2] + (B.P[0] * yy[1] - B.P[1] * yy[0]) - B.Q[2]);
-        w[0] = c * ((B.R[1] * yy[2] - B.R[2] * yy[1]) - B.U[0] + 1.5 * B.Hw[0] - 0.5 * B.P[0]);
-        w[1] = c * ((B.R[2] * yy[0] - B.R[0] * yy[2]) - B.U[1] + 1.5 * B.Hw[1] - 0.5 * B.P[1]);
-        w[2] = c * ((B.R[0] * yy[1] - B.R[1] * yy[0]) - B.U[2] + 1.5 * B.Hw[2] - 0.5 * B.P[2]);
-        rpy_store(out, S, K, k, n[j], v, w);
+        vw[j][0] = c * (B.G[0] + c23 * B.R[0] + B.Hv[0] + (B.P[1] * yy[2] - B.P[2] * yy[1]) - B.Q[0]);
+        vw[j][1] = c * (B.G[1] + c23 * B.R[1] + B.Hv[1] + (B.P[2] * yy[0] - B.P[0] * yy[2]) - B.Q[1]);
+        vw[j][2] = c * (B.G[2] + c23 * B.R[2] + B.Hv[2] + (B.P[0] * yy[1] - B.P[1] * yy[0]) - B.Q[2]);
+        vw[j][3] = c * ((B.R[1] * yy[2] - B.R[2] * yy[1]) - B.U[0] + 1.5 * B.Hw[0] - 0.5 * B.P[0]);
+        vw[j][4] = c * ((B.R[2] * yy[0] - B.R[0] * yy[2]) - B.U[1] + 1.5 * B.Hw[1] - 0.5 * B.P[1]);
+        vw[j][5] = c * ((B.R[0] * yy[1] - B.R[1] * yy[0]) - B.U[2] + 1.5 * B.Hw[2] - 0.5 * B.P[2]);
+    }
+    rpy_finish<TPL, WS>(out, base, S, Sg, K, k, n, vw);
+}
+
+// Single suspension: blockIdx.x -> (target block tb = bid / K, source chunk
+// k = bid % K); chunks adjacent in k land on different XCDs, so each XCD's L2
+// holds ~K/8 of the sources.
+template <int TPL, int WS>
+__global__ void __launch_bounds__(kRpyBlock) rpy_f64_kernel(int64_t S, int64_t chunk, int K,
+                                                          const double* __restrict__ pk,
+                                                          const double* __restrict__ Y, double a, double c,
+                                                          RpyOut out) {
+    const int k = (int)(blockIdx.x % (unsigned)K);
+    const int64_t tb = blockIdx.x / (unsigned)K;
+    rpy_item_f64<TPL, WS>(0, S, S, tb, k, K, chunk, pk, Y, a, c, out);
+}
+
+// Many suspensions in one persistent launch: a fixed grid walks a work list
+// sorted by cost (largest first), item i handled by block i mod gridDim.
+template <int TPL>
+__global__ void __launch_bounds__(kRpyBlock) rpy_f64_items_kernel(const RpyItem* __restrict__ items, int64_t nitems,
+                                                                int64_t Sg, const double* __restrict__ pk,
+                                                                const double* __restrict__ Y, double a, double c,
+                                                                RpyOut out) {
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const RpyItem w = items[it];
+        RpyOut o = out;
+        o.part = out.part + w.part;
+        rpy_item_f64<TPL, 1>(w.base, w.S, Sg, w.tb, w.k, w.K, w.chunk, pk, Y, a, c, o);
     }
 }
 
@@ -267,27 +327,41 @@ __device__ __forceinline__ void rpy_pair_f32(const double y[3], const SrcF32* __
 
 constexpr int kF32Tile = 64;  // sources accumulated in float before the double flush
 
-template <int TPL>
-__global__ void __launch_bounds__(kRpyBlock) rpy_f32_kernel(int64_t S, int64_t chunk, int K,
-                                                          const SrcF32* __restrict__ pk,
-                                                          const double* __restrict__ Y, double a, double c,
-                                                          RpyOut out) {
-    const int k = (int)(blockIdx.x % (unsigned)K);
-    const int64_t tb = blockIdx.x / (unsigned)K;
-    const int64_t m0 = (int64_t)k * chunk;
-    const int64_t m1 = min(S, m0 + chunk);
+template <int TPL, int WS>
+__device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg, int64_t tb, int k, int K,
+                                             int64_t chunk, const SrcF32* __restrict__ pk,
+                                             const double* __restrict__ Y, double a, double c, const RpyOut& out) {
+    constexpr int kTgtPerBlock = kRpyBlock / WS;
+    const int wave = threadIdx.x / 64;
+    const int tid = WS == 1 ? (int)threadIdx.x : (int)(threadIdx.x % 64);
+    int64_t m0 = (int64_t)k * chunk;
+    int64_t m1 = min(S, m0 + chunk);
+    if (WS > 1) {
+        const int64_t sub = (m1 - m0 + WS - 1) / WS;
+        const int64_t a0 = m0 + wave * sub;
+        m1 = min(m1, a0 + sub);
+        m0 = min(a0, m1);
+    }
     const float af = (float)a, four_a2 = (float)(4.0 * a * a), two_a2 = (float)(2.0 * a * a);
     const float c23 = (float)(2.0 * a * a / 3.0);
     int64_t n[TPL];
     double y[TPL][3], vd[TPL][3], wd[TPL][3];
 #pragma unroll
     for (int j = 0; j < TPL; j++) {
-        n[j] = tb * (kRpyBlock * TPL) + j * kRpyBlock + threadIdx.x;
-        const int64_t nn = n[j] < S ? n[j] : S - 1;
+        n[j] = tb * (kTgtPerBlock * TPL) + j * kTgtPerBlock + tid;
+        const int64_t nn = base + (n[j] < S ? n[j] : S - 1);
         for (int i = 0; i < 3; i++) {
-            y[j][i] = Y[i * S + nn];
+            y[j][i] = Y[i * Sg + nn];
             vd[j][i] = wd[j][i] = 0.0;
         }
+    }
+    const SrcF32* src = pk + base;
+    if constexpr (WS > 1) {
+        __shared__ SrcF32 lsrc[kLdsSources];
+        const int64_t cb0 = (int64_t)k * chunk, cb1 = min(S, cb0 + chunk);
+        for (int64_t e = threadIdx.x; e < cb1 - cb0; e += kRpyBlock) lsrc[e] = src[cb0 + e];
+        __syncthreads();
+        src = lsrc - cb0;
     }
     for (int64_t t0 = m0; t0 < m1; t0 += kF32Tile) {
         const int64_t t1 = min(m1, t0 + kF32Tile);
@@ -296,7 +370,7 @@ __global__ void __launch_bounds__(kRpyBlock) rpy_f32_kernel(int64_t S, int64_t c
         for (int j = 0; j < TPL; j++)
             for (int i = 0; i < 3; i++) v[j][i] = w[j][i] = 0.f;
         for (int64_t m = t0; m < t1; ++m) {
-            const SrcF32* s = pk + m;
+            const SrcF32* s = src + m;
 #pragma unroll
             for (int j = 0; j < TPL; j++) rpy_pair_f32(y[j], s, af, four_a2, two_a2, c23, v[j], w[j]);
         }
@@ -307,49 +381,96 @@ __global__ void __launch_bounds__(kRpyBlock) rpy_f32_kernel(int64_t S, int64_t c
                 wd[j][i] += (double)w[j][i];
             }
     }
+    double vw[TPL][6];
 #pragma unroll
-    for (int j = 0; j < TPL; j++) {
-        if (n[j] >= S) continue;
-        double v[3], w[3];
+    for (int j = 0; j < TPL; j++)
         for (int i = 0; i < 3; i++) {
-            v[i] = c * vd[j][i];
-            w[i] = c * wd[j][i];
+            vw[j][i] = c * vd[j][i];
+            vw[j][3 + i] = c * wd[j][i];
         }
-        rpy_store(out, S, K, k, n[j], v, w);
+    rpy_finish<TPL, WS>(out, base, S, Sg, K, k, n, vw);
+}
+
+template <int TPL, int WS>
+__global__ void __launch_bounds__(kRpyBlock) rpy_f32_kernel(int64_t S, int64_t chunk, int K,
+                                                          const SrcF32* __restrict__ pk,
+                                                          const double* __restrict__ Y, double a, double c,
+                                                          RpyOut out) {
+    const int k = (int)(blockIdx.x % (unsigned)K);
+    const int64_t tb = blockIdx.x / (unsigned)K;
+    rpy_item_f32<TPL, WS>(0, S, S, tb, k, K, chunk, pk, Y, a, c, out);
+}
+
+template <int TPL>
+__global__ void __launch_bounds__(kRpyBlock) rpy_f32_items_kernel(const RpyItem* __restrict__ items, int64_t nitems,
+                                                                int64_t Sg, const SrcF32* __restrict__ pk,
+                                                                const double* __restrict__ Y, double a, double c,
+                                                                RpyOut out) {
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const RpyItem w = items[it];
+        RpyOut o = out;
+        o.part = out.part + w.part;
+        rpy_item_f32<TPL, 1>(w.base, w.S, Sg, w.tb, w.k, w.K, w.chunk, pk, Y, a, c, o);
     }
 }
 
-// Fixed-order reduction of the K partial results.
+// Fixed-order reduction of the K partial results; one thread per (component, target).
 __global__ void __launch_bounds__(256) rpy_reduce(int64_t S, int K, const double* __restrict__ part,
                                                  double* __restrict__ V, double* __restrict__ W) {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= S) return;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < K; k++) {
-        const double* p = part + (int64_t)k * 6 * S + n;
-#pragma unroll
-        for (int c = 0; c < 6; c++) acc[c] += p[c * S];
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 6 * S) return;
+    const int64_t c = e / S, n = e - c * S;
+    // four independent partial sums keep several loads in flight; fixed order
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int k = 0;
+    for (; k + 4 <= K; k += 4) {
+        a0 += part[((int64_t)k * 6 + c) * S + n];
+        a1 += part[((int64_t)(k + 1) * 6 + c) * S + n];
+        a2 += part[((int64_t)(k + 2) * 6 + c) * S + n];
+        a3 += part[((int64_t)(k + 3) * 6 + c) * S + n];
     }
-    for (int i = 0; i < 3; i++) {
-        V[i * S + n] = acc[i];
-        W[i * S + n] = acc[3 + i];
-    }
+    for (; k < K; k++) a0 += part[((int64_t)k * 6 + c) * S + n];
+    const double acc = (a0 + a1) + (a2 + a3);
+    if (c < 3) V[c * S + n] = acc;
+    else W[(c - 3) * S + n] = acc;
+}
+
+// Reduction for the work-list launch: segment s of suspension i = seg_susp[s]
+// sums the K_i partials of its suspension (suspensions with K_i = 1 wrote V, W).
+__global__ void __launch_bounds__(256) rpy_reduce_items(int64_t Sg, const int32_t* __restrict__ seg_susp,
+                                                       const RpySusp* __restrict__ sus, const double* __restrict__ part,
+                                                       double* __restrict__ V, double* __restrict__ W) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 6 * Sg) return;
+    const int64_t c = e / Sg, s = e - c * Sg;
+    const RpySusp u = sus[seg_susp[s]];
+    if (u.K <= 1) return;
+    const int64_t n = s - u.base;
+    double acc = 0.0;
+    for (int k = 0; k < u.K; k++) acc += part[u.part + ((int64_t)k * 6 + c) * u.S + n];
+    if (c < 3) V[c * Sg + s] = acc;
+    else W[(c - 3) * Sg + s] = acc;
 }
 
 // ------------------------------------------------------------------ launch plan
 constexpr int kTplF64 = 2;
 constexpr int kTplF32 = 2;
+constexpr int64_t kSmallS = 12000;  // below this, one target per lane and short chunks (latency-bound sizes)
 
 RpyPlan rpy_plan(int64_t S, int prec) {
     RpyPlan p{};
     p.S = S;
     p.prec = prec;
-    p.tpl = prec == FIL_PREC_F64 ? kTplF64 : kTplF32;
+    const bool small = S < kSmallS;
+    p.tpl = small ? 1 : (prec == FIL_PREC_F64 ? kTplF64 : kTplF32);
+    p.ws = small ? 4 : 1;
     if (S <= 0) return p;
-    p.tb = ceil_div(S, (int64_t)kRpyBlock * p.tpl);
-    // aim for ~2048 workgroups (8 per CU), chunks of at least 64 sources
+    p.tb = ceil_div(S, (int64_t)(kRpyBlock / p.ws) * p.tpl);
+    // aim for ~2048 workgroups (8 per CU); every wave gets >= 32 (small) or 64 sources;
+    // on the small path a block's chunk must fit the LDS staging buffer
     int64_t K = ceil_div(2048, p.tb);
-    K = std::min<int64_t>(K, std::max<int64_t>(1, S / 64));
+    K = std::min<int64_t>(K, std::max<int64_t>(1, S / (small ? 32 * p.ws : 64)));
+    if (small) K = std::max<int64_t>(K, ceil_div(S, kLdsSources));
     if (K >= 8) K = ceil_div(K, 8) * 8;
     p.chunk = ceil_div(S, K);
     p.K = (int)ceil_div(S, p.chunk);
@@ -360,7 +481,7 @@ RpyPlan rpy_plan(int64_t S, int prec) {
 }
 
 int rpy_launch(const RpyPlan& p, const double* Y, const double* F, const double* T, double a, double eta, double* V,
-               double* W, void* work, hipStream_t st) {
+               double* W, void* work, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool packed, bool reduce) {
     if (p.S <= 0) return FIL_OK;
     char* base = static_cast<char*>(work);
     RpyOut out{reinterpret_cast<double*>(base + p.pack_bytes), V, W};
@@ -369,14 +490,116 @@ int rpy_launch(const RpyPlan& p, const double* Y, const double* F, const double*
     const unsigned pgrid = (unsigned)ceil_div(p.S, 256);
     if (p.prec == FIL_PREC_F64) {
         double* pk = reinterpret_cast<double*>(base);
-        rpy_pack_f64<<<pgrid, 256, 0, st>>>(p.S, Y, F, T, pk);
-        rpy_f64_kernel<kTplF64><<<grid, kRpyBlock, 0, st>>>(p.S, p.chunk, p.K, pk, Y, a, c, out);
+        if (!packed) rpy_pack<<<pgrid, 256, 0, st>>>(p.S, p.prec, Y, F, T, pk);
+        if (ev0) FIL_HIP_TRY(hipEventRecord(ev0, st));
+        if (p.ws == 4) rpy_f64_kernel<1, 4><<<grid, kRpyBlock, 0, st>>>(p.S, p.chunk, p.K, pk, Y, a, c, out);
+        else rpy_f64_kernel<kTplF64, 1><<<grid, kRpyBlock, 0, st>>>(p.S, p.chunk, p.K, pk, Y, a, c, out);
+        if (ev1) FIL_HIP_TRY(hipEventRecord(ev1, st));
     } else {
         SrcF32* pk = reinterpret_cast<SrcF32*>(base);
-        rpy_pack_f32<<<pgrid, 256, 0, st>>>(p.S, Y, F, T, pk);
-        rpy_f32_kernel<kTplF32><<<grid, kRpyBlock, 0, st>>>(p.S, p.chunk, p.K, pk, Y, a, c, out);
+        if (!packed) rpy_pack<<<pgrid, 256, 0, st>>>(p.S, p.prec, Y, F, T, pk);
+        if (ev0) FIL_HIP_TRY(hipEventRecord(ev0, st));
+        if (p.ws == 4) rpy_f32_kernel<1, 4><<<grid, kRpyBlock, 0, st>>>(p.S, p.chunk, p.K, pk, Y, a, c, out);
+        else rpy_f32_kernel<kTplF32, 1><<<grid, kRpyBlock, 0, st>>>(p.S, p.chunk, p.K, pk, Y, a, c, out);
+        if (ev1) FIL_HIP_TRY(hipEventRecord(ev1, st));
     }
-    if (p.K > 1) rpy_reduce<<<pgrid, 256, 0, st>>>(p.S, p.K, out.part, V, W);
+    if (p.K > 1 && reduce) rpy_reduce<<<(unsigned)ceil_div(6 * p.S, 256), 256, 0, st>>>(p.S, p.K, out.part, V, W);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+// ------------------------------------------------------------------ batched plan
+constexpr int kBatchChunk = 256;
+constexpr int kPersistentBlocks = 2048;
+
+RpyBatchPlan rpy_batch_plan(int64_t nsusp, const int64_t* susp_off, int prec) {
+    RpyBatchPlan p;
+    p.prec = prec;
+    p.Sg = susp_off[nsusp];
+    const int tpl = prec == FIL_PREC_F64 ? kTplF64 : kTplF32;
+    int64_t part = 0;
+    p.sus.resize(nsusp);
+    p.seg_susp.resize(p.Sg);
+    for (int64_t i = 0; i < nsusp; i++) {
+        const int64_t base = susp_off[i], S = susp_off[i + 1] - base;
+        for (int64_t s = base; s < base + S; s++) p.seg_susp[s] = (int32_t)i;
+        RpySusp u{base, 0, (int32_t)S, 1};
+        if (S > 0) {
+            const int64_t tb = ceil_div(S, (int64_t)kRpyBlock * tpl);
+            int64_t K = std::max<int64_t>(1, ceil_div(S, kBatchChunk));
+            const int64_t chunk = ceil_div(S, K);
+            K = ceil_div(S, chunk);
+            u.K = (int32_t)K;
+            if (K > 1) {
+                u.part = part;
+                part += K * 6 * S;
+                p.any_reduce = true;
+            }
+            for (int64_t t = 0; t < tb; t++)
+                for (int64_t k = 0; k < K; k++) p.items.push_back(RpyItem{base, u.part, (int32_t)S, (int32_t)t,
+                                                                          (int32_t)k, (int32_t)K, chunk});
+        }
+        p.sus[i] = u;
+    }
+    // largest items first: with a static round-robin walk this balances the blocks
+    auto cost = [tpl](const RpyItem& w) {
+        const int64_t nt = std::min<int64_t>((int64_t)kRpyBlock * tpl, w.S - (int64_t)w.tb * kRpyBlock * tpl);
+        const int64_t ns = std::min<int64_t>(w.chunk, w.S - (int64_t)w.k * w.chunk);
+        return nt * ns;
+    };
+    std::stable_sort(p.items.begin(), p.items.end(),
+                     [&](const RpyItem& x, const RpyItem& y) { return cost(x) > cost(y); });
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    p.pack_bytes = al((size_t)p.Sg * (prec == FIL_PREC_F64 ? 16 * sizeof(double) : sizeof(SrcF32)));
+    p.part_bytes = al((size_t)part * sizeof(double));
+    p.items_bytes = al(p.items.size() * sizeof(RpyItem));
+    p.sus_bytes = al(p.sus.size() * sizeof(RpySusp));
+    p.segs_bytes = al(p.seg_susp.size() * sizeof(int32_t));
+    return p;
+}
+
+int rpy_batch_upload(const RpyBatchPlan& p, void* work, hipStream_t st) {
+    char* base = static_cast<char*>(work) + p.pack_bytes + p.part_bytes;
+    if (!p.items.empty())
+        FIL_HIP_TRY(hipMemcpyAsync(base, p.items.data(), p.items.size() * sizeof(RpyItem), hipMemcpyHostToDevice, st));
+    base += p.items_bytes;
+    if (!p.sus.empty())
+        FIL_HIP_TRY(hipMemcpyAsync(base, p.sus.data(), p.sus.size() * sizeof(RpySusp), hipMemcpyHostToDevice, st));
+    base += p.sus_bytes;
+    if (!p.seg_susp.empty())
+        FIL_HIP_TRY(hipMemcpyAsync(base, p.seg_susp.data(), p.seg_susp.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, st));
+    return FIL_OK;
+}
+
+int rpy_batch_launch(const RpyBatchPlan& p, const double* Y, const double* F, const double* T, double a, double eta,
+                     double* V, double* W, void* work, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool packed) {
+    if (p.Sg <= 0) return FIL_OK;
+    char* base = static_cast<char*>(work);
+    RpyOut out{reinterpret_cast<double*>(base + p.pack_bytes), V, W};
+    const RpyItem* items = reinterpret_cast<const RpyItem*>(base + p.pack_bytes + p.part_bytes);
+    const RpySusp* sus = reinterpret_cast<const RpySusp*>(base + p.pack_bytes + p.part_bytes + p.items_bytes);
+    const int32_t* segs =
+        reinterpret_cast<const int32_t*>(base + p.pack_bytes + p.part_bytes + p.items_bytes + p.sus_bytes);
+    const double c = 1.0 / (8.0 * kPi * eta);
+    const int64_t nitems = (int64_t)p.items.size();
+    const unsigned grid = (unsigned)std::min<int64_t>(nitems, kPersistentBlocks);
+    const unsigned pgrid = (unsigned)ceil_div(p.Sg, 256);
+    if (p.prec == FIL_PREC_F64) {
+        double* pk = reinterpret_cast<double*>(base);
+        if (!packed) rpy_pack<<<pgrid, 256, 0, st>>>(p.Sg, p.prec, Y, F, T, pk);
+        if (ev0) FIL_HIP_TRY(hipEventRecord(ev0, st));
+        if (nitems) rpy_f64_items_kernel<kTplF64><<<grid, kRpyBlock, 0, st>>>(items, nitems, p.Sg, pk, Y, a, c, out);
+        if (ev1) FIL_HIP_TRY(hipEventRecord(ev1, st));
+    } else {
+        SrcF32* pk = reinterpret_cast<SrcF32*>(base);
+        if (!packed) rpy_pack<<<pgrid, 256, 0, st>>>(p.Sg, p.prec, Y, F, T, pk);
+        if (ev0) FIL_HIP_TRY(hipEventRecord(ev0, st));
+        if (nitems) rpy_f32_items_kernel<kTplF32><<<grid, kRpyBlock, 0, st>>>(items, nitems, p.Sg, pk, Y, a, c, out);
+        if (ev1) FIL_HIP_TRY(hipEventRecord(ev1, st));
+    }
+    if (p.any_reduce)
+        rpy_reduce_items<<<(unsigned)ceil_div(6 * p.Sg, 256), 256, 0, st>>>(p.Sg, segs, sus, out.part, V, W);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }

@@ -1,0 +1,68 @@
+// Device-side view of a simulation and launchers of the implicit-step kernels.
+#pragma once
+#include "common.h"
+
+namespace fil {
+
+constexpr int kMaxSeg = 50;       // segments per filament: LDS of the banded J0 solve (6N x 25 doubles)
+constexpr int kKL = 8;            // sub-diagonals of the row-differenced J0 in interleaved order
+constexpr int kKU = 8;            // super-diagonals (kKL + kKU after pivoting fill-in)
+constexpr int kBandW = 2 * kKL + kKU + 1;
+constexpr int kMaxIter = 256;     // Broyden history capacity
+constexpr int kMaxDots = kMaxIter + 2;
+constexpr int kVecBlock = 1024;   // residual-vector elements per Broyden vector block
+
+// BDF coefficients: y - a1 y^j - a2 y^{j-1} - b dt v = 0, u - g u^j - b dt dexpinv(Omega) = 0
+struct BdfCoef {
+    double a1, a2, b, g;
+};
+
+// Plain-old-data view of the simulation passed by value to kernels.
+struct SimDev {
+    int64_t S, M, nsusp;
+    const int64_t* seg_off;        // [M+1]
+    const int32_t* fil_susp;       // [M]
+    const int32_t* seg_fil;        // [S]
+    const int64_t* susp_seg_off;   // [nsusp+1]
+    const int32_t* tether;         // [M]
+    const double* base;            // [M][3]
+    const double* phase;           // [M] or null
+    const int64_t* susp_fil_off;   // [nsusp+1]
+    // vector blocks over the 6S unknowns (never straddling suspensions)
+    int64_t nvblk;
+    const int32_t* vblk_susp;      // [nvblk]
+    const int64_t* vblk_start;     // [nvblk+1]
+    const int64_t* susp_vblk_off;  // [nsusp+1]
+    int max_dots;
+    double a, eta, dL, KB, KT, chi, FS, grav[3], dt, K0, kw, omega;
+};
+
+// configuration from X, internal forces (F = F^C + gravity, T = T^C + T^E) and filament boxes
+int state_forces_launch(const SimDev& d, const double* X, const double* qj, double tt, const int32_t* active,
+                        double* Yc, double* qc, double* F, double* T, double* box, hipStream_t st);
+// adds the steric barrier into F and writes the mobility source records (precision prec)
+int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, const int32_t* active, double* F,
+                       const double* T, int prec, void* pk, hipStream_t st);
+// residual rows and max|f| per suspension into resbits (zeroed by the previous call);
+// velocities from the K mobility partials `part` when non-null, else from V, W
+int residual_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* Xj, const double* Yc,
+                    const double* Yj, const double* Yjm1, const double* V, const double* W, const double* part, int K,
+                    const int32_t* active, double* f, unsigned long long* resbits, unsigned long long* resbits_next,
+                    hipStream_t st);
+int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const double* Yjm1, const double* Xj,
+                         const double* Xjm1, const int32_t* active, double* X0, hipStream_t st);
+// J0 at X in row-differenced banded form (6N x kBandW per filament at 6*seg_off[f]*kBandW),
+// factorised with partial pivoting (ipiv at 6*seg_off[f]); flag[f] = 1 for a zero pivot
+int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* qc, const double* Tint,
+                     double tt, const int32_t* active, double* AB, int32_t* ipiv, int32_t* flag, hipStream_t st);
+int j0_solve_launch(const SimDev& d, const double* AB, const int32_t* ipiv, const double* v, const int32_t* active,
+                    double* out, hipStream_t st);
+int broyden_update_launch(const SimDev& d, int k, const double* AB, const int32_t* ipiv, double* Chist,
+                          double* Dhist, const double* fnew, double* fprev, double* g0, double* hvec, double* part,
+                          double* X, double* dXout, const int32_t* active, hipStream_t st);
+int first_step_launch(const SimDev& d, const double* h, const double* f, double* fprev, double* X, double* dXout,
+                      const int32_t* active, hipStream_t st);
+int finalize_launch(const SimDev& d, const int32_t* commit, const double* Yc, const double* qc, const double* X,
+                    double* Yj, double* Yjm1, double* qj, double* Xj, double* Xjm1, hipStream_t st);
+
+}  // namespace fil

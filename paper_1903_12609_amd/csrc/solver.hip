@@ -1,0 +1,900 @@
+// Device kernels of the implicit step (Sec. 2.9.3 system, Alg. 2 bad Broyden,
+// Sec. 3.2.2 / Appendix B.2 explicit J0) of arXiv:1903.12609.
+//
+// Vector layouts: positions, forces, velocities are component-major [3][S];
+// quaternions [4][S]; the unknown / residual vectors are filament-major
+// [6S] with filament f's block [Y_1 | u_1..u_N | Lambda_{3/2}..Lambda_{N-1/2}]
+// at 6*seg_off[f].  Every segment owns exactly six residual rows:
+// segment 0 of a filament owns f^1 and f^2_1, segment n >= 1 owns f^2_n, f^3_n.
+#include "common.h"
+#include "kernels.h"
+#include "quat.h"
+#include "solver.h"
+
+namespace fil {
+
+__device__ __forceinline__ V3 ld3(const double* __restrict__ v, int64_t ld, int64_t i) {
+    return v3(v[i], v[ld + i], v[2 * ld + i]);
+}
+__device__ __forceinline__ void st3(double* __restrict__ v, int64_t ld, int64_t i, V3 x) {
+    v[i] = x.x;
+    v[ld + i] = x.y;
+    v[2 * ld + i] = x.z;
+}
+__device__ __forceinline__ V3 ldx(const double* __restrict__ X, int64_t i) { return v3(X[i], X[i + 1], X[i + 2]); }
+__device__ __forceinline__ Q4 ldq(const double* __restrict__ q, int64_t S, int64_t s) {
+    return Q4{q[s], q[S + s], q[2 * S + s], q[3 * S + s]};
+}
+__device__ __forceinline__ void stq(double* __restrict__ q, int64_t S, int64_t s, Q4 x) {
+    q[s] = x.w;
+    q[S + s] = x.x;
+    q[2 * S + s] = x.y;
+    q[3 * S + s] = x.z;
+}
+
+// wave-uniform lane read of a double (the lane index must be uniform)
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// preferred curvature of joint k (between local segments k and k+1) at time tt,
+// evaluated at s = (k+1) dL
+__device__ __forceinline__ V3 joint_kappa(const SimDev& d, int64_t f, int64_t k, double tt) {
+    if (!d.phase) return v3(0, 0, 0);
+    return v3(0, 0, d.K0 * sin(d.kw * (double)(k + 1) * d.dL - d.omega * tt + d.phase[f]));
+}
+
+// ---------------------------------------------------------------- state + forces
+// One 64-lane workgroup per filament: q_n = exp(u_n) . q^j_n, t_n, robot-arm
+// positions, then F = F^C + gravity (+ lambda_1), T = T^C + T^E (+ lambda_2).
+__global__ void __launch_bounds__(64) state_forces_kernel(SimDev d, const double* __restrict__ X,
+                                                        const double* __restrict__ qj, double tt,
+                                                        const int32_t* __restrict__ active,
+                                                        double* __restrict__ Yc, double* __restrict__ qc,
+                                                        double* __restrict__ F, double* __restrict__ T,
+                                                        double* __restrict__ box) {
+    const int64_t f = blockIdx.x;
+    if (!active[d.fil_susp[f]]) return;
+    const int64_t S = d.S;
+    const int64_t s0 = d.seg_off[f], N = d.seg_off[f + 1] - s0;
+    const int teth = d.tether[f];
+    const double* Xf = X + 6 * s0;
+    __shared__ double sq[kMaxSeg][4];
+    __shared__ double st[kMaxSeg][3];
+    for (int64_t n = threadIdx.x; n < N; n += 64) {
+        V3 u = ldx(Xf, 3 + 3 * n);
+        if (teth && n == 0) u = v3(0, 0, 0);
+        const Q4 q = qmul(qexp(u), ldq(qj, S, s0 + n));
+        stq(qc, S, s0 + n, q);
+        sq[n][0] = q.w; sq[n][1] = q.x; sq[n][2] = q.y; sq[n][3] = q.z;
+        const V3 t = frame_t(q);
+        st[n][0] = t.x; st[n][1] = t.y; st[n][2] = t.z;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // robot-arm positions and the filament's bounding box (used by the steric pass)
+        V3 y = teth ? v3(d.base[3 * f], d.base[3 * f + 1], d.base[3 * f + 2]) : ldx(Xf, 0);
+        st3(Yc, S, s0, y);
+        V3 lo = y, hi = y;
+        for (int64_t n = 1; n < N; n++) {
+            y = y + (0.5 * d.dL) * v3(st[n - 1][0] + st[n][0], st[n - 1][1] + st[n][1], st[n - 1][2] + st[n][2]);
+            st3(Yc, S, s0 + n, y);
+            lo = v3(fmin(lo.x, y.x), fmin(lo.y, y.y), fmin(lo.z, y.z));
+            hi = v3(fmax(hi.x, y.x), fmax(hi.y, y.y), fmax(hi.z, y.z));
+        }
+        double* b = box + 6 * f;
+        b[0] = lo.x; b[1] = lo.y; b[2] = lo.z;
+        b[3] = hi.x; b[4] = hi.y; b[5] = hi.z;
+    }
+    for (int64_t n = threadIdx.x; n < N; n += 64) {
+        const Q4 qn{sq[n][0], sq[n][1], sq[n][2], sq[n][3]};
+        V3 lp = v3(0, 0, 0), lm = v3(0, 0, 0), mp = v3(0, 0, 0), mm = v3(0, 0, 0);
+        if (n + 1 < N) {
+            lp = ldx(Xf, 3 + 3 * N + 3 * n);
+            mp = joint_moment(qn, Q4{sq[n + 1][0], sq[n + 1][1], sq[n + 1][2], sq[n + 1][3]},
+                              joint_kappa(d, f, n, tt), d.dL, d.KB, d.KT);
+        }
+        if (n > 0) {
+            lm = ldx(Xf, 3 + 3 * N + 3 * (n - 1));
+            mm = joint_moment(Q4{sq[n - 1][0], sq[n - 1][1], sq[n - 1][2], sq[n - 1][3]}, qn,
+                              joint_kappa(d, f, n - 1, tt), d.dL, d.KB, d.KT);
+        }
+        V3 fc = lp - lm + v3(d.grav[0], d.grav[1], d.grav[2]);
+        V3 tc = (0.5 * d.dL) * cross(v3(st[n][0], st[n][1], st[n][2]), lp + lm) + (mp - mm);
+        if (teth && n == 0) {
+            fc = fc + ldx(Xf, 0);
+            tc = tc + ldx(Xf, 3);
+        }
+        st3(F, S, s0 + n, fc);
+        st3(T, S, s0 + n, tc);
+    }
+}
+
+int state_forces_launch(const SimDev& d, const double* X, const double* qj, double tt, const int32_t* active,
+                        double* Yc, double* qc, double* F, double* T, double* box, hipStream_t st) {
+    if (d.M == 0) return FIL_OK;
+    state_forces_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, X, qj, tt, active, Yc, qc, F, T, box);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+// ---------------------------------------------------------------- steric barrier
+// F^B_n = sum_m F^S ((4a^2 chi^2 - r^2)/(4a^2 (chi^2-1)))^4 r_nm/(2a) for r < 2 chi a,
+// excluding m = n and same-filament neighbours (Sec. 2.6).  The block of target
+// filament f tests the bounding boxes of its suspension's filaments 64 at a time
+// (one per lane), then walks the segments of every filament within the cutoff
+// with wave-uniform (scalar) loads.  It finishes the force F^H = F^C + F^B +
+// gravity and writes the mobility source record of each of its segments.
+__global__ void __launch_bounds__(64) steric_pack_kernel(SimDev d, const double* __restrict__ Yc,
+                                                       const double* __restrict__ box,
+                                                       const int32_t* __restrict__ active, double* __restrict__ F,
+                                                       const double* __restrict__ T, int prec, void* __restrict__ pk) {
+    const int64_t f = blockIdx.x;
+    const int32_t isus = d.fil_susp[f];
+    if (!active[isus]) return;
+    const int64_t S = d.S;
+    const int64_t s0 = d.seg_off[f], N = d.seg_off[f + 1] - s0;
+    const int lane = threadIdx.x;  // N <= 64
+    const bool valid = lane < N;
+    const int64_t sn = s0 + (valid ? lane : N - 1);
+    const double y0 = Yc[sn], y1 = Yc[S + sn], y2 = Yc[2 * S + sn];
+    double fx = 0, fy = 0, fz = 0;
+    if (d.FS != 0.0) {
+        const double rc = 2.0 * d.chi * d.a, rc2 = rc * rc;
+        const double k4 = 4.0 * d.a * d.a * d.chi * d.chi, kden = 1.0 / (4.0 * d.a * d.a * (d.chi * d.chi - 1.0));
+        const double fscale = d.FS / (2.0 * d.a);
+        const double* bf = box + 6 * f;
+        const double lo0 = bf[0], lo1 = bf[1], lo2 = bf[2], hi0 = bf[3], hi1 = bf[4], hi2 = bf[5];
+        const int64_t g0 = d.susp_fil_off[isus], g1 = d.susp_fil_off[isus + 1];
+        for (int64_t gb = g0; gb < g1; gb += 64) {
+            bool near = false;
+            const int64_t g = gb + lane;
+            if (g < g1) {
+                const double* bx = box + 6 * g;
+                const double gx = fmax(0.0, fmax(bx[0] - hi0, lo0 - bx[3]));
+                const double gy = fmax(0.0, fmax(bx[1] - hi1, lo1 - bx[4]));
+                const double gz = fmax(0.0, fmax(bx[2] - hi2, lo2 - bx[5]));
+                near = gx * gx + gy * gy + gz * gz < rc2;
+            }
+            unsigned long long mask = __ballot(near);
+            while (mask) {
+                const int l = __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+                const int64_t gg = gb + l;
+                const int64_t m0 = d.seg_off[gg];
+                const int ng = (int)(d.seg_off[gg + 1] - m0);  // <= 64
+                // one coalesced load of the neighbour's positions, then lane broadcasts
+                const int64_t ml = m0 + (lane < ng ? lane : 0);
+                const double p0 = Yc[ml], p1 = Yc[S + ml], p2 = Yc[2 * S + ml];
+                for (int q = 0; q < ng; q++) {
+                    const int64_t m = m0 + q;
+                    const double rx = y0 - readlane_f64(p0, q), ry = y1 - readlane_f64(p1, q),
+                                 rz = y2 - readlane_f64(p2, q);
+                    const double r2 = rx * rx + ry * ry + rz * rz;
+                    const bool excluded = m == sn || (gg == f && (m == sn + 1 || m + 1 == sn));
+                    if (r2 < rc2 && !excluded) {
+                        const double bb = (k4 - r2) * kden;
+                        const double b2 = bb * bb;
+                        const double sc = fscale * b2 * b2;
+                        fx += sc * rx;
+                        fy += sc * ry;
+                        fz += sc * rz;
+                    }
+                }
+            }
+        }
+    }
+    if (valid) {
+        fx += F[sn];
+        fy += F[S + sn];
+        fz += F[2 * S + sn];
+        F[sn] = fx;
+        F[S + sn] = fy;
+        F[2 * S + sn] = fz;
+        rpy_pack_record(prec, pk, sn, y0, y1, y2, fx, fy, fz, T[sn], T[S + sn], T[2 * S + sn]);
+    }
+}
+
+int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, const int32_t* active, double* F,
+                       const double* T, int prec, void* pk, hipStream_t st) {
+    if (d.M == 0) return FIL_OK;
+    steric_pack_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, Yc, box, active, F, T, prec, pk);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+// ---------------------------------------------------------------- residual
+// f^1 = Y_1 - a1 Y_1^j - a2 Y_1^{j-1} - b dt V_1
+// f^2_n = u_n - g u_n^j - b dt dexpinv_{u_n}(Omega_n)
+// f^3_n = Y_n - a1 Y_n^j - a2 Y_n^{j-1} - b dt V_n
+// plus max|f| per suspension (as the bit pattern of a non-negative double, so an
+// integer atomicMax orders it; a NaN compares above every finite value).
+__global__ void __launch_bounds__(256) residual_kernel(SimDev d, BdfCoef bc, const double* __restrict__ X,
+                                                     const double* __restrict__ Xj, const double* __restrict__ Yc,
+                                                     const double* __restrict__ Yj, const double* __restrict__ Yjm1,
+                                                     const double* __restrict__ V, const double* __restrict__ W,
+                                                     const double* __restrict__ part, int K,
+                                                     const int32_t* __restrict__ active, double* __restrict__ fout,
+                                                     unsigned long long* __restrict__ resbits,
+                                                     unsigned long long* __restrict__ resbits_next) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the other buffer is zeroed for the next evaluation (the host has read it)
+    if (blockIdx.x == 0)
+        for (int64_t i = threadIdx.x; i < d.nsusp; i += blockDim.x) resbits_next[i] = 0ull;
+    double amax = 0.0;
+    int32_t isus = -1;
+    if (s < d.S) {
+        const int32_t f = d.seg_fil[s];
+        isus = d.fil_susp[f];
+        if (active[isus]) {
+            const int64_t s0 = d.seg_off[f], N = d.seg_off[f + 1] - s0, n = s - s0;
+            const int teth = d.tether[f];
+            const int64_t S = d.S;
+            const double bdt = bc.b * d.dt;
+            const double* Xf = X + 6 * s0;
+            double* ff = fout + 6 * s0;
+            V3 vel, om;
+            if (part) {
+                // fixed-order sum of the mobility's K source-chunk partials
+                double acc[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 8
+                for (int k = 0; k < K; k++) {
+                    const double* pp = part + (int64_t)k * 6 * S + s;
+#pragma unroll
+                    for (int c = 0; c < 6; c++) acc[c] += pp[c * S];
+                }
+                vel = v3(acc[0], acc[1], acc[2]);
+                om = v3(acc[3], acc[4], acc[5]);
+            } else {
+                vel = ld3(V, S, s);
+                om = ld3(W, S, s);
+            }
+            const V3 yres = ld3(Yc, S, s) - bc.a1 * ld3(Yj, S, s) - bc.a2 * ld3(Yjm1, S, s) - bdt * vel;
+            V3 u = ldx(Xf, 3 + 3 * n), uj = ldx(Xj + 6 * s0, 3 + 3 * n);
+            if (teth && n == 0) u = uj = v3(0, 0, 0);
+            const V3 ures = u - bc.g * uj - bdt * dexpinv(u, om);
+            const int64_t ry = n == 0 ? 0 : 3 + 3 * N + 3 * (n - 1);
+            ff[ry] = yres.x;
+            ff[ry + 1] = yres.y;
+            ff[ry + 2] = yres.z;
+            ff[3 + 3 * n] = ures.x;
+            ff[4 + 3 * n] = ures.y;
+            ff[5 + 3 * n] = ures.z;
+            amax = fmax(fmax(fmax(fabs(yres.x), fabs(yres.y)), fmax(fabs(yres.z), fabs(ures.x))),
+                        fmax(fabs(ures.y), fabs(ures.z)));
+            if (!(yres.x == yres.x && yres.y == yres.y && yres.z == yres.z && ures.x == ures.x &&
+                  ures.y == ures.y && ures.z == ures.z))
+                amax = __longlong_as_double(0x7ff8000000000000ll);
+        }
+    }
+    // one atomic per wave for the wave's leading suspension, one per lane otherwise
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(amax);
+    const int32_t first = __shfl(isus, 0, 64);
+    unsigned long long m = isus == first ? bits : 0ull;
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_xor(m, o, 64);
+        m = other > m ? other : m;
+    }
+    if ((threadIdx.x & 63) == 0 && first >= 0 && active[first]) atomicMax(&resbits[first], m);
+    if (isus != first && isus >= 0 && active[isus]) atomicMax(&resbits[isus], bits);
+}
+
+int residual_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* Xj, const double* Yc,
+                    const double* Yj, const double* Yjm1, const double* V, const double* W, const double* part, int K,
+                    const int32_t* active, double* f, unsigned long long* resbits, unsigned long long* resbits_next,
+                    hipStream_t st) {
+    if (d.S > 0)
+        residual_kernel<<<(unsigned)ceil_div(d.S, 256), 256, 0, st>>>(d, bc, X, Xj, Yc, Yj, Yjm1, V, W, part, K,
+                                                                     active, f, resbits, resbits_next);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+// ---------------------------------------------------------------- warm start
+// step 0: (Y_1^0, 0, 0); step 1: (2Y_1^1 - Y_1^0, u^1, Lambda^1); later steps
+// extrapolate Y_1 and the multipliers linearly and reuse u^j.
+__global__ void __launch_bounds__(256) initial_guess_kernel(SimDev d, int64_t step, const double* __restrict__ Yj,
+                                                          const double* __restrict__ Yjm1,
+                                                          const double* __restrict__ Xj,
+                                                          const double* __restrict__ Xjm1,
+                                                          const int32_t* __restrict__ active,
+                                                          double* __restrict__ X0) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= d.S) return;
+    const int32_t f = d.seg_fil[s];
+    if (!active[d.fil_susp[f]]) return;
+    const int64_t s0 = d.seg_off[f], N = d.seg_off[f + 1] - s0, n = s - s0;
+    const int teth = d.tether[f];
+    // the six slots this segment owns: Y_1 / lambda_1 (n == 0) or Lambda_{n-1/2}, then u_n / lambda_2
+    const int64_t r0 = 6 * s0 + (n == 0 ? 0 : 3 + 3 * N + 3 * (n - 1));
+    const int64_t r1 = 6 * s0 + 3 + 3 * n;
+    for (int i = 0; i < 3; i++) {
+        double x0, x1;
+        if (step == 0) {
+            x0 = (n == 0 && !teth) ? Yj[i * d.S + s] : 0.0;
+            x1 = 0.0;
+        } else {
+            if (n == 0 && !teth) x0 = 2.0 * Yj[i * d.S + s] - Yjm1[i * d.S + s];
+            else x0 = step >= 2 ? 2.0 * Xj[r0 + i] - Xjm1[r0 + i] : Xj[r0 + i];
+            if (n == 0 && teth) x1 = step >= 2 ? 2.0 * Xj[r1 + i] - Xjm1[r1 + i] : Xj[r1 + i];
+            else x1 = Xj[r1 + i];
+        }
+        X0[r0 + i] = x0;
+        X0[r1 + i] = x1;
+    }
+}
+
+int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const double* Yjm1, const double* Xj,
+                         const double* Xjm1, const int32_t* active, double* X0, hipStream_t st) {
+    if (d.S == 0) return FIL_OK;
+    initial_guess_kernel<<<(unsigned)ceil_div(d.S, 256), 256, 0, st>>>(d, step, Yj, Yjm1, Xj, Xjm1, active, X0);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+// ---------------------------------------------------------------- J0 assembly
+struct M33 {
+    double m[9];
+};
+__device__ __forceinline__ M33 mzero() {
+    M33 r;
+    for (int i = 0; i < 9; i++) r.m[i] = 0.0;
+    return r;
+}
+__device__ __forceinline__ M33 meye(double s) {
+    M33 r = mzero();
+    r.m[0] = r.m[4] = r.m[8] = s;
+    return r;
+}
+// [v x] w = v x w
+__device__ __forceinline__ M33 mskew(V3 v) {
+    M33 r;
+    r.m[0] = 0; r.m[1] = -v.z; r.m[2] = v.y;
+    r.m[3] = v.z; r.m[4] = 0; r.m[5] = -v.x;
+    r.m[6] = -v.y; r.m[7] = v.x; r.m[8] = 0;
+    return r;
+}
+__device__ __forceinline__ M33 mscale(M33 a, double s) {
+    for (int i = 0; i < 9; i++) a.m[i] *= s;
+    return a;
+}
+__device__ __forceinline__ M33 madd(M33 a, M33 b) {
+    for (int i = 0; i < 9; i++) a.m[i] += b.m[i];
+    return a;
+}
+__device__ __forceinline__ M33 mmul(const M33& a, const M33& b) {
+    M33 r;
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++)
+            r.m[3 * i + j] = a.m[3 * i] * b.m[j] + a.m[3 * i + 1] * b.m[3 + j] + a.m[3 * i + 2] * b.m[6 + j];
+    return r;
+}
+__device__ __forceinline__ M33 mouter(V3 a, V3 b) {
+    M33 r;
+    const double av[3] = {a.x, a.y, a.z}, bv[3] = {b.x, b.y, b.z};
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) r.m[3 * i + j] = av[i] * bv[j];
+    return r;
+}
+
+struct SegFrame {
+    V3 t, mu, nu;
+};
+
+// Frame-vector approximation of dM_{k+1/2}/du_k (second = false) or du_{k+1}
+// (second = true), Appendix B.2; a = frame of segment k, b = frame of k+1.
+__device__ M33 dmoment_du(const SegFrame& a, const SegFrame& b, V3 kap, double dL, double KB, double KT,
+                          bool second) {
+    const double beta = (dot(b.mu, a.nu) - dot(a.mu, b.nu)) / (2.0 * dL) - kap.x;
+    const V3 gv = cross(a.nu, b.mu) - cross(a.mu, b.nu);
+    const V3 ts = a.t + b.t;
+    M33 bend;
+    if (!second) bend = mmul(mskew(-1.0 * b.t), mskew(-1.0 * a.t));   // [x t_{k+1}][x t_k]
+    else bend = mmul(mskew(a.t), mskew(-1.0 * b.t));                  // [t_k x][x t_{k+1}]
+    const SegFrame& own = second ? b : a;
+    M33 r = madd(mscale(bend, KB / dL),
+                 madd(mscale(mskew(-1.0 * own.mu), -0.5 * KB * kap.y), mscale(mskew(-1.0 * own.nu), -0.5 * KB * kap.z)));
+    r = madd(r, mscale(mskew(-1.0 * own.t), 0.5 * KT * beta));
+    r = madd(r, mscale(mouter(ts, gv), (second ? -1.0 : 1.0) * 0.5 * KT / (2.0 * dL)));
+    return r;
+}
+
+// ---------------------------------------------------------------- J0 blocks
+// Per-filament data staged in LDS for the J0 blocks: frame (t, mu, nu), u, and the
+// internal torque T^C + T^E of every segment.
+struct J0Ctx {
+    const double (*sh)[15];
+    const double* Xf;
+    int N, teth;
+    int64_t f;
+    double tt, cT, cR;
+};
+
+__device__ __forceinline__ SegFrame frame_at(const J0Ctx& c, int n) {
+    const double* p = c.sh[n];
+    return SegFrame{v3(p[0], p[1], p[2]), v3(p[3], p[4], p[5]), v3(p[6], p[7], p[8])};
+}
+
+// Block (I, J) of the explicit approximate Jacobian (Appendix B.2) in the
+// original ordering.  Row blocks: 0 -> f^1, 1..N -> f^2_m (m = I-1), N+1..2N-1 ->
+// f^3_m (m = I-N).  Column blocks: 0 -> Y_1 (lambda_1 when clamped), 1..N -> u_n
+// (n = J-1; lambda_2 for n = 0 when clamped), N+1..2N-1 -> Lambda of joint J-N-1.
+// cT = b dt/(6 pi eta a), cR = b dt/(8 pi eta a^3).
+__device__ M33 j0_block(const SimDev& d, const J0Ctx& c, int I, int Jb) {
+    const int N = c.N;
+    const int teth = c.teth;
+    M33 B = mzero();
+    if (I == 0) {  // f^1
+        if (Jb == 0) B = meye(teth ? -c.cT : 1.0);
+        else if (N > 1 && Jb == N + 1) B = meye(-c.cT);
+    } else if (I > N) {  // f^3_m, m = 1..N-1
+        const int m = I - N;
+        if (Jb == 0) {
+            if (!teth) B = meye(1.0);
+        } else if (Jb <= N) {
+            const int n = Jb - 1;
+            if (n <= m && !(n == 0 && teth)) {
+                const double w = (n == 0 || n == m) ? 1.0 : 2.0;
+                B = mscale(mskew(-1.0 * frame_at(c, n).t), 0.5 * d.dL * w);
+            }
+        } else {
+            const int k = Jb - N - 1;
+            if (k == m - 1) B = meye(c.cT);
+            else if (k == m) B = meye(-c.cT);
+        }
+    } else {  // f^2_m
+        const int m = I - 1;
+        const double* pm = c.sh[m];
+        const V3 um = v3(pm[9], pm[10], pm[11]);
+        const M33 U = mskew(um), U2 = mmul(U, U);
+        const M33 Tay = madd(madd(meye(1.0), mscale(U, -0.5)), mscale(U2, 1.0 / 12.0));
+        const SegFrame fm = frame_at(c, m);
+        if (Jb > N) {
+            const int k = Jb - N - 1;
+            if (k == m - 1 || k == m) B = mscale(mmul(Tay, mskew(fm.t)), -c.cR * 0.5 * d.dL);
+        } else if (Jb >= 1) {
+            const int n = Jb - 1;
+            if (n == m + 1 && m + 1 < N) {
+                const M33 dM = dmoment_du(fm, frame_at(c, m + 1), joint_kappa(d, c.f, m, c.tt), d.dL, d.KB, d.KT, true);
+                B = mscale(mmul(Tay, dM), -c.cR);
+            } else if (n == m - 1 && !(m == 1 && teth)) {
+                const M33 dM =
+                    dmoment_du(frame_at(c, m - 1), fm, joint_kappa(d, c.f, m - 1, c.tt), d.dL, d.KB, d.KT, false);
+                B = mscale(mmul(Tay, dM), c.cR);
+            } else if (n == m) {
+                if (teth && m == 0) {
+                    B = meye(-c.cR);
+                } else {
+                    V3 ls = v3(0, 0, 0);
+                    if (m + 1 < N) ls = ls + ldx(c.Xf, 3 + 3 * N + 3 * m);
+                    if (m >= 1) ls = ls + ldx(c.Xf, 3 + 3 * N + 3 * (m - 1));
+                    M33 dT = mscale(mmul(mskew(-1.0 * ls), mskew(-1.0 * fm.t)), 0.5 * d.dL);
+                    if (m + 1 < N)
+                        dT = madd(dT, dmoment_du(fm, frame_at(c, m + 1), joint_kappa(d, c.f, m, c.tt), d.dL, d.KB, d.KT,
+                                                 false));
+                    if (m >= 1)
+                        dT = madd(dT, mscale(dmoment_du(frame_at(c, m - 1), fm, joint_kappa(d, c.f, m - 1, c.tt), d.dL,
+                                                        d.KB, d.KT, true),
+                                             -1.0));
+                    const V3 Tv = v3(pm[12], pm[13], pm[14]);
+                    const M33 XT = mskew(-1.0 * Tv), XuT = mskew(-1.0 * cross(um, Tv));
+                    M33 inner = madd(dT, mscale(madd(XT, mmul(U, dT)), -0.5));
+                    inner = madd(inner, mscale(madd(madd(XuT, mmul(U, XT)), mmul(U2, dT)), 1.0 / 12.0));
+                    B = madd(meye(1.0), mscale(inner, -c.cR));
+                }
+            }
+        }
+    }
+    return B;
+}
+
+// ---------------------------------------------------------------- banded J0
+// The robot-arm rows f^3_m involve every u_n with n <= m.  Replacing them by
+// differences D_1 = f^3_1 - f^1, D_m = f^3_m - f^3_{m-1} (an invertible row
+// operation) leaves, in the interleaved order of 3-blocks
+//   columns: Y_1, u_0, Lambda_0, u_1, Lambda_1, ..., Lambda_{N-2}, u_{N-1}
+//   rows:    f^1, f^2_0, D_1,  f^2_1, D_2, ...,     D_{N-1},     f^2_{N-1}
+// a block-pentadiagonal matrix: scalar bandwidths kl = ku = 8.  Its LU with
+// partial pivoting (upper bandwidth kl + ku after fill-in) is computed once per
+// step and applied in every Broyden iteration; J0^{-1} v = (L J0)^{-1} (L v).
+__device__ __forceinline__ int orig_col(int C, int N) {
+    return C == 0 ? 0 : ((C & 1) ? 1 + (C - 1) / 2 : N + 1 + (C - 2) / 2);
+}
+// offset in the [6N] unknown / residual layout of interleaved 3-block P (column view)
+__device__ __forceinline__ int slot_of(int P, int N) {
+    return P == 0 ? 0 : ((P & 1) ? 3 + 3 * ((P - 1) / 2) : 3 + 3 * N + 3 * ((P - 2) / 2));
+}
+
+__global__ void __launch_bounds__(256) j0_band_assemble_kernel(SimDev d, BdfCoef bc, const double* __restrict__ X,
+                                                             const double* __restrict__ qc,
+                                                             const double* __restrict__ Tint, double tt,
+                                                             const int32_t* __restrict__ active,
+                                                             double* __restrict__ AB) {
+    const int64_t f = blockIdx.x;
+    if (!active[d.fil_susp[f]]) return;
+    const int64_t S = d.S;
+    const int64_t s0 = d.seg_off[f];
+    const int N = (int)(d.seg_off[f + 1] - s0);
+    const int n6 = 6 * N;
+    double* ab = AB + 6 * s0 * kBandW;
+    __shared__ double sh[kMaxSeg][15];  // t, mu, nu, u, T
+    const double* Xf = X + 6 * s0;
+    const int teth = d.tether[f];
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const Q4 q = ldq(qc, S, s0 + n);
+        const V3 t = frame_t(q), mu = frame_mu(q), nu = frame_nu(q);
+        V3 u = ldx(Xf, 3 + 3 * n);
+        if (teth && n == 0) u = v3(0, 0, 0);
+        const V3 Tm = ld3(Tint, S, s0 + n);
+        const double v[15] = {t.x, t.y, t.z, mu.x, mu.y, mu.z, nu.x, nu.y, nu.z, u.x, u.y, u.z, Tm.x, Tm.y, Tm.z};
+        for (int i = 0; i < 15; i++) sh[n][i] = v[i];
+    }
+    for (int e = threadIdx.x; e < n6 * kBandW; e += blockDim.x) ab[e] = 0.0;
+    __syncthreads();
+    J0Ctx c{sh, Xf, N, teth, f, tt, bc.b * d.dt / (6.0 * kPi * d.eta * d.a),
+            bc.b * d.dt / (8.0 * kPi * d.eta * d.a * d.a * d.a)};
+    const int nb = 2 * N;
+    for (int item = threadIdx.x; item < nb * 5; item += blockDim.x) {
+        const int R = item / 5, C = R + item % 5 - 2;
+        if (C < 0 || C >= nb) continue;
+        const int Jo = orig_col(C, N);
+        M33 B;
+        if (R == 0) B = j0_block(d, c, 0, Jo);
+        else if (R & 1) B = j0_block(d, c, 1 + (R - 1) / 2, Jo);
+        else {
+            const int m = R / 2;
+            B = madd(j0_block(d, c, N + m, Jo), mscale(j0_block(d, c, m == 1 ? 0 : N + m - 1, Jo), -1.0));
+        }
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) {
+                const int i = 3 * R + a, j = 3 * C + b;
+                ab[(int64_t)i * kBandW + (j - i + kKL)] = B.m[3 * a + b];
+            }
+    }
+}
+
+// Copies n8 doubles (an even count, 16-byte aligned source) into LDS with 16
+// double2 loads in flight per lane; one wave.
+__device__ __forceinline__ void stage_band(const double* __restrict__ g, double* l, int n8, int lane) {
+    const double2* g2 = reinterpret_cast<const double2*>(g);
+    double2* l2 = reinterpret_cast<double2*>(l);
+    const int cnt = n8 / 2;
+    for (int base = 0; base < cnt; base += 64 * 16) {
+        double2 v[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int idx = base + q * 64 + lane;
+            v[q] = g2[idx < cnt ? idx : cnt - 1];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int idx = base + q * 64 + lane;
+            if (idx < cnt) l2[idx] = v[q];
+        }
+    }
+}
+
+// band element (i, j) of the LDS copy
+#define AB_(i, j) ab[(i) * kBandW + ((j) - (i) + kKL)]
+
+// LU with partial pivoting of every filament's banded system, one wave each.
+__global__ void __launch_bounds__(64) j0_band_factor_kernel(SimDev d, const int32_t* __restrict__ active,
+                                                          double* __restrict__ AB, int32_t* __restrict__ ipiv,
+                                                          int32_t* __restrict__ flag) {
+    const int64_t f = blockIdx.x;
+    if (!active[d.fil_susp[f]]) return;
+    const int64_t s0 = d.seg_off[f];
+    const int n = 6 * (int)(d.seg_off[f + 1] - s0);
+    double* gab = AB + 6 * s0 * kBandW;
+    int32_t* gp = ipiv + 6 * s0;
+    __shared__ double ab[6 * kMaxSeg * kBandW];
+    const int lane = threadIdx.x;
+    stage_band(gab, ab, n * kBandW, lane);
+    int bad = 0;
+    __syncthreads();
+    for (int j = 0; j < n; j++) {
+        const int last = min(n - 1, j + kKL);
+        double v = -1.0;
+        int idx = j;
+        if (lane <= kKL && j + lane <= last) {
+            v = fabs(AB_(j + lane, j));
+            idx = j + lane;
+        }
+        for (int o = 8; o > 0; o >>= 1) {
+            const double v2 = __shfl_xor(v, o, 64);
+            const int i2 = __shfl_xor(idx, o, 64);
+            if (v2 > v || (v2 == v && i2 < idx)) {
+                v = v2;
+                idx = i2;
+            }
+        }
+        const int p = __shfl(idx, 0, 64);
+        const double pv = __shfl(v, 0, 64);
+        if (!(pv > 0.0)) bad = 1;
+        if (lane == 0) gp[j] = p;
+        const int cend = min(n - 1, j + kKU + kKL);
+        if (p != j) {
+            for (int cc = j + lane; cc <= cend; cc += 64) {
+                const double t = AB_(j, cc);
+                AB_(j, cc) = AB_(p, cc);
+                AB_(p, cc) = t;
+            }
+        }
+        __syncthreads();
+        const double piv = AB_(j, j);
+        if (lane >= 1 && lane <= kKL && j + lane <= last) AB_(j + lane, j) = AB_(j + lane, j) / piv;
+        __syncthreads();
+        const int nr = last - j, nc = cend - j;
+        for (int e = lane; e < nr * nc; e += 64) {
+            const int i = j + 1 + e / nc, cc = j + 1 + e % nc;
+            AB_(i, cc) -= AB_(i, j) * AB_(j, cc);
+        }
+        __syncthreads();
+    }
+    for (int e = lane; e < n * kBandW; e += 64) gab[e] = ab[e];
+    if (lane == 0) flag[f] = bad;
+}
+
+// out = J0^{-1} v for every active filament: L v (row differences) in the
+// interleaved order, then the pivoted forward substitution and the back
+// substitution.  The pending entries of each sweep live in a ring of lanes
+// (entry i in lane i mod 16, resp. mod 32), so a step is a few wave-uniform
+// lane reads and one fused update, with no barrier and no lane shuffling.
+__global__ void __launch_bounds__(64) j0_band_solve_kernel(SimDev d, const double* __restrict__ AB,
+                                                         const int32_t* __restrict__ ipiv,
+                                                         const double* __restrict__ v,
+                                                         const int32_t* __restrict__ active,
+                                                         double* __restrict__ out) {
+    const int64_t f = blockIdx.x;
+    if (!active[d.fil_susp[f]]) return;
+    const int64_t s0 = d.seg_off[f];
+    const int N = (int)(d.seg_off[f + 1] - s0);
+    const int n = 6 * N;
+    const double* gab = AB + 6 * s0 * kBandW;
+    const double* vf = v + 6 * s0;
+    __shared__ double ab[6 * kMaxSeg * kBandW];
+    __shared__ double y[6 * kMaxSeg];
+    __shared__ int ip[6 * kMaxSeg];
+    const int lane = threadIdx.x;
+    stage_band(gab, ab, n * kBandW, lane);
+    for (int i = lane; i < n; i += 64) {
+        ip[i] = ipiv[6 * s0 + i];
+        const int R = i / 3, a = i % 3;
+        double b;
+        if (R == 0 || (R & 1)) b = vf[slot_of(R, N) + a];
+        else {
+            const int m = R / 2;  // D_m = f^3_m - (m == 1 ? f^1 : f^3_{m-1})
+            const double prev = m == 1 ? vf[a] : vf[3 + 3 * N + 3 * (m - 2) + a];
+            b = vf[3 + 3 * N + 3 * (m - 1) + a] - prev;
+        }
+        y[i] = b;
+    }
+    __syncthreads();
+    // the diagonal of U is only ever divided by: keep its reciprocal in place
+    for (int i = lane; i < n; i += 64) ab[i * kBandW + kKL] = 1.0 / ab[i * kBandW + kKL];
+    __syncthreads();
+    // forward sweep: ring of 16 lanes holds y[j .. j+15].  The pivot index, the
+    // multiplier and the entry joining the ring are read one step ahead, from
+    // clamped (always valid) addresses, and applied with selects.
+    double w = (lane < 16 && lane < n) ? y[lane] : 0.0;
+    auto fwd_mult = [&](int jj) {
+        const int off = (lane - (jj & 15)) & 15;
+        const int offc = off <= kKL ? off : kKL;
+        const int row = min(jj + offc, n - 1);
+        const double L = ab[row * kBandW + (kKL - offc)];
+        return (lane < 16 && off >= 1 && off <= kKL && jj + off < n) ? L : 0.0;
+    };
+    int ipn = ip[0];
+    double Ln = fwd_mult(0);
+    double yin = y[min(16, n - 1)];
+    for (int j = 0; j < n; j++) {
+        const int h = j & 15;
+        const int hp = __builtin_amdgcn_readfirstlane(ipn) & 15;
+        const double L = Ln;
+        const double yi = j + 16 < n ? yin : 0.0;
+        const int j1 = min(j + 1, n - 1);
+        ipn = ip[j1];
+        Ln = fwd_mult(j + 1);
+        yin = y[min(j + 17, n - 1)];
+        const double vh = readlane_f64(w, h), vp = readlane_f64(w, hp);
+        w = lane == hp ? vh : w;
+        w -= L * vp;  // vp: the pivot row now at the head; L = 0 off the kKL entries below it
+        y[j] = vp;
+        w = lane == h ? yi : w;
+    }
+    __syncthreads();
+    // back substitution: ring of 32 lanes holds z[i-31 .. i]
+    constexpr int kU = kKL + kKU;
+    w = 0.0;
+    if (lane < 32) {
+        const int pos = (n - 1) - (((n - 1) - lane) & 31);
+        w = pos >= 0 ? y[pos] : 0.0;
+    }
+    auto bwd_coef = [&](int ii) {
+        const int off = ((ii & 31) - lane) & 31;
+        const int offc = off <= kU ? off : kU;
+        const int row = max(ii - offc, 0);
+        const double U = ab[row * kBandW + (offc + kKL)];
+        return (lane < 32 && off >= 1 && off <= kU && ii - off >= 0) ? U : 0.0;
+    };
+    double Un = bwd_coef(n - 1), dn = ab[(n - 1) * kBandW + kKL], zin = y[max(n - 33, 0)];
+    for (int i = n - 1; i >= 0; i--) {
+        const int h = i & 31;
+        const double U = Un, dv = dn;
+        const double zi = i - 32 >= 0 ? zin : 0.0;
+        const int i1 = max(i - 1, 0);
+        Un = bwd_coef(i1);
+        dn = ab[i1 * kBandW + kKL];
+        zin = y[max(i - 33, 0)];
+        const double xi = readlane_f64(w, h) * dv;
+        w -= U * xi;  // U = 0 off the kKL + kKU entries above the head
+        y[i] = xi;
+        w = lane == h ? zi : w;
+    }
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) out[6 * s0 + slot_of(i / 3, N) + i % 3] = y[i];
+}
+#undef AB_
+
+int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* qc, const double* Tint,
+                     double tt, const int32_t* active, double* AB, int32_t* ipiv, int32_t* flag, hipStream_t st) {
+    if (d.M == 0) return FIL_OK;
+    j0_band_assemble_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, bc, X, qc, Tint, tt, active, AB);
+    j0_band_factor_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, active, AB, ipiv, flag);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+int j0_solve_launch(const SimDev& d, const double* AB, const int32_t* ipiv, const double* v, const int32_t* active,
+                    double* out, hipStream_t st) {
+    if (d.M == 0) return FIL_OK;
+    j0_band_solve_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, AB, ipiv, v, active, out);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+// Partial dot products for one Broyden update of every active suspension; block
+// (b, h) reduces dot h over vector block b: h < k: d_h . fnew; h = k:
+// |fnew - fprev|^2; h = k+1: (fnew - fprev) . fnew.  Vector blocks never
+// straddle suspensions, so every partial belongs to one suspension.
+__global__ void __launch_bounds__(256) multidot_kernel(SimDev d, int k, const double* __restrict__ Dhist,
+                                                     const double* __restrict__ fnew,
+                                                     const double* __restrict__ fprev,
+                                                     const int32_t* __restrict__ active,
+                                                     double* __restrict__ part) {
+    const int64_t b = blockIdx.x;
+    const int h = blockIdx.y;
+    const int32_t isus = d.vblk_susp[b];
+    if (!active[isus]) return;
+    const int64_t e0 = d.vblk_start[b], e1 = d.vblk_start[b + 1];
+    const int64_t n6 = 6 * d.S;
+    double acc = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const double fn = fnew[e];
+        if (h < k) acc = fma(Dhist[(int64_t)h * n6 + e], fn, acc);
+        else {
+            const double df = fn - fprev[e];
+            acc = fma(df, h == k ? df : fn, acc);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[b * (int64_t)d.max_dots + h] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Finishes the update: g = J0^{-1} fnew + sum_h c_h (d_h . fnew);
+// c_k = -g/|df|, d_k = df/|df|, h_{k+1} = g + c_k (d_k . fnew); fprev <- fnew;
+// then the next quasi-Newton step X <- X - h_{k+1}.  Every block re-sums the
+// partial dots of its suspension in the same order, so all blocks agree.
+__global__ void __launch_bounds__(256) broyden_combine_kernel(SimDev d, int k, const double* __restrict__ part,
+                                                            const double* __restrict__ g0,
+                                                            double* __restrict__ Chist, double* __restrict__ Dhist,
+                                                            const double* __restrict__ fnew,
+                                                            double* __restrict__ fprev, double* __restrict__ hvec,
+                                                            double* __restrict__ X, double* __restrict__ dXout,
+                                                            const int32_t* __restrict__ active) {
+    const int64_t b = blockIdx.x;
+    const int32_t isus = d.vblk_susp[b];
+    if (!active[isus]) return;
+    __shared__ double dots[kMaxDots];
+    const int ndot = k + 2;
+    const int64_t pb0 = d.susp_vblk_off[isus], pb1 = d.susp_vblk_off[isus + 1];
+    for (int h = threadIdx.x; h < ndot; h += blockDim.x) {
+        double s = 0.0;
+        for (int64_t p = pb0; p < pb1; p++) s += part[p * (int64_t)d.max_dots + h];
+        dots[h] = s;
+    }
+    __syncthreads();
+    const double nrm = sqrt(dots[k]);
+    const double inrm = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    const double dfdot = dots[k + 1] * inrm;
+    const int64_t n6 = 6 * d.S;
+    const int64_t e0 = d.vblk_start[b], e1 = d.vblk_start[b + 1];
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        double g = g0[e];
+        for (int h = 0; h < k; h++) g = fma(Chist[(int64_t)h * n6 + e], dots[h], g);
+        const double fn = fnew[e];
+        const double c = -g * inrm;
+        const double dd = (fn - fprev[e]) * inrm;
+        Chist[(int64_t)k * n6 + e] = c;
+        Dhist[(int64_t)k * n6 + e] = dd;
+        const double hn = fma(c, dfdot, g);
+        hvec[e] = hn;
+        fprev[e] = fn;
+        X[e] -= hn;
+        if (dXout) dXout[e] = -hn;
+    }
+}
+
+int broyden_update_launch(const SimDev& d, int k, const double* AB, const int32_t* ipiv, double* Chist,
+                          double* Dhist, const double* fnew, double* fprev, double* g0, double* hvec, double* part,
+                          double* X, double* dXout, const int32_t* active, hipStream_t st) {
+    if (d.S == 0) return FIL_OK;
+    int rc = j0_solve_launch(d, AB, ipiv, fnew, active, g0, st);
+    if (rc) return rc;
+    multidot_kernel<<<dim3((unsigned)d.nvblk, (unsigned)(k + 2)), 256, 0, st>>>(d, k, Dhist, fnew, fprev, active, part);
+    broyden_combine_kernel<<<(unsigned)d.nvblk, 256, 0, st>>>(d, k, part, g0, Chist, Dhist, fnew, fprev, hvec, X,
+                                                             dXout, active);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+// X <- X - h (first quasi-Newton step of a solve) and fprev <- f
+__global__ void __launch_bounds__(256) first_step_kernel(SimDev d, const double* __restrict__ h,
+                                                       const double* __restrict__ f, double* __restrict__ fprev,
+                                                       double* __restrict__ X, double* __restrict__ dXout,
+                                                       const int32_t* __restrict__ active) {
+    const int64_t b = blockIdx.x;
+    const int32_t isus = d.vblk_susp[b];
+    if (!active[isus]) return;
+    for (int64_t e = d.vblk_start[b] + threadIdx.x; e < d.vblk_start[b + 1]; e += blockDim.x) {
+        X[e] -= h[e];
+        fprev[e] = f[e];
+        if (dXout) dXout[e] = -h[e];
+    }
+}
+
+int first_step_launch(const SimDev& d, const double* h, const double* f, double* fprev, double* X, double* dXout,
+                      const int32_t* active, hipStream_t st) {
+    if (d.S == 0) return FIL_OK;
+    first_step_kernel<<<(unsigned)d.nvblk, 256, 0, st>>>(d, h, f, fprev, X, dXout, active);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+// ---------------------------------------------------------------- finalise
+// History shift of converged suspensions: Y^{j-1} <- Y^j, Y^j <- Y(X*), q^j <- q(X*),
+// X^{j-1} <- X^j, X^j <- X*.
+__global__ void __launch_bounds__(256) finalize_kernel(SimDev d, const int32_t* __restrict__ commit,
+                                                     const double* __restrict__ Yc, const double* __restrict__ qc,
+                                                     const double* __restrict__ X, double* __restrict__ Yj,
+                                                     double* __restrict__ Yjm1, double* __restrict__ qj,
+                                                     double* __restrict__ Xj, double* __restrict__ Xjm1) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= d.S) return;
+    if (!commit[d.fil_susp[d.seg_fil[s]]]) return;
+    const int64_t S = d.S;
+    for (int i = 0; i < 3; i++) {
+        Yjm1[i * S + s] = Yj[i * S + s];
+        Yj[i * S + s] = Yc[i * S + s];
+    }
+    for (int i = 0; i < 4; i++) qj[i * S + s] = qc[i * S + s];
+    for (int i = 0; i < 6; i++) {
+        Xjm1[6 * s + i] = Xj[6 * s + i];
+        Xj[6 * s + i] = X[6 * s + i];
+    }
+}
+
+int finalize_launch(const SimDev& d, const int32_t* commit, const double* Yc, const double* qc, const double* X,
+                    double* Yj, double* Yjm1, double* qj, double* Xj, double* Xjm1, hipStream_t st) {
+    if (d.S == 0) return FIL_OK;
+    finalize_kernel<<<(unsigned)ceil_div(d.S, 256), 256, 0, st>>>(d, commit, Yc, qc, X, Yj, Yjm1, qj, Xj, Xjm1);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+}  // namespace fil
