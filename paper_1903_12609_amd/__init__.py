@@ -105,7 +105,7 @@ class Sim:
     into suspensions (default: one suspension).  prec: "f64" or "f32tile".
     """
 
-    def __init__(self, fil_off, Y0, q0, params, susp_fil_off=None, prec="f64"):
+    def __init__(self, fil_off, Y0, q0, params, susp_fil_off=None, prec="f64", j0_mode="auto"):
         import ctypes
         import numpy as np
         from ._native import Params
@@ -123,6 +123,7 @@ class Sim:
         P.grav[0], P.grav[1], P.grav[2] = g
         P.dt, P.tol, P.kmax = params["dt"], params.get("tol", 1e-6), int(params.get("kmax", 100))
         P.prec = PREC[prec]
+        P.j0_mode = {"auto": 0, "banded": 1, "dense": 2}[j0_mode]
         P.K0, P.kw, P.omega = params.get("K0", 0.0), params.get("kw", 0.0), params.get("omega", 0.0)
         self.params = P
         Y0 = np.ascontiguousarray(Y0, dtype=np.float64).reshape(self.S, 3)

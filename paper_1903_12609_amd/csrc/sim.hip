@@ -28,7 +28,7 @@ struct fil_sim {
     double *Yj = nullptr, *Yjm1 = nullptr, *qj = nullptr, *Xj = nullptr, *Xjm1 = nullptr;
     double *X = nullptr, *f = nullptr, *fprev = nullptr, *h = nullptr, *g0 = nullptr;
     double *Yc = nullptr, *qc = nullptr, *F = nullptr, *T = nullptr, *V = nullptr, *W = nullptr;
-    double *AB = nullptr, *Chist = nullptr, *Dhist = nullptr, *part = nullptr;
+    double *AB = nullptr, *AinvT = nullptr, *Chist = nullptr, *Dhist = nullptr, *part = nullptr;
     double* box = nullptr;
     int32_t *ipiv = nullptr, *active_d = nullptr, *commit_d = nullptr, *jflag_d = nullptr;
     unsigned long long* resbits_d = nullptr;
@@ -175,8 +175,9 @@ int upload_flags(fil_sim* s, int32_t* dst, const int32_t* src) {
 // factorised; h = J0^{-1} f.
 int begin_solve(fil_sim* s, double* dXout) {
     const double tt = s->t + s->p.dt;
-    TRY(j0_factor_launch(s->d, s->bc, s->X, s->qc, s->T, tt, s->active_d, s->AB, s->ipiv, s->jflag_d, s->st));
-    TRY(j0_solve_launch(s->d, s->AB, s->ipiv, s->f, s->active_d, s->h, s->st));
+    TRY(j0_factor_launch(s->d, s->bc, s->X, s->qc, s->T, tt, s->active_d, s->AB, s->ipiv, s->jflag_d, s->AinvT,
+                         s->st));
+    TRY(j0_solve_launch(s->d, s->AB, s->ipiv, s->AinvT, s->f, s->active_d, s->h, s->st));
     s->k = 0;
     return FIL_OK;
 }
@@ -195,6 +196,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
                   "fil_create: a, eta, dL, dt and tol must be > 0");
     FIL_CHECK_ARG(p->kmax >= 1 && p->kmax < kMaxIter, "fil_create: kmax must be in [1, 255]");
     FIL_CHECK_ARG(p->prec == FIL_PREC_F64 || p->prec == FIL_PREC_F32TILE, "fil_create: unknown precision");
+    FIL_CHECK_ARG(p->j0_mode >= 0 && p->j0_mode <= 2, "fil_create: j0_mode must be 0, 1 or 2");
     FIL_CHECK_ARG(p->FS == 0.0 || p->chi > 1.0, "fil_create: the steric range chi must exceed 1");
     FIL_CHECK_ARG(susp_fil_off[0] == 0, "fil_create: susp_fil_off[0] must be 0");
     for (int64_t i = 0; i < nsusp; i++)
@@ -203,7 +205,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     FIL_CHECK_ARG(fil_seg_off[0] == 0, "fil_create: fil_seg_off[0] must be 0");
     for (int64_t f = 0; f < M; f++) {
         const int64_t N = fil_seg_off[f + 1] - fil_seg_off[f];
-        FIL_CHECK_ARG(N >= 1 && N <= kMaxSeg, "fil_create: filaments need 1..50 segments");
+        FIL_CHECK_ARG(N >= 1 && N <= kMaxSeg, "fil_create: filaments need 1..64 segments");
     }
     const int64_t S = fil_seg_off[M];
     for (int64_t i = 0; i < 4 * S; i++) FIL_CHECK_ARG(std::isfinite(q0[i]), "fil_create: non-finite quaternion");
@@ -230,6 +232,16 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     std::vector<double> base(3 * M);
     for (int64_t f = 0; f < M; f++)
         for (int i = 0; i < 3; i++) base[3 * f + i] = Y0[3 * seg_off[f] + i];
+    int max_seg = 1;
+    std::vector<int64_t> dense_off(M);
+    int64_t dense_tot = 0;
+    for (int64_t f = 0; f < M; f++) {
+        const int64_t N = seg_off[f + 1] - seg_off[f];
+        max_seg = std::max<int>(max_seg, (int)N);
+        dense_off[f] = dense_tot;
+        dense_tot += 36 * N * N;
+    }
+    const bool dense = p->j0_mode == 2 || (p->j0_mode == 0 && (size_t)dense_tot * sizeof(double) <= kDenseInvBytes);
     std::vector<int64_t> vblk_start, susp_vblk_off(nsusp + 1);
     std::vector<int32_t> vblk_susp;
     std::vector<int64_t> sfo(susp_fil_off, susp_fil_off + nsusp + 1);
@@ -247,7 +259,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
 
     // ---- device allocations
     int rc = FIL_OK;
-    int64_t *d_seg_off, *d_susp_seg_off, *d_susp_fil_off, *d_vblk_start, *d_susp_vblk_off;
+    int64_t *d_seg_off, *d_susp_seg_off, *d_susp_fil_off, *d_vblk_start, *d_susp_vblk_off, *d_dense_off = nullptr;
     int32_t *d_fil_susp, *d_seg_fil, *d_teth, *d_vblk_susp;
     double *d_base, *d_phase = nullptr;
     const size_t n6 = 6 * (size_t)S;
@@ -262,6 +274,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     A(s->X, n6) A(s->f, n6) A(s->fprev, n6) A(s->h, n6) A(s->g0, n6)
     A(s->Yc, 3 * S) A(s->qc, 4 * S) A(s->F, 3 * S) A(s->T, 3 * S) A(s->V, 3 * S) A(s->W, 3 * S)
     A(s->AB, n6 * kBandW) A(s->ipiv, n6)
+    if (dense) { A(s->AinvT, dense_tot) A(d_dense_off, M) }
     A(s->Chist, (size_t)p->kmax * n6) A(s->Dhist, (size_t)p->kmax * n6) A(s->part, (size_t)nvblk * max_dots)
     A(s->box, 6 * M) A(s->active_d, nsusp) A(s->commit_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 2 * nsusp)
 #undef A
@@ -303,6 +316,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         TRY(upload(d_seg_off, seg_off));
         TRY(upload(d_susp_seg_off, susp_seg_off));
         TRY(upload(d_susp_fil_off, sfo));
+        if (dense) TRY(upload(d_dense_off, dense_off));
         TRY(upload(d_vblk_start, vblk_start));
         TRY(upload(d_susp_vblk_off, susp_vblk_off));
         TRY(upload(d_fil_susp, fil_susp));
@@ -340,6 +354,8 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     d.base = d_base;
     d.phase = d_phase;
     d.susp_fil_off = d_susp_fil_off;
+    d.dense_off = d_dense_off;
+    d.max_seg = max_seg;
     d.nvblk = nvblk;
     d.vblk_susp = d_vblk_susp;
     d.vblk_start = d_vblk_start;
@@ -431,8 +447,8 @@ int fil_bdf2_step(fil_sim* s, fil_step_report* report) {
         }
         if (!any) break;
         if (changed) TRY(upload_flags(s, s->active_d, s->active_h));
-        TRY(broyden_update_launch(s->d, s->k, s->AB, s->ipiv, s->Chist, s->Dhist, s->f, s->fprev, s->g0, s->h,
-                                  s->part, s->X, nullptr, s->active_d, s->st));
+        TRY(broyden_update_launch(s->d, s->k, s->AB, s->ipiv, s->AinvT, s->Chist, s->Dhist, s->f, s->fprev, s->g0,
+                                  s->h, s->part, s->X, nullptr, s->active_d, s->st));
         s->k++;
     }
     if (s->timing) {
@@ -506,8 +522,8 @@ int fil_broyden_begin(fil_sim* s, const double* X0, double* f0_out) {
 int fil_broyden_update(fil_sim* s, const double* f_new, double* dX_out) {
     FIL_CHECK_ARG(s && f_new, "fil_broyden_update: null argument");
     FIL_CHECK_ARG(s->k + 1 < s->p.kmax, "fil_broyden_update: history full (kmax updates)");
-    TRY(broyden_update_launch(s->d, s->k, s->AB, s->ipiv, s->Chist, s->Dhist, f_new, s->fprev, s->g0, s->h, s->part,
-                              s->X, dX_out, s->active_d, s->st));
+    TRY(broyden_update_launch(s->d, s->k, s->AB, s->ipiv, s->AinvT, s->Chist, s->Dhist, f_new, s->fprev, s->g0, s->h,
+                              s->part, s->X, dX_out, s->active_d, s->st));
     s->k++;
     return FIL_OK;
 }

@@ -4,10 +4,12 @@
 
 namespace fil {
 
-constexpr int kMaxSeg = 50;       // segments per filament: LDS of the banded J0 solve (6N x 25 doubles)
+constexpr int kMaxSeg = 64;       // segments per filament (one lane per segment in the steric pass)
 constexpr int kKL = 8;            // sub-diagonals of the row-differenced J0 in interleaved order
 constexpr int kKU = 8;            // super-diagonals (kKL + kKU after pivoting fill-in)
 constexpr int kBandW = 2 * kKL + kKU + 1;
+constexpr int kInvWaves = 8;      // column solves per workgroup when building the explicit J0^{-1}
+constexpr size_t kDenseInvBytes = size_t(64) << 20;  // explicit J0^{-1} used up to this total size
 constexpr int kMaxIter = 256;     // Broyden history capacity
 constexpr int kMaxDots = kMaxIter + 2;
 constexpr int kVecBlock = 1024;   // residual-vector elements per Broyden vector block
@@ -28,6 +30,8 @@ struct SimDev {
     const double* base;            // [M][3]
     const double* phase;           // [M] or null
     const int64_t* susp_fil_off;   // [nsusp+1]
+    const int64_t* dense_off;      // [M] offsets of the explicit inverses, or null
+    int max_seg;                   // largest filament
     // vector blocks over the 6S unknowns (never straddling suspensions)
     int64_t nvblk;
     const int32_t* vblk_susp;      // [nvblk]
@@ -53,13 +57,16 @@ int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const 
                          const double* Xjm1, const int32_t* active, double* X0, hipStream_t st);
 // J0 at X in row-differenced banded form (6N x kBandW per filament at 6*seg_off[f]*kBandW),
 // factorised with partial pivoting (ipiv at 6*seg_off[f]); flag[f] = 1 for a zero pivot
+// When AinvT is non-null the explicit inverse is also built (transposed, at dense_off[f]).
 int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* qc, const double* Tint,
-                     double tt, const int32_t* active, double* AB, int32_t* ipiv, int32_t* flag, hipStream_t st);
-int j0_solve_launch(const SimDev& d, const double* AB, const int32_t* ipiv, const double* v, const int32_t* active,
-                    double* out, hipStream_t st);
-int broyden_update_launch(const SimDev& d, int k, const double* AB, const int32_t* ipiv, double* Chist,
-                          double* Dhist, const double* fnew, double* fprev, double* g0, double* hvec, double* part,
-                          double* X, double* dXout, const int32_t* active, hipStream_t st);
+                     double tt, const int32_t* active, double* AB, int32_t* ipiv, int32_t* flag, double* AinvT,
+                     hipStream_t st);
+// out = J0^{-1} v: dense product when AinvT is non-null, else the banded sweeps
+int j0_solve_launch(const SimDev& d, const double* AB, const int32_t* ipiv, const double* AinvT, const double* v,
+                    const int32_t* active, double* out, hipStream_t st);
+int broyden_update_launch(const SimDev& d, int k, const double* AB, const int32_t* ipiv, const double* AinvT,
+                          double* Chist, double* Dhist, const double* fnew, double* fprev, double* g0, double* hvec,
+                          double* part, double* X, double* dXout, const int32_t* active, hipStream_t st);
 int first_step_launch(const SimDev& d, const double* h, const double* f, double* fprev, double* X, double* dXout,
                       const int32_t* active, hipStream_t st);
 int finalize_launch(const SimDev& d, const int32_t* commit, const double* Yc, const double* qc, const double* X,

@@ -583,13 +583,13 @@ __device__ __forceinline__ void stage_band(const double* __restrict__ g, double*
 __global__ void __launch_bounds__(64) j0_band_factor_kernel(SimDev d, const int32_t* __restrict__ active,
                                                           double* __restrict__ AB, int32_t* __restrict__ ipiv,
                                                           int32_t* __restrict__ flag) {
+    extern __shared__ double ab[];
     const int64_t f = blockIdx.x;
     if (!active[d.fil_susp[f]]) return;
     const int64_t s0 = d.seg_off[f];
     const int n = 6 * (int)(d.seg_off[f + 1] - s0);
     double* gab = AB + 6 * s0 * kBandW;
     int32_t* gp = ipiv + 6 * s0;
-    __shared__ double ab[6 * kMaxSeg * kBandW];
     const int lane = threadIdx.x;
     stage_band(gab, ab, n * kBandW, lane);
     int bad = 0;
@@ -637,47 +637,13 @@ __global__ void __launch_bounds__(64) j0_band_factor_kernel(SimDev d, const int3
     if (lane == 0) flag[f] = bad;
 }
 
-// out = J0^{-1} v for every active filament: L v (row differences) in the
-// interleaved order, then the pivoted forward substitution and the back
-// substitution.  The pending entries of each sweep live in a ring of lanes
-// (entry i in lane i mod 16, resp. mod 32), so a step is a few wave-uniform
-// lane reads and one fused update, with no barrier and no lane shuffling.
-__global__ void __launch_bounds__(64) j0_band_solve_kernel(SimDev d, const double* __restrict__ AB,
-                                                         const int32_t* __restrict__ ipiv,
-                                                         const double* __restrict__ v,
-                                                         const int32_t* __restrict__ active,
-                                                         double* __restrict__ out) {
-    const int64_t f = blockIdx.x;
-    if (!active[d.fil_susp[f]]) return;
-    const int64_t s0 = d.seg_off[f];
-    const int N = (int)(d.seg_off[f + 1] - s0);
-    const int n = 6 * N;
-    const double* gab = AB + 6 * s0 * kBandW;
-    const double* vf = v + 6 * s0;
-    __shared__ double ab[6 * kMaxSeg * kBandW];
-    __shared__ double y[6 * kMaxSeg];
-    __shared__ int ip[6 * kMaxSeg];
-    const int lane = threadIdx.x;
-    stage_band(gab, ab, n * kBandW, lane);
-    for (int i = lane; i < n; i += 64) {
-        ip[i] = ipiv[6 * s0 + i];
-        const int R = i / 3, a = i % 3;
-        double b;
-        if (R == 0 || (R & 1)) b = vf[slot_of(R, N) + a];
-        else {
-            const int m = R / 2;  // D_m = f^3_m - (m == 1 ? f^1 : f^3_{m-1})
-            const double prev = m == 1 ? vf[a] : vf[3 + 3 * N + 3 * (m - 2) + a];
-            b = vf[3 + 3 * N + 3 * (m - 1) + a] - prev;
-        }
-        y[i] = b;
-    }
-    __syncthreads();
-    // the diagonal of U is only ever divided by: keep its reciprocal in place
-    for (int i = lane; i < n; i += 64) ab[i * kBandW + kKL] = 1.0 / ab[i * kBandW + kKL];
-    __syncthreads();
-    // forward sweep: ring of 16 lanes holds y[j .. j+15].  The pivot index, the
-    // multiplier and the entry joining the ring are read one step ahead, from
-    // clamped (always valid) addresses, and applied with selects.
+// One wave solves (L J0) x = L v for one filament, given the staged band `ab`
+// (reciprocal pivots on its diagonal), the pivot rows `ip` and its own LDS
+// vector `y` that holds L v in the interleaved order on entry and x on exit.
+// The pending entries of each sweep live in a ring of lanes (entry i in lane
+// i mod 16, resp. mod 32), so a step is a few wave-uniform lane reads and one
+// fused update, with no barrier; every LDS read is issued one step ahead.
+__device__ __forceinline__ void band_sweeps(const double* ab, const int* ip, double* y, int n, int lane) {
     double w = (lane < 16 && lane < n) ? y[lane] : 0.0;
     auto fwd_mult = [&](int jj) {
         const int off = (lane - (jj & 15)) & 15;
@@ -694,8 +660,7 @@ __global__ void __launch_bounds__(64) j0_band_solve_kernel(SimDev d, const doubl
         const int hp = __builtin_amdgcn_readfirstlane(ipn) & 15;
         const double L = Ln;
         const double yi = j + 16 < n ? yin : 0.0;
-        const int j1 = min(j + 1, n - 1);
-        ipn = ip[j1];
+        ipn = ip[min(j + 1, n - 1)];
         Ln = fwd_mult(j + 1);
         yin = y[min(j + 17, n - 1)];
         const double vh = readlane_f64(w, h), vp = readlane_f64(w, hp);
@@ -704,8 +669,6 @@ __global__ void __launch_bounds__(64) j0_band_solve_kernel(SimDev d, const doubl
         y[j] = vp;
         w = lane == h ? yi : w;
     }
-    __syncthreads();
-    // back substitution: ring of 32 lanes holds z[i-31 .. i]
     constexpr int kU = kKL + kKU;
     w = 0.0;
     if (lane < 32) {
@@ -733,24 +696,152 @@ __global__ void __launch_bounds__(64) j0_band_solve_kernel(SimDev d, const doubl
         y[i] = xi;
         w = lane == h ? zi : w;
     }
+}
+
+// L v in the interleaved order for right-hand side v (X layout, filament block)
+__device__ __forceinline__ double diff_rhs(const double* vf, int i, int N) {
+    const int R = i / 3, a = i % 3;
+    if (R == 0 || (R & 1)) return vf[slot_of(R, N) + a];
+    const int m = R / 2;  // D_m = f^3_m - (m == 1 ? f^1 : f^3_{m-1})
+    const double prev = m == 1 ? vf[a] : vf[3 + 3 * N + 3 * (m - 2) + a];
+    return vf[3 + 3 * N + 3 * (m - 1) + a] - prev;
+}
+// the same for the unit vector e_c
+__device__ __forceinline__ double diff_unit(int c, int i, int N) {
+    const int R = i / 3, a = i % 3;
+    if (R == 0 || (R & 1)) return slot_of(R, N) + a == c ? 1.0 : 0.0;
+    const int m = R / 2;
+    const int prev = m == 1 ? a : 3 + 3 * N + 3 * (m - 2) + a;
+    return (3 + 3 * N + 3 * (m - 1) + a == c ? 1.0 : 0.0) - (prev == c ? 1.0 : 0.0);
+}
+
+// Stages a filament's factorised band and pivots into LDS (reciprocal pivots).
+__device__ __forceinline__ void stage_factor(const double* __restrict__ gab, const int32_t* __restrict__ gp,
+                                             double* ab, int* ip, int n) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    if (nt == 64) stage_band(gab, ab, n * kBandW, t);
+    else
+        for (int e = t; e < n * kBandW; e += nt) ab[e] = gab[e];
+    for (int i = t; i < n; i += nt) ip[i] = gp[i];
+    __syncthreads();
+    for (int i = t; i < n; i += nt) ab[i * kBandW + kKL] = 1.0 / ab[i * kBandW + kKL];
+    __syncthreads();
+}
+
+// dynamic LDS layout of the solve kernels: band [nmax][kBandW] | ip [nmax] | y [waves][nmax]
+__host__ __device__ inline size_t band_lds_bytes(int nmax, int waves) {
+    return (size_t)nmax * kBandW * sizeof(double) + (((size_t)nmax * sizeof(int) + 15) & ~(size_t)15) +
+           (size_t)waves * nmax * sizeof(double);
+}
+
+// out = J0^{-1} v for every active filament, one wave each
+__global__ void __launch_bounds__(64) j0_band_solve_kernel(SimDev d, const double* __restrict__ AB,
+                                                         const int32_t* __restrict__ ipiv,
+                                                         const double* __restrict__ v,
+                                                         const int32_t* __restrict__ active,
+                                                         double* __restrict__ out, int nmax) {
+    const int64_t f = blockIdx.x;
+    if (!active[d.fil_susp[f]]) return;
+    extern __shared__ double lds[];
+    const int64_t s0 = d.seg_off[f];
+    const int N = (int)(d.seg_off[f + 1] - s0);
+    const int n = 6 * N;
+    double* ab = lds;
+    int* ip = reinterpret_cast<int*>(lds + (size_t)nmax * kBandW);
+    double* y = reinterpret_cast<double*>(reinterpret_cast<char*>(ip) + (((size_t)nmax * sizeof(int) + 15) & ~(size_t)15));
+    const int lane = threadIdx.x;
+    const double* vf = v + 6 * s0;
+    for (int i = lane; i < n; i += 64) y[i] = diff_rhs(vf, i, N);
+    stage_factor(AB + 6 * s0 * kBandW, ipiv + 6 * s0, ab, ip, n);
+    band_sweeps(ab, ip, y, n, lane);
     __syncthreads();
     for (int i = lane; i < n; i += 64) out[6 * s0 + slot_of(i / 3, N) + i % 3] = y[i];
+}
+
+// Explicit inverse for the dense per-iteration product: block (f, g) runs
+// kInvWaves waves on the staged band of filament f; wave w solves for the unit
+// vector e_c, c = g * kInvWaves + w, and writes column c of J0^{-1} as row c of
+// Ainv^T (row-major n x n at dense_off[f]).
+__global__ void __launch_bounds__(64 * kInvWaves) j0_band_inverse_kernel(SimDev d, const double* __restrict__ AB,
+                                                                       const int32_t* __restrict__ ipiv,
+                                                                       const int32_t* __restrict__ active,
+                                                                       double* __restrict__ AinvT, int nmax) {
+    const int64_t f = blockIdx.x;
+    if (!active[d.fil_susp[f]]) return;
+    const int64_t s0 = d.seg_off[f];
+    const int N = (int)(d.seg_off[f + 1] - s0);
+    const int n = 6 * N;
+    if ((int)blockIdx.y * kInvWaves >= n) return;
+    extern __shared__ double lds[];
+    double* ab = lds;
+    int* ip = reinterpret_cast<int*>(lds + (size_t)nmax * kBandW);
+    double* ybase = reinterpret_cast<double*>(reinterpret_cast<char*>(ip) + (((size_t)nmax * sizeof(int) + 15) & ~(size_t)15));
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int c = blockIdx.y * kInvWaves + wave;
+    double* y = ybase + (size_t)wave * nmax;
+    if (c < n)
+        for (int i = lane; i < n; i += 64) y[i] = diff_unit(c, i, N);
+    stage_factor(AB + 6 * s0 * kBandW, ipiv + 6 * s0, ab, ip, n);
+    if (c >= n) return;
+    band_sweeps(ab, ip, y, n, lane);
+    double* col = AinvT + d.dense_off[f] + (int64_t)c * n;
+    for (int i = lane; i < n; i += 64) col[slot_of(i / 3, N) + i % 3] = y[i];
+}
+
+// out = J0^{-1} v with the explicit inverse: out_i = sum_c Ainv^T[c][i] v_c
+__global__ void __launch_bounds__(256) dense_matvec_kernel(SimDev d, const double* __restrict__ AinvT,
+                                                         const double* __restrict__ v,
+                                                         const int32_t* __restrict__ active,
+                                                         double* __restrict__ out) {
+    const int64_t f = blockIdx.x;
+    if (!active[d.fil_susp[f]]) return;
+    const int64_t s0 = d.seg_off[f];
+    const int n = 6 * (int)(d.seg_off[f + 1] - s0);
+    const double* A = AinvT + d.dense_off[f];
+    __shared__ double sv[6 * kMaxSeg];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) sv[j] = v[6 * s0 + j];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int c = 0;
+        for (; c + 4 <= n; c += 4) {
+            a0 = fma(A[(int64_t)c * n + i], sv[c], a0);
+            a1 = fma(A[(int64_t)(c + 1) * n + i], sv[c + 1], a1);
+            a2 = fma(A[(int64_t)(c + 2) * n + i], sv[c + 2], a2);
+            a3 = fma(A[(int64_t)(c + 3) * n + i], sv[c + 3], a3);
+        }
+        for (; c < n; c++) a0 = fma(A[(int64_t)c * n + i], sv[c], a0);
+        out[6 * s0 + i] = (a0 + a1) + (a2 + a3);
+    }
 }
 #undef AB_
 
 int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* qc, const double* Tint,
-                     double tt, const int32_t* active, double* AB, int32_t* ipiv, int32_t* flag, hipStream_t st) {
+                     double tt, const int32_t* active, double* AB, int32_t* ipiv, int32_t* flag, double* AinvT,
+                     hipStream_t st) {
     if (d.M == 0) return FIL_OK;
+    const int nmax = 6 * d.max_seg;
     j0_band_assemble_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, bc, X, qc, Tint, tt, active, AB);
-    j0_band_factor_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, active, AB, ipiv, flag);
+    j0_band_factor_kernel<<<(unsigned)d.M, 64, (size_t)nmax * kBandW * sizeof(double), st>>>(d, active, AB, ipiv,
+                                                                                           flag);
+    if (AinvT) {
+        const dim3 grid((unsigned)d.M, (unsigned)ceil_div(nmax, kInvWaves));
+        j0_band_inverse_kernel<<<grid, 64 * kInvWaves, band_lds_bytes(nmax, kInvWaves), st>>>(d, AB, ipiv, active,
+                                                                                           AinvT, nmax);
+    }
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }
 
-int j0_solve_launch(const SimDev& d, const double* AB, const int32_t* ipiv, const double* v, const int32_t* active,
-                    double* out, hipStream_t st) {
+int j0_solve_launch(const SimDev& d, const double* AB, const int32_t* ipiv, const double* AinvT, const double* v,
+                    const int32_t* active, double* out, hipStream_t st) {
     if (d.M == 0) return FIL_OK;
-    j0_band_solve_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, AB, ipiv, v, active, out);
+    if (AinvT) {
+        dense_matvec_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, AinvT, v, active, out);
+    } else {
+        const int nmax = 6 * d.max_seg;
+        j0_band_solve_kernel<<<(unsigned)d.M, 64, band_lds_bytes(nmax, 1), st>>>(d, AB, ipiv, v, active, out, nmax);
+    }
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }
@@ -830,11 +921,11 @@ __global__ void __launch_bounds__(256) broyden_combine_kernel(SimDev d, int k, c
     }
 }
 
-int broyden_update_launch(const SimDev& d, int k, const double* AB, const int32_t* ipiv, double* Chist,
-                          double* Dhist, const double* fnew, double* fprev, double* g0, double* hvec, double* part,
-                          double* X, double* dXout, const int32_t* active, hipStream_t st) {
+int broyden_update_launch(const SimDev& d, int k, const double* AB, const int32_t* ipiv, const double* AinvT,
+                          double* Chist, double* Dhist, const double* fnew, double* fprev, double* g0, double* hvec,
+                          double* part, double* X, double* dXout, const int32_t* active, hipStream_t st) {
     if (d.S == 0) return FIL_OK;
-    int rc = j0_solve_launch(d, AB, ipiv, fnew, active, g0, st);
+    int rc = j0_solve_launch(d, AB, ipiv, AinvT, fnew, active, g0, st);
     if (rc) return rc;
     multidot_kernel<<<dim3((unsigned)d.nvblk, (unsigned)(k + 2)), 256, 0, st>>>(d, k, Dhist, fnew, fprev, active, part);
     broyden_combine_kernel<<<(unsigned)d.nvblk, 256, 0, st>>>(d, k, part, g0, Chist, Dhist, fnew, fprev, hvec, X,
