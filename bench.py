@@ -112,7 +112,7 @@ def main():
         iters += r["iters"]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    rpy_ms, nl = sim.timing()
+    rpy_ms, nl = sim.timing()[args.prec]
     pairs = applies * float(S) ** 2
     kern_s = rpy_ms * 1e-3 / max(nl, 1)
     peak = PEAK_FP64_TFLOPS if args.prec == "f64" else PEAK_FP32_TFLOPS

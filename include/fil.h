@@ -119,8 +119,10 @@ typedef struct {
     int32_t iters;              /* Broyden updates taken */
     int32_t mobility_applies;   /* residual evaluations (one mobility apply each) */
     int32_t converged;          /* 1 if max|f|/a <= tol */
-    int32_t pad;
+    int32_t applies_f64;        /* of which with the FP64 mobility (all of them in FIL_PREC_F64 mode) */
     double resid;               /* final max|f| / a */
+    int32_t used_learned;       /* 1 if the step started from the learned warm start */
+    int32_t pad;
 } fil_step_report;
 
 typedef struct fil_sim fil_sim;
@@ -137,9 +139,22 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
                const double* Y0, const double* q0, const double* phase, const int32_t* tether, fil_sim** out);
 void fil_destroy(fil_sim* sim);
 
+/* Per-suspension parameters for ensembles of independent suspensions whose time
+ * step, gravity force (Sec. 5.4: W depends on each suspension's L) or steric
+ * strength F^S (Sec. 2.6) differ.  HOST arrays, each may be NULL to keep the
+ * value from fil_params: dt double[nsusp] (> 0), grav double[nsusp][3],
+ * FS double[nsusp] (>= 0).  Only before the first step.  Differing time steps
+ * need K0 = 0 (the time of the preferred curvature is the global step count x
+ * fil_params.dt).  FIL_EINVAL on a bad value, nothing changed. */
+int fil_set_suspension_params(fil_sim* sim, const double* dt, const double* grav, const double* FS);
+
 /* One time step: warm start, J0 and its inverse, Broyden iterations on the
  * device (one mobility apply each), then q^{j+1} = exp(u) . q^j, the robot-arm
  * positions and the history shift.  The first step is BDF1, later ones BDF2.
+ * In FIL_PREC_F32TILE mode the step's first mobility applies use FP32 pair
+ * tiles; once every running suspension's residual is within 10 tol, or within
+ * 30x the FP32 rounding floor (3e-8 x max|b dt V|), later applies use FP64, and
+ * only an FP64 residual ends a step (the FP32 floor can exceed tol).
  * report: HOST fil_step_report[nsusp] (may be NULL).  Synchronises the stream
  * once per Broyden iteration to test convergence.  Returns FIL_ENOCONV or
  * FIL_ENONFINITE if a suspension failed; its state is then left at step j. */
@@ -175,12 +190,84 @@ int fil_read_state(fil_sim* sim, double* Y, double* q, double* Xj);
 /* Timing of the mobility pair kernel inside fil_bdf2_step: when enabled, HIP
  * events on the simulation's stream bracket every launch of the main pair
  * kernel; fil_get_timing returns the summed duration (ms) and the launch count
- * since the last fil_set_timing call.  Enabling resets both counters. */
+ * since the last fil_set_timing call, HOST arrays of 2: [0] the FP64 kernel,
+ * [1] the FP32-tile kernel (either may be NULL).  Enabling resets the counters. */
 int fil_set_timing(fil_sim* sim, int enable);
 int fil_get_timing(fil_sim* sim, double* rpy_ms, int64_t* rpy_launches);
 
 /* Stream the simulation enqueues on (set before stepping). */
 int fil_set_stream(fil_sim* sim, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned warm start.  Not part of the paper's method: a per-filament       */
+/* network predicts, from the committed state of step j, how far the         */
+/* converged unknowns of step j+1 (Y_1, the Lie-algebra increments u_n and  */
+/* the multipliers Lambda) lie from the extrapolated first iterate of the    */
+/* warm start (Sec. 3.3.3 notes that the iteration count depends on that     */
+/* guess).  The prediction is added to the guess; if Broyden then fails, the */
+/* step is re-solved from the plain guess, and convergence is always judged  */
+/* by the same residual tolerance.                                           */
+/*                                                                           */
+/* Network: 19N inputs -> `depth` SiLU hidden layers of `width` -> 6N        */
+/* outputs for filaments of N segments; BF16 weights and activations with    */
+/* FP32 accumulation on the matrix cores, FP32 master weights, Adam.         */
+/* Dimensions are padded to multiples of 32 (n_in_pad, n_out_pad); the flat  */
+/* FP32 parameter vector holds, layer by layer, W [out_pad][in_pad]          */
+/* (row-major) then b [out_pad].  Loss: mean of (Y - T)^2 over the valid      */
+/* rows and n_out columns, T the standardised targets.                       */
+/* ------------------------------------------------------------------------ */
+typedef struct fil_mlp fil_mlp;
+
+/* Creates the network on the current device with a seeded uniform (He)
+ * initialisation; max_batch bounds B of every call.  FIL_EINVAL for
+ * n_seg outside [2, 64], width not a multiple of 32, depth outside [1, 16]. */
+int fil_mlp_create(int32_t n_seg, int32_t width, int32_t depth, int32_t max_batch, uint64_t seed, fil_mlp** out);
+void fil_mlp_destroy(fil_mlp* mlp);
+/* dims (HOST int32[8]): n_in, n_in_pad, n_out, n_out_pad, width, depth, max_batch, n_seg;
+ * n_params: length of the flat parameter vector.  Either may be NULL. */
+int fil_mlp_dims(const fil_mlp* mlp, int32_t* dims, int64_t* n_params);
+/* HOST float[n_params] in / out.  Setting resets the Adam moments. */
+int fil_mlp_set_params(fil_mlp* mlp, const float* params);
+int fil_mlp_get_params(const fil_mlp* mlp, float* params);
+/* Standardisation (HOST float[2 (n_in_pad + n_out_pad)]): mu_in, sd_in, mu_out, sd_out. */
+int fil_mlp_set_norm(fil_mlp* mlp, const float* norm);
+int fil_mlp_get_norm(const fil_mlp* mlp, float* norm);
+/* Fits the standardisation to n samples: feat DEVICE float[n][n_in], targ
+ * DEVICE float[n][n_out] (column means and population standard deviations;
+ * a constant column gets sd = 1). */
+int fil_mlp_fit_norm(fil_mlp* mlp, int64_t n, const float* feat, const float* targ, void* stream);
+/* xb (DEVICE bf16 as uint16[n][n_in_pad]) = (feat - mu_in) / sd_in, zero padded;
+ * t (DEVICE float[n][n_out_pad]) = (targ - mu_out) / sd_out.  Either pair may be NULL. */
+int fil_mlp_standardize(fil_mlp* mlp, int64_t n, const float* feat, const float* targ, uint16_t* xb, float* t,
+                        void* stream);
+/* Y (DEVICE float[B][n_out_pad]) = network(X), X DEVICE bf16 [B][n_in_pad], B <= max_batch. */
+int fil_mlp_forward(fil_mlp* mlp, int32_t B, const uint16_t* X, float* Y, void* stream);
+/* Loss and gradient of the minibatch of rows `rows` (DEVICE int32[B]; NULL:
+ * rows 0..B-1) of X (DEVICE bf16 [*][n_in_pad]) and T (DEVICE float
+ * [*][n_out_pad], standardised).  grad_out (DEVICE float[n_params]) and loss
+ * (DEVICE double) may be NULL.  The gradient is kept for fil_mlp_adam_step. */
+int fil_mlp_backward(fil_mlp* mlp, int32_t B, const int32_t* rows, const uint16_t* X, const float* T,
+                     float* grad_out, double* loss, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the last gradient. */
+int fil_mlp_adam_step(fil_mlp* mlp, float lr, void* stream);
+/* fil_mlp_backward followed by fil_mlp_adam_step. */
+int fil_mlp_train_step(fil_mlp* mlp, int32_t B, const int32_t* rows, const uint16_t* X, const float* T, float lr,
+                       double* loss, void* stream);
+
+/* Simulation side (every filament of the simulation must have N segments):
+ * fil_sim_features: the 19N raw features of every filament at the committed
+ *   state (DEVICE float[M][19N]); valid after at least one step.
+ * fil_sim_step_target: the scaled difference between the converged unknowns of
+ *   the last step and its extrapolated first iterate (DEVICE float[M][6N]).
+ * fil_sim_set_mlp: use the network for the first iterate of every step from
+ *   the fourth on (it needs three committed steps of history); tethered
+ *   filaments keep the plain guess.  The network must outlive its use and have
+ *   max_batch >= M.  enable = 0 switches it off.
+ * fil_sim_fallbacks: steps re-solved from the plain guess so far. */
+int fil_sim_features(fil_sim* sim, float* out);
+int fil_sim_step_target(fil_sim* sim, float* out);
+int fil_sim_set_mlp(fil_sim* sim, fil_mlp* mlp, int enable);
+int fil_sim_fallbacks(fil_sim* sim, int64_t* n);
 
 #ifdef __cplusplus
 }

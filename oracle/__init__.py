@@ -297,6 +297,17 @@ class Sim:
         lib().or_reconstruct(C.byref(self.P), _p(self.q), _p(X), _p(Y), _p(q))
         return Y, q
 
+    def forces(self, X, Y=None, q=None, tt=None):
+        """Total force and torque (internal + tether + gravity + steric) on every
+        segment at configuration (Y, q) (default: the committed state) with the
+        multipliers of X."""
+        Y = self.Y if Y is None else _f64(Y, (self.S, 3))
+        q = self.q if q is None else _f64(q, (self.S, 4))
+        tt = self.St.t if tt is None else tt
+        F, T = np.zeros((self.S, 3)), np.zeros((self.S, 3))
+        lib().or_forces(C.byref(self.P), _p(Y), _p(q), _p(_f64(X).copy()), tt, _p(F), _p(T))
+        return F, T
+
     def j0_filament(self, f, X):
         N = int(self.fil_off[f + 1] - self.fil_off[f])
         X = _f64(X).copy()

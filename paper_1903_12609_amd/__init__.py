@@ -9,7 +9,7 @@ from __future__ import annotations
 
 from ._native import FilError, PREC, check, lib  # noqa: F401
 
-__all__ = ["FilError", "Sim", "rpy_mobility_apply", "rpy_mobility_apply_batched", "rpy_workspace_bytes",
+__all__ = ["FilError", "MLP", "Sim", "rpy_mobility_apply", "rpy_mobility_apply_batched", "rpy_workspace_bytes",
            "filament_internal_forces"]
 
 
@@ -139,6 +139,44 @@ class Sim:
         self._h = h
         check(lib().fil_set_stream(h, _stream()))
 
+    def set_suspension_params(self, dt=None, grav=None, FS=None):
+        """Per-suspension dt [nsusp], gravity force [nsusp,3] and F^S [nsusp] (before the first step)."""
+        import ctypes
+        import numpy as np
+        ns = self.nsusp
+        arrs = []
+        for a, shape in ((dt, (ns,)), (grav, (ns, 3)), (FS, (ns,))):
+            arrs.append(None if a is None else np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape)))
+        vp = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+        check(lib().fil_set_suspension_params(self._h, *[vp(a) for a in arrs]))
+
+    def features(self):
+        """Raw per-filament features [M, 19N] (float32, device) at the committed state."""
+        import torch
+        N = int(self.fil_off[1] - self.fil_off[0])
+        out = torch.empty((self.M, 19 * N), dtype=torch.float32, device="cuda")
+        check(lib().fil_sim_features(self._h, _ptr(out)))
+        return out
+
+    def step_target(self):
+        """Scaled converged-minus-extrapolated unknowns of the last step [M, 6N] (float32, device)."""
+        import torch
+        N = int(self.fil_off[1] - self.fil_off[0])
+        out = torch.empty((self.M, 6 * N), dtype=torch.float32, device="cuda")
+        check(lib().fil_sim_step_target(self._h, _ptr(out)))
+        return out
+
+    def set_mlp(self, mlp, enable=True):
+        """Use (or stop using) a trained MLP for the first iterate of each step."""
+        self._mlp = mlp if enable else None
+        check(lib().fil_sim_set_mlp(self._h, mlp._h if mlp is not None else None, int(enable)))
+
+    def fallbacks(self):
+        import ctypes
+        n = ctypes.c_int64()
+        check(lib().fil_sim_fallbacks(self._h, ctypes.byref(n)))
+        return n.value
+
     def close(self):
         if getattr(self, "_h", None):
             lib().fil_destroy(self._h)
@@ -156,7 +194,8 @@ class Sim:
         from ._native import StepReport
         reps = (StepReport * self.nsusp)()
         rc = lib().fil_bdf2_step(self._h, reps)
-        out = [dict(iters=r.iters, applies=r.mobility_applies, converged=bool(r.converged), resid=r.resid)
+        out = [dict(iters=r.iters, applies=r.mobility_applies, applies_f64=r.applies_f64,
+                    converged=bool(r.converged), resid=r.resid, used_learned=bool(r.used_learned))
                for r in reps]
         if rc != 0 and raise_on_fail:
             check(rc)
@@ -189,11 +228,12 @@ class Sim:
         check(lib().fil_set_timing(self._h, int(enable)))
 
     def timing(self):
-        """(summed ms, launches) of the mobility pair kernel since set_timing."""
+        """{"f64": (ms, launches), "f32tile": (ms, launches)} of the mobility pair
+        kernels since set_timing (summed durations, HIP events on the sim's stream)."""
         import ctypes
-        ms, n = ctypes.c_double(), ctypes.c_int64()
-        check(lib().fil_get_timing(self._h, ctypes.byref(ms), ctypes.byref(n)))
-        return ms.value, n.value
+        ms, n = (ctypes.c_double * 2)(), (ctypes.c_int64 * 2)()
+        check(lib().fil_get_timing(self._h, ms, n))
+        return {"f64": (ms[0], n[0]), "f32tile": (ms[1], n[1])}
 
     def residual(self, X):
         import torch
@@ -212,3 +252,92 @@ class Sim:
         dX = torch.empty(6 * self.S, dtype=torch.float64, device="cuda")
         check(lib().fil_broyden_update(self._h, _ptr(f_new), _ptr(dX)))
         return dX
+
+
+class MLP:
+    """The learned warm start's network for filaments of n_seg segments
+    (19 n_seg inputs, `depth` SiLU layers of `width`, 6 n_seg outputs)."""
+
+    def __init__(self, n_seg, width=256, depth=3, max_batch=1024, seed=0):
+        import ctypes
+        h = ctypes.c_void_p()
+        check(lib().fil_mlp_create(n_seg, width, depth, max_batch, seed, ctypes.byref(h)))
+        self._h = h
+        dims = (ctypes.c_int32 * 8)()
+        n = ctypes.c_int64()
+        check(lib().fil_mlp_dims(h, dims, ctypes.byref(n)))
+        (self.n_in, self.n_in_pad, self.n_out, self.n_out_pad, self.width, self.depth, self.max_batch,
+         self.n_seg) = list(dims)
+        self.n_params = n.value
+        self.layer_dims = [(self.n_in_pad if l == 0 else width, width if l < depth else self.n_out_pad)
+                           for l in range(depth + 1)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fil_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import numpy as np
+        P = np.zeros(self.n_params, dtype=np.float32)
+        check(lib().fil_mlp_get_params(self._h, P.ctypes.data))
+        return P
+
+    def set_params(self, P):
+        import numpy as np
+        P = np.ascontiguousarray(P, dtype=np.float32)
+        assert P.size == self.n_params
+        check(lib().fil_mlp_set_params(self._h, P.ctypes.data))
+
+    def get_norm(self):
+        import numpy as np
+        a = np.zeros(2 * (self.n_in_pad + self.n_out_pad), dtype=np.float32)
+        check(lib().fil_mlp_get_norm(self._h, a.ctypes.data))
+        return a
+
+    def set_norm(self, a):
+        import numpy as np
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        check(lib().fil_mlp_set_norm(self._h, a.ctypes.data))
+
+    def fit_norm(self, feat, targ):
+        check(lib().fil_mlp_fit_norm(self._h, feat.shape[0], _ptr(feat), _ptr(targ), _stream()))
+
+    def standardize(self, feat=None, targ=None):
+        """(bf16 features as int16 [n, n_in_pad], standardised targets [n, n_out_pad]) on the device."""
+        import torch
+        n = (feat if feat is not None else targ).shape[0]
+        xb = None if feat is None else torch.empty((n, self.n_in_pad), dtype=torch.int16, device="cuda")
+        t = None if targ is None else torch.empty((n, self.n_out_pad), dtype=torch.float32, device="cuda")
+        p = lambda a: None if a is None else _ptr(a)
+        check(lib().fil_mlp_standardize(self._h, n, p(feat), p(targ), p(xb), p(t), _stream()))
+        return xb, t
+
+    def forward(self, xb):
+        import torch
+        Y = torch.empty((xb.shape[0], self.n_out_pad), dtype=torch.float32, device="cuda")
+        check(lib().fil_mlp_forward(self._h, xb.shape[0], _ptr(xb), _ptr(Y), _stream()))
+        return Y
+
+    def backward(self, xb, t, rows=None, B=None):
+        """(loss, flat gradient) of a minibatch (device tensors)."""
+        import torch
+        B = (rows.shape[0] if rows is not None else xb.shape[0]) if B is None else B
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        check(lib().fil_mlp_backward(self._h, B, None if rows is None else _ptr(rows), _ptr(xb), _ptr(t), _ptr(g),
+                                     _ptr(loss), _stream()))
+        return loss, g
+
+    def adam_step(self, lr):
+        check(lib().fil_mlp_adam_step(self._h, float(lr), _stream()))
+
+    def train_step(self, xb, t, rows, lr, loss):
+        check(lib().fil_mlp_train_step(self._h, rows.shape[0], _ptr(rows), _ptr(xb), _ptr(t), float(lr), _ptr(loss),
+                                       _stream()))

@@ -38,7 +38,7 @@ class Params(C.Structure):
 
 class StepReport(C.Structure):
     _fields_ = [("iters", C.c_int32), ("mobility_applies", C.c_int32), ("converged", C.c_int32),
-                ("pad", C.c_int32), ("resid", _d)]
+                ("applies_f64", C.c_int32), ("resid", _d), ("used_learned", C.c_int32), ("pad", C.c_int32)]
 
 
 def _declare(L):
@@ -66,6 +66,27 @@ def _declare(L):
                                     C.POINTER(_i64), C.POINTER(_d), C.POINTER(_i64)]
         L.fil_read_state.argtypes = [_vp, _vp, _vp, _vp]
         L.fil_set_stream.argtypes = [_vp, _vp]
+        L.fil_set_suspension_params.argtypes = [_vp, _vp, _vp, _vp]
+        L.fil_sim_features.argtypes = [_vp, _vp]
+        L.fil_sim_step_target.argtypes = [_vp, _vp]
+        L.fil_sim_set_mlp.argtypes = [_vp, _vp, _i]
+        L.fil_sim_fallbacks.argtypes = [_vp, C.POINTER(_i64)]
+    if hasattr(L, "fil_mlp_create"):
+        _i32 = C.c_int32
+        L.fil_mlp_create.argtypes = [_i32, _i32, _i32, _i32, C.c_uint64, C.POINTER(_vp)]
+        L.fil_mlp_destroy.argtypes = [_vp]
+        L.fil_mlp_destroy.restype = None
+        L.fil_mlp_dims.argtypes = [_vp, _vp, C.POINTER(_i64)]
+        L.fil_mlp_set_params.argtypes = [_vp, _vp]
+        L.fil_mlp_get_params.argtypes = [_vp, _vp]
+        L.fil_mlp_set_norm.argtypes = [_vp, _vp]
+        L.fil_mlp_get_norm.argtypes = [_vp, _vp]
+        L.fil_mlp_fit_norm.argtypes = [_vp, _i64, _vp, _vp, _vp]
+        L.fil_mlp_standardize.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp, _vp]
+        L.fil_mlp_forward.argtypes = [_vp, _i32, _vp, _vp, _vp]
+        L.fil_mlp_backward.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.fil_mlp_adam_step.argtypes = [_vp, C.c_float, _vp]
+        L.fil_mlp_train_step.argtypes = [_vp, _i32, _vp, _vp, _vp, C.c_float, _vp, _vp]
         L.fil_set_timing.argtypes = [_vp, _i]
         L.fil_get_timing.argtypes = [_vp, C.POINTER(_d), C.POINTER(_i64)]
 

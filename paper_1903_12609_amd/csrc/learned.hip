@@ -1,0 +1,129 @@
+// Per-filament features, training targets and the learned first iterate of the
+// implicit step (the network itself is in mlp.hip).
+//
+// For a filament of N segments the 19N features, taken at the committed state
+// of step j, are (group-major):
+//   [0, 3N)    (Y_n - centroid) / L                      L = N dL
+//   [3N, 7N)   q_n
+//   [7N, 10N)  F_n / F_s     total force of the converged evaluation of step j
+//   [10N, 13N) dt (V_{n-1} + V_n + V_{n+1}) / (count dL)  neighbour-averaged velocity
+//   [13N, 19N) the last changes of the unknowns in their own layout:
+//              Y_1: (X^j - 2X^{j-1} + X^{j-2}) / dL, u: u^j - u^{j-1},
+//              Lambda: (X^j - 2X^{j-1} + X^{j-2}) / F_s
+// with F_s the gravity force per segment (K_B / dL^2 without gravity).
+// The 6N targets are the converged unknowns minus the extrapolated first
+// iterate of the warm start, scaled like the history group (Y_1 / dL, u,
+// Lambda / F_s); the network's prediction is added back with the same scales.
+#include "common.h"
+#include "learned.h"
+#include "solver.h"
+
+namespace fil {
+
+namespace {
+
+__device__ __forceinline__ double force_scale(const SimDev& d, int64_t f) {
+    const double* sp = d.spar + kSpar * d.fil_susp[f];
+    const double g = sqrt(sp[1] * sp[1] + sp[2] * sp[2] + sp[3] * sp[3]);
+    return g > 0.0 ? g : d.KB / (d.dL * d.dL);
+}
+__device__ __forceinline__ double slot_scale(int c, int N, double dL, double Fs) {
+    return c < 3 ? dL : (c < 3 + 3 * N ? 1.0 : Fs);
+}
+
+__global__ void __launch_bounds__(64) features_kernel(SimDev d, int N, const double* __restrict__ Yj,
+                                                      const double* __restrict__ qj, const double* __restrict__ F,
+                                                      const double* __restrict__ V, const double* __restrict__ Xj,
+                                                      const double* __restrict__ Xjm1,
+                                                      const double* __restrict__ Xjm2, float* __restrict__ out) {
+    const int64_t f = blockIdx.x;
+    const int64_t S = d.S, s0 = d.seg_off[f];
+    const int n = threadIdx.x;  // N <= 64
+    const double Fs = force_scale(d, f);
+    const double dt = d.spar[kSpar * d.fil_susp[f]];
+    const double L = N * d.dL;
+    __shared__ double sv[3][kMaxSeg];
+    double y[3] = {0, 0, 0};
+    if (n < N)
+        for (int i = 0; i < 3; i++) y[i] = Yj[i * S + s0 + n];
+    // centroid by a wave reduction
+    double c[3];
+    for (int i = 0; i < 3; i++) {
+        double t = y[i];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        c[i] = t / N;
+    }
+    if (n < N)
+        for (int i = 0; i < 3; i++) sv[i][n] = V[i * S + s0 + n];
+    __syncthreads();
+    if (n >= N) return;
+    float* o = out + f * (int64_t)kMlpFeatPerSeg * N;
+    for (int i = 0; i < 3; i++) o[3 * n + i] = (float)((y[i] - c[i]) / L);
+    for (int i = 0; i < 4; i++) o[3 * N + 4 * n + i] = (float)qj[i * S + s0 + n];
+    for (int i = 0; i < 3; i++) o[7 * N + 3 * n + i] = (float)(F[i * S + s0 + n] / Fs);
+    const int lo = n > 0 ? n - 1 : n, hi = n + 1 < N ? n + 1 : n;
+    for (int i = 0; i < 3; i++) {
+        double a = 0.0;
+        for (int m = lo; m <= hi; m++) a += sv[i][m];
+        o[10 * N + 3 * n + i] = (float)(dt * a / ((hi - lo + 1) * d.dL));
+    }
+    const double* xj = Xj + 6 * s0;
+    const double* x1 = Xjm1 + 6 * s0;
+    const double* x2 = Xjm2 + 6 * s0;
+    for (int k = 0; k < 6; k++) {
+        const int cidx = 6 * n + k;  // slots are covered 6 per segment, in X's own order
+        const double dd = cidx >= 3 && cidx < 3 + 3 * N ? xj[cidx] - x1[cidx] : xj[cidx] - 2.0 * x1[cidx] + x2[cidx];
+        o[13 * N + cidx] = (float)(dd / slot_scale(cidx, N, d.dL, Fs));
+    }
+}
+
+__global__ void __launch_bounds__(256) target_kernel(SimDev d, int N, const double* __restrict__ Xj,
+                                                     const double* __restrict__ X0, float* __restrict__ out) {
+    const int64_t f = blockIdx.x;
+    const int64_t s0 = d.seg_off[f];
+    const double Fs = force_scale(d, f);
+    for (int c = threadIdx.x; c < 6 * N; c += blockDim.x)
+        out[f * 6 * N + c] = (float)((Xj[6 * s0 + c] - X0[6 * s0 + c]) / slot_scale(c, N, d.dL, Fs));
+}
+
+__global__ void __launch_bounds__(256) apply_kernel(SimDev d, int N, int out_pad, const float* __restrict__ Y,
+                                                    const float* __restrict__ mu, const float* __restrict__ sd,
+                                                    const int32_t* __restrict__ active,
+                                                    const double* __restrict__ X0, double* __restrict__ X) {
+    const int64_t f = blockIdx.x;
+    const int64_t s0 = d.seg_off[f];
+    if (d.seg_off[f + 1] - s0 != N || d.tether[f] || !active[d.fil_susp[f]]) return;
+    const double Fs = force_scale(d, f);
+    for (int c = threadIdx.x; c < 6 * N; c += blockDim.x) {
+        const double p = (double)Y[f * out_pad + c] * sd[c] + mu[c];
+        X[6 * s0 + c] = X0[6 * s0 + c] + p * slot_scale(c, N, d.dL, Fs);
+    }
+}
+
+}  // namespace
+
+int learned_features_launch(const SimDev& d, int N, const double* Yj, const double* qj, const double* F,
+                            const double* V, const double* Xj, const double* Xjm1, const double* Xjm2, float* out,
+                            hipStream_t st) {
+    if (d.M == 0) return FIL_OK;
+    features_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, N, Yj, qj, F, V, Xj, Xjm1, Xjm2, out);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+int learned_target_launch(const SimDev& d, int N, const double* Xj, const double* X0, float* out, hipStream_t st) {
+    if (d.M == 0) return FIL_OK;
+    target_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, N, Xj, X0, out);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+int learned_apply_launch(const SimDev& d, int N, int out_pad, const float* Y, const float* mu, const float* sd,
+                         const int32_t* active, const double* X0, double* X, hipStream_t st) {
+    if (d.M == 0) return FIL_OK;
+    apply_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, N, out_pad, Y, mu, sd, active, X0, X);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+}  // namespace fil

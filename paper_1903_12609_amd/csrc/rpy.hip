@@ -325,7 +325,7 @@ __device__ __forceinline__ void rpy_pair_f32(const double y[3], const SrcF32* __
     }
 }
 
-constexpr int kF32Tile = 64;  // sources accumulated in float before the double flush
+constexpr int kF32Tile = 16;  // sources accumulated in float before the double flush
 
 template <int TPL, int WS>
 __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg, int64_t tb, int k, int K,

@@ -14,6 +14,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "learned.h"
 #include "solver.h"
 
 using namespace fil;
@@ -25,20 +26,33 @@ struct fil_sim {
     std::vector<void*> dev_allocs;
     std::vector<void*> host_allocs;
     SimDev d{};
-    double *Yj = nullptr, *Yjm1 = nullptr, *qj = nullptr, *Xj = nullptr, *Xjm1 = nullptr;
+    double *Yj = nullptr, *Yjm1 = nullptr, *qj = nullptr, *Xj = nullptr, *Xjm1 = nullptr, *Xjm2 = nullptr;
+    double* X0p = nullptr;  // extrapolated first iterate of the last step (the plain warm start)
     double *X = nullptr, *f = nullptr, *fprev = nullptr, *h = nullptr, *g0 = nullptr;
     double *Yc = nullptr, *qc = nullptr, *F = nullptr, *T = nullptr, *V = nullptr, *W = nullptr;
     double *AB = nullptr, *AinvT = nullptr, *Chist = nullptr, *Dhist = nullptr, *part = nullptr;
     double* box = nullptr;
+    double* spar = nullptr;  // [nsusp][kSpar]
     int32_t *ipiv = nullptr, *active_d = nullptr, *commit_d = nullptr, *jflag_d = nullptr;
     unsigned long long* resbits_d = nullptr;
     int32_t *active_h = nullptr, *commit_h = nullptr, *jflag_h = nullptr;
     unsigned long long* resbits_h = nullptr;
-    void* rpy_work = nullptr;
-    int rb = 0;  // which half of resbits_d the last residual evaluation wrote
-    RpyPlan rplan{};
-    RpyBatchPlan bplan;
+    // mobility plans and workspaces: [0] FP64, [1] FP32-tile (only when prec is FP32-tile)
+    void* rpy_work[2] = {nullptr, nullptr};
+    RpyPlan rplan[2]{};
+    RpyBatchPlan bplan[2];
+    int cur = 0;  // plan of the next residual evaluation
+    int rb = 0;   // which half of resbits_d the last residual evaluation wrote
     bool batched = false;
+    // learned warm start
+    fil_mlp* mlp = nullptr;
+    bool use_mlp = false;
+    int seg_uniform = 0;           // N when every filament has N segments, else 0
+    float* feat = nullptr;         // [M][19N] raw features
+    uint16_t* featb = nullptr;     // [M][in_pad] standardised BF16 features
+    float* pred = nullptr;         // [M][out_pad] network output
+    int feat_in_pad = 0, feat_out_pad = 0;
+    int64_t fallbacks = 0;
     double t = 0.0;
     int64_t step = 0;
     int k = 0;
@@ -48,8 +62,9 @@ struct fil_sim {
     bool timing = false;
     std::vector<hipEvent_t> ev;
     int nev = 0;
-    double rpy_ms = 0.0;
-    int64_t rpy_launches = 0;
+    std::vector<int> ev_prec;  // plan of each recorded launch
+    double rpy_ms[2] = {0.0, 0.0};
+    int64_t rpy_launches[2] = {0, 0};
     int64_t pairs_per_apply = 0;
 };
 
@@ -96,13 +111,21 @@ BdfCoef coefs(int64_t step) {
     return BdfCoef{4.0 / 3.0, -1.0 / 3.0, 2.0 / 3.0, 1.0 / 3.0};
 }
 
+// FP32-tile mode: the switch to FP64 evaluations happens once every running
+// suspension has max|f|/a <= max(kSwitchTol tol, kNoiseMargin kF32Floor max|b dt V|/a),
+// kF32Floor being the measured rounding floor of an FP32-tile apply relative to
+// the size of its mobility term.
+constexpr double kSwitchTol = 10.0;
+constexpr double kF32Floor = 3e-8;
+constexpr double kNoiseMargin = 30.0;
+
 // adds the recorded mobility-kernel durations (stream already synchronised)
 int collect_timing(fil_sim* s) {
     for (int i = 0; i < s->nev; i++) {
         float ms = 0.f;
         FIL_HIP_TRY(hipEventElapsedTime(&ms, s->ev[2 * i], s->ev[2 * i + 1]));
-        s->rpy_ms += ms;
-        s->rpy_launches++;
+        s->rpy_ms[s->ev_prec[i]] += ms;
+        s->rpy_launches[s->ev_prec[i]]++;
     }
     s->nev = 0;
     return FIL_OK;
@@ -121,7 +144,9 @@ int eval_residual(fil_sim* s, const double* X, double* fout) {
     const double tt = s->t + s->p.dt;
     TRY(state_forces_launch(s->d, X, s->qj, tt, s->active_d, s->Yc, s->qc, s->F, s->T, s->box, s->st));
     // the source records sit at the start of the mobility workspace in both plans
-    TRY(steric_pack_launch(s->d, s->Yc, s->box, s->active_d, s->F, s->T, s->p.prec, s->rpy_work, s->st));
+    const int c = s->cur;
+    TRY(steric_pack_launch(s->d, s->Yc, s->box, s->active_d, s->F, s->T, c ? FIL_PREC_F32TILE : FIL_PREC_F64,
+                           s->rpy_work[c], s->st));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (s->timing) {
         while ((int)s->ev.size() < 2 * (s->nev + 1)) {
@@ -131,37 +156,46 @@ int eval_residual(fil_sim* s, const double* X, double* fout) {
         }
         e0 = s->ev[2 * s->nev];
         e1 = s->ev[2 * s->nev + 1];
+        if ((int)s->ev_prec.size() <= s->nev) s->ev_prec.resize(s->nev + 1);
+        s->ev_prec[s->nev] = c;
         s->nev++;
     }
     const double* part = nullptr;
     int K = 1;
     if (s->batched) {
-        TRY(rpy_batch_launch(s->bplan, s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->rpy_work, s->st, e0, e1,
+        TRY(rpy_batch_launch(s->bplan[c], s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->rpy_work[c], s->st, e0, e1,
                              true));
     } else {
         // the split-K partials are summed inside the residual kernel
-        TRY(rpy_launch(s->rplan, s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->rpy_work, s->st, e0, e1, true,
-                       false));
-        if (s->rplan.K > 1) {
-            part = rpy_partials(s->rplan, s->rpy_work);
-            K = s->rplan.K;
+        TRY(rpy_launch(s->rplan[c], s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->rpy_work[c], s->st, e0, e1,
+                       true, false));
+        if (s->rplan[c].K > 1) {
+            part = rpy_partials(s->rplan[c], s->rpy_work[c]);
+            K = s->rplan[c].K;
         }
     }
     s->rb ^= 1;
     TRY(residual_launch(s->d, s->bc, X, s->Xj, s->Yc, s->Yj, s->Yjm1, s->V, s->W, part, K, s->active_d, fout,
-                        s->resbits_d + s->rb * s->nsusp, s->resbits_d + (1 - s->rb) * s->nsusp, s->st));
+                        s->resbits_d + 2 * s->rb * s->nsusp, s->resbits_d + 2 * (1 - s->rb) * s->nsusp, s->st));
     return FIL_OK;
 }
 
-int read_resid(fil_sim* s, std::vector<double>& res) {
-    FIL_HIP_TRY(hipMemcpyAsync(s->resbits_h, s->resbits_d + s->rb * s->nsusp, s->nsusp * sizeof(unsigned long long),
+// max|f|/a and max|b dt (V, dexpinv Omega)| per suspension of the last evaluation
+int read_resid(fil_sim* s, std::vector<double>& res, std::vector<double>* vmax = nullptr) {
+    const int64_t ns = s->nsusp;
+    FIL_HIP_TRY(hipMemcpyAsync(s->resbits_h, s->resbits_d + 2 * s->rb * ns, 2 * ns * sizeof(unsigned long long),
                                hipMemcpyDeviceToHost, s->st));
     FIL_HIP_TRY(hipStreamSynchronize(s->st));
-    res.resize(s->nsusp);
-    for (int64_t i = 0; i < s->nsusp; i++) {
+    res.resize(ns);
+    if (vmax) vmax->resize(ns);
+    for (int64_t i = 0; i < ns; i++) {
         double v;
         std::memcpy(&v, &s->resbits_h[i], sizeof v);
         res[i] = v / s->p.a;
+        if (vmax) {
+            std::memcpy(&v, &s->resbits_h[ns + i], sizeof v);
+            (*vmax)[i] = v / s->p.a;
+        }
     }
     return FIL_OK;
 }
@@ -179,6 +213,111 @@ int begin_solve(fil_sim* s, double* dXout) {
                          s->st));
     TRY(j0_solve_launch(s->d, s->AB, s->ipiv, s->AinvT, s->f, s->active_d, s->h, s->st));
     s->k = 0;
+    return FIL_OK;
+}
+
+
+struct SolveLog {
+    std::vector<int32_t> state, iters, applies, applies_hi;  // state: 0 running, 1 converged, -1 failed
+    std::vector<double> last;
+    bool singular = false;
+    explicit SolveLog(int64_t ns) : state(ns, 0), iters(ns, 0), applies(ns, 0), applies_hi(ns, 0), last(ns, 0.0) {}
+};
+
+// Alg. 2 from the iterate in s->X for every active suspension: f_0 = f(X_0), J0
+// at X_0 and its inverse, X_1 = X_0 - J0^{-1} f_0, then one evaluation and one
+// bad-Broyden update per iteration until every suspension has converged or failed.
+// In FP32-tile mode the evaluations start in FP32 and switch to FP64 once every
+// running suspension is near the tolerance or near the FP32 rounding floor;
+// only an FP64 residual can end a step.
+int solve(fil_sim* s, SolveLog& L) {
+    const int64_t ns = s->nsusp;
+    s->cur = s->p.prec == FIL_PREC_F32TILE ? 1 : 0;
+    std::vector<double> res, vmx;
+    bool changed = false;
+    auto count = [&]() {
+        for (int64_t i = 0; i < ns; i++)
+            if (s->active_h[i]) {
+                L.applies[i]++;
+                L.applies_hi[i] += s->cur == 0;
+            }
+    };
+    auto judge = [&](int it) -> bool {
+        bool any = false, near = true;
+        for (int64_t i = 0; i < ns; i++) {
+            if (!s->active_h[i]) continue;
+            L.iters[i] = it;
+            L.last[i] = res[i];
+            if (!std::isfinite(res[i])) L.state[i] = -1;
+            else if (res[i] <= s->p.tol && s->cur == 0) L.state[i] = 1;
+            else if (it >= s->p.kmax) L.state[i] = -1;
+            if (L.state[i] != 0) {
+                s->active_h[i] = 0;
+                changed = true;
+                continue;
+            }
+            any = true;
+            near &= res[i] <= std::max(kSwitchTol * s->p.tol, kNoiseMargin * kF32Floor * vmx[i]);
+        }
+        if (s->cur == 1 && any && (near || 2 * it >= s->p.kmax)) s->cur = 0;
+        return any;
+    };
+    count();
+    TRY(eval_residual(s, s->X, s->f));
+    TRY(begin_solve(s, nullptr));
+    TRY(read_resid(s, res, &vmx));
+    FIL_HIP_TRY(hipMemcpyAsync(s->jflag_h, s->jflag_d, s->M * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+    FIL_HIP_TRY(hipStreamSynchronize(s->st));
+    bool any = judge(0);
+    for (int64_t f = 0; f < s->M; f++)
+        if (s->jflag_h[f]) {
+            set_error("fil_bdf2_step: approximate Jacobian block of filament " + std::to_string(f) + " is singular");
+            for (int64_t i = 0; i < ns; i++) s->active_h[i] = 0;
+            std::fill(L.state.begin(), L.state.end(), -1);
+            L.singular = true;
+            changed = true;
+            any = false;
+            break;
+        }
+    if (changed) TRY(upload_flags(s, s->active_d, s->active_h));
+    if (any) TRY(first_step_launch(s->d, s->h, s->f, s->fprev, s->X, nullptr, s->active_d, s->st));
+    for (int it = 1; any; it++) {
+        count();
+        TRY(eval_residual(s, s->X, s->f));
+        TRY(read_resid(s, res, &vmx));
+        changed = false;
+        any = judge(it);
+        if (!any) break;
+        if (changed) TRY(upload_flags(s, s->active_d, s->active_h));
+        TRY(broyden_update_launch(s->d, s->k, s->AB, s->ipiv, s->AinvT, s->Chist, s->Dhist, s->f, s->fprev, s->g0,
+                                  s->h, s->part, s->X, nullptr, s->active_d, s->st));
+        s->k++;
+    }
+    return FIL_OK;
+}
+
+int ensure_learned_buffers(fil_sim* s, int in_pad, int out_pad) {
+    if (!s->feat) TRY(dalloc(s, &s->feat, (size_t)s->M * kMlpFeatPerSeg * s->seg_uniform));
+    if (in_pad && (!s->featb || s->feat_in_pad != in_pad || s->feat_out_pad != out_pad)) {
+        TRY(dalloc(s, &s->featb, (size_t)s->M * in_pad));
+        TRY(dalloc(s, &s->pred, (size_t)s->M * out_pad));
+        s->feat_in_pad = in_pad;
+        s->feat_out_pad = out_pad;
+    }
+    return FIL_OK;
+}
+
+// X = X0 + the network's prediction for every free filament (X0p holds X0)
+int learned_guess(fil_sim* s) {
+    fil_mlp* m = s->mlp;
+    const int N = s->seg_uniform;
+    TRY(learned_features_launch(s->d, N, s->Yj, s->qj, s->F, s->V, s->Xj, s->Xjm1, s->Xjm2, s->feat, s->st));
+    TRY(mlp_standardize(m, s->M, s->feat, nullptr, s->featb, nullptr, s->st));
+    TRY(mlp_forward_rows(m, (int)s->M, s->featb, s->pred, s->st));
+    const float* nrm = mlp_norm(m);
+    const float* mu = nrm + 2 * mlp_in_pad(m);
+    TRY(learned_apply_launch(s->d, N, mlp_out_pad(m), s->pred, mu, mu + mlp_out_pad(m), s->active_d, s->X0p, s->X,
+                             s->st));
     return FIL_OK;
 }
 
@@ -229,6 +368,9 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         for (int64_t x = seg_off[f]; x < seg_off[f + 1]; x++) seg_fil[x] = (int32_t)f;
         if (tether) teth[f] = tether[f] ? 1 : 0;
     }
+    s->seg_uniform = (int)(seg_off[1] - seg_off[0]);
+    for (int64_t f = 0; f < M; f++)
+        if (seg_off[f + 1] - seg_off[f] != s->seg_uniform) s->seg_uniform = 0;
     std::vector<double> base(3 * M);
     for (int64_t f = 0; f < M; f++)
         for (int i = 0; i < 3; i++) base[3 * f + i] = Y0[3 * seg_off[f] + i];
@@ -270,38 +412,42 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     A(d_susp_vblk_off, nsusp + 1) A(d_fil_susp, M) A(d_seg_fil, S) A(d_teth, M) A(d_vblk_susp, nvblk)
     A(d_base, 3 * M)
     if (phase) A(d_phase, M)
-    A(s->Yj, 3 * S) A(s->Yjm1, 3 * S) A(s->qj, 4 * S) A(s->Xj, n6) A(s->Xjm1, n6)
+    A(s->Yj, 3 * S) A(s->Yjm1, 3 * S) A(s->qj, 4 * S) A(s->Xj, n6) A(s->Xjm1, n6) A(s->Xjm2, n6) A(s->X0p, n6)
     A(s->X, n6) A(s->f, n6) A(s->fprev, n6) A(s->h, n6) A(s->g0, n6)
     A(s->Yc, 3 * S) A(s->qc, 4 * S) A(s->F, 3 * S) A(s->T, 3 * S) A(s->V, 3 * S) A(s->W, 3 * S)
     A(s->AB, n6 * kBandW) A(s->ipiv, n6)
     if (dense) { A(s->AinvT, dense_tot) A(d_dense_off, M) }
     A(s->Chist, (size_t)p->kmax * n6) A(s->Dhist, (size_t)p->kmax * n6) A(s->part, (size_t)nvblk * max_dots)
-    A(s->box, 6 * M) A(s->active_d, nsusp) A(s->commit_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 2 * nsusp)
+    A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->active_d, nsusp) A(s->commit_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 4 * nsusp)
 #undef A
     if (rc == FIL_OK) rc = halloc(s, &s->active_h, nsusp);
     if (rc == FIL_OK) rc = halloc(s, &s->commit_h, nsusp);
     if (rc == FIL_OK) rc = halloc(s, &s->jflag_h, M);
-    if (rc == FIL_OK) rc = halloc(s, &s->resbits_h, nsusp);
+    if (rc == FIL_OK) rc = halloc(s, &s->resbits_h, 2 * nsusp);
     if (rc) {
         free_sim(s);
         return rc;
     }
-    // mobility workspace
+    // mobility workspaces: FP64 always (the FP32-tile mode finishes every step in FP64)
     s->batched = nsusp > 1;
-    size_t wbytes;
-    if (s->batched) {
-        s->bplan = rpy_batch_plan(nsusp, susp_seg_off.data(), p->prec);
-        wbytes = s->bplan.total();
-    } else {
-        s->rplan = rpy_plan(S, p->prec);
-        wbytes = s->rplan.total();
+    const int nplan = p->prec == FIL_PREC_F32TILE ? 2 : 1;
+    for (int c = 0; c < nplan; c++) {
+        const int pr = c ? FIL_PREC_F32TILE : FIL_PREC_F64;
+        size_t wbytes;
+        if (s->batched) {
+            s->bplan[c] = rpy_batch_plan(nsusp, susp_seg_off.data(), pr);
+            wbytes = s->bplan[c].total();
+        } else {
+            s->rplan[c] = rpy_plan(S, pr);
+            wbytes = s->rplan[c].total();
+        }
+        char* wk = nullptr;
+        if ((rc = dalloc(s, &wk, wbytes))) {
+            free_sim(s);
+            return rc;
+        }
+        s->rpy_work[c] = wk;
     }
-    char* wk = nullptr;
-    if ((rc = dalloc(s, &wk, wbytes))) {
-        free_sim(s);
-        return rc;
-    }
-    s->rpy_work = wk;
     // ---- uploads
     std::vector<double> Ysoa(3 * S), qsoa(4 * S);
     for (int64_t x = 0; x < S; x++) {
@@ -312,7 +458,13 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         for (int i = 0; i < 4; i++) qsoa[i * S + x] = q0[4 * x + i] * nq;
     }
     std::vector<double> zeros(n6, 0.0);
+    std::vector<double> spar(kSpar * nsusp);
+    for (int64_t i = 0; i < nsusp; i++) {
+        const double v[kSpar] = {p->dt, p->grav[0], p->grav[1], p->grav[2], p->FS};
+        for (int c = 0; c < kSpar; c++) spar[kSpar * i + c] = v[c];
+    }
     auto up = [&]() -> int {
+        TRY(upload(s->spar, spar));
         TRY(upload(d_seg_off, seg_off));
         TRY(upload(d_susp_seg_off, susp_seg_off));
         TRY(upload(d_susp_fil_off, sfo));
@@ -330,10 +482,12 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         TRY(upload(s->qj, qsoa));
         TRY(upload(s->Xj, zeros));
         TRY(upload(s->Xjm1, zeros));
+        TRY(upload(s->Xjm2, zeros));
+        TRY(upload(s->X0p, zeros));
         TRY(upload(s->X, zeros));
-        TRY(upload(s->resbits_d, std::vector<unsigned long long>(2 * nsusp, 0ull)));
+        TRY(upload(s->resbits_d, std::vector<unsigned long long>(4 * nsusp, 0ull)));
         if (s->batched) {
-            TRY(rpy_batch_upload(s->bplan, s->rpy_work, nullptr));
+            for (int c = 0; c < nplan; c++) TRY(rpy_batch_upload(s->bplan[c], s->rpy_work[c], nullptr));
             FIL_HIP_TRY(hipDeviceSynchronize());
         }
         return FIL_OK;
@@ -367,9 +521,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     d.KB = p->KB;
     d.KT = p->KT;
     d.chi = p->chi;
-    d.FS = p->FS;
-    for (int i = 0; i < 3; i++) d.grav[i] = p->grav[i];
-    d.dt = p->dt;
+    d.spar = s->spar;
     d.K0 = p->K0;
     d.kw = p->kw;
     d.omega = p->omega;
@@ -388,113 +540,147 @@ int fil_set_stream(fil_sim* sim, void* stream) {
     return FIL_OK;
 }
 
+int fil_set_suspension_params(fil_sim* s, const double* dt, const double* grav, const double* FS) {
+    FIL_CHECK_ARG(s, "fil_set_suspension_params: null sim");
+    FIL_CHECK_ARG(s->step == 0, "fil_set_suspension_params: only before the first step");
+    const int64_t ns = s->nsusp;
+    std::vector<double> sp(kSpar * ns);
+    FIL_HIP_TRY(hipMemcpy(sp.data(), s->spar, sp.size() * sizeof(double), hipMemcpyDeviceToHost));
+    bool differ = false;
+    for (int64_t i = 0; i < ns; i++) {
+        if (dt) {
+            FIL_CHECK_ARG(dt[i] > 0 && std::isfinite(dt[i]), "fil_set_suspension_params: dt must be finite and > 0");
+            sp[kSpar * i] = dt[i];
+            differ |= dt[i] != s->p.dt;
+        }
+        if (grav)
+            for (int c = 0; c < 3; c++) {
+                FIL_CHECK_ARG(std::isfinite(grav[3 * i + c]), "fil_set_suspension_params: non-finite gravity");
+                sp[kSpar * i + 1 + c] = grav[3 * i + c];
+            }
+        if (FS) {
+            FIL_CHECK_ARG(FS[i] >= 0 && std::isfinite(FS[i]), "fil_set_suspension_params: F^S must be >= 0");
+            FIL_CHECK_ARG(FS[i] == 0.0 || s->p.chi > 1.0, "fil_set_suspension_params: steric range chi must exceed 1");
+            sp[kSpar * i + 4] = FS[i];
+        }
+    }
+    FIL_CHECK_ARG(!differ || s->p.K0 == 0.0,
+                  "fil_set_suspension_params: per-suspension dt needs a time-independent preferred curvature (K0 = 0)");
+    FIL_HIP_TRY(hipMemcpy(s->spar, sp.data(), sp.size() * sizeof(double), hipMemcpyHostToDevice));
+    return FIL_OK;
+}
+
 int fil_bdf2_step(fil_sim* s, fil_step_report* report) {
     FIL_CHECK_ARG(s, "fil_bdf2_step: null sim");
     const int64_t ns = s->nsusp;
     s->bc = coefs(s->step);
     s->nev = 0;
-    std::vector<int32_t> state(ns, 0);  // 0 running, 1 converged, -1 failed
-    std::vector<int32_t> iters(ns, 0);
-    std::vector<double> res, last(ns, 0.0);
     for (int64_t i = 0; i < ns; i++) s->active_h[i] = 1;
     TRY(upload_flags(s, s->active_d, s->active_h));
     TRY(initial_guess_launch(s->d, s->step, s->Yj, s->Yjm1, s->Xj, s->Xjm1, s->active_d, s->X, s->st));
-    TRY(eval_residual(s, s->X, s->f));
-    TRY(begin_solve(s, nullptr));
-    TRY(read_resid(s, res));
-    FIL_HIP_TRY(hipMemcpyAsync(s->jflag_h, s->jflag_d, s->M * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
-    FIL_HIP_TRY(hipStreamSynchronize(s->st));
-    bool changed = false;
-    for (int64_t i = 0; i < ns; i++) {
-        last[i] = res[i];
-        if (!std::isfinite(res[i])) state[i] = -1;
-        else if (res[i] <= s->p.tol) state[i] = 1;
-        if (state[i] != 0) {
-            s->active_h[i] = 0;
-            changed = true;
-        }
-    }
-    for (int64_t f = 0; f < s->M; f++)
-        if (s->jflag_h[f]) {
-            set_error("fil_bdf2_step: approximate Jacobian block of filament " + std::to_string(f) + " is singular");
-            for (int64_t i = 0; i < ns; i++) s->active_h[i] = 0;
-            std::fill(state.begin(), state.end(), -1);
-            changed = true;
-            break;
-        }
-    bool any = false;
-    for (int64_t i = 0; i < ns; i++) any |= s->active_h[i] != 0;
-    if (changed) TRY(upload_flags(s, s->active_d, s->active_h));
-    if (any) TRY(first_step_launch(s->d, s->h, s->f, s->fprev, s->X, nullptr, s->active_d, s->st));
-    for (int it = 1; any; it++) {
-        TRY(eval_residual(s, s->X, s->f));
-        TRY(read_resid(s, res));
-        changed = false;
-        any = false;
+    FIL_HIP_TRY(hipMemcpyAsync(s->X0p, s->X, 6 * s->S * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+    bool learned = s->use_mlp && s->mlp && s->step >= 3;
+    if (learned) TRY(learned_guess(s));
+    SolveLog L(ns);
+    TRY(solve(s, L));
+    bool all_ok = std::all_of(L.state.begin(), L.state.end(), [](int32_t v) { return v == 1; });
+    if (!all_ok && learned) {
+        // the plain warm start is the fallback: the step restarts from it
+        s->fallbacks++;
+        learned = false;
+        for (int64_t i = 0; i < ns; i++) s->active_h[i] = 1;
+        TRY(upload_flags(s, s->active_d, s->active_h));
+        FIL_HIP_TRY(hipMemcpyAsync(s->X, s->X0p, 6 * s->S * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+        SolveLog L2(ns);
+        TRY(solve(s, L2));
         for (int64_t i = 0; i < ns; i++) {
-            if (!s->active_h[i]) continue;
-            iters[i] = it;
-            last[i] = res[i];
-            if (!std::isfinite(res[i])) state[i] = -1;
-            else if (res[i] <= s->p.tol) state[i] = 1;
-            else if (it >= s->p.kmax) state[i] = -1;
-            if (state[i] != 0) {
-                s->active_h[i] = 0;
-                changed = true;
-            } else {
-                any = true;
-            }
+            L2.applies[i] += L.applies[i];
+            L2.applies_hi[i] += L.applies_hi[i];
         }
-        if (!any) break;
-        if (changed) TRY(upload_flags(s, s->active_d, s->active_h));
-        TRY(broyden_update_launch(s->d, s->k, s->AB, s->ipiv, s->AinvT, s->Chist, s->Dhist, s->f, s->fprev, s->g0,
-                                  s->h, s->part, s->X, nullptr, s->active_d, s->st));
-        s->k++;
+        L = L2;
+        all_ok = std::all_of(L.state.begin(), L.state.end(), [](int32_t v) { return v == 1; });
     }
     if (s->timing) {
         FIL_HIP_TRY(hipStreamSynchronize(s->st));
         TRY(collect_timing(s));
     }
-    bool all_ok = true;
-    for (int64_t i = 0; i < ns; i++) {
-        all_ok &= state[i] == 1;
-        if (report) {
-            report[i].iters = iters[i];
-            report[i].mobility_applies = iters[i] + 1;
-            report[i].converged = state[i] == 1;
-            report[i].pad = 0;
-            report[i].resid = last[i];
-        }
+    for (int64_t i = 0; i < ns && report; i++) {
+        report[i].iters = L.iters[i];
+        report[i].mobility_applies = L.applies[i];
+        report[i].converged = L.state[i] == 1;
+        report[i].applies_f64 = L.applies_hi[i];
+        report[i].resid = L.last[i];
+        report[i].used_learned = learned ? 1 : 0;
+        report[i].pad = 0;
     }
     if (!all_ok) {
         bool nonfinite = false;
-        for (int64_t i = 0; i < ns; i++) nonfinite |= !std::isfinite(last[i]);
-        set_error(nonfinite ? "fil_bdf2_step: residual became non-finite; state left at the previous step"
-                            : "fil_bdf2_step: Broyden did not reach the tolerance; state left at the previous step");
-        return nonfinite ? FIL_ENONFINITE : FIL_ENOCONV;
+        for (int64_t i = 0; i < ns; i++) nonfinite |= !std::isfinite(L.last[i]);
+        if (!L.singular)
+            set_error(nonfinite ? "fil_bdf2_step: residual became non-finite; state left at the previous step"
+                                : "fil_bdf2_step: Broyden did not reach the tolerance; state left at the previous step");
+        return nonfinite || L.singular ? FIL_ENONFINITE : FIL_ENOCONV;
     }
     for (int64_t i = 0; i < ns; i++) s->commit_h[i] = 1;
     TRY(upload_flags(s, s->commit_d, s->commit_h));
-    TRY(finalize_launch(s->d, s->commit_d, s->Yc, s->qc, s->X, s->Yj, s->Yjm1, s->qj, s->Xj, s->Xjm1, s->st));
+    TRY(finalize_launch(s->d, s->commit_d, s->Yc, s->qc, s->X, s->Yj, s->Yjm1, s->qj, s->Xj, s->Xjm1, s->Xjm2,
+                        s->st));
     FIL_HIP_TRY(hipStreamSynchronize(s->st));
     s->t += s->p.dt;
     s->step += 1;
     return FIL_OK;
 }
 
+int fil_sim_set_mlp(fil_sim* s, fil_mlp* m, int enable) {
+    FIL_CHECK_ARG(s, "fil_sim_set_mlp: null sim");
+    if (enable) {
+        FIL_CHECK_ARG(m, "fil_sim_set_mlp: null network");
+        FIL_CHECK_ARG(s->seg_uniform == mlp_segments(m),
+                      "fil_sim_set_mlp: every filament must have the network's number of segments");
+        FIL_CHECK_ARG(s->M <= mlp_max_batch(m), "fil_sim_set_mlp: more filaments than the network's max_batch");
+        TRY(ensure_learned_buffers(s, mlp_in_pad(m), mlp_out_pad(m)));
+    }
+    s->mlp = enable ? m : nullptr;
+    s->use_mlp = enable != 0;
+    return FIL_OK;
+}
+
+int fil_sim_features(fil_sim* s, float* out) {
+    FIL_CHECK_ARG(s && out, "fil_sim_features: null argument");
+    FIL_CHECK_ARG(s->seg_uniform > 0, "fil_sim_features: filaments of different lengths");
+    FIL_CHECK_ARG(s->step >= 1, "fil_sim_features: no step taken yet");
+    return learned_features_launch(s->d, s->seg_uniform, s->Yj, s->qj, s->F, s->V, s->Xj, s->Xjm1, s->Xjm2, out,
+                                   s->st);
+}
+
+int fil_sim_step_target(fil_sim* s, float* out) {
+    FIL_CHECK_ARG(s && out, "fil_sim_step_target: null argument");
+    FIL_CHECK_ARG(s->seg_uniform > 0, "fil_sim_step_target: filaments of different lengths");
+    FIL_CHECK_ARG(s->step >= 1, "fil_sim_step_target: no step taken yet");
+    return learned_target_launch(s->d, s->seg_uniform, s->Xj, s->X0p, out, s->st);
+}
+
+int fil_sim_fallbacks(fil_sim* s, int64_t* n) {
+    FIL_CHECK_ARG(s && n, "fil_sim_fallbacks: null argument");
+    *n = s->fallbacks;
+    return FIL_OK;
+}
+
 int fil_set_timing(fil_sim* s, int enable) {
     FIL_CHECK_ARG(s, "fil_set_timing: null sim");
     s->timing = enable != 0;
-    s->rpy_ms = 0.0;
-    s->rpy_launches = 0;
+    s->rpy_ms[0] = s->rpy_ms[1] = 0.0;
+    s->rpy_launches[0] = s->rpy_launches[1] = 0;
     s->nev = 0;
     return FIL_OK;
 }
 
 int fil_get_timing(fil_sim* s, double* rpy_ms, int64_t* rpy_launches) {
     FIL_CHECK_ARG(s, "fil_get_timing: null sim");
-    if (rpy_ms) *rpy_ms = s->rpy_ms;
-    if (rpy_launches) *rpy_launches = s->rpy_launches;
+    for (int c = 0; c < 2; c++) {
+        if (rpy_ms) rpy_ms[c] = s->rpy_ms[c];
+        if (rpy_launches) rpy_launches[c] = s->rpy_launches[c];
+    }
     return FIL_OK;
 }
 

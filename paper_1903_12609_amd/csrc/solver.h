@@ -13,6 +13,7 @@ constexpr size_t kDenseInvBytes = size_t(64) << 20;  // explicit J0^{-1} used up
 constexpr int kMaxIter = 256;     // Broyden history capacity
 constexpr int kMaxDots = kMaxIter + 2;
 constexpr int kVecBlock = 1024;   // residual-vector elements per Broyden vector block
+constexpr int kSpar = 5;          // per-suspension parameters: dt, gravity force (3), F^S
 
 // BDF coefficients: y - a1 y^j - a2 y^{j-1} - b dt v = 0, u - g u^j - b dt dexpinv(Omega) = 0
 struct BdfCoef {
@@ -38,7 +39,8 @@ struct SimDev {
     const int64_t* vblk_start;     // [nvblk+1]
     const int64_t* susp_vblk_off;  // [nsusp+1]
     int max_dots;
-    double a, eta, dL, KB, KT, chi, FS, grav[3], dt, K0, kw, omega;
+    const double* spar;            // [nsusp][5] per suspension: dt, gravity force (3), steric strength F^S
+    double a, eta, dL, KB, KT, chi, K0, kw, omega;
 };
 
 // configuration from X, internal forces (F = F^C + gravity, T = T^C + T^E) and filament boxes
@@ -47,10 +49,11 @@ int state_forces_launch(const SimDev& d, const double* X, const double* qj, doub
 // adds the steric barrier into F and writes the mobility source records (precision prec)
 int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, const int32_t* active, double* F,
                        const double* T, int prec, void* pk, hipStream_t st);
-// residual rows and max|f| per suspension into resbits (zeroed by the previous call);
-// velocities from the K mobility partials `part` when non-null, else from V, W
+// residual rows; max|f| per suspension into resbits[0, nsusp) and max|b dt (V, dexpinv Omega)| into
+// resbits[nsusp, 2 nsusp) (zeroed by the previous call, which also zeroes resbits_next);
+// velocities from the K mobility partials `part` when non-null (then also stored to V, W), else from V, W
 int residual_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* Xj, const double* Yc,
-                    const double* Yj, const double* Yjm1, const double* V, const double* W, const double* part, int K,
+                    const double* Yj, const double* Yjm1, double* V, double* W, const double* part, int K,
                     const int32_t* active, double* f, unsigned long long* resbits, unsigned long long* resbits_next,
                     hipStream_t st);
 int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const double* Yjm1, const double* Xj,
@@ -69,7 +72,8 @@ int broyden_update_launch(const SimDev& d, int k, const double* AB, const int32_
                           double* part, double* X, double* dXout, const int32_t* active, hipStream_t st);
 int first_step_launch(const SimDev& d, const double* h, const double* f, double* fprev, double* X, double* dXout,
                       const int32_t* active, hipStream_t st);
+// commits the step: Y, q from the converged state; X history shifted (Xjm2 may be null)
 int finalize_launch(const SimDev& d, const int32_t* commit, const double* Yc, const double* qc, const double* X,
-                    double* Yj, double* Yjm1, double* qj, double* Xj, double* Xjm1, hipStream_t st);
+                    double* Yj, double* Yjm1, double* qj, double* Xj, double* Xjm1, double* Xjm2, hipStream_t st);
 
 }  // namespace fil

@@ -101,7 +101,8 @@ __global__ void __launch_bounds__(64) state_forces_kernel(SimDev d, const double
             mm = joint_moment(Q4{sq[n - 1][0], sq[n - 1][1], sq[n - 1][2], sq[n - 1][3]}, qn,
                               joint_kappa(d, f, n - 1, tt), d.dL, d.KB, d.KT);
         }
-        V3 fc = lp - lm + v3(d.grav[0], d.grav[1], d.grav[2]);
+        const double* sp = d.spar + kSpar * d.fil_susp[f];
+        V3 fc = lp - lm + v3(sp[1], sp[2], sp[3]);
         V3 tc = (0.5 * d.dL) * cross(v3(st[n][0], st[n][1], st[n][2]), lp + lm) + (mp - mm);
         if (teth && n == 0) {
             fc = fc + ldx(Xf, 0);
@@ -141,10 +142,11 @@ __global__ void __launch_bounds__(64) steric_pack_kernel(SimDev d, const double*
     const int64_t sn = s0 + (valid ? lane : N - 1);
     const double y0 = Yc[sn], y1 = Yc[S + sn], y2 = Yc[2 * S + sn];
     double fx = 0, fy = 0, fz = 0;
-    if (d.FS != 0.0) {
+    const double FS = d.spar[kSpar * isus + 4];
+    if (FS != 0.0) {
         const double rc = 2.0 * d.chi * d.a, rc2 = rc * rc;
         const double k4 = 4.0 * d.a * d.a * d.chi * d.chi, kden = 1.0 / (4.0 * d.a * d.a * (d.chi * d.chi - 1.0));
-        const double fscale = d.FS / (2.0 * d.a);
+        const double fscale = FS / (2.0 * d.a);
         const double* bf = box + 6 * f;
         const double lo0 = bf[0], lo1 = bf[1], lo2 = bf[2], hi0 = bf[3], hi1 = bf[4], hi2 = bf[5];
         const int64_t g0 = d.susp_fil_off[isus], g1 = d.susp_fil_off[isus + 1];
@@ -209,12 +211,29 @@ int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, con
 // f^1 = Y_1 - a1 Y_1^j - a2 Y_1^{j-1} - b dt V_1
 // f^2_n = u_n - g u_n^j - b dt dexpinv_{u_n}(Omega_n)
 // f^3_n = Y_n - a1 Y_n^j - a2 Y_n^{j-1} - b dt V_n
-// plus max|f| per suspension (as the bit pattern of a non-negative double, so an
-// integer atomicMax orders it; a NaN compares above every finite value).
+// plus, per suspension, max|f| and max|b dt (V, dexpinv Omega)| (the size of the
+// mobility term, which sets the rounding floor of a reduced-precision apply), each
+// as the bit pattern of a non-negative double so an integer atomicMax orders it
+// (a NaN compares above every finite value).  When the velocities come from the
+// mobility partials they are also stored to V, W.
+__device__ __forceinline__ void susp_max(double v, int32_t isus, const int32_t* __restrict__ active,
+                                         unsigned long long* __restrict__ out) {
+    // one atomic per wave for the wave's leading suspension, one per lane otherwise
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    const int32_t first = __shfl(isus, 0, 64);
+    unsigned long long m = isus == first ? bits : 0ull;
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long other = __shfl_xor(m, o, 64);
+        m = other > m ? other : m;
+    }
+    if ((threadIdx.x & 63) == 0 && first >= 0 && active[first]) atomicMax(&out[first], m);
+    if (isus != first && isus >= 0 && active[isus]) atomicMax(&out[isus], bits);
+}
+
 __global__ void __launch_bounds__(256) residual_kernel(SimDev d, BdfCoef bc, const double* __restrict__ X,
                                                      const double* __restrict__ Xj, const double* __restrict__ Yc,
                                                      const double* __restrict__ Yj, const double* __restrict__ Yjm1,
-                                                     const double* __restrict__ V, const double* __restrict__ W,
+                                                     double* __restrict__ V, double* __restrict__ W,
                                                      const double* __restrict__ part, int K,
                                                      const int32_t* __restrict__ active, double* __restrict__ fout,
                                                      unsigned long long* __restrict__ resbits,
@@ -222,8 +241,8 @@ __global__ void __launch_bounds__(256) residual_kernel(SimDev d, BdfCoef bc, con
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // the other buffer is zeroed for the next evaluation (the host has read it)
     if (blockIdx.x == 0)
-        for (int64_t i = threadIdx.x; i < d.nsusp; i += blockDim.x) resbits_next[i] = 0ull;
-    double amax = 0.0;
+        for (int64_t i = threadIdx.x; i < 2 * d.nsusp; i += blockDim.x) resbits_next[i] = 0ull;
+    double amax = 0.0, vmax = 0.0;
     int32_t isus = -1;
     if (s < d.S) {
         const int32_t f = d.seg_fil[s];
@@ -232,7 +251,7 @@ __global__ void __launch_bounds__(256) residual_kernel(SimDev d, BdfCoef bc, con
             const int64_t s0 = d.seg_off[f], N = d.seg_off[f + 1] - s0, n = s - s0;
             const int teth = d.tether[f];
             const int64_t S = d.S;
-            const double bdt = bc.b * d.dt;
+            const double bdt = bc.b * d.spar[kSpar * isus];
             const double* Xf = X + 6 * s0;
             double* ff = fout + 6 * s0;
             V3 vel, om;
@@ -247,6 +266,8 @@ __global__ void __launch_bounds__(256) residual_kernel(SimDev d, BdfCoef bc, con
                 }
                 vel = v3(acc[0], acc[1], acc[2]);
                 om = v3(acc[3], acc[4], acc[5]);
+                st3(V, S, s, vel);
+                st3(W, S, s, om);
             } else {
                 vel = ld3(V, S, s);
                 om = ld3(W, S, s);
@@ -254,7 +275,10 @@ __global__ void __launch_bounds__(256) residual_kernel(SimDev d, BdfCoef bc, con
             const V3 yres = ld3(Yc, S, s) - bc.a1 * ld3(Yj, S, s) - bc.a2 * ld3(Yjm1, S, s) - bdt * vel;
             V3 u = ldx(Xf, 3 + 3 * n), uj = ldx(Xj + 6 * s0, 3 + 3 * n);
             if (teth && n == 0) u = uj = v3(0, 0, 0);
-            const V3 ures = u - bc.g * uj - bdt * dexpinv(u, om);
+            const V3 dom = dexpinv(u, om);
+            const V3 ures = u - bc.g * uj - bdt * dom;
+            vmax = fabs(bdt) * fmax(fmax(fmax(fabs(vel.x), fabs(vel.y)), fmax(fabs(vel.z), fabs(dom.x))),
+                                    fmax(fabs(dom.y), fabs(dom.z)));
             const int64_t ry = n == 0 ? 0 : 3 + 3 * N + 3 * (n - 1);
             ff[ry] = yres.x;
             ff[ry + 1] = yres.y;
@@ -269,20 +293,12 @@ __global__ void __launch_bounds__(256) residual_kernel(SimDev d, BdfCoef bc, con
                 amax = __longlong_as_double(0x7ff8000000000000ll);
         }
     }
-    // one atomic per wave for the wave's leading suspension, one per lane otherwise
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(amax);
-    const int32_t first = __shfl(isus, 0, 64);
-    unsigned long long m = isus == first ? bits : 0ull;
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long other = __shfl_xor(m, o, 64);
-        m = other > m ? other : m;
-    }
-    if ((threadIdx.x & 63) == 0 && first >= 0 && active[first]) atomicMax(&resbits[first], m);
-    if (isus != first && isus >= 0 && active[isus]) atomicMax(&resbits[isus], bits);
+    susp_max(amax, isus, active, resbits);
+    susp_max(vmax, isus, active, resbits + d.nsusp);
 }
 
 int residual_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* Xj, const double* Yc,
-                    const double* Yj, const double* Yjm1, const double* V, const double* W, const double* part, int K,
+                    const double* Yj, const double* Yjm1, double* V, double* W, const double* part, int K,
                     const int32_t* active, double* f, unsigned long long* resbits, unsigned long long* resbits_next,
                     hipStream_t st) {
     if (d.S > 0)
@@ -533,8 +549,9 @@ __global__ void __launch_bounds__(256) j0_band_assemble_kernel(SimDev d, BdfCoef
     }
     for (int e = threadIdx.x; e < n6 * kBandW; e += blockDim.x) ab[e] = 0.0;
     __syncthreads();
-    J0Ctx c{sh, Xf, N, teth, f, tt, bc.b * d.dt / (6.0 * kPi * d.eta * d.a),
-            bc.b * d.dt / (8.0 * kPi * d.eta * d.a * d.a * d.a)};
+    const double dts = d.spar[kSpar * d.fil_susp[f]];
+    J0Ctx c{sh, Xf, N, teth, f, tt, bc.b * dts / (6.0 * kPi * d.eta * d.a),
+            bc.b * dts / (8.0 * kPi * d.eta * d.a * d.a * d.a)};
     const int nb = 2 * N;
     for (int item = threadIdx.x; item < nb * 5; item += blockDim.x) {
         const int R = item / 5, C = R + item % 5 - 2;
@@ -964,7 +981,8 @@ __global__ void __launch_bounds__(256) finalize_kernel(SimDev d, const int32_t* 
                                                      const double* __restrict__ Yc, const double* __restrict__ qc,
                                                      const double* __restrict__ X, double* __restrict__ Yj,
                                                      double* __restrict__ Yjm1, double* __restrict__ qj,
-                                                     double* __restrict__ Xj, double* __restrict__ Xjm1) {
+                                                     double* __restrict__ Xj, double* __restrict__ Xjm1,
+                                                     double* __restrict__ Xjm2) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= d.S) return;
     if (!commit[d.fil_susp[d.seg_fil[s]]]) return;
@@ -975,15 +993,16 @@ __global__ void __launch_bounds__(256) finalize_kernel(SimDev d, const int32_t* 
     }
     for (int i = 0; i < 4; i++) qj[i * S + s] = qc[i * S + s];
     for (int i = 0; i < 6; i++) {
+        if (Xjm2) Xjm2[6 * s + i] = Xjm1[6 * s + i];
         Xjm1[6 * s + i] = Xj[6 * s + i];
         Xj[6 * s + i] = X[6 * s + i];
     }
 }
 
 int finalize_launch(const SimDev& d, const int32_t* commit, const double* Yc, const double* qc, const double* X,
-                    double* Yj, double* Yjm1, double* qj, double* Xj, double* Xjm1, hipStream_t st) {
+                    double* Yj, double* Yjm1, double* qj, double* Xj, double* Xjm1, double* Xjm2, hipStream_t st) {
     if (d.S == 0) return FIL_OK;
-    finalize_kernel<<<(unsigned)ceil_div(d.S, 256), 256, 0, st>>>(d, commit, Yc, qc, X, Yj, Yjm1, qj, Xj, Xjm1);
+    finalize_kernel<<<(unsigned)ceil_div(d.S, 256), 256, 0, st>>>(d, commit, Yc, qc, X, Yj, Yjm1, qj, Xj, Xjm1, Xjm2);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }

@@ -1,0 +1,173 @@
+"""GPU parity of the learned warm start: the BF16 MFMA network's forward pass,
+gradients and Adam step against the FP64 oracle network, the feature and
+target kernels against their oracle definitions, and the learned first
+iterate inside the implicit step."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import learned as OL
+from oracle import mlp as OM
+from paper_1903_12609_amd import synth
+
+from gpu_util import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_bits(x):
+    a = np.ascontiguousarray(OM.bf16_round(x).astype(np.float32))
+    return (a.view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+
+
+def _setup(n_seg, width, depth, B, seed):
+    import torch
+    import paper_1903_12609_amd as fil
+    m = fil.MLP(n_seg, width=width, depth=depth, max_batch=max(B, 64), seed=seed)
+    rng = np.random.default_rng(seed)
+    P = m.get_params().astype(np.float64)
+    P += rng.standard_normal(P.size) * 0.02  # non-zero biases too
+    dims = m.layer_dims
+    # zero the padding (inputs beyond n_in, outputs beyond n_out)
+    params = OM.unflatten(P, dims)
+    params[0][0][:, m.n_in:] = 0.0
+    params[-1][0][m.n_out:, :] = 0.0
+    params[-1][1][m.n_out:] = 0.0
+    P = OM.flatten(params).astype(np.float32)
+    m.set_params(P)
+    X = np.zeros((B, m.n_in_pad))
+    X[:, :m.n_in] = rng.standard_normal((B, m.n_in))
+    T = np.zeros((B, m.n_out_pad))
+    T[:, :m.n_out] = rng.standard_normal((B, m.n_out))
+    xb = torch.from_numpy(_bf16_bits(X)).cuda()
+    # oracle at the BF16-rounded weights and inputs
+    ob = [(OM.bf16_round(W), b.astype(np.float32).astype(np.float64)) for W, b in OM.unflatten(P, dims)]
+    return m, P, xb, OM.bf16_round(X), T, ob
+
+
+@pytest.mark.parametrize("n_seg,width,depth,B", [(32, 256, 3, 500), (4, 64, 2, 70)])
+def test_forward_matches_oracle(n_seg, width, depth, B):
+    print("case forward", n_seg, width, depth, B, flush=True)
+    m, P, xb, Xr, T, ob = _setup(n_seg, width, depth, B, 11)
+    Y = m.forward(xb).cpu().numpy()
+    Yo, _, _ = OM.forward(ob, Xr)
+    err = rel_l2(Y[:, :m.n_out], Yo[:, :m.n_out])
+    print("forward rel L2 %.3e" % err)
+    assert err <= 2e-2
+
+
+@pytest.mark.parametrize("n_seg,width,depth,B", [(32, 256, 3, 500), (4, 64, 2, 70)])
+def test_gradients_match_oracle(n_seg, width, depth, B):
+    import torch
+    print("case backward", n_seg, width, depth, B, flush=True)
+    m, P, xb, Xr, T, ob = _setup(n_seg, width, depth, B, 12)
+    t = torch.from_numpy(T.astype(np.float32)).cuda()
+    rows = torch.from_numpy(np.random.default_rng(1).permutation(B).astype(np.int32)).cuda()
+    loss, g = m.backward(xb, t, rows=rows)
+    order = rows.cpu().numpy()
+    Lo, Go = OM.gradients(ob, Xr[order], T[order], n_out=m.n_out)
+    assert abs(loss.item() - Lo) <= 1e-2 * Lo
+    G = OM.unflatten(g.cpu().numpy(), m.layer_dims)
+    for l, ((gW, gb), (oW, obb)) in enumerate(zip(G, Go)):
+        eW, eb = rel_l2(gW, oW), rel_l2(gb, obb)
+        print("layer %d: dW rel L2 %.3e, db rel L2 %.3e" % (l, eW, eb))
+        assert eW <= 2e-2 and eb <= 2e-2
+
+
+def test_adam_first_step_closed_form():
+    """First Adam step: bias-corrected moments are g and g^2, so every
+    parameter moves by -lr g / (|g| + eps) (FP32)."""
+    import torch
+    m, P, xb, Xr, T, ob = _setup(4, 64, 2, 70, 13)
+    t = torch.from_numpy(T.astype(np.float32)).cuda()
+    _, g = m.backward(xb, t)
+    g = g.cpu().numpy().astype(np.float64)
+    lr = 1e-3
+    m.adam_step(lr)
+    P1 = m.get_params().astype(np.float64)
+    ref = P.astype(np.float64) - lr * g / (np.abs(g) + 1e-8)
+    assert np.max(np.abs(P1 - ref)) <= 1e-6 * max(1.0, np.max(np.abs(P)))
+
+
+def test_training_reduces_loss():
+    """Targets that are a fixed smooth function of the inputs are learned."""
+    import torch
+    import paper_1903_12609_amd as fil
+    m = fil.MLP(4, width=64, depth=2, max_batch=256, seed=3)
+    rng = np.random.default_rng(4)
+    n = 2048
+    X = rng.standard_normal((n, m.n_in))
+    A = rng.standard_normal((m.n_in, m.n_out)) / np.sqrt(m.n_in)
+    T = np.tanh(X @ A)
+    feat = torch.from_numpy(X.astype(np.float32)).cuda()
+    targ = torch.from_numpy(T.astype(np.float32)).cuda()
+    from paper_1903_12609_amd import learned
+    hist = learned.train(m, feat, targ, epochs=40, batch=256, lr=3e-3)
+    print("loss: first epoch %.4f -> last %.4f (validation %.4f -> %.4f)" % (hist[0][0], hist[-1][0], hist[0][1],
+                                                                          hist[-1][1]))
+    assert hist[-1][1] < 0.1 * hist[0][1]
+
+
+def _small_run(steps=5):
+    import paper_1903_12609_amd as fil
+    w = synth.sediment_suspension(M=3, N=8, side=30.0, seed=51, dt_over_T=1 / 30)
+    o = oracle.Sim(w.fil_off, w.Y, w.q, nthreads=8, **w.params)
+    g = fil.Sim(w.fil_off, w.Y, w.q, w.params)
+    Xh = [np.zeros(6 * w.S)] * 3
+    for j in range(steps):
+        X0 = o.initial_guess()
+        rc, rep = o.step()
+        r = g.step()[0]
+        assert rc == 0 and r["iters"] == rep.iters
+        Xh = [o.X.copy()] + Xh[:2]
+    return w, o, g, Xh, X0
+
+
+def test_features_and_target_match_oracle():
+    w, o, g, Xh, X0 = _small_run()
+    p = w.params
+    F, T = o.forces(o.X)
+    V, _ = oracle.rpy_apply(o.Y, F, T, p["a"], p["eta"])
+    fo = OL.features(w.fil_off, o.Y, o.q, F, V, Xh[0], Xh[1], Xh[2], p["dL"], p["dt"], p["grav"], p["KB"])
+    fg = g.features().cpu().numpy()
+    err = rel_l2(fg, fo)
+    print("features rel L2 %.3e" % err)
+    assert err <= 1e-6
+    to = OL.target(w.fil_off, o.X, X0, p["dL"], p["grav"], p["KB"])
+    tg = g.step_target().cpu().numpy()
+    err = rel_l2(tg, to)
+    print("target rel L2 %.3e" % err)
+    assert err <= 1e-5
+
+
+def test_zero_prediction_reproduces_plain_steps():
+    """A network whose prediction is exactly zero leaves the first iterate at
+    the plain warm start, so the learned path reproduces the plain run."""
+    import paper_1903_12609_amd as fil
+    w = synth.sediment_suspension(M=4, N=8, side=30.0, seed=52, dt_over_T=1 / 30)
+    m = fil.MLP(8, width=64, depth=2, max_batch=64, seed=1)
+    params = OM.unflatten(m.get_params().astype(np.float64), m.layer_dims)
+    params[-1] = (np.zeros_like(params[-1][0]), np.zeros_like(params[-1][1]))
+    m.set_params(OM.flatten(params).astype(np.float32))
+    a = fil.Sim(w.fil_off, w.Y, w.q, w.params)
+    b = fil.Sim(w.fil_off, w.Y, w.q, w.params)
+    b.set_mlp(m)
+    for j in range(6):
+        ra, rb = a.step()[0], b.step()[0]
+        assert ra["iters"] == rb["iters"]
+        assert rb["used_learned"] == (j >= 3)
+    assert np.array_equal(a.read_state()[0], b.read_state()[0])
+
+
+def test_learned_start_with_untrained_network_still_converges():
+    """An arbitrary prediction cannot change the result's tolerance: each step
+    either converges from the learned start or falls back to the plain one."""
+    import paper_1903_12609_amd as fil
+    w = synth.sediment_suspension(M=4, N=8, side=30.0, seed=53, dt_over_T=1 / 30)
+    m = fil.MLP(8, width=64, depth=2, max_batch=64, seed=2)
+    g = fil.Sim(w.fil_off, w.Y, w.q, w.params)
+    g.set_mlp(m)
+    for j in range(6):
+        r = g.step()[0]
+        assert r["converged"] and r["resid"] <= w.params["tol"]
+    print("fallbacks", g.fallbacks())

@@ -151,3 +151,47 @@ def test_batched_suspensions_match_separate_runs():
     Yg, _, _ = g.read_state()
     Yo = np.concatenate([o.Y for o in os_])
     assert rel_l2(Yg, Yo) <= 1e-8
+
+
+def test_batched_suspensions_with_their_own_parameters():
+    """Suspensions of different N carry their own dt, gravity W dL and F^S
+    (each from its own length L); each matches its own oracle run."""
+    import paper_1903_12609_amd as fil
+    ws = [synth.sediment_suspension(M=m, N=n, side=40.0 * m ** (1 / 3), seed=40 + m, dt_over_T=1 / 30)
+          for m, n in ((2, 12), (4, 20), (1, 33))]
+    fil_off = [0]
+    for w in ws:
+        fil_off += list(fil_off[-1] + w.fil_off[1:])
+    sfo = np.concatenate([[0], np.cumsum([w.M for w in ws])])
+    g = fil.Sim(fil_off, np.concatenate([w.Y for w in ws]), np.concatenate([w.q for w in ws]), ws[0].params,
+                susp_fil_off=sfo)
+    g.set_suspension_params(dt=[w.params["dt"] for w in ws], grav=[w.params["grav"] for w in ws],
+                            FS=[w.params["FS"] for w in ws])
+    os_ = [oracle.Sim(w.fil_off, w.Y, w.q, nthreads=8, **w.params) for w in ws]
+    for j in range(4):
+        reps = g.step()
+        for i, o in enumerate(os_):
+            rc, rep = o.step()
+            assert rc == 0 and reps[i]["iters"] == rep.iters
+    Yg, _, _ = g.read_state()
+    Yo = np.concatenate([o.Y for o in os_])
+    assert rel_l2(Yg, Yo) <= 1e-8
+
+
+def test_f32tile_steps_finish_in_fp64():
+    """FP32-tile mode: every step starts with FP32 pair tiles and ends on an FP64
+    residual within tol, so the trajectory stays within the tolerance of the
+    FP64 oracle's."""
+    import paper_1903_12609_amd as fil
+    w = WL["susp8x20"]
+    o = oracle.Sim(w.fil_off, w.Y, w.q, nthreads=8, **w.params)
+    g = fil.Sim(w.fil_off, w.Y, w.q, w.params, prec="f32tile")
+    for j in range(8):
+        r = g.step()[0]
+        rc, rep = o.step()
+        assert rc == 0 and r["converged"] and r["resid"] <= w.params["tol"]
+        assert 1 <= r["applies_f64"] < r["applies"], r
+    Yg, _, _ = g.read_state()
+    err = rel_l2(Yg, o.Y)
+    print("f32tile trajectory vs FP64 oracle after 8 steps: rel L2 %.3e" % err)
+    assert err <= 1e-6
