@@ -14,7 +14,8 @@ After `warm` steps (the features need three committed steps of history) every
 step contributes one (features, target) pair per filament.  The
 "suspension" source draws the pairs from small sedimenting suspensions of
 the same filaments instead (placed like the sedimenting suspension at its
-density), so the features see hydrodynamic interactions.
+density), so the features see hydrodynamic interactions, and the "dense"
+source from one large suspension at that density.
 """
 from __future__ import annotations
 
@@ -46,6 +47,11 @@ def _ensemble(source, n_fil, N, seed, dt_over_T):
             w = synth.single_filament(N=N, seed=int(rng.integers(1 << 31)), B=B, dt_over_T=dt_over_T,
                                       bend=rng.uniform(0.0, 0.05))
             ws.append(w)
+    elif source == "dense":
+        # one suspension of n_fil filaments at the sedimenting suspension's density
+        side = 200.0 * (n_fil * N / 2000.0) ** (1.0 / 3.0)
+        ws.append(synth.sediment_suspension(M=n_fil, N=N, side=side, seed=int(rng.integers(1 << 31)),
+                                            dt_over_T=dt_over_T))
     elif source == "suspension":
         per = 10
         for i in range(max(1, n_fil // per)):
@@ -58,26 +64,42 @@ def _ensemble(source, n_fil, N, seed, dt_over_T):
 
 
 def generate(n_fil=500, N=32, steps=100, warm=3, seed=2024, source="single", dt_over_T=1 / 30, log=None):
-    """(features [n, 19N], targets [n, 6N]) float32 device tensors, n = n_fil x steps."""
+    """(features [n, 19N], targets [n, 6N]) float32 device tensors, n = n_fil x steps.
+    A simulation whose step fails (Broyden diverging) is dropped from that step
+    on and replaced by a freshly seeded one until n samples are collected."""
     import torch
-    ws = _ensemble(source, n_fil, N, seed, dt_over_T)
-    fil_off, sfo, Y, q = _batch(ws)
-    sim = Sim(fil_off, Y, q, ws[0].params, susp_fil_off=sfo)
-    sim.set_suspension_params(dt=[w.params["dt"] for w in ws], grav=[w.params["grav"] for w in ws],
-                              FS=[w.params["FS"] for w in ws])
+    from ._native import FilError
     feats, targs = [], []
+    have, attempt = 0, 0
     t0 = time.perf_counter()
-    for j in range(warm + steps):
-        f = sim.features() if j >= warm else None
-        sim.step()
-        if j >= warm:
-            feats.append(f)
-            targs.append(sim.step_target())
-        if log and (j + 1) % 25 == 0:
-            log("training data: step %d/%d (%.1f s)" % (j + 1, warm + steps, time.perf_counter() - t0))
-    sim.close()
+    while have < n_fil * steps:
+        if attempt >= 10:
+            raise RuntimeError("training data: too many diverging simulations")
+        ws = _ensemble(source, n_fil, N, seed + 7919 * attempt, dt_over_T)
+        attempt += 1
+        fil_off, sfo, Y, q = _batch(ws)
+        sim = Sim(fil_off, Y, q, ws[0].params, susp_fil_off=sfo)
+        sim.set_suspension_params(dt=[w.params["dt"] for w in ws], grav=[w.params["grav"] for w in ws],
+                                  FS=[w.params["FS"] for w in ws])
+        try:
+            for j in range(warm + steps):
+                f = sim.features() if j >= warm else None
+                sim.step()
+                if j >= warm:
+                    feats.append(f)
+                    targs.append(sim.step_target())
+                    have += f.shape[0]
+                    if have >= n_fil * steps:
+                        break
+                if log and (j + 1) % 25 == 0:
+                    log("training data: step %d (%.1f s)" % (j + 1, time.perf_counter() - t0))
+        except FilError as e:
+            if log:
+                log("training data: simulation %d stopped (%s); %d samples so far" % (attempt, e, have))
+        finally:
+            sim.close()
     torch.cuda.synchronize()
-    return torch.cat(feats), torch.cat(targs)
+    return torch.cat(feats)[:n_fil * steps], torch.cat(targs)[:n_fil * steps]
 
 
 def train(mlp, feat, targ, epochs=60, batch=1024, lr=1e-3, val_frac=0.1, seed=7, log=None):
