@@ -198,6 +198,20 @@ int fil_get_timing(fil_sim* sim, double* rpy_ms, int64_t* rpy_launches);
 /* Stream the simulation enqueues on (set before stepping). */
 int fil_set_stream(fil_sim* sim, void* stream);
 
+/* Graph execution of the Broyden iterations (the batched-execution form; not
+ * part of the paper): with iters_per_launch = U > 0, fil_bdf2_step runs the
+ * iterations in blocks of U, each block (per iteration: the residual
+ * evaluation with its mobility apply, a device-side convergence test and the
+ * bad-Broyden update) captured once into a HIP graph on a private stream and
+ * replayed on the simulation's stream; the host synchronises once per block
+ * instead of once per iteration.  Iterations after a suspension has converged
+ * inside a block are skipped by its kernels.  Results are identical to
+ * U = 0 (the default, one host test per iteration).  Graphs are cached per
+ * (first iteration, U, precision) and freed by fil_destroy.  U in [0, 64].
+ * fil_set_timing then times only the host-driven evaluations (the first of
+ * each step); captured blocks carry no timing events. */
+int fil_set_graph(fil_sim* sim, int iters_per_launch);
+
 /* ------------------------------------------------------------------------ */
 /* Learned warm start.  Not part of the paper's method: a per-filament       */
 /* network predicts, from the committed state of step j, how far the         */

@@ -105,7 +105,7 @@ class Sim:
     into suspensions (default: one suspension).  prec: "f64" or "f32tile".
     """
 
-    def __init__(self, fil_off, Y0, q0, params, susp_fil_off=None, prec="f64", j0_mode="auto"):
+    def __init__(self, fil_off, Y0, q0, params, susp_fil_off=None, prec="f64", j0_mode="auto", graph=0):
         import ctypes
         import numpy as np
         from ._native import Params
@@ -138,6 +138,12 @@ class Sim:
                                vp(th), ctypes.byref(h)))
         self._h = h
         check(lib().fil_set_stream(h, _stream()))
+        if graph:
+            self.set_graph(graph)
+
+    def set_graph(self, iters_per_launch=4):
+        """Run Broyden iterations in captured HIP-graph blocks of this many iterations (0: off)."""
+        check(lib().fil_set_graph(self._h, int(iters_per_launch)))
 
     def set_suspension_params(self, dt=None, grav=None, FS=None):
         """Per-suspension dt [nsusp], gravity force [nsusp,3] and F^S [nsusp] (before the first step)."""

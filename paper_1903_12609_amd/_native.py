@@ -67,6 +67,7 @@ def _declare(L):
         L.fil_read_state.argtypes = [_vp, _vp, _vp, _vp]
         L.fil_set_stream.argtypes = [_vp, _vp]
         L.fil_set_suspension_params.argtypes = [_vp, _vp, _vp, _vp]
+        L.fil_set_graph.argtypes = [_vp, _i]
         L.fil_sim_features.argtypes = [_vp, _vp]
         L.fil_sim_step_target.argtypes = [_vp, _vp]
         L.fil_sim_set_mlp.argtypes = [_vp, _vp, _i]

@@ -48,6 +48,8 @@ struct RpyItem {
     int32_t k;      // source chunk
     int32_t K;      // chunks of the suspension
     int64_t chunk;  // sources per chunk
+    int32_t susp;   // suspension index
+    int32_t pad;
 };
 struct RpySusp {
     int64_t base, part;
@@ -70,7 +72,7 @@ RpyBatchPlan rpy_batch_plan(int64_t nsusp, const int64_t* susp_off, int prec);
 int rpy_batch_upload(const RpyBatchPlan& p, void* work, hipStream_t st);
 int rpy_batch_launch(const RpyBatchPlan& p, const double* Y, const double* F, const double* T, double a, double eta,
                      double* V, double* W, void* work, hipStream_t st, hipEvent_t ev0 = nullptr,
-                     hipEvent_t ev1 = nullptr, bool packed = false);
+                     hipEvent_t ev1 = nullptr, bool packed = false, const int32_t* active = nullptr);
 
 struct RpyPlan {
     int64_t S;
@@ -88,9 +90,10 @@ RpyPlan rpy_plan(int64_t S, int prec);
 // ev0/ev1 (may be null) are recorded on `st` just before and after the main pair kernel.
 // packed: the source records are already in the workspace (Y, F, T unused).
 // reduce: false leaves the K partials in the workspace (rpy_partials) for the caller.
+// active: optional device flag of the (single) suspension; when it is 0 the pair kernel exits at once.
 int rpy_launch(const RpyPlan& p, const double* Y, const double* F, const double* T, double a, double eta, double* V,
                double* W, void* work, hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
-               bool packed = false, bool reduce = true);
+               bool packed = false, bool reduce = true, const int32_t* active = nullptr);
 inline double* rpy_partials(const RpyPlan& p, void* work) {
     return reinterpret_cast<double*>(static_cast<char*>(work) + p.pack_bytes);
 }

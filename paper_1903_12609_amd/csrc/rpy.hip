@@ -133,6 +133,7 @@ struct RpyOut {
     double* part;
     double* V;
     double* W;
+    const int32_t* active;  // per-suspension flags (null: always compute); inactive ones are skipped
 };
 
 __device__ __forceinline__ void rpy_store(const RpyOut& o, int64_t base, int64_t S, int64_t Sg, int K, int k,
@@ -271,6 +272,7 @@ __global__ void __launch_bounds__(kRpyBlock) rpy_f64_kernel(int64_t S, int64_t c
                                                           const double* __restrict__ pk,
                                                           const double* __restrict__ Y, double a, double c,
                                                           RpyOut out) {
+    if (out.active && !out.active[0]) return;
     const int k = (int)(blockIdx.x % (unsigned)K);
     const int64_t tb = blockIdx.x / (unsigned)K;
     rpy_item_f64<TPL, WS>(0, S, S, tb, k, K, chunk, pk, Y, a, c, out);
@@ -285,6 +287,7 @@ __global__ void __launch_bounds__(kRpyBlock) rpy_f64_items_kernel(const RpyItem*
                                                                 RpyOut out) {
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const RpyItem w = items[it];
+        if (out.active && !out.active[w.susp]) continue;
         RpyOut o = out;
         o.part = out.part + w.part;
         rpy_item_f64<TPL, 1>(w.base, w.S, Sg, w.tb, w.k, w.K, w.chunk, pk, Y, a, c, o);
@@ -396,6 +399,7 @@ __global__ void __launch_bounds__(kRpyBlock) rpy_f32_kernel(int64_t S, int64_t c
                                                           const SrcF32* __restrict__ pk,
                                                           const double* __restrict__ Y, double a, double c,
                                                           RpyOut out) {
+    if (out.active && !out.active[0]) return;
     const int k = (int)(blockIdx.x % (unsigned)K);
     const int64_t tb = blockIdx.x / (unsigned)K;
     rpy_item_f32<TPL, WS>(0, S, S, tb, k, K, chunk, pk, Y, a, c, out);
@@ -408,6 +412,7 @@ __global__ void __launch_bounds__(kRpyBlock) rpy_f32_items_kernel(const RpyItem*
                                                                 RpyOut out) {
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         const RpyItem w = items[it];
+        if (out.active && !out.active[w.susp]) continue;
         RpyOut o = out;
         o.part = out.part + w.part;
         rpy_item_f32<TPL, 1>(w.base, w.S, Sg, w.tb, w.k, w.K, w.chunk, pk, Y, a, c, o);
@@ -439,10 +444,12 @@ __global__ void __launch_bounds__(256) rpy_reduce(int64_t S, int K, const double
 // sums the K_i partials of its suspension (suspensions with K_i = 1 wrote V, W).
 __global__ void __launch_bounds__(256) rpy_reduce_items(int64_t Sg, const int32_t* __restrict__ seg_susp,
                                                        const RpySusp* __restrict__ sus, const double* __restrict__ part,
-                                                       double* __restrict__ V, double* __restrict__ W) {
+                                                       double* __restrict__ V, double* __restrict__ W,
+                                                       const int32_t* __restrict__ active) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= 6 * Sg) return;
     const int64_t c = e / Sg, s = e - c * Sg;
+    if (active && !active[seg_susp[s]]) return;
     const RpySusp u = sus[seg_susp[s]];
     if (u.K <= 1) return;
     const int64_t n = s - u.base;
@@ -481,10 +488,11 @@ RpyPlan rpy_plan(int64_t S, int prec) {
 }
 
 int rpy_launch(const RpyPlan& p, const double* Y, const double* F, const double* T, double a, double eta, double* V,
-               double* W, void* work, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool packed, bool reduce) {
+               double* W, void* work, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool packed, bool reduce,
+               const int32_t* active) {
     if (p.S <= 0) return FIL_OK;
     char* base = static_cast<char*>(work);
-    RpyOut out{reinterpret_cast<double*>(base + p.pack_bytes), V, W};
+    RpyOut out{reinterpret_cast<double*>(base + p.pack_bytes), V, W, active};
     const double c = 1.0 / (8.0 * kPi * eta);
     const unsigned grid = (unsigned)(p.tb * p.K);
     const unsigned pgrid = (unsigned)ceil_div(p.S, 256);
@@ -537,7 +545,8 @@ RpyBatchPlan rpy_batch_plan(int64_t nsusp, const int64_t* susp_off, int prec) {
             }
             for (int64_t t = 0; t < tb; t++)
                 for (int64_t k = 0; k < K; k++) p.items.push_back(RpyItem{base, u.part, (int32_t)S, (int32_t)t,
-                                                                          (int32_t)k, (int32_t)K, chunk});
+                                                                          (int32_t)k, (int32_t)K, chunk,
+                                                                          (int32_t)i, 0});
         }
         p.sus[i] = u;
     }
@@ -573,10 +582,11 @@ int rpy_batch_upload(const RpyBatchPlan& p, void* work, hipStream_t st) {
 }
 
 int rpy_batch_launch(const RpyBatchPlan& p, const double* Y, const double* F, const double* T, double a, double eta,
-                     double* V, double* W, void* work, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool packed) {
+                     double* V, double* W, void* work, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool packed,
+                     const int32_t* active) {
     if (p.Sg <= 0) return FIL_OK;
     char* base = static_cast<char*>(work);
-    RpyOut out{reinterpret_cast<double*>(base + p.pack_bytes), V, W};
+    RpyOut out{reinterpret_cast<double*>(base + p.pack_bytes), V, W, active};
     const RpyItem* items = reinterpret_cast<const RpyItem*>(base + p.pack_bytes + p.part_bytes);
     const RpySusp* sus = reinterpret_cast<const RpySusp*>(base + p.pack_bytes + p.part_bytes + p.items_bytes);
     const int32_t* segs =
@@ -599,7 +609,7 @@ int rpy_batch_launch(const RpyBatchPlan& p, const double* Y, const double* F, co
         if (ev1) FIL_HIP_TRY(hipEventRecord(ev1, st));
     }
     if (p.any_reduce)
-        rpy_reduce_items<<<(unsigned)ceil_div(6 * p.Sg, 256), 256, 0, st>>>(p.Sg, segs, sus, out.part, V, W);
+        rpy_reduce_items<<<(unsigned)ceil_div(6 * p.Sg, 256), 256, 0, st>>>(p.Sg, segs, sus, out.part, V, W, active);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }

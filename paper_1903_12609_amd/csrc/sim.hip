@@ -6,10 +6,16 @@
 //   filament; X1 = X0 - J0^{-1} f0; then for k = 1, 2, ...: f_k = f(X_k)
 //   (one mobility apply), stop when max|f_k|/a <= tol, else the bad-Broyden
 //   update reusing H_{k-1} f_k for both c_k and the next step.
-// Convergence is tested on the host once per iteration (one small D2H copy).
+// Convergence is tested on the host once per iteration (one small D2H copy),
+// or, with graph execution on, on the device: blocks of U iterations (each an
+// evaluation, the convergence test and the Broyden update) are captured once
+// into a HIP graph and replayed, and the host reads the per-suspension state
+// once per block.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "common.h"
@@ -44,6 +50,18 @@ struct fil_sim {
     int cur = 0;  // plan of the next residual evaluation
     int rb = 0;   // which half of resbits_d the last residual evaluation wrote
     bool batched = false;
+    // device time t^{j+1} (read by the state kernel) and its pinned staging slot
+    double *time_d = nullptr, *time_h = nullptr;
+    // graph execution of the Broyden iterations
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        int rb_end = 0;
+    };
+    int graph_iters = 0;  // iterations per captured block; 0 runs every iteration from the host
+    hipStream_t cap_st = nullptr;  // private stream the blocks are captured on (launches go to st)
+    std::map<std::array<int, 5>, GraphEntry> graphs;
+    int32_t *jlog_d = nullptr, *jlog_h = nullptr;  // [nsusp][4] state, iters, applies, FP64 applies
+    double *jlast_d = nullptr, *jlast_h = nullptr;
     // learned warm start
     fil_mlp* mlp = nullptr;
     bool use_mlp = false;
@@ -134,41 +152,56 @@ int collect_timing(fil_sim* s) {
 void free_sim(fil_sim* s) {
     if (!s) return;
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    for (auto& kv : s->graphs)
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
     for (void* p : s->dev_allocs) (void)hipFree(p);
     for (void* p : s->host_allocs) (void)hipHostFree(p);
     delete s;
 }
 
-// f = f(X) for the active suspensions; resbits receives max|f| per suspension
-int eval_residual(fil_sim* s, const double* X, double* fout) {
-    const double tt = s->t + s->p.dt;
-    TRY(state_forces_launch(s->d, X, s->qj, tt, s->active_d, s->Yc, s->qc, s->F, s->T, s->box, s->st));
+// a pair of timing events from the pool (null when timing is off)
+int pool_events(fil_sim* s, hipEvent_t* e0, hipEvent_t* e1) {
+    *e0 = *e1 = nullptr;
+    if (!s->timing) return FIL_OK;
+    while ((int)s->ev.size() < 2 * (s->nev + 1)) {
+        hipEvent_t e;
+        FIL_HIP_TRY(hipEventCreate(&e));
+        s->ev.push_back(e);
+    }
+    *e0 = s->ev[2 * s->nev];
+    *e1 = s->ev[2 * s->nev + 1];
+    if ((int)s->ev_prec.size() <= s->nev) s->ev_prec.resize(s->nev + 1);
+    s->ev_prec[s->nev] = s->cur;
+    s->nev++;
+    return FIL_OK;
+}
+
+// the time t^{j+1} of the current step, on the device
+int set_time(fil_sim* s) {
+    FIL_HIP_TRY(hipStreamSynchronize(s->st));  // the staging slot may still feed an earlier copy
+    s->time_h[0] = s->t + s->p.dt;
+    FIL_HIP_TRY(hipMemcpyAsync(s->time_d, s->time_h, sizeof(double), hipMemcpyHostToDevice, s->st));
+    return FIL_OK;
+}
+
+// f = f(X) for the active suspensions; resbits receives max|f| per suspension.
+// e0/e1 (may be null) bracket the mobility pair kernel.
+int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipEvent_t e1) {
+    TRY(state_forces_launch(s->d, X, s->qj, s->time_d, s->active_d, s->Yc, s->qc, s->F, s->T, s->box, s->st));
     // the source records sit at the start of the mobility workspace in both plans
     const int c = s->cur;
     TRY(steric_pack_launch(s->d, s->Yc, s->box, s->active_d, s->F, s->T, c ? FIL_PREC_F32TILE : FIL_PREC_F64,
                            s->rpy_work[c], s->st));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (s->timing) {
-        while ((int)s->ev.size() < 2 * (s->nev + 1)) {
-            hipEvent_t e;
-            FIL_HIP_TRY(hipEventCreate(&e));
-            s->ev.push_back(e);
-        }
-        e0 = s->ev[2 * s->nev];
-        e1 = s->ev[2 * s->nev + 1];
-        if ((int)s->ev_prec.size() <= s->nev) s->ev_prec.resize(s->nev + 1);
-        s->ev_prec[s->nev] = c;
-        s->nev++;
-    }
     const double* part = nullptr;
     int K = 1;
     if (s->batched) {
         TRY(rpy_batch_launch(s->bplan[c], s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->rpy_work[c], s->st, e0, e1,
-                             true));
+                             true, s->active_d));
     } else {
         // the split-K partials are summed inside the residual kernel
         TRY(rpy_launch(s->rplan[c], s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->rpy_work[c], s->st, e0, e1,
-                       true, false));
+                       true, false, s->active_d));
         if (s->rplan[c].K > 1) {
             part = rpy_partials(s->rplan[c], s->rpy_work[c]);
             K = s->rplan[c].K;
@@ -217,6 +250,69 @@ int begin_solve(fil_sim* s, double* dXout) {
 }
 
 
+// Iterations it0 .. it0+U-1 (evaluation, device-side convergence test, bad-Broyden
+// update with k = it-1) as one HIP graph, captured on first use for this
+// (it0, U, precision, resbits parity, first-step coefficients) and replayed on
+// the simulation's stream.  The captured work holds no memset, no host copy and
+// no timing event (the mobility kernel is timed only in host-driven iterations).
+using GraphEntry = fil_sim::GraphEntry;
+int capture_block(fil_sim* s, int it0, int U, GraphEntry& g) {
+    const int64_t ns = s->nsusp;
+    const int rb0 = s->rb;
+    // captured on a private stream (the simulation's may be the null stream, which cannot be captured)
+    if (!s->cap_st) FIL_HIP_TRY(hipStreamCreateWithFlags(&s->cap_st, hipStreamNonBlocking));
+    hipStream_t run_st = s->st;
+    s->st = s->cap_st;
+    if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        s->st = run_st;
+        set_error("graph capture could not start");
+        return FIL_EHIP;
+    }
+    int rc = FIL_OK;
+    for (int i = 0; i < U && rc == FIL_OK; i++) {
+        const int it = it0 + i;
+        rc = eval_residual(s, s->X, s->f, nullptr, nullptr);
+        if (rc == FIL_OK)
+            rc = judge_launch(ns, it, s->p.tol, s->p.a, s->p.kmax, s->cur == 0, s->resbits_d + 2 * s->rb * ns,
+                              s->active_d, s->jlog_d, s->jlast_d, s->st);
+        if (rc == FIL_OK)
+            rc = broyden_update_launch(s->d, it - 1, s->AB, s->ipiv, s->AinvT, s->Chist, s->Dhist, s->f, s->fprev,
+                                       s->g0, s->h, s->part, s->X, nullptr, s->active_d, s->st);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s->st, &graph);
+    s->st = run_st;
+    g.rb_end = s->rb;
+    s->rb = rb0;
+    if (rc == FIL_OK && e != hipSuccess) {
+        set_error(std::string("graph capture: ") + hipGetErrorString(e));
+        rc = FIL_EHIP;
+    }
+    if (rc == FIL_OK && hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        set_error("graph instantiation failed");
+        rc = FIL_EHIP;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc != FIL_OK) {
+        (void)hipGetLastError();
+        g.exec = nullptr;
+    }
+    return rc;
+}
+
+int graph_block(fil_sim* s, int it0, int U) {
+    const std::array<int, 5> key{it0, U, s->cur, s->rb, s->step == 0 ? 1 : 0};
+    auto itg = s->graphs.find(key);
+    if (itg == s->graphs.end()) {
+        GraphEntry g;
+        TRY(capture_block(s, it0, U, g));
+        itg = s->graphs.emplace(key, std::move(g)).first;
+    }
+    FIL_HIP_TRY(hipGraphLaunch(itg->second.exec, s->st));
+    s->rb = itg->second.rb_end;
+    return FIL_OK;
+}
+
 struct SolveLog {
     std::vector<int32_t> state, iters, applies, applies_hi;  // state: 0 running, 1 converged, -1 failed
     std::vector<double> last;
@@ -262,8 +358,10 @@ int solve(fil_sim* s, SolveLog& L) {
         if (s->cur == 1 && any && (near || 2 * it >= s->p.kmax)) s->cur = 0;
         return any;
     };
+    hipEvent_t e0, e1;
     count();
-    TRY(eval_residual(s, s->X, s->f));
+    TRY(pool_events(s, &e0, &e1));
+    TRY(eval_residual(s, s->X, s->f, e0, e1));
     TRY(begin_solve(s, nullptr));
     TRY(read_resid(s, res, &vmx));
     FIL_HIP_TRY(hipMemcpyAsync(s->jflag_h, s->jflag_d, s->M * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
@@ -281,9 +379,48 @@ int solve(fil_sim* s, SolveLog& L) {
         }
     if (changed) TRY(upload_flags(s, s->active_d, s->active_h));
     if (any) TRY(first_step_launch(s->d, s->h, s->f, s->fprev, s->X, nullptr, s->active_d, s->st));
-    for (int it = 1; any; it++) {
+    // FP64 iterations run in captured graph blocks when enabled; FP32-tile
+    // iterations stay host-driven so the precision switch happens at the same
+    // iteration either way
+    for (int it = 1; any;) {
+        if (s->graph_iters > 0 && s->cur == 0) {
+            // device-side iterations: the log starts from the host's counts
+            for (int64_t i = 0; i < ns; i++) {
+                int32_t* g = s->jlog_h + 4 * i;
+                g[0] = L.state[i];
+                g[1] = L.iters[i];
+                g[2] = L.applies[i];
+                g[3] = L.applies_hi[i];
+                s->jlast_h[i] = L.last[i];
+            }
+            FIL_HIP_TRY(hipMemcpyAsync(s->jlog_d, s->jlog_h, 4 * ns * sizeof(int32_t), hipMemcpyHostToDevice, s->st));
+            FIL_HIP_TRY(hipMemcpyAsync(s->jlast_d, s->jlast_h, ns * sizeof(double), hipMemcpyHostToDevice, s->st));
+            while (any) {
+                const int U = std::min(s->graph_iters, s->p.kmax - it + 1);
+                TRY(graph_block(s, it, U));
+                // the rb parity a block ends on is part of its key, so it is tracked across blocks
+                FIL_HIP_TRY(hipMemcpyAsync(s->jlog_h, s->jlog_d, 4 * ns * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+                FIL_HIP_TRY(hipMemcpyAsync(s->jlast_h, s->jlast_d, ns * sizeof(double), hipMemcpyDeviceToHost, s->st));
+                FIL_HIP_TRY(hipStreamSynchronize(s->st));
+                any = false;
+                for (int64_t i = 0; i < ns; i++) {
+                    const int32_t* q = s->jlog_h + 4 * i;
+                    L.state[i] = q[0];
+                    L.iters[i] = q[1];
+                    L.applies[i] = q[2];
+                    L.applies_hi[i] = q[3];
+                    L.last[i] = s->jlast_h[i];
+                    s->active_h[i] = q[0] == 0;
+                    any |= q[0] == 0;
+                }
+                it += U;
+                s->k += U;
+            }
+            return FIL_OK;
+        }
         count();
-        TRY(eval_residual(s, s->X, s->f));
+        TRY(pool_events(s, &e0, &e1));
+        TRY(eval_residual(s, s->X, s->f, e0, e1));
         TRY(read_resid(s, res, &vmx));
         changed = false;
         any = judge(it);
@@ -292,6 +429,7 @@ int solve(fil_sim* s, SolveLog& L) {
         TRY(broyden_update_launch(s->d, s->k, s->AB, s->ipiv, s->AinvT, s->Chist, s->Dhist, s->f, s->fprev, s->g0,
                                   s->h, s->part, s->X, nullptr, s->active_d, s->st));
         s->k++;
+        it++;
     }
     return FIL_OK;
 }
@@ -418,12 +556,16 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     A(s->AB, n6 * kBandW) A(s->ipiv, n6)
     if (dense) { A(s->AinvT, dense_tot) A(d_dense_off, M) }
     A(s->Chist, (size_t)p->kmax * n6) A(s->Dhist, (size_t)p->kmax * n6) A(s->part, (size_t)nvblk * max_dots)
-    A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->active_d, nsusp) A(s->commit_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 4 * nsusp)
+    A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->time_d, 1) A(s->jlog_d, 4 * nsusp) A(s->jlast_d, nsusp)
+    A(s->active_d, nsusp) A(s->commit_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 4 * nsusp)
 #undef A
     if (rc == FIL_OK) rc = halloc(s, &s->active_h, nsusp);
     if (rc == FIL_OK) rc = halloc(s, &s->commit_h, nsusp);
     if (rc == FIL_OK) rc = halloc(s, &s->jflag_h, M);
     if (rc == FIL_OK) rc = halloc(s, &s->resbits_h, 2 * nsusp);
+    if (rc == FIL_OK) rc = halloc(s, &s->time_h, 1);
+    if (rc == FIL_OK) rc = halloc(s, &s->jlog_h, 4 * nsusp);
+    if (rc == FIL_OK) rc = halloc(s, &s->jlast_h, nsusp);
     if (rc) {
         free_sim(s);
         return rc;
@@ -576,6 +718,7 @@ int fil_bdf2_step(fil_sim* s, fil_step_report* report) {
     s->bc = coefs(s->step);
     s->nev = 0;
     for (int64_t i = 0; i < ns; i++) s->active_h[i] = 1;
+    TRY(set_time(s));
     TRY(upload_flags(s, s->active_d, s->active_h));
     TRY(initial_guess_launch(s->d, s->step, s->Yj, s->Yjm1, s->Xj, s->Xjm1, s->active_d, s->X, s->st));
     FIL_HIP_TRY(hipMemcpyAsync(s->X0p, s->X, 6 * s->S * sizeof(double), hipMemcpyDeviceToDevice, s->st));
@@ -628,6 +771,13 @@ int fil_bdf2_step(fil_sim* s, fil_step_report* report) {
     FIL_HIP_TRY(hipStreamSynchronize(s->st));
     s->t += s->p.dt;
     s->step += 1;
+    return FIL_OK;
+}
+
+int fil_set_graph(fil_sim* s, int iters_per_launch) {
+    FIL_CHECK_ARG(s, "fil_set_graph: null sim");
+    FIL_CHECK_ARG(iters_per_launch >= 0 && iters_per_launch <= 64, "fil_set_graph: iterations per launch in [0, 64]");
+    s->graph_iters = iters_per_launch;
     return FIL_OK;
 }
 
@@ -689,7 +839,10 @@ int fil_residual(fil_sim* s, const double* X, double* f_out) {
     s->bc = coefs(s->step);
     for (int64_t i = 0; i < s->nsusp; i++) s->active_h[i] = 1;
     TRY(upload_flags(s, s->active_d, s->active_h));
-    return eval_residual(s, X, f_out);
+    TRY(set_time(s));
+    hipEvent_t e0, e1;
+    TRY(pool_events(s, &e0, &e1));
+    return eval_residual(s, X, f_out, e0, e1);
 }
 
 int fil_broyden_begin(fil_sim* s, const double* X0, double* f0_out) {
@@ -698,7 +851,10 @@ int fil_broyden_begin(fil_sim* s, const double* X0, double* f0_out) {
     for (int64_t i = 0; i < s->nsusp; i++) s->active_h[i] = 1;
     TRY(upload_flags(s, s->active_d, s->active_h));
     FIL_HIP_TRY(hipMemcpyAsync(s->X, X0, 6 * s->S * sizeof(double), hipMemcpyDeviceToDevice, s->st));
-    TRY(eval_residual(s, s->X, s->f));
+    TRY(set_time(s));
+    hipEvent_t e0, e1;
+    TRY(pool_events(s, &e0, &e1));
+    TRY(eval_residual(s, s->X, s->f, e0, e1));
     TRY(begin_solve(s, nullptr));
     if (f0_out) FIL_HIP_TRY(hipMemcpyAsync(f0_out, s->f, 6 * s->S * sizeof(double), hipMemcpyDeviceToDevice, s->st));
     TRY(first_step_launch(s->d, s->h, s->f, s->fprev, s->X, nullptr, s->active_d, s->st));

@@ -44,7 +44,8 @@ struct SimDev {
 };
 
 // configuration from X, internal forces (F = F^C + gravity, T = T^C + T^E) and filament boxes
-int state_forces_launch(const SimDev& d, const double* X, const double* qj, double tt, const int32_t* active,
+// tt: device pointer to the time t^{j+1} of the step
+int state_forces_launch(const SimDev& d, const double* X, const double* qj, const double* tt, const int32_t* active,
                         double* Yc, double* qc, double* F, double* T, double* box, hipStream_t st);
 // adds the steric barrier into F and writes the mobility source records (precision prec)
 int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, const int32_t* active, double* F,
@@ -72,6 +73,10 @@ int broyden_update_launch(const SimDev& d, int k, const double* AB, const int32_
                           double* part, double* X, double* dXout, const int32_t* active, hipStream_t st);
 int first_step_launch(const SimDev& d, const double* h, const double* f, double* fprev, double* X, double* dXout,
                       const int32_t* active, hipStream_t st);
+// convergence test of evaluation `it` on the device; log[4i..4i+3] = state (0 running, 1 converged,
+// -1 failed), last iteration, evaluations, FP64 evaluations; last[i] = max|f|/a
+int judge_launch(int64_t ns, int it, double tol, double a, int kmax, int can_converge,
+                 const unsigned long long* resbits, int32_t* active, int32_t* log, double* last, hipStream_t st);
 // commits the step: Y, q from the converged state; X history shifted (Xjm2 may be null)
 int finalize_launch(const SimDev& d, const int32_t* commit, const double* Yc, const double* qc, const double* X,
                     double* Yj, double* Yjm1, double* qj, double* Xj, double* Xjm1, double* Xjm2, hipStream_t st);

@@ -50,11 +50,12 @@ __device__ __forceinline__ V3 joint_kappa(const SimDev& d, int64_t f, int64_t k,
 // One 64-lane workgroup per filament: q_n = exp(u_n) . q^j_n, t_n, robot-arm
 // positions, then F = F^C + gravity (+ lambda_1), T = T^C + T^E (+ lambda_2).
 __global__ void __launch_bounds__(64) state_forces_kernel(SimDev d, const double* __restrict__ X,
-                                                        const double* __restrict__ qj, double tt,
+                                                        const double* __restrict__ qj, const double* __restrict__ ttp,
                                                         const int32_t* __restrict__ active,
                                                         double* __restrict__ Yc, double* __restrict__ qc,
                                                         double* __restrict__ F, double* __restrict__ T,
                                                         double* __restrict__ box) {
+    const double tt = *ttp;  // t^{j+1}, read on the device so captured launches stay valid
     const int64_t f = blockIdx.x;
     if (!active[d.fil_susp[f]]) return;
     const int64_t S = d.S;
@@ -113,7 +114,7 @@ __global__ void __launch_bounds__(64) state_forces_kernel(SimDev d, const double
     }
 }
 
-int state_forces_launch(const SimDev& d, const double* X, const double* qj, double tt, const int32_t* active,
+int state_forces_launch(const SimDev& d, const double* X, const double* qj, const double* tt, const int32_t* active,
                         double* Yc, double* qc, double* F, double* T, double* box, hipStream_t st) {
     if (d.M == 0) return FIL_OK;
     state_forces_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, X, qj, tt, active, Yc, qc, F, T, box);
@@ -970,6 +971,42 @@ int first_step_launch(const SimDev& d, const double* h, const double* f, double*
                       const int32_t* active, hipStream_t st) {
     if (d.S == 0) return FIL_OK;
     first_step_kernel<<<(unsigned)d.nvblk, 256, 0, st>>>(d, h, f, fprev, X, dXout, active);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+// ---------------------------------------------------------------- device-side convergence test
+// Test of evaluation `it` for iterations that run without the host (captured
+// in a graph): max|f|/a of each active suspension (from the residual kernel's
+// bit pattern) ends it when <= tol (if this evaluation may end a step), fails
+// it when non-finite or at it >= kmax; counts the evaluation.
+__global__ void __launch_bounds__(256) judge_kernel(int64_t ns, int it, double tol, double inv_a, int kmax,
+                                                    int can_converge, const unsigned long long* __restrict__ resbits,
+                                                    int32_t* __restrict__ active, int32_t* __restrict__ log,
+                                                    double* __restrict__ last) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!active[i]) continue;
+        const double r = __longlong_as_double((long long)resbits[i]) * inv_a;
+        int32_t* L = log + 4 * i;  // state, iters, applies, FP64 applies
+        L[1] = it;
+        L[2] += 1;
+        L[3] += can_converge;
+        last[i] = r;
+        int32_t st = 0;
+        if (!(r <= 1.7976931348623157e308)) st = -1;  // NaN or infinite
+        else if (r <= tol && can_converge) st = 1;
+        else if (it >= kmax) st = -1;
+        if (st) {
+            L[0] = st;
+            active[i] = 0;
+        }
+    }
+}
+
+int judge_launch(int64_t ns, int it, double tol, double a, int kmax, int can_converge,
+                 const unsigned long long* resbits, int32_t* active, int32_t* log, double* last, hipStream_t st) {
+    judge_kernel<<<(unsigned)ceil_div(ns, 256), 256, 0, st>>>(ns, it, tol, 1.0 / a, kmax, can_converge, resbits,
+                                                             active, log, last);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }
