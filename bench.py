@@ -3,17 +3,22 @@
 Workload: the sedimenting suspension of 100 filaments x 20 segments (2,000
 segments), every segment under gravity, steric barrier on, RPY hydrodynamics,
 BDF2 steps solved by bad Broyden with the explicit block-diagonal J0 to a
-1e-6 residual.  One "step" is one full implicit time step (warm start, J0 and
-its inverse, every Broyden iteration with its mobility apply, finalisation).
+1e-6 residual (max|f|/a).  One "step" is one full implicit time step (warm
+start, J0 and its inverse, every Broyden iteration with its mobility apply,
+finalisation); the FP64 iterations run in captured HIP-graph blocks.
 
 Prints one JSON line: value = RPY pair-interactions per second of whole-step
-wall time (mobility applies x S^2 / elapsed), ms_per_step, the roofline of the
-mobility pair kernel (its duration measured with HIP events on the stream it
-runs on, inside the timed steps) and the CPU oracle's rate on a bounded sample.
+wall time (mobility applies x S^2 / elapsed), ms_per_step, the roofline of
+the mobility pair kernel (its duration measured with HIP events on the stream
+it runs on, inside the timed steps), the same steps with FP32 pair tiles, the
+stand-alone mobility apply at the workload sizes (FP64 and FP32 tiles, and the
+ragged 256-suspension batch), the learned warm start against plain Broyden on
+the 500 x 32 suspension, and the CPU oracle's rate on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,14 +31,31 @@ FLOP_PER_PAIR = 85          # algorithmic flops of one ordered (target, source) 
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (packed)
 PEAK_HBM_GBS = 8000.0
+GRAPH_ITERS = 4             # Broyden iterations per captured graph block
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rpy_f64_sediment2000_traffic.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _time_applies(fn, reps):
+    import torch
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
 def rpy_sweep(sizes=(2000, 16000, 32000), reps=10):
-    """Stand-alone mobility applies (pairs/s) at the paper-workload sizes."""
+    """Stand-alone mobility applies (pairs/s) at the workload sizes."""
     import torch
     import paper_1903_12609_amd as fil
     from paper_1903_12609_amd import synth
@@ -45,17 +67,7 @@ def rpy_sweep(sizes=(2000, 16000, 32000), reps=10):
         for prec in ("f64", "f32tile"):
             V, W = torch.empty_like(Yd), torch.empty_like(Yd)
             work = torch.empty(fil.rpy_workspace_bytes(S, prec), dtype=torch.uint8, device="cuda")
-            for _ in range(3):
-                fil.rpy_mobility_apply(Yd, Fd, Td, 1.0, 1.0, prec, V, W, work)
-            st = torch.cuda.current_stream()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            e0.record(st)
-            for _ in range(reps):
-                fil.rpy_mobility_apply(Yd, Fd, Td, 1.0, 1.0, prec, V, W, work)
-            e1.record(st)
-            torch.cuda.synchronize()
-            t = e0.elapsed_time(e1) * 1e-3 / reps
+            t = _time_applies(lambda: fil.rpy_mobility_apply(Yd, Fd, Td, 1.0, 1.0, prec, V, W, work), reps)
             pairs = float(S) * S
             peak = PEAK_FP64_TFLOPS if prec == "f64" else PEAK_FP32_TFLOPS
             out.append(dict(S=S, prec=prec, ms=round(t * 1e3, 4), pairs_per_s=pairs / t,
@@ -65,19 +77,106 @@ def rpy_sweep(sizes=(2000, 16000, 32000), reps=10):
     return out
 
 
-def cpu_baseline(w, steps=2):
-    """The FP64 oracle on the host cores, on a bounded sample of the same workload."""
+def rpy_batched(reps=5):
+    """One apply over the 256 ragged suspensions (filaments U{1..64} x N U{10..50})."""
+    import numpy as np
+    import torch
+    import paper_1903_12609_amd as fil
+    rng = np.random.default_rng(1004)
+    sizes = [int(rng.integers(1, 65)) * int(rng.integers(10, 51)) for _ in range(256)]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    S = int(off[-1])
+    Y = np.concatenate([rng.uniform(0, 200.0 * (n / 2000.0) ** (1 / 3), (n, 3)) for n in sizes])
+    F, T = rng.standard_normal((S, 3)), rng.standard_normal((S, 3))
+    d = lambda a: torch.from_numpy(a.T.copy()).cuda()
+    Yd, Fd, Td = d(Y), d(F), d(T)
+    out = []
+    pairs = float(sum(n * n for n in sizes))
+    for prec in ("f64", "f32tile"):
+        V, W = torch.empty_like(Yd), torch.empty_like(Yd)
+        t = _time_applies(lambda: fil.rpy_mobility_apply_batched(off, Yd, Fd, Td, 1.0, 1.0, prec, V, W), reps)
+        peak = PEAK_FP64_TFLOPS if prec == "f64" else PEAK_FP32_TFLOPS
+        out.append(dict(suspensions=256, segments=S, pairs=pairs, prec=prec, ms=round(t * 1e3, 4),
+                        pairs_per_s=pairs / t, tflops=FLOP_PER_PAIR * pairs / t / 1e12,
+                        frac_of_peak=FLOP_PER_PAIR * pairs / t / 1e12 / peak))
+        log("rpy batched apply", out[-1])
+    return out
+
+
+def run_steps(w, prec, steps, warmup, graph):
+    """Timed implicit steps; returns (elapsed s, applies, iters, kernel timing)."""
+    import torch
+    import paper_1903_12609_amd as fil
+    sim = fil.Sim(w.fil_off, w.Y, w.q, w.params, prec=prec, graph=graph)
+    for _ in range(warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    sim.set_timing(True)
+    applies, iters = 0, 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = sim.step()[0]
+        applies += r["applies"]
+        iters += r["iters"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tm = sim.timing()
+    sim.close()
+    return el, applies, iters, tm
+
+
+def learned_gain(log_fn):
+    """Learned warm start vs plain Broyden on the 500 x 32 sedimenting suspension
+    (network trained here, on the GPU, from single-filament runs)."""
+    import torch
+    import paper_1903_12609_amd as fil
+    from paper_1903_12609_amd import learned, synth
+    t0 = time.perf_counter()
+    feat, targ = learned.generate(n_fil=500, N=32, steps=100, source="single")
+    t1 = time.perf_counter()
+    m = fil.MLP(32, width=256, depth=3, max_batch=1024, seed=0)
+    hist = learned.train(m, feat, targ, epochs=60, batch=1024, lr=1e-3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    w = synth.sediment_suspension(M=500, N=32, side=400.0, seed=1005, dt_over_T=1 / 30)
+    res = learned.compare(w, m, steps=20, skip=5, log=log_fn)
+    res.update(train_samples=int(feat.shape[0]), data_s=t1 - t0, train_s=t2 - t1,
+               final_validation_loss=hist[-1][1], network="608-256-256-256-192 SiLU, BF16 MFMA",
+               workload="sedimenting suspension 500 x 32 (S=16000), dt=T/30, tol 1e-6")
+    m.close()
+    return res
+
+
+def traffic_per_launch():
+    """HBM bytes per launch of the FP64 pair kernel from the committed rocprofv3
+    counter summary, or None when the kernel source changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+        with open(os.path.join(ROOT, "paper_1903_12609_amd", "csrc", "rpy.hip"), "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+        if t.get("rpy_hip_sha256") != sha:
+            return None
+        return float(t["bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def cpu_baseline(w, budget_s=12.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the same workload
+    (whole steps until about budget_s seconds have passed)."""
     import oracle
     nthreads = len(os.sched_getaffinity(0))
     sim = oracle.Sim(w.fil_off, w.Y, w.q, nthreads=nthreads, **w.params)
-    applies = 0
+    applies, steps = 0, 0
     t0 = time.perf_counter()
-    for _ in range(steps):
+    while steps < 2 or time.perf_counter() - t0 < budget_s:
         rc, rep = sim.step()
         applies += rep.applies
+        steps += 1
     dt = time.perf_counter() - t0
     return dict(value=applies * float(w.S) ** 2 / dt, unit="pairs/s", cores=nthreads, kind="oracle",
-                sample="%d implicit steps (%d mobility applies) of the %d-segment suspension, %.1f s" %
+                sample="first %d implicit steps (%d mobility applies) of the %d-segment suspension, %.1f s" %
                        (steps, applies, w.S, dt), ms_per_step=dt / steps * 1e3)
 
 
@@ -86,40 +185,29 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", default="f64", choices=["f64", "f32tile"])
+    ap.add_argument("--graph", type=int, default=GRAPH_ITERS, help="Broyden iterations per graph block (0: off)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only; multi-GPU runs are not part of this build", file=sys.stderr)
+        print("bench.py measures one GPU: runs on several GPUs are not part of this implementation",
+              file=sys.stderr)
         sys.exit(2)
-    import torch
-    import paper_1903_12609_amd as fil
+    import paper_1903_12609_amd as fil  # noqa: F401  (fails loudly without the HIP library)
     from paper_1903_12609_amd import synth
 
     w = synth.sediment_suspension(M=100, N=20, side=200.0, seed=1002, dt_over_T=1 / 30)
     S = w.S
-    sim = fil.Sim(w.fil_off, w.Y, w.q, w.params, prec=args.prec)
-    for _ in range(args.warmup):
-        sim.step()
-    torch.cuda.synchronize()
-    sim.set_timing(True)
-    applies, iters = 0, 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r = sim.step()[0]
-        applies += r["applies"]
-        iters += r["iters"]
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    rpy_ms, nl = sim.timing()[args.prec]
-    pairs = applies * float(S) ** 2
+    el, applies, iters, tm = run_steps(w, "f64", args.steps, args.warmup, args.graph)
+    rpy_ms, nl = tm["f64"]
     kern_s = rpy_ms * 1e-3 / max(nl, 1)
-    peak = PEAK_FP64_TFLOPS if args.prec == "f64" else PEAK_FP32_TFLOPS
-    achieved = FLOP_PER_PAIR * float(S) ** 2 / kern_s / 1e12
+    flop = FLOP_PER_PAIR * float(S) ** 2
+    achieved = flop / kern_s / 1e12
+    traffic = traffic_per_launch()
     res = {
         "metric": "RPY pair-interactions/s (fp64 vs fp32) + ms/step to tol, plain vs learned",
-        "value": pairs / el,
+        "value": applies * float(S) ** 2 / el,
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -128,20 +216,28 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "f64" else "f32+f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "sedimenting suspension, 100 filaments x 20 segments (S=2000), B=1e3, "
                                "dt=T/30, tol 1e-6, steric on, unbounded RPY", "segments": S,
-                   "precision": args.prec},
+                   "precision": "f64", "graph_iters": args.graph},
         "iters_per_step": iters / args.steps,
         "mobility_applies_per_step": applies / args.steps,
-        "roofline": {"bound": "alu", "kernel": "rpy_%s_kernel" % ("f64" if args.prec == "f64" else "f32"),
-                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "avg_kernel_us": kern_s * 1e6, "launches": nl,
-                     "flop_per_launch": FLOP_PER_PAIR * float(S) ** 2},
+        "roofline": {"bound": "alu", "kernel": "rpy_f64_kernel", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "avg_kernel_us": kern_s * 1e6, "launches": nl, "flop_per_launch": flop},
     }
+    el32, ap32, it32, tm32 = run_steps(w, "f32tile", args.steps, args.warmup, args.graph)
+    ms32, n32 = tm32["f32tile"]
+    res["f32tile_steps"] = {"value": ap32 * float(S) ** 2 / el32, "ms_per_step": el32 / args.steps * 1e3,
+                            "iters_per_step": it32 / args.steps, "mobility_applies_per_step": ap32 / args.steps,
+                            "f32_kernel_avg_us": ms32 * 1e3 / max(n32, 1)}
+    log("f32tile steps", res["f32tile_steps"])
     if not args.no_sweep:
         res["rpy_apply"] = rpy_sweep()
+        res["rpy_apply_batched"] = rpy_batched()
+    if not args.no_learned:
+        res["learned_warm_start"] = learned_gain(log)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res))
