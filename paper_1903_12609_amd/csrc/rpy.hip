@@ -233,13 +233,15 @@ __device__ __forceinline__ void rpy_item_f64(int64_t base, int64_t S, int64_t Sg
     } else {
         // the next source record is requested before the current one is used, so
         // the scalar-load latency overlaps the pair arithmetic
-        const double* src = pk + 16 * base;
+        // (32-bit, wave-uniform loop arithmetic stays on the scalar unit)
+        const double* src = pk + 16 * (base + m0);
+        const int cnt = (int)(m1 - m0);
         double cur[15];
-        if (m0 < m1) {
-            for (int i = 0; i < 15; i++) cur[i] = src[16 * m0 + i];
+        if (cnt > 0) {
+            for (int i = 0; i < 15; i++) cur[i] = src[i];
         }
-        for (int64_t m = m0; m < m1; ++m) {
-            const int64_t mn = m + 1 < m1 ? m + 1 : m;
+        for (int m = 0; m < cnt; ++m) {
+            const int mn = m + 1 < cnt ? m + 1 : m;
             double nxt[15];
             for (int i = 0; i < 15; i++) nxt[i] = src[16 * mn + i];
 #pragma unroll
@@ -295,30 +297,47 @@ __global__ void __launch_bounds__(kRpyBlock) rpy_f64_items_kernel(const RpyItem*
 }
 
 // ------------------------------------------------------------------ FP32-tile pair
-// Accumulates (V, Omega) / c of one pair in float.
-__device__ __forceinline__ void rpy_pair_f32(const double y[3], const SrcF32* __restrict__ s, float a, float four_a2,
+// Accumulates (V, Omega) / c of one pair in float.  With q = s^3 r:
+//   v += (s + 2a^2/3 s^3) F + (1 - 2a^2 s^2)(r.F) q + T x q
+//   w += -1/2 s^3 T + 3/2 s^2 (r.T) q + F x q
+// (53 VALU operations per pair).
+struct SrcRegF32 {
+    double y[3];
+    float f[3], t[3];
+};
+__device__ __forceinline__ SrcRegF32 load_src_f32(const SrcF32* __restrict__ s) {
+    SrcRegF32 r;
+    for (int i = 0; i < 3; i++) {
+        r.y[i] = s->y[i];
+        r.f[i] = s->f[i];
+        r.t[i] = s->t[i];
+    }
+    return r;
+}
+__device__ __forceinline__ void rpy_pair_f32(const double y[3], const SrcRegF32& s, float a, float four_a2,
                                              float two_a2, float c23, float v[3], float w[3]) {
-    const float rx = (float)(y[0] - s->y[0]);
-    const float ry = (float)(y[1] - s->y[1]);
-    const float rz = (float)(y[2] - s->y[2]);
+    const float rx = (float)(y[0] - s.y[0]);
+    const float ry = (float)(y[1] - s.y[1]);
+    const float rz = (float)(y[2] - s.y[2]);
     const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
     const bool near = r2 < four_a2;
     float sv = __builtin_amdgcn_rsqf(r2);
     sv = near ? 0.f : sv;
     const float s2 = sv * sv, s3 = s2 * sv;
-    const float Fx = s->f[0], Fy = s->f[1], Fz = s->f[2], Tx = s->t[0], Ty = s->t[1], Tz = s->t[2];
+    const float qx = s3 * rx, qy = s3 * ry, qz = s3 * rz;
+    const float Fx = s.f[0], Fy = s.f[1], Fz = s.f[2], Tx = s.t[0], Ty = s.t[1], Tz = s.t[2];
     const float rF = fmaf(rx, Fx, fmaf(ry, Fy, rz * Fz));
     const float rT = fmaf(rx, Tx, fmaf(ry, Ty, rz * Tz));
     const float A = fmaf(c23, s3, sv);                 // s + 2a^2/3 s^3
-    const float Br = s3 * fmaf(-two_a2, s2, 1.f) * rF;  // s^3 (1 - 2a^2 s^2) (r.F)
-    const float D = 1.5f * s3 * s2 * rT;               // 3/2 s^5 (r.T)
+    const float B = fmaf(-two_a2, s2, 1.f) * rF;       // (1 - 2a^2 s^2) (r.F)
+    const float D = (1.5f * s2) * rT;                  // 3/2 s^2 (r.T)
     const float E = -0.5f * s3;
-    v[0] = fmaf(A, Fx, fmaf(Br, rx, fmaf(s3, fmaf(Ty, rz, -Tz * ry), v[0])));
-    v[1] = fmaf(A, Fy, fmaf(Br, ry, fmaf(s3, fmaf(Tz, rx, -Tx * rz), v[1])));
-    v[2] = fmaf(A, Fz, fmaf(Br, rz, fmaf(s3, fmaf(Tx, ry, -Ty * rx), v[2])));
-    w[0] = fmaf(E, Tx, fmaf(D, rx, fmaf(s3, fmaf(Fy, rz, -Fz * ry), w[0])));
-    w[1] = fmaf(E, Ty, fmaf(D, ry, fmaf(s3, fmaf(Fz, rx, -Fx * rz), w[1])));
-    w[2] = fmaf(E, Tz, fmaf(D, rz, fmaf(s3, fmaf(Fx, ry, -Fy * rx), w[2])));
+    v[0] = fmaf(A, Fx, fmaf(B, qx, fmaf(Ty, qz, fmaf(-Tz, qy, v[0]))));
+    v[1] = fmaf(A, Fy, fmaf(B, qy, fmaf(Tz, qx, fmaf(-Tx, qz, v[1]))));
+    v[2] = fmaf(A, Fz, fmaf(B, qz, fmaf(Tx, qy, fmaf(-Ty, qx, v[2]))));
+    w[0] = fmaf(E, Tx, fmaf(D, qx, fmaf(Fy, qz, fmaf(-Fz, qy, w[0]))));
+    w[1] = fmaf(E, Ty, fmaf(D, qy, fmaf(Fz, qx, fmaf(-Fx, qz, w[1]))));
+    w[2] = fmaf(E, Tz, fmaf(D, qz, fmaf(Fx, qy, fmaf(-Fy, qx, w[2]))));
     if (near) {
         const Ovl<float> o = rpy_overlap<float>(rx, ry, rz, r2, Fx, Fy, Fz, Tx, Ty, Tz, a);
         for (int i = 0; i < 3; i++) {
@@ -372,10 +391,16 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
 #pragma unroll
         for (int j = 0; j < TPL; j++)
             for (int i = 0; i < 3; i++) v[j][i] = w[j][i] = 0.f;
-        for (int64_t m = t0; m < t1; ++m) {
-            const SrcF32* s = src + m;
+        // the next record is requested before the current one is used (latency overlap);
+        // 32-bit, wave-uniform loop arithmetic stays on the scalar unit
+        const SrcF32* ts = src + t0;
+        const int cnt = (int)(t1 - t0);
+        SrcRegF32 cur = load_src_f32(ts);
+        for (int i = 0; i < cnt; ++i) {
+            const SrcRegF32 nxt = load_src_f32(ts + (i + 1 < cnt ? i + 1 : i));
 #pragma unroll
-            for (int j = 0; j < TPL; j++) rpy_pair_f32(y[j], s, af, four_a2, two_a2, c23, v[j], w[j]);
+            for (int j = 0; j < TPL; j++) rpy_pair_f32(y[j], cur, af, four_a2, two_a2, c23, v[j], w[j]);
+            cur = nxt;
         }
 #pragma unroll
         for (int j = 0; j < TPL; j++)
