@@ -99,6 +99,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libfil.so is not built (run `python -m paper_1903_12609_amd.build`); "
                                "there is no fallback path")
+        # torch carries its own HIP runtime; it must bring the device up before
+        # the library's runtime makes its first call, or torch no longer finds it
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         _lib = C.CDLL(LIB_PATH)
         _declare(_lib)
     return _lib

@@ -498,10 +498,10 @@ RpyPlan rpy_plan(int64_t S, int prec) {
     p.ws = small ? 4 : 1;
     if (S <= 0) return p;
     p.tb = ceil_div(S, (int64_t)(kRpyBlock / p.ws) * p.tpl);
-    // aim for ~2048 workgroups (8 per CU); every wave gets >= 32 (small) or 64 sources;
+    // aim for ~2048 workgroups (8 per CU); every wave gets >= 16 (small) or 64 sources;
     // on the small path a block's chunk must fit the LDS staging buffer
     int64_t K = ceil_div(2048, p.tb);
-    K = std::min<int64_t>(K, std::max<int64_t>(1, S / (small ? 32 * p.ws : 64)));
+    K = std::min<int64_t>(K, std::max<int64_t>(1, S / (small ? 16 * p.ws : 64)));
     if (small) K = std::max<int64_t>(K, ceil_div(S, kLdsSources));
     if (K >= 8) K = ceil_div(K, 8) * 8;
     p.chunk = ceil_div(S, K);

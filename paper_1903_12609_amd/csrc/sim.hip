@@ -61,6 +61,7 @@ struct fil_sim {
     hipStream_t cap_st = nullptr;  // private stream the blocks are captured on (launches go to st)
     std::map<std::array<int, 5>, GraphEntry> graphs;
     int32_t *jlog_d = nullptr, *jlog_h = nullptr;  // [nsusp][4] state, iters, applies, FP64 applies
+    unsigned int* ticket_d = nullptr;              // last-workgroup counter of the fused convergence test
     double *jlast_d = nullptr, *jlast_h = nullptr;
     // learned warm start
     fil_mlp* mlp = nullptr;
@@ -187,7 +188,8 @@ int set_time(fil_sim* s) {
 
 // f = f(X) for the active suspensions; resbits receives max|f| per suspension.
 // e0/e1 (may be null) bracket the mobility pair kernel.
-int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipEvent_t e1) {
+int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipEvent_t e1,
+                  const JudgeArgs* judge = nullptr) {
     TRY(state_forces_launch(s->d, X, s->qj, s->time_d, s->active_d, s->Yc, s->qc, s->F, s->T, s->box, s->st));
     // the source records sit at the start of the mobility workspace in both plans
     const int c = s->cur;
@@ -209,7 +211,8 @@ int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipE
     }
     s->rb ^= 1;
     TRY(residual_launch(s->d, s->bc, X, s->Xj, s->Yc, s->Yj, s->Yjm1, s->V, s->W, part, K, s->active_d, fout,
-                        s->resbits_d + 2 * s->rb * s->nsusp, s->resbits_d + 2 * (1 - s->rb) * s->nsusp, s->st));
+                        s->resbits_d + 2 * s->rb * s->nsusp, s->resbits_d + 2 * (1 - s->rb) * s->nsusp, s->st,
+                        judge));
     return FIL_OK;
 }
 
@@ -271,10 +274,9 @@ int capture_block(fil_sim* s, int it0, int U, GraphEntry& g) {
     int rc = FIL_OK;
     for (int i = 0; i < U && rc == FIL_OK; i++) {
         const int it = it0 + i;
-        rc = eval_residual(s, s->X, s->f, nullptr, nullptr);
-        if (rc == FIL_OK)
-            rc = judge_launch(ns, it, s->p.tol, s->p.a, s->p.kmax, s->cur == 0, s->resbits_d + 2 * s->rb * ns,
-                              s->active_d, s->jlog_d, s->jlast_d, s->st);
+        JudgeArgs jg{s->ticket_d, s->active_d, s->jlog_d, s->jlast_d, s->p.tol, 1.0 / s->p.a, it, s->p.kmax,
+                     s->cur == 0 ? 1 : 0};
+        rc = eval_residual(s, s->X, s->f, nullptr, nullptr, &jg);
         if (rc == FIL_OK)
             rc = broyden_update_launch(s->d, it - 1, s->AB, s->ipiv, s->AinvT, s->Chist, s->Dhist, s->f, s->fprev,
                                        s->g0, s->h, s->part, s->X, nullptr, s->active_d, s->st);
@@ -557,6 +559,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     if (dense) { A(s->AinvT, dense_tot) A(d_dense_off, M) }
     A(s->Chist, (size_t)p->kmax * n6) A(s->Dhist, (size_t)p->kmax * n6) A(s->part, (size_t)nvblk * max_dots)
     A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->time_d, 1) A(s->jlog_d, 4 * nsusp) A(s->jlast_d, nsusp)
+    A(s->ticket_d, 1)
     A(s->active_d, nsusp) A(s->commit_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 4 * nsusp)
 #undef A
     if (rc == FIL_OK) rc = halloc(s, &s->active_h, nsusp);
@@ -625,6 +628,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         TRY(upload(s->Xj, zeros));
         TRY(upload(s->Xjm1, zeros));
         TRY(upload(s->Xjm2, zeros));
+        TRY(upload(s->ticket_d, std::vector<unsigned int>(1, 0u)));
         TRY(upload(s->X0p, zeros));
         TRY(upload(s->X, zeros));
         TRY(upload(s->resbits_d, std::vector<unsigned long long>(4 * nsusp, 0ull)));

@@ -12,8 +12,10 @@ constexpr int kInvWaves = 8;      // column solves per workgroup when building t
 constexpr size_t kDenseInvBytes = size_t(64) << 20;  // explicit J0^{-1} used up to this total size
 constexpr int kMaxIter = 256;     // Broyden history capacity
 constexpr int kMaxDots = kMaxIter + 2;
-constexpr int kVecBlock = 1024;   // residual-vector elements per Broyden vector block
-constexpr int kSpar = 5;          // per-suspension parameters: dt, gravity force (3), F^S
+constexpr int kVecBlock = 256;    // residual-vector elements per Broyden vector block
+constexpr int kSpar = 5;
+constexpr int kResSeg = 64;
+constexpr int kStericWaves = 4;   // waves per filament in the steric pass       // segments per residual workgroup (six waves sum the partials)          // per-suspension parameters: dt, gravity force (3), F^S
 
 // BDF coefficients: y - a1 y^j - a2 y^{j-1} - b dt v = 0, u - g u^j - b dt dexpinv(Omega) = 0
 struct BdfCoef {
@@ -50,13 +52,24 @@ int state_forces_launch(const SimDev& d, const double* X, const double* qj, cons
 // adds the steric barrier into F and writes the mobility source records (precision prec)
 int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, const int32_t* active, double* F,
                        const double* T, int prec, void* pk, hipStream_t st);
+// device-side convergence test fused into the residual kernel (graph-captured iterations)
+struct JudgeArgs {
+    unsigned int* ticket;  // zero-initialised counter; null: no test
+    int32_t* active;       // per suspension, cleared when it ends
+    int32_t* log;          // [nsusp][4] state (0 running, 1 converged, -1 failed), last iteration, evaluations,
+                           // FP64 evaluations
+    double* last;          // [nsusp] max|f|/a of the last evaluation
+    double tol, inv_a;
+    int it, kmax, can_converge;
+};
+
 // residual rows; max|f| per suspension into resbits[0, nsusp) and max|b dt (V, dexpinv Omega)| into
 // resbits[nsusp, 2 nsusp) (zeroed by the previous call, which also zeroes resbits_next);
 // velocities from the K mobility partials `part` when non-null (then also stored to V, W), else from V, W
 int residual_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* Xj, const double* Yc,
                     const double* Yj, const double* Yjm1, double* V, double* W, const double* part, int K,
                     const int32_t* active, double* f, unsigned long long* resbits, unsigned long long* resbits_next,
-                    hipStream_t st);
+                    hipStream_t st, const JudgeArgs* judge = nullptr);
 int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const double* Yjm1, const double* Xj,
                          const double* Xjm1, const int32_t* active, double* X0, hipStream_t st);
 // J0 at X in row-differenced banded form (6N x kBandW per filament at 6*seg_off[f]*kBandW),
@@ -73,10 +86,6 @@ int broyden_update_launch(const SimDev& d, int k, const double* AB, const int32_
                           double* part, double* X, double* dXout, const int32_t* active, hipStream_t st);
 int first_step_launch(const SimDev& d, const double* h, const double* f, double* fprev, double* X, double* dXout,
                       const int32_t* active, hipStream_t st);
-// convergence test of evaluation `it` on the device; log[4i..4i+3] = state (0 running, 1 converged,
-// -1 failed), last iteration, evaluations, FP64 evaluations; last[i] = max|f|/a
-int judge_launch(int64_t ns, int it, double tol, double a, int kmax, int can_converge,
-                 const unsigned long long* resbits, int32_t* active, int32_t* log, double* last, hipStream_t st);
 // commits the step: Y, q from the converged state; X history shifted (Xjm2 may be null)
 int finalize_launch(const SimDev& d, const int32_t* commit, const double* Yc, const double* qc, const double* X,
                     double* Yj, double* Yjm1, double* qj, double* Xj, double* Xjm1, double* Xjm2, hipStream_t st);

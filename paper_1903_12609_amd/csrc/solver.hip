@@ -74,20 +74,41 @@ __global__ void __launch_bounds__(64) state_forces_kernel(SimDev d, const double
         st[n][0] = t.x; st[n][1] = t.y; st[n][2] = t.z;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        // robot-arm positions and the filament's bounding box (used by the steric pass)
-        V3 y = teth ? v3(d.base[3 * f], d.base[3 * f + 1], d.base[3 * f + 2]) : ldx(Xf, 0);
-        st3(Yc, S, s0, y);
-        V3 lo = y, hi = y;
-        for (int64_t n = 1; n < N; n++) {
-            y = y + (0.5 * d.dL) * v3(st[n - 1][0] + st[n][0], st[n - 1][1] + st[n][1], st[n - 1][2] + st[n][2]);
-            st3(Yc, S, s0 + n, y);
-            lo = v3(fmin(lo.x, y.x), fmin(lo.y, y.y), fmin(lo.z, y.z));
-            hi = v3(fmax(hi.x, y.x), fmax(hi.y, y.y), fmax(hi.z, y.z));
+    {
+        // robot-arm positions Y_n = Y_1 + dL/2 sum_{m<n} (t_m + t_{m+1}) by a wave
+        // prefix sum (N <= 64, one lane per segment), then the filament's bounding box
+        const int n = threadIdx.x;
+        double e[3];
+        if (n == 0) {
+            const V3 y1 = teth ? v3(d.base[3 * f], d.base[3 * f + 1], d.base[3 * f + 2]) : ldx(Xf, 0);
+            e[0] = y1.x;
+            e[1] = y1.y;
+            e[2] = y1.z;
+        } else {
+            for (int i = 0; i < 3; i++) e[i] = n < N ? (0.5 * d.dL) * (st[n - 1][i] + st[n][i]) : 0.0;
         }
-        double* b = box + 6 * f;
-        b[0] = lo.x; b[1] = lo.y; b[2] = lo.z;
-        b[3] = hi.x; b[4] = hi.y; b[5] = hi.z;
+        for (int o = 1; o < 64; o <<= 1)
+            for (int i = 0; i < 3; i++) {
+                const double t = __shfl_up(e[i], o, 64);
+                if (n >= o) e[i] += t;
+            }
+        if (n < N) st3(Yc, S, s0 + n, v3(e[0], e[1], e[2]));
+        double lo[3], hi[3];
+        for (int i = 0; i < 3; i++) lo[i] = hi[i] = __shfl(e[i], 0, 64);
+        for (int i = 0; i < 3; i++)
+            if (n < N) lo[i] = hi[i] = e[i];
+        for (int o = 32; o > 0; o >>= 1)
+            for (int i = 0; i < 3; i++) {
+                lo[i] = fmin(lo[i], __shfl_xor(lo[i], o, 64));
+                hi[i] = fmax(hi[i], __shfl_xor(hi[i], o, 64));
+            }
+        if (n == 0) {
+            double* b = box + 6 * f;
+            for (int i = 0; i < 3; i++) {
+                b[i] = lo[i];
+                b[3 + i] = hi[i];
+            }
+        }
     }
     for (int64_t n = threadIdx.x; n < N; n += 64) {
         const Q4 qn{sq[n][0], sq[n][1], sq[n][2], sq[n][3]};
@@ -129,7 +150,7 @@ int state_forces_launch(const SimDev& d, const double* X, const double* qj, cons
 // (one per lane), then walks the segments of every filament within the cutoff
 // with wave-uniform (scalar) loads.  It finishes the force F^H = F^C + F^B +
 // gravity and writes the mobility source record of each of its segments.
-__global__ void __launch_bounds__(64) steric_pack_kernel(SimDev d, const double* __restrict__ Yc,
+__global__ void __launch_bounds__(64 * kStericWaves) steric_pack_kernel(SimDev d, const double* __restrict__ Yc,
                                                        const double* __restrict__ box,
                                                        const int32_t* __restrict__ active, double* __restrict__ F,
                                                        const double* __restrict__ T, int prec, void* __restrict__ pk) {
@@ -138,7 +159,8 @@ __global__ void __launch_bounds__(64) steric_pack_kernel(SimDev d, const double*
     if (!active[isus]) return;
     const int64_t S = d.S;
     const int64_t s0 = d.seg_off[f], N = d.seg_off[f + 1] - s0;
-    const int lane = threadIdx.x;  // N <= 64
+    const int lane = threadIdx.x & 63;  // N <= 64
+    const int wave = threadIdx.x >> 6;   // the waves split each neighbour's segments
     const bool valid = lane < N;
     const int64_t sn = s0 + (valid ? lane : N - 1);
     const double y0 = Yc[sn], y1 = Yc[S + sn], y2 = Yc[2 * S + sn];
@@ -162,16 +184,28 @@ __global__ void __launch_bounds__(64) steric_pack_kernel(SimDev d, const double*
                 near = gx * gx + gy * gy + gz * gz < rc2;
             }
             unsigned long long mask = __ballot(near);
+            // one coalesced load of a near filament's positions, then lane broadcasts;
+            // the next near filament's load is issued before the current one is used
+            auto load_pos = [&](unsigned long long msk, double& q0, double& q1, double& q2) {
+                const int64_t g2 = gb + (__ffsll((long long)msk) - 1);
+                const int64_t a0 = d.seg_off[g2];
+                const int nn = (int)(d.seg_off[g2 + 1] - a0);
+                const int64_t ml = a0 + (lane < nn ? lane : 0);
+                q0 = Yc[ml];
+                q1 = Yc[S + ml];
+                q2 = Yc[2 * S + ml];
+            };
+            double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+            if (mask) load_pos(mask, p0, p1, p2);
             while (mask) {
                 const int l = __ffsll((long long)mask) - 1;
                 mask &= mask - 1;
+                double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+                if (mask) load_pos(mask, n0, n1, n2);
                 const int64_t gg = gb + l;
                 const int64_t m0 = d.seg_off[gg];
                 const int ng = (int)(d.seg_off[gg + 1] - m0);  // <= 64
-                // one coalesced load of the neighbour's positions, then lane broadcasts
-                const int64_t ml = m0 + (lane < ng ? lane : 0);
-                const double p0 = Yc[ml], p1 = Yc[S + ml], p2 = Yc[2 * S + ml];
-                for (int q = 0; q < ng; q++) {
+                for (int q = wave; q < ng; q += kStericWaves) {
                     const int64_t m = m0 + q;
                     const double rx = y0 - readlane_f64(p0, q), ry = y1 - readlane_f64(p1, q),
                                  rz = y2 - readlane_f64(p2, q);
@@ -186,24 +220,40 @@ __global__ void __launch_bounds__(64) steric_pack_kernel(SimDev d, const double*
                         fz += sc * rz;
                     }
                 }
+                p0 = n0;
+                p1 = n1;
+                p2 = n2;
             }
         }
     }
-    if (valid) {
-        fx += F[sn];
-        fy += F[S + sn];
-        fz += F[2 * S + sn];
-        F[sn] = fx;
-        F[S + sn] = fy;
-        F[2 * S + sn] = fz;
-        rpy_pack_record(prec, pk, sn, y0, y1, y2, fx, fy, fz, T[sn], T[S + sn], T[2 * S + sn]);
+    // fixed-order combination of the waves' partial forces
+    __shared__ double red[kStericWaves][3][64];
+    red[wave][0][lane] = fx;
+    red[wave][1][lane] = fy;
+    red[wave][2][lane] = fz;
+    __syncthreads();
+    if (wave != 0 || !valid) return;
+    fx = red[0][0][lane];
+    fy = red[0][1][lane];
+    fz = red[0][2][lane];
+    for (int w = 1; w < kStericWaves; w++) {
+        fx += red[w][0][lane];
+        fy += red[w][1][lane];
+        fz += red[w][2][lane];
     }
+    fx += F[sn];
+    fy += F[S + sn];
+    fz += F[2 * S + sn];
+    F[sn] = fx;
+    F[S + sn] = fy;
+    F[2 * S + sn] = fz;
+    rpy_pack_record(prec, pk, sn, y0, y1, y2, fx, fy, fz, T[sn], T[S + sn], T[2 * S + sn]);
 }
 
 int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, const int32_t* active, double* F,
                        const double* T, int prec, void* pk, hipStream_t st) {
     if (d.M == 0) return FIL_OK;
-    steric_pack_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, Yc, box, active, F, T, prec, pk);
+    steric_pack_kernel<<<(unsigned)d.M, 64 * kStericWaves, 0, st>>>(d, Yc, box, active, F, T, prec, pk);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }
@@ -231,48 +281,95 @@ __device__ __forceinline__ void susp_max(double v, int32_t isus, const int32_t* 
     if (isus != first && isus >= 0 && active[isus]) atomicMax(&out[isus], bits);
 }
 
-__global__ void __launch_bounds__(256) residual_kernel(SimDev d, BdfCoef bc, const double* __restrict__ X,
-                                                     const double* __restrict__ Xj, const double* __restrict__ Yc,
-                                                     const double* __restrict__ Yj, const double* __restrict__ Yjm1,
-                                                     double* __restrict__ V, double* __restrict__ W,
-                                                     const double* __restrict__ part, int K,
-                                                     const int32_t* __restrict__ active, double* __restrict__ fout,
-                                                     unsigned long long* __restrict__ resbits,
-                                                     unsigned long long* __restrict__ resbits_next) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Convergence test of evaluation `it` for iterations that run without the host
+// (captured in a graph): max|f|/a of each active suspension ends it when <= tol
+// (if this evaluation may end a step), fails it when non-finite or at it >= kmax;
+// the evaluation is counted.  log[4i..4i+3]: state, last iteration, evaluations,
+// FP64 evaluations.
+__device__ void judge_suspensions(const JudgeArgs& j, int64_t ns, const unsigned long long* __restrict__ resbits,
+                                  int tid, int nthreads) {
+    for (int64_t i = tid; i < ns; i += nthreads) {
+        if (!j.active[i]) continue;
+        const double r = __longlong_as_double((long long)resbits[i]) * j.inv_a;
+        int32_t* L = j.log + 4 * i;
+        L[1] = j.it;
+        L[2] += 1;
+        L[3] += j.can_converge;
+        j.last[i] = r;
+        int32_t st = 0;
+        if (!(r <= 1.7976931348623157e308)) st = -1;  // NaN or infinite
+        else if (r <= j.tol && j.can_converge) st = 1;
+        else if (j.it >= j.kmax) st = -1;
+        if (st) {
+            L[0] = st;
+            j.active[i] = 0;
+        }
+    }
+}
+
+// One workgroup per 64 segments: its six waves first sum one velocity component
+// each over the K mobility partials (coalesced, fixed order), then the first
+// wave forms the six residual rows of its segments.  With a judge ticket, the
+// last workgroup to finish runs the convergence test (and resets the ticket).
+__global__ void __launch_bounds__(6 * kResSeg) residual_kernel(SimDev d, BdfCoef bc, const double* __restrict__ X,
+                                                             const double* __restrict__ Xj,
+                                                             const double* __restrict__ Yc,
+                                                             const double* __restrict__ Yj,
+                                                             const double* __restrict__ Yjm1,
+                                                             double* __restrict__ V, double* __restrict__ W,
+                                                             const double* __restrict__ part, int K,
+                                                             const int32_t* __restrict__ active,
+                                                             double* __restrict__ fout,
+                                                             unsigned long long* __restrict__ resbits,
+                                                             unsigned long long* __restrict__ resbits_next,
+                                                             JudgeArgs jg) {
+    const int64_t S = d.S;
     // the other buffer is zeroed for the next evaluation (the host has read it)
     if (blockIdx.x == 0)
         for (int64_t i = threadIdx.x; i < 2 * d.nsusp; i += blockDim.x) resbits_next[i] = 0ull;
+    __shared__ double sv[6][kResSeg];
+    const int c = threadIdx.x / kResSeg, l = threadIdx.x % kResSeg;
+    {
+        const int64_t s = (int64_t)blockIdx.x * kResSeg + l;
+        if (s < S && active[d.fil_susp[d.seg_fil[s]]]) {
+            double v;
+            if (part) {
+                const double* pp = part + (int64_t)c * S + s;
+                const int64_t stride = 6 * S;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int k = 0;
+                for (; k + 4 <= K; k += 4) {
+                    a0 += pp[(int64_t)k * stride];
+                    a1 += pp[(int64_t)(k + 1) * stride];
+                    a2 += pp[(int64_t)(k + 2) * stride];
+                    a3 += pp[(int64_t)(k + 3) * stride];
+                }
+                for (; k < K; k++) a0 += pp[(int64_t)k * stride];
+                v = (a0 + a1) + (a2 + a3);
+                if (c < 3) V[c * S + s] = v;
+                else W[(c - 3) * S + s] = v;
+            } else {
+                v = c < 3 ? V[c * S + s] : W[(c - 3) * S + s];
+            }
+            sv[c][l] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x >= kResSeg) return;
+    const int64_t s = (int64_t)blockIdx.x * kResSeg + threadIdx.x;
     double amax = 0.0, vmax = 0.0;
     int32_t isus = -1;
-    if (s < d.S) {
+    if (s < S) {
         const int32_t f = d.seg_fil[s];
         isus = d.fil_susp[f];
         if (active[isus]) {
             const int64_t s0 = d.seg_off[f], N = d.seg_off[f + 1] - s0, n = s - s0;
             const int teth = d.tether[f];
-            const int64_t S = d.S;
             const double bdt = bc.b * d.spar[kSpar * isus];
             const double* Xf = X + 6 * s0;
             double* ff = fout + 6 * s0;
-            V3 vel, om;
-            if (part) {
-                // fixed-order sum of the mobility's K source-chunk partials
-                double acc[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll 8
-                for (int k = 0; k < K; k++) {
-                    const double* pp = part + (int64_t)k * 6 * S + s;
-#pragma unroll
-                    for (int c = 0; c < 6; c++) acc[c] += pp[c * S];
-                }
-                vel = v3(acc[0], acc[1], acc[2]);
-                om = v3(acc[3], acc[4], acc[5]);
-                st3(V, S, s, vel);
-                st3(W, S, s, om);
-            } else {
-                vel = ld3(V, S, s);
-                om = ld3(W, S, s);
-            }
+            const V3 vel = v3(sv[0][l], sv[1][l], sv[2][l]);
+            const V3 om = v3(sv[3][l], sv[4][l], sv[5][l]);
             const V3 yres = ld3(Yc, S, s) - bc.a1 * ld3(Yj, S, s) - bc.a2 * ld3(Yjm1, S, s) - bdt * vel;
             V3 u = ldx(Xf, 3 + 3 * n), uj = ldx(Xj + 6 * s0, 3 + 3 * n);
             if (teth && n == 0) u = uj = v3(0, 0, 0);
@@ -296,15 +393,28 @@ __global__ void __launch_bounds__(256) residual_kernel(SimDev d, BdfCoef bc, con
     }
     susp_max(amax, isus, active, resbits);
     susp_max(vmax, isus, active, resbits + d.nsusp);
+    if (!jg.ticket) return;
+    // last-workgroup convergence test: this wave's atomics are made visible, then
+    // one ticket per workgroup; the workgroup drawing the last ticket sees all of them
+    __threadfence();
+    unsigned int t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(jg.ticket, 1u);
+    t = __shfl(t, 0, 64);
+    if (t != gridDim.x - 1) return;
+    __threadfence();
+    judge_suspensions(jg, d.nsusp, resbits, threadIdx.x, kResSeg);
+    if (threadIdx.x == 0) atomicExch(jg.ticket, 0u);
 }
 
 int residual_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* Xj, const double* Yc,
                     const double* Yj, const double* Yjm1, double* V, double* W, const double* part, int K,
                     const int32_t* active, double* f, unsigned long long* resbits, unsigned long long* resbits_next,
-                    hipStream_t st) {
+                    hipStream_t st, const JudgeArgs* judge) {
+    JudgeArgs jg{};
+    if (judge) jg = *judge;
     if (d.S > 0)
-        residual_kernel<<<(unsigned)ceil_div(d.S, 256), 256, 0, st>>>(d, bc, X, Xj, Yc, Yj, Yjm1, V, W, part, K,
-                                                                     active, f, resbits, resbits_next);
+        residual_kernel<<<(unsigned)ceil_div(d.S, kResSeg), 6 * kResSeg, 0, st>>>(
+            d, bc, X, Xj, Yc, Yj, Yjm1, V, W, part, K, active, f, resbits, resbits_next, jg);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }
@@ -819,17 +929,30 @@ __global__ void __launch_bounds__(256) dense_matvec_kernel(SimDev d, const doubl
     __shared__ double sv[6 * kMaxSeg];
     for (int j = threadIdx.x; j < n; j += blockDim.x) sv[j] = v[6 * s0 + j];
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int c = 0;
-        for (; c + 4 <= n; c += 4) {
-            a0 = fma(A[(int64_t)c * n + i], sv[c], a0);
-            a1 = fma(A[(int64_t)(c + 1) * n + i], sv[c + 1], a1);
-            a2 = fma(A[(int64_t)(c + 2) * n + i], sv[c + 2], a2);
-            a3 = fma(A[(int64_t)(c + 3) * n + i], sv[c + 3], a3);
+    // two threads per row, each over half of the columns (four chains each), combined in LDS
+    __shared__ double red[128];
+    const int half = threadIdx.x >> 7, li = threadIdx.x & 127;
+    const int cmid = ((n + 7) / 8) * 4;  // first column of the second half (multiple of 4)
+    const int cb = half ? cmid : 0, ce = half ? n : (cmid < n ? cmid : n);
+    for (int i0 = 0; i0 < n; i0 += 128) {
+        const int i = i0 + li;
+        double acc = 0.0;
+        if (i < n) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int c = cb;
+            for (; c + 4 <= ce; c += 4) {
+                a0 = fma(A[(int64_t)c * n + i], sv[c], a0);
+                a1 = fma(A[(int64_t)(c + 1) * n + i], sv[c + 1], a1);
+                a2 = fma(A[(int64_t)(c + 2) * n + i], sv[c + 2], a2);
+                a3 = fma(A[(int64_t)(c + 3) * n + i], sv[c + 3], a3);
+            }
+            for (; c < ce; c++) a0 = fma(A[(int64_t)c * n + i], sv[c], a0);
+            acc = (a0 + a1) + (a2 + a3);
         }
-        for (; c < n; c++) a0 = fma(A[(int64_t)c * n + i], sv[c], a0);
-        out[6 * s0 + i] = (a0 + a1) + (a2 + a3);
+        if (half) red[li] = acc;
+        __syncthreads();
+        if (!half && i < n) out[6 * s0 + i] = acc + red[li];
+        __syncthreads();
     }
 }
 #undef AB_
@@ -912,10 +1035,15 @@ __global__ void __launch_bounds__(256) broyden_combine_kernel(SimDev d, int k, c
     __shared__ double dots[kMaxDots];
     const int ndot = k + 2;
     const int64_t pb0 = d.susp_vblk_off[isus], pb1 = d.susp_vblk_off[isus + 1];
-    for (int h = threadIdx.x; h < ndot; h += blockDim.x) {
-        double s = 0.0;
-        for (int64_t p = pb0; p < pb1; p++) s += part[p * (int64_t)d.max_dots + h];
-        dots[h] = s;
+    // dot h is summed by wave h mod 4: lane-strided partials, then a fixed shuffle tree
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int h = wave; h < ndot; h += (int)(blockDim.x >> 6)) {
+            double s = 0.0;
+            for (int64_t p = pb0 + lane; p < pb1; p += 64) s += part[p * (int64_t)d.max_dots + h];
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+            if (lane == 0) dots[h] = s;
+        }
     }
     __syncthreads();
     const double nrm = sqrt(dots[k]);
@@ -924,8 +1052,17 @@ __global__ void __launch_bounds__(256) broyden_combine_kernel(SimDev d, int k, c
     const int64_t n6 = 6 * d.S;
     const int64_t e0 = d.vblk_start[b], e1 = d.vblk_start[b + 1];
     for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        double g = g0[e];
-        for (int h = 0; h < k; h++) g = fma(Chist[(int64_t)h * n6 + e], dots[h], g);
+        // four independent chains over the history keep several loads in flight
+        double g1 = 0.0, g2 = 0.0, g3 = 0.0, g4 = 0.0;
+        int h = 0;
+        for (; h + 4 <= k; h += 4) {
+            g1 = fma(Chist[(int64_t)h * n6 + e], dots[h], g1);
+            g2 = fma(Chist[(int64_t)(h + 1) * n6 + e], dots[h + 1], g2);
+            g3 = fma(Chist[(int64_t)(h + 2) * n6 + e], dots[h + 2], g3);
+            g4 = fma(Chist[(int64_t)(h + 3) * n6 + e], dots[h + 3], g4);
+        }
+        for (; h < k; h++) g1 = fma(Chist[(int64_t)h * n6 + e], dots[h], g1);
+        const double g = g0[e] + ((g1 + g2) + (g3 + g4));
         const double fn = fnew[e];
         const double c = -g * inrm;
         const double dd = (fn - fprev[e]) * inrm;
@@ -971,42 +1108,6 @@ int first_step_launch(const SimDev& d, const double* h, const double* f, double*
                       const int32_t* active, hipStream_t st) {
     if (d.S == 0) return FIL_OK;
     first_step_kernel<<<(unsigned)d.nvblk, 256, 0, st>>>(d, h, f, fprev, X, dXout, active);
-    FIL_HIP_TRY(hipGetLastError());
-    return FIL_OK;
-}
-
-// ---------------------------------------------------------------- device-side convergence test
-// Test of evaluation `it` for iterations that run without the host (captured
-// in a graph): max|f|/a of each active suspension (from the residual kernel's
-// bit pattern) ends it when <= tol (if this evaluation may end a step), fails
-// it when non-finite or at it >= kmax; counts the evaluation.
-__global__ void __launch_bounds__(256) judge_kernel(int64_t ns, int it, double tol, double inv_a, int kmax,
-                                                    int can_converge, const unsigned long long* __restrict__ resbits,
-                                                    int32_t* __restrict__ active, int32_t* __restrict__ log,
-                                                    double* __restrict__ last) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x) {
-        if (!active[i]) continue;
-        const double r = __longlong_as_double((long long)resbits[i]) * inv_a;
-        int32_t* L = log + 4 * i;  // state, iters, applies, FP64 applies
-        L[1] = it;
-        L[2] += 1;
-        L[3] += can_converge;
-        last[i] = r;
-        int32_t st = 0;
-        if (!(r <= 1.7976931348623157e308)) st = -1;  // NaN or infinite
-        else if (r <= tol && can_converge) st = 1;
-        else if (it >= kmax) st = -1;
-        if (st) {
-            L[0] = st;
-            active[i] = 0;
-        }
-    }
-}
-
-int judge_launch(int64_t ns, int it, double tol, double a, int kmax, int can_converge,
-                 const unsigned long long* resbits, int32_t* active, int32_t* log, double* last, hipStream_t st) {
-    judge_kernel<<<(unsigned)ceil_div(ns, 256), 256, 0, st>>>(ns, it, tol, 1.0 / a, kmax, can_converge, resbits,
-                                                             active, log, last);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }
