@@ -8,7 +8,6 @@ constexpr int kMaxSeg = 64;       // segments per filament (one lane per segment
 constexpr int kKL = 8;            // sub-diagonals of the row-differenced J0 in interleaved order
 constexpr int kKU = 8;            // super-diagonals (kKL + kKU after pivoting fill-in)
 constexpr int kBandW = 2 * kKL + kKU + 1;
-constexpr int kInvWaves = 8;      // column solves per workgroup when building the explicit J0^{-1}
 constexpr size_t kDenseInvBytes = size_t(64) << 20;  // explicit J0^{-1} used up to this total size
 constexpr int kMaxIter = 256;     // Broyden history capacity
 constexpr int kMaxDots = kMaxIter + 2;

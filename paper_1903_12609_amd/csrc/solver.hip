@@ -9,6 +9,9 @@
 #include "common.h"
 #include "kernels.h"
 #include "quat.h"
+#include <map>
+#include <mutex>
+
 #include "solver.h"
 
 namespace fil {
@@ -886,34 +889,116 @@ __global__ void __launch_bounds__(64) j0_band_solve_kernel(SimDev d, const doubl
     for (int i = lane; i < n; i += 64) out[6 * s0 + slot_of(i / 3, N) + i % 3] = y[i];
 }
 
-// Explicit inverse for the dense per-iteration product: block (f, g) runs
-// kInvWaves waves on the staged band of filament f; wave w solves for the unit
-// vector e_c, c = g * kInvWaves + w, and writes column c of J0^{-1} as row c of
-// Ainv^T (row-major n x n at dense_off[f]).
-__global__ void __launch_bounds__(64 * kInvWaves) j0_band_inverse_kernel(SimDev d, const double* __restrict__ AB,
-                                                                       const int32_t* __restrict__ ipiv,
-                                                                       const int32_t* __restrict__ active,
-                                                                       double* __restrict__ AinvT, int nmax) {
+// Explicit inverse for the dense per-iteration product.  Block (f, g) owns cb
+// columns c = g*cb + t of filament f's J0^{-1}, one per thread: the thread
+// solves (D J0) y = D e_c (D the row differencing) through the band factor
+// with its column held in a sliding register window (kKL + 1 rows forward,
+// kKL + kKU + 1 rows backward), so each sweep step is a few FMAs on registers;
+// the band coefficients and pivots, staged in LDS, are the same for all threads.
+// Forward results wait in LDS for the backward sweep, whose results are then
+// written as row c of Ainv^T with coalesced stores.
+template <int CB>
+__global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const double* __restrict__ AB,
+                                                            const int32_t* __restrict__ ipiv,
+                                                            const int32_t* __restrict__ active,
+                                                            double* __restrict__ AinvT) {
+    constexpr int kU = kKL + kKU;
     const int64_t f = blockIdx.x;
     if (!active[d.fil_susp[f]]) return;
     const int64_t s0 = d.seg_off[f];
     const int N = (int)(d.seg_off[f + 1] - s0);
     const int n = 6 * N;
-    if ((int)blockIdx.y * kInvWaves >= n) return;
+    const int c0 = blockIdx.y * CB;
+    if (c0 >= n) return;
+    // LDS: the filament's band factor [n][kBandW] | forward results [n][CB] | pivots [n]
     extern __shared__ double lds[];
     double* ab = lds;
-    int* ip = reinterpret_cast<int*>(lds + (size_t)nmax * kBandW);
-    double* ybase = reinterpret_cast<double*>(reinterpret_cast<char*>(ip) + (((size_t)nmax * sizeof(int) + 15) & ~(size_t)15));
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int c = blockIdx.y * kInvWaves + wave;
-    double* y = ybase + (size_t)wave * nmax;
-    if (c < n)
-        for (int i = lane; i < n; i += 64) y[i] = diff_unit(c, i, N);
-    stage_factor(AB + 6 * s0 * kBandW, ipiv + 6 * s0, ab, ip, n);
-    if (c >= n) return;
-    band_sweeps(ab, ip, y, n, lane);
-    double* col = AinvT + d.dense_off[f] + (int64_t)c * n;
-    for (int i = lane; i < n; i += 64) col[slot_of(i / 3, N) + i % 3] = y[i];
+    double* ybuf = lds + (size_t)n * kBandW;
+    int* ip = reinterpret_cast<int*>(ybuf + (size_t)n * CB);
+    const int t = threadIdx.x;
+    const int c = c0 + t;
+    const bool live = t < CB && c < n;
+    {
+        const double* gab = AB + 6 * s0 * kBandW;
+        for (int e = t; e < n * kBandW; e += blockDim.x) ab[e] = gab[e];
+        for (int e = t; e < n; e += blockDim.x) ip[e] = ipiv[6 * s0 + e];
+        __syncthreads();
+    }
+    auto rhs = [&](int i) { return (live && i < n) ? diff_unit(c, i, N) : 0.0; };
+    // ---- forward: W[k] = y[j + k]
+    double W[kKL + 1];
+#pragma unroll
+    for (int k = 0; k <= kKL; k++) W[k] = rhs(k);
+    // the next step's pivot and multipliers are requested before this step's arithmetic
+    auto load_fwd = [&](int j, double (&Lv)[kKL + 1], int& pv) {
+        const double* col = ab + (int64_t)j * kBandW + kKL;  // L(j+k, j) = col[k*(kBandW-1)]
+        pv = ip[j] - j;                                       // 0..kKL, the same for every thread
+#pragma unroll
+        for (int k = 1; k <= kKL; k++) Lv[k] = j + k < n ? col[k * (kBandW - 1)] : 0.0;
+    };
+    double Lc[kKL + 1], Ln[kKL + 1];
+    int pc, pn = 0;
+    load_fwd(0, Lc, pc);
+    for (int j = 0; j < n; j++) {
+        if (j + 1 < n) load_fwd(j + 1, Ln, pn);
+        if (pc != 0) {
+            const double w0 = W[0];
+#pragma unroll
+            for (int k = 1; k <= kKL; k++)
+                if (pc == k) {
+                    W[0] = W[k];
+                    W[k] = w0;
+                }
+        }
+        const double yj = W[0];
+#pragma unroll
+        for (int k = 1; k <= kKL; k++) W[k] = fma(-Lc[k], yj, W[k]);
+        if (t < CB) ybuf[(int64_t)j * CB + t] = yj;
+#pragma unroll
+        for (int k = 0; k < kKL; k++) W[k] = W[k + 1];
+        W[kKL] = rhs(j + kKL + 1);
+#pragma unroll
+        for (int k = 1; k <= kKL; k++) Lc[k] = Ln[k];
+        pc = pn;
+    }
+    __syncthreads();
+    // ---- backward: B[k] = y[i - kU + k]
+    double B[kU + 1];
+    const int i0 = n - 1;
+#pragma unroll
+    for (int k = 0; k <= kU; k++) {
+        const int r = i0 - kU + k;
+        B[k] = (r >= 0 && t < CB) ? ybuf[(int64_t)r * CB + t] : 0.0;
+    }
+    auto load_bwd = [&](int i, double (&Uv)[kU + 1]) {
+        const double* row = ab + (int64_t)i * kBandW + kKL;  // U(i-k, i) = row[k - k*kBandW]
+        Uv[0] = 1.0 / row[0];
+#pragma unroll
+        for (int k = 1; k <= kU; k++) Uv[k] = i - k >= 0 ? row[k - (int64_t)k * kBandW] : 0.0;
+    };
+    double Uc[kU + 1], Un[kU + 1];
+    load_bwd(i0, Uc);
+    for (int i = i0; i >= 0; i--) {
+        if (i > 0) load_bwd(i - 1, Un);
+        const double xi = B[kU] * Uc[0];
+#pragma unroll
+        for (int k = 1; k <= kU; k++) B[kU - k] = fma(-Uc[k], xi, B[kU - k]);
+        if (t < CB) ybuf[(int64_t)i * CB + t] = xi;
+#pragma unroll
+        for (int k = kU; k > 0; k--) B[k] = B[k - 1];
+        const int r = i - kU - 1;
+        B[0] = (r >= 0 && t < CB) ? ybuf[(int64_t)r * CB + t] : 0.0;
+#pragma unroll
+        for (int k = 0; k <= kU; k++) Uc[k] = Un[k];
+    }
+    __syncthreads();
+    // ---- row c of Ainv^T (original unknown order), coalesced over i
+    const int ncols = min(CB, n - c0);
+    double* base = AinvT + d.dense_off[f] + (int64_t)c0 * n;
+    for (int e = t; e < ncols * n; e += blockDim.x) {
+        const int cc = e / n, i = e % n;
+        base[(int64_t)cc * n + slot_of(i / 3, N) + i % 3] = ybuf[(int64_t)i * CB + cc];
+    }
 }
 
 // out = J0^{-1} v with the explicit inverse: out_i = sum_c Ainv^T[c][i] v_c
@@ -957,18 +1042,50 @@ __global__ void __launch_bounds__(256) dense_matvec_kernel(SimDev d, const doubl
 }
 #undef AB_
 
+// Dynamic LDS beyond 64 KB has to be granted to a kernel (gfx950 has 160 KB per
+// workgroup); granted once per kernel, before any launch that is captured.
+template <class Kernel>
+int allow_lds(Kernel kernel, size_t bytes) {
+    static std::mutex mu;
+    static std::map<const void*, size_t> granted;
+    if (bytes <= 65536) return FIL_OK;
+    const void* k = reinterpret_cast<const void*>(kernel);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = granted.find(k);
+    if (it != granted.end() && it->second >= bytes) return FIL_OK;
+    FIL_HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    granted[k] = bytes;
+    return FIL_OK;
+}
+
 int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* qc, const double* Tint,
                      double tt, const int32_t* active, double* AB, int32_t* ipiv, int32_t* flag, double* AinvT,
                      hipStream_t st) {
     if (d.M == 0) return FIL_OK;
     const int nmax = 6 * d.max_seg;
     j0_band_assemble_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, bc, X, qc, Tint, tt, active, AB);
-    j0_band_factor_kernel<<<(unsigned)d.M, 64, (size_t)nmax * kBandW * sizeof(double), st>>>(d, active, AB, ipiv,
-                                                                                           flag);
+    const size_t fl = (size_t)nmax * kBandW * sizeof(double);
+    if (int rc = allow_lds(j0_band_factor_kernel, fl)) return rc;
+    j0_band_factor_kernel<<<(unsigned)d.M, 64, fl, st>>>(d, active, AB, ipiv, flag);
     if (AinvT) {
-        const dim3 grid((unsigned)d.M, (unsigned)ceil_div(nmax, kInvWaves));
-        j0_band_inverse_kernel<<<grid, 64 * kInvWaves, band_lds_bytes(nmax, kInvWaves), st>>>(d, AB, ipiv, active,
-                                                                                           AinvT, nmax);
+        // one thread per inverse column; a block's columns (64, 32 or 16, so that its
+        // band, pivots and forward results fit in LDS) share the staged factor
+        auto lds = [nmax](int cb) {
+            return (size_t)nmax * (kBandW + cb) * sizeof(double) + (size_t)nmax * sizeof(int);
+        };
+        if (nmax <= 128) {
+            const dim3 grid((unsigned)d.M, (unsigned)ceil_div(nmax, 64));
+            if (int rc = allow_lds(j0_inverse_cols_kernel<64>, lds(64))) return rc;
+            j0_inverse_cols_kernel<64><<<grid, 64, lds(64), st>>>(d, AB, ipiv, active, AinvT);
+        } else if (nmax <= 256) {
+            const dim3 grid((unsigned)d.M, (unsigned)ceil_div(nmax, 32));
+            if (int rc = allow_lds(j0_inverse_cols_kernel<32>, lds(32))) return rc;
+            j0_inverse_cols_kernel<32><<<grid, 64, lds(32), st>>>(d, AB, ipiv, active, AinvT);
+        } else {
+            const dim3 grid((unsigned)d.M, (unsigned)ceil_div(nmax, 16));
+            if (int rc = allow_lds(j0_inverse_cols_kernel<16>, lds(16))) return rc;
+            j0_inverse_cols_kernel<16><<<grid, 64, lds(16), st>>>(d, AB, ipiv, active, AinvT);
+        }
     }
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
@@ -981,6 +1098,7 @@ int j0_solve_launch(const SimDev& d, const double* AB, const int32_t* ipiv, cons
         dense_matvec_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, AinvT, v, active, out);
     } else {
         const int nmax = 6 * d.max_seg;
+        if (int rc = allow_lds(j0_band_solve_kernel, band_lds_bytes(nmax, 1))) return rc;
         j0_band_solve_kernel<<<(unsigned)d.M, 64, band_lds_bytes(nmax, 1), st>>>(d, AB, ipiv, v, active, out, nmax);
     }
     FIL_HIP_TRY(hipGetLastError());
