@@ -542,14 +542,32 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     // ---- device allocations
     int rc = FIL_OK;
     int64_t *d_seg_off, *d_susp_seg_off, *d_susp_fil_off, *d_vblk_start, *d_susp_vblk_off, *d_dense_off = nullptr;
-    int32_t *d_fil_susp, *d_seg_fil, *d_teth, *d_vblk_susp;
+    int32_t *d_fil_susp, *d_seg_fil, *d_teth, *d_vblk_susp, *d_cls_fil;
+    // size classes of the filaments
+    const int cls_bound[kMaxCls] = {16, 24, 32, 40, 48, kMaxSeg};
+    std::vector<int32_t> cls_fil;
+    int64_t cls_off[kMaxCls + 1];
+    int cls_n[kMaxCls];
+    for (int k = 0; k < kMaxCls; k++) {
+        cls_off[k] = (int64_t)cls_fil.size();
+        int nmx = 0;
+        for (int64_t f = 0; f < M; f++) {
+            const int N = (int)(seg_off[f + 1] - seg_off[f]);
+            if (N <= cls_bound[k] && (k == 0 || N > cls_bound[k - 1])) {
+                cls_fil.push_back((int32_t)f);
+                nmx = std::max(nmx, 6 * N);
+            }
+        }
+        cls_n[k] = nmx;
+    }
+    cls_off[kMaxCls] = (int64_t)cls_fil.size();
     double *d_base, *d_phase = nullptr;
     const size_t n6 = 6 * (size_t)S;
     const int max_dots = p->kmax + 2;
 #define A(ptr, n)                                  \
     if (rc == FIL_OK) rc = dalloc(s, &(ptr), (n));
     A(d_seg_off, M + 1) A(d_susp_seg_off, nsusp + 1) A(d_susp_fil_off, nsusp + 1) A(d_vblk_start, nvblk + 1)
-    A(d_susp_vblk_off, nsusp + 1) A(d_fil_susp, M) A(d_seg_fil, S) A(d_teth, M) A(d_vblk_susp, nvblk)
+    A(d_susp_vblk_off, nsusp + 1) A(d_fil_susp, M) A(d_seg_fil, S) A(d_teth, M) A(d_vblk_susp, nvblk) A(d_cls_fil, M)
     A(d_base, 3 * M)
     if (phase) A(d_phase, M)
     A(s->Yj, 3 * S) A(s->Yjm1, 3 * S) A(s->qj, 4 * S) A(s->Xj, n6) A(s->Xjm1, n6) A(s->Xjm2, n6) A(s->X0p, n6)
@@ -620,6 +638,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         TRY(upload(d_seg_fil, seg_fil));
         TRY(upload(d_teth, teth));
         TRY(upload(d_vblk_susp, vblk_susp));
+        TRY(upload(d_cls_fil, cls_fil));
         TRY(upload(d_base, base));
         if (phase) TRY(upload(d_phase, std::vector<double>(phase, phase + M)));
         TRY(upload(s->Yj, Ysoa));
@@ -668,6 +687,10 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     d.KT = p->KT;
     d.chi = p->chi;
     d.spar = s->spar;
+    d.cls_fil = d_cls_fil;
+    d.ncls = kMaxCls;
+    for (int k = 0; k <= kMaxCls; k++) d.cls_off[k] = cls_off[k];
+    for (int k = 0; k < kMaxCls; k++) d.cls_n[k] = cls_n[k];
     d.K0 = p->K0;
     d.kw = p->kw;
     d.omega = p->omega;

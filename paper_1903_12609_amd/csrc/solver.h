@@ -14,6 +14,7 @@ constexpr int kMaxDots = kMaxIter + 2;
 constexpr int kVecBlock = 256;    // residual-vector elements per Broyden vector block
 constexpr int kSpar = 5;
 constexpr int kResSeg = 64;
+constexpr int kMaxCls = 6;        // filament size classes: N <= 16, 24, 32, 40, 48, 64
 constexpr int kStericWaves = 4;   // waves per filament in the steric pass       // segments per residual workgroup (six waves sum the partials)          // per-suspension parameters: dt, gravity force (3), F^S
 
 // BDF coefficients: y - a1 y^j - a2 y^{j-1} - b dt v = 0, u - g u^j - b dt dexpinv(Omega) = 0
@@ -41,6 +42,12 @@ struct SimDev {
     const int64_t* susp_vblk_off;  // [nsusp+1]
     int max_dots;
     const double* spar;            // [nsusp][5] per suspension: dt, gravity force (3), steric strength F^S
+    // filaments by size class (for launches whose LDS scales with 6N): class k holds
+    // cls_fil[cls_off[k] .. cls_off[k+1]), all with 6N <= cls_n[k]
+    const int32_t* cls_fil;
+    int ncls;
+    int64_t cls_off[kMaxCls + 1];
+    int cls_n[kMaxCls];
     double a, eta, dL, KB, KT, chi, K0, kw, omega;
 };
 

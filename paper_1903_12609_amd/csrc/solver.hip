@@ -713,9 +713,9 @@ __device__ __forceinline__ void stage_band(const double* __restrict__ g, double*
 // LU with partial pivoting of every filament's banded system, one wave each.
 __global__ void __launch_bounds__(64) j0_band_factor_kernel(SimDev d, const int32_t* __restrict__ active,
                                                           double* __restrict__ AB, int32_t* __restrict__ ipiv,
-                                                          int32_t* __restrict__ flag) {
+                                                          int32_t* __restrict__ flag, int64_t coff) {
     extern __shared__ double ab[];
-    const int64_t f = blockIdx.x;
+    const int64_t f = d.cls_fil[coff + blockIdx.x];
     if (!active[d.fil_susp[f]]) return;
     const int64_t s0 = d.seg_off[f];
     const int n = 6 * (int)(d.seg_off[f + 1] - s0);
@@ -870,8 +870,8 @@ __global__ void __launch_bounds__(64) j0_band_solve_kernel(SimDev d, const doubl
                                                          const int32_t* __restrict__ ipiv,
                                                          const double* __restrict__ v,
                                                          const int32_t* __restrict__ active,
-                                                         double* __restrict__ out, int nmax) {
-    const int64_t f = blockIdx.x;
+                                                         double* __restrict__ out, int nmax, int64_t coff) {
+    const int64_t f = d.cls_fil[coff + blockIdx.x];
     if (!active[d.fil_susp[f]]) return;
     extern __shared__ double lds[];
     const int64_t s0 = d.seg_off[f];
@@ -901,9 +901,9 @@ template <int CB>
 __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const double* __restrict__ AB,
                                                             const int32_t* __restrict__ ipiv,
                                                             const int32_t* __restrict__ active,
-                                                            double* __restrict__ AinvT) {
+                                                            double* __restrict__ AinvT, int64_t coff) {
     constexpr int kU = kKL + kKU;
-    const int64_t f = blockIdx.x;
+    const int64_t f = d.cls_fil[coff + blockIdx.x];
     if (!active[d.fil_susp[f]]) return;
     const int64_t s0 = d.seg_off[f];
     const int N = (int)(d.seg_off[f + 1] - s0);
@@ -1062,29 +1062,31 @@ int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const 
                      double tt, const int32_t* active, double* AB, int32_t* ipiv, int32_t* flag, double* AinvT,
                      hipStream_t st) {
     if (d.M == 0) return FIL_OK;
-    const int nmax = 6 * d.max_seg;
     j0_band_assemble_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, bc, X, qc, Tint, tt, active, AB);
-    const size_t fl = (size_t)nmax * kBandW * sizeof(double);
-    if (int rc = allow_lds(j0_band_factor_kernel, fl)) return rc;
-    j0_band_factor_kernel<<<(unsigned)d.M, 64, fl, st>>>(d, active, AB, ipiv, flag);
-    if (AinvT) {
+    // filaments grouped by size so that each launch's LDS fits its own largest filament
+    for (int k = 0; k < d.ncls; k++) {
+        const int64_t coff = d.cls_off[k], cnt = d.cls_off[k + 1] - coff;
+        if (cnt == 0) continue;
+        const int nc = d.cls_n[k];
+        const size_t fl = (size_t)nc * kBandW * sizeof(double);
+        if (int rc = allow_lds(j0_band_factor_kernel, fl)) return rc;
+        j0_band_factor_kernel<<<(unsigned)cnt, 64, fl, st>>>(d, active, AB, ipiv, flag, coff);
+        if (!AinvT) continue;
         // one thread per inverse column; a block's columns (64, 32 or 16, so that its
         // band, pivots and forward results fit in LDS) share the staged factor
-        auto lds = [nmax](int cb) {
-            return (size_t)nmax * (kBandW + cb) * sizeof(double) + (size_t)nmax * sizeof(int);
-        };
-        if (nmax <= 128) {
-            const dim3 grid((unsigned)d.M, (unsigned)ceil_div(nmax, 64));
+        auto lds = [nc](int cb) { return (size_t)nc * (kBandW + cb) * sizeof(double) + (size_t)nc * sizeof(int); };
+        if (nc <= 128) {
+            const dim3 grid((unsigned)cnt, (unsigned)ceil_div(nc, 64));
             if (int rc = allow_lds(j0_inverse_cols_kernel<64>, lds(64))) return rc;
-            j0_inverse_cols_kernel<64><<<grid, 64, lds(64), st>>>(d, AB, ipiv, active, AinvT);
-        } else if (nmax <= 256) {
-            const dim3 grid((unsigned)d.M, (unsigned)ceil_div(nmax, 32));
+            j0_inverse_cols_kernel<64><<<grid, 64, lds(64), st>>>(d, AB, ipiv, active, AinvT, coff);
+        } else if (nc <= 256) {
+            const dim3 grid((unsigned)cnt, (unsigned)ceil_div(nc, 32));
             if (int rc = allow_lds(j0_inverse_cols_kernel<32>, lds(32))) return rc;
-            j0_inverse_cols_kernel<32><<<grid, 64, lds(32), st>>>(d, AB, ipiv, active, AinvT);
+            j0_inverse_cols_kernel<32><<<grid, 64, lds(32), st>>>(d, AB, ipiv, active, AinvT, coff);
         } else {
-            const dim3 grid((unsigned)d.M, (unsigned)ceil_div(nmax, 16));
+            const dim3 grid((unsigned)cnt, (unsigned)ceil_div(nc, 16));
             if (int rc = allow_lds(j0_inverse_cols_kernel<16>, lds(16))) return rc;
-            j0_inverse_cols_kernel<16><<<grid, 64, lds(16), st>>>(d, AB, ipiv, active, AinvT);
+            j0_inverse_cols_kernel<16><<<grid, 64, lds(16), st>>>(d, AB, ipiv, active, AinvT, coff);
         }
     }
     FIL_HIP_TRY(hipGetLastError());
@@ -1097,9 +1099,14 @@ int j0_solve_launch(const SimDev& d, const double* AB, const int32_t* ipiv, cons
     if (AinvT) {
         dense_matvec_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, AinvT, v, active, out);
     } else {
-        const int nmax = 6 * d.max_seg;
-        if (int rc = allow_lds(j0_band_solve_kernel, band_lds_bytes(nmax, 1))) return rc;
-        j0_band_solve_kernel<<<(unsigned)d.M, 64, band_lds_bytes(nmax, 1), st>>>(d, AB, ipiv, v, active, out, nmax);
+        for (int k = 0; k < d.ncls; k++) {
+            const int64_t coff = d.cls_off[k], cnt = d.cls_off[k + 1] - coff;
+            if (cnt == 0) continue;
+            const int nc = d.cls_n[k];
+            if (int rc = allow_lds(j0_band_solve_kernel, band_lds_bytes(nc, 1))) return rc;
+            j0_band_solve_kernel<<<(unsigned)cnt, 64, band_lds_bytes(nc, 1), st>>>(d, AB, ipiv, v, active, out, nc,
+                                                                                coff);
+        }
     }
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
