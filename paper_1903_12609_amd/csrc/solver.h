@@ -14,6 +14,7 @@ constexpr int kMaxDots = kMaxIter + 2;
 constexpr int kVecBlock = 256;    // residual-vector elements per Broyden vector block
 constexpr int kSpar = 5;
 constexpr int kResSeg = 64;
+constexpr int kFusedJudgeBlocks = 64;  // residual grids up to this size run the convergence test themselves
 constexpr int kMaxCls = 6;        // filament size classes: N <= 16, 24, 32, 40, 48, 64
 constexpr int kStericWaves = 4;   // waves per filament in the steric pass       // segments per residual workgroup (six waves sum the partials)          // per-suspension parameters: dt, gravity force (3), F^S
 
