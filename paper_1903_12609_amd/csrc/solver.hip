@@ -725,63 +725,94 @@ __device__ __forceinline__ void stage_band(const double* __restrict__ g, double*
 // band element (i, j) of the LDS copy
 #define AB_(i, j) ab[(i) * kBandW + ((j) - (i) + kKL)]
 
-// LU with partial pivoting of every filament's banded system, one wave each.
-__global__ void __launch_bounds__(64) j0_band_factor_kernel(SimDev d, const int32_t* __restrict__ active,
-                                                          double* __restrict__ AB, int32_t* __restrict__ ipiv,
-                                                          int32_t* __restrict__ flag, int64_t coff) {
-    extern __shared__ double ab[];
-    const int64_t f = d.cls_fil[coff + blockIdx.x];
+// LU with partial pivoting of every filament's banded system, one wave each, in a
+// register window: lane l holds column j + l (l <= kKL + kKU) of rows j .. j + kKL,
+// the only rows and columns step j reads or writes (row p <= j + kKL has no
+// entries right of column j + kKL + kKU, before or after fill-in).  Step j takes
+// the pivot from lane 0's column (broadcast), swaps rows inside every lane, writes
+// row j of U and column j of L to the band, updates the window and shifts it one
+// column left / one row down; the row entering at the bottom was requested
+// kFacAhead steps earlier.  No LDS, so every filament of a large ensemble can be
+// resident at once.
+constexpr int kFacAhead = 4;
+__global__ void __launch_bounds__(64) j0_band_factor_regs_kernel(SimDev d, const int32_t* __restrict__ active,
+                                                               double* __restrict__ AB, int32_t* __restrict__ ipiv,
+                                                               int32_t* __restrict__ flag) {
+    constexpr int kWin = kKL + kKU + 1;  // window columns (17)
+    const int64_t f = blockIdx.x;
     if (!active[d.fil_susp[f]]) return;
     const int64_t s0 = d.seg_off[f];
     const int n = 6 * (int)(d.seg_off[f + 1] - s0);
-    double* gab = AB + 6 * s0 * kBandW;
+    double* ab = AB + 6 * s0 * kBandW;
     int32_t* gp = ipiv + 6 * s0;
-    const int lane = threadIdx.x;
-    stage_band(gab, ab, n * kBandW, lane);
+    const int l = threadIdx.x;
+    const bool lw = l < kWin;
+    // element (r, c) of the band (0 outside the matrix); the band stores columns r-kKL .. r+kKL+kKU
+    auto at = [&](int r, int c) {
+        return (lw && r < n && c < n && c - r >= -kKL && c - r <= kKL + kKU) ? ab[(int64_t)r * kBandW + (c - r + kKL)]
+                                                                            : 0.0;
+    };
+    double W[kKL + 1];
+#pragma unroll
+    for (int r = 0; r <= kKL; r++) W[r] = at(r, l);
+    double Q[kFacAhead];  // rows kKL+1 .. kKL+kFacAhead of this lane's future columns
+#pragma unroll
+    for (int q = 0; q < kFacAhead; q++) Q[q] = at(kKL + 1 + q, l + 1 + q);
     int bad = 0;
-    __syncthreads();
     for (int j = 0; j < n; j++) {
-        const int last = min(n - 1, j + kKL);
-        double v = -1.0;
-        int idx = j;
-        if (lane <= kKL && j + lane <= last) {
-            v = fabs(AB_(j + lane, j));
-            idx = j + lane;
-        }
-        for (int o = 8; o > 0; o >>= 1) {
-            const double v2 = __shfl_xor(v, o, 64);
-            const int i2 = __shfl_xor(idx, o, 64);
-            if (v2 > v || (v2 == v && i2 < idx)) {
-                v = v2;
-                idx = i2;
+        // pivot column j (lane 0) broadcast to the wave
+        double col[kKL + 1];
+#pragma unroll
+        for (int r = 0; r <= kKL; r++) col[r] = readlane_f64(W[r], 0);
+        int pr = 0;
+        double best = fabs(col[0]);
+#pragma unroll
+        for (int r = 1; r <= kKL; r++)
+            if (fabs(col[r]) > best) {
+                best = fabs(col[r]);
+                pr = r;
             }
+        if (!(best > 0.0)) bad = 1;
+        if (pr != 0) {
+            const double w0 = W[0], c0 = col[0];
+#pragma unroll
+            for (int r = 1; r <= kKL; r++)
+                if (pr == r) {
+                    W[0] = W[r];
+                    W[r] = w0;
+                    col[0] = col[r];
+                    col[r] = c0;
+                }
         }
-        const int p = __shfl(idx, 0, 64);
-        const double pv = __shfl(v, 0, 64);
-        if (!(pv > 0.0)) bad = 1;
-        if (lane == 0) gp[j] = p;
-        const int cend = min(n - 1, j + kKU + kKL);
-        if (p != j) {
-            for (int cc = j + lane; cc <= cend; cc += 64) {
-                const double t = AB_(j, cc);
-                AB_(j, cc) = AB_(p, cc);
-                AB_(p, cc) = t;
-            }
+        const double rp = 1.0 / col[0];
+        double m[kKL + 1];
+#pragma unroll
+        for (int r = 1; r <= kKL; r++) m[r] = col[r] * rp;
+        // final row j of U (lanes 0..16) and column j of L (lane 0)
+        if (lw && j + l < n) ab[(int64_t)j * kBandW + kKL + l] = W[0];
+        if (l == 0) {
+            gp[j] = j + pr;
+#pragma unroll
+            for (int r = 1; r <= kKL; r++)
+                if (j + r < n) ab[(int64_t)(j + r) * kBandW + kKL - r] = m[r];
         }
-        __syncthreads();
-        const double piv = AB_(j, j);
-        if (lane >= 1 && lane <= kKL && j + lane <= last) AB_(j + lane, j) = AB_(j + lane, j) / piv;
-        __syncthreads();
-        const int nr = last - j, nc = cend - j;
-        for (int e = lane; e < nr * nc; e += 64) {
-            const int i = j + 1 + e / nc, cc = j + 1 + e % nc;
-            AB_(i, cc) -= AB_(i, j) * AB_(j, cc);
-        }
-        __syncthreads();
+        // rank-1 update of the window's lower rows (lane 0's column is done)
+#pragma unroll
+        for (int r = 1; r <= kKL; r++) W[r] = fma(-m[r], W[0], W[r]);
+        // shift: lane l takes column j+1+l, rows j+1 .. j+1+kKL (lanes past the window hold
+        // zeros, which is what rows j+1 .. j+kKL of column j+1+kKL+kKU are: beyond the
+        // original upper bandwidth and untouched so far); the entering bottom row comes
+        // from the queue, refilled with the row needed kFacAhead shifts later
+#pragma unroll
+        for (int r = 0; r < kKL; r++) W[r] = __shfl_down(W[r + 1], 1, 64);
+        W[kKL] = Q[0];
+#pragma unroll
+        for (int q = 0; q + 1 < kFacAhead; q++) Q[q] = Q[q + 1];
+        Q[kFacAhead - 1] = at(j + 1 + kKL + kFacAhead, j + 1 + kFacAhead + l);
     }
-    for (int e = lane; e < n * kBandW; e += 64) gab[e] = ab[e];
-    if (lane == 0) flag[f] = bad;
+    if (l == 0) flag[f] = bad;
 }
+
 
 // One wave solves (L J0) x = L v for one filament, given the staged band `ab`
 // (reciprocal pivots on its diagonal), the pivot rows `ip` and its own LDS
@@ -1078,14 +1109,12 @@ int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const 
                      hipStream_t st) {
     if (d.M == 0) return FIL_OK;
     j0_band_assemble_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, bc, X, qc, Tint, tt, active, AB);
+    j0_band_factor_regs_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, active, AB, ipiv, flag);
     // filaments grouped by size so that each launch's LDS fits its own largest filament
     for (int k = 0; k < d.ncls; k++) {
         const int64_t coff = d.cls_off[k], cnt = d.cls_off[k + 1] - coff;
         if (cnt == 0) continue;
         const int nc = d.cls_n[k];
-        const size_t fl = (size_t)nc * kBandW * sizeof(double);
-        if (int rc = allow_lds(j0_band_factor_kernel, fl)) return rc;
-        j0_band_factor_kernel<<<(unsigned)cnt, 64, fl, st>>>(d, active, AB, ipiv, flag, coff);
         if (!AinvT) continue;
         // one thread per inverse column; a block's columns (64, 32 or 16, so that its
         // band, pivots and forward results fit in LDS) share the staged factor

@@ -114,7 +114,8 @@ def test_trajectory_parity(name, steps, j0_mode):
     for f in range(w.M):
         a, b = w.fil_off[f], w.fil_off[f + 1]
         gap = Y[a + 1:b] - Y[a:b - 1] - 0.5 * w.params["dL"] * (t[a:b - 1] + t[a + 1:b])
-        assert np.abs(gap).max() <= 1e-13 * w.params["dL"]
+        # met to rounding: a few ulps of the positions, which grow as the filament settles
+        assert np.abs(gap).max() <= 1e-13 * w.params["dL"] + 8 * np.finfo(float).eps * np.abs(Y).max()
 
 
 def test_trajectory_tight_tolerance():
