@@ -701,29 +701,7 @@ __global__ void __launch_bounds__(256) j0_band_assemble_kernel(SimDev d, BdfCoef
     }
 }
 
-// Copies n8 doubles (an even count, 16-byte aligned source) into LDS with 16
-// double2 loads in flight per lane; one wave.
-__device__ __forceinline__ void stage_band(const double* __restrict__ g, double* l, int n8, int lane) {
-    const double2* g2 = reinterpret_cast<const double2*>(g);
-    double2* l2 = reinterpret_cast<double2*>(l);
-    const int cnt = n8 / 2;
-    for (int base = 0; base < cnt; base += 64 * 16) {
-        double2 v[16];
-#pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const int idx = base + q * 64 + lane;
-            v[q] = g2[idx < cnt ? idx : cnt - 1];
-        }
-#pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const int idx = base + q * 64 + lane;
-            if (idx < cnt) l2[idx] = v[q];
-        }
-    }
-}
 
-// band element (i, j) of the LDS copy
-#define AB_(i, j) ab[(i) * kBandW + ((j) - (i) + kKL)]
 
 // LU with partial pivoting of every filament's banded system, one wave each, in a
 // register window: lane l holds column j + l (l <= kKL + kKU) of rows j .. j + kKL,
@@ -820,25 +798,34 @@ __global__ void __launch_bounds__(64) j0_band_factor_regs_kernel(SimDev d, const
 // The pending entries of each sweep live in a ring of lanes (entry i in lane
 // i mod 16, resp. mod 32), so a step is a few wave-uniform lane reads and one
 // fused update, with no barrier; every LDS read is issued one step ahead.
-__device__ __forceinline__ void band_sweeps(const double* ab, const int* ip, double* y, int n, int lane) {
+// Forward and backward sweeps of one banded LU solve by one wave, the solution
+// vector y in LDS and a ring of lanes holding the active rows (16 forward, 32
+// backward).  The band factor ab is read from global memory: each lane's
+// coefficient for the next kSweepAhead steps is already in flight (lane queue);
+// pivots ip and reciprocal diagonal rd are in LDS.
+constexpr int kSweepAhead = 6;
+__device__ __forceinline__ void band_sweeps(const double* __restrict__ ab, const int* ip, const double* rd, double* y,
+                                            int n, int lane) {
     double w = (lane < 16 && lane < n) ? y[lane] : 0.0;
     auto fwd_mult = [&](int jj) {
         const int off = (lane - (jj & 15)) & 15;
-        const int offc = off <= kKL ? off : kKL;
-        const int row = min(jj + offc, n - 1);
-        const double L = ab[row * kBandW + (kKL - offc)];
-        return (lane < 16 && off >= 1 && off <= kKL && jj + off < n) ? L : 0.0;
+        if (!(lane < 16 && off >= 1 && off <= kKL && jj + off < n)) return 0.0;
+        return ab[(int64_t)(jj + off) * kBandW + (kKL - off)];
     };
+    double Lq[kSweepAhead];
+#pragma unroll
+    for (int q = 0; q < kSweepAhead; q++) Lq[q] = fwd_mult(q);
     int ipn = ip[0];
-    double Ln = fwd_mult(0);
     double yin = y[min(16, n - 1)];
     for (int j = 0; j < n; j++) {
         const int h = j & 15;
         const int hp = __builtin_amdgcn_readfirstlane(ipn) & 15;
-        const double L = Ln;
+        const double L = Lq[0];
+#pragma unroll
+        for (int q = 0; q + 1 < kSweepAhead; q++) Lq[q] = Lq[q + 1];
+        Lq[kSweepAhead - 1] = fwd_mult(j + kSweepAhead);
         const double yi = j + 16 < n ? yin : 0.0;
         ipn = ip[min(j + 1, n - 1)];
-        Ln = fwd_mult(j + 1);
         yin = y[min(j + 17, n - 1)];
         const double vh = readlane_f64(w, h), vp = readlane_f64(w, hp);
         w = lane == hp ? vh : w;
@@ -854,19 +841,20 @@ __device__ __forceinline__ void band_sweeps(const double* ab, const int* ip, dou
     }
     auto bwd_coef = [&](int ii) {
         const int off = ((ii & 31) - lane) & 31;
-        const int offc = off <= kU ? off : kU;
-        const int row = max(ii - offc, 0);
-        const double U = ab[row * kBandW + (offc + kKL)];
-        return (lane < 32 && off >= 1 && off <= kU && ii - off >= 0) ? U : 0.0;
+        if (!(lane < 32 && off >= 1 && off <= kU && ii - off >= 0)) return 0.0;
+        return ab[(int64_t)(ii - off) * kBandW + (off + kKL)];
     };
-    double Un = bwd_coef(n - 1), dn = ab[(n - 1) * kBandW + kKL], zin = y[max(n - 33, 0)];
+    double Uq[kSweepAhead];
+#pragma unroll
+    for (int q = 0; q < kSweepAhead; q++) Uq[q] = bwd_coef(n - 1 - q);
+    double zin = y[max(n - 33, 0)];
     for (int i = n - 1; i >= 0; i--) {
         const int h = i & 31;
-        const double U = Un, dv = dn;
+        const double U = Uq[0], dv = rd[i];
+#pragma unroll
+        for (int q = 0; q + 1 < kSweepAhead; q++) Uq[q] = Uq[q + 1];
+        Uq[kSweepAhead - 1] = bwd_coef(i - kSweepAhead);
         const double zi = i - 32 >= 0 ? zin : 0.0;
-        const int i1 = max(i - 1, 0);
-        Un = bwd_coef(i1);
-        dn = ab[i1 * kBandW + kKL];
         zin = y[max(i - 33, 0)];
         const double xi = readlane_f64(w, h) * dv;
         w -= U * xi;  // U = 0 off the kKL + kKU entries above the head
@@ -892,45 +880,33 @@ __device__ __forceinline__ double diff_unit(int c, int i, int N) {
     return (3 + 3 * N + 3 * (m - 1) + a == c ? 1.0 : 0.0) - (prev == c ? 1.0 : 0.0);
 }
 
-// Stages a filament's factorised band and pivots into LDS (reciprocal pivots).
-__device__ __forceinline__ void stage_factor(const double* __restrict__ gab, const int32_t* __restrict__ gp,
-                                             double* ab, int* ip, int n) {
-    const int t = threadIdx.x, nt = blockDim.x;
-    if (nt == 64) stage_band(gab, ab, n * kBandW, t);
-    else
-        for (int e = t; e < n * kBandW; e += nt) ab[e] = gab[e];
-    for (int i = t; i < n; i += nt) ip[i] = gp[i];
-    __syncthreads();
-    for (int i = t; i < n; i += nt) ab[i * kBandW + kKL] = 1.0 / ab[i * kBandW + kKL];
-    __syncthreads();
-}
 
-// dynamic LDS layout of the solve kernels: band [nmax][kBandW] | ip [nmax] | y [waves][nmax]
-__host__ __device__ inline size_t band_lds_bytes(int nmax, int waves) {
-    return (size_t)nmax * kBandW * sizeof(double) + (((size_t)nmax * sizeof(int) + 15) & ~(size_t)15) +
-           (size_t)waves * nmax * sizeof(double);
-}
 
 // out = J0^{-1} v for every active filament, one wave each
 __global__ void __launch_bounds__(64) j0_band_solve_kernel(SimDev d, const double* __restrict__ AB,
                                                          const int32_t* __restrict__ ipiv,
                                                          const double* __restrict__ v,
                                                          const int32_t* __restrict__ active,
-                                                         double* __restrict__ out, int nmax, int64_t coff) {
-    const int64_t f = d.cls_fil[coff + blockIdx.x];
+                                                         double* __restrict__ out, int nmax) {
+    const int64_t f = blockIdx.x;
     if (!active[d.fil_susp[f]]) return;
-    extern __shared__ double lds[];
+    extern __shared__ double lds[];  // y [nmax] | rd [nmax] | ip [nmax]
     const int64_t s0 = d.seg_off[f];
     const int N = (int)(d.seg_off[f + 1] - s0);
     const int n = 6 * N;
-    double* ab = lds;
-    int* ip = reinterpret_cast<int*>(lds + (size_t)nmax * kBandW);
-    double* y = reinterpret_cast<double*>(reinterpret_cast<char*>(ip) + (((size_t)nmax * sizeof(int) + 15) & ~(size_t)15));
+    double* y = lds;
+    double* rd = lds + nmax;
+    int* ip = reinterpret_cast<int*>(lds + 2 * (size_t)nmax);
     const int lane = threadIdx.x;
     const double* vf = v + 6 * s0;
-    for (int i = lane; i < n; i += 64) y[i] = diff_rhs(vf, i, N);
-    stage_factor(AB + 6 * s0 * kBandW, ipiv + 6 * s0, ab, ip, n);
-    band_sweeps(ab, ip, y, n, lane);
+    const double* ab = AB + 6 * s0 * kBandW;
+    for (int i = lane; i < n; i += 64) {
+        y[i] = diff_rhs(vf, i, N);
+        rd[i] = 1.0 / ab[(int64_t)i * kBandW + kKL];
+        ip[i] = ipiv[6 * s0 + i];
+    }
+    __syncthreads();
+    band_sweeps(ab, ip, rd, y, n, lane);
     __syncthreads();
     for (int i = lane; i < n; i += 64) out[6 * s0 + slot_of(i / 3, N) + i % 3] = y[i];
 }
@@ -1086,7 +1062,6 @@ __global__ void __launch_bounds__(256) dense_matvec_kernel(SimDev d, const doubl
         __syncthreads();
     }
 }
-#undef AB_
 
 // Dynamic LDS beyond 64 KB has to be granted to a kernel (gfx950 has 160 KB per
 // workgroup); granted once per kernel, before any launch that is captured.
@@ -1143,14 +1118,9 @@ int j0_solve_launch(const SimDev& d, const double* AB, const int32_t* ipiv, cons
     if (AinvT) {
         dense_matvec_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, AinvT, v, active, out);
     } else {
-        for (int k = 0; k < d.ncls; k++) {
-            const int64_t coff = d.cls_off[k], cnt = d.cls_off[k + 1] - coff;
-            if (cnt == 0) continue;
-            const int nc = d.cls_n[k];
-            if (int rc = allow_lds(j0_band_solve_kernel, band_lds_bytes(nc, 1))) return rc;
-            j0_band_solve_kernel<<<(unsigned)cnt, 64, band_lds_bytes(nc, 1), st>>>(d, AB, ipiv, v, active, out, nc,
-                                                                                coff);
-        }
+        const int nmax = 6 * d.max_seg;
+        j0_band_solve_kernel<<<(unsigned)d.M, 64, (size_t)nmax * (2 * sizeof(double) + sizeof(int)), st>>>(
+            d, AB, ipiv, v, active, out, nmax);
     }
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
