@@ -28,7 +28,7 @@
 namespace fil {
 
 constexpr int kRpyBlock = 256;
-constexpr int kLdsSources = 256;  // source records staged in LDS per block on the small-size path
+constexpr int kMaxChunkSmall = 256;  // most sources per block on the small-size path (64 per wave)
 
 // ------------------------------------------------------------------ packing
 __global__ void __launch_bounds__(256) rpy_pack(int64_t S, int prec, const double* __restrict__ Y,
@@ -190,7 +190,9 @@ __device__ __forceinline__ void rpy_item_f64(int64_t base, int64_t S, int64_t Sg
                                              int64_t chunk, const double* __restrict__ pk,
                                              const double* __restrict__ Y, double a, double c, const RpyOut& out) {
     constexpr int kTgtPerBlock = kRpyBlock / WS;  // targets per j-slice
-    const int wave = threadIdx.x / 64;
+    // the wave index is made visibly wave-uniform so that the source range, the
+    // loop and the source addresses stay on the scalar unit
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int tid = WS == 1 ? (int)threadIdx.x : (int)(threadIdx.x % 64);
     int64_t m0 = (int64_t)k * chunk;
     int64_t m1 = min(S, m0 + chunk);
@@ -214,23 +216,7 @@ __device__ __forceinline__ void rpy_item_f64(int64_t base, int64_t S, int64_t Sg
         for (int i = 0; i < 3; i++)
             A[j].G[i] = A[j].R[i] = A[j].P[i] = A[j].Q[i] = A[j].U[i] = A[j].Hv[i] = A[j].Hw[i] = 0.0;
     }
-    if constexpr (WS > 1) {
-        // small sizes: the block's whole source chunk is copied to LDS with
-        // coalesced loads, and each wave reads its quarter from there
-        __shared__ double lsrc[kLdsSources * 16];
-        const int64_t cb0 = (int64_t)k * chunk, cb1 = min(S, cb0 + chunk);
-        const double* g = pk + 16 * (base + cb0);
-#pragma unroll 8
-        for (int64_t e = threadIdx.x; e < (cb1 - cb0) * 16; e += kRpyBlock) lsrc[e] = g[e];
-        __syncthreads();
-        for (int64_t m = m0; m < m1; ++m) {
-            const double* sp = lsrc + 16 * (m - cb0);
-            double cur[15];
-            for (int i = 0; i < 15; i++) cur[i] = sp[i];
-#pragma unroll
-            for (int j = 0; j < TPL; j++) rpy_pair_f64(y[j], cur, a, four_a2, two_a2, A[j]);
-        }
-    } else {
+    {
         // the next source record is requested before the current one is used, so
         // the scalar-load latency overlaps the pair arithmetic
         // (32-bit, wave-uniform loop arithmetic stays on the scalar unit)
@@ -354,7 +340,7 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
                                              int64_t chunk, const SrcF32* __restrict__ pk,
                                              const double* __restrict__ Y, double a, double c, const RpyOut& out) {
     constexpr int kTgtPerBlock = kRpyBlock / WS;
-    const int wave = threadIdx.x / 64;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int tid = WS == 1 ? (int)threadIdx.x : (int)(threadIdx.x % 64);
     int64_t m0 = (int64_t)k * chunk;
     int64_t m1 = min(S, m0 + chunk);
@@ -378,13 +364,6 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
         }
     }
     const SrcF32* src = pk + base;
-    if constexpr (WS > 1) {
-        __shared__ SrcF32 lsrc[kLdsSources];
-        const int64_t cb0 = (int64_t)k * chunk, cb1 = min(S, cb0 + chunk);
-        for (int64_t e = threadIdx.x; e < cb1 - cb0; e += kRpyBlock) lsrc[e] = src[cb0 + e];
-        __syncthreads();
-        src = lsrc - cb0;
-    }
     for (int64_t t0 = m0; t0 < m1; t0 += kF32Tile) {
         const int64_t t1 = min(m1, t0 + kF32Tile);
         float v[TPL][3], w[TPL][3];
@@ -499,10 +478,10 @@ RpyPlan rpy_plan(int64_t S, int prec) {
     if (S <= 0) return p;
     p.tb = ceil_div(S, (int64_t)(kRpyBlock / p.ws) * p.tpl);
     // aim for ~2048 workgroups (8 per CU); every wave gets >= 16 (small) or 64 sources;
-    // on the small path a block's chunk must fit the LDS staging buffer
+    // and on the small path no wave walks more than 64 sources
     int64_t K = ceil_div(2048, p.tb);
     K = std::min<int64_t>(K, std::max<int64_t>(1, S / (small ? 16 * p.ws : 64)));
-    if (small) K = std::max<int64_t>(K, ceil_div(S, kLdsSources));
+    if (small) K = std::max<int64_t>(K, ceil_div(S, kMaxChunkSmall));
     if (K >= 8) K = ceil_div(K, 8) * 8;
     p.chunk = ceil_div(S, K);
     p.K = (int)ceil_div(S, p.chunk);

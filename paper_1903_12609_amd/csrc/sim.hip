@@ -34,7 +34,7 @@ struct fil_sim {
     SimDev d{};
     double *Yj = nullptr, *Yjm1 = nullptr, *qj = nullptr, *Xj = nullptr, *Xjm1 = nullptr, *Xjm2 = nullptr;
     double* X0p = nullptr;  // extrapolated first iterate of the last step (the plain warm start)
-    double *X = nullptr, *f = nullptr, *fprev = nullptr, *h = nullptr, *g0 = nullptr;
+    double *X = nullptr, *f = nullptr, *fprev = nullptr;
     double *Yc = nullptr, *qc = nullptr, *F = nullptr, *T = nullptr, *V = nullptr, *W = nullptr;
     double *AB = nullptr, *AinvT = nullptr, *Chist = nullptr, *Dhist = nullptr, *part = nullptr;
     double* box = nullptr;
@@ -61,8 +61,11 @@ struct fil_sim {
     hipStream_t cap_st = nullptr;  // private stream the blocks are captured on (launches go to st)
     std::map<std::array<int, 5>, GraphEntry> graphs;
     int32_t *jlog_d = nullptr, *jlog_h = nullptr;  // [nsusp][4] state, iters, applies, FP64 applies
-    unsigned int* ticket_d = nullptr;              // last-workgroup counter of the fused convergence test
     double *jlast_d = nullptr, *jlast_h = nullptr;
+    // two host slots for the logs of graph blocks in flight, each with its copy's event
+    int32_t* jlog_slot[2] = {nullptr, nullptr};
+    double* jlast_slot[2] = {nullptr, nullptr};
+    hipEvent_t log_ev[2] = {nullptr, nullptr};
     // learned warm start
     fil_mlp* mlp = nullptr;
     bool use_mlp = false;
@@ -153,6 +156,8 @@ int collect_timing(fil_sim* s) {
 void free_sim(fil_sim* s) {
     if (!s) return;
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->log_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto& kv : s->graphs)
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
@@ -186,11 +191,14 @@ int set_time(fil_sim* s) {
     return FIL_OK;
 }
 
-// f = f(X) for the active suspensions; resbits receives max|f| per suspension.
-// e0/e1 (may be null) bracket the mobility pair kernel.
-int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipEvent_t e1,
-                  const JudgeArgs* judge = nullptr) {
-    TRY(state_forces_launch(s->d, X, s->qj, s->time_d, s->active_d, s->Yc, s->qc, s->F, s->T, s->box, s->st));
+// f = f(X) for the active suspensions: the state at X first when `state` (else the
+// update kernel left it), then the steric pass, the mobility apply and the residual
+// kernel, which also leaves the dot products of Broyden update dots_k (< 0: none).
+// resbits receives max|f| per suspension; e0/e1 (may be null) bracket the mobility
+// pair kernel.
+int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipEvent_t e1, bool state, int dots_k) {
+    if (state)
+        TRY(state_forces_launch(s->d, X, s->qj, s->time_d, s->active_d, s->Yc, s->qc, s->F, s->T, s->box, s->st));
     // the source records sit at the start of the mobility workspace in both plans
     const int c = s->cur;
     TRY(steric_pack_launch(s->d, s->Yc, s->box, s->active_d, s->F, s->T, c ? FIL_PREC_F32TILE : FIL_PREC_F64,
@@ -210,10 +218,16 @@ int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipE
         }
     }
     s->rb ^= 1;
+    const DotArgs da{dots_k, s->Dhist, s->fprev, s->part};
     TRY(residual_launch(s->d, s->bc, X, s->Xj, s->Yc, s->Yj, s->Yjm1, s->V, s->W, part, K, s->active_d, fout,
-                        s->resbits_d + 2 * s->rb * s->nsusp, s->resbits_d + 2 * (1 - s->rb) * s->nsusp, s->st,
-                        judge));
+                        s->resbits_d + 2 * s->rb * s->nsusp, s->resbits_d + 2 * (1 - s->rb) * s->nsusp, da, s->st));
     return FIL_OK;
+}
+
+// Broyden update k (k < 0: the first step) from the residual fnew, then the state at the new X
+UpdateArgs update_args(fil_sim* s, int k, const double* fnew, double* dXout) {
+    return UpdateArgs{k,        s->AB,    s->ipiv, s->AinvT, s->part, s->Chist, s->Dhist, fnew, s->fprev,
+                      s->X,     dXout,    s->qj,   s->time_d, s->Yc,  s->qc,    s->F,     s->T, s->box};
 }
 
 // max|f|/a and max|b dt (V, dexpinv Omega)| per suspension of the last evaluation
@@ -241,20 +255,18 @@ int upload_flags(fil_sim* s, int32_t* dst, const int32_t* src) {
     return FIL_OK;
 }
 
-// J0 at the configuration of X (state buffers already filled by eval_residual),
-// factorised; h = J0^{-1} f.
-int begin_solve(fil_sim* s, double* dXout) {
+// J0 at the configuration of X (state buffers already filled by eval_residual), factorised
+// (and inverted explicitly when the inverses fit)
+int begin_solve(fil_sim* s) {
     const double tt = s->t + s->p.dt;
     TRY(j0_factor_launch(s->d, s->bc, s->X, s->qc, s->T, tt, s->active_d, s->AB, s->ipiv, s->jflag_d, s->AinvT,
                          s->st));
-    TRY(j0_solve_launch(s->d, s->AB, s->ipiv, s->AinvT, s->f, s->active_d, s->h, s->st));
     s->k = 0;
     return FIL_OK;
 }
 
-
 // Iterations it0 .. it0+U-1 (evaluation, device-side convergence test, bad-Broyden
-// update with k = it-1) as one HIP graph, captured on first use for this
+// update with k = it-1 and the state at the new iterate) as one HIP graph, captured on first use for this
 // (it0, U, precision, resbits parity, first-step coefficients) and replayed on
 // the simulation's stream.  The captured work holds no memset, no host copy and
 // no timing event (the mobility kernel is timed only in host-driven iterations).
@@ -274,12 +286,10 @@ int capture_block(fil_sim* s, int it0, int U, GraphEntry& g) {
     int rc = FIL_OK;
     for (int i = 0; i < U && rc == FIL_OK; i++) {
         const int it = it0 + i;
-        JudgeArgs jg{s->ticket_d, s->active_d, s->jlog_d, s->jlast_d, s->p.tol, 1.0 / s->p.a, it, s->p.kmax,
-                     s->cur == 0 ? 1 : 0};
-        rc = eval_residual(s, s->X, s->f, nullptr, nullptr, &jg);
-        if (rc == FIL_OK)
-            rc = broyden_update_launch(s->d, it - 1, s->AB, s->ipiv, s->AinvT, s->Chist, s->Dhist, s->f, s->fprev,
-                                       s->g0, s->h, s->part, s->X, nullptr, s->active_d, s->st);
+        rc = eval_residual(s, s->X, s->f, nullptr, nullptr, false, it - 1);
+        const JudgeArgs jg{s->jlog_d, s->jlast_d, s->resbits_d + 2 * s->rb * ns, nullptr, s->p.tol, 1.0 / s->p.a,
+                           it,        s->p.kmax, s->cur == 0 ? 1 : 0};
+        if (rc == FIL_OK) rc = broyden_state_launch(s->d, update_args(s, it - 1, s->f, nullptr), jg, s->active_d, s->st);
     }
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(s->st, &graph);
@@ -322,11 +332,54 @@ struct SolveLog {
     explicit SolveLog(int64_t ns) : state(ns, 0), iters(ns, 0), applies(ns, 0), applies_hi(ns, 0), last(ns, 0.0) {}
 };
 
+// Graph blocks from iteration `it` until every suspension has ended (the device log
+// holds the counts so far).  The next block is launched before the log of the
+// previous one is read, so the GPU never waits for the host; a block launched after
+// the end runs only kernels that find their suspension finished.
+int device_iterations(fil_sim* s, SolveLog& L, int it) {
+    const int64_t ns = s->nsusp;
+    int pending = 0, wslot = 0, rslot = 0;
+    for (;;) {
+        while (pending < 2 && it <= s->p.kmax) {
+            const int U = std::min(s->graph_iters, s->p.kmax - it + 1);
+            TRY(graph_block(s, it, U));
+            it += U;
+            s->k += U;
+            FIL_HIP_TRY(hipMemcpyAsync(s->jlog_slot[wslot], s->jlog_d, 4 * ns * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                       s->st));
+            FIL_HIP_TRY(hipMemcpyAsync(s->jlast_slot[wslot], s->jlast_d, ns * sizeof(double), hipMemcpyDeviceToHost,
+                                       s->st));
+            FIL_HIP_TRY(hipEventRecord(s->log_ev[wslot], s->st));
+            wslot ^= 1;
+            pending++;
+        }
+        if (pending == 0) break;  // every iteration up to kmax has run (its test failed what was left)
+        FIL_HIP_TRY(hipEventSynchronize(s->log_ev[rslot]));
+        bool any = false;
+        for (int64_t i = 0; i < ns; i++) {
+            const int32_t* q = s->jlog_slot[rslot] + 4 * i;
+            L.state[i] = q[0];
+            L.iters[i] = q[1];
+            L.applies[i] = q[2];
+            L.applies_hi[i] = q[3];
+            L.last[i] = s->jlast_slot[rslot][i];
+            s->active_h[i] = q[0] == 0;
+            any |= q[0] == 0;
+        }
+        rslot ^= 1;
+        pending--;
+        if (!any) break;
+    }
+    return FIL_OK;
+}
+
 // Alg. 2 from the iterate in s->X for every active suspension: f_0 = f(X_0), J0
 // at X_0 and its inverse, X_1 = X_0 - J0^{-1} f_0, then one evaluation and one
 // bad-Broyden update per iteration until every suspension has converged or failed.
-// In FP32-tile mode the evaluations start in FP32 and switch to FP64 once every
-// running suspension is near the tolerance or near the FP32 rounding floor;
+// FP64 iterations run in captured graph blocks when enabled, with every test on the
+// device (the first one included) and no host round trip between blocks.  In
+// FP32-tile mode the evaluations start in FP32, host-driven, and switch to FP64 once
+// every running suspension is near the tolerance or near the FP32 rounding floor;
 // only an FP64 residual can end a step.
 int solve(fil_sim* s, SolveLog& L) {
     const int64_t ns = s->nsusp;
@@ -360,33 +413,48 @@ int solve(fil_sim* s, SolveLog& L) {
         if (s->cur == 1 && any && (near || 2 * it >= s->p.kmax)) s->cur = 0;
         return any;
     };
+    auto singular = [&]() {
+        for (int64_t f = 0; f < s->M; f++)
+            if (s->jflag_h[f]) {
+                set_error("fil_bdf2_step: approximate Jacobian block of filament " + std::to_string(f) + " is singular");
+                std::fill(L.state.begin(), L.state.end(), -1);
+                L.singular = true;
+                return true;
+            }
+        return false;
+    };
     hipEvent_t e0, e1;
-    count();
     TRY(pool_events(s, &e0, &e1));
-    TRY(eval_residual(s, s->X, s->f, e0, e1));
-    TRY(begin_solve(s, nullptr));
+    TRY(eval_residual(s, s->X, s->f, e0, e1, true, -1));
+    TRY(begin_solve(s));
+    if (s->graph_iters > 0 && s->cur == 0) {
+        // the first test runs in the first-step kernel; the log starts empty
+        FIL_HIP_TRY(hipMemsetAsync(s->jlog_d, 0, 4 * ns * sizeof(int32_t), s->st));
+        FIL_HIP_TRY(hipMemsetAsync(s->jlast_d, 0, ns * sizeof(double), s->st));
+        const JudgeArgs jg{s->jlog_d, s->jlast_d, s->resbits_d + 2 * s->rb * ns, s->jflag_d, s->p.tol, 1.0 / s->p.a,
+                           0,         s->p.kmax, 1};
+        TRY(broyden_state_launch(s->d, update_args(s, -1, s->f, nullptr), jg, s->active_d, s->st));
+        FIL_HIP_TRY(hipMemcpyAsync(s->jflag_h, s->jflag_d, s->M * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+        TRY(device_iterations(s, L, 1));
+        if (singular())
+            for (int64_t i = 0; i < ns; i++) s->active_h[i] = 0;
+        return FIL_OK;
+    }
+    count();
     TRY(read_resid(s, res, &vmx));
     FIL_HIP_TRY(hipMemcpyAsync(s->jflag_h, s->jflag_d, s->M * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
     FIL_HIP_TRY(hipStreamSynchronize(s->st));
     bool any = judge(0);
-    for (int64_t f = 0; f < s->M; f++)
-        if (s->jflag_h[f]) {
-            set_error("fil_bdf2_step: approximate Jacobian block of filament " + std::to_string(f) + " is singular");
-            for (int64_t i = 0; i < ns; i++) s->active_h[i] = 0;
-            std::fill(L.state.begin(), L.state.end(), -1);
-            L.singular = true;
-            changed = true;
-            any = false;
-            break;
-        }
+    if (singular()) {
+        for (int64_t i = 0; i < ns; i++) s->active_h[i] = 0;
+        changed = true;
+        any = false;
+    }
     if (changed) TRY(upload_flags(s, s->active_d, s->active_h));
-    if (any) TRY(first_step_launch(s->d, s->h, s->f, s->fprev, s->X, nullptr, s->active_d, s->st));
-    // FP64 iterations run in captured graph blocks when enabled; FP32-tile
-    // iterations stay host-driven so the precision switch happens at the same
-    // iteration either way
+    if (any) TRY(broyden_state_launch(s->d, update_args(s, -1, s->f, nullptr), JudgeArgs{}, s->active_d, s->st));
     for (int it = 1; any;) {
         if (s->graph_iters > 0 && s->cur == 0) {
-            // device-side iterations: the log starts from the host's counts
+            // FP32 iterations are done: the device continues from the host's counts
             for (int64_t i = 0; i < ns; i++) {
                 int32_t* g = s->jlog_h + 4 * i;
                 g[0] = L.state[i];
@@ -397,39 +465,17 @@ int solve(fil_sim* s, SolveLog& L) {
             }
             FIL_HIP_TRY(hipMemcpyAsync(s->jlog_d, s->jlog_h, 4 * ns * sizeof(int32_t), hipMemcpyHostToDevice, s->st));
             FIL_HIP_TRY(hipMemcpyAsync(s->jlast_d, s->jlast_h, ns * sizeof(double), hipMemcpyHostToDevice, s->st));
-            while (any) {
-                const int U = std::min(s->graph_iters, s->p.kmax - it + 1);
-                TRY(graph_block(s, it, U));
-                // the rb parity a block ends on is part of its key, so it is tracked across blocks
-                FIL_HIP_TRY(hipMemcpyAsync(s->jlog_h, s->jlog_d, 4 * ns * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
-                FIL_HIP_TRY(hipMemcpyAsync(s->jlast_h, s->jlast_d, ns * sizeof(double), hipMemcpyDeviceToHost, s->st));
-                FIL_HIP_TRY(hipStreamSynchronize(s->st));
-                any = false;
-                for (int64_t i = 0; i < ns; i++) {
-                    const int32_t* q = s->jlog_h + 4 * i;
-                    L.state[i] = q[0];
-                    L.iters[i] = q[1];
-                    L.applies[i] = q[2];
-                    L.applies_hi[i] = q[3];
-                    L.last[i] = s->jlast_h[i];
-                    s->active_h[i] = q[0] == 0;
-                    any |= q[0] == 0;
-                }
-                it += U;
-                s->k += U;
-            }
-            return FIL_OK;
+            return device_iterations(s, L, it);
         }
         count();
         TRY(pool_events(s, &e0, &e1));
-        TRY(eval_residual(s, s->X, s->f, e0, e1));
+        TRY(eval_residual(s, s->X, s->f, e0, e1, false, s->k));
         TRY(read_resid(s, res, &vmx));
         changed = false;
         any = judge(it);
         if (!any) break;
         if (changed) TRY(upload_flags(s, s->active_d, s->active_h));
-        TRY(broyden_update_launch(s->d, s->k, s->AB, s->ipiv, s->AinvT, s->Chist, s->Dhist, s->f, s->fprev, s->g0,
-                                  s->h, s->part, s->X, nullptr, s->active_d, s->st));
+        TRY(broyden_state_launch(s->d, update_args(s, s->k, s->f, nullptr), JudgeArgs{}, s->active_d, s->st));
         s->k++;
         it++;
     }
@@ -524,25 +570,13 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         dense_tot += 36 * N * N;
     }
     const bool dense = p->j0_mode == 2 || (p->j0_mode == 0 && (size_t)dense_tot * sizeof(double) <= kDenseInvBytes);
-    std::vector<int64_t> vblk_start, susp_vblk_off(nsusp + 1);
-    std::vector<int32_t> vblk_susp;
     std::vector<int64_t> sfo(susp_fil_off, susp_fil_off + nsusp + 1);
-    for (int64_t i = 0; i < nsusp; i++) {
-        susp_vblk_off[i] = (int64_t)vblk_susp.size();
-        for (int64_t e = 6 * susp_seg_off[i]; e < 6 * susp_seg_off[i + 1]; e += kVecBlock) {
-            vblk_start.push_back(e);
-            vblk_susp.push_back((int32_t)i);
-        }
-    }
-    susp_vblk_off[nsusp] = (int64_t)vblk_susp.size();
-    const int64_t nvblk = (int64_t)vblk_susp.size();
-    vblk_start.push_back(6 * S);
     s->susp_seg_off = susp_seg_off;
 
     // ---- device allocations
     int rc = FIL_OK;
-    int64_t *d_seg_off, *d_susp_seg_off, *d_susp_fil_off, *d_vblk_start, *d_susp_vblk_off, *d_dense_off = nullptr;
-    int32_t *d_fil_susp, *d_seg_fil, *d_teth, *d_vblk_susp, *d_cls_fil;
+    int64_t *d_seg_off, *d_susp_seg_off, *d_susp_fil_off, *d_dense_off = nullptr;
+    int32_t *d_fil_susp, *d_seg_fil, *d_teth, *d_cls_fil;
     // size classes of the filaments
     const int cls_bound[kMaxCls] = {16, 24, 32, 40, 48, kMaxSeg};
     std::vector<int32_t> cls_fil;
@@ -566,18 +600,17 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     const int max_dots = p->kmax + 2;
 #define A(ptr, n)                                  \
     if (rc == FIL_OK) rc = dalloc(s, &(ptr), (n));
-    A(d_seg_off, M + 1) A(d_susp_seg_off, nsusp + 1) A(d_susp_fil_off, nsusp + 1) A(d_vblk_start, nvblk + 1)
-    A(d_susp_vblk_off, nsusp + 1) A(d_fil_susp, M) A(d_seg_fil, S) A(d_teth, M) A(d_vblk_susp, nvblk) A(d_cls_fil, M)
+    A(d_seg_off, M + 1) A(d_susp_seg_off, nsusp + 1) A(d_susp_fil_off, nsusp + 1)
+    A(d_fil_susp, M) A(d_seg_fil, S) A(d_teth, M) A(d_cls_fil, M)
     A(d_base, 3 * M)
     if (phase) A(d_phase, M)
     A(s->Yj, 3 * S) A(s->Yjm1, 3 * S) A(s->qj, 4 * S) A(s->Xj, n6) A(s->Xjm1, n6) A(s->Xjm2, n6) A(s->X0p, n6)
-    A(s->X, n6) A(s->f, n6) A(s->fprev, n6) A(s->h, n6) A(s->g0, n6)
+    A(s->X, n6) A(s->f, n6) A(s->fprev, n6)
     A(s->Yc, 3 * S) A(s->qc, 4 * S) A(s->F, 3 * S) A(s->T, 3 * S) A(s->V, 3 * S) A(s->W, 3 * S)
     A(s->AB, n6 * kBandW) A(s->ipiv, n6)
     if (dense) { A(s->AinvT, dense_tot) A(d_dense_off, M) }
-    A(s->Chist, (size_t)p->kmax * n6) A(s->Dhist, (size_t)p->kmax * n6) A(s->part, (size_t)nvblk * max_dots)
+    A(s->Chist, (size_t)p->kmax * n6) A(s->Dhist, (size_t)p->kmax * n6) A(s->part, (size_t)M * max_dots)
     A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->time_d, 1) A(s->jlog_d, 4 * nsusp) A(s->jlast_d, nsusp)
-    A(s->ticket_d, 1)
     A(s->active_d, nsusp) A(s->commit_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 4 * nsusp)
 #undef A
     if (rc == FIL_OK) rc = halloc(s, &s->active_h, nsusp);
@@ -587,6 +620,14 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     if (rc == FIL_OK) rc = halloc(s, &s->time_h, 1);
     if (rc == FIL_OK) rc = halloc(s, &s->jlog_h, 4 * nsusp);
     if (rc == FIL_OK) rc = halloc(s, &s->jlast_h, nsusp);
+    for (int i = 0; i < 2; i++) {
+        if (rc == FIL_OK) rc = halloc(s, &s->jlog_slot[i], 4 * nsusp);
+        if (rc == FIL_OK) rc = halloc(s, &s->jlast_slot[i], nsusp);
+        if (rc == FIL_OK && hipEventCreateWithFlags(&s->log_ev[i], hipEventDisableTiming) != hipSuccess) {
+            set_error("fil_create: event creation failed");
+            rc = FIL_EHIP;
+        }
+    }
     if (rc) {
         free_sim(s);
         return rc;
@@ -632,12 +673,9 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         TRY(upload(d_susp_seg_off, susp_seg_off));
         TRY(upload(d_susp_fil_off, sfo));
         if (dense) TRY(upload(d_dense_off, dense_off));
-        TRY(upload(d_vblk_start, vblk_start));
-        TRY(upload(d_susp_vblk_off, susp_vblk_off));
         TRY(upload(d_fil_susp, fil_susp));
         TRY(upload(d_seg_fil, seg_fil));
         TRY(upload(d_teth, teth));
-        TRY(upload(d_vblk_susp, vblk_susp));
         TRY(upload(d_cls_fil, cls_fil));
         TRY(upload(d_base, base));
         if (phase) TRY(upload(d_phase, std::vector<double>(phase, phase + M)));
@@ -647,7 +685,6 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         TRY(upload(s->Xj, zeros));
         TRY(upload(s->Xjm1, zeros));
         TRY(upload(s->Xjm2, zeros));
-        TRY(upload(s->ticket_d, std::vector<unsigned int>(1, 0u)));
         TRY(upload(s->X0p, zeros));
         TRY(upload(s->X, zeros));
         TRY(upload(s->resbits_d, std::vector<unsigned long long>(4 * nsusp, 0ull)));
@@ -675,10 +712,6 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     d.susp_fil_off = d_susp_fil_off;
     d.dense_off = d_dense_off;
     d.max_seg = max_seg;
-    d.nvblk = nvblk;
-    d.vblk_susp = d_vblk_susp;
-    d.vblk_start = d_vblk_start;
-    d.susp_vblk_off = d_susp_vblk_off;
     d.max_dots = max_dots;
     d.a = p->a;
     d.eta = p->eta;
@@ -869,7 +902,7 @@ int fil_residual(fil_sim* s, const double* X, double* f_out) {
     TRY(set_time(s));
     hipEvent_t e0, e1;
     TRY(pool_events(s, &e0, &e1));
-    return eval_residual(s, X, f_out, e0, e1);
+    return eval_residual(s, X, f_out, e0, e1, true, -1);
 }
 
 int fil_broyden_begin(fil_sim* s, const double* X0, double* f0_out) {
@@ -881,18 +914,18 @@ int fil_broyden_begin(fil_sim* s, const double* X0, double* f0_out) {
     TRY(set_time(s));
     hipEvent_t e0, e1;
     TRY(pool_events(s, &e0, &e1));
-    TRY(eval_residual(s, s->X, s->f, e0, e1));
-    TRY(begin_solve(s, nullptr));
+    TRY(eval_residual(s, s->X, s->f, e0, e1, true, -1));
+    TRY(begin_solve(s));
     if (f0_out) FIL_HIP_TRY(hipMemcpyAsync(f0_out, s->f, 6 * s->S * sizeof(double), hipMemcpyDeviceToDevice, s->st));
-    TRY(first_step_launch(s->d, s->h, s->f, s->fprev, s->X, nullptr, s->active_d, s->st));
+    TRY(broyden_state_launch(s->d, update_args(s, -1, s->f, nullptr), JudgeArgs{}, s->active_d, s->st));
     return FIL_OK;
 }
 
 int fil_broyden_update(fil_sim* s, const double* f_new, double* dX_out) {
     FIL_CHECK_ARG(s && f_new, "fil_broyden_update: null argument");
     FIL_CHECK_ARG(s->k + 1 < s->p.kmax, "fil_broyden_update: history full (kmax updates)");
-    TRY(broyden_update_launch(s->d, s->k, s->AB, s->ipiv, s->AinvT, s->Chist, s->Dhist, f_new, s->fprev, s->g0, s->h,
-                              s->part, s->X, dX_out, s->active_d, s->st));
+    TRY(update_dots_launch(s->d, f_new, s->active_d, DotArgs{s->k, s->Dhist, s->fprev, s->part}, s->st));
+    TRY(broyden_state_launch(s->d, update_args(s, s->k, f_new, dX_out), JudgeArgs{}, s->active_d, s->st));
     s->k++;
     return FIL_OK;
 }

@@ -11,12 +11,9 @@ constexpr int kBandW = 2 * kKL + kKU + 1;
 constexpr size_t kDenseInvBytes = size_t(64) << 20;  // explicit J0^{-1} used up to this total size
 constexpr int kMaxIter = 256;     // Broyden history capacity
 constexpr int kMaxDots = kMaxIter + 2;
-constexpr int kVecBlock = 256;    // residual-vector elements per Broyden vector block
-constexpr int kSpar = 5;
-constexpr int kResSeg = 64;
-constexpr int kFusedJudgeBlocks = 64;  // residual grids up to this size run the convergence test themselves
+constexpr int kSpar = 5;          // per-suspension parameters: dt, gravity force (3), F^S
 constexpr int kMaxCls = 6;        // filament size classes: N <= 16, 24, 32, 40, 48, 64
-constexpr int kStericWaves = 4;   // waves per filament in the steric pass       // segments per residual workgroup (six waves sum the partials)          // per-suspension parameters: dt, gravity force (3), F^S
+constexpr int kStericWaves = 4;   // waves per filament in the steric pass
 
 // BDF coefficients: y - a1 y^j - a2 y^{j-1} - b dt v = 0, u - g u^j - b dt dexpinv(Omega) = 0
 struct BdfCoef {
@@ -36,12 +33,7 @@ struct SimDev {
     const int64_t* susp_fil_off;   // [nsusp+1]
     const int64_t* dense_off;      // [M] offsets of the explicit inverses, or null
     int max_seg;                   // largest filament
-    // vector blocks over the 6S unknowns (never straddling suspensions)
-    int64_t nvblk;
-    const int32_t* vblk_susp;      // [nvblk]
-    const int64_t* vblk_start;     // [nvblk+1]
-    const int64_t* susp_vblk_off;  // [nsusp+1]
-    int max_dots;
+    int max_dots;                  // dot products per Broyden update at most (kmax + 2)
     const double* spar;            // [nsusp][5] per suspension: dt, gravity force (3), steric strength F^S
     // filaments by size class (for launches whose LDS scales with 6N): class k holds
     // cls_fil[cls_off[k] .. cls_off[k+1]), all with 6N <= cls_n[k]
@@ -59,24 +51,54 @@ int state_forces_launch(const SimDev& d, const double* X, const double* qj, cons
 // adds the steric barrier into F and writes the mobility source records (precision prec)
 int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, const int32_t* active, double* F,
                        const double* T, int prec, void* pk, hipStream_t st);
-// device-side convergence test fused into the residual kernel (graph-captured iterations)
-struct JudgeArgs {
-    unsigned int* ticket;  // zero-initialised counter; null: no test
-    int32_t* active;       // per suspension, cleared when it ends
-    int32_t* log;          // [nsusp][4] state (0 running, 1 converged, -1 failed), last iteration, evaluations,
-                           // FP64 evaluations
-    double* last;          // [nsusp] max|f|/a of the last evaluation
-    double tol, inv_a;
-    int it, kmax, can_converge;
+// Dot products of Broyden update k (k < 0: none): per filament f, dpart[f][h] holds
+// its share of h < k: d_h . f;  h = k: |f - fprev|^2;  h = k+1: (f - fprev) . f
+struct DotArgs {
+    int k;
+    const double* Dhist;  // [kmax][6S]
+    const double* fprev;  // [6S]
+    double* dpart;        // [M][max_dots]
 };
-
 // residual rows; max|f| per suspension into resbits[0, nsusp) and max|b dt (V, dexpinv Omega)| into
 // resbits[nsusp, 2 nsusp) (zeroed by the previous call, which also zeroes resbits_next);
-// velocities from the K mobility partials `part` when non-null (then also stored to V, W), else from V, W
+// velocities from the K mobility partials `part` when non-null (then also stored to V, W), else from V, W;
+// and the dot products of update da.k
 int residual_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* Xj, const double* Yc,
                     const double* Yj, const double* Yjm1, double* V, double* W, const double* part, int K,
                     const int32_t* active, double* f, unsigned long long* resbits, unsigned long long* resbits_next,
-                    hipStream_t st, const JudgeArgs* judge = nullptr);
+                    const DotArgs& da, hipStream_t st);
+// the same dot products for a residual given by the caller
+int update_dots_launch(const SimDev& d, const double* fnew, const int32_t* active, const DotArgs& da,
+                       hipStream_t st);
+// Convergence test of the evaluation just made, for iterations that run without the host
+// (captured in a graph).  log null: no test.
+struct JudgeArgs {
+    int32_t* log;   // [nsusp][4] state (0 running, 1 converged, -1 failed), last iteration, evaluations,
+                    // FP64 evaluations
+    double* last;   // [nsusp] max|f|/a of the last evaluation
+    const unsigned long long* resbits;  // the maxima that evaluation left
+    const int32_t* jflag;  // [M] singular-J0 flags (first step only; null: not checked): fail the suspension
+    double tol, inv_a;
+    int it, kmax, can_converge;
+};
+// Broyden update k (k < 0: first step X <- X - J0^{-1} f) and the state at the new X
+struct UpdateArgs {
+    int k;
+    const double* AB;      // band factor (used when AinvT is null)
+    const int32_t* ipiv;
+    const double* AinvT;   // explicit inverses, or null
+    const double* dpart;   // partial dot products of update k
+    double* Chist;         // [kmax][6S]
+    double* Dhist;
+    const double* fnew;    // residual at the current iterate
+    double* fprev;         // <- fnew
+    double* X;             // <- X - step
+    double* dXout;         // -step, or null
+    const double* qj;      // state at the new X, as state_forces_launch
+    const double* tt;
+    double *Yc, *qc, *F, *T, *box;
+};
+int broyden_state_launch(const SimDev& d, const UpdateArgs& u, const JudgeArgs& jg, int32_t* active, hipStream_t st);
 int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const double* Yjm1, const double* Xj,
                          const double* Xjm1, const int32_t* active, double* X0, hipStream_t st);
 // J0 at X in row-differenced banded form (6N x kBandW per filament at 6*seg_off[f]*kBandW),
@@ -85,14 +107,6 @@ int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const 
 int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* qc, const double* Tint,
                      double tt, const int32_t* active, double* AB, int32_t* ipiv, int32_t* flag, double* AinvT,
                      hipStream_t st);
-// out = J0^{-1} v: dense product when AinvT is non-null, else the banded sweeps
-int j0_solve_launch(const SimDev& d, const double* AB, const int32_t* ipiv, const double* AinvT, const double* v,
-                    const int32_t* active, double* out, hipStream_t st);
-int broyden_update_launch(const SimDev& d, int k, const double* AB, const int32_t* ipiv, const double* AinvT,
-                          double* Chist, double* Dhist, const double* fnew, double* fprev, double* g0, double* hvec,
-                          double* part, double* X, double* dXout, const int32_t* active, hipStream_t st);
-int first_step_launch(const SimDev& d, const double* h, const double* f, double* fprev, double* X, double* dXout,
-                      const int32_t* active, hipStream_t st);
 // commits the step: Y, q from the converged state; X history shifted (Xjm2 may be null)
 int finalize_launch(const SimDev& d, const int32_t* commit, const double* Yc, const double* qc, const double* X,
                     double* Yj, double* Yjm1, double* qj, double* Xj, double* Xjm1, double* Xjm2, hipStream_t st);

@@ -50,24 +50,24 @@ __device__ __forceinline__ V3 joint_kappa(const SimDev& d, int64_t f, int64_t k,
 }
 
 // ---------------------------------------------------------------- state + forces
-// One 64-lane workgroup per filament: q_n = exp(u_n) . q^j_n, t_n, robot-arm
-// positions, then F = F^C + gravity (+ lambda_1), T = T^C + T^E (+ lambda_2).
-__global__ void __launch_bounds__(64) state_forces_kernel(SimDev d, const double* __restrict__ X,
-                                                        const double* __restrict__ qj, const double* __restrict__ ttp,
-                                                        const int32_t* __restrict__ active,
-                                                        double* __restrict__ Yc, double* __restrict__ qc,
-                                                        double* __restrict__ F, double* __restrict__ T,
-                                                        double* __restrict__ box) {
-    const double tt = *ttp;  // t^{j+1}, read on the device so captured launches stay valid
-    const int64_t f = blockIdx.x;
-    if (!active[d.fil_susp[f]]) return;
+// Filament f's configuration from its unknowns Xf (global memory or LDS):
+// q_n = exp(u_n) q^j_n, t_n, robot-arm positions Y_n = Y_1 + dL/2 sum_{m<n} (t_m + t_{m+1})
+// and the filament's bounding box, then F = F^C + gravity (+ lambda_1),
+// T = T^C + T^E (+ lambda_2).  Every thread of the workgroup calls it (it holds a
+// barrier); lane n of the first wave owns segment n (N <= 64).  Nothing may follow
+// it in the caller that needs a barrier.
+__device__ void filament_state(const SimDev& d, int64_t f, const double* Xf, const double* __restrict__ qj,
+                               double tt, double* __restrict__ Yc, double* __restrict__ qc, double* __restrict__ F,
+                               double* __restrict__ T, double* __restrict__ box) {
     const int64_t S = d.S;
-    const int64_t s0 = d.seg_off[f], N = d.seg_off[f + 1] - s0;
+    const int64_t s0 = d.seg_off[f];
+    const int N = (int)(d.seg_off[f + 1] - s0);
     const int teth = d.tether[f];
-    const double* Xf = X + 6 * s0;
     __shared__ double sq[kMaxSeg][4];
     __shared__ double st[kMaxSeg][3];
-    for (int64_t n = threadIdx.x; n < N; n += 64) {
+    const int n = threadIdx.x;
+    const bool seg = n < N;
+    if (seg) {
         V3 u = ldx(Xf, 3 + 3 * n);
         if (teth && n == 0) u = v3(0, 0, 0);
         const Q4 q = qmul(qexp(u), ldq(qj, S, s0 + n));
@@ -77,10 +77,9 @@ __global__ void __launch_bounds__(64) state_forces_kernel(SimDev d, const double
         st[n][0] = t.x; st[n][1] = t.y; st[n][2] = t.z;
     }
     __syncthreads();
+    if (n >= 64) return;
     {
-        // robot-arm positions Y_n = Y_1 + dL/2 sum_{m<n} (t_m + t_{m+1}) by a wave
-        // prefix sum (N <= 64, one lane per segment), then the filament's bounding box
-        const int n = threadIdx.x;
+        // wave prefix sum of the half-segment steps, then the bounding box
         double e[3];
         if (n == 0) {
             const V3 y1 = teth ? v3(d.base[3 * f], d.base[3 * f + 1], d.base[3 * f + 2]) : ldx(Xf, 0);
@@ -88,18 +87,18 @@ __global__ void __launch_bounds__(64) state_forces_kernel(SimDev d, const double
             e[1] = y1.y;
             e[2] = y1.z;
         } else {
-            for (int i = 0; i < 3; i++) e[i] = n < N ? (0.5 * d.dL) * (st[n - 1][i] + st[n][i]) : 0.0;
+            for (int i = 0; i < 3; i++) e[i] = seg ? (0.5 * d.dL) * (st[n - 1][i] + st[n][i]) : 0.0;
         }
         for (int o = 1; o < 64; o <<= 1)
             for (int i = 0; i < 3; i++) {
                 const double t = __shfl_up(e[i], o, 64);
                 if (n >= o) e[i] += t;
             }
-        if (n < N) st3(Yc, S, s0 + n, v3(e[0], e[1], e[2]));
+        if (seg) st3(Yc, S, s0 + n, v3(e[0], e[1], e[2]));
         double lo[3], hi[3];
         for (int i = 0; i < 3; i++) lo[i] = hi[i] = __shfl(e[i], 0, 64);
         for (int i = 0; i < 3; i++)
-            if (n < N) lo[i] = hi[i] = e[i];
+            if (seg) lo[i] = hi[i] = e[i];
         for (int o = 32; o > 0; o >>= 1)
             for (int i = 0; i < 3; i++) {
                 lo[i] = fmin(lo[i], __shfl_xor(lo[i], o, 64));
@@ -113,29 +112,41 @@ __global__ void __launch_bounds__(64) state_forces_kernel(SimDev d, const double
             }
         }
     }
-    for (int64_t n = threadIdx.x; n < N; n += 64) {
-        const Q4 qn{sq[n][0], sq[n][1], sq[n][2], sq[n][3]};
-        V3 lp = v3(0, 0, 0), lm = v3(0, 0, 0), mp = v3(0, 0, 0), mm = v3(0, 0, 0);
-        if (n + 1 < N) {
-            lp = ldx(Xf, 3 + 3 * N + 3 * n);
-            mp = joint_moment(qn, Q4{sq[n + 1][0], sq[n + 1][1], sq[n + 1][2], sq[n + 1][3]},
-                              joint_kappa(d, f, n, tt), d.dL, d.KB, d.KT);
-        }
-        if (n > 0) {
-            lm = ldx(Xf, 3 + 3 * N + 3 * (n - 1));
-            mm = joint_moment(Q4{sq[n - 1][0], sq[n - 1][1], sq[n - 1][2], sq[n - 1][3]}, qn,
-                              joint_kappa(d, f, n - 1, tt), d.dL, d.KB, d.KT);
-        }
-        const double* sp = d.spar + kSpar * d.fil_susp[f];
-        V3 fc = lp - lm + v3(sp[1], sp[2], sp[3]);
-        V3 tc = (0.5 * d.dL) * cross(v3(st[n][0], st[n][1], st[n][2]), lp + lm) + (mp - mm);
-        if (teth && n == 0) {
-            fc = fc + ldx(Xf, 0);
-            tc = tc + ldx(Xf, 3);
-        }
-        st3(F, S, s0 + n, fc);
-        st3(T, S, s0 + n, tc);
+    if (!seg) return;
+    const Q4 qn{sq[n][0], sq[n][1], sq[n][2], sq[n][3]};
+    V3 lp = v3(0, 0, 0), lm = v3(0, 0, 0), mp = v3(0, 0, 0), mm = v3(0, 0, 0);
+    if (n + 1 < N) {
+        lp = ldx(Xf, 3 + 3 * N + 3 * n);
+        mp = joint_moment(qn, Q4{sq[n + 1][0], sq[n + 1][1], sq[n + 1][2], sq[n + 1][3]}, joint_kappa(d, f, n, tt),
+                          d.dL, d.KB, d.KT);
     }
+    if (n > 0) {
+        lm = ldx(Xf, 3 + 3 * N + 3 * (n - 1));
+        mm = joint_moment(Q4{sq[n - 1][0], sq[n - 1][1], sq[n - 1][2], sq[n - 1][3]}, qn,
+                          joint_kappa(d, f, n - 1, tt), d.dL, d.KB, d.KT);
+    }
+    const double* sp = d.spar + kSpar * d.fil_susp[f];
+    V3 fc = lp - lm + v3(sp[1], sp[2], sp[3]);
+    V3 tc = (0.5 * d.dL) * cross(v3(st[n][0], st[n][1], st[n][2]), lp + lm) + (mp - mm);
+    if (teth && n == 0) {
+        fc = fc + ldx(Xf, 0);
+        tc = tc + ldx(Xf, 3);
+    }
+    st3(F, S, s0 + n, fc);
+    st3(T, S, s0 + n, tc);
+}
+
+// one 64-lane workgroup per filament
+__global__ void __launch_bounds__(64) state_forces_kernel(SimDev d, const double* __restrict__ X,
+                                                        const double* __restrict__ qj, const double* __restrict__ ttp,
+                                                        const int32_t* __restrict__ active,
+                                                        double* __restrict__ Yc, double* __restrict__ qc,
+                                                        double* __restrict__ F, double* __restrict__ T,
+                                                        double* __restrict__ box) {
+    const int64_t f = blockIdx.x;
+    if (!active[d.fil_susp[f]]) return;
+    // t^{j+1} is read on the device so that captured launches stay valid
+    filament_state(d, f, X + 6 * d.seg_off[f], qj, *ttp, Yc, qc, F, T, box);
 }
 
 int state_forces_launch(const SimDev& d, const double* X, const double* qj, const double* tt, const int32_t* active,
@@ -265,119 +276,123 @@ int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, con
 // f^1 = Y_1 - a1 Y_1^j - a2 Y_1^{j-1} - b dt V_1
 // f^2_n = u_n - g u_n^j - b dt dexpinv_{u_n}(Omega_n)
 // f^3_n = Y_n - a1 Y_n^j - a2 Y_n^{j-1} - b dt V_n
-// plus, per suspension, max|f| and max|b dt (V, dexpinv Omega)| (the size of the
-// mobility term, which sets the rounding floor of a reduced-precision apply), each
-// as the bit pattern of a non-negative double so an integer atomicMax orders it
-// (a NaN compares above every finite value).  When the velocities come from the
-// mobility partials they are also stored to V, W.
-__device__ __forceinline__ void susp_max(double v, int32_t isus, const int32_t* __restrict__ active,
-                                         unsigned long long* __restrict__ out) {
-    // one atomic per wave for the wave's leading suspension, one per lane otherwise
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-    const int32_t first = __shfl(isus, 0, 64);
-    unsigned long long m = isus == first ? bits : 0ull;
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long other = __shfl_xor(m, o, 64);
-        m = other > m ? other : m;
-    }
-    // a plain read first: once the running maximum is large, most waves need no atomic
-    // (a stale read only costs an unneeded atomic; the maximum is monotonic)
-    if ((threadIdx.x & 63) == 0 && first >= 0 && active[first] &&
-        m > __atomic_load_n(&out[first], __ATOMIC_RELAXED))
-        atomicMax(&out[first], m);
-    if (isus != first && isus >= 0 && active[isus] && bits > __atomic_load_n(&out[isus], __ATOMIC_RELAXED))
-        atomicMax(&out[isus], bits);
+// One workgroup per filament.  Per suspension it also records max|f| and
+// max|b dt (V, dexpinv Omega)| (the size of the mobility term, which sets the
+// rounding floor of a reduced-precision apply), each as the bit pattern of a
+// non-negative double so that an integer atomicMax orders it (a NaN compares above
+// every finite value).  When the velocities come from the mobility partials they
+// are also stored to V, W.  For a Broyden update it leaves the filament's share of
+// the update's dot products.
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
-// Convergence test of evaluation `it` for iterations that run without the host
-// (captured in a graph): max|f|/a of each active suspension ends it when <= tol
-// (if this evaluation may end a step), fails it when non-finite or at it >= kmax;
-// the evaluation is counted.  log[4i..4i+3]: state, last iteration, evaluations,
-// FP64 evaluations.
-__device__ void judge_suspensions(const JudgeArgs& j, int64_t ns, const unsigned long long* __restrict__ resbits,
-                                  int tid, int nthreads) {
-    for (int64_t i = tid; i < ns; i += nthreads) {
-        if (!j.active[i]) continue;
-        const double r = __longlong_as_double((long long)resbits[i]) * j.inv_a;
-        int32_t* L = j.log + 4 * i;
-        L[1] = j.it;
-        L[2] += 1;
-        L[3] += j.can_converge;
-        j.last[i] = r;
-        int32_t st = 0;
-        if (!(r <= 1.7976931348623157e308)) st = -1;  // NaN or infinite
-        else if (r <= j.tol && j.can_converge) st = 1;
-        else if (j.it >= j.kmax) st = -1;
-        if (st) {
-            L[0] = st;
-            j.active[i] = 0;
+// Filament f's share of the dot products of Broyden update k (Alg. 2), its rows of
+// f in LDS: h < k: d_h . f;  h = k: |f - fprev|^2;  h = k+1: (f - fprev) . f.
+// Dot h is reduced by wave h mod (NT / 64) in a fixed order, two dots per pass.
+template <int NT>
+__device__ void filament_dots(const SimDev& d, int64_t f, const DotArgs& da, const double* sf, int nrow) {
+    constexpr int NW = NT / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t e0 = 6 * d.seg_off[f], n6 = 6 * d.S;
+    const int nd = da.k + 2;
+    auto term = [&](int h, int e, double fn) {
+        if (h < da.k) return da.Dhist[(int64_t)h * n6 + e0 + e] * fn;
+        const double df = fn - da.fprev[e0 + e];
+        return df * (h == da.k ? df : fn);
+    };
+    for (int h0 = wave; h0 < nd; h0 += 2 * NW) {
+        const int h1 = h0 + NW;
+        double a0 = 0.0, a1 = 0.0;
+        for (int e = lane; e < nrow; e += 64) {
+            const double fn = sf[e];
+            a0 += term(h0, e, fn);
+            if (h1 < nd) a1 += term(h1, e, fn);
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        if (lane == 0) {
+            da.dpart[f * d.max_dots + h0] = a0;
+            if (h1 < nd) da.dpart[f * d.max_dots + h1] = a1;
         }
     }
 }
 
-// One workgroup per 64 segments: its six waves first sum one velocity component
-// each over the K mobility partials (coalesced, fixed order), then the first
-// wave forms the six residual rows of its segments.  With a judge ticket, the
-// last workgroup to finish runs the convergence test (and resets the ticket).
-__global__ void __launch_bounds__(6 * kResSeg) residual_kernel(SimDev d, BdfCoef bc, const double* __restrict__ X,
-                                                             const double* __restrict__ Xj,
-                                                             const double* __restrict__ Yc,
-                                                             const double* __restrict__ Yj,
-                                                             const double* __restrict__ Yjm1,
-                                                             double* __restrict__ V, double* __restrict__ W,
-                                                             const double* __restrict__ part, int K,
-                                                             const int32_t* __restrict__ active,
-                                                             double* __restrict__ fout,
-                                                             unsigned long long* __restrict__ resbits,
-                                                             unsigned long long* __restrict__ resbits_next,
-                                                             JudgeArgs jg) {
+// Up to kSplit threads share one sum (over mobility partials, inverse columns or
+// history vectors) so that each has few loads in flight; partial sums are combined
+// in a fixed order.
+constexpr int kSplit = 8;
+constexpr int lds_rows(int nt) { return nt > 6 * kMaxSeg ? nt : 6 * kMaxSeg; }
+
+template <int NT>
+__global__ void __launch_bounds__(NT) residual_kernel(SimDev d, BdfCoef bc, const double* __restrict__ X,
+                                                    const double* __restrict__ Xj, const double* __restrict__ Yc,
+                                                    const double* __restrict__ Yj, const double* __restrict__ Yjm1,
+                                                    double* __restrict__ V, double* __restrict__ W,
+                                                    const double* __restrict__ part, int K,
+                                                    const int32_t* __restrict__ active, double* __restrict__ fout,
+                                                    unsigned long long* __restrict__ resbits,
+                                                    unsigned long long* __restrict__ resbits_next, DotArgs da) {
     const int64_t S = d.S;
-    // the other buffer is zeroed for the next evaluation (the host has read it)
+    // the other buffer is zeroed for the next evaluation (its last reader has run)
     if (blockIdx.x == 0)
         for (int64_t i = threadIdx.x; i < 2 * d.nsusp; i += blockDim.x) resbits_next[i] = 0ull;
-    __shared__ double sv[6][kResSeg];
-    const int c = threadIdx.x / kResSeg, l = threadIdx.x % kResSeg;
-    {
-        const int64_t s = (int64_t)blockIdx.x * kResSeg + l;
-        if (s < S && active[d.fil_susp[d.seg_fil[s]]]) {
-            double v;
-            if (part) {
-                const double* pp = part + (int64_t)c * S + s;
-                const int64_t stride = 6 * S;
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                int k = 0;
-                for (; k + 4 <= K; k += 4) {
-                    a0 += pp[(int64_t)k * stride];
-                    a1 += pp[(int64_t)(k + 1) * stride];
-                    a2 += pp[(int64_t)(k + 2) * stride];
-                    a3 += pp[(int64_t)(k + 3) * stride];
-                }
-                for (; k < K; k++) a0 += pp[(int64_t)k * stride];
-                v = (a0 + a1) + (a2 + a3);
-                if (c < 3) V[c * S + s] = v;
-                else W[(c - 3) * S + s] = v;
-            } else {
-                v = c < 3 ? V[c * S + s] : W[(c - 3) * S + s];
+    const int64_t f = blockIdx.x;
+    const int32_t isus = d.fil_susp[f];
+    if (!active[isus]) return;
+    const int64_t s0 = d.seg_off[f];
+    const int N = (int)(d.seg_off[f + 1] - s0);
+    const int ni = 6 * N;  // items (c, l): velocity component c of segment l
+    __shared__ double sv[6][kMaxSeg];
+    __shared__ double sf[6 * kMaxSeg];
+    __shared__ double red[lds_rows(NT)];
+    if (part) {
+        // R threads per item, thread q summing partials q, q + R, ...
+        const int R = max(1, min(kSplit, NT / ni));
+        const int64_t stride = 6 * S;
+        for (int e = threadIdx.x; e < R * ni; e += NT) {
+            const int q = e / ni, item = e - q * ni;
+            const int c = item / N, l = item - c * N;
+            const double* pp = part + (int64_t)c * S + s0 + l;
+            double a0 = 0.0, a1 = 0.0;
+            int k = q;
+            for (; k + R < K; k += 2 * R) {
+                a0 += pp[(int64_t)k * stride];
+                a1 += pp[(int64_t)(k + R) * stride];
             }
+            if (k < K) a0 += pp[(int64_t)k * stride];
+            red[e] = a0 + a1;
+        }
+        __syncthreads();
+        for (int item = threadIdx.x; item < ni; item += NT) {
+            double v = red[item];
+            for (int q = 1; q < R; q++) v += red[q * ni + item];
+            const int c = item / N, l = item - c * N;
+            const int64_t s = s0 + l;
+            if (c < 3) V[c * S + s] = v;
+            else W[(c - 3) * S + s] = v;
             sv[c][l] = v;
+        }
+    } else {
+        for (int item = threadIdx.x; item < ni; item += NT) {
+            const int c = item / N, l = item - c * N;
+            const int64_t s = s0 + l;
+            sv[c][l] = c < 3 ? V[c * S + s] : W[(c - 3) * S + s];
         }
     }
     __syncthreads();
-    if (threadIdx.x >= kResSeg) return;
-    const int64_t s = (int64_t)blockIdx.x * kResSeg + threadIdx.x;
-    double amax = 0.0, vmax = 0.0;
-    int32_t isus = -1;
-    if (s < S) {
-        const int32_t f = d.seg_fil[s];
-        isus = d.fil_susp[f];
-        if (active[isus]) {
-            const int64_t s0 = d.seg_off[f], N = d.seg_off[f + 1] - s0, n = s - s0;
+    const int n = threadIdx.x;
+    if (n < 64) {
+        double amax = 0.0, vmax = 0.0;
+        if (n < N) {
+            const int64_t s = s0 + n;
             const int teth = d.tether[f];
             const double bdt = bc.b * d.spar[kSpar * isus];
             const double* Xf = X + 6 * s0;
             double* ff = fout + 6 * s0;
-            const V3 vel = v3(sv[0][l], sv[1][l], sv[2][l]);
-            const V3 om = v3(sv[3][l], sv[4][l], sv[5][l]);
+            const V3 vel = v3(sv[0][n], sv[1][n], sv[2][n]);
+            const V3 om = v3(sv[3][n], sv[4][n], sv[5][n]);
             const V3 yres = ld3(Yc, S, s) - bc.a1 * ld3(Yj, S, s) - bc.a2 * ld3(Yjm1, S, s) - bdt * vel;
             V3 u = ldx(Xf, 3 + 3 * n), uj = ldx(Xj + 6 * s0, 3 + 3 * n);
             if (teth && n == 0) u = uj = v3(0, 0, 0);
@@ -385,54 +400,55 @@ __global__ void __launch_bounds__(6 * kResSeg) residual_kernel(SimDev d, BdfCoef
             const V3 ures = u - bc.g * uj - bdt * dom;
             vmax = fabs(bdt) * fmax(fmax(fmax(fabs(vel.x), fabs(vel.y)), fmax(fabs(vel.z), fabs(dom.x))),
                                     fmax(fabs(dom.y), fabs(dom.z)));
-            const int64_t ry = n == 0 ? 0 : 3 + 3 * N + 3 * (n - 1);
-            ff[ry] = yres.x;
-            ff[ry + 1] = yres.y;
-            ff[ry + 2] = yres.z;
-            ff[3 + 3 * n] = ures.x;
-            ff[4 + 3 * n] = ures.y;
-            ff[5 + 3 * n] = ures.z;
+            const int ry = n == 0 ? 0 : 3 + 3 * N + 3 * (n - 1);
+            ff[ry] = sf[ry] = yres.x;
+            ff[ry + 1] = sf[ry + 1] = yres.y;
+            ff[ry + 2] = sf[ry + 2] = yres.z;
+            ff[3 + 3 * n] = sf[3 + 3 * n] = ures.x;
+            ff[4 + 3 * n] = sf[4 + 3 * n] = ures.y;
+            ff[5 + 3 * n] = sf[5 + 3 * n] = ures.z;
             amax = fmax(fmax(fmax(fabs(yres.x), fabs(yres.y)), fmax(fabs(yres.z), fabs(ures.x))),
                         fmax(fabs(ures.y), fabs(ures.z)));
             if (!(yres.x == yres.x && yres.y == yres.y && yres.z == yres.z && ures.x == ures.x &&
                   ures.y == ures.y && ures.z == ures.z))
                 amax = __longlong_as_double(0x7ff8000000000000ll);
         }
+        // the workgroup belongs to one suspension: wave maxima, one atomic each (a plain
+        // read first: once the running maximum is large most workgroups need no atomic;
+        // a stale read only costs an unneeded atomic, the maximum being monotonic)
+        unsigned long long ma = (unsigned long long)__double_as_longlong(amax);
+        unsigned long long mv = (unsigned long long)__double_as_longlong(vmax);
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long oa = __shfl_xor(ma, o, 64), ov = __shfl_xor(mv, o, 64);
+            ma = oa > ma ? oa : ma;
+            mv = ov > mv ? ov : mv;
+        }
+        if (n == 0) {
+            if (ma > __atomic_load_n(&resbits[isus], __ATOMIC_RELAXED)) atomicMax(&resbits[isus], ma);
+            if (mv > __atomic_load_n(&resbits[d.nsusp + isus], __ATOMIC_RELAXED))
+                atomicMax(&resbits[d.nsusp + isus], mv);
+        }
     }
-    susp_max(amax, isus, active, resbits);
-    susp_max(vmax, isus, active, resbits + d.nsusp);
-    if (!jg.ticket) return;
-    // last-workgroup convergence test: this wave's atomics are made visible, then
-    // one ticket per workgroup; the workgroup drawing the last ticket sees all of them
-    __threadfence();
-    unsigned int t = 0;
-    if (threadIdx.x == 0) t = atomicAdd(jg.ticket, 1u);
-    t = __shfl(t, 0, 64);
-    if (t != gridDim.x - 1) return;
-    __threadfence();
-    judge_suspensions(jg, d.nsusp, resbits, threadIdx.x, kResSeg);
-    if (threadIdx.x == 0) atomicExch(jg.ticket, 0u);
+    if (da.k < 0) return;
+    __syncthreads();
+    filament_dots<NT>(d, f, da, sf, ni);
 }
 
-__global__ void __launch_bounds__(256) judge_kernel(JudgeArgs jg, int64_t ns,
-                                                    const unsigned long long* __restrict__ resbits) {
-    judge_suspensions(jg, ns, resbits, threadIdx.x, blockDim.x);
-}
+// workgroup size of the per-filament kernels: 1024 threads (more loads in flight per
+// filament) while one workgroup per CU covers all filaments, else 256
+int fil_threads(const SimDev& d) { return d.M <= 256 ? 1024 : 256; }
 
 int residual_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* Xj, const double* Yc,
                     const double* Yj, const double* Yjm1, double* V, double* W, const double* part, int K,
                     const int32_t* active, double* f, unsigned long long* resbits, unsigned long long* resbits_next,
-                    hipStream_t st, const JudgeArgs* judge) {
-    // the test is fused (last workgroup) for small grids; for large ones the
-    // per-workgroup ticket atomics would serialise, so it runs as its own kernel
-    const int64_t nb = ceil_div(d.S, kResSeg);
-    JudgeArgs jg{};
-    const bool fused = judge && nb <= kFusedJudgeBlocks;
-    if (fused) jg = *judge;
-    if (d.S > 0)
-        residual_kernel<<<(unsigned)nb, 6 * kResSeg, 0, st>>>(d, bc, X, Xj, Yc, Yj, Yjm1, V, W, part, K, active, f,
-                                                              resbits, resbits_next, jg);
-    if (judge && !fused) judge_kernel<<<1, 256, 0, st>>>(*judge, d.nsusp, resbits);
+                    const DotArgs& da, hipStream_t st) {
+    if (d.M == 0) return FIL_OK;
+    if (fil_threads(d) == 1024)
+        residual_kernel<1024><<<(unsigned)d.M, 1024, 0, st>>>(d, bc, X, Xj, Yc, Yj, Yjm1, V, W, part, K, active, f,
+                                                              resbits, resbits_next, da);
+    else
+        residual_kernel<256><<<(unsigned)d.M, 256, 0, st>>>(d, bc, X, Xj, Yc, Yj, Yjm1, V, W, part, K, active, f,
+                                                            resbits, resbits_next, da);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }
@@ -792,12 +808,6 @@ __global__ void __launch_bounds__(64) j0_band_factor_regs_kernel(SimDev d, const
 }
 
 
-// One wave solves (L J0) x = L v for one filament, given the staged band `ab`
-// (reciprocal pivots on its diagonal), the pivot rows `ip` and its own LDS
-// vector `y` that holds L v in the interleaved order on entry and x on exit.
-// The pending entries of each sweep live in a ring of lanes (entry i in lane
-// i mod 16, resp. mod 32), so a step is a few wave-uniform lane reads and one
-// fused update, with no barrier; every LDS read is issued one step ahead.
 // Forward and backward sweeps of one banded LU solve by one wave, the solution
 // vector y in LDS and a ring of lanes holding the active rows (16 forward, 32
 // backward).  The band factor ab is read from global memory: each lane's
@@ -881,35 +891,6 @@ __device__ __forceinline__ double diff_unit(int c, int i, int N) {
 }
 
 
-
-// out = J0^{-1} v for every active filament, one wave each
-__global__ void __launch_bounds__(64) j0_band_solve_kernel(SimDev d, const double* __restrict__ AB,
-                                                         const int32_t* __restrict__ ipiv,
-                                                         const double* __restrict__ v,
-                                                         const int32_t* __restrict__ active,
-                                                         double* __restrict__ out, int nmax) {
-    const int64_t f = blockIdx.x;
-    if (!active[d.fil_susp[f]]) return;
-    extern __shared__ double lds[];  // y [nmax] | rd [nmax] | ip [nmax]
-    const int64_t s0 = d.seg_off[f];
-    const int N = (int)(d.seg_off[f + 1] - s0);
-    const int n = 6 * N;
-    double* y = lds;
-    double* rd = lds + nmax;
-    int* ip = reinterpret_cast<int*>(lds + 2 * (size_t)nmax);
-    const int lane = threadIdx.x;
-    const double* vf = v + 6 * s0;
-    const double* ab = AB + 6 * s0 * kBandW;
-    for (int i = lane; i < n; i += 64) {
-        y[i] = diff_rhs(vf, i, N);
-        rd[i] = 1.0 / ab[(int64_t)i * kBandW + kKL];
-        ip[i] = ipiv[6 * s0 + i];
-    }
-    __syncthreads();
-    band_sweeps(ab, ip, rd, y, n, lane);
-    __syncthreads();
-    for (int i = lane; i < n; i += 64) out[6 * s0 + slot_of(i / 3, N) + i % 3] = y[i];
-}
 
 // Explicit inverse for the dense per-iteration product.  Block (f, g) owns cb
 // columns c = g*cb + t of filament f's J0^{-1}, one per thread: the thread
@@ -1023,46 +1004,6 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
     }
 }
 
-// out = J0^{-1} v with the explicit inverse: out_i = sum_c Ainv^T[c][i] v_c
-__global__ void __launch_bounds__(256) dense_matvec_kernel(SimDev d, const double* __restrict__ AinvT,
-                                                         const double* __restrict__ v,
-                                                         const int32_t* __restrict__ active,
-                                                         double* __restrict__ out) {
-    const int64_t f = blockIdx.x;
-    if (!active[d.fil_susp[f]]) return;
-    const int64_t s0 = d.seg_off[f];
-    const int n = 6 * (int)(d.seg_off[f + 1] - s0);
-    const double* A = AinvT + d.dense_off[f];
-    __shared__ double sv[6 * kMaxSeg];
-    for (int j = threadIdx.x; j < n; j += blockDim.x) sv[j] = v[6 * s0 + j];
-    __syncthreads();
-    // two threads per row, each over half of the columns (four chains each), combined in LDS
-    __shared__ double red[128];
-    const int half = threadIdx.x >> 7, li = threadIdx.x & 127;
-    const int cmid = ((n + 7) / 8) * 4;  // first column of the second half (multiple of 4)
-    const int cb = half ? cmid : 0, ce = half ? n : (cmid < n ? cmid : n);
-    for (int i0 = 0; i0 < n; i0 += 128) {
-        const int i = i0 + li;
-        double acc = 0.0;
-        if (i < n) {
-            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-            int c = cb;
-            for (; c + 4 <= ce; c += 4) {
-                a0 = fma(A[(int64_t)c * n + i], sv[c], a0);
-                a1 = fma(A[(int64_t)(c + 1) * n + i], sv[c + 1], a1);
-                a2 = fma(A[(int64_t)(c + 2) * n + i], sv[c + 2], a2);
-                a3 = fma(A[(int64_t)(c + 3) * n + i], sv[c + 3], a3);
-            }
-            for (; c < ce; c++) a0 = fma(A[(int64_t)c * n + i], sv[c], a0);
-            acc = (a0 + a1) + (a2 + a3);
-        }
-        if (half) red[li] = acc;
-        __syncthreads();
-        if (!half && i < n) out[6 * s0 + i] = acc + red[li];
-        __syncthreads();
-    }
-}
-
 // Dynamic LDS beyond 64 KB has to be granted to a kernel (gfx950 has 160 KB per
 // workgroup); granted once per kernel, before any launch that is captured.
 template <class Kernel>
@@ -1112,141 +1053,203 @@ int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const 
     return FIL_OK;
 }
 
-int j0_solve_launch(const SimDev& d, const double* AB, const int32_t* ipiv, const double* AinvT, const double* v,
-                    const int32_t* active, double* out, hipStream_t st) {
-    if (d.M == 0) return FIL_OK;
-    if (AinvT) {
-        dense_matvec_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, AinvT, v, active, out);
+// ---------------------------------------------------------------- Broyden update + state
+// out_i = sum_c Ainv^T[c][i] v_c (explicit J0^{-1} of one filament, n rows) by the
+// workgroup: P = min(kSplit, NT / n) threads per row over contiguous column ranges,
+// their sums combined in a fixed order.  Holds a barrier.
+template <int NT>
+__device__ void dense_apply(const double* __restrict__ A, const double* v, double* out, int n, double* red) {
+    const int t = threadIdx.x;
+    const int P = max(1, min(kSplit, NT / n));
+    for (int e = t; e < P * n; e += NT) {
+        const int p = e / n, i = e - p * n;
+        const int cb = (n * p) / P, ce = (n * (p + 1)) / P;
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int c = cb;
+        for (; c + 8 <= ce; c += 8)
+#pragma unroll
+            for (int q = 0; q < 8; q++) a[q] = fma(A[(int64_t)(c + q) * n + i], v[c + q], a[q]);
+        for (; c < ce; c++) a[0] = fma(A[(int64_t)c * n + i], v[c], a[0]);
+        red[e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += NT) {
+        double acc = red[i];
+        for (int p = 1; p < P; p++) acc += red[p * n + i];
+        out[i] = acc;
+    }
+}
+
+// One workgroup per filament, after the residual kernel of the same evaluation:
+//  1. with a judge: the convergence test of the filament's suspension from the
+//     maxima the residual kernel left (max|f|/a <= tol ends it when this evaluation
+//     may end a step; a non-finite value or it >= kmax fails it).  Every workgroup
+//     of the suspension takes the same decision; the one of its first filament logs
+//     it and clears the suspension's flag.  A singular J0 block (first step) fails
+//     its suspension.
+//  2. the suspension's dot products, summed over its filaments in a fixed order (so
+//     every workgroup of the suspension holds the same values);
+//  3. g = J0^{-1} f for the filament's rows: explicit inverse, or the banded sweeps
+//     by the first wave;
+//  4. the bad-Broyden update (Alg. 2): g += sum_{h<k} c_h (d_h . f);
+//     c_k = -g/|df|, d_k = df/|df|, step = g + c_k (d_k . f), or for the first step
+//     (k < 0) step = g; then fprev <- f and X <- X - step;
+//  5. the configuration and internal forces at the new X.
+template <int NT>
+__global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs u, JudgeArgs jg,
+                                                         int32_t* __restrict__ active) {
+    constexpr int NW = NT / 64;
+    const int64_t f = blockIdx.x;
+    const int32_t isus = d.fil_susp[f];
+    if (!active[isus]) return;
+    if (jg.log) {
+        const double r = __longlong_as_double((long long)jg.resbits[isus]) * jg.inv_a;
+        int32_t state = 0;
+        if (!(r <= 1.7976931348623157e308)) state = -1;  // NaN or infinite
+        else if (r <= jg.tol && jg.can_converge) state = 1;
+        else if (jg.it >= jg.kmax) state = -1;
+        if (jg.jflag && jg.jflag[f] && threadIdx.x == 0) {
+            // singular J0 block: the suspension fails (every such workgroup writes the same)
+            jg.log[4 * isus] = -1;
+            active[isus] = 0;
+        }
+        if (jg.jflag && jg.jflag[f]) return;
+        if (threadIdx.x == 0 && f == d.susp_fil_off[isus]) {
+            int32_t* L = jg.log + 4 * isus;
+            L[1] = jg.it;
+            L[2] += 1;
+            L[3] += jg.can_converge;
+            jg.last[isus] = r;
+            if (state) {
+                L[0] = state;
+                active[isus] = 0;
+            }
+        }
+        if (state) return;
+    }
+    const int64_t s0 = d.seg_off[f];
+    const int N = (int)(d.seg_off[f + 1] - s0);
+    const int n = 6 * N;
+    const int64_t e0 = 6 * s0, n6 = 6 * d.S;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    __shared__ double sf[6 * kMaxSeg], sg[6 * kMaxSeg], sx[6 * kMaxSeg];
+    __shared__ double sdots[kMaxDots];
+    __shared__ double red[lds_rows(NT)];
+    for (int e = t; e < n; e += NT) sf[e] = u.fnew[e0 + e];
+    if (u.k >= 0) {
+        // dot h by wave h mod NW, two per pass, over the filaments' partials in order
+        const int64_t g0 = d.susp_fil_off[isus], g1 = d.susp_fil_off[isus + 1];
+        const int nd = u.k + 2;
+        for (int h0 = wave; h0 < nd; h0 += 2 * NW) {
+            const int h1 = h0 + NW;
+            double a0 = 0.0, a1 = 0.0;
+            for (int64_t g = g0 + lane; g < g1; g += 64) {
+                a0 += u.dpart[g * d.max_dots + h0];
+                if (h1 < nd) a1 += u.dpart[g * d.max_dots + h1];
+            }
+            a0 = wave_sum(a0);
+            a1 = wave_sum(a1);
+            if (lane == 0) {
+                sdots[h0] = a0;
+                if (h1 < nd) sdots[h1] = a1;
+            }
+        }
+    }
+    __syncthreads();
+    if (u.AinvT) {
+        dense_apply<NT>(u.AinvT + d.dense_off[f], sf, sg, n, red);
     } else {
-        const int nmax = 6 * d.max_seg;
-        j0_band_solve_kernel<<<(unsigned)d.M, 64, (size_t)nmax * (2 * sizeof(double) + sizeof(int)), st>>>(
-            d, AB, ipiv, v, active, out, nmax);
+        // L f in the interleaved order, then the sweeps through the band factor
+        __shared__ double y[6 * kMaxSeg], rd[6 * kMaxSeg];
+        __shared__ int ip[6 * kMaxSeg];
+        const double* ab = u.AB + e0 * kBandW;
+        for (int i = t; i < n; i += NT) {
+            y[i] = diff_rhs(sf, i, N);
+            rd[i] = 1.0 / ab[(int64_t)i * kBandW + kKL];
+            ip[i] = u.ipiv[e0 + i];
+        }
+        __syncthreads();
+        if (wave == 0) band_sweeps(ab, ip, rd, y, n, lane);
+        __syncthreads();
+        for (int i = t; i < n; i += NT) sg[slot_of(i / 3, N) + i % 3] = y[i];
     }
+    __syncthreads();
+    if (u.k >= 0) {
+        // sum_{h<k} c_h (d_h . f) per row: R threads per row, thread q over h = q, q + R, ...
+        const int R = max(1, min(kSplit, NT / n));
+        for (int e = t; e < R * n; e += NT) {
+            const int q = e / n, i = e - q * n;
+            const int64_t ge = e0 + i;
+            double a0 = 0.0, a1 = 0.0;
+            int h = q;
+            for (; h + R < u.k; h += 2 * R) {
+                a0 = fma(u.Chist[(int64_t)h * n6 + ge], sdots[h], a0);
+                a1 = fma(u.Chist[(int64_t)(h + R) * n6 + ge], sdots[h + R], a1);
+            }
+            if (h < u.k) a0 = fma(u.Chist[(int64_t)h * n6 + ge], sdots[h], a0);
+            red[e] = a0 + a1;
+        }
+        __syncthreads();
+        const double nrm = sqrt(sdots[u.k]);
+        const double inrm = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        const double dfdot = sdots[u.k + 1] * inrm;
+        for (int e = t; e < n; e += NT) {
+            const int64_t ge = e0 + e;
+            double g = red[e];
+            for (int q = 1; q < R; q++) g += red[q * n + e];
+            g += sg[e];
+            const double fn = sf[e];
+            const double c = -g * inrm;
+            u.Chist[(int64_t)u.k * n6 + ge] = c;
+            u.Dhist[(int64_t)u.k * n6 + ge] = (fn - u.fprev[ge]) * inrm;
+            const double hn = fma(c, dfdot, g);
+            u.fprev[ge] = fn;
+            const double xn = u.X[ge] - hn;
+            u.X[ge] = xn;
+            sx[e] = xn;
+            if (u.dXout) u.dXout[ge] = -hn;
+        }
+    } else {
+        for (int e = t; e < n; e += NT) {
+            const int64_t ge = e0 + e;
+            const double hn = sg[e];
+            u.fprev[ge] = sf[e];
+            const double xn = u.X[ge] - hn;
+            u.X[ge] = xn;
+            sx[e] = xn;
+            if (u.dXout) u.dXout[ge] = -hn;
+        }
+    }
+    __syncthreads();
+    filament_state(d, f, sx, u.qj, *u.tt, u.Yc, u.qc, u.F, u.T, u.box);
+}
+
+int broyden_state_launch(const SimDev& d, const UpdateArgs& u, const JudgeArgs& jg, int32_t* active, hipStream_t st) {
+    if (d.M == 0) return FIL_OK;
+    if (fil_threads(d) == 1024) broyden_state_kernel<1024><<<(unsigned)d.M, 1024, 0, st>>>(d, u, jg, active);
+    else broyden_state_kernel<256><<<(unsigned)d.M, 256, 0, st>>>(d, u, jg, active);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }
 
-// Partial dot products for one Broyden update of every active suspension; block
-// (b, h) reduces dot h over vector block b: h < k: d_h . fnew; h = k:
-// |fnew - fprev|^2; h = k+1: (fnew - fprev) . fnew.  Vector blocks never
-// straddle suspensions, so every partial belongs to one suspension.
-__global__ void __launch_bounds__(256) multidot_kernel(SimDev d, int k, const double* __restrict__ Dhist,
-                                                     const double* __restrict__ fnew,
-                                                     const double* __restrict__ fprev,
-                                                     const int32_t* __restrict__ active,
-                                                     double* __restrict__ part) {
-    const int64_t b = blockIdx.x;
-    const int h = blockIdx.y;
-    const int32_t isus = d.vblk_susp[b];
-    if (!active[isus]) return;
-    const int64_t e0 = d.vblk_start[b], e1 = d.vblk_start[b + 1];
-    const int64_t n6 = 6 * d.S;
-    double acc = 0.0;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        const double fn = fnew[e];
-        if (h < k) acc = fma(Dhist[(int64_t)h * n6 + e], fn, acc);
-        else {
-            const double df = fn - fprev[e];
-            acc = fma(df, h == k ? df : fn, acc);
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+// dot products of an update from a residual the caller provides
+template <int NT>
+__global__ void __launch_bounds__(NT) update_dots_kernel(SimDev d, const double* __restrict__ fnew,
+                                                       const int32_t* __restrict__ active, DotArgs da) {
+    const int64_t f = blockIdx.x;
+    if (!active[d.fil_susp[f]]) return;
+    const int64_t e0 = 6 * d.seg_off[f];
+    const int n = 6 * (int)(d.seg_off[f + 1] - d.seg_off[f]);
+    __shared__ double sf[6 * kMaxSeg];
+    for (int e = threadIdx.x; e < n; e += NT) sf[e] = fnew[e0 + e];
     __syncthreads();
-    if (threadIdx.x == 0) part[b * (int64_t)d.max_dots + h] = (red[0] + red[1]) + (red[2] + red[3]);
+    filament_dots<NT>(d, f, da, sf, n);
 }
 
-// Finishes the update: g = J0^{-1} fnew + sum_h c_h (d_h . fnew);
-// c_k = -g/|df|, d_k = df/|df|, h_{k+1} = g + c_k (d_k . fnew); fprev <- fnew;
-// then the next quasi-Newton step X <- X - h_{k+1}.  Every block re-sums the
-// partial dots of its suspension in the same order, so all blocks agree.
-__global__ void __launch_bounds__(256) broyden_combine_kernel(SimDev d, int k, const double* __restrict__ part,
-                                                            const double* __restrict__ g0,
-                                                            double* __restrict__ Chist, double* __restrict__ Dhist,
-                                                            const double* __restrict__ fnew,
-                                                            double* __restrict__ fprev, double* __restrict__ hvec,
-                                                            double* __restrict__ X, double* __restrict__ dXout,
-                                                            const int32_t* __restrict__ active) {
-    const int64_t b = blockIdx.x;
-    const int32_t isus = d.vblk_susp[b];
-    if (!active[isus]) return;
-    __shared__ double dots[kMaxDots];
-    const int ndot = k + 2;
-    const int64_t pb0 = d.susp_vblk_off[isus], pb1 = d.susp_vblk_off[isus + 1];
-    // dot h is summed by wave h mod 4: lane-strided partials, then a fixed shuffle tree
-    {
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        for (int h = wave; h < ndot; h += (int)(blockDim.x >> 6)) {
-            double s = 0.0;
-            for (int64_t p = pb0 + lane; p < pb1; p += 64) s += part[p * (int64_t)d.max_dots + h];
-            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-            if (lane == 0) dots[h] = s;
-        }
-    }
-    __syncthreads();
-    const double nrm = sqrt(dots[k]);
-    const double inrm = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    const double dfdot = dots[k + 1] * inrm;
-    const int64_t n6 = 6 * d.S;
-    const int64_t e0 = d.vblk_start[b], e1 = d.vblk_start[b + 1];
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        // four independent chains over the history keep several loads in flight
-        double g1 = 0.0, g2 = 0.0, g3 = 0.0, g4 = 0.0;
-        int h = 0;
-        for (; h + 4 <= k; h += 4) {
-            g1 = fma(Chist[(int64_t)h * n6 + e], dots[h], g1);
-            g2 = fma(Chist[(int64_t)(h + 1) * n6 + e], dots[h + 1], g2);
-            g3 = fma(Chist[(int64_t)(h + 2) * n6 + e], dots[h + 2], g3);
-            g4 = fma(Chist[(int64_t)(h + 3) * n6 + e], dots[h + 3], g4);
-        }
-        for (; h < k; h++) g1 = fma(Chist[(int64_t)h * n6 + e], dots[h], g1);
-        const double g = g0[e] + ((g1 + g2) + (g3 + g4));
-        const double fn = fnew[e];
-        const double c = -g * inrm;
-        const double dd = (fn - fprev[e]) * inrm;
-        Chist[(int64_t)k * n6 + e] = c;
-        Dhist[(int64_t)k * n6 + e] = dd;
-        const double hn = fma(c, dfdot, g);
-        hvec[e] = hn;
-        fprev[e] = fn;
-        X[e] -= hn;
-        if (dXout) dXout[e] = -hn;
-    }
-}
-
-int broyden_update_launch(const SimDev& d, int k, const double* AB, const int32_t* ipiv, const double* AinvT,
-                          double* Chist, double* Dhist, const double* fnew, double* fprev, double* g0, double* hvec,
-                          double* part, double* X, double* dXout, const int32_t* active, hipStream_t st) {
-    if (d.S == 0) return FIL_OK;
-    int rc = j0_solve_launch(d, AB, ipiv, AinvT, fnew, active, g0, st);
-    if (rc) return rc;
-    multidot_kernel<<<dim3((unsigned)d.nvblk, (unsigned)(k + 2)), 256, 0, st>>>(d, k, Dhist, fnew, fprev, active, part);
-    broyden_combine_kernel<<<(unsigned)d.nvblk, 256, 0, st>>>(d, k, part, g0, Chist, Dhist, fnew, fprev, hvec, X,
-                                                             dXout, active);
-    FIL_HIP_TRY(hipGetLastError());
-    return FIL_OK;
-}
-
-// X <- X - h (first quasi-Newton step of a solve) and fprev <- f
-__global__ void __launch_bounds__(256) first_step_kernel(SimDev d, const double* __restrict__ h,
-                                                       const double* __restrict__ f, double* __restrict__ fprev,
-                                                       double* __restrict__ X, double* __restrict__ dXout,
-                                                       const int32_t* __restrict__ active) {
-    const int64_t b = blockIdx.x;
-    const int32_t isus = d.vblk_susp[b];
-    if (!active[isus]) return;
-    for (int64_t e = d.vblk_start[b] + threadIdx.x; e < d.vblk_start[b + 1]; e += blockDim.x) {
-        X[e] -= h[e];
-        fprev[e] = f[e];
-        if (dXout) dXout[e] = -h[e];
-    }
-}
-
-int first_step_launch(const SimDev& d, const double* h, const double* f, double* fprev, double* X, double* dXout,
-                      const int32_t* active, hipStream_t st) {
-    if (d.S == 0) return FIL_OK;
-    first_step_kernel<<<(unsigned)d.nvblk, 256, 0, st>>>(d, h, f, fprev, X, dXout, active);
+int update_dots_launch(const SimDev& d, const double* fnew, const int32_t* active, const DotArgs& da,
+                       hipStream_t st) {
+    if (d.M == 0) return FIL_OK;
+    update_dots_kernel<256><<<(unsigned)d.M, 256, 0, st>>>(d, fnew, active, da);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }
