@@ -155,8 +155,12 @@ int fil_set_suspension_params(fil_sim* sim, const double* dt, const double* grav
  * tiles; once every running suspension's residual is within 10 tol, or within
  * 30x the FP32 rounding floor (3e-8 x max|b dt V|), later applies use FP64, and
  * only an FP64 residual ends a step (the FP32 floor can exceed tol).
- * report: HOST fil_step_report[nsusp] (may be NULL).  Synchronises the stream
- * once per Broyden iteration to test convergence.  Returns FIL_ENOCONV or
+ * report: HOST fil_step_report[nsusp] (may be NULL).  Host-driven iterations
+ * (graph execution off, and FP32-tile iterations) synchronise the stream once
+ * per iteration to test convergence; see fil_set_graph for the device-driven
+ * form.  On success the commit of the new state may still be running when the
+ * call returns: work on the simulation's stream is ordered after it, other
+ * streams synchronise first (fil_read_state does).  Returns FIL_ENOCONV or
  * FIL_ENONFINITE if a suspension failed; its state is then left at step j. */
 int fil_bdf2_step(fil_sim* sim, fil_step_report* report);
 
@@ -191,7 +195,8 @@ int fil_read_state(fil_sim* sim, double* Y, double* q, double* Xj);
  * events on the simulation's stream bracket every launch of the main pair
  * kernel; fil_get_timing returns the summed duration (ms) and the launch count
  * since the last fil_set_timing call, HOST arrays of 2: [0] the FP64 kernel,
- * [1] the FP32-tile kernel (either may be NULL).  Enabling resets the counters. */
+ * [1] the FP32-tile kernel (either may be NULL).  Enabling resets the counters;
+ * fil_get_timing synchronises the stream. */
 int fil_set_timing(fil_sim* sim, int enable);
 int fil_get_timing(fil_sim* sim, double* rpy_ms, int64_t* rpy_launches);
 
@@ -203,13 +208,14 @@ int fil_set_stream(fil_sim* sim, void* stream);
  * iterations in blocks of U, each block (per iteration: the residual
  * evaluation with its mobility apply, a device-side convergence test and the
  * bad-Broyden update) captured once into a HIP graph on a private stream and
- * replayed on the simulation's stream; the host synchronises once per block
- * instead of once per iteration.  Iterations after a suspension has converged
- * inside a block are skipped by its kernels.  Results are identical to
- * U = 0 (the default, one host test per iteration).  Graphs are cached per
- * (first iteration, U, precision) and freed by fil_destroy.  U in [0, 64].
- * fil_set_timing then times only the host-driven evaluations (the first of
- * each step); captured blocks carry no timing events. */
+ * replayed on the simulation's stream.  Every test, the first included, then
+ * runs on the device; the host reads a block's log while the next block runs,
+ * so a block launched after the end only runs kernels that find their
+ * suspension finished.  Results are identical to U = 0 (the default, one host
+ * test per iteration).  Graphs are cached per (first iteration, U, precision)
+ * and freed by fil_destroy.  U in [0, 64].  fil_set_timing then times only the
+ * host-driven evaluations (the first of each step); captured blocks carry no
+ * timing events. */
 int fil_set_graph(fil_sim* sim, int iters_per_launch);
 
 /* ------------------------------------------------------------------------ */

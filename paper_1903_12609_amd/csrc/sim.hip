@@ -39,9 +39,9 @@ struct fil_sim {
     double *AB = nullptr, *AinvT = nullptr, *Chist = nullptr, *Dhist = nullptr, *part = nullptr;
     double* box = nullptr;
     double* spar = nullptr;  // [nsusp][kSpar]
-    int32_t *ipiv = nullptr, *active_d = nullptr, *commit_d = nullptr, *jflag_d = nullptr;
+    int32_t *ipiv = nullptr, *active_d = nullptr, *jflag_d = nullptr;
     unsigned long long* resbits_d = nullptr;
-    int32_t *active_h = nullptr, *commit_h = nullptr, *jflag_h = nullptr;
+    int32_t *active_h = nullptr, *jflag_h = nullptr;
     unsigned long long* resbits_h = nullptr;
     // mobility plans and workspaces: [0] FP64, [1] FP32-tile (only when prec is FP32-tile)
     void* rpy_work[2] = {nullptr, nullptr};
@@ -60,11 +60,11 @@ struct fil_sim {
     int graph_iters = 0;  // iterations per captured block; 0 runs every iteration from the host
     hipStream_t cap_st = nullptr;  // private stream the blocks are captured on (launches go to st)
     std::map<std::array<int, 5>, GraphEntry> graphs;
-    int32_t *jlog_d = nullptr, *jlog_h = nullptr;  // [nsusp][4] state, iters, applies, FP64 applies
-    double *jlast_d = nullptr, *jlast_h = nullptr;
-    // two host slots for the logs of graph blocks in flight, each with its copy's event
-    int32_t* jlog_slot[2] = {nullptr, nullptr};
-    double* jlast_slot[2] = {nullptr, nullptr};
+    SuspLog* log_d = nullptr;  // device log of the current solve [nsusp]
+    SuspLog* log_h = nullptr;  // staging of the host's counts when the device takes over a solve
+    // two pinned slots for the logs of graph blocks in flight, each with its export's event
+    SuspLog* log_slot[2] = {nullptr, nullptr};
+    SuspLog* log_slot_dev[2] = {nullptr, nullptr};  // the same slots as the device addresses them
     hipEvent_t log_ev[2] = {nullptr, nullptr};
     // learned warm start
     fil_mlp* mlp = nullptr;
@@ -140,6 +140,8 @@ BdfCoef coefs(int64_t step) {
 constexpr double kSwitchTol = 10.0;
 constexpr double kF32Floor = 3e-8;
 constexpr double kNoiseMargin = 30.0;
+// timing events of mobility launches not yet read (read when the pool is this full, or on request)
+constexpr int kMaxPendingTimings = 256;
 
 // adds the recorded mobility-kernel durations (stream already synchronised)
 int collect_timing(fil_sim* s) {
@@ -287,8 +289,8 @@ int capture_block(fil_sim* s, int it0, int U, GraphEntry& g) {
     for (int i = 0; i < U && rc == FIL_OK; i++) {
         const int it = it0 + i;
         rc = eval_residual(s, s->X, s->f, nullptr, nullptr, false, it - 1);
-        const JudgeArgs jg{s->jlog_d, s->jlast_d, s->resbits_d + 2 * s->rb * ns, nullptr, s->p.tol, 1.0 / s->p.a,
-                           it,        s->p.kmax, s->cur == 0 ? 1 : 0};
+        const JudgeArgs jg{s->log_d, s->resbits_d + 2 * s->rb * ns, nullptr, s->p.tol, 1.0 / s->p.a, it, s->p.kmax,
+                           s->cur == 0 ? 1 : 0};
         if (rc == FIL_OK) rc = broyden_state_launch(s->d, update_args(s, it - 1, s->f, nullptr), jg, s->active_d, s->st);
     }
     hipGraph_t graph = nullptr;
@@ -345,10 +347,7 @@ int device_iterations(fil_sim* s, SolveLog& L, int it) {
             TRY(graph_block(s, it, U));
             it += U;
             s->k += U;
-            FIL_HIP_TRY(hipMemcpyAsync(s->jlog_slot[wslot], s->jlog_d, 4 * ns * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                       s->st));
-            FIL_HIP_TRY(hipMemcpyAsync(s->jlast_slot[wslot], s->jlast_d, ns * sizeof(double), hipMemcpyDeviceToHost,
-                                       s->st));
+            TRY(log_export_launch(s->log_d, ns, s->log_slot_dev[wslot], s->st));
             FIL_HIP_TRY(hipEventRecord(s->log_ev[wslot], s->st));
             wslot ^= 1;
             pending++;
@@ -357,14 +356,14 @@ int device_iterations(fil_sim* s, SolveLog& L, int it) {
         FIL_HIP_TRY(hipEventSynchronize(s->log_ev[rslot]));
         bool any = false;
         for (int64_t i = 0; i < ns; i++) {
-            const int32_t* q = s->jlog_slot[rslot] + 4 * i;
-            L.state[i] = q[0];
-            L.iters[i] = q[1];
-            L.applies[i] = q[2];
-            L.applies_hi[i] = q[3];
-            L.last[i] = s->jlast_slot[rslot][i];
-            s->active_h[i] = q[0] == 0;
-            any |= q[0] == 0;
+            const SuspLog& q = s->log_slot[rslot][i];
+            L.state[i] = q.state;
+            L.iters[i] = q.it;
+            L.applies[i] = q.evals;
+            L.applies_hi[i] = q.evals_hi;
+            L.last[i] = q.last;
+            s->active_h[i] = q.state == 0;
+            any |= q.state == 0;
         }
         rslot ^= 1;
         pending--;
@@ -428,16 +427,20 @@ int solve(fil_sim* s, SolveLog& L) {
     TRY(eval_residual(s, s->X, s->f, e0, e1, true, -1));
     TRY(begin_solve(s));
     if (s->graph_iters > 0 && s->cur == 0) {
-        // the first test runs in the first-step kernel; the log starts empty
-        FIL_HIP_TRY(hipMemsetAsync(s->jlog_d, 0, 4 * ns * sizeof(int32_t), s->st));
-        FIL_HIP_TRY(hipMemsetAsync(s->jlast_d, 0, ns * sizeof(double), s->st));
-        const JudgeArgs jg{s->jlog_d, s->jlast_d, s->resbits_d + 2 * s->rb * ns, s->jflag_d, s->p.tol, 1.0 / s->p.a,
-                           0,         s->p.kmax, 1};
+        // the first test runs in the first-step kernel (the log was cleared at the start
+        // of the step), which also fails a suspension with a singular J0 block
+        const JudgeArgs jg{s->log_d, s->resbits_d + 2 * s->rb * ns, s->jflag_d, s->p.tol, 1.0 / s->p.a, 0,
+                           s->p.kmax, 1};
         TRY(broyden_state_launch(s->d, update_args(s, -1, s->f, nullptr), jg, s->active_d, s->st));
-        FIL_HIP_TRY(hipMemcpyAsync(s->jflag_h, s->jflag_d, s->M * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
         TRY(device_iterations(s, L, 1));
-        if (singular())
-            for (int64_t i = 0; i < ns; i++) s->active_h[i] = 0;
+        for (int64_t i = 0; i < ns; i++)
+            if (L.state[i] == -2) {
+                set_error("fil_bdf2_step: an approximate Jacobian block of suspension " + std::to_string(i) +
+                          " is singular");
+                std::fill(L.state.begin(), L.state.end(), -1);
+                L.singular = true;
+                break;
+            }
         return FIL_OK;
     }
     count();
@@ -455,16 +458,9 @@ int solve(fil_sim* s, SolveLog& L) {
     for (int it = 1; any;) {
         if (s->graph_iters > 0 && s->cur == 0) {
             // FP32 iterations are done: the device continues from the host's counts
-            for (int64_t i = 0; i < ns; i++) {
-                int32_t* g = s->jlog_h + 4 * i;
-                g[0] = L.state[i];
-                g[1] = L.iters[i];
-                g[2] = L.applies[i];
-                g[3] = L.applies_hi[i];
-                s->jlast_h[i] = L.last[i];
-            }
-            FIL_HIP_TRY(hipMemcpyAsync(s->jlog_d, s->jlog_h, 4 * ns * sizeof(int32_t), hipMemcpyHostToDevice, s->st));
-            FIL_HIP_TRY(hipMemcpyAsync(s->jlast_d, s->jlast_h, ns * sizeof(double), hipMemcpyHostToDevice, s->st));
+            for (int64_t i = 0; i < ns; i++)
+                s->log_h[i] = SuspLog{L.state[i], L.iters[i], L.applies[i], L.applies_hi[i], L.last[i]};
+            FIL_HIP_TRY(hipMemcpyAsync(s->log_d, s->log_h, ns * sizeof(SuspLog), hipMemcpyHostToDevice, s->st));
             return device_iterations(s, L, it);
         }
         count();
@@ -610,19 +606,20 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     A(s->AB, n6 * kBandW) A(s->ipiv, n6)
     if (dense) { A(s->AinvT, dense_tot) A(d_dense_off, M) }
     A(s->Chist, (size_t)p->kmax * n6) A(s->Dhist, (size_t)p->kmax * n6) A(s->part, (size_t)M * max_dots)
-    A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->time_d, 1) A(s->jlog_d, 4 * nsusp) A(s->jlast_d, nsusp)
-    A(s->active_d, nsusp) A(s->commit_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 4 * nsusp)
+    A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->time_d, 1) A(s->log_d, nsusp)
+    A(s->active_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 4 * nsusp)
 #undef A
     if (rc == FIL_OK) rc = halloc(s, &s->active_h, nsusp);
-    if (rc == FIL_OK) rc = halloc(s, &s->commit_h, nsusp);
     if (rc == FIL_OK) rc = halloc(s, &s->jflag_h, M);
     if (rc == FIL_OK) rc = halloc(s, &s->resbits_h, 2 * nsusp);
     if (rc == FIL_OK) rc = halloc(s, &s->time_h, 1);
-    if (rc == FIL_OK) rc = halloc(s, &s->jlog_h, 4 * nsusp);
-    if (rc == FIL_OK) rc = halloc(s, &s->jlast_h, nsusp);
+    if (rc == FIL_OK) rc = halloc(s, &s->log_h, nsusp);
     for (int i = 0; i < 2; i++) {
-        if (rc == FIL_OK) rc = halloc(s, &s->jlog_slot[i], 4 * nsusp);
-        if (rc == FIL_OK) rc = halloc(s, &s->jlast_slot[i], nsusp);
+        if (rc == FIL_OK) rc = halloc(s, &s->log_slot[i], nsusp);
+        if (rc == FIL_OK && hipHostGetDevicePointer((void**)&s->log_slot_dev[i], s->log_slot[i], 0) != hipSuccess) {
+            set_error("fil_create: no device address for a pinned log slot");
+            rc = FIL_EHIP;
+        }
         if (rc == FIL_OK && hipEventCreateWithFlags(&s->log_ev[i], hipEventDisableTiming) != hipSuccess) {
             set_error("fil_create: event creation failed");
             rc = FIL_EHIP;
@@ -776,12 +773,15 @@ int fil_bdf2_step(fil_sim* s, fil_step_report* report) {
     FIL_CHECK_ARG(s, "fil_bdf2_step: null sim");
     const int64_t ns = s->nsusp;
     s->bc = coefs(s->step);
-    s->nev = 0;
+    if (s->timing && s->nev >= kMaxPendingTimings) {
+        FIL_HIP_TRY(hipStreamSynchronize(s->st));
+        TRY(collect_timing(s));
+    }
     for (int64_t i = 0; i < ns; i++) s->active_h[i] = 1;
-    TRY(set_time(s));
-    TRY(upload_flags(s, s->active_d, s->active_h));
-    TRY(initial_guess_launch(s->d, s->step, s->Yj, s->Yjm1, s->Xj, s->Xjm1, s->active_d, s->X, s->st));
-    FIL_HIP_TRY(hipMemcpyAsync(s->X0p, s->X, 6 * s->S * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+    // one kernel starts the step: first iterate and its copy, every suspension running,
+    // the device log cleared, the time t^{j+1}
+    TRY(initial_guess_launch(s->d, s->step, s->Yj, s->Yjm1, s->Xj, s->Xjm1, s->X, s->X0p, s->active_d, s->log_d,
+                             s->time_d, s->t + s->p.dt, s->st));
     bool learned = s->use_mlp && s->mlp && s->step >= 3;
     if (learned) TRY(learned_guess(s));
     SolveLog L(ns);
@@ -793,6 +793,7 @@ int fil_bdf2_step(fil_sim* s, fil_step_report* report) {
         learned = false;
         for (int64_t i = 0; i < ns; i++) s->active_h[i] = 1;
         TRY(upload_flags(s, s->active_d, s->active_h));
+        FIL_HIP_TRY(hipMemsetAsync(s->log_d, 0, ns * sizeof(SuspLog), s->st));
         FIL_HIP_TRY(hipMemcpyAsync(s->X, s->X0p, 6 * s->S * sizeof(double), hipMemcpyDeviceToDevice, s->st));
         SolveLog L2(ns);
         TRY(solve(s, L2));
@@ -802,10 +803,6 @@ int fil_bdf2_step(fil_sim* s, fil_step_report* report) {
         }
         L = L2;
         all_ok = std::all_of(L.state.begin(), L.state.end(), [](int32_t v) { return v == 1; });
-    }
-    if (s->timing) {
-        FIL_HIP_TRY(hipStreamSynchronize(s->st));
-        TRY(collect_timing(s));
     }
     for (int64_t i = 0; i < ns && report; i++) {
         report[i].iters = L.iters[i];
@@ -824,11 +821,8 @@ int fil_bdf2_step(fil_sim* s, fil_step_report* report) {
                                 : "fil_bdf2_step: Broyden did not reach the tolerance; state left at the previous step");
         return nonfinite || L.singular ? FIL_ENONFINITE : FIL_ENOCONV;
     }
-    for (int64_t i = 0; i < ns; i++) s->commit_h[i] = 1;
-    TRY(upload_flags(s, s->commit_d, s->commit_h));
-    TRY(finalize_launch(s->d, s->commit_d, s->Yc, s->qc, s->X, s->Yj, s->Yjm1, s->qj, s->Xj, s->Xjm1, s->Xjm2,
-                        s->st));
-    FIL_HIP_TRY(hipStreamSynchronize(s->st));
+    // the commit stays queued on the stream (reads of the state synchronise first)
+    TRY(finalize_launch(s->d, nullptr, s->Yc, s->qc, s->X, s->Yj, s->Yjm1, s->qj, s->Xj, s->Xjm1, s->Xjm2, s->st));
     s->t += s->p.dt;
     s->step += 1;
     return FIL_OK;
@@ -887,6 +881,8 @@ int fil_set_timing(fil_sim* s, int enable) {
 
 int fil_get_timing(fil_sim* s, double* rpy_ms, int64_t* rpy_launches) {
     FIL_CHECK_ARG(s, "fil_get_timing: null sim");
+    FIL_HIP_TRY(hipStreamSynchronize(s->st));
+    TRY(collect_timing(s));
     for (int c = 0; c < 2; c++) {
         if (rpy_ms) rpy_ms[c] = s->rpy_ms[c];
         if (rpy_launches) rpy_launches[c] = s->rpy_launches[c];

@@ -70,12 +70,18 @@ int residual_launch(const SimDev& d, const BdfCoef& bc, const double* X, const d
 // the same dot products for a residual given by the caller
 int update_dots_launch(const SimDev& d, const double* fnew, const int32_t* active, const DotArgs& da,
                        hipStream_t st);
+// Per-suspension record of a solve run by the device
+struct SuspLog {
+    int32_t state;     // 0 running, 1 converged, -1 failed, -2 failed on a singular J0 block
+    int32_t it;        // last iteration tested
+    int32_t evals;     // residual evaluations (mobility applies)
+    int32_t evals_hi;  // of which in FP64
+    double last;       // max|f|/a of the last evaluation
+};
 // Convergence test of the evaluation just made, for iterations that run without the host
 // (captured in a graph).  log null: no test.
 struct JudgeArgs {
-    int32_t* log;   // [nsusp][4] state (0 running, 1 converged, -1 failed), last iteration, evaluations,
-                    // FP64 evaluations
-    double* last;   // [nsusp] max|f|/a of the last evaluation
+    SuspLog* log;                       // [nsusp]
     const unsigned long long* resbits;  // the maxima that evaluation left
     const int32_t* jflag;  // [M] singular-J0 flags (first step only; null: not checked): fail the suspension
     double tol, inv_a;
@@ -99,15 +105,21 @@ struct UpdateArgs {
     double *Yc, *qc, *F, *T, *box;
 };
 int broyden_state_launch(const SimDev& d, const UpdateArgs& u, const JudgeArgs& jg, int32_t* active, hipStream_t st);
+// Start of a step: the first iterate X0 (and its copy X0c) for every suspension, every
+// suspension marked running, the device log cleared and the device time set to tt.
 int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const double* Yjm1, const double* Xj,
-                         const double* Xjm1, const int32_t* active, double* X0, hipStream_t st);
+                         const double* Xjm1, double* X0, double* X0c, int32_t* active, SuspLog* log, double* time_d,
+                         double tt, hipStream_t st);
+// copies the device log to `out` (pinned host memory, written by the kernel)
+int log_export_launch(const SuspLog* log, int64_t ns, SuspLog* out, hipStream_t st);
 // J0 at X in row-differenced banded form (6N x kBandW per filament at 6*seg_off[f]*kBandW),
 // factorised with partial pivoting (ipiv at 6*seg_off[f]); flag[f] = 1 for a zero pivot
 // When AinvT is non-null the explicit inverse is also built (transposed, at dense_off[f]).
 int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* qc, const double* Tint,
                      double tt, const int32_t* active, double* AB, int32_t* ipiv, int32_t* flag, double* AinvT,
                      hipStream_t st);
-// commits the step: Y, q from the converged state; X history shifted (Xjm2 may be null)
+// commits the step of the suspensions flagged in commit (null: all): Y, q from the
+// converged state; X history shifted (Xjm2 may be null)
 int finalize_launch(const SimDev& d, const int32_t* commit, const double* Yc, const double* qc, const double* X,
                     double* Yj, double* Yjm1, double* qj, double* Xj, double* Xjm1, double* Xjm2, hipStream_t st);
 

@@ -459,13 +459,20 @@ int residual_launch(const SimDev& d, const BdfCoef& bc, const double* X, const d
 __global__ void __launch_bounds__(256) initial_guess_kernel(SimDev d, int64_t step, const double* __restrict__ Yj,
                                                           const double* __restrict__ Yjm1,
                                                           const double* __restrict__ Xj,
-                                                          const double* __restrict__ Xjm1,
-                                                          const int32_t* __restrict__ active,
-                                                          double* __restrict__ X0) {
+                                                          const double* __restrict__ Xjm1, double* __restrict__ X0,
+                                                          double* __restrict__ X0c, int32_t* __restrict__ active,
+                                                          SuspLog* __restrict__ log, double* __restrict__ time_d,
+                                                          double tt) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0) {
+        for (int64_t i = threadIdx.x; i < d.nsusp; i += blockDim.x) {
+            active[i] = 1;
+            log[i] = SuspLog{0, 0, 0, 0, 0.0};
+        }
+        if (threadIdx.x == 0) *time_d = tt;
+    }
     if (s >= d.S) return;
     const int32_t f = d.seg_fil[s];
-    if (!active[d.fil_susp[f]]) return;
     const int64_t s0 = d.seg_off[f], N = d.seg_off[f + 1] - s0, n = s - s0;
     const int teth = d.tether[f];
     // the six slots this segment owns: Y_1 / lambda_1 (n == 0) or Lambda_{n-1/2}, then u_n / lambda_2
@@ -482,15 +489,30 @@ __global__ void __launch_bounds__(256) initial_guess_kernel(SimDev d, int64_t st
             if (n == 0 && teth) x1 = step >= 2 ? 2.0 * Xj[r1 + i] - Xjm1[r1 + i] : Xj[r1 + i];
             else x1 = Xj[r1 + i];
         }
-        X0[r0 + i] = x0;
-        X0[r1 + i] = x1;
+        X0[r0 + i] = X0c[r0 + i] = x0;
+        X0[r1 + i] = X0c[r1 + i] = x1;
     }
 }
 
 int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const double* Yjm1, const double* Xj,
-                         const double* Xjm1, const int32_t* active, double* X0, hipStream_t st) {
-    if (d.S == 0) return FIL_OK;
-    initial_guess_kernel<<<(unsigned)ceil_div(d.S, 256), 256, 0, st>>>(d, step, Yj, Yjm1, Xj, Xjm1, active, X0);
+                         const double* Xjm1, double* X0, double* X0c, int32_t* active, SuspLog* log, double* time_d,
+                         double tt, hipStream_t st) {
+    initial_guess_kernel<<<(unsigned)std::max<int64_t>(1, ceil_div(d.S, 256)), 256, 0, st>>>(
+        d, step, Yj, Yjm1, Xj, Xjm1, X0, X0c, active, log, time_d, tt);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+__global__ void __launch_bounds__(256) log_export_kernel(const SuspLog* __restrict__ log, int64_t ns,
+                                                       SuspLog* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = log[i];
+    __threadfence_system();
+}
+
+int log_export_launch(const SuspLog* log, int64_t ns, SuspLog* out, hipStream_t st) {
+    log_export_kernel<<<(unsigned)std::min<int64_t>(64, std::max<int64_t>(1, ceil_div(ns, 256))), 256, 0, st>>>(
+        log, ns, out);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }
@@ -1110,20 +1132,18 @@ __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs 
         else if (jg.it >= jg.kmax) state = -1;
         if (jg.jflag && jg.jflag[f] && threadIdx.x == 0) {
             // singular J0 block: the suspension fails (every such workgroup writes the same)
-            jg.log[4 * isus] = -1;
+            jg.log[isus].state = -2;
             active[isus] = 0;
         }
         if (jg.jflag && jg.jflag[f]) return;
         if (threadIdx.x == 0 && f == d.susp_fil_off[isus]) {
-            int32_t* L = jg.log + 4 * isus;
-            L[1] = jg.it;
-            L[2] += 1;
-            L[3] += jg.can_converge;
-            jg.last[isus] = r;
-            if (state) {
-                L[0] = state;
-                active[isus] = 0;
-            }
+            SuspLog& L = jg.log[isus];
+            L.it = jg.it;
+            L.evals += 1;
+            L.evals_hi += jg.can_converge;
+            L.last = r;
+            if (state && L.state == 0) L.state = state;
+            if (state) active[isus] = 0;
         }
         if (state) return;
     }
@@ -1265,7 +1285,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(SimDev d, const int32_t* 
                                                      double* __restrict__ Xjm2) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= d.S) return;
-    if (!commit[d.fil_susp[d.seg_fil[s]]]) return;
+    if (commit && !commit[d.fil_susp[d.seg_fil[s]]]) return;
     const int64_t S = d.S;
     for (int i = 0; i < 3; i++) {
         Yjm1[i * S + s] = Yj[i * S + s];
