@@ -37,6 +37,7 @@ struct fil_sim {
     double *X = nullptr, *f = nullptr, *fprev = nullptr;
     double *Yc = nullptr, *qc = nullptr, *F = nullptr, *T = nullptr, *V = nullptr, *W = nullptr;
     double *AB = nullptr, *AinvT = nullptr, *Chist = nullptr, *Dhist = nullptr, *part = nullptr;
+    double* rdiag = nullptr;  // reciprocal pivots of the band factor [6S]
     double* box = nullptr;
     double* spar = nullptr;  // [nsusp][kSpar]
     int32_t *ipiv = nullptr, *active_d = nullptr, *jflag_d = nullptr;
@@ -228,8 +229,8 @@ int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipE
 
 // Broyden update k (k < 0: the first step) from the residual fnew, then the state at the new X
 UpdateArgs update_args(fil_sim* s, int k, const double* fnew, double* dXout) {
-    return UpdateArgs{k,        s->AB,    s->ipiv, s->AinvT, s->part, s->Chist, s->Dhist, fnew, s->fprev,
-                      s->X,     dXout,    s->qj,   s->time_d, s->Yc,  s->qc,    s->F,     s->T, s->box};
+    return UpdateArgs{k,     s->AB,    s->ipiv, s->rdiag, s->AinvT, s->part, s->Chist, s->Dhist, fnew, s->fprev,
+                      s->X,  dXout,    s->qj,   s->time_d, s->Yc,   s->qc,   s->F,     s->T,     s->box};
 }
 
 // max|f|/a and max|b dt (V, dexpinv Omega)| per suspension of the last evaluation
@@ -261,8 +262,8 @@ int upload_flags(fil_sim* s, int32_t* dst, const int32_t* src) {
 // (and inverted explicitly when the inverses fit)
 int begin_solve(fil_sim* s) {
     const double tt = s->t + s->p.dt;
-    TRY(j0_factor_launch(s->d, s->bc, s->X, s->qc, s->T, tt, s->active_d, s->AB, s->ipiv, s->jflag_d, s->AinvT,
-                         s->st));
+    TRY(j0_factor_launch(s->d, s->bc, s->X, s->qc, s->T, tt, s->active_d, s->AB, s->ipiv, s->rdiag, s->jflag_d,
+                         s->AinvT, s->st));
     s->k = 0;
     return FIL_OK;
 }
@@ -603,7 +604,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     A(s->Yj, 3 * S) A(s->Yjm1, 3 * S) A(s->qj, 4 * S) A(s->Xj, n6) A(s->Xjm1, n6) A(s->Xjm2, n6) A(s->X0p, n6)
     A(s->X, n6) A(s->f, n6) A(s->fprev, n6)
     A(s->Yc, 3 * S) A(s->qc, 4 * S) A(s->F, 3 * S) A(s->T, 3 * S) A(s->V, 3 * S) A(s->W, 3 * S)
-    A(s->AB, n6 * kBandW) A(s->ipiv, n6)
+    A(s->AB, n6 * kBandW) A(s->ipiv, n6) A(s->rdiag, n6)
     if (dense) { A(s->AinvT, dense_tot) A(d_dense_off, M) }
     A(s->Chist, (size_t)p->kmax * n6) A(s->Dhist, (size_t)p->kmax * n6) A(s->part, (size_t)M * max_dots)
     A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->time_d, 1) A(s->log_d, nsusp)

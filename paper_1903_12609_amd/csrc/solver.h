@@ -92,6 +92,7 @@ struct UpdateArgs {
     int k;
     const double* AB;      // band factor (used when AinvT is null)
     const int32_t* ipiv;
+    const double* rdiag;   // reciprocal pivots of the band factor
     const double* AinvT;   // explicit inverses, or null
     const double* dpart;   // partial dot products of update k
     double* Chist;         // [kmax][6S]
@@ -116,8 +117,8 @@ int log_export_launch(const SuspLog* log, int64_t ns, SuspLog* out, hipStream_t 
 // factorised with partial pivoting (ipiv at 6*seg_off[f]); flag[f] = 1 for a zero pivot
 // When AinvT is non-null the explicit inverse is also built (transposed, at dense_off[f]).
 int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* qc, const double* Tint,
-                     double tt, const int32_t* active, double* AB, int32_t* ipiv, int32_t* flag, double* AinvT,
-                     hipStream_t st);
+                     double tt, const int32_t* active, double* AB, int32_t* ipiv, double* rdiag, int32_t* flag,
+                     double* AinvT, hipStream_t st);
 // commits the step of the suspensions flagged in commit (null: all): Y, q from the
 // converged state; X history shifted (Xjm2 may be null)
 int finalize_launch(const SimDev& d, const int32_t* commit, const double* Yc, const double* qc, const double* X,

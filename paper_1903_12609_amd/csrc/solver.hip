@@ -753,7 +753,7 @@ __global__ void __launch_bounds__(256) j0_band_assemble_kernel(SimDev d, BdfCoef
 constexpr int kFacAhead = 4;
 __global__ void __launch_bounds__(64) j0_band_factor_regs_kernel(SimDev d, const int32_t* __restrict__ active,
                                                                double* __restrict__ AB, int32_t* __restrict__ ipiv,
-                                                               int32_t* __restrict__ flag) {
+                                                               double* __restrict__ rdiag, int32_t* __restrict__ flag) {
     constexpr int kWin = kKL + kKU + 1;  // window columns (17)
     const int64_t f = blockIdx.x;
     if (!active[d.fil_susp[f]]) return;
@@ -808,6 +808,7 @@ __global__ void __launch_bounds__(64) j0_band_factor_regs_kernel(SimDev d, const
         if (lw && j + l < n) ab[(int64_t)j * kBandW + kKL + l] = W[0];
         if (l == 0) {
             gp[j] = j + pr;
+            rdiag[6 * s0 + j] = rp;
 #pragma unroll
             for (int r = 1; r <= kKL; r++)
                 if (j + r < n) ab[(int64_t)(j + r) * kBandW + kKL - r] = m[r];
@@ -925,6 +926,7 @@ __device__ __forceinline__ double diff_unit(int c, int i, int N) {
 template <int CB>
 __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const double* __restrict__ AB,
                                                             const int32_t* __restrict__ ipiv,
+                                                            const double* __restrict__ rdiag,
                                                             const int32_t* __restrict__ active,
                                                             double* __restrict__ AinvT, int64_t coff) {
     constexpr int kU = kKL + kKU;
@@ -935,18 +937,23 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
     const int n = 6 * N;
     const int c0 = blockIdx.y * CB;
     if (c0 >= n) return;
-    // LDS: the filament's band factor [n][kBandW] | forward results [n][CB] | pivots [n]
+    // LDS: the filament's band factor [n][kBandW] | forward results [n][CB] | reciprocal
+    // pivots [n] | pivot rows [n]
     extern __shared__ double lds[];
     double* ab = lds;
     double* ybuf = lds + (size_t)n * kBandW;
-    int* ip = reinterpret_cast<int*>(ybuf + (size_t)n * CB);
+    double* rd = ybuf + (size_t)n * CB;
+    int* ip = reinterpret_cast<int*>(rd + n);
     const int t = threadIdx.x;
     const int c = c0 + t;
     const bool live = t < CB && c < n;
     {
         const double* gab = AB + 6 * s0 * kBandW;
         for (int e = t; e < n * kBandW; e += blockDim.x) ab[e] = gab[e];
-        for (int e = t; e < n; e += blockDim.x) ip[e] = ipiv[6 * s0 + e];
+        for (int e = t; e < n; e += blockDim.x) {
+            ip[e] = ipiv[6 * s0 + e];
+            rd[e] = rdiag[6 * s0 + e];
+        }
         __syncthreads();
     }
     auto rhs = [&](int i) { return (live && i < n) ? diff_unit(c, i, N) : 0.0; };
@@ -997,7 +1004,7 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
     }
     auto load_bwd = [&](int i, double (&Uv)[kU + 1]) {
         const double* row = ab + (int64_t)i * kBandW + kKL;  // U(i-k, i) = row[k - k*kBandW]
-        Uv[0] = 1.0 / row[0];
+        Uv[0] = rd[i];
 #pragma unroll
         for (int k = 1; k <= kU; k++) Uv[k] = i - k >= 0 ? row[k - (int64_t)k * kBandW] : 0.0;
     };
@@ -1043,11 +1050,11 @@ int allow_lds(Kernel kernel, size_t bytes) {
 }
 
 int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* qc, const double* Tint,
-                     double tt, const int32_t* active, double* AB, int32_t* ipiv, int32_t* flag, double* AinvT,
-                     hipStream_t st) {
+                     double tt, const int32_t* active, double* AB, int32_t* ipiv, double* rdiag, int32_t* flag,
+                     double* AinvT, hipStream_t st) {
     if (d.M == 0) return FIL_OK;
     j0_band_assemble_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, bc, X, qc, Tint, tt, active, AB);
-    j0_band_factor_regs_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, active, AB, ipiv, flag);
+    j0_band_factor_regs_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, active, AB, ipiv, rdiag, flag);
     // filaments grouped by size so that each launch's LDS fits its own largest filament
     for (int k = 0; k < d.ncls; k++) {
         const int64_t coff = d.cls_off[k], cnt = d.cls_off[k + 1] - coff;
@@ -1056,19 +1063,19 @@ int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const 
         if (!AinvT) continue;
         // one thread per inverse column; a block's columns (64, 32 or 16, so that its
         // band, pivots and forward results fit in LDS) share the staged factor
-        auto lds = [nc](int cb) { return (size_t)nc * (kBandW + cb) * sizeof(double) + (size_t)nc * sizeof(int); };
+        auto lds = [nc](int cb) { return (size_t)nc * (kBandW + cb + 1) * sizeof(double) + (size_t)nc * sizeof(int); };
         if (nc <= 128) {
             const dim3 grid((unsigned)cnt, (unsigned)ceil_div(nc, 64));
             if (int rc = allow_lds(j0_inverse_cols_kernel<64>, lds(64))) return rc;
-            j0_inverse_cols_kernel<64><<<grid, 64, lds(64), st>>>(d, AB, ipiv, active, AinvT, coff);
+            j0_inverse_cols_kernel<64><<<grid, 64, lds(64), st>>>(d, AB, ipiv, rdiag, active, AinvT, coff);
         } else if (nc <= 256) {
             const dim3 grid((unsigned)cnt, (unsigned)ceil_div(nc, 32));
             if (int rc = allow_lds(j0_inverse_cols_kernel<32>, lds(32))) return rc;
-            j0_inverse_cols_kernel<32><<<grid, 64, lds(32), st>>>(d, AB, ipiv, active, AinvT, coff);
+            j0_inverse_cols_kernel<32><<<grid, 64, lds(32), st>>>(d, AB, ipiv, rdiag, active, AinvT, coff);
         } else {
             const dim3 grid((unsigned)cnt, (unsigned)ceil_div(nc, 16));
             if (int rc = allow_lds(j0_inverse_cols_kernel<16>, lds(16))) return rc;
-            j0_inverse_cols_kernel<16><<<grid, 64, lds(16), st>>>(d, AB, ipiv, active, AinvT, coff);
+            j0_inverse_cols_kernel<16><<<grid, 64, lds(16), st>>>(d, AB, ipiv, rdiag, active, AinvT, coff);
         }
     }
     FIL_HIP_TRY(hipGetLastError());
@@ -1185,7 +1192,7 @@ __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs 
         const double* ab = u.AB + e0 * kBandW;
         for (int i = t; i < n; i += NT) {
             y[i] = diff_rhs(sf, i, N);
-            rd[i] = 1.0 / ab[(int64_t)i * kBandW + kKL];
+            rd[i] = u.rdiag[e0 + i];
             ip[i] = u.ipiv[e0 + i];
         }
         __syncthreads();
