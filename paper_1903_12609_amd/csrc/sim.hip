@@ -59,6 +59,7 @@ struct fil_sim {
         int rb_end = 0;
     };
     int graph_iters = 0;  // iterations per captured block; 0 runs every iteration from the host
+    int pred_iters = 0;   // iterations the last device-driven solve took (0: none yet)
     hipStream_t cap_st = nullptr;  // private stream the blocks are captured on (launches go to st)
     std::map<std::array<int, 5>, GraphEntry> graphs;
     SuspLog* log_d = nullptr;  // device log of the current solve [nsusp]
@@ -338,13 +339,18 @@ struct SolveLog {
 // Graph blocks from iteration `it` until every suspension has ended (the device log
 // holds the counts so far).  The next block is launched before the log of the
 // previous one is read, so the GPU never waits for the host; a block launched after
-// the end runs only kernels that find their suspension finished.
+// the end runs only kernels that find their suspension finished.  Blocks are full
+// up to the iteration count of the previous solve and single iterations beyond it,
+// which bounds that waste.
 int device_iterations(fil_sim* s, SolveLog& L, int it) {
     const int64_t ns = s->nsusp;
+    const int pred = s->pred_iters;
     int pending = 0, wslot = 0, rslot = 0;
     for (;;) {
         while (pending < 2 && it <= s->p.kmax) {
-            const int U = std::min(s->graph_iters, s->p.kmax - it + 1);
+            int U = s->graph_iters;
+            if (pred > 0) U = it <= pred ? std::min(U, pred - it + 1) : 1;
+            U = std::min(U, s->p.kmax - it + 1);
             TRY(graph_block(s, it, U));
             it += U;
             s->k += U;
@@ -370,6 +376,7 @@ int device_iterations(fil_sim* s, SolveLog& L, int it) {
         pending--;
         if (!any) break;
     }
+    s->pred_iters = *std::max_element(L.iters.begin(), L.iters.end());
     return FIL_OK;
 }
 
