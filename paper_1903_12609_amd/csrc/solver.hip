@@ -35,6 +35,14 @@ __device__ __forceinline__ void stq(double* __restrict__ q, int64_t S, int64_t s
     q[3 * S + s] = x.z;
 }
 
+// lane l receives lane l+1's value, lane 63 zero: a DPP shift of the whole wave
+// by one lane (VALU only, no LDS round trip)
+__device__ __forceinline__ double wave_next_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
 // wave-uniform lane read of a double (the lane index must be uniform)
 __device__ __forceinline__ double readlane_f64(double v, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -771,61 +779,84 @@ __global__ void __launch_bounds__(64) j0_band_factor_regs_kernel(SimDev d, const
     double W[kKL + 1];
 #pragma unroll
     for (int r = 0; r <= kKL; r++) W[r] = at(r, l);
-    double Q[kFacAhead];  // rows kKL+1 .. kKL+kFacAhead of this lane's future columns
+    // queue of the rows kKL+1 .. kKL+kFacAhead of this lane's future columns: each load
+    // is unconditional (a clamped address inside the filament's band) and its validity
+    // is applied when the value is used, so the load can stay in flight until then
+    auto at_queued = [&](int r, int c, bool& ok) {
+        ok = lw && r < n && c < n && c - r >= -kKL && c - r <= kKL + kKU;
+        return ab[ok ? (int64_t)r * kBandW + (c - r + kKL) : 0];
+    };
+    double Q[kFacAhead];
+    bool Qok[kFacAhead];
 #pragma unroll
-    for (int q = 0; q < kFacAhead; q++) Q[q] = at(kKL + 1 + q, l + 1 + q);
+    for (int q = 0; q < kFacAhead; q++) Q[q] = at_queued(kKL + 1 + q, l + 1 + q, Qok[q]);
     int bad = 0;
-    for (int j = 0; j < n; j++) {
-        // pivot column j (lane 0) broadcast to the wave
-        double col[kKL + 1];
+    // unrolled by the queue depth: slot qs is consumed at steps j = qs (mod depth) and
+    // refilled in place, so each row load has kFacAhead steps to arrive
+    for (int j0 = 0; j0 < n; j0 += kFacAhead) {
 #pragma unroll
-        for (int r = 0; r <= kKL; r++) col[r] = readlane_f64(W[r], 0);
-        int pr = 0;
-        double best = fabs(col[0]);
+        for (int qs = 0; qs < kFacAhead; qs++) {
+            const int j = j0 + qs;
+            if (j >= n) break;
+                // pivot column j (lane 0) broadcast to the wave
+                double col[kKL + 1];
 #pragma unroll
-        for (int r = 1; r <= kKL; r++)
-            if (fabs(col[r]) > best) {
-                best = fabs(col[r]);
-                pr = r;
-            }
-        if (!(best > 0.0)) bad = 1;
-        if (pr != 0) {
-            const double w0 = W[0], c0 = col[0];
+                for (int r = 0; r <= kKL; r++) col[r] = readlane_f64(W[r], 0);
+                int pr = 0;
+                double best = fabs(col[0]);
 #pragma unroll
-            for (int r = 1; r <= kKL; r++)
-                if (pr == r) {
-                    W[0] = W[r];
-                    W[r] = w0;
-                    col[0] = col[r];
-                    col[r] = c0;
+                for (int r = 1; r <= kKL; r++)
+                    if (fabs(col[r]) > best) {
+                        best = fabs(col[r]);
+                        pr = r;
+                    }
+                if (!(best > 0.0)) bad = 1;
+                // row exchange (wave-uniform; rare for these blocks, so a scalar branch)
+                if (__builtin_expect(pr != 0, 0)) {
+                    const double w0 = W[0], c0 = col[0];
+                    switch (pr) {
+        #define FIL_SWAP_ROW(r)      \
+            case r:                  \
+                W[0] = W[r];         \
+                W[r] = w0;           \
+                col[0] = col[r];     \
+                col[r] = c0;         \
+                break;
+                        FIL_SWAP_ROW(1) FIL_SWAP_ROW(2) FIL_SWAP_ROW(3) FIL_SWAP_ROW(4)
+                        FIL_SWAP_ROW(5) FIL_SWAP_ROW(6) FIL_SWAP_ROW(7) FIL_SWAP_ROW(8)
+        #undef FIL_SWAP_ROW
+                        default: break;
+                    }
                 }
+                const double rp = 1.0 / col[0];
+                double m[kKL + 1];
+#pragma unroll
+                for (int r = 1; r <= kKL; r++) m[r] = col[r] * rp;
+                // final row j of U (lanes 0..16) and column j of L (lane r holds m[r]).  The
+                // stores are unconditional so that the memory counter stays static and the
+                // queued row loads remain in flight: a lane with nothing to store writes the
+                // reciprocal pivot to its slot, as every lane does.
+                double* const rslot = rdiag + 6 * s0 + j;
+                const bool su = lw && j + l < n;
+                *(su ? ab + (int64_t)j * kBandW + kKL + l : rslot) = su ? W[0] : rp;
+                double ml = 0.0;
+#pragma unroll
+                for (int r = 1; r <= kKL; r++) ml = l == r ? m[r] : ml;
+                const bool sm = l >= 1 && l <= kKL && j + l < n;
+                *(sm ? ab + (int64_t)(j + l) * kBandW + kKL - l : rslot) = sm ? ml : rp;
+                gp[j] = j + pr;
+                // rank-1 update of the window's lower rows (lane 0's column is done)
+#pragma unroll
+                for (int r = 1; r <= kKL; r++) W[r] = fma(-m[r], W[0], W[r]);
+                // shift: lane l takes column j+1+l, rows j+1 .. j+1+kKL (lanes past the window hold
+                // zeros, which is what rows j+1 .. j+kKL of column j+1+kKL+kKU are: beyond the
+                // original upper bandwidth and untouched so far); the entering bottom row comes
+                // from the queue, refilled with the row needed kFacAhead shifts later
+#pragma unroll
+                for (int r = 0; r < kKL; r++) W[r] = wave_next_f64(W[r + 1]);
+                W[kKL] = Qok[qs] ? Q[qs] : 0.0;
+                Q[qs] = at_queued(j + 1 + kKL + kFacAhead, j + 1 + kFacAhead + l, Qok[qs]);
         }
-        const double rp = 1.0 / col[0];
-        double m[kKL + 1];
-#pragma unroll
-        for (int r = 1; r <= kKL; r++) m[r] = col[r] * rp;
-        // final row j of U (lanes 0..16) and column j of L (lane 0)
-        if (lw && j + l < n) ab[(int64_t)j * kBandW + kKL + l] = W[0];
-        if (l == 0) {
-            gp[j] = j + pr;
-            rdiag[6 * s0 + j] = rp;
-#pragma unroll
-            for (int r = 1; r <= kKL; r++)
-                if (j + r < n) ab[(int64_t)(j + r) * kBandW + kKL - r] = m[r];
-        }
-        // rank-1 update of the window's lower rows (lane 0's column is done)
-#pragma unroll
-        for (int r = 1; r <= kKL; r++) W[r] = fma(-m[r], W[0], W[r]);
-        // shift: lane l takes column j+1+l, rows j+1 .. j+1+kKL (lanes past the window hold
-        // zeros, which is what rows j+1 .. j+kKL of column j+1+kKL+kKU are: beyond the
-        // original upper bandwidth and untouched so far); the entering bottom row comes
-        // from the queue, refilled with the row needed kFacAhead shifts later
-#pragma unroll
-        for (int r = 0; r < kKL; r++) W[r] = __shfl_down(W[r + 1], 1, 64);
-        W[kKL] = Q[0];
-#pragma unroll
-        for (int q = 0; q + 1 < kFacAhead; q++) Q[q] = Q[q + 1];
-        Q[kFacAhead - 1] = at(j + 1 + kKL + kFacAhead, j + 1 + kFacAhead + l);
     }
     if (l == 0) flag[f] = bad;
 }
@@ -840,31 +871,40 @@ constexpr int kSweepAhead = 6;
 __device__ __forceinline__ void band_sweeps(const double* __restrict__ ab, const int* ip, const double* rd, double* y,
                                             int n, int lane) {
     double w = (lane < 16 && lane < n) ? y[lane] : 0.0;
-    auto fwd_mult = [&](int jj) {
+    // queued coefficients are loaded unconditionally (clamped address) and masked when
+    // used, so each load stays in flight for kSweepAhead steps
+    auto fwd_mult = [&](int jj, bool& ok) {
         const int off = (lane - (jj & 15)) & 15;
-        if (!(lane < 16 && off >= 1 && off <= kKL && jj + off < n)) return 0.0;
-        return ab[(int64_t)(jj + off) * kBandW + (kKL - off)];
+        ok = lane < 16 && off >= 1 && off <= kKL && jj + off < n;
+        return ab[ok ? (int64_t)(jj + off) * kBandW + (kKL - off) : 0];
     };
     double Lq[kSweepAhead];
+    bool Lok[kSweepAhead];
 #pragma unroll
-    for (int q = 0; q < kSweepAhead; q++) Lq[q] = fwd_mult(q);
+    for (int q = 0; q < kSweepAhead; q++) Lq[q] = fwd_mult(q, Lok[q]);
     int ipn = ip[0];
     double yin = y[min(16, n - 1)];
-    for (int j = 0; j < n; j++) {
-        const int h = j & 15;
-        const int hp = __builtin_amdgcn_readfirstlane(ipn) & 15;
-        const double L = Lq[0];
+    // unrolled by the queue depth: slot q is consumed at steps j = q (mod depth) and
+    // refilled in place, so each load has kSweepAhead steps to arrive
+    for (int j0 = 0; j0 < n; j0 += kSweepAhead) {
 #pragma unroll
-        for (int q = 0; q + 1 < kSweepAhead; q++) Lq[q] = Lq[q + 1];
-        Lq[kSweepAhead - 1] = fwd_mult(j + kSweepAhead);
-        const double yi = j + 16 < n ? yin : 0.0;
-        ipn = ip[min(j + 1, n - 1)];
-        yin = y[min(j + 17, n - 1)];
-        const double vh = readlane_f64(w, h), vp = readlane_f64(w, hp);
-        w = lane == hp ? vh : w;
-        w -= L * vp;  // vp: the pivot row now at the head; L = 0 off the kKL entries below it
-        y[j] = vp;
-        w = lane == h ? yi : w;
+        for (int q = 0; q < kSweepAhead; q++) {
+            const int j = j0 + q;
+            if (j < n) {
+                const int h = j & 15;
+                const int hp = __builtin_amdgcn_readfirstlane(ipn) & 15;
+                const double L = Lok[q] ? Lq[q] : 0.0;
+                Lq[q] = fwd_mult(j + kSweepAhead, Lok[q]);
+                const double yi = j + 16 < n ? yin : 0.0;
+                ipn = ip[min(j + 1, n - 1)];
+                yin = y[min(j + 17, n - 1)];
+                const double vh = readlane_f64(w, h), vp = readlane_f64(w, hp);
+                w = lane == hp ? vh : w;
+                w -= L * vp;  // vp: the pivot row now at the head; L = 0 off the kKL entries below it
+                y[j] = vp;
+                w = lane == h ? yi : w;
+            }
+        }
     }
     constexpr int kU = kKL + kKU;
     w = 0.0;
@@ -872,27 +912,32 @@ __device__ __forceinline__ void band_sweeps(const double* __restrict__ ab, const
         const int pos = (n - 1) - (((n - 1) - lane) & 31);
         w = pos >= 0 ? y[pos] : 0.0;
     }
-    auto bwd_coef = [&](int ii) {
+    auto bwd_coef = [&](int ii, bool& ok) {
         const int off = ((ii & 31) - lane) & 31;
-        if (!(lane < 32 && off >= 1 && off <= kU && ii - off >= 0)) return 0.0;
-        return ab[(int64_t)(ii - off) * kBandW + (off + kKL)];
+        ok = lane < 32 && off >= 1 && off <= kU && ii - off >= 0;
+        return ab[ok ? (int64_t)(ii - off) * kBandW + (off + kKL) : 0];
     };
     double Uq[kSweepAhead];
+    bool Uok[kSweepAhead];
 #pragma unroll
-    for (int q = 0; q < kSweepAhead; q++) Uq[q] = bwd_coef(n - 1 - q);
+    for (int q = 0; q < kSweepAhead; q++) Uq[q] = bwd_coef(n - 1 - q, Uok[q]);
     double zin = y[max(n - 33, 0)];
-    for (int i = n - 1; i >= 0; i--) {
-        const int h = i & 31;
-        const double U = Uq[0], dv = rd[i];
+    for (int i0 = n - 1; i0 >= 0; i0 -= kSweepAhead) {
 #pragma unroll
-        for (int q = 0; q + 1 < kSweepAhead; q++) Uq[q] = Uq[q + 1];
-        Uq[kSweepAhead - 1] = bwd_coef(i - kSweepAhead);
-        const double zi = i - 32 >= 0 ? zin : 0.0;
-        zin = y[max(i - 33, 0)];
-        const double xi = readlane_f64(w, h) * dv;
-        w -= U * xi;  // U = 0 off the kKL + kKU entries above the head
-        y[i] = xi;
-        w = lane == h ? zi : w;
+        for (int q = 0; q < kSweepAhead; q++) {
+            const int i = i0 - q;
+            if (i >= 0) {
+                const int h = i & 31;
+                const double U = Uok[q] ? Uq[q] : 0.0, dv = rd[i];
+                Uq[q] = bwd_coef(i - kSweepAhead, Uok[q]);
+                const double zi = i - 32 >= 0 ? zin : 0.0;
+                zin = y[max(i - 33, 0)];
+                const double xi = readlane_f64(w, h) * dv;
+                w -= U * xi;  // U = 0 off the kKL + kKU entries above the head
+                y[i] = xi;
+                w = lane == h ? zi : w;
+            }
+        }
     }
 }
 
