@@ -964,10 +964,33 @@ __device__ __forceinline__ double diff_unit(int c, int i, int N) {
 // columns c = g*cb + t of filament f's J0^{-1}, one per thread: the thread
 // solves (D J0) y = D e_c (D the row differencing) through the band factor
 // with its column held in a sliding register window (kKL + 1 rows forward,
-// kKL + kKU + 1 rows backward), so each sweep step is a few FMAs on registers;
-// the band coefficients and pivots, staged in LDS, are the same for all threads.
-// Forward results wait in LDS for the backward sweep, whose results are then
-// written as row c of Ainv^T with coalesced stores.
+// kKL + kKU + 1 rows backward), so each sweep step is a few FMAs on registers.
+// The band (between zero rows, so that no coefficient read needs a bounds test),
+// the reciprocal pivots and the pivot rows are staged in LDS and shared by all
+// threads; the pivot row is wave-uniform.  Forward results wait in LDS for the
+// backward sweep, whose results are then written as row c of Ainv^T.
+// zero band rows before / after the filament: the prefetches one step past either end stay inside
+constexpr int kInvPadLo = kKL + kKU + 1, kInvPadHi = kKL + 1;
+
+// the (at most two) nonzero entries of D e_c in the interleaved order, c in the
+// original unknown order: Y_1 and the multipliers are row-differenced, u is not
+__device__ __forceinline__ void diff_unit_nonzeros(int c, int N, int& ia, double& va, int& ib, double& vb) {
+    ia = ib = -1;
+    va = 1.0;
+    vb = -1.0;
+    if (c < 3) {  // Y_1: block row 0, and minus in block row 2 (the first multiplier difference)
+        ia = c;
+        if (N >= 2) ib = 6 + c;
+    } else if (c < 3 + 3 * N) {  // u_k: block row 2k + 1
+        const int k = (c - 3) / 3, a = (c - 3) % 3;
+        ia = 3 * (2 * k + 1) + a;
+    } else {  // Lambda_q: plus in block row 2q + 2, minus in block row 2q + 4
+        const int q = (c - 3 - 3 * N) / 3, a = (c - 3 - 3 * N) % 3;
+        ia = 3 * (2 * q + 2) + a;
+        if (q + 2 <= N - 1) ib = 3 * (2 * q + 4) + a;
+    }
+}
+
 template <int CB>
 __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const double* __restrict__ AB,
                                                             const int32_t* __restrict__ ipiv,
@@ -982,11 +1005,12 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
     const int n = 6 * N;
     const int c0 = blockIdx.y * CB;
     if (c0 >= n) return;
-    // LDS: the filament's band factor [n][kBandW] | forward results [n][CB] | reciprocal
+    // LDS: band rows [-kInvPadLo, n + kInvPadHi) | forward results [n][CB] | reciprocal
     // pivots [n] | pivot rows [n]
     extern __shared__ double lds[];
-    double* ab = lds;
-    double* ybuf = lds + (size_t)n * kBandW;
+    const int nrows = n + kInvPadLo + kInvPadHi;
+    double* ab = lds + (size_t)kInvPadLo * kBandW;  // ab[i * kBandW + k] for i in [-kInvPadLo, n + kInvPadHi)
+    double* ybuf = lds + (size_t)nrows * kBandW;
     double* rd = ybuf + (size_t)n * CB;
     int* ip = reinterpret_cast<int*>(rd + n);
     const int t = threadIdx.x;
@@ -994,45 +1018,55 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
     const bool live = t < CB && c < n;
     {
         const double* gab = AB + 6 * s0 * kBandW;
-        for (int e = t; e < n * kBandW; e += blockDim.x) ab[e] = gab[e];
+        for (int e = t; e < nrows * kBandW; e += blockDim.x) {
+            const int r = e / kBandW - kInvPadLo;
+            lds[e] = (r >= 0 && r < n) ? gab[(int64_t)r * kBandW + e % kBandW] : 0.0;
+        }
         for (int e = t; e < n; e += blockDim.x) {
             ip[e] = ipiv[6 * s0 + e];
             rd[e] = rdiag[6 * s0 + e];
         }
         __syncthreads();
     }
-    auto rhs = [&](int i) { return (live && i < n) ? diff_unit(c, i, N) : 0.0; };
+    int ia, ib;
+    double va, vb;
+    diff_unit_nonzeros(live ? c : 0, N, ia, va, ib, vb);
+    if (!live) ia = ib = -1;
+    auto rhs = [&](int i) { return (i == ia ? va : 0.0) + (i == ib ? vb : 0.0); };
     // ---- forward: W[k] = y[j + k]
     double W[kKL + 1];
 #pragma unroll
     for (int k = 0; k <= kKL; k++) W[k] = rhs(k);
-    // the next step's pivot and multipliers are requested before this step's arithmetic
-    auto load_fwd = [&](int j, double (&Lv)[kKL + 1], int& pv) {
-        const double* col = ab + (int64_t)j * kBandW + kKL;  // L(j+k, j) = col[k*(kBandW-1)]
-        pv = ip[j] - j;                                       // 0..kKL, the same for every thread
-#pragma unroll
-        for (int k = 1; k <= kKL; k++) Lv[k] = j + k < n ? col[k * (kBandW - 1)] : 0.0;
-    };
+    // the next step's pivot and multipliers are read before this step's arithmetic
     double Lc[kKL + 1], Ln[kKL + 1];
     int pc, pn = 0;
+    auto load_fwd = [&](int j, double (&Lv)[kKL + 1], int& pv) {
+        const double* col = ab + (int64_t)j * kBandW + kKL;  // L(j+k, j) = col[k*(kBandW-1)] (zero rows past n)
+        pv = __builtin_amdgcn_readfirstlane(ip[min(j, n - 1)]) - j;  // 0..kKL, the same for every thread
+#pragma unroll
+        for (int k = 1; k <= kKL; k++) Lv[k] = col[k * (kBandW - 1)];
+    };
     load_fwd(0, Lc, pc);
     for (int j = 0; j < n; j++) {
-        if (j + 1 < n) load_fwd(j + 1, Ln, pn);
-        if (pc != 0) {
+        load_fwd(j + 1, Ln, pn);
+        if (__builtin_expect(pc != 0, 0)) {
             const double w0 = W[0];
-#pragma unroll
-            for (int k = 1; k <= kKL; k++)
-                if (pc == k) {
-                    W[0] = W[k];
-                    W[k] = w0;
-                }
+            switch (pc) {
+#define FIL_SWAP_W(k)  \
+    case k:            \
+        W[0] = W[k];   \
+        W[k] = w0;     \
+        break;
+                FIL_SWAP_W(1) FIL_SWAP_W(2) FIL_SWAP_W(3) FIL_SWAP_W(4)
+                FIL_SWAP_W(5) FIL_SWAP_W(6) FIL_SWAP_W(7) FIL_SWAP_W(8)
+#undef FIL_SWAP_W
+                default: break;
+            }
         }
         const double yj = W[0];
-#pragma unroll
-        for (int k = 1; k <= kKL; k++) W[k] = fma(-Lc[k], yj, W[k]);
         if (t < CB) ybuf[(int64_t)j * CB + t] = yj;
 #pragma unroll
-        for (int k = 0; k < kKL; k++) W[k] = W[k + 1];
+        for (int k = 0; k < kKL; k++) W[k] = fma(-Lc[k + 1], yj, W[k + 1]);
         W[kKL] = rhs(j + kKL + 1);
 #pragma unroll
         for (int k = 1; k <= kKL; k++) Lc[k] = Ln[k];
@@ -1048,23 +1082,23 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
         B[k] = (r >= 0 && t < CB) ? ybuf[(int64_t)r * CB + t] : 0.0;
     }
     auto load_bwd = [&](int i, double (&Uv)[kU + 1]) {
-        const double* row = ab + (int64_t)i * kBandW + kKL;  // U(i-k, i) = row[k - k*kBandW]
-        Uv[0] = rd[i];
+        const double* row = ab + (int64_t)i * kBandW + kKL;  // U(i-k, i) = row[k - k*kBandW] (zero rows before 0)
+        Uv[0] = rd[max(i, 0)];
 #pragma unroll
-        for (int k = 1; k <= kU; k++) Uv[k] = i - k >= 0 ? row[k - (int64_t)k * kBandW] : 0.0;
+        for (int k = 1; k <= kU; k++) Uv[k] = row[k - (int64_t)k * kBandW];
     };
     double Uc[kU + 1], Un[kU + 1];
     load_bwd(i0, Uc);
+    const int tt = t < CB ? t : 0;
     for (int i = i0; i >= 0; i--) {
-        if (i > 0) load_bwd(i - 1, Un);
+        load_bwd(i - 1, Un);
+        const int r = i - kU - 1;
+        const double bnext = ybuf[(int64_t)max(r, 0) * CB + tt];
         const double xi = B[kU] * Uc[0];
 #pragma unroll
-        for (int k = 1; k <= kU; k++) B[kU - k] = fma(-Uc[k], xi, B[kU - k]);
+        for (int k = kU; k > 0; k--) B[k] = fma(-Uc[kU - k + 1], xi, B[k - 1]);
         if (t < CB) ybuf[(int64_t)i * CB + t] = xi;
-#pragma unroll
-        for (int k = kU; k > 0; k--) B[k] = B[k - 1];
-        const int r = i - kU - 1;
-        B[0] = (r >= 0 && t < CB) ? ybuf[(int64_t)r * CB + t] : 0.0;
+        B[0] = r >= 0 ? bnext : 0.0;
 #pragma unroll
         for (int k = 0; k <= kU; k++) Uc[k] = Un[k];
     }
@@ -1108,7 +1142,10 @@ int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const 
         if (!AinvT) continue;
         // one thread per inverse column; a block's columns (64, 32 or 16, so that its
         // band, pivots and forward results fit in LDS) share the staged factor
-        auto lds = [nc](int cb) { return (size_t)nc * (kBandW + cb + 1) * sizeof(double) + (size_t)nc * sizeof(int); };
+        auto lds = [nc](int cb) {
+            return ((size_t)(nc + kInvPadLo + kInvPadHi) * kBandW + (size_t)nc * (cb + 1)) * sizeof(double) +
+                   (size_t)nc * sizeof(int);
+        };
         if (nc <= 128) {
             const dim3 grid((unsigned)cnt, (unsigned)ceil_div(nc, 64));
             if (int rc = allow_lds(j0_inverse_cols_kernel<64>, lds(64))) return rc;
