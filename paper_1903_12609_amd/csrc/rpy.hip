@@ -84,7 +84,7 @@ __device__ __forceinline__ Ovl<R> rpy_overlap(R rx, R ry, R rz, R r2, R Fx, R Fy
 }
 
 __device__ __forceinline__ void rpy_pair_f64(const double y[3], const double (&s)[15], double a, double four_a2,
-                                             double two_a2, AccF64& A) {
+                                             double two_a2, bool self, AccF64& A) {
     const double rx = y[0] - s[0], ry = y[1] - s[1], rz = y[2] - s[2];
     const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
     const bool near = r2 < four_a2;
@@ -117,8 +117,9 @@ __device__ __forceinline__ void rpy_pair_f64(const double y[3], const double (&s
     A.Hw[0] = fma(D, rx, A.Hw[0]);
     A.Hw[1] = fma(D, ry, A.Hw[1]);
     A.Hw[2] = fma(D, rz, A.Hw[2]);
-    if (near) {
-        // overlap: added to G (velocity), subtracted from U (angular velocity)
+    if (near && !self) {
+        // overlap: added to G (velocity), subtracted from U (angular velocity); the self
+        // pair is added once per target after the loop
         const Ovl<double> o = rpy_overlap<double>(rx, ry, rz, r2, Fx, Fy, Fz, Tx, Ty, Tz, a);
         for (int i = 0; i < 3; i++) {
             A.G[i] += o.v[i];
@@ -231,10 +232,21 @@ __device__ __forceinline__ void rpy_item_f64(int64_t base, int64_t S, int64_t Sg
             double nxt[15];
             for (int i = 0; i < 15; i++) nxt[i] = src[16 * mn + i];
 #pragma unroll
-            for (int j = 0; j < TPL; j++) rpy_pair_f64(y[j], cur, a, four_a2, two_a2, A[j]);
+            for (int j = 0; j < TPL; j++) rpy_pair_f64(y[j], cur, a, four_a2, two_a2, m0 + m == n[j], A[j]);
             for (int i = 0; i < 15; i++) cur[i] = nxt[i];
         }
     }
+    // the self pair (r = 0 in the overlap forms): 4/(3a) F and T / a^3
+#pragma unroll
+    for (int j = 0; j < TPL; j++)
+        if (n[j] >= m0 && n[j] < m1) {
+            const double* sr = pk + 16 * (base + n[j]);
+            const double cv = 4.0 / (3.0 * a), cw = 1.0 / (a * a * a);
+            for (int i = 0; i < 3; i++) {
+                A[j].G[i] = fma(cv, sr[3 + i], A[j].G[i]);
+                A[j].U[i] = fma(-cw, sr[6 + i], A[j].U[i]);
+            }
+        }
     const double c23 = 2.0 * a * a / 3.0;
     double vw[TPL][6];
 #pragma unroll
@@ -301,7 +313,7 @@ __device__ __forceinline__ SrcRegF32 load_src_f32(const SrcF32* __restrict__ s) 
     return r;
 }
 __device__ __forceinline__ void rpy_pair_f32(const double y[3], const SrcRegF32& s, float a, float four_a2,
-                                             float two_a2, float c23, float v[3], float w[3]) {
+                                             float two_a2, float c23, bool self, float v[3], float w[3]) {
     const float rx = (float)(y[0] - s.y[0]);
     const float ry = (float)(y[1] - s.y[1]);
     const float rz = (float)(y[2] - s.y[2]);
@@ -324,7 +336,7 @@ __device__ __forceinline__ void rpy_pair_f32(const double y[3], const SrcRegF32&
     w[0] = fmaf(E, Tx, fmaf(D, qx, fmaf(Fy, qz, fmaf(-Fz, qy, w[0]))));
     w[1] = fmaf(E, Ty, fmaf(D, qy, fmaf(Fz, qx, fmaf(-Fx, qz, w[1]))));
     w[2] = fmaf(E, Tz, fmaf(D, qz, fmaf(Fx, qy, fmaf(-Fy, qx, w[2]))));
-    if (near) {
+    if (near && !self) {
         const Ovl<float> o = rpy_overlap<float>(rx, ry, rz, r2, Fx, Fy, Fz, Tx, Ty, Tz, a);
         for (int i = 0; i < 3; i++) {
             v[i] += o.v[i];
@@ -378,7 +390,8 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
         for (int i = 0; i < cnt; ++i) {
             const SrcRegF32 nxt = load_src_f32(ts + (i + 1 < cnt ? i + 1 : i));
 #pragma unroll
-            for (int j = 0; j < TPL; j++) rpy_pair_f32(y[j], cur, af, four_a2, two_a2, c23, v[j], w[j]);
+            for (int j = 0; j < TPL; j++)
+                rpy_pair_f32(y[j], cur, af, four_a2, two_a2, c23, t0 + i == n[j], v[j], w[j]);
             cur = nxt;
         }
 #pragma unroll
@@ -388,6 +401,17 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
                 wd[j][i] += (double)w[j][i];
             }
     }
+    // the self pair (r = 0 in the overlap forms): 4/(3a) F and T / a^3, in double
+#pragma unroll
+    for (int j = 0; j < TPL; j++)
+        if (n[j] >= m0 && n[j] < m1) {
+            const SrcF32& sr = pk[base + n[j]];
+            const double cv = 4.0 / (3.0 * a), cw = 1.0 / (a * a * a);
+            for (int i = 0; i < 3; i++) {
+                vd[j][i] = fma(cv, (double)sr.f[i], vd[j][i]);
+                wd[j][i] = fma(cw, (double)sr.t[i], wd[j][i]);
+            }
+        }
     double vw[TPL][6];
 #pragma unroll
     for (int j = 0; j < TPL; j++)
