@@ -62,10 +62,11 @@ __device__ __forceinline__ V3 joint_kappa(const SimDev& d, int64_t f, int64_t k,
 // q_n = exp(u_n) q^j_n, t_n, robot-arm positions Y_n = Y_1 + dL/2 sum_{m<n} (t_m + t_{m+1})
 // and the filament's bounding box, then F = F^C + gravity (+ lambda_1),
 // T = T^C + T^E (+ lambda_2).  Every thread of the workgroup calls it (it holds a
-// barrier); lane n of the first wave owns segment n (N <= 64).  Nothing may follow
-// it in the caller that needs a barrier.
-__device__ void filament_state(const SimDev& d, int64_t f, const double* Xf, const double* __restrict__ qj,
-                               double tt, double* __restrict__ Yc, double* __restrict__ qc, double* __restrict__ F,
+// barrier); lane n of the first wave owns segment n (N <= 64) and passes q^j_n (read
+// by the caller, possibly well before).  Nothing may follow it in the caller that
+// needs a barrier.
+__device__ void filament_state(const SimDev& d, int64_t f, const double* Xf, Q4 qjn, double tt,
+                               double* __restrict__ Yc, double* __restrict__ qc, double* __restrict__ F,
                                double* __restrict__ T, double* __restrict__ box) {
     const int64_t S = d.S;
     const int64_t s0 = d.seg_off[f];
@@ -78,7 +79,7 @@ __device__ void filament_state(const SimDev& d, int64_t f, const double* Xf, con
     if (seg) {
         V3 u = ldx(Xf, 3 + 3 * n);
         if (teth && n == 0) u = v3(0, 0, 0);
-        const Q4 q = qmul(qexp(u), ldq(qj, S, s0 + n));
+        const Q4 q = qmul(qexp(u), qjn);
         stq(qc, S, s0 + n, q);
         sq[n][0] = q.w; sq[n][1] = q.x; sq[n][2] = q.y; sq[n][3] = q.z;
         const V3 t = frame_t(q);
@@ -153,8 +154,11 @@ __global__ void __launch_bounds__(64) state_forces_kernel(SimDev d, const double
                                                         double* __restrict__ box) {
     const int64_t f = blockIdx.x;
     if (!active[d.fil_susp[f]]) return;
+    const int64_t s0 = d.seg_off[f];
+    const int N = (int)(d.seg_off[f + 1] - s0);
+    const Q4 qjn = threadIdx.x < N ? ldq(qj, d.S, s0 + threadIdx.x) : Q4{1.0, 0.0, 0.0, 0.0};
     // t^{j+1} is read on the device so that captured launches stay valid
-    filament_state(d, f, X + 6 * d.seg_off[f], qj, *ttp, Yc, qc, F, T, box);
+    filament_state(d, f, X + 6 * s0, qjn, *ttp, Yc, qc, F, T, box);
 }
 
 int state_forces_launch(const SimDev& d, const double* X, const double* qj, const double* tt, const int32_t* active,
@@ -186,6 +190,13 @@ __global__ void __launch_bounds__(64 * kStericWaves) steric_pack_kernel(SimDev d
     const bool valid = lane < N;
     const int64_t sn = s0 + (valid ? lane : N - 1);
     const double y0 = Yc[sn], y1 = Yc[S + sn], y2 = Yc[2 * S + sn];
+    // the forces and torques for the source record are read now, used at the end
+    double Fp[3] = {0.0, 0.0, 0.0}, Tp[3] = {0.0, 0.0, 0.0};
+    if (wave == 0)
+        for (int i = 0; i < 3; i++) {
+            Fp[i] = F[i * S + sn];
+            Tp[i] = T[i * S + sn];
+        }
     double fx = 0, fy = 0, fz = 0;
     const double FS = d.spar[kSpar * isus + 4];
     if (FS != 0.0) {
@@ -263,13 +274,13 @@ __global__ void __launch_bounds__(64 * kStericWaves) steric_pack_kernel(SimDev d
         fy += red[w][1][lane];
         fz += red[w][2][lane];
     }
-    fx += F[sn];
-    fy += F[S + sn];
-    fz += F[2 * S + sn];
+    fx += Fp[0];
+    fy += Fp[1];
+    fz += Fp[2];
     F[sn] = fx;
     F[S + sn] = fy;
     F[2 * S + sn] = fz;
-    rpy_pack_record(prec, pk, sn, y0, y1, y2, fx, fy, fz, T[sn], T[S + sn], T[2 * S + sn]);
+    rpy_pack_record(prec, pk, sn, y0, y1, y2, fx, fy, fz, Tp[0], Tp[1], Tp[2]);
 }
 
 int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, const int32_t* active, double* F,
@@ -355,6 +366,36 @@ __global__ void __launch_bounds__(NT) residual_kernel(SimDev d, BdfCoef bc, cons
     __shared__ double sv[6][kMaxSeg];
     __shared__ double sf[6 * kMaxSeg];
     __shared__ double red[lds_rows(NT)];
+    // read ahead: the residual inputs of the first wave's segment, and each wave's
+    // terms of its first two dot products for the first 128 rows
+    const int n = threadIdx.x;
+    const bool seg = n < N;
+    const int teth = d.tether[f];
+    V3 ycur = v3(0, 0, 0), yold = v3(0, 0, 0), yold2 = v3(0, 0, 0), uu = v3(0, 0, 0), uj = v3(0, 0, 0);
+    if (seg) {
+        const int64_t s = s0 + n;
+        ycur = ld3(Yc, S, s);
+        yold = ld3(Yj, S, s);
+        yold2 = ld3(Yjm1, S, s);
+        uu = ldx(X + 6 * s0, 3 + 3 * n);
+        uj = ldx(Xj + 6 * s0, 3 + 3 * n);
+    }
+    constexpr int NW = NT / 64;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t e0 = 6 * s0, n6 = 6 * S;
+    const int nd = da.k + 2;
+    const int h0 = wave, h1 = wave + NW;
+    const bool dpre = NT >= 1024 && da.k >= 0 && ni <= 128;  // uniform (1024-thread form only)
+    double dt0[2] = {0.0, 0.0}, dt1[2] = {0.0, 0.0}, fpv[2] = {0.0, 0.0};
+    if (dpre) {
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            const int e = min(lane + 64 * r, ni - 1);  // clamped; rows past ni are not used
+            fpv[r] = da.fprev[e0 + e];
+            if (h0 < da.k) dt0[r] = da.Dhist[(int64_t)h0 * n6 + e0 + e];
+            if (h1 < da.k) dt1[r] = da.Dhist[(int64_t)h1 * n6 + e0 + e];
+        }
+    }
     if (part) {
         // R threads per item, thread q summing partials q, q + R, ...
         const int R = max(1, min(kSplit, NT / ni));
@@ -390,19 +431,15 @@ __global__ void __launch_bounds__(NT) residual_kernel(SimDev d, BdfCoef bc, cons
         }
     }
     __syncthreads();
-    const int n = threadIdx.x;
     if (n < 64) {
         double amax = 0.0, vmax = 0.0;
-        if (n < N) {
-            const int64_t s = s0 + n;
-            const int teth = d.tether[f];
+        if (seg) {
             const double bdt = bc.b * d.spar[kSpar * isus];
-            const double* Xf = X + 6 * s0;
             double* ff = fout + 6 * s0;
             const V3 vel = v3(sv[0][n], sv[1][n], sv[2][n]);
             const V3 om = v3(sv[3][n], sv[4][n], sv[5][n]);
-            const V3 yres = ld3(Yc, S, s) - bc.a1 * ld3(Yj, S, s) - bc.a2 * ld3(Yjm1, S, s) - bdt * vel;
-            V3 u = ldx(Xf, 3 + 3 * n), uj = ldx(Xj + 6 * s0, 3 + 3 * n);
+            const V3 yres = ycur - bc.a1 * yold - bc.a2 * yold2 - bdt * vel;
+            V3 u = uu;
             if (teth && n == 0) u = uj = v3(0, 0, 0);
             const V3 dom = dexpinv(u, om);
             const V3 ures = u - bc.g * uj - bdt * dom;
@@ -439,7 +476,46 @@ __global__ void __launch_bounds__(NT) residual_kernel(SimDev d, BdfCoef bc, cons
     }
     if (da.k < 0) return;
     __syncthreads();
-    filament_dots<NT>(d, f, da, sf, ni);
+    if (!dpre) {
+        filament_dots<NT>(d, f, da, sf, ni);
+        return;
+    }
+    // the first pass from the terms read ahead (ni <= 128: two rows per lane), then any
+    // further dots as in filament_dots
+    auto term = [&](int h, int r, double dterm) {
+        const int e = lane + 64 * r;
+        if (e >= ni) return 0.0;
+        const double fn = sf[e];
+        if (h < da.k) return dterm * fn;
+        const double df = fn - fpv[r];
+        return df * (h == da.k ? df : fn);
+    };
+    if (h0 < nd) {
+        double a0 = term(h0, 0, dt0[0]) + term(h0, 1, dt0[1]);
+        double a1 = h1 < nd ? term(h1, 0, dt1[0]) + term(h1, 1, dt1[1]) : 0.0;
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        if (lane == 0) {
+            da.dpart[f * d.max_dots + h0] = a0;
+            if (h1 < nd) da.dpart[f * d.max_dots + h1] = a1;
+        }
+    }
+    for (int g0 = wave + 2 * NW; g0 < nd; g0 += 2 * NW) {
+        const int g1 = g0 + NW;
+        double a0 = 0.0, a1 = 0.0;
+        for (int r = 0; r < 2; r++) {
+            const int e = lane + 64 * r;
+            if (e >= ni) continue;
+            a0 += term(g0, r, g0 < da.k ? da.Dhist[(int64_t)g0 * n6 + e0 + e] : 0.0);
+            if (g1 < nd) a1 += term(g1, r, g1 < da.k ? da.Dhist[(int64_t)g1 * n6 + e0 + e] : 0.0);
+        }
+        a0 = wave_sum(a0);
+        a1 = wave_sum(a1);
+        if (lane == 0) {
+            da.dpart[f * d.max_dots + g0] = a0;
+            if (g1 < nd) da.dpart[f * d.max_dots + g1] = a1;
+        }
+    }
 }
 
 // workgroup size of the per-filament kernels: 1024 threads (more loads in flight per
@@ -1165,32 +1241,6 @@ int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const 
 }
 
 // ---------------------------------------------------------------- Broyden update + state
-// out_i = sum_c Ainv^T[c][i] v_c (explicit J0^{-1} of one filament, n rows) by the
-// workgroup: P = min(kSplit, NT / n) threads per row over contiguous column ranges,
-// their sums combined in a fixed order.  Holds a barrier.
-template <int NT>
-__device__ void dense_apply(const double* __restrict__ A, const double* v, double* out, int n, double* red) {
-    const int t = threadIdx.x;
-    const int P = max(1, min(kSplit, NT / n));
-    for (int e = t; e < P * n; e += NT) {
-        const int p = e / n, i = e - p * n;
-        const int cb = (n * p) / P, ce = (n * (p + 1)) / P;
-        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int c = cb;
-        for (; c + 8 <= ce; c += 8)
-#pragma unroll
-            for (int q = 0; q < 8; q++) a[q] = fma(A[(int64_t)(c + q) * n + i], v[c + q], a[q]);
-        for (; c < ce; c++) a[0] = fma(A[(int64_t)c * n + i], v[c], a[0]);
-        red[e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-    }
-    __syncthreads();
-    for (int i = t; i < n; i += NT) {
-        double acc = red[i];
-        for (int p = 1; p < P; p++) acc += red[p * n + i];
-        out[i] = acc;
-    }
-}
-
 // One workgroup per filament, after the residual kernel of the same evaluation:
 //  1. with a judge: the convergence test of the filament's suspension from the
 //     maxima the residual kernel left (max|f|/a <= tol ends it when this evaluation
@@ -1200,12 +1250,20 @@ __device__ void dense_apply(const double* __restrict__ A, const double* v, doubl
 //     its suspension.
 //  2. the suspension's dot products, summed over its filaments in a fixed order (so
 //     every workgroup of the suspension holds the same values);
-//  3. g = J0^{-1} f for the filament's rows: explicit inverse, or the banded sweeps
-//     by the first wave;
-//  4. the bad-Broyden update (Alg. 2): g += sum_{h<k} c_h (d_h . f);
-//     c_k = -g/|df|, d_k = df/|df|, step = g + c_k (d_k . f), or for the first step
-//     (k < 0) step = g; then fprev <- f and X <- X - step;
+//  3. g = J0^{-1} f for the filament's rows: explicit inverse (P threads per row over
+//     contiguous column ranges), or the banded sweeps by the first wave;
+//  4. the bad-Broyden update (Alg. 2): g += sum_{h<k} c_h (d_h . f) (R threads per row,
+//     thread q over h = q, q + R, ...); c_k = -g/|df|, d_k = df/|df|,
+//     step = g + c_k (d_k . f), or for the first step (k < 0) step = g; then
+//     fprev <- f and X <- X - step;
 //  5. the configuration and internal forces at the new X.
+// Every load that does not depend on the kernel's own results (the thread's columns of
+// the inverse and history terms when they fit in registers, the rows of f, fprev and
+// X, q^j) is issued first, so the phases do not wait for memory one after another.
+// Partial sums are combined in a fixed order.
+constexpr int kPreCols = 16;  // inverse columns per thread held in registers
+constexpr int kPreHist = 4;   // history terms per thread held in registers
+
 template <int NT>
 __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs u, JudgeArgs jg,
                                                          int32_t* __restrict__ active) {
@@ -1213,6 +1271,39 @@ __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs 
     const int64_t f = blockIdx.x;
     const int32_t isus = d.fil_susp[f];
     if (!active[isus]) return;
+    const int64_t s0 = d.seg_off[f];
+    const int N = (int)(d.seg_off[f + 1] - s0);
+    const int n = 6 * N;
+    const int64_t e0 = 6 * s0, n6 = 6 * d.S;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    // threads per row (inverse columns, history terms); P <= n keeps every column range non-empty
+    const int P = max(1, min(min(kSplit, NT / n), n));
+    const int pq = t / n, pi = t - pq * n;      // this thread's share: part pq of row pi
+    const bool part_thr = t < P * n;
+    // ---- loads issued before any use
+    const double* A = u.AinvT ? u.AinvT + d.dense_off[f] : nullptr;
+    const int cb = (n * pq) / P, ce = (n * (pq + 1)) / P;
+    // (only in the 1024-thread form, used for few filaments: the register cost would
+    // lower the occupancy the many-filament form relies on)
+    const bool areg = NT >= 1024 && A && P * n <= NT && (n + P - 1) / P <= kPreCols;  // uniform
+    double ap[kPreCols];
+    if (areg && part_thr) {
+#pragma unroll
+        for (int q = 0; q < kPreCols; q++) ap[q] = A[(int64_t)min(cb + q, ce - 1) * n + pi];  // masked at use
+    }
+    const bool hreg = NT >= 1024 && P * n <= NT && u.k <= kPreHist * P;  // uniform
+    double hp[kPreHist];
+    if (hreg && part_thr && u.k > 0) {
+#pragma unroll
+        for (int m = 0; m < kPreHist; m++) hp[m] = u.Chist[(int64_t)min(pq + m * P, u.k - 1) * n6 + e0 + pi];
+    }
+    double fr = 0.0, fp = 0.0, xr = 0.0;
+    if (t < n) {
+        fr = u.fnew[e0 + t];
+        fp = u.fprev[e0 + t];
+        xr = u.X[e0 + t];
+    }
+    const Q4 qjn = t < N ? ldq(u.qj, d.S, s0 + t) : Q4{1.0, 0.0, 0.0, 0.0};
     if (jg.log) {
         const double r = __longlong_as_double((long long)jg.resbits[isus]) * jg.inv_a;
         int32_t state = 0;
@@ -1236,15 +1327,10 @@ __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs 
         }
         if (state) return;
     }
-    const int64_t s0 = d.seg_off[f];
-    const int N = (int)(d.seg_off[f + 1] - s0);
-    const int n = 6 * N;
-    const int64_t e0 = 6 * s0, n6 = 6 * d.S;
-    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     __shared__ double sf[6 * kMaxSeg], sg[6 * kMaxSeg], sx[6 * kMaxSeg];
     __shared__ double sdots[kMaxDots];
     __shared__ double red[lds_rows(NT)];
-    for (int e = t; e < n; e += NT) sf[e] = u.fnew[e0 + e];
+    for (int e = t; e < n; e += NT) sf[e] = e == t ? fr : u.fnew[e0 + e];
     if (u.k >= 0) {
         // dot h by wave h mod NW, two per pass, over the filaments' partials in order
         const int64_t g0 = d.susp_fil_off[isus], g1 = d.susp_fil_off[isus + 1];
@@ -1265,8 +1351,35 @@ __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs 
         }
     }
     __syncthreads();
-    if (u.AinvT) {
-        dense_apply<NT>(u.AinvT + d.dense_off[f], sf, sg, n, red);
+    if (A) {
+        // g_i = sum_c Ainv^T[c][i] f_c
+        for (int e = t; e < P * n; e += NT) {
+            const int p = e / n, i = e - p * n;
+            const int c1 = (n * p) / P, c2 = (n * (p + 1)) / P;
+            double acc = 0.0;
+            if (areg) {
+                double a8[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q < kPreCols; q++)
+                    if (c1 + q < c2) a8[q & 3] = fma(ap[q], sf[c1 + q], a8[q & 3]);
+                acc = (a8[0] + a8[1]) + (a8[2] + a8[3]);
+            } else {
+                double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                int c = c1;
+                for (; c + 8 <= c2; c += 8)
+#pragma unroll
+                    for (int q = 0; q < 8; q++) a8[q] = fma(A[(int64_t)(c + q) * n + i], sf[c + q], a8[q]);
+                for (; c < c2; c++) a8[0] = fma(A[(int64_t)c * n + i], sf[c], a8[0]);
+                acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
+            }
+            red[e] = acc;
+        }
+        __syncthreads();
+        for (int i = t; i < n; i += NT) {
+            double acc = red[i];
+            for (int p = 1; p < P; p++) acc += red[p * n + i];
+            sg[i] = acc;
+        }
     } else {
         // L f in the interleaved order, then the sweeps through the band factor
         __shared__ double y[6 * kMaxSeg], rd[6 * kMaxSeg];
@@ -1284,53 +1397,59 @@ __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs 
     }
     __syncthreads();
     if (u.k >= 0) {
-        // sum_{h<k} c_h (d_h . f) per row: R threads per row, thread q over h = q, q + R, ...
-        const int R = max(1, min(kSplit, NT / n));
-        for (int e = t; e < R * n; e += NT) {
+        // sum_{h<k} c_h (d_h . f) per row
+        for (int e = t; e < P * n; e += NT) {
             const int q = e / n, i = e - q * n;
-            const int64_t ge = e0 + i;
-            double a0 = 0.0, a1 = 0.0;
-            int h = q;
-            for (; h + R < u.k; h += 2 * R) {
-                a0 = fma(u.Chist[(int64_t)h * n6 + ge], sdots[h], a0);
-                a1 = fma(u.Chist[(int64_t)(h + R) * n6 + ge], sdots[h + R], a1);
+            double acc = 0.0;
+            if (hreg) {
+                double a2[2] = {0.0, 0.0};
+#pragma unroll
+                for (int m = 0; m < kPreHist; m++) {
+                    const int h = q + m * P;
+                    if (h < u.k) a2[m & 1] = fma(hp[m], sdots[h], a2[m & 1]);
+                }
+                acc = a2[0] + a2[1];
+            } else {
+                double a0 = 0.0, a1 = 0.0;
+                int h = q;
+                for (; h + P < u.k; h += 2 * P) {
+                    a0 = fma(u.Chist[(int64_t)h * n6 + e0 + i], sdots[h], a0);
+                    a1 = fma(u.Chist[(int64_t)(h + P) * n6 + e0 + i], sdots[h + P], a1);
+                }
+                if (h < u.k) a0 = fma(u.Chist[(int64_t)h * n6 + e0 + i], sdots[h], a0);
+                acc = a0 + a1;
             }
-            if (h < u.k) a0 = fma(u.Chist[(int64_t)h * n6 + ge], sdots[h], a0);
-            red[e] = a0 + a1;
+            red[e] = acc;
         }
         __syncthreads();
-        const double nrm = sqrt(sdots[u.k]);
-        const double inrm = nrm > 0.0 ? 1.0 / nrm : 0.0;
-        const double dfdot = sdots[u.k + 1] * inrm;
-        for (int e = t; e < n; e += NT) {
-            const int64_t ge = e0 + e;
+    }
+    for (int e = t; e < n; e += NT) {
+        const int64_t ge = e0 + e;
+        // rows past the first NT were not read ahead
+        const double fe = e == t ? fr : sf[e], pe = e == t ? fp : u.fprev[ge], xe = e == t ? xr : u.X[ge];
+        double hn;
+        if (u.k >= 0) {
+            const double nrm = sqrt(sdots[u.k]);
+            const double inrm = nrm > 0.0 ? 1.0 / nrm : 0.0;
+            const double dfdot = sdots[u.k + 1] * inrm;
             double g = red[e];
-            for (int q = 1; q < R; q++) g += red[q * n + e];
+            for (int q = 1; q < P; q++) g += red[q * n + e];
             g += sg[e];
-            const double fn = sf[e];
             const double c = -g * inrm;
             u.Chist[(int64_t)u.k * n6 + ge] = c;
-            u.Dhist[(int64_t)u.k * n6 + ge] = (fn - u.fprev[ge]) * inrm;
-            const double hn = fma(c, dfdot, g);
-            u.fprev[ge] = fn;
-            const double xn = u.X[ge] - hn;
-            u.X[ge] = xn;
-            sx[e] = xn;
-            if (u.dXout) u.dXout[ge] = -hn;
+            u.Dhist[(int64_t)u.k * n6 + ge] = (fe - pe) * inrm;
+            hn = fma(c, dfdot, g);
+        } else {
+            hn = sg[e];
         }
-    } else {
-        for (int e = t; e < n; e += NT) {
-            const int64_t ge = e0 + e;
-            const double hn = sg[e];
-            u.fprev[ge] = sf[e];
-            const double xn = u.X[ge] - hn;
-            u.X[ge] = xn;
-            sx[e] = xn;
-            if (u.dXout) u.dXout[ge] = -hn;
-        }
+        u.fprev[ge] = fe;
+        const double xn = xe - hn;
+        u.X[ge] = xn;
+        sx[e] = xn;
+        if (u.dXout) u.dXout[ge] = -hn;
     }
     __syncthreads();
-    filament_state(d, f, sx, u.qj, *u.tt, u.Yc, u.qc, u.F, u.T, u.box);
+    filament_state(d, f, sx, qjn, *u.tt, u.Yc, u.qc, u.F, u.T, u.box);
 }
 
 int broyden_state_launch(const SimDev& d, const UpdateArgs& u, const JudgeArgs& jg, int32_t* active, hipStream_t st) {

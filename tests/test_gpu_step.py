@@ -118,6 +118,34 @@ def test_trajectory_parity(name, steps, j0_mode):
         assert np.abs(gap).max() <= 1e-13 * w.params["dL"] + 8 * np.finfo(float).eps * np.abs(Y).max()
 
 
+def _ragged():
+    """Filaments of 1, 2, 7, 20, 33 and 64 segments in one suspension: the smallest and
+    largest sizes of the per-filament kernels beside ordinary ones."""
+    rng = np.random.default_rng(23)
+    Ns = [1, 2, 64, 7, 20, 33]
+    fil_off, Y, q = synth._place(rng, len(Ns), Ns, 80.0, 0.02)
+    params, _ = synth.sedimentation_params(20, 1e3, 1 / 30, 1e-6, 100, steric=True)
+    return synth.Workload("ragged", fil_off, Y, q, params)
+
+
+@pytest.mark.parametrize("j0_mode,graph", [("dense", 0), ("banded", 0), ("dense", 3)])
+def test_ragged_filament_sizes(j0_mode, graph):
+    """Protocol as test_trajectory_parity, 6 steps, for filaments of 1 to 64 segments."""
+    import paper_1903_12609_amd as fil
+    print("case ragged", j0_mode, graph, flush=True)
+    w = _ragged()
+    o = oracle.Sim(w.fil_off, w.Y, w.q, nthreads=8, **w.params)
+    g = fil.Sim(w.fil_off, w.Y, w.q, w.params, j0_mode=j0_mode, graph=graph)
+    for j in range(6):
+        rc, rep = o.step()
+        assert rc == 0
+        r = g.step()[0]
+        assert r["converged"] and r["resid"] <= w.params["tol"]
+        assert r["iters"] == rep.iters, (j, r["iters"], rep.iters)
+    Y, q, X = g.read_state()
+    assert rel_l2(Y, o.Y) <= 1e-8 and rel_l2(q, o.q) <= 1e-8, (rel_l2(Y, o.Y), rel_l2(q, o.q))
+
+
 def test_trajectory_tight_tolerance():
     """At tol 1e-11 the converged roots agree independently of iteration counts."""
     w = WL["single15"]
