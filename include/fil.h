@@ -191,6 +191,16 @@ int fil_get_state(fil_sim* sim, const double** Y, const double** q, const double
  * any may be NULL. */
 int fil_read_state(fil_sim* sim, double* Y, double* q, double* Xj);
 
+/* Checkpoint of the committed state (time, step count, Y^j, Y^{j-1}, q^j, X^j,
+ * X^{j-1}, X^{j-2} and the per-suspension parameters) to a file (HOST path), and
+ * its restore into a simulation created with the same filament and suspension
+ * layout; a restored simulation continues exactly as the saved one would (Broyden
+ * histories do not outlive a step).  Synchronises the stream.  FIL_EINVAL when the
+ * file cannot be opened, written or read, is not a checkpoint, belongs to another
+ * layout or holds non-finite values; the simulation is then unchanged. */
+int fil_checkpoint(fil_sim* sim, const char* path);
+int fil_restore(fil_sim* sim, const char* path);
+
 /* Timing of the mobility pair kernel inside fil_bdf2_step: when enabled, HIP
  * events on the simulation's stream bracket every launch of the main pair
  * kernel; fil_get_timing returns the summed duration (ms) and the launch count
@@ -243,6 +253,11 @@ typedef struct fil_mlp fil_mlp;
  * n_seg outside [2, 64], width not a multiple of 32, depth outside [1, 16]. */
 int fil_mlp_create(int32_t n_seg, int32_t width, int32_t depth, int32_t max_batch, uint64_t seed, fil_mlp** out);
 void fil_mlp_destroy(fil_mlp* mlp);
+/* The FP32 master parameters and the normalisation to a file (HOST path), and back
+ * into a network of the same architecture (batch capacity may differ; Adam moments
+ * restart).  Synchronising.  FIL_EINVAL on an unreadable, incomplete or mismatched file. */
+int fil_mlp_save(const fil_mlp* mlp, const char* path);
+int fil_mlp_load(fil_mlp* mlp, const char* path);
 /* dims (HOST int32[8]): n_in, n_in_pad, n_out, n_out_pad, width, depth, max_batch, n_seg;
  * n_params: length of the flat parameter vector.  Either may be NULL. */
 int fil_mlp_dims(const fil_mlp* mlp, int32_t* dims, int64_t* n_params);

@@ -7,6 +7,8 @@ the C ABI declared in ``include/fil.h``.
 """
 from __future__ import annotations
 
+import os
+
 from ._native import FilError, PREC, check, lib  # noqa: F401
 
 __all__ = ["FilError", "MLP", "Sim", "rpy_mobility_apply", "rpy_mobility_apply_batched", "rpy_workspace_bytes",
@@ -216,6 +218,14 @@ class Sim:
         check(lib().fil_read_state(self._h, vp(Y), vp(q), vp(X)))
         return Y, q, X
 
+    def checkpoint(self, path):
+        """Committed state and per-suspension parameters to a file (synchronising)."""
+        check(lib().fil_checkpoint(self._h, os.fsencode(path)))
+
+    def restore(self, path):
+        """State from a checkpoint of a simulation with the same layout."""
+        check(lib().fil_restore(self._h, os.fsencode(path)))
+
     def time_step(self):
         import ctypes
         t, st = ctypes.c_double(), ctypes.c_int64()
@@ -300,6 +310,14 @@ class MLP:
         P = np.ascontiguousarray(P, dtype=np.float32)
         assert P.size == self.n_params
         check(lib().fil_mlp_set_params(self._h, P.ctypes.data))
+
+    def save(self, path):
+        """Parameters and normalisation to a file."""
+        check(lib().fil_mlp_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        """Parameters and normalisation from a file of a network of the same architecture."""
+        check(lib().fil_mlp_load(self._h, os.fsencode(path)))
 
     def get_norm(self):
         import numpy as np

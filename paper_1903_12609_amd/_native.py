@@ -65,6 +65,8 @@ def _declare(L):
         L.fil_get_state.argtypes = [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
                                     C.POINTER(_i64), C.POINTER(_d), C.POINTER(_i64)]
         L.fil_read_state.argtypes = [_vp, _vp, _vp, _vp]
+        L.fil_checkpoint.argtypes = [_vp, C.c_char_p]
+        L.fil_restore.argtypes = [_vp, C.c_char_p]
         L.fil_set_stream.argtypes = [_vp, _vp]
         L.fil_set_suspension_params.argtypes = [_vp, _vp, _vp, _vp]
         L.fil_set_graph.argtypes = [_vp, _i]
@@ -82,6 +84,8 @@ def _declare(L):
         L.fil_mlp_get_params.argtypes = [_vp, _vp]
         L.fil_mlp_set_norm.argtypes = [_vp, _vp]
         L.fil_mlp_get_norm.argtypes = [_vp, _vp]
+        L.fil_mlp_save.argtypes = [_vp, C.c_char_p]
+        L.fil_mlp_load.argtypes = [_vp, C.c_char_p]
         L.fil_mlp_fit_norm.argtypes = [_vp, _i64, _vp, _vp, _vp]
         L.fil_mlp_standardize.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp, _vp]
         L.fil_mlp_forward.argtypes = [_vp, _i32, _vp, _vp, _vp]

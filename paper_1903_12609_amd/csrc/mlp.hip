@@ -15,6 +15,8 @@
 #include <cstring>
 #include <vector>
 
+#include <cstdio>
+#include <string>
 #include "common.h"
 #include "mlp.h"
 
@@ -614,6 +616,59 @@ int fil_mlp_train_step(fil_mlp* m, int32_t B, const int32_t* rows, const uint16_
     int rc = fil_mlp_backward(m, B, rows, X, T, nullptr, loss, stream);
     if (rc) return rc;
     return fil_mlp_adam_step(m, lr, stream);
+}
+
+// File layout (native byte order): "FILMLP01", int32 dims[8] as fil_mlp_dims,
+// int64 number of parameters, int64 number of normalisation values, then the FP32
+// master parameters and the normalisation (mu, sd of inputs, then of outputs).
+static const char kMlpMagic[8] = {'F', 'I', 'L', 'M', 'L', 'P', '0', '1'};
+
+int fil_mlp_save(const fil_mlp* m, const char* path) {
+    FIL_CHECK_ARG(m && path, "fil_mlp_save: null argument");
+    int32_t dims[8];
+    int64_t np = 0;
+    if (int rc = fil_mlp_dims(m, dims, &np)) return rc;
+    const int64_t nn = 2 * (int64_t)(m->n_in_pad + m->n_out_pad);
+    std::vector<float> P(np), nrm(nn);
+    if (int rc = fil_mlp_get_params(m, P.data())) return rc;
+    if (int rc = fil_mlp_get_norm(m, nrm.data())) return rc;
+    FILE* fp = fopen(path, "wb");
+    FIL_CHECK_ARG(fp, std::string("fil_mlp_save: cannot open ") + path);
+    bool ok = fwrite(kMlpMagic, 1, 8, fp) == 8 && fwrite(dims, sizeof(int32_t), 8, fp) == 8 &&
+              fwrite(&np, sizeof(int64_t), 1, fp) == 1 && fwrite(&nn, sizeof(int64_t), 1, fp) == 1 &&
+              fwrite(P.data(), sizeof(float), P.size(), fp) == P.size() &&
+              fwrite(nrm.data(), sizeof(float), nrm.size(), fp) == nrm.size();
+    ok = (fclose(fp) == 0) && ok;
+    FIL_CHECK_ARG(ok, std::string("fil_mlp_save: write to ") + path + " failed");
+    return FIL_OK;
+}
+
+int fil_mlp_load(fil_mlp* m, const char* path) {
+    FIL_CHECK_ARG(m && path, "fil_mlp_load: null argument");
+    int32_t want[8];
+    int64_t np_want = 0;
+    if (int rc = fil_mlp_dims(m, want, &np_want)) return rc;
+    FILE* fp = fopen(path, "rb");
+    FIL_CHECK_ARG(fp, std::string("fil_mlp_load: cannot open ") + path);
+    char magic[8];
+    int32_t dims[8];
+    int64_t np = 0, nn = 0;
+    bool ok = fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, kMlpMagic, 8) == 0 &&
+              fread(dims, sizeof(int32_t), 8, fp) == 8 && fread(&np, sizeof(int64_t), 1, fp) == 1 &&
+              fread(&nn, sizeof(int64_t), 1, fp) == 1;
+    // the architecture must match (the batch capacity, dims[6], may differ)
+    const bool same = ok && dims[0] == want[0] && dims[1] == want[1] && dims[2] == want[2] && dims[3] == want[3] &&
+                      dims[4] == want[4] && dims[5] == want[5] && dims[7] == want[7] && np == np_want &&
+                      nn == 2 * (int64_t)(m->n_in_pad + m->n_out_pad);
+    std::vector<float> P(same ? np : 0), nrm(same ? nn : 0);
+    if (same)
+        ok = fread(P.data(), sizeof(float), P.size(), fp) == P.size() &&
+             fread(nrm.data(), sizeof(float), nrm.size(), fp) == nrm.size();
+    fclose(fp);
+    FIL_CHECK_ARG(ok, std::string("fil_mlp_load: ") + path + " is not a complete network file");
+    FIL_CHECK_ARG(same, "fil_mlp_load: network of a different architecture");
+    if (int rc = fil_mlp_set_params(m, P.data())) return rc;
+    return fil_mlp_set_norm(m, nrm.data());
 }
 
 }  // extern "C"

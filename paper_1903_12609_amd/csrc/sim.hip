@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <vector>
@@ -82,6 +83,7 @@ struct fil_sim {
     int k = 0;
     BdfCoef bc{};
     std::vector<int64_t> susp_seg_off;
+    std::vector<int64_t> fil_seg_off_h;  // filament offsets (host copy, for checkpoint checks)
     // optional timing of the main mobility kernel: one event pair per apply of a step
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -576,6 +578,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     const bool dense = p->j0_mode == 2 || (p->j0_mode == 0 && (size_t)dense_tot * sizeof(double) <= kDenseInvBytes);
     std::vector<int64_t> sfo(susp_fil_off, susp_fil_off + nsusp + 1);
     s->susp_seg_off = susp_seg_off;
+    s->fil_seg_off_h = seg_off;
 
     // ---- device allocations
     int rc = FIL_OK;
@@ -963,6 +966,101 @@ int fil_read_state(fil_sim* s, double* Y, double* q, double* Xj) {
             for (int i = 0; i < 4; i++) q[4 * x + i] = buf[i * S + x];
     }
     if (Xj) FIL_HIP_TRY(hipMemcpy(Xj, s->Xj, 6 * S * sizeof(double), hipMemcpyDeviceToHost));
+    return FIL_OK;
+}
+
+// ---------------------------------------------------------------- checkpoint / restore
+// File layout (native byte order): "FILSIM01", int64 S, M, nsusp, step, double t,
+// int64 fil_seg_off[M+1], int64 susp_fil_off[nsusp+1], double spar[nsusp][5],
+// then Y^j, Y^{j-1} [3][S], q^j [4][S], X^j, X^{j-1}, X^{j-2} [6S].
+}  // extern "C"
+
+namespace {
+constexpr char kSimMagic[8] = {'F', 'I', 'L', 'S', 'I', 'M', '0', '1'};
+
+struct FileCloser {
+    FILE* f;
+    ~FileCloser() {
+        if (f) fclose(f);
+    }
+};
+
+// the committed arrays of a simulation with their element counts
+std::vector<std::pair<double*, size_t>> state_arrays(fil_sim* s) {
+    const size_t S = (size_t)s->S, n6 = 6 * S;
+    return {{s->Yj, 3 * S}, {s->Yjm1, 3 * S}, {s->qj, 4 * S}, {s->Xj, n6}, {s->Xjm1, n6}, {s->Xjm2, n6}};
+}
+}  // namespace
+
+extern "C" {
+
+int fil_checkpoint(fil_sim* s, const char* path) {
+    FIL_CHECK_ARG(s && path, "fil_checkpoint: null argument");
+    FIL_HIP_TRY(hipStreamSynchronize(s->st));
+    FileCloser fc{fopen(path, "wb")};
+    FIL_CHECK_ARG(fc.f, std::string("fil_checkpoint: cannot open ") + path);
+    const int64_t hdr[4] = {s->S, s->M, s->nsusp, s->step};
+    std::vector<int64_t> sfo(s->nsusp + 1);
+    FIL_HIP_TRY(hipMemcpy(sfo.data(), s->d.susp_fil_off, sfo.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    std::vector<double> spar(kSpar * s->nsusp);
+    FIL_HIP_TRY(hipMemcpy(spar.data(), s->spar, spar.size() * sizeof(double), hipMemcpyDeviceToHost));
+    bool ok = fwrite(kSimMagic, 1, 8, fc.f) == 8 && fwrite(hdr, sizeof(int64_t), 4, fc.f) == 4 &&
+              fwrite(&s->t, sizeof(double), 1, fc.f) == 1 &&
+              fwrite(s->fil_seg_off_h.data(), sizeof(int64_t), s->fil_seg_off_h.size(), fc.f) ==
+                  s->fil_seg_off_h.size() &&
+              fwrite(sfo.data(), sizeof(int64_t), sfo.size(), fc.f) == sfo.size() &&
+              fwrite(spar.data(), sizeof(double), spar.size(), fc.f) == spar.size();
+    std::vector<double> buf;
+    for (auto& a : state_arrays(s)) {
+        if (!ok) break;
+        buf.resize(a.second);
+        FIL_HIP_TRY(hipMemcpy(buf.data(), a.first, a.second * sizeof(double), hipMemcpyDeviceToHost));
+        ok = fwrite(buf.data(), sizeof(double), a.second, fc.f) == a.second;
+    }
+    ok = ok && fflush(fc.f) == 0;
+    FIL_CHECK_ARG(ok, std::string("fil_checkpoint: write to ") + path + " failed");
+    return FIL_OK;
+}
+
+int fil_restore(fil_sim* s, const char* path) {
+    FIL_CHECK_ARG(s && path, "fil_restore: null argument");
+    FileCloser fc{fopen(path, "rb")};
+    FIL_CHECK_ARG(fc.f, std::string("fil_restore: cannot open ") + path);
+    char magic[8];
+    int64_t hdr[4];
+    double t = 0.0;
+    FIL_CHECK_ARG(fread(magic, 1, 8, fc.f) == 8 && std::memcmp(magic, kSimMagic, 8) == 0 &&
+                      fread(hdr, sizeof(int64_t), 4, fc.f) == 4 && fread(&t, sizeof(double), 1, fc.f) == 1,
+                  "fil_restore: not a simulation checkpoint");
+    FIL_CHECK_ARG(hdr[0] == s->S && hdr[1] == s->M && hdr[2] == s->nsusp && hdr[3] >= 0,
+                  "fil_restore: checkpoint of a different simulation (segments, filaments or suspensions)");
+    std::vector<int64_t> off(s->M + 1), sfo(s->nsusp + 1), sfo_d(s->nsusp + 1);
+    std::vector<double> spar(kSpar * s->nsusp);
+    FIL_CHECK_ARG(fread(off.data(), sizeof(int64_t), off.size(), fc.f) == off.size() &&
+                      fread(sfo.data(), sizeof(int64_t), sfo.size(), fc.f) == sfo.size() &&
+                      fread(spar.data(), sizeof(double), spar.size(), fc.f) == spar.size(),
+                  "fil_restore: truncated checkpoint");
+    FIL_HIP_TRY(hipMemcpy(sfo_d.data(), s->d.susp_fil_off, sfo_d.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    FIL_CHECK_ARG(off == s->fil_seg_off_h && sfo == sfo_d,
+                  "fil_restore: checkpoint of a different simulation (filament or suspension layout)");
+    for (double v : spar) FIL_CHECK_ARG(std::isfinite(v), "fil_restore: non-finite parameter");
+    std::vector<std::vector<double>> data;
+    for (auto& a : state_arrays(s)) {
+        data.emplace_back(a.second);
+        FIL_CHECK_ARG(fread(data.back().data(), sizeof(double), a.second, fc.f) == a.second,
+                      "fil_restore: truncated checkpoint");
+        for (double v : data.back()) FIL_CHECK_ARG(std::isfinite(v), "fil_restore: non-finite state");
+    }
+    // everything read and checked: the simulation is changed only now
+    FIL_HIP_TRY(hipStreamSynchronize(s->st));
+    FIL_HIP_TRY(hipMemcpy(s->spar, spar.data(), spar.size() * sizeof(double), hipMemcpyHostToDevice));
+    const auto arrays = state_arrays(s);
+    for (size_t i = 0; i < arrays.size(); i++)
+        FIL_HIP_TRY(hipMemcpy(arrays[i].first, data[i].data(), arrays[i].second * sizeof(double),
+                              hipMemcpyHostToDevice));
+    s->t = t;
+    s->step = hdr[3];
+    s->pred_iters = 0;
     return FIL_OK;
 }
 
