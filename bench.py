@@ -31,7 +31,7 @@ FLOP_PER_PAIR = 85          # algorithmic flops of one ordered (target, source) 
 PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (packed)
 PEAK_HBM_GBS = 8000.0
-GRAPH_ITERS = 8             # Broyden iterations per captured graph block (at most)
+GRAPH_ITERS = 32            # Broyden iterations per captured graph block (at most)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rpy_f64_sediment2000_traffic.json")
 
 

@@ -69,6 +69,8 @@ struct fil_sim {
     SuspLog* log_slot[2] = {nullptr, nullptr};
     SuspLog* log_slot_dev[2] = {nullptr, nullptr};  // the same slots as the device addresses them
     hipEvent_t log_ev[2] = {nullptr, nullptr};
+    int64_t* exports_d = nullptr;  // exports so far (device; selects the slot), mirrored by exports_h
+    int64_t exports_h = 0;
     // learned warm start
     fil_mlp* mlp = nullptr;
     bool use_mlp = false;
@@ -297,6 +299,9 @@ int capture_block(fil_sim* s, int it0, int U, GraphEntry& g) {
                            s->cur == 0 ? 1 : 0};
         if (rc == FIL_OK) rc = broyden_state_launch(s->d, update_args(s, it - 1, s->f, nullptr), jg, s->active_d, s->st);
     }
+    // the block ends by exporting its log to the next pinned slot
+    if (rc == FIL_OK)
+        rc = log_export_launch(s->log_d, ns, s->log_slot_dev[0], s->log_slot_dev[1], s->exports_d, s->st);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(s->st, &graph);
     s->st = run_st;
@@ -347,18 +352,18 @@ struct SolveLog {
 int device_iterations(fil_sim* s, SolveLog& L, int it) {
     const int64_t ns = s->nsusp;
     const int pred = s->pred_iters;
-    int pending = 0, wslot = 0, rslot = 0;
+    int pending = 0;
+    int rslot = (int)(s->exports_h & 1);
     for (;;) {
         while (pending < 2 && it <= s->p.kmax) {
             int U = s->graph_iters;
             if (pred > 0) U = it <= pred ? std::min(U, pred - it + 1) : 1;
             U = std::min(U, s->p.kmax - it + 1);
-            TRY(graph_block(s, it, U));
+            TRY(graph_block(s, it, U));  // ends with the log export to slot (exports so far) mod 2
             it += U;
             s->k += U;
-            TRY(log_export_launch(s->log_d, ns, s->log_slot_dev[wslot], s->st));
+            const int wslot = (int)(s->exports_h++ & 1);
             FIL_HIP_TRY(hipEventRecord(s->log_ev[wslot], s->st));
-            wslot ^= 1;
             pending++;
         }
         if (pending == 0) break;  // every iteration up to kmax has run (its test failed what was left)
@@ -617,7 +622,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     A(s->AB, n6 * kBandW) A(s->ipiv, n6) A(s->rdiag, n6)
     if (dense) { A(s->AinvT, dense_tot) A(d_dense_off, M) }
     A(s->Chist, (size_t)p->kmax * n6) A(s->Dhist, (size_t)p->kmax * n6) A(s->part, (size_t)M * max_dots)
-    A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->time_d, 1) A(s->log_d, nsusp)
+    A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->time_d, 1) A(s->log_d, nsusp) A(s->exports_d, 1)
     A(s->active_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 4 * nsusp)
 #undef A
     if (rc == FIL_OK) rc = halloc(s, &s->active_h, nsusp);
@@ -694,6 +699,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         TRY(upload(s->Xjm1, zeros));
         TRY(upload(s->Xjm2, zeros));
         TRY(upload(s->X0p, zeros));
+        TRY(upload(s->exports_d, std::vector<int64_t>(1, 0)));
         TRY(upload(s->X, zeros));
         TRY(upload(s->resbits_d, std::vector<unsigned long long>(4 * nsusp, 0ull)));
         if (s->batched) {

@@ -111,8 +111,9 @@ int broyden_state_launch(const SimDev& d, const UpdateArgs& u, const JudgeArgs& 
 int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const double* Yjm1, const double* Xj,
                          const double* Xjm1, double* X0, double* X0c, int32_t* active, SuspLog* log, double* time_d,
                          double tt, hipStream_t st);
-// copies the device log to `out` (pinned host memory, written by the kernel)
-int log_export_launch(const SuspLog* log, int64_t ns, SuspLog* out, hipStream_t st);
+// copies the device log to pinned host slot (*counter mod 2) and advances *counter
+int log_export_launch(const SuspLog* log, int64_t ns, SuspLog* slot0, SuspLog* slot1, int64_t* counter,
+                      hipStream_t st);
 // J0 at X in row-differenced banded form (6N x kBandW per filament at 6*seg_off[f]*kBandW),
 // factorised with partial pivoting (ipiv at 6*seg_off[f]); flag[f] = 1 for a zero pivot
 // When AinvT is non-null the explicit inverse is also built (transposed, at dense_off[f]).

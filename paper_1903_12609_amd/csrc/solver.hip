@@ -587,16 +587,23 @@ int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const 
     return FIL_OK;
 }
 
+// One workgroup: the device log to the pinned slot `counter` mod 2 (the count of
+// exports so far, advanced here in stream order, so a captured export needs no
+// host argument per launch).
 __global__ void __launch_bounds__(256) log_export_kernel(const SuspLog* __restrict__ log, int64_t ns,
-                                                       SuspLog* __restrict__ out) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = log[i];
+                                                       SuspLog* __restrict__ slot0, SuspLog* __restrict__ slot1,
+                                                       int64_t* __restrict__ counter) {
+    const int64_t c = *counter;
+    SuspLog* out = (c & 1) ? slot1 : slot0;
+    for (int64_t i = threadIdx.x; i < ns; i += blockDim.x) out[i] = log[i];
     __threadfence_system();
+    __syncthreads();  // every thread has read the count
+    if (threadIdx.x == 0) *counter = c + 1;
 }
 
-int log_export_launch(const SuspLog* log, int64_t ns, SuspLog* out, hipStream_t st) {
-    log_export_kernel<<<(unsigned)std::min<int64_t>(64, std::max<int64_t>(1, ceil_div(ns, 256))), 256, 0, st>>>(
-        log, ns, out);
+int log_export_launch(const SuspLog* log, int64_t ns, SuspLog* slot0, SuspLog* slot1, int64_t* counter,
+                      hipStream_t st) {
+    log_export_kernel<<<1, 256, 0, st>>>(log, ns, slot0, slot1, counter);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }
