@@ -18,8 +18,9 @@
 //   * FP32-tile path: r = Y_n - Y_m is formed in double and rounded once, the
 //     pair arithmetic runs in float and each tile of sources is accumulated in
 //     float and then added into double accumulators.
-//   * Overlapping pairs (r < 2a, the self pair included) take a rarely executed
-//     branch with the regularised forms; the far-field weights are zeroed there.
+//   * Overlapping pairs (r < 2a) take a rarely executed branch with the regularised
+//     forms; the far-field weights are zeroed there.  The self pair (r = 0) is taken in
+//     its closed form 4/(3a) F, T/a^3 (in the FP32-tile path: in double, per target).
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -86,7 +87,7 @@ __device__ __forceinline__ Ovl<R> rpy_overlap(R rx, R ry, R rz, R r2, R Fx, R Fy
 }
 
 __device__ __forceinline__ void rpy_pair_f64(const double y[3], const double (&s)[15], double a, double four_a2,
-                                             double two_a2, bool self, AccF64& A) {
+                                             double two_a2, AccF64& A) {
     const double rx = y[0] - s[0], ry = y[1] - s[1], rz = y[2] - s[2];
     const double r2 = fma(rx, rx, fma(ry, ry, rz * rz));
     const bool near = r2 < four_a2;
@@ -119,13 +120,23 @@ __device__ __forceinline__ void rpy_pair_f64(const double y[3], const double (&s
     A.Hw[0] = fma(D, rx, A.Hw[0]);
     A.Hw[1] = fma(D, ry, A.Hw[1]);
     A.Hw[2] = fma(D, rz, A.Hw[2]);
-    if (near && !self) {
-        // overlap: added to G (velocity), subtracted from U (angular velocity); the self
-        // pair is added once per target after the loop
-        const Ovl<double> o = rpy_overlap<double>(rx, ry, rz, r2, Fx, Fy, Fz, Tx, Ty, Tz, a);
-        for (int i = 0; i < 3; i++) {
-            A.G[i] += o.v[i];
-            A.U[i] -= o.w[i];
+    if (near) {
+        // overlap: added to G (velocity), subtracted from U (angular velocity).  At r = 0
+        // (the self pair) the overlap forms reduce to 4/(3a) F and T/a^3, taken directly
+        if (r2 > 0.0) {
+            const Ovl<double> o = rpy_overlap<double>(rx, ry, rz, r2, Fx, Fy, Fz, Tx, Ty, Tz, a);
+            for (int i = 0; i < 3; i++) {
+                A.G[i] += o.v[i];
+                A.U[i] -= o.w[i];
+            }
+        } else {
+            const double cv = 4.0 / (3.0 * a), cw = 1.0 / (a * a * a);
+            A.G[0] = fma(cv, Fx, A.G[0]);
+            A.G[1] = fma(cv, Fy, A.G[1]);
+            A.G[2] = fma(cv, Fz, A.G[2]);
+            A.U[0] = fma(-cw, Tx, A.U[0]);
+            A.U[1] = fma(-cw, Ty, A.U[1]);
+            A.U[2] = fma(-cw, Tz, A.U[2]);
         }
     }
 }
@@ -234,21 +245,10 @@ __device__ __forceinline__ void rpy_item_f64(int64_t base, int64_t S, int64_t Sg
             double nxt[15];
             for (int i = 0; i < 15; i++) nxt[i] = src[16 * mn + i];
 #pragma unroll
-            for (int j = 0; j < TPL; j++) rpy_pair_f64(y[j], cur, a, four_a2, two_a2, m0 + m == n[j], A[j]);
+            for (int j = 0; j < TPL; j++) rpy_pair_f64(y[j], cur, a, four_a2, two_a2, A[j]);
             for (int i = 0; i < 15; i++) cur[i] = nxt[i];
         }
     }
-    // the self pair (r = 0 in the overlap forms): 4/(3a) F and T / a^3
-#pragma unroll
-    for (int j = 0; j < TPL; j++)
-        if (n[j] >= m0 && n[j] < m1) {
-            const double* sr = pk + 16 * (base + n[j]);
-            const double cv = 4.0 / (3.0 * a), cw = 1.0 / (a * a * a);
-            for (int i = 0; i < 3; i++) {
-                A[j].G[i] = fma(cv, sr[3 + i], A[j].G[i]);
-                A[j].U[i] = fma(-cw, sr[6 + i], A[j].U[i]);
-            }
-        }
     const double c23 = 2.0 * a * a / 3.0;
     double vw[TPL][6];
 #pragma unroll
@@ -315,7 +315,7 @@ __device__ __forceinline__ SrcRegF32 load_src_f32(const SrcF32* __restrict__ s) 
     return r;
 }
 __device__ __forceinline__ void rpy_pair_f32(const double y[3], const SrcRegF32& s, float a, float four_a2,
-                                             float two_a2, float c23, bool self, float v[3], float w[3]) {
+                                             float two_a2, float c23, float v[3], float w[3]) {
     const float rx = (float)(y[0] - s.y[0]);
     const float ry = (float)(y[1] - s.y[1]);
     const float rz = (float)(y[2] - s.y[2]);
@@ -338,7 +338,7 @@ __device__ __forceinline__ void rpy_pair_f32(const double y[3], const SrcRegF32&
     w[0] = fmaf(E, Tx, fmaf(D, qx, fmaf(Fy, qz, fmaf(-Fz, qy, w[0]))));
     w[1] = fmaf(E, Ty, fmaf(D, qy, fmaf(Fz, qx, fmaf(-Fx, qz, w[1]))));
     w[2] = fmaf(E, Tz, fmaf(D, qz, fmaf(Fx, qy, fmaf(-Fy, qx, w[2]))));
-    if (near && !self) {
+    if (near && r2 > 0.f) {  // the self pair (r = 0) is added per target, in double, after the loop
         const Ovl<float> o = rpy_overlap<float>(rx, ry, rz, r2, Fx, Fy, Fz, Tx, Ty, Tz, a);
         for (int i = 0; i < 3; i++) {
             v[i] += o.v[i];
@@ -393,7 +393,7 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
             const SrcRegF32 nxt = load_src_f32(ts + (i + 1 < cnt ? i + 1 : i));
 #pragma unroll
             for (int j = 0; j < TPL; j++)
-                rpy_pair_f32(y[j], cur, af, four_a2, two_a2, c23, t0 + i == n[j], v[j], w[j]);
+                rpy_pair_f32(y[j], cur, af, four_a2, two_a2, c23, v[j], w[j]);
             cur = nxt;
         }
 #pragma unroll
