@@ -458,9 +458,8 @@ __global__ void __launch_bounds__(NT) residual_kernel(SimDev d, BdfCoef bc, cons
                   ures.y == ures.y && ures.z == ures.z))
                 amax = __longlong_as_double(0x7ff8000000000000ll);
         }
-        // the workgroup belongs to one suspension: wave maxima, one atomic each (a plain
-        // read first: once the running maximum is large most workgroups need no atomic;
-        // a stale read only costs an unneeded atomic, the maximum being monotonic)
+        // the workgroup belongs to one suspension: wave maxima, one atomic each (results
+        // unused, so the workgroup does not wait for them)
         unsigned long long ma = (unsigned long long)__double_as_longlong(amax);
         unsigned long long mv = (unsigned long long)__double_as_longlong(vmax);
         for (int o = 32; o > 0; o >>= 1) {
@@ -469,9 +468,8 @@ __global__ void __launch_bounds__(NT) residual_kernel(SimDev d, BdfCoef bc, cons
             mv = ov > mv ? ov : mv;
         }
         if (n == 0) {
-            if (ma > __atomic_load_n(&resbits[isus], __ATOMIC_RELAXED)) atomicMax(&resbits[isus], ma);
-            if (mv > __atomic_load_n(&resbits[d.nsusp + isus], __ATOMIC_RELAXED))
-                atomicMax(&resbits[d.nsusp + isus], mv);
+            atomicMax(&resbits[isus], ma);
+            atomicMax(&resbits[d.nsusp + isus], mv);
         }
     }
     if (da.k < 0) return;
@@ -1311,6 +1309,20 @@ __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs 
         xr = u.X[e0 + t];
     }
     const Q4 qjn = t < N ? ldq(u.qj, d.S, s0 + t) : Q4{1.0, 0.0, 0.0, 0.0};
+    // the suspension's partial dots of this wave's first two dots, for up to 128 filaments
+    const int64_t sg0 = d.susp_fil_off[isus], sg1 = d.susp_fil_off[isus + 1];
+    const int nd = u.k + 2;
+    const int h0 = wave, h1 = wave + NW;
+    const bool ppre = NT >= 1024 && u.k >= 0 && sg1 - sg0 <= 128;  // uniform
+    double pd0[2] = {0.0, 0.0}, pd1[2] = {0.0, 0.0};
+    if (ppre) {
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            const int64_t g = min(sg0 + lane + 64 * r, sg1 - 1);  // clamped; masked when summed
+            if (h0 < nd) pd0[r] = u.dpart[g * d.max_dots + h0];
+            if (h1 < nd) pd1[r] = u.dpart[g * d.max_dots + h1];
+        }
+    }
     if (jg.log) {
         const double r = __longlong_as_double((long long)jg.resbits[isus]) * jg.inv_a;
         int32_t state = 0;
@@ -1340,20 +1352,27 @@ __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs 
     for (int e = t; e < n; e += NT) sf[e] = e == t ? fr : u.fnew[e0 + e];
     if (u.k >= 0) {
         // dot h by wave h mod NW, two per pass, over the filaments' partials in order
-        const int64_t g0 = d.susp_fil_off[isus], g1 = d.susp_fil_off[isus + 1];
-        const int nd = u.k + 2;
-        for (int h0 = wave; h0 < nd; h0 += 2 * NW) {
-            const int h1 = h0 + NW;
+        for (int q0 = h0; q0 < nd; q0 += 2 * NW) {
+            const int q1 = q0 + NW;
             double a0 = 0.0, a1 = 0.0;
-            for (int64_t g = g0 + lane; g < g1; g += 64) {
-                a0 += u.dpart[g * d.max_dots + h0];
-                if (h1 < nd) a1 += u.dpart[g * d.max_dots + h1];
+            if (ppre && q0 == h0) {  // the first pass from the values read ahead
+#pragma unroll
+                for (int r = 0; r < 2; r++)
+                    if (sg0 + lane + 64 * r < sg1) {
+                        a0 += pd0[r];
+                        a1 += pd1[r];
+                    }
+            } else {
+                for (int64_t g = sg0 + lane; g < sg1; g += 64) {
+                    a0 += u.dpart[g * d.max_dots + q0];
+                    if (q1 < nd) a1 += u.dpart[g * d.max_dots + q1];
+                }
             }
             a0 = wave_sum(a0);
             a1 = wave_sum(a1);
             if (lane == 0) {
-                sdots[h0] = a0;
-                if (h1 < nd) sdots[h1] = a1;
+                sdots[q0] = a0;
+                if (q1 < nd) sdots[q1] = a1;
             }
         }
     }
