@@ -49,6 +49,79 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
     return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int l) {
+    const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, l);
+    const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// DPP lane moves inside each row of 16 lanes (VALU only, no LDS round trip); a lane
+// whose source falls outside its row receives zero.  Every lane of the wave must be
+// active.
+enum : int {
+    kDppQuadSwap1 = 0xb1,  // quad permutation [1,0,3,2]
+    kDppQuadSwap2 = 0x4e,  // quad permutation [2,3,0,1]
+    kDppHalfMirror = 0x141,
+    kDppRowMirror = 0x140,
+    kDppRowShr = 0x110,  // + shift (1..15)
+};
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+    const unsigned lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xf, 0xf, true);
+    const unsigned hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xf, 0xf, true);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// op over each row of 16 lanes, left in every lane of the row: pairs, quads, half rows,
+// rows.  Each step combines a lane with its partner symmetrically, so for a commutative
+// op every lane of a row holds the same bits.
+template <typename Op>
+__device__ __forceinline__ double row_allreduce_f64(double v, Op op) {
+    v = op(v, dpp_f64<kDppQuadSwap1>(v));
+    v = op(v, dpp_f64<kDppQuadSwap2>(v));
+    v = op(v, dpp_f64<kDppHalfMirror>(v));
+    return op(v, dpp_f64<kDppRowMirror>(v));
+}
+template <typename Op>
+__device__ __forceinline__ unsigned long long row_allreduce_u64(unsigned long long v, Op op) {
+    v = op(v, dpp_u64<kDppQuadSwap1>(v));
+    v = op(v, dpp_u64<kDppQuadSwap2>(v));
+    v = op(v, dpp_u64<kDppHalfMirror>(v));
+    return op(v, dpp_u64<kDppRowMirror>(v));
+}
+
+// sum over the wave in a fixed order (rows, then (r0 + r1) + (r2 + r3)); uniform result
+__device__ __forceinline__ double wave_sum(double v) {
+    v = row_allreduce_f64(v, [](double a, double b) { return a + b; });
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// maximum over the wave of unsigned 64-bit values; uniform result
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+    auto mx = [](unsigned long long a, unsigned long long b) { return a > b ? a : b; };
+    v = row_allreduce_u64(v, mx);
+    return mx(mx(readlane_u64(v, 0), readlane_u64(v, 16)), mx(readlane_u64(v, 32), readlane_u64(v, 48)));
+}
+
+// inclusive prefix sum over the wave: shifts by 1, 2, 4, 8 inside each row, then each
+// row adds the totals of the rows before it
+__device__ __forceinline__ double wave_inclusive_sum(double v, int lane) {
+    v += dpp_f64<kDppRowShr + 1>(v);
+    v += dpp_f64<kDppRowShr + 2>(v);
+    v += dpp_f64<kDppRowShr + 4>(v);
+    v += dpp_f64<kDppRowShr + 8>(v);
+    const double t0 = readlane_f64(v, 15), t1 = readlane_f64(v, 31), t2 = readlane_f64(v, 47);
+    const int row = lane >> 4;
+    const double t01 = t0 + t1;
+    const double carry = row == 0 ? 0.0 : row == 1 ? t0 : row == 2 ? t01 : t01 + t2;
+    return row == 0 ? v : v + carry;
+}
 
 // preferred curvature of joint k (between local segments k and k+1) at time tt,
 // evaluated at s = (k+1) dL
@@ -98,21 +171,18 @@ __device__ void filament_state(const SimDev& d, int64_t f, const double* Xf, Q4 
         } else {
             for (int i = 0; i < 3; i++) e[i] = seg ? (0.5 * d.dL) * (st[n - 1][i] + st[n][i]) : 0.0;
         }
-        for (int o = 1; o < 64; o <<= 1)
-            for (int i = 0; i < 3; i++) {
-                const double t = __shfl_up(e[i], o, 64);
-                if (n >= o) e[i] += t;
-            }
+        for (int i = 0; i < 3; i++) e[i] = wave_inclusive_sum(e[i], n);
         if (seg) st3(Yc, S, s0 + n, v3(e[0], e[1], e[2]));
         double lo[3], hi[3];
-        for (int i = 0; i < 3; i++) lo[i] = hi[i] = __shfl(e[i], 0, 64);
-        for (int i = 0; i < 3; i++)
-            if (seg) lo[i] = hi[i] = e[i];
-        for (int o = 32; o > 0; o >>= 1)
-            for (int i = 0; i < 3; i++) {
-                lo[i] = fmin(lo[i], __shfl_xor(lo[i], o, 64));
-                hi[i] = fmax(hi[i], __shfl_xor(hi[i], o, 64));
-            }
+        for (int i = 0; i < 3; i++) {
+            const double y = seg ? e[i] : readlane_f64(e[i], 0);
+            lo[i] = row_allreduce_f64(y, [](double a, double b) { return fmin(a, b); });
+            hi[i] = row_allreduce_f64(y, [](double a, double b) { return fmax(a, b); });
+            lo[i] = fmin(fmin(readlane_f64(lo[i], 0), readlane_f64(lo[i], 16)),
+                         fmin(readlane_f64(lo[i], 32), readlane_f64(lo[i], 48)));
+            hi[i] = fmax(fmax(readlane_f64(hi[i], 0), readlane_f64(hi[i], 16)),
+                         fmax(readlane_f64(hi[i], 32), readlane_f64(hi[i], 48)));
+        }
         if (n == 0) {
             double* b = box + 6 * f;
             for (int i = 0; i < 3; i++) {
@@ -302,10 +372,6 @@ int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, con
 // every finite value).  When the velocities come from the mobility partials they
 // are also stored to V, W.  For a Broyden update it leaves the filament's share of
 // the update's dot products.
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
 
 // Filament f's share of the dot products of Broyden update k (Alg. 2), its rows of
 // f in LDS: h < k: d_h . f;  h = k: |f - fprev|^2;  h = k+1: (f - fprev) . f.
@@ -460,13 +526,8 @@ __global__ void __launch_bounds__(NT) residual_kernel(SimDev d, BdfCoef bc, cons
         }
         // the workgroup belongs to one suspension: wave maxima, one atomic each (results
         // unused, so the workgroup does not wait for them)
-        unsigned long long ma = (unsigned long long)__double_as_longlong(amax);
-        unsigned long long mv = (unsigned long long)__double_as_longlong(vmax);
-        for (int o = 32; o > 0; o >>= 1) {
-            const unsigned long long oa = __shfl_xor(ma, o, 64), ov = __shfl_xor(mv, o, 64);
-            ma = oa > ma ? oa : ma;
-            mv = ov > mv ? ov : mv;
-        }
+        const unsigned long long ma = wave_max_u64((unsigned long long)__double_as_longlong(amax));
+        const unsigned long long mv = wave_max_u64((unsigned long long)__double_as_longlong(vmax));
         if (n == 0) {
             atomicMax(&resbits[isus], ma);
             atomicMax(&resbits[d.nsusp + isus], mv);
