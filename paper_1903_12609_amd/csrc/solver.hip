@@ -9,6 +9,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "quat.h"
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -896,23 +897,54 @@ __global__ void __launch_bounds__(256) j0_band_assemble_kernel(SimDev d, BdfCoef
 // the only rows and columns step j reads or writes (row p <= j + kKL has no
 // entries right of column j + kKL + kKU, before or after fill-in).  Step j takes
 // the pivot from lane 0's column (broadcast), swaps rows inside every lane, writes
-// row j of U and column j of L to the band, updates the window and shifts it one
-// column left / one row down; the row entering at the bottom was requested
-// kFacAhead steps earlier.  No LDS, so every filament of a large ensemble can be
-// resident at once.
+// row j of U and column j of L, updates the window and shifts it one column left /
+// one row down; the row entering at the bottom was requested kFacAhead steps
+// earlier.
+// kStaged: the filament's band is first copied to LDS (all loads in flight at
+// once) and factored there in place, with the pivots and reciprocal pivots, and
+// copied back at the end, so the row loop holds no global memory access: a global
+// load in the loop makes every row wait for a memory round trip.  Without staging
+// (no LDS, so that every filament of a large ensemble can be resident at once) the
+// rows enter from global memory and the results go straight there.
 constexpr int kFacAhead = 4;
-__global__ void __launch_bounds__(64) j0_band_factor_regs_kernel(SimDev d, const int32_t* __restrict__ active,
-                                                               double* __restrict__ AB, int32_t* __restrict__ ipiv,
-                                                               double* __restrict__ rdiag, int32_t* __restrict__ flag) {
+// launch choice: MI355X has 256 CUs with 160 KB of LDS each; the unstaged factor's
+// register use allows 20 of its waves per CU; staging is taken while a class needs at
+// most 4 rounds of resident workgroups
+constexpr int64_t kNumCU = 256, kFacWavesPerCU = 20, kFacStagedRounds = 4;
+constexpr size_t kLdsPerCU = 160 * 1024;
+template <bool kStaged>
+__global__ void __launch_bounds__(64) j0_band_factor_kernel(SimDev d, const int32_t* __restrict__ active,
+                                                          double* __restrict__ AB, int32_t* __restrict__ ipiv,
+                                                          double* __restrict__ rdiag, int32_t* __restrict__ flag,
+                                                          int64_t coff) {
     constexpr int kWin = kKL + kKU + 1;  // window columns (17)
-    const int64_t f = blockIdx.x;
+    const int64_t f = d.cls_fil[coff + blockIdx.x];
     if (!active[d.fil_susp[f]]) return;
     const int64_t s0 = d.seg_off[f];
     const int n = 6 * (int)(d.seg_off[f + 1] - s0);
-    double* ab = AB + 6 * s0 * kBandW;
-    int32_t* gp = ipiv + 6 * s0;
+    double* const gab = AB + 6 * s0 * kBandW;
+    int32_t* const gip = ipiv + 6 * s0;
+    double* const grd = rdiag + 6 * s0;
     const int l = threadIdx.x;
     const bool lw = l < kWin;
+    // LDS (staged): band [n][kBandW] | reciprocal pivots [n] | pivot rows [n]
+    extern __shared__ double fac_lds[];
+    double* const ab = kStaged ? fac_lds : gab;
+    double* const rd = kStaged ? fac_lds + (size_t)n * kBandW : grd;
+    int32_t* const ip = kStaged ? reinterpret_cast<int32_t*>(rd + n) : gip;
+    if (kStaged) {
+        const int ne = n * kBandW;
+        int e = l;
+        for (; e + 7 * 64 < ne; e += 8 * 64) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[u] = gab[e + u * 64];
+#pragma unroll
+            for (int u = 0; u < 8; u++) ab[e + u * 64] = v[u];
+        }
+        for (; e < ne; e += 64) ab[e] = gab[e];
+        __syncthreads();
+    }
     // element (r, c) of the band (0 outside the matrix); the band stores columns r-kKL .. r+kKL+kKU
     auto at = [&](int r, int c) {
         return (lw && r < n && c < n && c - r >= -kKL && c - r <= kKL + kKU) ? ab[(int64_t)r * kBandW + (c - r + kKL)]
@@ -940,67 +972,92 @@ __global__ void __launch_bounds__(64) j0_band_factor_regs_kernel(SimDev d, const
         for (int qs = 0; qs < kFacAhead; qs++) {
             const int j = j0 + qs;
             if (j >= n) break;
-                // pivot column j (lane 0) broadcast to the wave
-                double col[kKL + 1];
+            // pivot column j (lane 0) broadcast to the wave
+            double col[kKL + 1];
 #pragma unroll
-                for (int r = 0; r <= kKL; r++) col[r] = readlane_f64(W[r], 0);
-                int pr = 0;
-                double best = fabs(col[0]);
+            for (int r = 0; r <= kKL; r++) col[r] = readlane_f64(W[r], 0);
+            // pivot row: the first maximum of |W[r]| in every lane's own column (lane 0's
+            // is used), a pairwise tree in which a later row wins only when strictly larger
+            double av[kKL + 1];
+            int ix[kKL + 1];
 #pragma unroll
-                for (int r = 1; r <= kKL; r++)
-                    if (fabs(col[r]) > best) {
-                        best = fabs(col[r]);
-                        pr = r;
+            for (int r = 0; r <= kKL; r++) {
+                av[r] = fabs(W[r]);
+                ix[r] = r;
+            }
+#pragma unroll
+            for (int w = 1; w <= kKL; w *= 2)
+#pragma unroll
+                for (int r = 0; r + w <= kKL; r += 2 * w)
+                    if (av[r + w] > av[r]) {
+                        av[r] = av[r + w];
+                        ix[r] = ix[r + w];
                     }
-                if (!(best > 0.0)) bad = 1;
-                // row exchange (wave-uniform; rare for these blocks, so a scalar branch)
-                if (__builtin_expect(pr != 0, 0)) {
-                    const double w0 = W[0], c0 = col[0];
-                    switch (pr) {
-        #define FIL_SWAP_ROW(r)      \
-            case r:                  \
-                W[0] = W[r];         \
-                W[r] = w0;           \
-                col[0] = col[r];     \
-                col[r] = c0;         \
-                break;
-                        FIL_SWAP_ROW(1) FIL_SWAP_ROW(2) FIL_SWAP_ROW(3) FIL_SWAP_ROW(4)
-                        FIL_SWAP_ROW(5) FIL_SWAP_ROW(6) FIL_SWAP_ROW(7) FIL_SWAP_ROW(8)
-        #undef FIL_SWAP_ROW
-                        default: break;
-                    }
+            const int pr = __builtin_amdgcn_readfirstlane(ix[0]);
+            // row exchange (wave-uniform and rare for these blocks: one branch, selects inside)
+            if (__builtin_expect(pr != 0, 0)) {
+                const double w0 = W[0], c0 = col[0];
+                double wp = w0, cp = c0;
+#pragma unroll
+                for (int r = 1; r <= kKL; r++) {
+                    const bool sw = pr == r;
+                    wp = sw ? W[r] : wp;
+                    W[r] = sw ? w0 : W[r];
+                    cp = sw ? col[r] : cp;
+                    col[r] = sw ? c0 : col[r];
                 }
-                const double rp = 1.0 / col[0];
-                double m[kKL + 1];
+                W[0] = wp;
+                col[0] = cp;
+            }
+            if (!(fabs(col[0]) > 0.0)) bad = 1;
+            // 1 / pivot: hardware reciprocal and two Newton steps
+            double rp = __builtin_amdgcn_rcp(col[0]);
+            rp = fma(rp, fma(-col[0], rp, 1.0), rp);
+            rp = fma(rp, fma(-col[0], rp, 1.0), rp);
+            double m[kKL + 1];
 #pragma unroll
-                for (int r = 1; r <= kKL; r++) m[r] = col[r] * rp;
-                // final row j of U (lanes 0..16) and column j of L (lane r holds m[r]).  The
-                // stores are unconditional so that the memory counter stays static and the
-                // queued row loads remain in flight: a lane with nothing to store writes the
-                // reciprocal pivot to its slot, as every lane does.
-                double* const rslot = rdiag + 6 * s0 + j;
-                const bool su = lw && j + l < n;
-                *(su ? ab + (int64_t)j * kBandW + kKL + l : rslot) = su ? W[0] : rp;
-                double ml = 0.0;
+            for (int r = 1; r <= kKL; r++) m[r] = col[r] * rp;
+            // final row j of U (lanes 0..16) and column j of L (lane r holds m[r]).  The
+            // stores are unconditional so that the memory counter stays static and the
+            // queued row loads remain in flight: a lane with nothing to store writes the
+            // reciprocal pivot to its slot, as every lane does.
+            double* const rslot = rd + j;
+            const bool su = lw && j + l < n;
+            *(su ? ab + (int64_t)j * kBandW + kKL + l : rslot) = su ? W[0] : rp;
+            double ml = 0.0;
 #pragma unroll
-                for (int r = 1; r <= kKL; r++) ml = l == r ? m[r] : ml;
-                const bool sm = l >= 1 && l <= kKL && j + l < n;
-                *(sm ? ab + (int64_t)(j + l) * kBandW + kKL - l : rslot) = sm ? ml : rp;
-                gp[j] = j + pr;
-                // rank-1 update of the window's lower rows (lane 0's column is done)
+            for (int r = 1; r <= kKL; r++) ml = l == r ? m[r] : ml;
+            const bool sm = l >= 1 && l <= kKL && j + l < n;
+            *(sm ? ab + (int64_t)(j + l) * kBandW + kKL - l : rslot) = sm ? ml : rp;
+            ip[j] = j + pr;
+            // rank-1 update of the window's lower rows (lane 0's column is done)
 #pragma unroll
-                for (int r = 1; r <= kKL; r++) W[r] = fma(-m[r], W[0], W[r]);
-                // shift: lane l takes column j+1+l, rows j+1 .. j+1+kKL (lanes past the window hold
-                // zeros, which is what rows j+1 .. j+kKL of column j+1+kKL+kKU are: beyond the
-                // original upper bandwidth and untouched so far); the entering bottom row comes
-                // from the queue, refilled with the row needed kFacAhead shifts later
+            for (int r = 1; r <= kKL; r++) W[r] = fma(-m[r], W[0], W[r]);
+            // shift: lane l takes column j+1+l, rows j+1 .. j+1+kKL (lanes past the window hold
+            // zeros, which is what rows j+1 .. j+kKL of column j+1+kKL+kKU are: beyond the
+            // original upper bandwidth and untouched so far); the entering bottom row comes
+            // from the queue, refilled with the row needed kFacAhead shifts later
 #pragma unroll
-                for (int r = 0; r < kKL; r++) W[r] = wave_next_f64(W[r + 1]);
-                W[kKL] = Qok[qs] ? Q[qs] : 0.0;
-                Q[qs] = at_queued(j + 1 + kKL + kFacAhead, j + 1 + kFacAhead + l, Qok[qs]);
+            for (int r = 0; r < kKL; r++) W[r] = wave_next_f64(W[r + 1]);
+            W[kKL] = Qok[qs] ? Q[qs] : 0.0;
+            Q[qs] = at_queued(j + 1 + kKL + kFacAhead, j + 1 + kFacAhead + l, Qok[qs]);
+        }
+    }
+    if (kStaged) {
+        __syncthreads();
+        const int ne = n * kBandW;
+        for (int e = l; e < ne; e += 64) gab[e] = ab[e];
+        for (int e = l; e < n; e += 64) {
+            grd[e] = rd[e];
+            gip[e] = ip[e];
         }
     }
     if (l == 0) flag[f] = bad;
+}
+
+// LDS of the staged factor of a filament of n unknowns
+__host__ __device__ constexpr size_t factor_lds_bytes(int n) {
+    return (size_t)n * kBandW * sizeof(double) + (size_t)n * (sizeof(double) + sizeof(int32_t));
 }
 
 
@@ -1109,10 +1166,13 @@ __device__ __forceinline__ double diff_unit(int c, int i, int N) {
 // kKL + kKU + 1 rows backward), so each sweep step is a few FMAs on registers.
 // The band (between zero rows, so that no coefficient read needs a bounds test),
 // the reciprocal pivots and the pivot rows are staged in LDS and shared by all
-// threads; the pivot row is wave-uniform.  Forward results wait in LDS for the
-// backward sweep, whose results are then written as row c of Ainv^T.
-// zero band rows before / after the filament: the prefetches one step past either end stay inside
-constexpr int kInvPadLo = kKL + kKU + 1, kInvPadHi = kKL + 1;
+// threads.  A step's coefficients are read two steps ahead into one of two
+// register sets (even and odd steps), and the pivot rows of 64 steps sit in one
+// register (lane k: step 64q + k) read by lane index, so no step waits on LDS for
+// its own data.  Forward results wait in LDS for the backward sweep, whose results
+// are then written as row c of Ainv^T.
+// zero band rows before / after the filament: the reads two steps past either end stay inside
+constexpr int kInvPadLo = kKL + kKU + 2, kInvPadHi = kKL + 2;
 
 // the (at most two) nonzero entries of D e_c in the interleaved order, c in the
 // original unknown order: Y_1 and the multipliers are row-differenced, u is not
@@ -1159,11 +1219,21 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
     const int c = c0 + t;
     const bool live = t < CB && c < n;
     {
+        // the band rows are contiguous: zero the padding, copy n * kBandW values with
+        // eight loads in flight per thread
         const double* gab = AB + 6 * s0 * kBandW;
-        for (int e = t; e < nrows * kBandW; e += blockDim.x) {
-            const int r = e / kBandW - kInvPadLo;
-            lds[e] = (r >= 0 && r < n) ? gab[(int64_t)r * kBandW + e % kBandW] : 0.0;
+        for (int e = t; e < kInvPadLo * kBandW; e += 64) lds[e] = 0.0;
+        for (int e = t; e < kInvPadHi * kBandW; e += 64) ab[(int64_t)n * kBandW + e] = 0.0;
+        const int ne = n * kBandW;
+        int e = t;
+        for (; e + 7 * 64 < ne; e += 8 * 64) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[u] = gab[e + u * 64];
+#pragma unroll
+            for (int u = 0; u < 8; u++) ab[e + u * 64] = v[u];
         }
+        for (; e < ne; e += 64) ab[e] = gab[e];
         for (int e = t; e < n; e += blockDim.x) {
             ip[e] = ipiv[6 * s0 + e];
             rd[e] = rdiag[6 * s0 + e];
@@ -1179,70 +1249,88 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
     double W[kKL + 1];
 #pragma unroll
     for (int k = 0; k <= kKL; k++) W[k] = rhs(k);
-    // the next step's pivot and multipliers are read before this step's arithmetic
-    double Lc[kKL + 1], Ln[kKL + 1];
-    int pc, pn = 0;
-    auto load_fwd = [&](int j, double (&Lv)[kKL + 1], int& pv) {
-        const double* col = ab + (int64_t)j * kBandW + kKL;  // L(j+k, j) = col[k*(kBandW-1)] (zero rows past n)
-        pv = __builtin_amdgcn_readfirstlane(ip[min(j, n - 1)]) - j;  // 0..kKL, the same for every thread
+    // L(j+k, j) = ab[(j + k) * kBandW + kKL - k], k = 1..kKL (zero rows past n)
+    auto load_fwd = [&](int j, double (&Lv)[kKL]) {
+        const double* col = ab + (int64_t)j * kBandW + kKL;
 #pragma unroll
-        for (int k = 1; k <= kKL; k++) Lv[k] = col[k * (kBandW - 1)];
+        for (int k = 1; k <= kKL; k++) Lv[k - 1] = col[k * (kBandW - 1)];
     };
-    load_fwd(0, Lc, pc);
-    for (int j = 0; j < n; j++) {
-        load_fwd(j + 1, Ln, pn);
+    int ipc = ip[min(t, n - 1)], ipn = ip[min(64 + t, n - 1)];
+    auto fwd_step = [&](int j, const double (&L)[kKL]) {
+        if ((j & 63) == 0 && j > 0) {
+            ipc = ipn;
+            ipn = ip[min(j + 64 + t, n - 1)];
+        }
+        const int pc = __builtin_amdgcn_readlane(ipc, j & 63) - j;  // 0..kKL, wave-uniform
         if (__builtin_expect(pc != 0, 0)) {
             const double w0 = W[0];
-            switch (pc) {
-#define FIL_SWAP_W(k)  \
-    case k:            \
-        W[0] = W[k];   \
-        W[k] = w0;     \
-        break;
-                FIL_SWAP_W(1) FIL_SWAP_W(2) FIL_SWAP_W(3) FIL_SWAP_W(4)
-                FIL_SWAP_W(5) FIL_SWAP_W(6) FIL_SWAP_W(7) FIL_SWAP_W(8)
-#undef FIL_SWAP_W
-                default: break;
+            double wp = w0;
+#pragma unroll
+            for (int k = 1; k <= kKL; k++) {
+                const bool s = pc == k;
+                wp = s ? W[k] : wp;
+                W[k] = s ? w0 : W[k];
             }
+            W[0] = wp;
         }
         const double yj = W[0];
         if (t < CB) ybuf[(int64_t)j * CB + t] = yj;
 #pragma unroll
-        for (int k = 0; k < kKL; k++) W[k] = fma(-Lc[k + 1], yj, W[k + 1]);
+        for (int k = 0; k < kKL; k++) W[k] = fma(-L[k], yj, W[k + 1]);
         W[kKL] = rhs(j + kKL + 1);
-#pragma unroll
-        for (int k = 1; k <= kKL; k++) Lc[k] = Ln[k];
-        pc = pn;
+    };
+    {
+        double LA[kKL], LB[kKL];
+        load_fwd(0, LA);
+        load_fwd(1, LB);
+        for (int j = 0; j < n; j += 2) {
+            fwd_step(j, LA);
+            load_fwd(j + 2, LA);
+            if (j + 1 < n) {
+                fwd_step(j + 1, LB);
+                load_fwd(j + 3, LB);
+            }
+        }
     }
     __syncthreads();
     // ---- backward: B[k] = y[i - kU + k]
     double B[kU + 1];
     const int i0 = n - 1;
+    const int tt = t < CB ? t : 0;
 #pragma unroll
     for (int k = 0; k <= kU; k++) {
         const int r = i0 - kU + k;
         B[k] = (r >= 0 && t < CB) ? ybuf[(int64_t)r * CB + t] : 0.0;
     }
-    auto load_bwd = [&](int i, double (&Uv)[kU + 1]) {
-        const double* row = ab + (int64_t)i * kBandW + kKL;  // U(i-k, i) = row[k - k*kBandW] (zero rows before 0)
+    // U(i-k, i) = ab[(i - k) * kBandW + kKL + k] (zero rows before 0) and 1 / U(i, i);
+    // y[i - kU - 1], the value entering the window after step i
+    auto load_bwd = [&](int i, double (&Uv)[kU + 1], double& bn) {
+        const double* row = ab + (int64_t)i * kBandW + kKL;
         Uv[0] = rd[max(i, 0)];
 #pragma unroll
         for (int k = 1; k <= kU; k++) Uv[k] = row[k - (int64_t)k * kBandW];
+        bn = ybuf[(int64_t)max(i - kU - 1, 0) * CB + tt];
     };
-    double Uc[kU + 1], Un[kU + 1];
-    load_bwd(i0, Uc);
-    const int tt = t < CB ? t : 0;
-    for (int i = i0; i >= 0; i--) {
-        load_bwd(i - 1, Un);
-        const int r = i - kU - 1;
-        const double bnext = ybuf[(int64_t)max(r, 0) * CB + tt];
-        const double xi = B[kU] * Uc[0];
+    auto bwd_step = [&](int i, const double (&U)[kU + 1], double bn) {
+        const double xi = B[kU] * U[0];
 #pragma unroll
-        for (int k = kU; k > 0; k--) B[k] = fma(-Uc[kU - k + 1], xi, B[k - 1]);
+        for (int k = kU; k > 0; k--) B[k] = fma(-U[kU - k + 1], xi, B[k - 1]);
         if (t < CB) ybuf[(int64_t)i * CB + t] = xi;
-        B[0] = r >= 0 ? bnext : 0.0;
-#pragma unroll
-        for (int k = 0; k <= kU; k++) Uc[k] = Un[k];
+        B[0] = i - kU - 1 >= 0 ? bn : 0.0;
+    };
+    {
+        double UA[kU + 1], UB[kU + 1];
+        double bA, bB;
+        load_bwd(i0, UA, bA);
+        load_bwd(i0 - 1, UB, bB);
+        for (int i = i0; i >= 0; i -= 2) {
+            bwd_step(i, UA, bA);
+            load_bwd(i - 2, UA, bA);
+            if (i - 1 >= 0) {
+                bwd_step(i - 1, UB, bB);
+                load_bwd(i - 3, UB, bB);
+            }
+        }
     }
     __syncthreads();
     // ---- row c of Ainv^T (original unknown order), coalesced over i
@@ -1275,12 +1363,22 @@ int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const 
                      double* AinvT, hipStream_t st) {
     if (d.M == 0) return FIL_OK;
     j0_band_assemble_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, bc, X, qc, Tint, tt, active, AB);
-    j0_band_factor_regs_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, active, AB, ipiv, rdiag, flag);
     // filaments grouped by size so that each launch's LDS fits its own largest filament
     for (int k = 0; k < d.ncls; k++) {
         const int64_t coff = d.cls_off[k], cnt = d.cls_off[k + 1] - coff;
         if (cnt == 0) continue;
         const int nc = d.cls_n[k];
+        // the staged factor while the class's filaments fit on the chip in at most
+        // kFacStagedRounds rounds of resident workgroups, else the one without LDS (all
+        // resident at once)
+        const size_t fl = factor_lds_bytes(nc);
+        const int64_t per_cu = std::min<int64_t>(kFacWavesPerCU, (int64_t)(kLdsPerCU / fl));
+        if (per_cu > 0 && cnt <= kFacStagedRounds * kNumCU * per_cu) {
+            if (int rc = allow_lds(j0_band_factor_kernel<true>, fl)) return rc;
+            j0_band_factor_kernel<true><<<(unsigned)cnt, 64, fl, st>>>(d, active, AB, ipiv, rdiag, flag, coff);
+        } else {
+            j0_band_factor_kernel<false><<<(unsigned)cnt, 64, 0, st>>>(d, active, AB, ipiv, rdiag, flag, coff);
+        }
         if (!AinvT) continue;
         // one thread per inverse column; a block's columns (64, 32 or 16, so that its
         // band, pivots and forward results fit in LDS) share the staged factor
