@@ -892,110 +892,109 @@ __global__ void __launch_bounds__(256) j0_band_assemble_kernel(SimDev d, BdfCoef
 
 
 
+// 1 / x: hardware reciprocal and two Newton steps
+__device__ __forceinline__ double rcp_f64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // LU with partial pivoting of every filament's banded system, one wave each, in a
 // register window: lane l holds column j + l (l <= kKL + kKU) of rows j .. j + kKL,
 // the only rows and columns step j reads or writes (row p <= j + kKL has no
 // entries right of column j + kKL + kKU, before or after fill-in).  Step j takes
 // the pivot from lane 0's column (broadcast), swaps rows inside every lane, writes
 // row j of U and column j of L, updates the window and shifts it one column left /
-// one row down; the row entering at the bottom was requested kFacAhead steps
-// earlier.
-// kStaged: the filament's band is first copied to LDS (all loads in flight at
-// once) and factored there in place, with the pivots and reciprocal pivots, and
-// copied back at the end, so the row loop holds no global memory access: a global
-// load in the loop makes every row wait for a memory round trip.  Without staging
-// (no LDS, so that every filament of a large ensemble can be resident at once) the
-// rows enter from global memory and the results go straight there.
-constexpr int kFacAhead = 4;
-// launch choice: MI355X has 256 CUs with 160 KB of LDS each; the unstaged factor's
-// register use allows 20 of its waves per CU; staging is taken while a class needs at
-// most 4 rounds of resident workgroups
-constexpr int64_t kNumCU = 256, kFacWavesPerCU = 20, kFacStagedRounds = 4;
-constexpr size_t kLdsPerCU = 160 * 1024;
+// one row down; the row entering at the bottom comes from global memory, requested
+// a few steps earlier (a queue unrolled by its depth, each load unconditional at a
+// clamped address and masked when used, so that it stays in flight).
+// kStaged: the results (U rows, L columns, pivots, reciprocal pivots) are kept in
+// LDS and written out in band layout at the end, so the only memory counter the row
+// loop waits on is that of its own queued loads; the loop runs a multiple of the
+// queue depth with the surplus steps inert, so it has no exit inside.  Without
+// staging (no LDS, so that every filament of a large ensemble can be resident at
+// once) the results go straight to the band, every store unconditional.
 template <bool kStaged>
 __global__ void __launch_bounds__(64) j0_band_factor_kernel(SimDev d, const int32_t* __restrict__ active,
                                                           double* __restrict__ AB, int32_t* __restrict__ ipiv,
                                                           double* __restrict__ rdiag, int32_t* __restrict__ flag,
                                                           int64_t coff) {
     constexpr int kWin = kKL + kKU + 1;  // window columns (17)
+    constexpr int QD = kStaged ? 8 : 4;  // queue depth
     const int64_t f = d.cls_fil[coff + blockIdx.x];
     if (!active[d.fil_susp[f]]) return;
     const int64_t s0 = d.seg_off[f];
     const int n = 6 * (int)(d.seg_off[f + 1] - s0);
     double* const gab = AB + 6 * s0 * kBandW;
-    int32_t* const gip = ipiv + 6 * s0;
-    double* const grd = rdiag + 6 * s0;
     const int l = threadIdx.x;
     const bool lw = l < kWin;
-    // LDS (staged): band [n][kBandW] | reciprocal pivots [n] | pivot rows [n]
+    // LDS (staged): U rows [n][kWin] | L columns [n][kKL] | reciprocal pivots [n] | pivot rows [n]
     extern __shared__ double fac_lds[];
-    double* const ab = kStaged ? fac_lds : gab;
-    double* const rd = kStaged ? fac_lds + (size_t)n * kBandW : grd;
-    int32_t* const ip = kStaged ? reinterpret_cast<int32_t*>(rd + n) : gip;
-    if (kStaged) {
-        const int ne = n * kBandW;
-        int e = l;
-        for (; e + 7 * 64 < ne; e += 8 * 64) {
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; u++) v[u] = gab[e + u * 64];
-#pragma unroll
-            for (int u = 0; u < 8; u++) ab[e + u * 64] = v[u];
-        }
-        for (; e < ne; e += 64) ab[e] = gab[e];
-        __syncthreads();
-    }
+    double* const Ur = fac_lds;
+    double* const Lm = Ur + (size_t)n * kWin;
+    double* const rd = kStaged ? Lm + (size_t)n * kKL : rdiag + 6 * s0;
+    int32_t* const ip = kStaged ? reinterpret_cast<int32_t*>(rd + n) : ipiv + 6 * s0;
     // element (r, c) of the band (0 outside the matrix); the band stores columns r-kKL .. r+kKL+kKU
     auto at = [&](int r, int c) {
-        return (lw && r < n && c < n && c - r >= -kKL && c - r <= kKL + kKU) ? ab[(int64_t)r * kBandW + (c - r + kKL)]
-                                                                            : 0.0;
+        return (lw && r < n && c < n && c - r >= -kKL && c - r <= kKL + kKU)
+                   ? gab[(int64_t)r * kBandW + (c - r + kKL)]
+                   : 0.0;
     };
     double W[kKL + 1];
 #pragma unroll
     for (int r = 0; r <= kKL; r++) W[r] = at(r, l);
-    // queue of the rows kKL+1 .. kKL+kFacAhead of this lane's future columns: each load
-    // is unconditional (a clamped address inside the filament's band) and its validity
-    // is applied when the value is used, so the load can stay in flight until then
     auto at_queued = [&](int r, int c, bool& ok) {
         ok = lw && r < n && c < n && c - r >= -kKL && c - r <= kKL + kKU;
-        return ab[ok ? (int64_t)r * kBandW + (c - r + kKL) : 0];
+        return gab[ok ? (int64_t)r * kBandW + (c - r + kKL) : 0];
     };
-    double Q[kFacAhead];
-    bool Qok[kFacAhead];
+    double Q[QD];
+    bool Qok[QD];
 #pragma unroll
-    for (int q = 0; q < kFacAhead; q++) Q[q] = at_queued(kKL + 1 + q, l + 1 + q, Qok[q]);
+    for (int q = 0; q < QD; q++) Q[q] = at_queued(kKL + 1 + q, l + 1 + q, Qok[q]);
     int bad = 0;
-    // unrolled by the queue depth: slot qs is consumed at steps j = qs (mod depth) and
-    // refilled in place, so each row load has kFacAhead steps to arrive
-    for (int j0 = 0; j0 < n; j0 += kFacAhead) {
+    // slot qs is consumed at steps j = qs (mod QD) and refilled in place
+    for (int j0 = 0; j0 < n; j0 += QD) {
 #pragma unroll
-        for (int qs = 0; qs < kFacAhead; qs++) {
+        for (int qs = 0; qs < QD; qs++) {
             const int j = j0 + qs;
-            if (j >= n) break;
+            if (!kStaged && j >= n) break;
             // pivot column j (lane 0) broadcast to the wave
             double col[kKL + 1];
 #pragma unroll
             for (int r = 0; r <= kKL; r++) col[r] = readlane_f64(W[r], 0);
-            // pivot row: the first maximum of |W[r]| in every lane's own column (lane 0's
-            // is used), a pairwise tree in which a later row wins only when strictly larger
-            double av[kKL + 1];
-            int ix[kKL + 1];
+            // reciprocal pivot and multipliers as if row j were its own pivot (the usual
+            // case for these blocks), beside the test of that: lane 0's |W[0]| is at least
+            // every |W[r]| of its column
+            double rp = rcp_f64(col[0]);
+            double m[kKL + 1];
 #pragma unroll
-            for (int r = 0; r <= kKL; r++) {
-                av[r] = fabs(W[r]);
-                ix[r] = r;
-            }
+            for (int r = 1; r <= kKL; r++) m[r] = col[r] * rp;
+            const double mx = fmax(fmax(fmax(fmax(fabs(W[0]), fabs(W[1])), fmax(fabs(W[2]), fabs(W[3]))),
+                                        fmax(fmax(fabs(W[4]), fabs(W[5])), fmax(fabs(W[6]), fabs(W[7])))),
+                                   fabs(W[8]));
+            const int keep = __builtin_amdgcn_readfirstlane((int)(fabs(W[0]) >= mx));
+            int pr = 0;
+            if (__builtin_expect(!keep, 0)) {
+                // pivot row: the first maximum of |W[r]| in every lane's own column (lane
+                // 0's is used), a pairwise tree in which a later row wins only when
+                // strictly larger; then the exchange (wave-uniform: selects) and the
+                // reciprocal and multipliers again
+                double bv[kKL + 1];
+                int ix[kKL + 1];
 #pragma unroll
-            for (int w = 1; w <= kKL; w *= 2)
+                for (int r = 0; r <= kKL; r++) {
+                    bv[r] = W[r];
+                    ix[r] = r;
+                }
 #pragma unroll
-                for (int r = 0; r + w <= kKL; r += 2 * w)
-                    if (av[r + w] > av[r]) {
-                        av[r] = av[r + w];
-                        ix[r] = ix[r + w];
-                    }
-            const int pr = __builtin_amdgcn_readfirstlane(ix[0]);
-            // row exchange (wave-uniform and rare for these blocks: one branch, selects inside)
-            if (__builtin_expect(pr != 0, 0)) {
+                for (int w = 1; w <= kKL; w *= 2)
+#pragma unroll
+                    for (int r = 0; r + w <= kKL; r += 2 * w)
+                        if (fabs(bv[r + w]) > fabs(bv[r])) {
+                            bv[r] = bv[r + w];
+                            ix[r] = ix[r + w];
+                        }
+                pr = __builtin_amdgcn_readfirstlane(ix[0]);
                 const double w0 = W[0], c0 = col[0];
                 double wp = w0, cp = c0;
 #pragma unroll
@@ -1008,56 +1007,90 @@ __global__ void __launch_bounds__(64) j0_band_factor_kernel(SimDev d, const int3
                 }
                 W[0] = wp;
                 col[0] = cp;
+                rp = rcp_f64(col[0]);
+#pragma unroll
+                for (int r = 1; r <= kKL; r++) m[r] = col[r] * rp;
             }
-            if (!(fabs(col[0]) > 0.0)) bad = 1;
-            // 1 / pivot: hardware reciprocal and two Newton steps
-            double rp = __builtin_amdgcn_rcp(col[0]);
-            rp = fma(rp, fma(-col[0], rp, 1.0), rp);
-            rp = fma(rp, fma(-col[0], rp, 1.0), rp);
-            double m[kKL + 1];
-#pragma unroll
-            for (int r = 1; r <= kKL; r++) m[r] = col[r] * rp;
-            // final row j of U (lanes 0..16) and column j of L (lane r holds m[r]).  The
-            // stores are unconditional so that the memory counter stays static and the
-            // queued row loads remain in flight: a lane with nothing to store writes the
-            // reciprocal pivot to its slot, as every lane does.
-            double* const rslot = rd + j;
             const bool su = lw && j + l < n;
-            *(su ? ab + (int64_t)j * kBandW + kKL + l : rslot) = su ? W[0] : rp;
-            double ml = 0.0;
+            if (kStaged) {
+                // row j of U (lanes 0..16); lane 0 keeps column j of L, the pivot row and
+                // the reciprocal pivot.  Steps past n write nothing.
+                if (su) Ur[(int64_t)j * kWin + l] = W[0];
+                if (l == 0 && j < n) {
+                    double2* lj = reinterpret_cast<double2*>(Lm + (int64_t)j * kKL);
 #pragma unroll
-            for (int r = 1; r <= kKL; r++) ml = l == r ? m[r] : ml;
-            const bool sm = l >= 1 && l <= kKL && j + l < n;
-            *(sm ? ab + (int64_t)(j + l) * kBandW + kKL - l : rslot) = sm ? ml : rp;
-            ip[j] = j + pr;
+                    for (int r = 1; r <= kKL; r += 2) lj[r / 2] = make_double2(m[r], m[r + 1]);
+                    ip[j] = j + pr;
+                    rd[j] = rp;
+                }
+                if (j < n && !(fabs(col[0]) > 0.0)) bad = 1;
+            } else {
+                // final row j of U (lanes 0..16) and column j of L (lane r holds m[r]) in
+                // the band.  The stores are unconditional so that the memory counter stays
+                // static and the queued row loads remain in flight: a lane with nothing to
+                // store writes the reciprocal pivot to its slot, as every lane does.
+                double* const rslot = rd + j;
+                *(su ? gab + (int64_t)j * kBandW + kKL + l : rslot) = su ? W[0] : rp;
+                double ml = 0.0;
+#pragma unroll
+                for (int r = 1; r <= kKL; r++) ml = l == r ? m[r] : ml;
+                const bool sm = l >= 1 && l <= kKL && j + l < n;
+                *(sm ? gab + (int64_t)(j + l) * kBandW + kKL - l : rslot) = sm ? ml : rp;
+                ip[j] = j + pr;
+                if (!(fabs(col[0]) > 0.0)) bad = 1;
+            }
             // rank-1 update of the window's lower rows (lane 0's column is done)
 #pragma unroll
             for (int r = 1; r <= kKL; r++) W[r] = fma(-m[r], W[0], W[r]);
             // shift: lane l takes column j+1+l, rows j+1 .. j+1+kKL (lanes past the window hold
             // zeros, which is what rows j+1 .. j+kKL of column j+1+kKL+kKU are: beyond the
             // original upper bandwidth and untouched so far); the entering bottom row comes
-            // from the queue, refilled with the row needed kFacAhead shifts later
+            // from the queue, refilled with the row needed QD shifts later
 #pragma unroll
             for (int r = 0; r < kKL; r++) W[r] = wave_next_f64(W[r + 1]);
             W[kKL] = Qok[qs] ? Q[qs] : 0.0;
-            Q[qs] = at_queued(j + 1 + kKL + kFacAhead, j + 1 + kFacAhead + l, Qok[qs]);
+            Q[qs] = at_queued(j + 1 + kKL + QD, j + 1 + QD + l, Qok[qs]);
         }
     }
     if (kStaged) {
         __syncthreads();
+        // band row r, slot k: k < kKL is L(r, c), c = r - kKL + k (column c's multiplier
+        // r - c); k >= kKL is U(r, r + k - kKL); slots outside the matrix are zero
         const int ne = n * kBandW;
-        for (int e = l; e < ne; e += 64) gab[e] = ab[e];
-        for (int e = l; e < n; e += 64) {
-            grd[e] = rd[e];
-            gip[e] = ip[e];
+        auto band_out = [&](int e) {
+            const int r = e / kBandW, k = e - r * kBandW;
+            if (k < kKL) {
+                const int c = r - kKL + k;
+                return c >= 0 ? Lm[(int64_t)c * kKL + (kKL - 1 - k)] : 0.0;
+            }
+            return r + (k - kKL) < n ? Ur[(int64_t)r * kWin + (k - kKL)] : 0.0;
+        };
+        int e = l;
+        for (; e + 7 * 64 < ne; e += 8 * 64) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[u] = band_out(e + u * 64);
+#pragma unroll
+            for (int u = 0; u < 8; u++) gab[e + u * 64] = v[u];
+        }
+        for (; e < ne; e += 64) gab[e] = band_out(e);
+        for (int i = l; i < n; i += 64) {
+            rdiag[6 * s0 + i] = rd[i];
+            ipiv[6 * s0 + i] = ip[i];
         }
     }
     if (l == 0) flag[f] = bad;
 }
 
+// launch choice: MI355X has 256 CUs with 160 KB of LDS each; the unstaged factor's
+// register use allows 20 of its waves per CU; staging is taken while a class needs at
+// most 4 rounds of resident workgroups
+constexpr int64_t kNumCU = 256, kFacWavesPerCU = 20, kFacStagedRounds = 4;
+constexpr size_t kLdsPerCU = 160 * 1024;
+
 // LDS of the staged factor of a filament of n unknowns
 __host__ __device__ constexpr size_t factor_lds_bytes(int n) {
-    return (size_t)n * kBandW * sizeof(double) + (size_t)n * (sizeof(double) + sizeof(int32_t));
+    return (size_t)n * (kKL + kKU + 1 + kKL + 1) * sizeof(double) + (size_t)n * sizeof(int32_t);
 }
 
 
@@ -1207,13 +1240,15 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
     const int n = 6 * N;
     const int c0 = blockIdx.y * CB;
     if (c0 >= n) return;
-    // LDS: band rows [-kInvPadLo, n + kInvPadHi) | forward results [n][CB] | reciprocal
+    // LDS: band rows [-kInvPadLo, n + kInvPadHi) | forward results [n][CB + 1] (rows padded
+    // by one so that a column read across lanes spreads over the banks) | reciprocal
     // pivots [n] | pivot rows [n]
     extern __shared__ double lds[];
     const int nrows = n + kInvPadLo + kInvPadHi;
     double* ab = lds + (size_t)kInvPadLo * kBandW;  // ab[i * kBandW + k] for i in [-kInvPadLo, n + kInvPadHi)
     double* ybuf = lds + (size_t)nrows * kBandW;
-    double* rd = ybuf + (size_t)n * CB;
+    constexpr int YS = CB + 1;  // row stride of the forward results
+    double* rd = ybuf + (size_t)n * YS;
     int* ip = reinterpret_cast<int*>(rd + n);
     const int t = threadIdx.x;
     const int c = c0 + t;
@@ -1274,7 +1309,7 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
             W[0] = wp;
         }
         const double yj = W[0];
-        if (t < CB) ybuf[(int64_t)j * CB + t] = yj;
+        if (t < CB) ybuf[(int64_t)j * YS + t] = yj;
 #pragma unroll
         for (int k = 0; k < kKL; k++) W[k] = fma(-L[k], yj, W[k + 1]);
         W[kKL] = rhs(j + kKL + 1);
@@ -1300,7 +1335,7 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
 #pragma unroll
     for (int k = 0; k <= kU; k++) {
         const int r = i0 - kU + k;
-        B[k] = (r >= 0 && t < CB) ? ybuf[(int64_t)r * CB + t] : 0.0;
+        B[k] = (r >= 0 && t < CB) ? ybuf[(int64_t)r * YS + t] : 0.0;
     }
     // U(i-k, i) = ab[(i - k) * kBandW + kKL + k] (zero rows before 0) and 1 / U(i, i);
     // y[i - kU - 1], the value entering the window after step i
@@ -1309,13 +1344,13 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
         Uv[0] = rd[max(i, 0)];
 #pragma unroll
         for (int k = 1; k <= kU; k++) Uv[k] = row[k - (int64_t)k * kBandW];
-        bn = ybuf[(int64_t)max(i - kU - 1, 0) * CB + tt];
+        bn = ybuf[(int64_t)max(i - kU - 1, 0) * YS + tt];
     };
     auto bwd_step = [&](int i, const double (&U)[kU + 1], double bn) {
         const double xi = B[kU] * U[0];
 #pragma unroll
         for (int k = kU; k > 0; k--) B[k] = fma(-U[kU - k + 1], xi, B[k - 1]);
-        if (t < CB) ybuf[(int64_t)i * CB + t] = xi;
+        if (t < CB) ybuf[(int64_t)i * YS + t] = xi;
         B[0] = i - kU - 1 >= 0 ? bn : 0.0;
     };
     {
@@ -1333,12 +1368,35 @@ __global__ void __launch_bounds__(64) j0_inverse_cols_kernel(SimDev d, const dou
         }
     }
     __syncthreads();
-    // ---- row c of Ainv^T (original unknown order), coalesced over i
+    // ---- row c of Ainv^T (original unknown order): column by column, lane t taking
+    // rows t, t + 64, ... whose destination slots it computes once
+    constexpr int kRowsPerLane = (6 * kMaxSeg + 63) / 64;
+    int sl[kRowsPerLane];
+#pragma unroll
+    for (int q = 0; q < kRowsPerLane; q++) {
+        const int i = t + 64 * q;
+        sl[q] = i < n ? slot_of(i / 3, N) + i % 3 : 0;
+    }
     const int ncols = min(CB, n - c0);
     double* base = AinvT + d.dense_off[f] + (int64_t)c0 * n;
-    for (int e = t; e < ncols * n; e += blockDim.x) {
-        const int cc = e / n, i = e % n;
-        base[(int64_t)cc * n + slot_of(i / 3, N) + i % 3] = ybuf[(int64_t)i * CB + cc];
+    // four columns per pass: their LDS reads are issued before any of the stores
+    for (int cb = 0; cb < ncols; cb += 4) {
+        double v[4][kRowsPerLane];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int q = 0; q < kRowsPerLane; q++) {
+                const int i = t + 64 * q;
+                v[u][q] = i < n ? ybuf[(int64_t)i * YS + min(cb + u, CB - 1)] : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (cb + u >= ncols) break;
+            double* row = base + (int64_t)(cb + u) * n;
+#pragma unroll
+            for (int q = 0; q < kRowsPerLane; q++)
+                if (t + 64 * q < n) row[sl[q]] = v[u][q];
+        }
     }
 }
 
@@ -1383,7 +1441,7 @@ int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const 
         // one thread per inverse column; a block's columns (64, 32 or 16, so that its
         // band, pivots and forward results fit in LDS) share the staged factor
         auto lds = [nc](int cb) {
-            return ((size_t)(nc + kInvPadLo + kInvPadHi) * kBandW + (size_t)nc * (cb + 1)) * sizeof(double) +
+            return ((size_t)(nc + kInvPadLo + kInvPadHi) * kBandW + (size_t)nc * (cb + 2)) * sizeof(double) +
                    (size_t)nc * sizeof(int);
         };
         if (nc <= 128) {
