@@ -1,0 +1,124 @@
+"""Validation workloads on the GPU path (the paper's convergence and sedimentation
+checks, Sec. 5: convergence in time; Sec. 6.2.1, settling filament).
+
+* BDF2 in time: settling filaments integrated to the same final time with halved
+  steps converge at second order toward a run with a much smaller step and a tight
+  Broyden tolerance.
+* Settling filament (N = 31, dt = T/30, unbounded RPY): the normal deflection A/L
+  grows linearly with the elasto-gravitational number B and then levels off; the
+  effective drag relative to a rigid rod decays with B; and at small B the settling
+  speed is that of a rigid rod, computed here independently from the oracle's
+  assembled RPY mobility matrix.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _fil():
+    import paper_1903_12609_amd as fil
+    from paper_1903_12609_amd import synth
+    return fil, synth
+
+
+def _square_of_filaments(synth, N, dt_over_T, tol, d=20.0):
+    """Four straight filaments along x, perpendicular to gravity (-z), their centres at
+    the corners of a square of side d in the plane normal to their axes."""
+    q = np.tile(np.array([1.0, 0.0, 0.0, 0.0]), (N, 1))
+    Ys, qs = [], []
+    for oy, oz in ((-d / 2, -d / 2), (d / 2, -d / 2), (-d / 2, d / 2), (d / 2, d / 2)):
+        Y = synth.chain(np.zeros(3), q)
+        Y -= Y.mean(axis=0)
+        Ys.append(Y + np.array([0.0, oy, oz]))
+        qs.append(q)
+    params, T = synth.sedimentation_params(N, 1e3, dt_over_T, tol, 100, steric=False)
+    return np.arange(0, 4 * N + 1, N, dtype=np.int64), np.concatenate(Ys), np.concatenate(qs), params
+
+
+def _positions_at(fil, synth, steps_per_T, tf_T, tol, N=30):
+    fo, Y, q, params = _square_of_filaments(synth, N, 1.0 / steps_per_T, tol)
+    sim = fil.Sim(fo, Y, q, params, graph=8)
+    for _ in range(int(round(tf_T * steps_per_T))):
+        rep = sim.step()
+        assert rep[0]["converged"]
+    return sim.read_state()[0]
+
+
+def test_bdf2_second_order_in_time():
+    fil, synth = _fil()
+    tf = 0.5  # final time in settling times T
+    ref = _positions_at(fil, synth, 3200, tf, 1e-12)
+    errs = []
+    for m in (50, 100, 200, 400):
+        Y = _positions_at(fil, synth, m, tf, 1e-10)
+        errs.append(float(np.max(np.linalg.norm(Y - ref, axis=1))))
+    print("max position error at dt = T/50 .. T/400:", errs)
+    for e0, e1 in zip(errs, errs[1:]):
+        # halving dt divides the error by 4 (observed 4.03-4.06)
+        assert 3.6 < e0 / e1 < 4.4, errs
+    assert errs[0] > 1e3 * 1e-10  # the errors measured are the scheme's, not the tolerance's
+
+
+def _rigid_rod_speed(oracle, N, dL, a, eta):
+    """Settling speed per unit force per length (V eta / W) of a rigid straight rod of N
+    spheres moving broadside without rotating: the grand RPY mobility solved for the
+    force and torque distribution giving every sphere the same velocity and no spin."""
+    Y = np.zeros((N, 3))
+    Y[:, 0] = dL * np.arange(N)
+    Mg = oracle.rpy_matrix(Y, a, eta)
+    rhs = np.zeros(6 * N)
+    rhs[2:3 * N:3] = 1.0  # unit velocity along z, zero angular velocity
+    ft = np.linalg.solve(Mg, rhs)
+    drag = ft[2:3 * N:3].sum()  # total force per unit speed
+    return N * dL * eta / drag
+
+
+def test_settling_filament_deflection_and_drag():
+    fil, synth = _fil()
+    import oracle
+    Bs = [0.1, 1.0, 10.0, 1e3, 3e3]
+    N = 31
+    L = N * synth.DL
+    q = np.tile(np.array([1.0, 0.0, 0.0, 0.0]), (N, 1))
+    Ys = []
+    for i in range(len(Bs)):
+        Y = synth.chain(np.zeros(3), q)
+        Y -= Y.mean(axis=0)
+        Y[:, 1] += 1000.0 * i  # separate suspensions; far apart anyway
+        Ys.append(Y)
+    fo = np.arange(0, len(Bs) * N + 1, N, dtype=np.int64)
+    sfo = np.arange(0, len(Bs) + 1, dtype=np.int64)
+    params, _ = synth.sedimentation_params(N, 1e3, 1.0 / 30, 1e-8, 100, steric=False)
+    sim = fil.Sim(fo, np.concatenate(Ys), np.tile(q, (len(Bs), 1)), params, susp_fil_off=sfo, graph=8)
+    W = np.array([b * synth.KB / L ** 3 for b in Bs])
+    T = synth.ETA * L / W
+    sim.set_suspension_params(dt=T / 30, grav=np.stack([0 * W, 0 * W, -W * synth.DL], 1), FS=np.zeros(len(Bs)))
+    snaps = []
+    for s in range(900):  # 30 settling times
+        rep = sim.step()
+        assert all(r["converged"] for r in rep)
+        if s % 30 == 29:
+            snaps.append(sim.read_state()[0])
+    A, V, Vprev = [], [], []
+    for i in range(len(Bs)):
+        seg = slice(i * N, (i + 1) * N)
+        y2, y1, y0 = snaps[-3][seg], snaps[-2][seg], snaps[-1][seg]
+        A.append((y0[:, 2].max() - y0[:, 2].min()) / L)
+        V.append((y1[:, 2].mean() - y0[:, 2].mean()) / T[i] * synth.ETA / W[i])
+        Vprev.append((y2[:, 2].mean() - y1[:, 2].mean()) / T[i] * synth.ETA / W[i])
+    gam = [V[0] / v for v in V]  # gamma / gamma^0 with the stiffest filament as the rod
+    print("B", Bs, "\nA/L", A, "\nV eta/W", V, "\ngamma/gamma0", gam)
+    # steady state reached: the settling speed over the last two settling times agrees
+    for v, vp in zip(V, Vprev):
+        assert abs(v - vp) < 1e-4 * abs(v)
+    # linear growth of the deflection with B at small B
+    assert 9.5 < A[1] / A[0] < 10.5 and 9.5 < A[2] / A[1] < 10.5, A
+    # levelling off at large B
+    assert 0.3 < A[3] < 0.5 and abs(A[4] - A[3]) < 0.06 * A[3], A
+    # the drag decays with B from the rigid rod's
+    assert gam[2] > 0.999 and gam[3] < 0.8 and gam[4] < gam[3], gam
+    # small B: the rigid rod's settling speed from the oracle's RPY matrix (observed
+    # agreement 1.3e-8; the deflection at B = 0.1 changes the drag at O((A/L)^2))
+    v_rod = _rigid_rod_speed(oracle, N, synth.DL, synth.A, synth.ETA)
+    assert abs(V[0] - v_rod) < 1e-6 * v_rod, (V[0], v_rod)
