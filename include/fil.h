@@ -148,6 +148,14 @@ void fil_destroy(fil_sim* sim);
  * fil_params.dt).  FIL_EINVAL on a bad value, nothing changed. */
 int fil_set_suspension_params(fil_sim* sim, const double* dt, const double* grav, const double* FS);
 
+/* A further external force on every segment, added to the gravity force in the force
+ * balance of each segment (the external forces of Sec. 2.5, e.g. the end load of the
+ * clamped filament of Sec. 5.1).  HOST array double[S][3], copied in; NULL removes it.
+ * Only before the first step (captured iterations read the force's address).  Not
+ * part of checkpoints.  FIL_EINVAL on a non-finite value, FIL_ENOMEM if the device
+ * copy cannot be allocated. */
+int fil_set_external_forces(fil_sim* sim, const double* Fext);
+
 /* One time step: warm start, J0 and its inverse, Broyden iterations on the
  * device (one mobility apply each), then q^{j+1} = exp(u) . q^j, the robot-arm
  * positions and the history shift.  The first step is BDF1, later ones BDF2.

@@ -57,6 +57,7 @@ class Params(C.Structure):
         ("dt", C.c_double), ("tol", C.c_double), ("kmax", C.c_int64),
         ("K0", C.c_double), ("kw", C.c_double), ("omega", C.c_double), ("phase", _dp),
         ("tether", _i32p), ("base", _dp), ("nthreads", C.c_int64), ("drag_only", C.c_int64),
+        ("fext", _dp),
     ]
 
 
@@ -215,7 +216,8 @@ class Sim:
     ``fil_off`` [M+1] segment offsets; ``Y0`` [S,3] and ``q0`` [S,4] the initial
     configuration (from the shared synthetic generators).  Keyword parameters
     mirror the method's: a, eta, dL, KB, KT, chi, FS, grav, dt, tol, kmax, K0,
-    kw, omega, phase [M], tether [M] (0/1), base [M,3], nthreads.
+    kw, omega, phase [M], tether [M] (0/1), base [M,3], fext [S,3] (a further external
+    force on each segment), nthreads.
     """
 
     def __init__(self, fil_off, Y0, q0, **kw):
@@ -254,6 +256,11 @@ class Sim:
             self._keep += [th, base]
             P.tether = th.ctypes.data_as(_i32p)
             P.base = _p(base)
+        fx = kw.get("fext")
+        if fx is not None:
+            fx = _f64(fx, (S, 3))
+            self._keep.append(fx)
+            P.fext = _p(fx)
         P.nthreads = kw.get("nthreads", 0)
         P.drag_only = int(kw.get("drag_only", 0))
         self.P = P

@@ -349,6 +349,7 @@ typedef struct {
     const double* base;      /* [M][3] clamped base positions */
     int64_t nthreads;        /* OpenMP threads for the RPY target loop (0: default) */
     int64_t drag_only;       /* 1: diagonal drag mobility, no steric, no gravity: the f0 of Sec. 3.2.1 */
+    const double* fext;      /* [S][3] further external force on each segment (Sec. 2.5), or NULL */
 } or_params;
 
 typedef struct {
@@ -417,7 +418,8 @@ void or_reconstruct(const or_params* P, const double* qj, const double* X, doubl
 }
 
 /* Forces and torques the segments exert on the fluid for configuration (Y, q) and
- * multipliers in X: F^H = F^C + F^B + gravity, T^H = T^C + T^E (Sec. 2.5 and the
+ * multipliers in X: F^H = F^C + F^B + gravity (+ further external forces),
+ * T^H = T^C + T^E (Sec. 2.5 and the
  * mobility problem of Sec. 2.8.2), plus tether multipliers on clamped bases. */
 void or_forces(const or_params* P, const double* Y, const double* q, const double* X, double tt, double* F,
                double* T) {
@@ -444,7 +446,7 @@ void or_forces(const or_params* P, const double* Y, const double* q, const doubl
         free(kap);
     }
     for (int64_t n = 0; n < S; n++)
-        for (int i = 0; i < 3; i++) F[3 * n + i] += P->grav[i];
+        for (int i = 0; i < 3; i++) F[3 * n + i] += P->grav[i] + (P->fext ? P->fext[3 * n + i] : 0.0);
     if (P->FS != 0.0) {
         int64_t* seg_fil = (int64_t*)malloc(S * sizeof(int64_t));
         for (int64_t f = 0; f < P->M; f++)
@@ -475,7 +477,7 @@ double or_residual(const or_params* P, const or_state* St, const double* X, doub
     if (P->drag_only) {
         /* f0: M replaced by diag(M) and no steric or external forces (Sec. 3.2.1) */
         or_params P0 = *P;
-        P0.FS = 0; P0.grav[0] = P0.grav[1] = P0.grav[2] = 0;
+        P0.FS = 0; P0.grav[0] = P0.grav[1] = P0.grav[2] = 0; P0.fext = NULL;
         or_forces(&P0, Y, q, X, tt, F, T);
         for (int64_t i = 0; i < 3 * S; i++) {
             V[i] = F[i] / (6.0 * PI * P->eta * P->a);

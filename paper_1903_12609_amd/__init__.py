@@ -158,6 +158,16 @@ class Sim:
         vp = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
         check(lib().fil_set_suspension_params(self._h, *[vp(a) for a in arrs]))
 
+    def set_external_forces(self, F):
+        """Further external force on every segment, [S, 3] (None removes it; before the first step)."""
+        import ctypes
+        import numpy as np
+        if F is None:
+            check(lib().fil_set_external_forces(self._h, None))
+            return
+        a = np.ascontiguousarray(np.asarray(F, dtype=np.float64).reshape(self.S, 3))
+        check(lib().fil_set_external_forces(self._h, a.ctypes.data_as(ctypes.c_void_p)))
+
     def features(self):
         """Raw per-filament features [M, 19N] (float32, device) at the committed state."""
         import torch

@@ -62,6 +62,7 @@ struct fil_sim {
     int graph_iters = 0;  // iterations per captured block; 0 runs every iteration from the host
     int pred_iters = 0;   // iterations the last device-driven solve took (0: none yet)
     hipStream_t cap_st = nullptr;  // private stream the blocks are captured on (launches go to st)
+    double* fext_d = nullptr;      // [3][S] external forces per segment (null until set)
     std::map<std::array<int, 5>, GraphEntry> graphs;
     SuspLog* log_d = nullptr;  // device log of the current solve [nsusp]
     SuspLog* log_h = nullptr;  // staging of the host's counts when the device takes over a solve
@@ -783,6 +784,34 @@ int fil_set_suspension_params(fil_sim* s, const double* dt, const double* grav, 
     FIL_CHECK_ARG(!differ || s->p.K0 == 0.0,
                   "fil_set_suspension_params: per-suspension dt needs a time-independent preferred curvature (K0 = 0)");
     FIL_HIP_TRY(hipMemcpy(s->spar, sp.data(), sp.size() * sizeof(double), hipMemcpyHostToDevice));
+    return FIL_OK;
+}
+
+int fil_set_external_forces(fil_sim* s, const double* Fext) {
+    FIL_CHECK_ARG(s, "fil_set_external_forces: null sim");
+    FIL_CHECK_ARG(s->step == 0, "fil_set_external_forces: only before the first step");
+    if (!Fext) {
+        s->d.fext = nullptr;
+        return FIL_OK;
+    }
+    const int64_t S = s->S;
+    std::vector<double> soa(3 * S);
+    for (int64_t n = 0; n < S; n++)
+        for (int c = 0; c < 3; c++) {
+            FIL_CHECK_ARG(std::isfinite(Fext[3 * n + c]), "fil_set_external_forces: non-finite force");
+            soa[c * S + n] = Fext[3 * n + c];
+        }
+    if (!s->fext_d) {
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(1, soa.size()) * sizeof(double)) != hipSuccess) {
+            set_error("fil_set_external_forces: out of device memory");
+            return FIL_ENOMEM;
+        }
+        s->dev_allocs.push_back(p);
+        s->fext_d = static_cast<double*>(p);
+    }
+    FIL_HIP_TRY(hipMemcpy(s->fext_d, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice));
+    s->d.fext = s->fext_d;
     return FIL_OK;
 }
 

@@ -134,7 +134,7 @@ __device__ __forceinline__ V3 joint_kappa(const SimDev& d, int64_t f, int64_t k,
 // ---------------------------------------------------------------- state + forces
 // Filament f's configuration from its unknowns Xf (global memory or LDS):
 // q_n = exp(u_n) q^j_n, t_n, robot-arm positions Y_n = Y_1 + dL/2 sum_{m<n} (t_m + t_{m+1})
-// and the filament's bounding box, then F = F^C + gravity (+ lambda_1),
+// and the filament's bounding box, then F = F^C + gravity (+ external) (+ lambda_1),
 // T = T^C + T^E (+ lambda_2).  Every thread of the workgroup calls it (it holds a
 // barrier); lane n of the first wave owns segment n (N <= 64) and passes q^j_n (read
 // by the caller, possibly well before).  Nothing may follow it in the caller that
@@ -207,6 +207,7 @@ __device__ void filament_state(const SimDev& d, int64_t f, const double* Xf, Q4 
     }
     const double* sp = d.spar + kSpar * d.fil_susp[f];
     V3 fc = lp - lm + v3(sp[1], sp[2], sp[3]);
+    if (d.fext) fc = fc + ld3(d.fext, S, s0 + n);
     V3 tc = (0.5 * d.dL) * cross(v3(st[n][0], st[n][1], st[n][2]), lp + lm) + (mp - mm);
     if (teth && n == 0) {
         fc = fc + ldx(Xf, 0);

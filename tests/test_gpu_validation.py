@@ -122,3 +122,53 @@ def test_settling_filament_deflection_and_drag():
     # agreement 1.3e-8; the deflection at B = 0.1 changes the drag at O((A/L)^2))
     v_rod = _rigid_rod_speed(oracle, N, synth.DL, synth.A, synth.ETA)
     assert abs(V[0] - v_rod) < 1e-6 * v_rod, (V[0], v_rod)
+
+
+def test_clamped_elastica_second_order_in_space():
+    """Sec. 5.1: the steady shape of a clamped filament under an end load converges at
+    second order in dL to the analytic elastica (F l^2 / K_B = 1.93)."""
+    fil, synth = _fil()
+    import elastica_ref as er
+    theta, _ = er.elastica_theta(1.93)
+    errs = []
+    for N in (11, 21, 41):
+        fo, Y, q, params, fext = er.clamped_filament(N)
+        sim = fil.Sim(fo, Y, q, params, graph=8)
+        sim.set_external_forces(fext)
+        prev = None
+        for s in range(400):  # 20 relaxation times
+            assert sim.step()[0]["converged"]
+            if s == 349:
+                prev = sim.read_state()[0]
+        Yf, qf, _ = sim.read_state()
+        assert np.abs(Yf - prev).max() < 1e-9  # steady
+        errs.append(er.l2_angle_error(qf, params["dL"], 40.0, theta))
+    print("E2 at dL = 4, 2, 1:", errs)
+    # halving dL divides E2 by 4 (observed 4.16, 4.08)
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.6 < e0 / e1 < 4.6, errs
+    assert errs[0] < 2e-3, errs
+
+
+@pytest.mark.parametrize("graph", [0, 4])
+def test_external_forces_trajectory_parity(graph):
+    """A clamped filament under an end load and random per-segment forces: GPU steps
+    against the oracle's (same iteration counts, positions to 1e-8)."""
+    fil, synth = _fil()
+    import elastica_ref as er
+    import oracle
+    fo, Y, q, params, fext = er.clamped_filament(16, steps_per_tau=200, tol=1e-8)
+    fext = fext + np.random.default_rng(41).standard_normal(fext.shape) * 2e-4
+    o = oracle.Sim(fo, Y, q, nthreads=8, fext=fext, **params)
+    g = fil.Sim(fo, Y, q, params, graph=graph)
+    g.set_external_forces(fext)
+    for j in range(8):
+        rc, rep = o.step()
+        assert rc == 0
+        r = g.step()[0]
+        assert r["converged"] and r["iters"] == rep.iters, (j, r["iters"], rep.iters)
+    Yg, qg, _ = g.read_state()
+    assert np.linalg.norm(Yg - o.Y) <= 1e-8 * np.linalg.norm(o.Y)
+    assert np.linalg.norm(qg - o.q) <= 1e-8 * np.linalg.norm(o.q)
+    # the load moved the filament
+    assert np.abs(o.Y - Y).max() > 1e-3
