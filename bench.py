@@ -147,6 +147,37 @@ def learned_gain(log_fn):
     return res
 
 
+def solver_comparison(w, steps=5, warmup=2):
+    """Bad Broyden with the explicit J0 against Jacobian-free Newton-Krylov (J0 left
+    preconditioner, none), at the tolerances of the paper's comparison (Newton/Broyden
+    1e-4, GMRES 1e-4, finite-difference delta 1e-7), on the same suspension and GPU."""
+    import torch
+    import paper_1903_12609_amd as fil
+    out = {}
+    for name in ("ejb_b", "jfnk_j0", "jfnk_none"):
+        sim = fil.Sim(w.fil_off, w.Y, w.q, dict(w.params, tol=1e-4), graph=GRAPH_ITERS)
+        run = (lambda: sim.step()[0]) if name == "ejb_b" else \
+            (lambda: sim.jfnk_step(precond=name[5:], krylov_tol=1e-4, fd_delta=1e-7))
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        applies = krylov = 0
+        for _ in range(steps):
+            r = run()
+            applies += r["applies"]
+            krylov += r.get("krylov", 0)
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_step": (time.perf_counter() - t0) / steps * 1e3, "mobility_applies_per_step": applies / steps}
+        if name != "ejb_b":
+            out[name]["krylov_iters_per_step"] = krylov / steps
+        sim.close()
+        log("solver", name, out[name])
+    out["jfnk_j0_over_ejb_b_time"] = out["jfnk_j0"]["ms_per_step"] / out["ejb_b"]["ms_per_step"]
+    out["workload"] = "sedimenting suspension 100 x 20 (S=2000), dt=T/30, tolerances 1e-4 (paper's comparison)"
+    return out
+
+
 def traffic_per_launch():
     """HBM bytes per launch of the FP64 pair kernel from the committed rocprofv3
     counter summary, or None when the kernel source changed since it was taken."""
@@ -189,6 +220,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-solvers", action="store_true", help="skip the Broyden vs Newton-Krylov comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: runs on several GPUs are not part of this implementation",
@@ -236,6 +268,8 @@ def main():
     if not args.no_sweep:
         res["rpy_apply"] = rpy_sweep()
         res["rpy_apply_batched"] = rpy_batched()
+    if not args.no_solvers:
+        res["solver_comparison"] = solver_comparison(w)
     if not args.no_learned:
         res["learned_warm_start"] = learned_gain(log)
     if not args.no_cpu:

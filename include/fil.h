@@ -172,6 +172,30 @@ int fil_set_external_forces(fil_sim* sim, const double* Fext);
  * FIL_ENONFINITE if a suspension failed; its state is then left at step j. */
 int fil_bdf2_step(fil_sim* sim, fil_step_report* report);
 
+/* One time step solved by Jacobian-free Newton-Krylov instead of bad Broyden (the
+ * comparison method of Sec. 3.1 and 4.1): Newton iterations X <- X + dX until
+ * max|f|/a <= fil_params.tol (at most fil_params.kmax of them), each solving
+ * J(X) dX = -f(X) by restarted GMRES (restart length min(krylov_max, 100)) to a
+ * relative residual krylov_tol (the paper's 1e-4), the products J v taken as
+ * (f(X + fd_delta v) - f(X)) / fd_delta (the paper's delta = 1e-7), one mobility
+ * apply each.  precond: 0 none; 1 right preconditioner P_dt, applied as its inverse
+ * (the multiplier unknowns scaled by 6 pi eta a / dt); 2 left preconditioner J0^{-1}
+ * (the block-diagonal J0 of the step's initial guess; needs the explicit inverse,
+ * fil_params.j0_mode 0 within its size limit, or 2).  One suspension, FP64 mobility.
+ * The step starts from the same warm start as fil_bdf2_step and commits the same way;
+ * on failure the state stays at the previous step (FIL_ENOCONV, FIL_ENONFINITE).
+ * report: HOST, may be NULL.  Synchronises the stream several times per Krylov
+ * iteration (the Arnoldi coefficients go to the host). */
+typedef struct {
+    int32_t newton_iters;       /* Newton updates taken */
+    int32_t krylov_iters;       /* GMRES iterations over all Newton steps */
+    int32_t mobility_applies;   /* residual evaluations (one mobility apply each) */
+    int32_t converged;
+    double resid;               /* final max|f| / a */
+} fil_jfnk_report;
+int fil_jfnk_step(fil_sim* sim, int precond, double krylov_tol, double fd_delta, int krylov_max,
+                  fil_jfnk_report* report);
+
 /* One bad-Broyden update (Alg. 2) on the simulation's current iterate, given
  * the residual f_new = f(X_{k+1}) (device double[6S]):
  *   c_{k+1} = -H_k f_new / |f_new - f_k|,  d_{k+1} = (f_new - f_k) / |f_new - f_k|,

@@ -329,6 +329,19 @@ class Sim:
         rc = lib().or_broyden(C.byref(self.P), C.byref(self.St), _p(X), C.byref(rep))
         return X, rc, rep
 
+    def commit(self, X):
+        """Accept X as the converged unknowns of the step: q^{j+1} = exp(u) . q^j, the
+        robot-arm positions, the history shift and t += dt (as or_bdf2_step does)."""
+        X = _f64(X).copy()
+        Yn, qn = self.reconstruct(X)
+        self.Yprev[:] = self.Y
+        self.Y[:] = Yn
+        self.q[:] = qn
+        self.Xprev[:] = self.X
+        self.X[:] = X
+        self.St.t += self.P.dt
+        self.St.step += 1
+
     def step(self):
         rep = Report()
         rc = lib().or_bdf2_step(C.byref(self.P), C.byref(self.St), C.byref(rep))

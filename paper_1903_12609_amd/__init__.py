@@ -219,6 +219,20 @@ class Sim:
             check(rc)
         return out if rc == 0 else (rc, out)
 
+    def jfnk_step(self, precond="j0", krylov_tol=1e-4, fd_delta=1e-7, krylov_max=1000, raise_on_fail=True):
+        """One step by Jacobian-free Newton-Krylov (precond: "none", "pdt" or "j0");
+        returns a dict of Newton and GMRES iterations and mobility applies."""
+        import ctypes
+        from ._native import JfnkReport
+        rep = JfnkReport()
+        rc = lib().fil_jfnk_step(self._h, {"none": 0, "pdt": 1, "j0": 2}[precond], float(krylov_tol),
+                                 float(fd_delta), int(krylov_max), ctypes.byref(rep))
+        out = dict(newton=rep.newton_iters, krylov=rep.krylov_iters, applies=rep.mobility_applies,
+                   converged=bool(rep.converged), resid=rep.resid)
+        if rc != 0 and raise_on_fail:
+            check(rc)
+        return out if rc == 0 else (rc, out)
+
     def read_state(self):
         """(Y [S,3], q [S,4], X^j [6S]) as numpy arrays (synchronising)."""
         import ctypes

@@ -41,6 +41,11 @@ class StepReport(C.Structure):
                 ("applies_f64", C.c_int32), ("resid", _d), ("used_learned", C.c_int32), ("pad", C.c_int32)]
 
 
+class JfnkReport(C.Structure):
+    _fields_ = [("newton_iters", C.c_int32), ("krylov_iters", C.c_int32), ("mobility_applies", C.c_int32),
+                ("converged", C.c_int32), ("resid", _d)]
+
+
 def _declare(L):
     L.fil_last_error.restype = C.c_char_p
     L.fil_rpy_workspace_bytes.argtypes = [_i64, _i]
@@ -70,6 +75,7 @@ def _declare(L):
         L.fil_set_stream.argtypes = [_vp, _vp]
         L.fil_set_suspension_params.argtypes = [_vp, _vp, _vp, _vp]
         L.fil_set_external_forces.argtypes = [_vp, _vp]
+        L.fil_jfnk_step.argtypes = [_vp, C.c_int, _d, _d, C.c_int, _vp]
         L.fil_set_graph.argtypes = [_vp, _i]
         L.fil_sim_features.argtypes = [_vp, _vp]
         L.fil_sim_step_target.argtypes = [_vp, _vp]

@@ -63,6 +63,13 @@ struct fil_sim {
     int pred_iters = 0;   // iterations the last device-driven solve took (0: none yet)
     hipStream_t cap_st = nullptr;  // private stream the blocks are captured on (launches go to st)
     double* fext_d = nullptr;      // [3][S] external forces per segment (null until set)
+    // Newton-Krylov workspace (allocated on first use): Krylov basis [(m+1)][6S], residuals
+    // at the Newton point and a perturbed point, work vectors, P^{-1} diagonal, dot partials
+    int kry_m = 0;
+    double *kry_V = nullptr, *kry_f0 = nullptr, *kry_fp = nullptr, *kry_Xp = nullptr, *kry_w = nullptr,
+           *kry_u = nullptr, *kry_x = nullptr, *kry_pinv = nullptr, *kry_partial = nullptr, *kry_dots_d = nullptr,
+           *kry_coef_d = nullptr;
+    double *kry_dots_h = nullptr, *kry_coef_h = nullptr;
     std::map<std::array<int, 5>, GraphEntry> graphs;
     SuspLog* log_d = nullptr;  // device log of the current solve [nsusp]
     SuspLog* log_h = nullptr;  // staging of the host's counts when the device takes over a solve
@@ -1096,6 +1103,264 @@ int fil_restore(fil_sim* s, const char* path) {
     s->t = t;
     s->step = hdr[3];
     s->pred_iters = 0;
+    return FIL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- Newton-Krylov step
+// One implicit step solved by Jacobian-free Newton-Krylov (Sec. 3.1): Newton iterations
+// X <- X + dX with J(X) dX = -f(X) solved by restarted GMRES, each product J v taken as
+// (f(X + delta v) - f(X)) / delta (one mobility apply).  Preconditioning (Sec. 4.1):
+// none; right, with P_dt^{-1} (multiplier rows scaled by 6 pi eta a / dt, the inverse of
+// the Delta t / (6 pi eta a) factor their Jacobian columns carry); or left, with the
+// block-diagonal J0^{-1} of the step's initial guess.
+namespace {
+
+struct KryOpts {
+    int precond;  // 0 none, 1 right P_dt, 2 left J0
+    double rtol, delta;
+    int kmax;     // Krylov iterations per Newton step at most
+};
+
+int kry_ensure(fil_sim* s, int m) {
+    if (s->kry_V && s->kry_m >= m) return FIL_OK;
+    FIL_CHECK_ARG(!s->kry_V, "fil_jfnk_step: the Krylov workspace was sized by an earlier call with a smaller limit");
+    const size_t n6 = 6 * (size_t)s->S;
+    TRY(dalloc(s, &s->kry_V, (size_t)(m + 1) * n6));
+    TRY(dalloc(s, &s->kry_f0, n6));
+    TRY(dalloc(s, &s->kry_fp, n6));
+    TRY(dalloc(s, &s->kry_Xp, n6));
+    TRY(dalloc(s, &s->kry_w, n6));
+    TRY(dalloc(s, &s->kry_u, n6));
+    TRY(dalloc(s, &s->kry_x, n6));
+    TRY(dalloc(s, &s->kry_pinv, n6));
+    TRY(dalloc(s, &s->kry_partial, multi_dot_partial_count((int64_t)n6, m + 1)));
+    TRY(dalloc(s, &s->kry_dots_d, (size_t)m + 2));
+    TRY(dalloc(s, &s->kry_coef_d, (size_t)m + 2));
+    TRY(halloc(s, &s->kry_dots_h, (size_t)m + 2));
+    TRY(halloc(s, &s->kry_coef_h, (size_t)m + 2));
+    s->kry_m = m;
+    return FIL_OK;
+}
+
+// out[0..k) = V_j . w on the host
+int kry_dots(fil_sim* s, const double* V, int k, const double* w, double* out) {
+    const int64_t n6 = 6 * s->S;
+    TRY(multi_dot_launch(n6, V, n6, k, w, s->kry_partial, s->kry_dots_d, s->st));
+    FIL_HIP_TRY(hipMemcpyAsync(s->kry_dots_h, s->kry_dots_d, k * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    FIL_HIP_TRY(hipStreamSynchronize(s->st));
+    for (int j = 0; j < k; j++) out[j] = s->kry_dots_h[j];
+    return FIL_OK;
+}
+
+// w += sign sum_j c[j] V_j with the coefficients uploaded from the host
+int kry_axpy(fil_sim* s, const double* V, int k, const double* c, double sign, double* w) {
+    const int64_t n6 = 6 * s->S;
+    for (int j = 0; j < k; j++) s->kry_coef_h[j] = c[j];
+    FIL_HIP_TRY(hipMemcpyAsync(s->kry_coef_d, s->kry_coef_h, k * sizeof(double), hipMemcpyHostToDevice, s->st));
+    TRY(multi_axpy_launch(n6, k, V, n6, s->kry_coef_d, sign, w, s->st));
+    // the pinned coefficients may be overwritten only after the copy has run
+    FIL_HIP_TRY(hipStreamSynchronize(s->st));
+    return FIL_OK;
+}
+
+// w = A v: the preconditioned Jacobian at s->X (f(X) in kry_f0) applied to v
+int kry_apply(fil_sim* s, const KryOpts& o, const double* v, double* w, int& applies) {
+    const int64_t n6 = 6 * s->S;
+    const double* u = v;
+    if (o.precond == 1) {
+        TRY(mul_launch(n6, s->kry_pinv, v, s->kry_u, s->st));
+        u = s->kry_u;
+    }
+    TRY(axpby_launch(n6, 1.0, s->X, o.delta, u, s->kry_Xp, s->st));
+    TRY(eval_residual(s, s->kry_Xp, s->kry_fp, nullptr, nullptr, true, -1));
+    applies++;
+    if (o.precond == 2) {
+        TRY(axpby_launch(n6, 1.0 / o.delta, s->kry_fp, -1.0 / o.delta, s->kry_f0, s->kry_u, s->st));
+        TRY(j0_apply_launch(s->d, s->AinvT, s->kry_u, w, s->st));
+    } else {
+        TRY(axpby_launch(n6, 1.0 / o.delta, s->kry_fp, -1.0 / o.delta, s->kry_f0, w, s->st));
+    }
+    return FIL_OK;
+}
+
+// restarted GMRES for A x = b, b = -f(X) (left J0: -J0^{-1} f(X)), x0 = 0, stopping when
+// the residual norm is at most rtol ||b||; the Newton step dX = x (right: P^{-1} x) is
+// left in kry_x.  Gram-Schmidt runs twice per Arnoldi step (classical, for the device).
+int kry_gmres(fil_sim* s, const KryOpts& o, int& kiters, int& applies) {
+    const int64_t n6 = 6 * s->S;
+    const int m = s->kry_m;
+    double* V = s->kry_V;
+    double* b = s->kry_w;  // b first, then the Arnoldi vectors' images
+    FIL_HIP_TRY(hipMemsetAsync(s->kry_x, 0, n6 * sizeof(double), s->st));
+    if (o.precond == 2) {
+        TRY(j0_apply_launch(s->d, s->AinvT, s->kry_f0, s->kry_u, s->st));
+        TRY(axpby_launch(n6, -1.0, s->kry_u, 0.0, nullptr, V, s->st));
+    } else {
+        TRY(axpby_launch(n6, -1.0, s->kry_f0, 0.0, nullptr, V, s->st));
+    }
+    double nb = 0.0;
+    TRY(kry_dots(s, V, 1, V, &nb));
+    nb = std::sqrt(nb);
+    if (!(nb > 0.0)) return std::isfinite(nb) ? FIL_OK : FIL_ENONFINITE;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 2), h2(m + 2);
+    bool first = true;
+    while (true) {
+        double beta;
+        if (first) {
+            beta = nb;  // V_0 holds b
+        } else {
+            // r = b - A x, b rebuilt in V_0
+            TRY(kry_apply(s, o, s->kry_x, b, applies));
+            if (o.precond == 2) {
+                TRY(j0_apply_launch(s->d, s->AinvT, s->kry_f0, s->kry_u, s->st));
+                TRY(axpby_launch(n6, -1.0, s->kry_u, -1.0, b, V, s->st));
+            } else {
+                TRY(axpby_launch(n6, -1.0, s->kry_f0, -1.0, b, V, s->st));
+            }
+            TRY(kry_dots(s, V, 1, V, &beta));
+            beta = std::sqrt(beta);
+        }
+        first = false;
+        if (!std::isfinite(beta)) return FIL_ENONFINITE;
+        if (beta <= o.rtol * nb) return FIL_OK;
+        TRY(axpby_launch(n6, 1.0 / beta, V, 0.0, nullptr, V, s->st));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        bool done = false;
+        for (; k < m && kiters < o.kmax; k++) {
+            double* vk1 = V + (int64_t)(k + 1) * n6;
+            TRY(kry_apply(s, o, V + (int64_t)k * n6, vk1, applies));
+            kiters++;
+            // twice classical Gram-Schmidt against V_0 .. V_k
+            TRY(kry_dots(s, V, k + 1, vk1, h.data()));
+            TRY(kry_axpy(s, V, k + 1, h.data(), -1.0, vk1));
+            TRY(kry_dots(s, V, k + 1, vk1, h2.data()));
+            TRY(kry_axpy(s, V, k + 1, h2.data(), -1.0, vk1));
+            for (int j = 0; j <= k; j++) h[j] += h2[j];
+            double hn = 0.0;
+            TRY(kry_dots(s, vk1, 1, vk1, &hn));
+            hn = std::sqrt(hn);
+            if (!std::isfinite(hn)) return FIL_ENONFINITE;
+            if (hn > 0.0) TRY(axpby_launch(n6, 1.0 / hn, vk1, 0.0, nullptr, vk1, s->st));
+            // Givens rotations of the Hessenberg column
+            for (int j = 0; j < k; j++) {
+                const double t = cs[j] * h[j] + sn[j] * h[j + 1];
+                h[j + 1] = -sn[j] * h[j] + cs[j] * h[j + 1];
+                h[j] = t;
+            }
+            const double r = std::hypot(h[k], hn);
+            cs[k] = r > 0.0 ? h[k] / r : 1.0;
+            sn[k] = r > 0.0 ? hn / r : 0.0;
+            h[k] = r;
+            for (int j = 0; j <= k; j++) H[(size_t)j * m + k] = h[j];
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            if (std::fabs(g[k + 1]) <= o.rtol * nb || hn == 0.0) {
+                k++;
+                done = true;
+                break;
+            }
+        }
+        // y = H^{-1} g (upper triangular), x += V y
+        for (int i = k - 1; i >= 0; i--) {
+            double t = g[i];
+            for (int j = i + 1; j < k; j++) t -= H[(size_t)i * m + j] * y[j];
+            y[i] = t / H[(size_t)i * m + i];
+        }
+        TRY(kry_axpy(s, V, k, y.data(), 1.0, s->kry_x));
+        if (done || kiters >= o.kmax) break;
+    }
+    if (o.precond == 1) TRY(mul_launch(n6, s->kry_pinv, s->kry_x, s->kry_x, s->st));
+    return FIL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fil_jfnk_step(fil_sim* s, int precond, double krylov_tol, double fd_delta, int krylov_max,
+                  fil_jfnk_report* report) {
+    FIL_CHECK_ARG(s, "fil_jfnk_step: null sim");
+    FIL_CHECK_ARG(s->nsusp == 1, "fil_jfnk_step: one suspension per simulation");
+    FIL_CHECK_ARG(s->p.prec == FIL_PREC_F64, "fil_jfnk_step: FP64 mobility only");
+    FIL_CHECK_ARG(precond >= 0 && precond <= 2, "fil_jfnk_step: precond must be 0 (none), 1 (P_dt) or 2 (J0)");
+    FIL_CHECK_ARG(precond != 2 || s->AinvT, "fil_jfnk_step: the J0 preconditioner needs the explicit inverse (j0_mode 0 or 2)");
+    FIL_CHECK_ARG(krylov_tol > 0.0 && krylov_tol < 1.0 && fd_delta > 0.0 && std::isfinite(fd_delta),
+                  "fil_jfnk_step: krylov_tol in (0, 1), fd_delta > 0");
+    FIL_CHECK_ARG(krylov_max >= 1 && krylov_max <= 100000, "fil_jfnk_step: krylov_max in [1, 100000]");
+    const int64_t n6 = 6 * s->S;
+    TRY(kry_ensure(s, std::min(krylov_max, 100)));
+    const KryOpts o{precond, krylov_tol, fd_delta, krylov_max};
+    s->bc = coefs(s->step);
+    s->cur = 0;
+    s->active_h[0] = 1;
+    TRY(initial_guess_launch(s->d, s->step, s->Yj, s->Yjm1, s->Xj, s->Xjm1, s->X, s->X0p, s->active_d, s->log_d,
+                             s->time_d, s->t + s->p.dt, s->st));
+    if (precond == 1) {
+        // P^{-1}: 1 on Y_1 and u, 6 pi eta a / dt on the multipliers of each filament
+        double dt = 0.0;
+        FIL_HIP_TRY(hipMemcpy(&dt, s->spar, sizeof(double), hipMemcpyDeviceToHost));
+        std::vector<double> pinv(n6, 1.0);
+        const double sc = 6.0 * kPi * s->p.eta * s->p.a / dt;
+        for (int64_t f = 0; f < s->M; f++) {
+            const int64_t s0 = s->fil_seg_off_h[f], N = s->fil_seg_off_h[f + 1] - s0;
+            for (int64_t e = 3 + 3 * N; e < 6 * N; e++) pinv[6 * s0 + e] = sc;
+        }
+        FIL_HIP_TRY(hipMemcpy(s->kry_pinv, pinv.data(), n6 * sizeof(double), hipMemcpyHostToDevice));
+    }
+    int applies = 0, kiters = 0, newton = 0;
+    TRY(state_forces_launch(s->d, s->X, s->qj, s->time_d, s->active_d, s->Yc, s->qc, s->F, s->T, s->box, s->st));
+    if (precond == 2) {
+        TRY(j0_factor_launch(s->d, s->bc, s->X, s->qc, s->T, s->t + s->p.dt, s->active_d, s->AB, s->ipiv, s->rdiag,
+                             s->jflag_d, s->AinvT, s->st));
+        FIL_HIP_TRY(hipMemcpyAsync(s->jflag_h, s->jflag_d, s->M * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+    }
+    TRY(eval_residual(s, s->X, s->kry_f0, nullptr, nullptr, false, -1));
+    applies++;
+    std::vector<double> res;
+    TRY(read_resid(s, res));
+    if (precond == 2)
+        for (int64_t f = 0; f < s->M; f++)
+            if (s->jflag_h[f]) {
+                set_error("fil_jfnk_step: approximate Jacobian block of filament " + std::to_string(f) + " is singular");
+                return FIL_ENONFINITE;
+            }
+    int rc = FIL_OK;
+    while (!(res[0] <= s->p.tol)) {
+        if (!std::isfinite(res[0])) {
+            rc = FIL_ENONFINITE;
+            break;
+        }
+        if (newton >= s->p.kmax) {
+            rc = FIL_ENOCONV;
+            break;
+        }
+        rc = kry_gmres(s, o, kiters, applies);
+        if (rc != FIL_OK) break;
+        TRY(axpby_launch(n6, 1.0, s->X, 1.0, s->kry_x, s->X, s->st));
+        TRY(eval_residual(s, s->X, s->kry_f0, nullptr, nullptr, true, -1));
+        applies++;
+        newton++;
+        TRY(read_resid(s, res));
+    }
+    if (report) {
+        report->newton_iters = newton;
+        report->krylov_iters = kiters;
+        report->mobility_applies = applies;
+        report->converged = rc == FIL_OK ? 1 : 0;
+        report->resid = res.empty() ? 0.0 : res[0];
+    }
+    if (rc != FIL_OK) {
+        set_error(rc == FIL_ENONFINITE ? "fil_jfnk_step: residual became non-finite; state left at the previous step"
+                                       : "fil_jfnk_step: Newton did not reach the tolerance; state left at the previous step");
+        return rc;
+    }
+    TRY(finalize_launch(s->d, nullptr, s->Yc, s->qc, s->X, s->Yj, s->Yjm1, s->qj, s->Xj, s->Xjm1, s->Xjm2, s->st));
+    s->t += s->p.dt;
+    s->step += 1;
     return FIL_OK;
 }
 

@@ -126,4 +126,17 @@ int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const 
 int finalize_launch(const SimDev& d, const int32_t* commit, const double* Yc, const double* qc, const double* X,
                     double* Yj, double* Yjm1, double* qj, double* Xj, double* Xjm1, double* Xjm2, hipStream_t st);
 
+// Vector kernels of the Newton-Krylov solve (krylov.hip).  out[j] = V_j . w for the k
+// rows of V (row stride ldv), through partial[multi_dot_partial_count(n, k)], summed in
+// a fixed order; w += sign sum_j coef[j] V_j; out = a x + b y (y null: a x);
+// out = dvec * x; y = J0^{-1} w with the explicit inverses (dense_off must be set).
+int multi_dot_launch(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* partial, double* out,
+                     hipStream_t st);
+size_t multi_dot_partial_count(int64_t n, int k);
+int multi_axpy_launch(int64_t n, int k, const double* V, int64_t ldv, const double* coef, double sign, double* w,
+                      hipStream_t st);
+int axpby_launch(int64_t n, double a, const double* x, double b, const double* y, double* out, hipStream_t st);
+int mul_launch(int64_t n, const double* dvec, const double* x, double* out, hipStream_t st);
+int j0_apply_launch(const SimDev& d, const double* AinvT, const double* w, double* y, hipStream_t st);
+
 }  // namespace fil

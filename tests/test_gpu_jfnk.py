@@ -1,0 +1,61 @@
+"""GPU Jacobian-free Newton-Krylov steps (Sec. 3.1, 4.1) against the oracle's:
+the same Newton and GMRES iteration counts and the same trajectory for each
+preconditioner, and the same root as the bad-Broyden step."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import jfnk
+from paper_1903_12609_amd import synth
+
+from gpu_util import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precond", ["j0", "pdt", "none"])
+def test_jfnk_steps_match_oracle(precond):
+    import paper_1903_12609_amd as fil
+    print("case jfnk", precond, flush=True)
+    w = synth.sediment_suspension(M=8, N=20, side=60.0, seed=21, dt_over_T=1 / 30)
+    p = dict(w.params, tol=1e-4)
+    o = oracle.Sim(w.fil_off, w.Y, w.q, nthreads=8, **p)
+    g = fil.Sim(w.fil_off, w.Y, w.q, p)
+    for j in range(3):
+        rc, ro = jfnk.jfnk_step(o, precond=precond)
+        assert rc == 0
+        rg = g.jfnk_step(precond=precond)
+        assert rg["converged"] and rg["resid"] <= p["tol"]
+        assert (rg["newton"], rg["krylov"], rg["applies"]) == (ro["newton"], ro["krylov"], ro["applies"]), (j, rg, ro)
+    Y, q, X = g.read_state()
+    # observed 1e-10 (J0) to 1.2e-8 (hundreds of finite-difference products)
+    assert rel_l2(Y, o.Y) <= 1e-7 and rel_l2(q, o.q) <= 1e-7, (rel_l2(Y, o.Y), rel_l2(q, o.q))
+
+
+def test_jfnk_and_broyden_reach_the_same_root():
+    import paper_1903_12609_amd as fil
+    w = synth.sediment_suspension(M=8, N=20, side=60.0, seed=21, dt_over_T=1 / 30)
+    p = dict(w.params, tol=1e-10, kmax=200)
+    a = fil.Sim(w.fil_off, w.Y, w.q, p)
+    b = fil.Sim(w.fil_off, w.Y, w.q, p)
+    for _ in range(2):
+        assert a.step()[0]["converged"]
+        assert b.jfnk_step(precond="j0", krylov_tol=1e-9)["converged"]
+    Xa, Xb = a.read_state()[2], b.read_state()[2]
+    assert np.abs(Xa - Xb).max() <= 1e-8 * np.abs(Xa).max(), np.abs(Xa - Xb).max()
+
+
+def test_jfnk_refusals():
+    import paper_1903_12609_amd as fil
+    from paper_1903_12609_amd._native import FilError
+    w = synth.sediment_suspension(M=4, N=12, side=40.0, seed=22, dt_over_T=1 / 30)
+    banded = fil.Sim(w.fil_off, w.Y, w.q, w.params, j0_mode="banded")
+    with pytest.raises(FilError):
+        banded.jfnk_step(precond="j0")  # the J0 preconditioner needs the explicit inverse
+    assert banded.jfnk_step(precond="none")["converged"]
+    two = fil.Sim(np.concatenate([w.fil_off, w.fil_off[1:] + w.S]), np.concatenate([w.Y, w.Y + 500.0]),
+                  np.concatenate([w.q, w.q]), w.params, susp_fil_off=[0, w.M, 2 * w.M])
+    with pytest.raises(FilError):
+        two.jfnk_step()
+    with pytest.raises(FilError):
+        fil.Sim(w.fil_off, w.Y, w.q, w.params).jfnk_step(krylov_tol=0.0)
