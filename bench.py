@@ -149,15 +149,20 @@ def learned_gain(log_fn):
 
 def solver_comparison(w, steps=5, warmup=2):
     """Bad Broyden with the explicit J0 against Jacobian-free Newton-Krylov (J0 left
-    preconditioner, none), at the tolerances of the paper's comparison (Newton/Broyden
-    1e-4, GMRES 1e-4, finite-difference delta 1e-7), on the same suspension and GPU."""
+    preconditioner, none) and the Jacobian-free good Broyden method (J0 left
+    preconditioner), at the tolerances of the paper's comparisons (Newton/Broyden 1e-4,
+    GMRES 1e-4, finite-difference delta 1e-7), on the same suspension and GPU."""
     import torch
     import paper_1903_12609_amd as fil
     out = {}
-    for name in ("ejb_b", "jfnk_j0", "jfnk_none"):
+    for name in ("ejb_b", "jfnk_j0", "jfnk_none", "jfb_g_j0"):
         sim = fil.Sim(w.fil_off, w.Y, w.q, dict(w.params, tol=1e-4), graph=GRAPH_ITERS)
-        run = (lambda: sim.step()[0]) if name == "ejb_b" else \
-            (lambda: sim.jfnk_step(precond=name[5:], krylov_tol=1e-4, fd_delta=1e-7))
+        if name == "ejb_b":
+            run = lambda: sim.step()[0]
+        elif name.startswith("jfnk"):
+            run = lambda: sim.jfnk_step(precond=name[5:], krylov_tol=1e-4, fd_delta=1e-7)
+        else:
+            run = lambda: sim.jfb_step(precond=name[6:], krylov_tol=1e-4, fd_delta=1e-7)
         for _ in range(warmup):
             run()
         torch.cuda.synchronize()
@@ -174,6 +179,7 @@ def solver_comparison(w, steps=5, warmup=2):
         sim.close()
         log("solver", name, out[name])
     out["jfnk_j0_over_ejb_b_time"] = out["jfnk_j0"]["ms_per_step"] / out["ejb_b"]["ms_per_step"]
+    out["jfb_g_j0_over_ejb_b_time"] = out["jfb_g_j0"]["ms_per_step"] / out["ejb_b"]["ms_per_step"]
     out["workload"] = "sedimenting suspension 100 x 20 (S=2000), dt=T/30, tolerances 1e-4 (paper's comparison)"
     return out
 

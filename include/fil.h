@@ -187,7 +187,7 @@ int fil_bdf2_step(fil_sim* sim, fil_step_report* report);
  * report: HOST, may be NULL.  Synchronises the stream several times per Krylov
  * iteration (the Arnoldi coefficients go to the host). */
 typedef struct {
-    int32_t newton_iters;       /* Newton updates taken */
+    int32_t newton_iters;       /* Newton updates taken (Broyden updates for fil_jfb_step) */
     int32_t krylov_iters;       /* GMRES iterations over all Newton steps */
     int32_t mobility_applies;   /* residual evaluations (one mobility apply each) */
     int32_t converged;
@@ -195,6 +195,19 @@ typedef struct {
 } fil_jfnk_report;
 int fil_jfnk_step(fil_sim* sim, int precond, double krylov_tol, double fd_delta, int krylov_max,
                   fil_jfnk_report* report);
+
+/* One time step solved by the Jacobian-free good Broyden method JFB-g (Sec. 3.2.1,
+ * Alg. 1, compared in Sec. 4.2): Broyden iterations dX = -[J0 + sum_i c_i d_i^T]^{-1}
+ * f(X_k), c = f(X_{k+1}) / |dX|, d = dX / |dX|, until max|f|/a <= fil_params.tol (at
+ * most fil_params.kmax iterations).  J0 = grad f0 at the step's initial guess, with f0
+ * the residual computed with the drag-only mobility diag(M) and without steric or
+ * external forces; its products are taken as (f0(X0 + fd_delta v) - f0(X0)) / fd_delta,
+ * and each system is solved by restarted GMRES to relative residual krylov_tol.  One
+ * mobility apply per Broyden iteration.  precond, the restart, the report (with
+ * newton_iters holding the Broyden iterations), the refusals and the state on failure
+ * as fil_jfnk_step. */
+int fil_jfb_step(fil_sim* sim, int precond, double krylov_tol, double fd_delta, int krylov_max,
+                 fil_jfnk_report* report);
 
 /* One bad-Broyden update (Alg. 2) on the simulation's current iterate, given
  * the residual f_new = f(X_{k+1}) (device double[6S]):

@@ -1,11 +1,13 @@
-"""Test infrastructure (not the product path): a plain Jacobian-free Newton-Krylov step
-(Sec. 3.1) on top of the oracle's residual and J0 blocks, to check the GPU solver
-against.  Newton iterations X <- X + dX with J dX = -f solved by restarted GMRES
-(Arnoldi with modified Gram-Schmidt, Givens rotations), each J v taken by the finite
-difference (f(X + delta v) - f(X)) / delta.  Preconditioners (Sec. 4.1): none; right,
-P_dt applied as its inverse (multiplier unknowns scaled by 6 pi eta a / dt, undoing
-the dt / (6 pi eta a) of their Jacobian columns); left, J0^{-1} with the block-diagonal
-J0 of the initial guess (Sec. 3.2.2).
+"""Test infrastructure (not the product path): plain Jacobian-free Newton-Krylov (Sec. 3.1)
+and Jacobian-free good Broyden (JFB-g, Sec. 3.2.1 with Alg. 1) steps on top of the
+oracle's residual and J0 blocks, to check the GPU solvers against.  Linear systems are
+solved by restarted GMRES (Arnoldi with modified Gram-Schmidt, Givens rotations).  JFNK
+takes each J v by the finite difference (f(X + delta v) - f(X)) / delta; JFB-g takes
+J0 v the same way from f0, the residual with the drag-only mobility and without steric
+or external forces, at the initial guess.  Preconditioners (Sec. 4.1): none; right,
+P_dt applied as its inverse (multiplier unknowns scaled by 6 pi eta a / dt, undoing the
+dt / (6 pi eta a) of their Jacobian columns); left, J0^{-1} with the block-diagonal J0 of
+the initial guess (Sec. 3.2.2).
 """
 import numpy as np
 import scipy.linalg as sla
@@ -107,3 +109,67 @@ def jfnk_step(sim, precond="j0", krylov_tol=1e-4, fd_delta=1e-7, krylov_max=1000
         newton += 1
     sim.commit(X)
     return 0, dict(newton=newton, krylov=kry, applies=applies, resid=r)
+
+
+def jfb_step(sim, precond="j0", krylov_tol=1e-4, fd_delta=1e-7, krylov_max=1000, restart=100):
+    """One step of `sim` by the Jacobian-free good Broyden method JFB-g (Sec. 3.2.1,
+    Alg. 1): dX = -[J0 + sum_i c_i d_i^T]^{-1} f(X_k) by GMRES, J0 v taken by finite
+    differences of f0 (drag-only mobility, no steric or external forces) at the
+    initial guess, then c = f(X_{k+1}) / |dX|, d = dX / |dX|.  Commits when converged.
+    Returns (rc, dict(newton=Broyden iterations, krylov, applies, resid))."""
+    P = sim.P
+    X = sim.initial_guess()
+    X0 = X.copy()
+    f, r = sim.residual(X)
+    applies = 1
+    lu = []
+    if precond == "j0":
+        for fi in range(sim.M):
+            lu.append(sla.lu_factor(sim.j0_filament(fi, X)))
+    pinv = np.ones(6 * sim.S)
+    if precond == "pdt":
+        for fi in range(sim.M):
+            s0, N = int(sim.fil_off[fi]), int(sim.fil_off[fi + 1] - sim.fil_off[fi])
+            pinv[6 * s0 + 3 + 3 * N:6 * (s0 + N)] = 6.0 * np.pi * P.eta * P.a / P.dt
+
+    def j0_solve(v):
+        out = np.empty_like(v)
+        for fi in range(sim.M):
+            a, b = 6 * int(sim.fil_off[fi]), 6 * int(sim.fil_off[fi + 1])
+            out[a:b] = sla.lu_solve(lu[fi], v[a:b])
+        return out
+
+    def f0(Xv):
+        P.drag_only = 1
+        try:
+            return sim.residual(Xv)[0]
+        finally:
+            P.drag_only = 0
+
+    f00 = f0(X0)
+    C, D = [], []
+    it = kry = 0
+    while not r <= P.tol:
+        if not np.isfinite(r) or it >= P.kmax:
+            return (-4 if not np.isfinite(r) else -3), dict(newton=it, krylov=kry, applies=applies, resid=r)
+
+        def apply(v):
+            u = pinv * v if precond == "pdt" else v
+            Jv = (f0(X0 + fd_delta * u) - f00) / fd_delta
+            for c, d in zip(C, D):
+                Jv = Jv + c * np.dot(d, u)
+            return j0_solve(Jv) if precond == "j0" else Jv
+
+        b = -j0_solve(f) if precond == "j0" else -f
+        x, its = gmres(apply, b, krylov_tol, restart, krylov_max)
+        kry += its
+        dX = pinv * x if precond == "pdt" else x
+        X = X + dX
+        f, r = sim.residual(X)
+        applies += 1
+        it += 1
+        nx = np.linalg.norm(dX)
+        C.append(f / nx)
+        D.append(dX / nx)
+    sim.commit(X)
+    return 0, dict(newton=it, krylov=kry, applies=applies, resid=r)

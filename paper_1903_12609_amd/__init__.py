@@ -222,11 +222,19 @@ class Sim:
     def jfnk_step(self, precond="j0", krylov_tol=1e-4, fd_delta=1e-7, krylov_max=1000, raise_on_fail=True):
         """One step by Jacobian-free Newton-Krylov (precond: "none", "pdt" or "j0");
         returns a dict of Newton and GMRES iterations and mobility applies."""
+        return self._krylov_step(lib().fil_jfnk_step, precond, krylov_tol, fd_delta, krylov_max, raise_on_fail)
+
+    def jfb_step(self, precond="j0", krylov_tol=1e-4, fd_delta=1e-7, krylov_max=1000, raise_on_fail=True):
+        """One step by the Jacobian-free good Broyden method JFB-g ("newton" holds the
+        Broyden iterations)."""
+        return self._krylov_step(lib().fil_jfb_step, precond, krylov_tol, fd_delta, krylov_max, raise_on_fail)
+
+    def _krylov_step(self, fn, precond, krylov_tol, fd_delta, krylov_max, raise_on_fail):
         import ctypes
         from ._native import JfnkReport
         rep = JfnkReport()
-        rc = lib().fil_jfnk_step(self._h, {"none": 0, "pdt": 1, "j0": 2}[precond], float(krylov_tol),
-                                 float(fd_delta), int(krylov_max), ctypes.byref(rep))
+        rc = fn(self._h, {"none": 0, "pdt": 1, "j0": 2}[precond], float(krylov_tol), float(fd_delta),
+                int(krylov_max), ctypes.byref(rep))
         out = dict(newton=rep.newton_iters, krylov=rep.krylov_iters, applies=rep.mobility_applies,
                    converged=bool(rep.converged), resid=rep.resid)
         if rc != 0 and raise_on_fail:

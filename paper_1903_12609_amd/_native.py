@@ -76,6 +76,7 @@ def _declare(L):
         L.fil_set_suspension_params.argtypes = [_vp, _vp, _vp, _vp]
         L.fil_set_external_forces.argtypes = [_vp, _vp]
         L.fil_jfnk_step.argtypes = [_vp, C.c_int, _d, _d, C.c_int, _vp]
+        L.fil_jfb_step.argtypes = [_vp, C.c_int, _d, _d, C.c_int, _vp]
         L.fil_set_graph.argtypes = [_vp, _i]
         L.fil_sim_features.argtypes = [_vp, _vp]
         L.fil_sim_step_target.argtypes = [_vp, _vp]

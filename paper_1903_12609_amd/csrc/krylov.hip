@@ -93,6 +93,17 @@ __global__ void __launch_bounds__(kKryBlock) j0_apply_kernel(SimDev d, const dou
     }
 }
 
+// the drag-only mobility of f0 (Sec. 3.2.1): V = F / (6 pi eta a), W = T / (8 pi eta a^3)
+__global__ void __launch_bounds__(kKryBlock) diag_mobility_kernel(int64_t n3, double ct, double cr,
+                                                                  const double* __restrict__ F,
+                                                                  const double* __restrict__ T,
+                                                                  double* __restrict__ V, double* __restrict__ W) {
+    const int64_t i = (int64_t)blockIdx.x * kKryBlock + threadIdx.x;
+    if (i >= n3) return;
+    V[i] = ct * F[i];
+    W[i] = cr * T[i];
+}
+
 static unsigned blocks_for(int64_t n) { return (unsigned)ceil_div(n, (int64_t)kKryBlock); }
 
 int multi_dot_launch(int64_t n, const double* V, int64_t ldv, int k, const double* w, double* partial, double* out,
@@ -125,6 +136,15 @@ int axpby_launch(int64_t n, double a, const double* x, double b, const double* y
 int mul_launch(int64_t n, const double* dvec, const double* x, double* out, hipStream_t st) {
     if (n <= 0) return FIL_OK;
     mul_kernel<<<blocks_for(n), kKryBlock, 0, st>>>(n, dvec, x, out);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+int diag_mobility_launch(const SimDev& d, const double* F, const double* T, double* V, double* W, hipStream_t st) {
+    const int64_t n3 = 3 * d.S;
+    if (n3 <= 0) return FIL_OK;
+    diag_mobility_kernel<<<blocks_for(n3), kKryBlock, 0, st>>>(n3, 1.0 / (6.0 * kPi * d.eta * d.a),
+                                                               1.0 / (8.0 * kPi * d.eta * d.a * d.a * d.a), F, T, V, W);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }

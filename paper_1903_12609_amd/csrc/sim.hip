@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <vector>
 
@@ -70,6 +71,9 @@ struct fil_sim {
            *kry_u = nullptr, *kry_x = nullptr, *kry_pinv = nullptr, *kry_partial = nullptr, *kry_dots_d = nullptr,
            *kry_coef_d = nullptr;
     double *kry_dots_h = nullptr, *kry_coef_h = nullptr;
+    double *kry_f00 = nullptr, *kry_spar0 = nullptr;  // f0 at the initial guess; parameters without external forces
+    unsigned long long* kry_rb = nullptr;              // maxima of f0 evaluations (unused, two alternating pairs)
+    int kry_rbi = 0;
     std::map<std::array<int, 5>, GraphEntry> graphs;
     SuspLog* log_d = nullptr;  // device log of the current solve [nsusp]
     SuspLog* log_h = nullptr;  // staging of the host's counts when the device takes over a solve
@@ -1108,38 +1112,42 @@ int fil_restore(fil_sim* s, const char* path) {
 
 }  // extern "C"
 
-// ---------------------------------------------------------------- Newton-Krylov step
-// One implicit step solved by Jacobian-free Newton-Krylov (Sec. 3.1): Newton iterations
-// X <- X + dX with J(X) dX = -f(X) solved by restarted GMRES, each product J v taken as
-// (f(X + delta v) - f(X)) / delta (one mobility apply).  Preconditioning (Sec. 4.1):
-// none; right, with P_dt^{-1} (multiplier rows scaled by 6 pi eta a / dt, the inverse of
-// the Delta t / (6 pi eta a) factor their Jacobian columns carry); or left, with the
-// block-diagonal J0^{-1} of the step's initial guess.
+// ---------------------------------------------------------------- Newton-Krylov and JFB steps
+// Two steps whose linear systems are solved by restarted GMRES with Jacobian-free
+// products (Sec. 3.1, 3.2.1, 4.1, 4.2):
+//  * Newton-Krylov: X <- X + dX with J(X) dX = -f(X), J v = (f(X + delta v) - f(X)) / delta
+//    (one mobility apply per Krylov iteration);
+//  * JFB-g, good Broyden (Alg. 1) with J0 = grad f0 taken the same way from f0, the
+//    residual with the drag-only mobility and no steric or external forces, at the
+//    step's initial guess: [J0 + sum_i c_i d_i^T] dX = -f(X_k), then c = f(X_{k+1}) /
+//    |dX|, d = dX / |dX| (one mobility apply per Broyden iteration; the Krylov
+//    iterations evaluate f0 only).
+// Preconditioning: none; right, with P_dt^{-1} (multiplier rows scaled by 6 pi eta a /
+// dt, the inverse of the Delta t / (6 pi eta a) factor their Jacobian columns carry);
+// or left, with the block-diagonal explicit J0^{-1} of the initial guess.
 namespace {
 
 struct KryOpts {
     int precond;  // 0 none, 1 right P_dt, 2 left J0
     double rtol, delta;
-    int kmax;     // Krylov iterations per Newton step at most
+    int kmax;     // Krylov iterations per linear solve at most
 };
+using KryOp = std::function<int(const double*, double*)>;
 
 int kry_ensure(fil_sim* s, int m) {
     if (s->kry_V && s->kry_m >= m) return FIL_OK;
-    FIL_CHECK_ARG(!s->kry_V, "fil_jfnk_step: the Krylov workspace was sized by an earlier call with a smaller limit");
+    FIL_CHECK_ARG(!s->kry_V, "Krylov solve: the workspace was sized by an earlier call with a smaller krylov_max");
     const size_t n6 = 6 * (size_t)s->S;
     TRY(dalloc(s, &s->kry_V, (size_t)(m + 1) * n6));
-    TRY(dalloc(s, &s->kry_f0, n6));
-    TRY(dalloc(s, &s->kry_fp, n6));
-    TRY(dalloc(s, &s->kry_Xp, n6));
-    TRY(dalloc(s, &s->kry_w, n6));
-    TRY(dalloc(s, &s->kry_u, n6));
-    TRY(dalloc(s, &s->kry_x, n6));
-    TRY(dalloc(s, &s->kry_pinv, n6));
-    TRY(dalloc(s, &s->kry_partial, multi_dot_partial_count((int64_t)n6, m + 1)));
-    TRY(dalloc(s, &s->kry_dots_d, (size_t)m + 2));
-    TRY(dalloc(s, &s->kry_coef_d, (size_t)m + 2));
-    TRY(halloc(s, &s->kry_dots_h, (size_t)m + 2));
-    TRY(halloc(s, &s->kry_coef_h, (size_t)m + 2));
+    for (double** v : {&s->kry_f0, &s->kry_fp, &s->kry_Xp, &s->kry_w, &s->kry_u, &s->kry_x, &s->kry_pinv, &s->kry_f00})
+        TRY(dalloc(s, v, n6));
+    TRY(dalloc(s, &s->kry_partial, multi_dot_partial_count((int64_t)n6, std::max(m + 1, s->p.kmax + 1))));
+    TRY(dalloc(s, &s->kry_dots_d, (size_t)std::max(m, s->p.kmax) + 2));
+    TRY(dalloc(s, &s->kry_coef_d, (size_t)std::max(m, s->p.kmax) + 2));
+    TRY(halloc(s, &s->kry_dots_h, (size_t)std::max(m, s->p.kmax) + 2));
+    TRY(halloc(s, &s->kry_coef_h, (size_t)std::max(m, s->p.kmax) + 2));
+    TRY(dalloc(s, &s->kry_spar0, (size_t)kSpar * s->nsusp));
+    TRY(dalloc(s, &s->kry_rb, 4 * (size_t)s->nsusp));
     s->kry_m = m;
     return FIL_OK;
 }
@@ -1157,6 +1165,7 @@ int kry_dots(fil_sim* s, const double* V, int k, const double* w, double* out) {
 // w += sign sum_j c[j] V_j with the coefficients uploaded from the host
 int kry_axpy(fil_sim* s, const double* V, int k, const double* c, double sign, double* w) {
     const int64_t n6 = 6 * s->S;
+    if (k <= 0) return FIL_OK;
     for (int j = 0; j < k; j++) s->kry_coef_h[j] = c[j];
     FIL_HIP_TRY(hipMemcpyAsync(s->kry_coef_d, s->kry_coef_h, k * sizeof(double), hipMemcpyHostToDevice, s->st));
     TRY(multi_axpy_launch(n6, k, V, n6, s->kry_coef_d, sign, w, s->st));
@@ -1165,43 +1174,23 @@ int kry_axpy(fil_sim* s, const double* V, int k, const double* c, double sign, d
     return FIL_OK;
 }
 
-// w = A v: the preconditioned Jacobian at s->X (f(X) in kry_f0) applied to v
-int kry_apply(fil_sim* s, const KryOpts& o, const double* v, double* w, int& applies) {
-    const int64_t n6 = 6 * s->S;
-    const double* u = v;
-    if (o.precond == 1) {
-        TRY(mul_launch(n6, s->kry_pinv, v, s->kry_u, s->st));
-        u = s->kry_u;
-    }
-    TRY(axpby_launch(n6, 1.0, s->X, o.delta, u, s->kry_Xp, s->st));
-    TRY(eval_residual(s, s->kry_Xp, s->kry_fp, nullptr, nullptr, true, -1));
-    applies++;
-    if (o.precond == 2) {
-        TRY(axpby_launch(n6, 1.0 / o.delta, s->kry_fp, -1.0 / o.delta, s->kry_f0, s->kry_u, s->st));
-        TRY(j0_apply_launch(s->d, s->AinvT, s->kry_u, w, s->st));
-    } else {
-        TRY(axpby_launch(n6, 1.0 / o.delta, s->kry_fp, -1.0 / o.delta, s->kry_f0, w, s->st));
-    }
-    return FIL_OK;
-}
-
-// restarted GMRES for A x = b, b = -f(X) (left J0: -J0^{-1} f(X)), x0 = 0, stopping when
-// the residual norm is at most rtol ||b||; the Newton step dX = x (right: P^{-1} x) is
-// left in kry_x.  Gram-Schmidt runs twice per Arnoldi step (classical, for the device).
-int kry_gmres(fil_sim* s, const KryOpts& o, int& kiters, int& applies) {
+// restarted GMRES for A x = b (b a device vector, x0 = 0) until the residual norm is at
+// most rtol |b| or o.kmax iterations of this solve; x is left in kry_x and the iterations
+// are added to kiters.  Gram-Schmidt runs twice per Arnoldi step (classical, for the
+// device); the operator may use kry_u, kry_Xp, kry_fp but not V, kry_w, kry_x.
+int kry_gmres(fil_sim* s, const KryOpts& o, const KryOp& A, const double* b, int& kiters_total) {
+    int kiters = 0;
+    struct Add {
+        int& total;
+        const int& n;
+        ~Add() { total += n; }
+    } add{kiters_total, kiters};
     const int64_t n6 = 6 * s->S;
     const int m = s->kry_m;
     double* V = s->kry_V;
-    double* b = s->kry_w;  // b first, then the Arnoldi vectors' images
     FIL_HIP_TRY(hipMemsetAsync(s->kry_x, 0, n6 * sizeof(double), s->st));
-    if (o.precond == 2) {
-        TRY(j0_apply_launch(s->d, s->AinvT, s->kry_f0, s->kry_u, s->st));
-        TRY(axpby_launch(n6, -1.0, s->kry_u, 0.0, nullptr, V, s->st));
-    } else {
-        TRY(axpby_launch(n6, -1.0, s->kry_f0, 0.0, nullptr, V, s->st));
-    }
     double nb = 0.0;
-    TRY(kry_dots(s, V, 1, V, &nb));
+    TRY(kry_dots(s, b, 1, b, &nb));
     nb = std::sqrt(nb);
     if (!(nb > 0.0)) return std::isfinite(nb) ? FIL_OK : FIL_ENONFINITE;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), h(m + 2), h2(m + 2);
@@ -1209,22 +1198,17 @@ int kry_gmres(fil_sim* s, const KryOpts& o, int& kiters, int& applies) {
     while (true) {
         double beta;
         if (first) {
-            beta = nb;  // V_0 holds b
+            TRY(axpby_launch(n6, 1.0, b, 0.0, nullptr, V, s->st));
+            beta = nb;
         } else {
-            // r = b - A x, b rebuilt in V_0
-            TRY(kry_apply(s, o, s->kry_x, b, applies));
-            if (o.precond == 2) {
-                TRY(j0_apply_launch(s->d, s->AinvT, s->kry_f0, s->kry_u, s->st));
-                TRY(axpby_launch(n6, -1.0, s->kry_u, -1.0, b, V, s->st));
-            } else {
-                TRY(axpby_launch(n6, -1.0, s->kry_f0, -1.0, b, V, s->st));
-            }
+            TRY(A(s->kry_x, s->kry_w));  // r = b - A x
+            TRY(axpby_launch(n6, 1.0, b, -1.0, s->kry_w, V, s->st));
             TRY(kry_dots(s, V, 1, V, &beta));
             beta = std::sqrt(beta);
         }
         first = false;
         if (!std::isfinite(beta)) return FIL_ENONFINITE;
-        if (beta <= o.rtol * nb) return FIL_OK;
+        if (beta <= o.rtol * nb || kiters >= o.kmax) return FIL_OK;
         TRY(axpby_launch(n6, 1.0 / beta, V, 0.0, nullptr, V, s->st));
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
@@ -1232,7 +1216,7 @@ int kry_gmres(fil_sim* s, const KryOpts& o, int& kiters, int& applies) {
         bool done = false;
         for (; k < m && kiters < o.kmax; k++) {
             double* vk1 = V + (int64_t)(k + 1) * n6;
-            TRY(kry_apply(s, o, V + (int64_t)k * n6, vk1, applies));
+            TRY(A(V + (int64_t)k * n6, vk1));
             kiters++;
             // twice classical Gram-Schmidt against V_0 .. V_k
             TRY(kry_dots(s, V, k + 1, vk1, h.data()));
@@ -1271,9 +1255,108 @@ int kry_gmres(fil_sim* s, const KryOpts& o, int& kiters, int& applies) {
             y[i] = t / H[(size_t)i * m + i];
         }
         TRY(kry_axpy(s, V, k, y.data(), 1.0, s->kry_x));
-        if (done || kiters >= o.kmax) break;
+        if (done || kiters >= o.kmax) return FIL_OK;
     }
-    if (o.precond == 1) TRY(mul_launch(n6, s->kry_pinv, s->kry_x, s->kry_x, s->st));
+}
+
+// f0(X) (drag-only mobility, no steric or external forces) into fout; overwrites the
+// state buffers and V, W like an evaluation of f
+int eval_f0(fil_sim* s, const double* X, double* fout) {
+    SimDev d0 = s->d;
+    d0.spar = s->kry_spar0;
+    d0.fext = nullptr;
+    TRY(state_forces_launch(d0, X, s->qj, s->time_d, s->active_d, s->Yc, s->qc, s->F, s->T, s->box, s->st));
+    TRY(diag_mobility_launch(d0, s->F, s->T, s->V, s->W, s->st));
+    unsigned long long* rb = s->kry_rb + 2 * s->kry_rbi * s->nsusp;
+    unsigned long long* rbn = s->kry_rb + 2 * (1 - s->kry_rbi) * s->nsusp;
+    s->kry_rbi ^= 1;
+    const DotArgs none{-1, nullptr, nullptr, nullptr};
+    return residual_launch(d0, s->bc, X, s->Xj, s->Yc, s->Yj, s->Yjm1, s->V, s->W, nullptr, 1, s->active_d, fout, rb,
+                           rbn, none, s->st);
+}
+
+// common checks, the warm start, P^{-1} and (left preconditioner) J0 at the initial
+// guess; leaves f(X0) in kry_f0 and max|f|/a in res
+int kry_begin(fil_sim* s, const char* who, int precond, double krylov_tol, double fd_delta, int krylov_max,
+              std::vector<double>& res, int& applies) {
+    FIL_CHECK_ARG(s, std::string(who) + ": null sim");
+    FIL_CHECK_ARG(s->nsusp == 1, std::string(who) + ": one suspension per simulation");
+    FIL_CHECK_ARG(s->p.prec == FIL_PREC_F64, std::string(who) + ": FP64 mobility only");
+    FIL_CHECK_ARG(precond >= 0 && precond <= 2, std::string(who) + ": precond must be 0 (none), 1 (P_dt) or 2 (J0)");
+    FIL_CHECK_ARG(precond != 2 || s->AinvT,
+                  std::string(who) + ": the J0 preconditioner needs the explicit inverse (j0_mode 0 or 2)");
+    FIL_CHECK_ARG(krylov_tol > 0.0 && krylov_tol < 1.0 && fd_delta > 0.0 && std::isfinite(fd_delta),
+                  std::string(who) + ": krylov_tol in (0, 1), fd_delta > 0");
+    FIL_CHECK_ARG(krylov_max >= 1 && krylov_max <= 100000, std::string(who) + ": krylov_max in [1, 100000]");
+    const int64_t n6 = 6 * s->S;
+    TRY(kry_ensure(s, std::min(krylov_max, 100)));
+    s->bc = coefs(s->step);
+    s->cur = 0;
+    s->active_h[0] = 1;
+    TRY(initial_guess_launch(s->d, s->step, s->Yj, s->Yjm1, s->Xj, s->Xjm1, s->X, s->X0p, s->active_d, s->log_d,
+                             s->time_d, s->t + s->p.dt, s->st));
+    std::vector<double> sp(kSpar * s->nsusp);
+    FIL_HIP_TRY(hipMemcpy(sp.data(), s->spar, sp.size() * sizeof(double), hipMemcpyDeviceToHost));
+    if (precond == 1) {
+        // P^{-1}: 1 on Y_1 and u, 6 pi eta a / dt on the multipliers of each filament
+        std::vector<double> pinv(n6, 1.0);
+        const double sc = 6.0 * kPi * s->p.eta * s->p.a / sp[0];
+        for (int64_t f = 0; f < s->M; f++) {
+            const int64_t s0 = s->fil_seg_off_h[f], N = s->fil_seg_off_h[f + 1] - s0;
+            for (int64_t e = 3 + 3 * N; e < 6 * N; e++) pinv[6 * s0 + e] = sc;
+        }
+        FIL_HIP_TRY(hipMemcpy(s->kry_pinv, pinv.data(), n6 * sizeof(double), hipMemcpyHostToDevice));
+    }
+    // the parameters of f0: gravity and steric strength zero, the same time step
+    for (int64_t i = 0; i < s->nsusp; i++)
+        for (int c = 1; c < kSpar; c++) sp[kSpar * i + c] = 0.0;
+    FIL_HIP_TRY(hipMemcpy(s->kry_spar0, sp.data(), sp.size() * sizeof(double), hipMemcpyHostToDevice));
+    TRY(state_forces_launch(s->d, s->X, s->qj, s->time_d, s->active_d, s->Yc, s->qc, s->F, s->T, s->box, s->st));
+    if (precond == 2) {
+        TRY(j0_factor_launch(s->d, s->bc, s->X, s->qc, s->T, s->t + s->p.dt, s->active_d, s->AB, s->ipiv, s->rdiag,
+                             s->jflag_d, s->AinvT, s->st));
+        FIL_HIP_TRY(hipMemcpyAsync(s->jflag_h, s->jflag_d, s->M * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+    }
+    TRY(eval_residual(s, s->X, s->kry_f0, nullptr, nullptr, false, -1));
+    applies++;
+    TRY(read_resid(s, res));
+    if (precond == 2)
+        for (int64_t f = 0; f < s->M; f++)
+            if (s->jflag_h[f]) {
+                set_error(std::string(who) + ": approximate Jacobian block of filament " + std::to_string(f) +
+                          " is singular");
+                return FIL_ENONFINITE;
+            }
+    return FIL_OK;
+}
+
+// b = -f (left: -J0^{-1} f) into out
+int kry_rhs(fil_sim* s, int precond, const double* f, double* out) {
+    const int64_t n6 = 6 * s->S;
+    if (precond == 2) {
+        TRY(j0_apply_launch(s->d, s->AinvT, f, s->kry_u, s->st));
+        return axpby_launch(n6, -1.0, s->kry_u, 0.0, nullptr, out, s->st);
+    }
+    return axpby_launch(n6, -1.0, f, 0.0, nullptr, out, s->st);
+}
+
+int kry_finish(fil_sim* s, const char* who, int rc, int outer, int kiters, int applies, const std::vector<double>& res,
+               fil_jfnk_report* report) {
+    if (report) {
+        report->newton_iters = outer;
+        report->krylov_iters = kiters;
+        report->mobility_applies = applies;
+        report->converged = rc == FIL_OK ? 1 : 0;
+        report->resid = res.empty() ? 0.0 : res[0];
+    }
+    if (rc != FIL_OK) {
+        set_error(std::string(who) + (rc == FIL_ENONFINITE ? ": residual became non-finite; state left at the previous step"
+                                                          : ": did not reach the tolerance; state left at the previous step"));
+        return rc;
+    }
+    TRY(finalize_launch(s->d, nullptr, s->Yc, s->qc, s->X, s->Yj, s->Yjm1, s->qj, s->Xj, s->Xjm1, s->Xjm2, s->st));
+    s->t += s->p.dt;
+    s->step += 1;
     return FIL_OK;
 }
 
@@ -1283,51 +1366,26 @@ extern "C" {
 
 int fil_jfnk_step(fil_sim* s, int precond, double krylov_tol, double fd_delta, int krylov_max,
                   fil_jfnk_report* report) {
-    FIL_CHECK_ARG(s, "fil_jfnk_step: null sim");
-    FIL_CHECK_ARG(s->nsusp == 1, "fil_jfnk_step: one suspension per simulation");
-    FIL_CHECK_ARG(s->p.prec == FIL_PREC_F64, "fil_jfnk_step: FP64 mobility only");
-    FIL_CHECK_ARG(precond >= 0 && precond <= 2, "fil_jfnk_step: precond must be 0 (none), 1 (P_dt) or 2 (J0)");
-    FIL_CHECK_ARG(precond != 2 || s->AinvT, "fil_jfnk_step: the J0 preconditioner needs the explicit inverse (j0_mode 0 or 2)");
-    FIL_CHECK_ARG(krylov_tol > 0.0 && krylov_tol < 1.0 && fd_delta > 0.0 && std::isfinite(fd_delta),
-                  "fil_jfnk_step: krylov_tol in (0, 1), fd_delta > 0");
-    FIL_CHECK_ARG(krylov_max >= 1 && krylov_max <= 100000, "fil_jfnk_step: krylov_max in [1, 100000]");
-    const int64_t n6 = 6 * s->S;
-    TRY(kry_ensure(s, std::min(krylov_max, 100)));
-    const KryOpts o{precond, krylov_tol, fd_delta, krylov_max};
-    s->bc = coefs(s->step);
-    s->cur = 0;
-    s->active_h[0] = 1;
-    TRY(initial_guess_launch(s->d, s->step, s->Yj, s->Yjm1, s->Xj, s->Xjm1, s->X, s->X0p, s->active_d, s->log_d,
-                             s->time_d, s->t + s->p.dt, s->st));
-    if (precond == 1) {
-        // P^{-1}: 1 on Y_1 and u, 6 pi eta a / dt on the multipliers of each filament
-        double dt = 0.0;
-        FIL_HIP_TRY(hipMemcpy(&dt, s->spar, sizeof(double), hipMemcpyDeviceToHost));
-        std::vector<double> pinv(n6, 1.0);
-        const double sc = 6.0 * kPi * s->p.eta * s->p.a / dt;
-        for (int64_t f = 0; f < s->M; f++) {
-            const int64_t s0 = s->fil_seg_off_h[f], N = s->fil_seg_off_h[f + 1] - s0;
-            for (int64_t e = 3 + 3 * N; e < 6 * N; e++) pinv[6 * s0 + e] = sc;
-        }
-        FIL_HIP_TRY(hipMemcpy(s->kry_pinv, pinv.data(), n6 * sizeof(double), hipMemcpyHostToDevice));
-    }
-    int applies = 0, kiters = 0, newton = 0;
-    TRY(state_forces_launch(s->d, s->X, s->qj, s->time_d, s->active_d, s->Yc, s->qc, s->F, s->T, s->box, s->st));
-    if (precond == 2) {
-        TRY(j0_factor_launch(s->d, s->bc, s->X, s->qc, s->T, s->t + s->p.dt, s->active_d, s->AB, s->ipiv, s->rdiag,
-                             s->jflag_d, s->AinvT, s->st));
-        FIL_HIP_TRY(hipMemcpyAsync(s->jflag_h, s->jflag_d, s->M * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
-    }
-    TRY(eval_residual(s, s->X, s->kry_f0, nullptr, nullptr, false, -1));
-    applies++;
     std::vector<double> res;
-    TRY(read_resid(s, res));
-    if (precond == 2)
-        for (int64_t f = 0; f < s->M; f++)
-            if (s->jflag_h[f]) {
-                set_error("fil_jfnk_step: approximate Jacobian block of filament " + std::to_string(f) + " is singular");
-                return FIL_ENONFINITE;
-            }
+    int applies = 0, kiters = 0, newton = 0;
+    TRY(kry_begin(s, "fil_jfnk_step", precond, krylov_tol, fd_delta, krylov_max, res, applies));
+    const int64_t n6 = 6 * s->S;
+    const KryOpts o{precond, krylov_tol, fd_delta, krylov_max};
+    // (J P^{-1}) v, left-multiplied by J0^{-1} when preconditioned so
+    const KryOp A = [&](const double* v, double* w) -> int {
+        const double* u = v;
+        if (precond == 1) {
+            TRY(mul_launch(n6, s->kry_pinv, v, s->kry_u, s->st));
+            u = s->kry_u;
+        }
+        TRY(axpby_launch(n6, 1.0, s->X, o.delta, u, s->kry_Xp, s->st));
+        TRY(eval_residual(s, s->kry_Xp, s->kry_fp, nullptr, nullptr, true, -1));
+        applies++;
+        double* jv = precond == 2 ? s->kry_u : w;
+        TRY(axpby_launch(n6, 1.0 / o.delta, s->kry_fp, -1.0 / o.delta, s->kry_f0, jv, s->st));
+        if (precond == 2) TRY(j0_apply_launch(s->d, s->AinvT, s->kry_u, w, s->st));
+        return FIL_OK;
+    };
     int rc = FIL_OK;
     while (!(res[0] <= s->p.tol)) {
         if (!std::isfinite(res[0])) {
@@ -1338,30 +1396,81 @@ int fil_jfnk_step(fil_sim* s, int precond, double krylov_tol, double fd_delta, i
             rc = FIL_ENOCONV;
             break;
         }
-        rc = kry_gmres(s, o, kiters, applies);
+        TRY(kry_rhs(s, precond, s->kry_f0, s->kry_f00));  // b, apart from the operator's buffers
+        rc = kry_gmres(s, o, A, s->kry_f00, kiters);
         if (rc != FIL_OK) break;
+        if (precond == 1) TRY(mul_launch(n6, s->kry_pinv, s->kry_x, s->kry_x, s->st));
         TRY(axpby_launch(n6, 1.0, s->X, 1.0, s->kry_x, s->X, s->st));
         TRY(eval_residual(s, s->X, s->kry_f0, nullptr, nullptr, true, -1));
         applies++;
         newton++;
         TRY(read_resid(s, res));
     }
-    if (report) {
-        report->newton_iters = newton;
-        report->krylov_iters = kiters;
-        report->mobility_applies = applies;
-        report->converged = rc == FIL_OK ? 1 : 0;
-        report->resid = res.empty() ? 0.0 : res[0];
+    return kry_finish(s, "fil_jfnk_step", rc, newton, kiters, applies, res, report);
+}
+
+int fil_jfb_step(fil_sim* s, int precond, double krylov_tol, double fd_delta, int krylov_max,
+                 fil_jfnk_report* report) {
+    std::vector<double> res;
+    int applies = 0, kiters = 0, iters = 0;
+    TRY(kry_begin(s, "fil_jfb_step", precond, krylov_tol, fd_delta, krylov_max, res, applies));
+    const int64_t n6 = 6 * s->S;
+    const KryOpts o{precond, krylov_tol, fd_delta, krylov_max};
+    double* C = s->Chist;
+    double* D = s->Dhist;
+    int k = 0;
+    std::vector<double> dd(std::max(1, s->p.kmax));
+    // f0 at the initial guess, the base point of J0 = grad f0
+    TRY(eval_f0(s, s->X0p, s->kry_f00));
+    // ([J0 + C D^T] P^{-1}) v, left-multiplied by J0^{-1} when preconditioned so
+    const KryOp A = [&](const double* v, double* w) -> int {
+        const double* u = v;
+        if (precond == 1) {
+            TRY(mul_launch(n6, s->kry_pinv, v, s->kry_u, s->st));
+            u = s->kry_u;
+        }
+        TRY(axpby_launch(n6, 1.0, s->X0p, o.delta, u, s->kry_Xp, s->st));
+        TRY(eval_f0(s, s->kry_Xp, s->kry_fp));
+        double* jv = precond == 2 ? s->kry_Xp : w;  // kry_Xp is free once f0 has been evaluated
+        TRY(axpby_launch(n6, 1.0 / o.delta, s->kry_fp, -1.0 / o.delta, s->kry_f00, jv, s->st));
+        if (k > 0) {
+            TRY(kry_dots(s, D, k, u, dd.data()));
+            TRY(kry_axpy(s, C, k, dd.data(), 1.0, jv));
+        }
+        if (precond == 2) TRY(j0_apply_launch(s->d, s->AinvT, s->kry_Xp, w, s->st));
+        return FIL_OK;
+    };
+    int rc = FIL_OK;
+    while (!(res[0] <= s->p.tol)) {
+        if (!std::isfinite(res[0])) {
+            rc = FIL_ENONFINITE;
+            break;
+        }
+        if (iters >= s->p.kmax) {
+            rc = FIL_ENOCONV;
+            break;
+        }
+        // the right-hand side -f (left: -J0^{-1} f) in the slot of the next d
+        double* rhs = D + (int64_t)k * n6;
+        TRY(kry_rhs(s, precond, s->kry_f0, rhs));
+        rc = kry_gmres(s, o, A, rhs, kiters);
+        if (rc != FIL_OK) break;
+        if (precond == 1) TRY(mul_launch(n6, s->kry_pinv, s->kry_x, s->kry_x, s->st));
+        TRY(axpby_launch(n6, 1.0, s->X, 1.0, s->kry_x, s->X, s->st));
+        TRY(eval_residual(s, s->X, s->kry_f0, nullptr, nullptr, true, -1));
+        applies++;
+        iters++;
+        TRY(read_resid(s, res));
+        // good-Broyden rank-one term: c = f(X_{k+1}) / |dX|, d = dX / |dX|
+        double nx = 0.0;
+        TRY(kry_dots(s, s->kry_x, 1, s->kry_x, &nx));
+        nx = std::sqrt(nx);
+        if (!(nx > 0.0)) continue;
+        TRY(axpby_launch(n6, 1.0 / nx, s->kry_f0, 0.0, nullptr, C + (int64_t)k * n6, s->st));
+        TRY(axpby_launch(n6, 1.0 / nx, s->kry_x, 0.0, nullptr, D + (int64_t)k * n6, s->st));
+        k++;
     }
-    if (rc != FIL_OK) {
-        set_error(rc == FIL_ENONFINITE ? "fil_jfnk_step: residual became non-finite; state left at the previous step"
-                                       : "fil_jfnk_step: Newton did not reach the tolerance; state left at the previous step");
-        return rc;
-    }
-    TRY(finalize_launch(s->d, nullptr, s->Yc, s->qc, s->X, s->Yj, s->Yjm1, s->qj, s->Xj, s->Xjm1, s->Xjm2, s->st));
-    s->t += s->p.dt;
-    s->step += 1;
-    return FIL_OK;
+    return kry_finish(s, "fil_jfb_step", rc, iters, kiters, applies, res, report);
 }
 
 }  // extern "C"

@@ -138,5 +138,7 @@ int multi_axpy_launch(int64_t n, int k, const double* V, int64_t ldv, const doub
 int axpby_launch(int64_t n, double a, const double* x, double b, const double* y, double* out, hipStream_t st);
 int mul_launch(int64_t n, const double* dvec, const double* x, double* out, hipStream_t st);
 int j0_apply_launch(const SimDev& d, const double* AinvT, const double* w, double* y, hipStream_t st);
+// V = F / (6 pi eta a), W = T / (8 pi eta a^3) on [3][S] (the mobility of f0)
+int diag_mobility_launch(const SimDev& d, const double* F, const double* T, double* V, double* W, hipStream_t st);
 
 }  // namespace fil

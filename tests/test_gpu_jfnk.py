@@ -1,6 +1,6 @@
-"""GPU Jacobian-free Newton-Krylov steps (Sec. 3.1, 4.1) against the oracle's:
-the same Newton and GMRES iteration counts and the same trajectory for each
-preconditioner, and the same root as the bad-Broyden step."""
+"""GPU Jacobian-free Newton-Krylov (Sec. 3.1, 4.1) and JFB-g (Sec. 3.2.1, 4.2) steps
+against the oracle's: the same outer and GMRES iteration counts and the same trajectory
+for each preconditioner, and the same root as the bad-Broyden step."""
 import numpy as np
 import pytest
 
@@ -59,3 +59,39 @@ def test_jfnk_refusals():
         two.jfnk_step()
     with pytest.raises(FilError):
         fil.Sim(w.fil_off, w.Y, w.q, w.params).jfnk_step(krylov_tol=0.0)
+
+
+@pytest.mark.parametrize("precond", ["j0", "none"])
+def test_jfb_steps_match_oracle(precond):
+    import paper_1903_12609_amd as fil
+    print("case jfb", precond, flush=True)
+    w = synth.sediment_suspension(M=8, N=20, side=60.0, seed=21, dt_over_T=1 / 30)
+    p = dict(w.params, tol=1e-4)
+    o = oracle.Sim(w.fil_off, w.Y, w.q, nthreads=8, **p)
+    g = fil.Sim(w.fil_off, w.Y, w.q, p)
+    for j in range(3):
+        rc, ro = jfnk.jfb_step(o, precond=precond)
+        assert rc == 0
+        rg = g.jfb_step(precond=precond)
+        assert rg["converged"] and rg["resid"] <= p["tol"]
+        assert rg["newton"] == ro["newton"] and rg["applies"] == ro["applies"], (j, rg, ro)
+        # with J0 the GMRES counts agree exactly; unpreconditioned, a solve takes ~1000
+        # restarted iterations on an ill-conditioned system and the count depends on
+        # rounding (classical Gram-Schmidt twice here, modified in the oracle): observed
+        # within 1.8%, while the Broyden iterations and the roots agree
+        assert abs(rg["krylov"] - ro["krylov"]) <= (0 if precond == "j0" else 0.05 * ro["krylov"]), (j, rg, ro)
+    Y, q, X = g.read_state()
+    assert rel_l2(Y, o.Y) <= 1e-7 and rel_l2(q, o.q) <= 1e-7, (rel_l2(Y, o.Y), rel_l2(q, o.q))
+
+
+def test_jfb_and_broyden_reach_the_same_root():
+    import paper_1903_12609_amd as fil
+    w = synth.sediment_suspension(M=8, N=20, side=60.0, seed=21, dt_over_T=1 / 30)
+    p = dict(w.params, tol=1e-10, kmax=200)
+    a = fil.Sim(w.fil_off, w.Y, w.q, p)
+    b = fil.Sim(w.fil_off, w.Y, w.q, p)
+    for _ in range(2):
+        assert a.step()[0]["converged"]
+        assert b.jfb_step(precond="j0", krylov_tol=1e-9)["converged"]
+    Xa, Xb = a.read_state()[2], b.read_state()[2]
+    assert np.abs(Xa - Xb).max() <= 1e-8 * np.abs(Xa).max(), np.abs(Xa - Xb).max()

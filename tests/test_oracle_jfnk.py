@@ -32,3 +32,17 @@ def test_newton_krylov_root_equals_broyden_root():
         rc, r = jfnk.jfnk_step(b, precond=pc, krylov_tol=1e-10)
         assert rc == 0 and r["resid"] <= 1e-11
         assert np.abs(b.X - X_b).max() <= 1e-9 * max(1.0, np.abs(X_b).max()), (pc, np.abs(b.X - X_b).max())
+
+
+def test_jfb_root_equals_broyden_root():
+    """JFB-g (good Broyden with J0 = grad f0 by finite differences) reaches the root of
+    the oracle's bad Broyden."""
+    w = synth.single_filament(N=15)
+    p = dict(w.params, tol=1e-11, kmax=200)
+    a = oracle.Sim(w.fil_off, w.Y, w.q, **p)
+    X_b, rc, rep = a.broyden(a.initial_guess())
+    assert rc == 0
+    b = oracle.Sim(w.fil_off, w.Y, w.q, **p)
+    rc, r = jfnk.jfb_step(b, precond="j0", krylov_tol=1e-10)
+    assert rc == 0 and r["resid"] <= 1e-11
+    assert np.abs(b.X - X_b).max() <= 1e-9 * max(1.0, np.abs(X_b).max())
