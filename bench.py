@@ -184,6 +184,35 @@ def solver_comparison(w, steps=5, warmup=2):
     return out
 
 
+def fcm_apply_bench(reps=5):
+    """Force-coupling-method applies on the paper's FCM grid (1024 x 1024 x 64 points over
+    141 dL x 141 dL x 8.8 dL, a monolayer of M filaments of N = 15 segments): M = 1024
+    (S = 15360 segments at random positions in the box), Gaussians truncated at 4 and 7.5
+    widths."""
+    import numpy as np
+    import torch
+    import paper_1903_12609_amd as fil
+    dL = 2.2
+    box = (141 * dL, 141 * dL, 8.8 * dL)
+    grid = (1024, 1024, 64)
+    S = 1024 * 15
+    rng = np.random.default_rng(13)
+    Y = torch.from_numpy(np.ascontiguousarray((rng.uniform(0, 1, (S, 3)) * np.array(box)).T)).cuda()
+    F = torch.from_numpy(np.ascontiguousarray(rng.standard_normal((3, S)))).cuda()
+    T = torch.from_numpy(np.ascontiguousarray(rng.standard_normal((3, S)))).cuda()
+    out = []
+    for cut in (4.0, 7.5):
+        m = fil.FCM(box, grid, a=1.0, eta=1.0, cut=cut)
+        V, W = m.apply(Y, F, T)
+        ms = _time_applies(lambda: m.apply(Y, F, T, V, W), reps) * 1e3
+        npts = grid[0] * grid[1] * grid[2]
+        out.append(dict(grid=list(grid), box=list(box), segments=S, cut_widths=cut, ms=ms,
+                        grid_points_per_s=npts / (ms * 1e-3), segments_per_s=S / (ms * 1e-3)))
+        log("fcm apply", out[-1])
+        m.close()
+    return out
+
+
 def traffic_per_launch():
     """HBM bytes per launch of the FP64 pair kernel from the committed rocprofv3
     counter summary, or None when the kernel source changed since it was taken."""
@@ -274,6 +303,8 @@ def main():
     if not args.no_sweep:
         res["rpy_apply"] = rpy_sweep()
         res["rpy_apply_batched"] = rpy_batched()
+    if not args.no_sweep:
+        res["fcm_apply"] = fcm_apply_bench()
     if not args.no_solvers:
         res["solver_comparison"] = solver_comparison(w)
     if not args.no_learned:

@@ -70,6 +70,28 @@ int64_t fil_rpy_workspace_bytes(int64_t S, int prec);
 int fil_rpy_mobility_apply(int64_t S, const double* Y, const double* F, const double* T, double a, double eta,
                            int prec, double* V, double* Omega, void* work, int64_t work_bytes, void* stream);
 
+/* Force-coupling-method mobility (Sec. 2.7.2) in a periodic box: the forces and
+ * torques enter the Stokes equations as Gaussian monopoles F_m Delta_m and rotlets
+ * -1/2 T_m x grad Theta_m (widths sigma_D = a / sqrt(pi), sigma_T = a / (6 sqrt(pi))^(1/3),
+ * truncated at distance cut * sigma), the equations are solved spectrally on a regular
+ * grid, and V_n, Omega_n are the Gaussian-weighted averages of the velocity and half the
+ * vorticity (trapezoidal rule).  The zero mode and the Nyquist planes of even axes are
+ * dropped.  The mean force is not balanced: the result is the periodic mobility.
+ *   box   HOST double[3]: box lengths (positions are wrapped into [0, L))
+ *   grid  HOST int32[3]: grid points per axis (4 .. 4096); the support 2 ceil(cut sigma_D
+ *         / h) + 1 must fit in the grid and in 65 points
+ *   cut   truncation radius in Gaussian widths, in [2, 12] (7.5: tails below 1e-12)
+ * fil_fcm_create allocates the grids and the FFT plans (FIL_ENOMEM, FIL_EHIP on failure);
+ * fil_fcm_apply then allocates nothing: S segments, Y, F, T device double[3][S], outputs
+ * V, Omega device double[3][S] (not aliasing the inputs), asynchronous on stream.  Two
+ * applies in flight must not share a handle.  Spreading adds with atomics, so results
+ * may differ between runs in the last bits. */
+typedef struct fil_fcm fil_fcm;
+int fil_fcm_create(const double* box, const int32_t* grid, double a, double eta, double cut, fil_fcm** out);
+int fil_fcm_apply(fil_fcm* fcm, int64_t S, const double* Y, const double* F, const double* T, double* V,
+                  double* Omega, void* stream);
+void fil_fcm_destroy(fil_fcm* fcm);
+
 /* Batched form: nsusp independent suspensions in one launch; suspension i owns
  * segments susp_off[i] .. susp_off[i+1]-1 and interacts only with itself.
  * susp_off is a HOST int64[nsusp+1] (non-decreasing, susp_off[0] = 0);

@@ -98,6 +98,41 @@ class _DevView:
                                          "version": 2, "strides": None}
 
 
+class FCM:
+    """Force-coupling-method mobility in a periodic box (Sec. 2.7.2): box lengths [3],
+    grid points [3], radius a, viscosity eta, Gaussian truncation in widths."""
+
+    def __init__(self, box, grid, a=1.0, eta=1.0, cut=7.5):
+        import ctypes
+        import numpy as np
+        b = np.ascontiguousarray(np.broadcast_to(np.asarray(box, dtype=np.float64), (3,)))
+        g = np.ascontiguousarray(np.broadcast_to(np.asarray(grid, dtype=np.int32), (3,)))
+        h = ctypes.c_void_p()
+        check(lib().fil_fcm_create(b.ctypes.data_as(ctypes.c_void_p), g.ctypes.data_as(ctypes.c_void_p), float(a),
+                                   float(eta), float(cut), ctypes.byref(h)))
+        self._h = h
+
+    def apply(self, Y, F, T, V=None, Omega=None):
+        """(V, Omega) for device float64 tensors Y, F, T of shape [3, S]."""
+        import torch
+        S = Y.shape[1]
+        V = torch.empty_like(Y) if V is None else V
+        Omega = torch.empty_like(Y) if Omega is None else Omega
+        check(lib().fil_fcm_apply(self._h, S, _ptr(Y), _ptr(F), _ptr(T), _ptr(V), _ptr(Omega), _stream()))
+        return V, Omega
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fil_fcm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Sim:
     """A simulation of one or more independent suspensions on the GPU.
 

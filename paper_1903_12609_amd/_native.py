@@ -75,6 +75,10 @@ def _declare(L):
         L.fil_set_stream.argtypes = [_vp, _vp]
         L.fil_set_suspension_params.argtypes = [_vp, _vp, _vp, _vp]
         L.fil_set_external_forces.argtypes = [_vp, _vp]
+        L.fil_fcm_create.argtypes = [_vp, _vp, _d, _d, _d, _vp]
+        L.fil_fcm_apply.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.fil_fcm_destroy.argtypes = [_vp]
+        L.fil_fcm_destroy.restype = None
         L.fil_jfnk_step.argtypes = [_vp, C.c_int, _d, _d, C.c_int, _vp]
         L.fil_jfb_step.argtypes = [_vp, C.c_int, _d, _d, C.c_int, _vp]
         L.fil_set_graph.argtypes = [_vp, _i]

@@ -16,6 +16,7 @@ FLAGS = [
     # packed FP32 VALU ops stay disabled for correctness on this hardware
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    "-lhipfft",  # the spectral Stokes solve of the force-coupling method
 ]
 
 
