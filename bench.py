@@ -256,6 +256,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-solvers", action="store_true", help="skip the Broyden vs Newton-Krylov comparison")
+    ap.add_argument("--fcm-only", action="store_true", help="only the FCM applies (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: runs on several GPUs are not part of this implementation",
@@ -263,6 +264,9 @@ def main():
         sys.exit(2)
     import paper_1903_12609_amd as fil  # noqa: F401  (fails loudly without the HIP library)
     from paper_1903_12609_amd import synth
+    if args.fcm_only:
+        print(json.dumps({"fcm_apply": fcm_apply_bench()}))
+        return
 
     w = synth.sediment_suspension(M=100, N=20, side=200.0, seed=1002, dt_over_T=1 / 30)
     S = w.S
