@@ -131,7 +131,7 @@ typedef struct {
     double dt, tol;             /* time step; stop when max|f| / a <= tol */
     int32_t kmax;               /* Broyden iteration cap per step (<= 255) */
     int32_t prec;               /* fil_prec of the mobility apply */
-    int32_t j0_mode;            /* how J0^{-1} is applied: 0 auto (explicit inverse up to 64 MB),
+    int32_t j0_mode;            /* how J0^{-1} is applied: 0 auto (explicit inverse up to 256 MB),
                                    1 banded LU sweeps, 2 explicit inverse */
     int32_t pad0;
     double K0, kw, omega;       /* kappa_nu(s,t) = K0 sin(kw s - omega t + phase_f) */

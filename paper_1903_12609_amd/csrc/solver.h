@@ -8,7 +8,9 @@ constexpr int kMaxSeg = 64;       // segments per filament (one lane per segment
 constexpr int kKL = 8;            // sub-diagonals of the row-differenced J0 in interleaved order
 constexpr int kKU = 8;            // super-diagonals (kKL + kKU after pivoting fill-in)
 constexpr int kBandW = 2 * kKL + kKU + 1;
-constexpr size_t kDenseInvBytes = size_t(64) << 20;  // explicit J0^{-1} used up to this total size
+// explicit J0^{-1} used up to this total size: streaming it in each update beats the
+// banded sweeps (latency-bound, 6N sequential steps) up to a few hundred MB
+constexpr size_t kDenseInvBytes = size_t(256) << 20;
 constexpr int kMaxIter = 256;     // Broyden history capacity
 constexpr int kMaxDots = kMaxIter + 2;
 constexpr int kSpar = 5;          // per-suspension parameters: dt, gravity force (3), F^S
