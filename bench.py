@@ -249,8 +249,10 @@ def cpu_baseline(w, budget_s=12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    # untimed steps: the first steps capture the HIP graphs of the Broyden iteration blocks
+    # (one per first iteration and length) that later steps replay
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--graph", type=int, default=GRAPH_ITERS, help="Broyden iterations per graph block (0: off)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
