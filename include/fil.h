@@ -178,6 +178,17 @@ int fil_set_suspension_params(fil_sim* sim, const double* dt, const double* grav
  * copy cannot be allocated. */
 int fil_set_external_forces(fil_sim* sim, const double* Fext);
 
+/* The suspension in a periodic box, its mobility the force-coupling method
+ * (fil_fcm_create's box, grid and cut; Sec. 2.7.2) in place of the unbounded RPY
+ * tensor, and its steric barrier (Sec. 2.6) between nearest periodic images.  Positions
+ * stay unwrapped.  Only before the first step, for one suspension (nsusp == 1) in
+ * FIL_PREC_F64; every box length must exceed 4 chi a (the steric cutoff is below half the
+ * box).  The iterations of later steps then run from the host (no captured graphs), one
+ * FCM apply per residual evaluation; the Newton-Krylov steps and fil_residual use it too.
+ * The mobility timing of fil_set_timing then times whole FCM applies.  FIL_EINVAL on a
+ * bad argument, and fil_fcm_create's errors. */
+int fil_set_periodic_fcm(fil_sim* sim, const double* box, const int32_t* grid, double cut);
+
 /* One time step: warm start, J0 and its inverse, Broyden iterations on the
  * device (one mobility apply each), then q^{j+1} = exp(u) . q^j, the robot-arm
  * positions and the history shift.  The first step is BDF1, later ones BDF2.

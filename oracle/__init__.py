@@ -57,8 +57,12 @@ class Params(C.Structure):
         ("dt", C.c_double), ("tol", C.c_double), ("kmax", C.c_int64),
         ("K0", C.c_double), ("kw", C.c_double), ("omega", C.c_double), ("phase", _dp),
         ("tether", _i32p), ("base", _dp), ("nthreads", C.c_int64), ("drag_only", C.c_int64),
-        ("fext", _dp),
+        ("fext", _dp), ("Lper", _dp), ("mobility", C.c_void_p), ("mob_ctx", C.c_void_p),
     ]
+
+
+# (V, W) = M(Y) (F, T) over [S][3] arrays, in place of the unbounded RPY apply
+MOBILITY_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int64, _dp, _dp, _dp, _dp, _dp)
 
 
 class State(C.Structure):
@@ -82,7 +86,7 @@ def _declare(L):
     L.or_rpy_matrix.argtypes = [C.c_int64, _dp, C.c_double, C.c_double, _dp]
     L.or_rpy_apply_targets.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_int64, _i64p, _dp,
                                        _dp, C.c_int64]
-    L.or_steric.argtypes = [C.c_int64, _dp, _i64p, C.c_double, C.c_double, C.c_double, _dp]
+    L.or_steric.argtypes = [C.c_int64, _dp, _i64p, C.c_double, C.c_double, C.c_double, _dp, _dp]
     L.or_moment.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
     L.or_internal_forces.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp, _dp]
     L.or_reconstruct.argtypes = [C.POINTER(Params), _dp, _dp, _dp, _dp]
@@ -183,11 +187,14 @@ def rpy_matrix(Y, a, eta):
     return Mg
 
 
-def steric(Y, seg_fil, a, chi, FS):
+def steric(Y, seg_fil, a, chi, FS, L=None):
+    """Steric barrier forces [S, 3]; L [3]: the lengths of a periodic box (None: unbounded)."""
     Y = _f64(Y)
     seg_fil = np.ascontiguousarray(seg_fil, dtype=np.int64)
     FB = np.zeros_like(Y)
-    lib().or_steric(Y.shape[0], _p(Y), seg_fil.ctypes.data_as(_i64p), a, chi, FS, _p(FB))
+    Lp = None if L is None else _f64(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)))
+    lib().or_steric(Y.shape[0], _p(Y), seg_fil.ctypes.data_as(_i64p), a, chi, FS, None if Lp is None else _p(Lp),
+                    _p(FB))
     return FB
 
 
@@ -217,7 +224,10 @@ class Sim:
     configuration (from the shared synthetic generators).  Keyword parameters
     mirror the method's: a, eta, dL, KB, KT, chi, FS, grav, dt, tol, kmax, K0,
     kw, omega, phase [M], tether [M] (0/1), base [M,3], fext [S,3] (a further external
-    force on each segment), nthreads.
+    force on each segment), nthreads; periodic = dict(box [3], grid [3], cut) puts the
+    suspension in a periodic box with the force-coupling-method mobility (Sec. 2.7.2) and
+    nearest-image steric forces; mobility = callable (Y, F, T) -> (V, W) over [S, 3] arrays
+    replaces the RPY apply otherwise.
     """
 
     def __init__(self, fil_off, Y0, q0, **kw):
@@ -263,6 +273,31 @@ class Sim:
             P.fext = _p(fx)
         P.nthreads = kw.get("nthreads", 0)
         P.drag_only = int(kw.get("drag_only", 0))
+        per = kw.get("periodic")
+        mob = kw.get("mobility")
+        if per is not None:
+            # periodic box with the force-coupling-method mobility
+            from .fcm import fcm_apply
+            Lp = _f64(np.broadcast_to(np.asarray(per["box"], dtype=np.float64), (3,)))
+            self._keep.append(Lp)
+            P.Lper = _p(Lp)
+            box, grid, cut, a_, eta_ = per["box"], per["grid"], per.get("cut", 7.5), P.a, P.eta
+            mob = lambda Y, F, T: fcm_apply(Y, F, T, a_, eta_, box, grid, cut=cut)
+        if mob is not None:
+            def _cb(ctx, n, Yp, Fp, Tp, Vp, Wp, _mob=mob):
+                V = np.ctypeslib.as_array(Vp, shape=(n, 3))
+                W = np.ctypeslib.as_array(Wp, shape=(n, 3))
+                try:
+                    Vn, Wn = _mob(*(np.ctypeslib.as_array(p, shape=(n, 3)).copy() for p in (Yp, Fp, Tp)))
+                    V[:] = Vn
+                    W[:] = Wn
+                except Exception:  # an error inside the callback reaches C as NaN velocities
+                    V[:] = np.nan
+                    W[:] = np.nan
+                    raise
+            cb = MOBILITY_FN(_cb)
+            self._keep.append(cb)
+            P.mobility = C.cast(cb, C.c_void_p)
         self.P = P
         self.Y = _f64(Y0, (S, 3)).copy()
         self.Yprev = self.Y.copy()

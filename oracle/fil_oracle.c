@@ -269,14 +269,19 @@ void or_rpy_matrix(int64_t S, const double* Y, double a, double eta, double* Mg)
 /* ------------------------------------------------------------------------ */
 /* F^B_n = sum_m F^S ((4a^2 chi^2 - r^2) / (4a^2 (chi^2 - 1)))^4 r_nm / (2a) for r < 2 chi a,
  * skipping m = n and the neighbours m = n +- 1 of the same filament.  seg_fil[S]
- * gives each segment's filament.  Adds into FB. */
-void or_steric(int64_t S, const double* Y, const int64_t* seg_fil, double a, double chi, double FS, double* FB) {
+ * gives each segment's filament.  Lper[3] (or NULL: unbounded) are the lengths of a
+ * periodic box, where r_nm is the nearest periodic image of Y_n - Y_m (the cutoff is
+ * below half of every length).  Adds into FB. */
+void or_steric(int64_t S, const double* Y, const int64_t* seg_fil, double a, double chi, double FS,
+               const double* Lper, double* FB) {
     double rc = 2.0 * chi * a;
     for (int64_t n = 0; n < S; n++)
         for (int64_t m = 0; m < S; m++) {
             if (m == n) continue;
             if (seg_fil[m] == seg_fil[n] && (m == n + 1 || m + 1 == n)) continue;
             double r[3] = {Y[3 * n] - Y[3 * m], Y[3 * n + 1] - Y[3 * m + 1], Y[3 * n + 2] - Y[3 * m + 2]};
+            if (Lper)
+                for (int i = 0; i < 3; i++) r[i] -= Lper[i] * nearbyint(r[i] / Lper[i]);
             double d2 = dot3(r, r);
             if (d2 >= rc * rc) continue;
             double b = (4.0 * a * a * chi * chi - d2) / (4.0 * a * a * (chi * chi - 1.0));
@@ -350,6 +355,12 @@ typedef struct {
     int64_t nthreads;        /* OpenMP threads for the RPY target loop (0: default) */
     int64_t drag_only;       /* 1: diagonal drag mobility, no steric, no gravity: the f0 of Sec. 3.2.1 */
     const double* fext;      /* [S][3] further external force on each segment (Sec. 2.5), or NULL */
+    /* periodic box (Sec. 2.7.2): its lengths [3] for the steric barrier's nearest images
+     * (NULL: unbounded), and a mobility (V, W) = M(Y) (F, T) over [S][3] arrays that takes
+     * the place of the unbounded RPY apply (NULL: RPY) */
+    const double* Lper;
+    void (*mobility)(void* ctx, int64_t S, const double* Y, const double* F, const double* T, double* V, double* W);
+    void* mob_ctx;
 } or_params;
 
 typedef struct {
@@ -451,7 +462,7 @@ void or_forces(const or_params* P, const double* Y, const double* q, const doubl
         int64_t* seg_fil = (int64_t*)malloc(S * sizeof(int64_t));
         for (int64_t f = 0; f < P->M; f++)
             for (int64_t n = P->fil_off[f]; n < P->fil_off[f + 1]; n++) seg_fil[n] = f;
-        or_steric(S, Y, seg_fil, P->a, P->chi, P->FS, F);
+        or_steric(S, Y, seg_fil, P->a, P->chi, P->FS, P->Lper, F);
         free(seg_fil);
     }
 }
@@ -485,7 +496,10 @@ double or_residual(const or_params* P, const or_state* St, const double* X, doub
         }
     } else {
         or_forces(P, Y, q, X, tt, F, T);
-        or_rpy_apply(S, Y, F, T, P->a, P->eta, V, W, P->nthreads);
+        if (P->mobility)
+            P->mobility(P->mob_ctx, S, Y, F, T, V, W);
+        else
+            or_rpy_apply(S, Y, F, T, P->a, P->eta, V, W, P->nthreads);
     }
     double fmax = 0.0;
     for (int64_t f = 0; f < P->M; f++) {

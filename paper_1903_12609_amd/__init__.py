@@ -203,6 +203,16 @@ class Sim:
         a = np.ascontiguousarray(np.asarray(F, dtype=np.float64).reshape(self.S, 3))
         check(lib().fil_set_external_forces(self._h, a.ctypes.data_as(ctypes.c_void_p)))
 
+    def set_periodic_fcm(self, box, grid, cut=7.5):
+        """Periodic box of lengths box [3] with the force-coupling-method mobility on a grid
+        of grid [3] points (Gaussians truncated at cut widths); before the first step."""
+        import ctypes
+        import numpy as np
+        b = np.ascontiguousarray(np.broadcast_to(np.asarray(box, dtype=np.float64), (3,)))
+        g = np.ascontiguousarray(np.broadcast_to(np.asarray(grid, dtype=np.int32), (3,)))
+        check(lib().fil_set_periodic_fcm(self._h, b.ctypes.data_as(ctypes.c_void_p), g.ctypes.data_as(ctypes.c_void_p),
+                                         float(cut)))
+
     def features(self):
         """Raw per-filament features [M, 19N] (float32, device) at the committed state."""
         import torch

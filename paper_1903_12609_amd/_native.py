@@ -75,6 +75,7 @@ def _declare(L):
         L.fil_set_stream.argtypes = [_vp, _vp]
         L.fil_set_suspension_params.argtypes = [_vp, _vp, _vp, _vp]
         L.fil_set_external_forces.argtypes = [_vp, _vp]
+        L.fil_set_periodic_fcm.argtypes = [_vp, _vp, _vp, _d]
         L.fil_fcm_create.argtypes = [_vp, _vp, _d, _d, _d, _vp]
         L.fil_fcm_apply.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
         L.fil_fcm_destroy.argtypes = [_vp]

@@ -64,6 +64,9 @@ struct fil_sim {
     int pred_iters = 0;   // iterations the last device-driven solve took (0: none yet)
     hipStream_t cap_st = nullptr;  // private stream the blocks are captured on (launches go to st)
     double* fext_d = nullptr;      // [3][S] external forces per segment (null until set)
+    // force-coupling-method mobility of a periodic box (null: the unbounded RPY mobility);
+    // its iterations run host-driven (the FFTs are not captured)
+    fil_fcm* fcm = nullptr;
     // Newton-Krylov workspace (allocated on first use): Krylov basis [(m+1)][6S], residuals
     // at the Newton point and a perturbed point, work vectors, P^{-1} diagonal, dot partials
     int kry_m = 0;
@@ -181,6 +184,7 @@ void free_sim(fil_sim* s) {
     for (auto& kv : s->graphs)
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     if (s->cap_st) (void)hipStreamDestroy(s->cap_st);
+    if (s->fcm) fil_fcm_destroy(s->fcm);
     for (void* p : s->dev_allocs) (void)hipFree(p);
     for (void* p : s->host_allocs) (void)hipHostFree(p);
     delete s;
@@ -225,7 +229,11 @@ int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipE
                            s->rpy_work[c], s->st));
     const double* part = nullptr;
     int K = 1;
-    if (s->batched) {
+    if (s->fcm) {
+        if (e0) FIL_HIP_TRY(hipEventRecord(e0, s->st));
+        TRY(fil_fcm_apply(s->fcm, s->S, s->Yc, s->F, s->T, s->V, s->W, s->st));
+        if (e1) FIL_HIP_TRY(hipEventRecord(e1, s->st));
+    } else if (s->batched) {
         TRY(rpy_batch_launch(s->bplan[c], s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->rpy_work[c], s->st, e0, e1,
                              true, s->active_d));
     } else {
@@ -453,7 +461,8 @@ int solve(fil_sim* s, SolveLog& L) {
     TRY(pool_events(s, &e0, &e1));
     TRY(eval_residual(s, s->X, s->f, e0, e1, true, -1));
     TRY(begin_solve(s));
-    if (s->graph_iters > 0 && s->cur == 0) {
+    const bool graphs = s->graph_iters > 0 && !s->fcm;
+    if (graphs && s->cur == 0) {
         // the first test runs in the first-step kernel (the log was cleared at the start
         // of the step), which also fails a suspension with a singular J0 block
         const JudgeArgs jg{s->log_d, s->resbits_d + 2 * s->rb * ns, s->jflag_d, s->p.tol, 1.0 / s->p.a, 0,
@@ -483,7 +492,7 @@ int solve(fil_sim* s, SolveLog& L) {
     if (changed) TRY(upload_flags(s, s->active_d, s->active_h));
     if (any) TRY(broyden_state_launch(s->d, update_args(s, -1, s->f, nullptr), JudgeArgs{}, s->active_d, s->st));
     for (int it = 1; any;) {
-        if (s->graph_iters > 0 && s->cur == 0) {
+        if (graphs && s->cur == 0) {
             // FP32 iterations are done: the device continues from the host's counts
             for (int64_t i = 0; i < ns; i++)
                 s->log_h[i] = SuspLog{L.state[i], L.iters[i], L.applies[i], L.applies_hi[i], L.last[i]};
@@ -823,6 +832,24 @@ int fil_set_external_forces(fil_sim* s, const double* Fext) {
     }
     FIL_HIP_TRY(hipMemcpy(s->fext_d, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice));
     s->d.fext = s->fext_d;
+    return FIL_OK;
+}
+
+int fil_set_periodic_fcm(fil_sim* s, const double* box, const int32_t* grid, double cut) {
+    FIL_CHECK_ARG(s, "fil_set_periodic_fcm: null sim");
+    FIL_CHECK_ARG(s->step == 0, "fil_set_periodic_fcm: only before the first step");
+    FIL_CHECK_ARG(!s->fcm, "fil_set_periodic_fcm: the periodic box is already set");
+    FIL_CHECK_ARG(s->nsusp == 1, "fil_set_periodic_fcm: one suspension per periodic box");
+    FIL_CHECK_ARG(s->p.prec == FIL_PREC_F64, "fil_set_periodic_fcm: needs FIL_PREC_F64");
+    FIL_CHECK_ARG(box && grid, "fil_set_periodic_fcm: null box or grid");
+    for (int c = 0; c < 3; c++)
+        FIL_CHECK_ARG(std::isfinite(box[c]) && 4.0 * s->p.chi * s->p.a < box[c],
+                      "fil_set_periodic_fcm: every box length must exceed twice the steric range 2 chi a");
+    fil_fcm* f = nullptr;
+    TRY(fil_fcm_create(box, grid, s->p.a, s->p.eta, cut, &f));
+    s->fcm = f;
+    for (int c = 0; c < 3; c++) s->d.per[c] = box[c];
+    s->d.periodic = 1;
     return FIL_OK;
 }
 

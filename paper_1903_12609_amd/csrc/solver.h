@@ -38,6 +38,10 @@ struct SimDev {
     int max_dots;                  // dot products per Broyden update at most (kmax + 2)
     const double* spar;            // [nsusp][5] per suspension: dt, gravity force (3), steric strength F^S
     const double* fext;            // [3][S] further external force per segment, or null
+    // periodic box lengths of the steric pass (minimum-image distances); periodic == 0:
+    // unbounded
+    double per[3];
+    int periodic;
     // filaments by size class (for launches whose LDS scales with 6N): class k holds
     // cls_fil[cls_off[k] .. cls_off[k+1]), all with 6N <= cls_n[k]
     const int32_t* cls_fil;

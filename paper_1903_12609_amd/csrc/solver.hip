@@ -247,7 +247,21 @@ int state_forces_launch(const SimDev& d, const double* X, const double* qj, cons
 // filament f tests the bounding boxes of its suspension's filaments 64 at a time
 // (one per lane), then walks the segments of every filament within the cutoff
 // with wave-uniform (scalar) loads.  It finishes the force F^H = F^C + F^B +
-// gravity and writes the mobility source record of each of its segments.
+// gravity and writes the mobility source record of each of its segments.  In a
+// periodic box r_nm is the nearest image (the cutoff is below half of every box
+// length) and two filaments are near when their box centres, nearest image apart,
+// are closer than the half-widths plus the cutoff along every axis; that never
+// misses a pair of segments within the cutoff.
+// r - L round(r / L): the nearest periodic image of a separation
+__device__ __forceinline__ double nearest_image(double r, double L) { return r - L * rint(r / L); }
+
+// gap along one axis between the intervals [lo_a, hi_a] and [lo_b, hi_b] of a periodic
+// axis of length L: the nearest-image distance of the centres less both half-widths
+__device__ __forceinline__ double box_gap_periodic(double lo_a, double hi_a, double lo_b, double hi_b, double L) {
+    const double dc = nearest_image(0.5 * (lo_b + hi_b) - 0.5 * (lo_a + hi_a), L);
+    return fmax(0.0, fabs(dc) - 0.5 * (hi_a - lo_a) - 0.5 * (hi_b - lo_b));
+}
+
 __global__ void __launch_bounds__(64 * kStericWaves) steric_pack_kernel(SimDev d, const double* __restrict__ Yc,
                                                        const double* __restrict__ box,
                                                        const int32_t* __restrict__ active, double* __restrict__ F,
@@ -283,9 +297,16 @@ __global__ void __launch_bounds__(64 * kStericWaves) steric_pack_kernel(SimDev d
             const int64_t g = gb + lane;
             if (g < g1) {
                 const double* bx = box + 6 * g;
-                const double gx = fmax(0.0, fmax(bx[0] - hi0, lo0 - bx[3]));
-                const double gy = fmax(0.0, fmax(bx[1] - hi1, lo1 - bx[4]));
-                const double gz = fmax(0.0, fmax(bx[2] - hi2, lo2 - bx[5]));
+                double gx, gy, gz;
+                if (!d.periodic) {
+                    gx = fmax(0.0, fmax(bx[0] - hi0, lo0 - bx[3]));
+                    gy = fmax(0.0, fmax(bx[1] - hi1, lo1 - bx[4]));
+                    gz = fmax(0.0, fmax(bx[2] - hi2, lo2 - bx[5]));
+                } else {
+                    gx = box_gap_periodic(lo0, hi0, bx[0], bx[3], d.per[0]);
+                    gy = box_gap_periodic(lo1, hi1, bx[1], bx[4], d.per[1]);
+                    gz = box_gap_periodic(lo2, hi2, bx[2], bx[5], d.per[2]);
+                }
                 near = gx * gx + gy * gy + gz * gz < rc2;
             }
             unsigned long long mask = __ballot(near);
@@ -312,8 +333,13 @@ __global__ void __launch_bounds__(64 * kStericWaves) steric_pack_kernel(SimDev d
                 const int ng = (int)(d.seg_off[gg + 1] - m0);  // <= 64
                 for (int q = wave; q < ng; q += kStericWaves) {
                     const int64_t m = m0 + q;
-                    const double rx = y0 - readlane_f64(p0, q), ry = y1 - readlane_f64(p1, q),
-                                 rz = y2 - readlane_f64(p2, q);
+                    double rx = y0 - readlane_f64(p0, q), ry = y1 - readlane_f64(p1, q),
+                           rz = y2 - readlane_f64(p2, q);
+                    if (d.periodic) {
+                        rx = nearest_image(rx, d.per[0]);
+                        ry = nearest_image(ry, d.per[1]);
+                        rz = nearest_image(rz, d.per[2]);
+                    }
                     const double r2 = rx * rx + ry * ry + rz * rz;
                     const bool excluded = m == sn || (gg == f && (m == sn + 1 || m + 1 == sn));
                     if (r2 < rc2 && !excluded) {

@@ -171,6 +171,46 @@ def sediment_suspension(M=100, N=20, side=200.0, seed=1002, B=1e3, dt_over_T=1.0
     return Workload("sediment_suspension", fil_off, Y, q, params, extra=dict(T=T, side=side))
 
 
+# the paper's periodic monolayer: a 141 dL x 141 dL x 8.8 dL box on a 1024 x 1024 x 64 grid
+MONOLAYER_BOX = (141.0 * DL, 141.0 * DL, 8.8 * DL)
+MONOLAYER_GRID = (1024, 1024, 64)
+
+
+def periodic_monolayer(M=256, N=15, box=MONOLAYER_BOX, grid=MONOLAYER_GRID, seed=1005, B=1e3, dt_over_T=1 / 300,
+                       tol=1e-4, kmax=100, min_sep=DL, max_tries=200000):
+    """Straight filaments in the centre plane z = Lz / 2 of a periodic box: centres uniform
+    over the plane, orientations uniform in the plane, placements closer than min_sep to
+    a placed segment (nearest periodic image) rejected.  The force per unit length W
+    acts in the plane, along -y.  Positions are not wrapped into the box."""
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, dtype=np.float64)
+    Ys, qs = [], []
+    placed = np.zeros((0, 3))
+    tries = 0
+    for m in range(M):
+        while True:
+            tries += 1
+            if tries > max_tries:
+                raise RuntimeError("placement failed: monolayer too dense")
+            th = rng.uniform(0.0, 2 * math.pi)
+            q = np.tile(np.array([math.cos(th / 2), 0.0, 0.0, math.sin(th / 2)]), (N, 1))
+            Y = chain(np.zeros(3), q)
+            Y += np.array([rng.uniform(0, box[0]), rng.uniform(0, box[1]), box[2] / 2]) - Y.mean(axis=0)
+            if len(placed):
+                d = Y[:, None, :] - placed[None, :, :]
+                d -= box * np.round(d / box)
+                if (d ** 2).sum(-1).min() < min_sep ** 2:
+                    continue
+            break
+        Ys.append(Y)
+        qs.append(q)
+        placed = np.concatenate([placed, Y])
+    params, T = sedimentation_params(N, B, dt_over_T, tol, kmax, steric=True)
+    params["grav"] = (0.0, params["grav"][2], 0.0)
+    return Workload("periodic_monolayer", np.arange(0, M * N + 1, N, dtype=np.int64), np.concatenate(Ys),
+                    np.concatenate(qs), params, extra=dict(T=T, box=tuple(box), grid=tuple(grid)))
+
+
 def active_array(nx=40, ny=25, N=32, spacing=20.0, seed=1003, tol=1e-6, kmax=100, steps_per_beat=100):
     """Base-clamped filaments on a square lattice, initially straight along +z,
     driven by kappa_nu(s,t) = K0 sin(k s - omega t + phi) with K0 = 10.61/L,
