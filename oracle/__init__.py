@@ -224,7 +224,7 @@ class Sim:
     configuration (from the shared synthetic generators).  Keyword parameters
     mirror the method's: a, eta, dL, KB, KT, chi, FS, grav, dt, tol, kmax, K0,
     kw, omega, phase [M], tether [M] (0/1), base [M,3], fext [S,3] (a further external
-    force on each segment), nthreads; periodic = dict(box [3], grid [3], cut) puts the
+    force on each segment), nthreads; periodic = dict(box [3], grid [3], cut, omega) puts the
     suspension in a periodic box with the force-coupling-method mobility (Sec. 2.7.2) and
     nearest-image steric forces; mobility = callable (Y, F, T) -> (V, W) over [S, 3] arrays
     replaces the RPY apply otherwise.
@@ -282,7 +282,8 @@ class Sim:
             self._keep.append(Lp)
             P.Lper = _p(Lp)
             box, grid, cut, a_, eta_ = per["box"], per["grid"], per.get("cut", 7.5), P.a, P.eta
-            mob = lambda Y, F, T: fcm_apply(Y, F, T, a_, eta_, box, grid, cut=cut)
+            om = per.get("omega", "curl")
+            mob = lambda Y, F, T: fcm_apply(Y, F, T, a_, eta_, box, grid, cut=cut, omega=om)
         if mob is not None:
             def _cb(ctx, n, Yp, Fp, Tp, Vp, Wp, _mob=mob):
                 V = np.ctypeslib.as_array(Vp, shape=(n, 3))

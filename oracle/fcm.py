@@ -12,6 +12,11 @@ In a periodic box [0, Lx) x [0, Ly) x [0, Lz) on an nx x ny x nz grid (spacings 
     not defined there;
   * V_n = sum over the grid of u Delta_n hx hy hz and Omega_n = 1/2 sum of w Theta_n hx hy hz
     (the trapezoidal rule).
+With omega="by_parts" the rotation is the same average after integrating by parts over
+the periodic box, Omega_n = 1/2 int u x grad Theta_n dV = 1/2 int (r x u) Theta_n / sigma_T^2
+dV (r = x - Y_n), summed by the same rule: no vorticity field is formed, and the averaging
+is then the exact adjoint of the rotlet spreading.  The two forms agree up to the grid's
+discretisation error.
 Everything is evaluated on the whole grid with numpy, in float64.
 """
 import numpy as np
@@ -42,9 +47,12 @@ def _gauss(Y, L, n, sigma, cut):
     return g, np.stack([rx, ry, rz])
 
 
-def fcm_apply(Y, F, T, a, eta, L, n, cut=7.5):
+def fcm_apply(Y, F, T, a, eta, L, n, cut=7.5, omega="curl"):
     """(V, Omega) [S, 3] of S segments at Y [S, 3] with forces F and torques T [S, 3];
-    L and n are the box lengths and grid sizes (scalars for a cube)."""
+    L and n are the box lengths and grid sizes (scalars for a cube); omega: "curl" (the
+    average of the spectral vorticity) or "by_parts"."""
+    if omega not in ("curl", "by_parts"):
+        raise ValueError("omega must be 'curl' or 'by_parts'")
     Y, F, T = (np.asarray(v, dtype=np.float64).reshape(-1, 3) for v in (Y, F, T))
     L, n, h = _axes(L, n)
     sD, sT = widths(a)
@@ -73,14 +81,19 @@ def fcm_apply(Y, F, T, a, eta, L, n, cut=7.5):
             idx = [slice(None)] * 4
             idx[1 + c] = int(n[c]) // 2
             uk[tuple(idx)] = 0.0
-    wk = 1j * np.stack([k[1] * uk[2] - k[2] * uk[1], k[2] * uk[0] - k[0] * uk[2], k[0] * uk[1] - k[1] * uk[0]])
     u = np.real(np.fft.ifftn(uk, axes=(1, 2, 3)))
-    w = np.real(np.fft.ifftn(wk, axes=(1, 2, 3)))
+    if omega == "curl":
+        wk = 1j * np.stack([k[1] * uk[2] - k[2] * uk[1], k[2] * uk[0] - k[0] * uk[2], k[0] * uk[1] - k[1] * uk[0]])
+        w = np.real(np.fft.ifftn(wk, axes=(1, 2, 3)))
     V, W = np.zeros_like(Y), np.zeros_like(Y)
     dv = float(np.prod(h))
     for m in range(Y.shape[0]):
         gD, _ = _gauss(Y[m], L, n, sD, cut)
-        gT, _ = _gauss(Y[m], L, n, sT, cut)
+        gT, r = _gauss(Y[m], L, n, sT, cut)
         V[m] = (u * gD).sum(axis=(1, 2, 3)) * dv
-        W[m] = 0.5 * (w * gT).sum(axis=(1, 2, 3)) * dv
+        if omega == "curl":
+            W[m] = 0.5 * (w * gT).sum(axis=(1, 2, 3)) * dv
+        else:
+            rxu = np.stack([r[1] * u[2] - r[2] * u[1], r[2] * u[0] - r[0] * u[2], r[0] * u[1] - r[1] * u[0]])
+            W[m] = 0.5 * (rxu * gT).sum(axis=(1, 2, 3)) * dv / (sT * sT)
     return V, W
