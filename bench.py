@@ -147,16 +147,21 @@ def learned_gain(log_fn):
     return res
 
 
-def solver_comparison(w, steps=5, warmup=2):
+def solver_comparison(w, steps=5, warmup=2, names=("ejb_b", "jfnk_j0", "jfnk_none", "jfb_g_j0"), periodic=None,
+                      workload="sedimenting suspension 100 x 20 (S=2000), dt=T/30, tolerances 1e-4 (paper's comparison)"):
     """Bad Broyden with the explicit J0 against Jacobian-free Newton-Krylov (J0 left
-    preconditioner, none) and the Jacobian-free good Broyden method (J0 left
-    preconditioner), at the tolerances of the paper's comparisons (Newton/Broyden 1e-4,
-    GMRES 1e-4, finite-difference delta 1e-7), on the same suspension and GPU."""
+    preconditioner, the time-step right preconditioner, none) and the Jacobian-free good
+    Broyden method (J0 left preconditioner), at the tolerances of the paper's comparisons
+    (Newton/Broyden 1e-4, GMRES 1e-4, finite-difference delta 1e-7), on the same
+    suspension and GPU; periodic = (box, grid, cut) puts it in a periodic box with the
+    force-coupling mobility."""
     import torch
     import paper_1903_12609_amd as fil
     out = {}
-    for name in ("ejb_b", "jfnk_j0", "jfnk_none", "jfb_g_j0"):
+    for name in names:
         sim = fil.Sim(w.fil_off, w.Y, w.q, dict(w.params, tol=1e-4), graph=GRAPH_ITERS)
+        if periodic is not None:
+            sim.set_periodic_fcm(*periodic)
         if name == "ejb_b":
             run = lambda: sim.step()[0]
         elif name.startswith("jfnk"):
@@ -178,10 +183,26 @@ def solver_comparison(w, steps=5, warmup=2):
             out[name]["krylov_iters_per_step"] = krylov / steps
         sim.close()
         log("solver", name, out[name])
-    out["jfnk_j0_over_ejb_b_time"] = out["jfnk_j0"]["ms_per_step"] / out["ejb_b"]["ms_per_step"]
-    out["jfb_g_j0_over_ejb_b_time"] = out["jfb_g_j0"]["ms_per_step"] / out["ejb_b"]["ms_per_step"]
-    out["workload"] = "sedimenting suspension 100 x 20 (S=2000), dt=T/30, tolerances 1e-4 (paper's comparison)"
+    for name in names:
+        if name != "ejb_b":
+            out[name + "_over_ejb_b_time"] = out[name]["ms_per_step"] / out["ejb_b"]["ms_per_step"]
+    out["workload"] = workload
     return out
+
+
+def fcm_monolayer_steps(steps=4, warmup=1, cut=4.5):
+    """The paper's solver test bed with its own mobility: a monolayer of 256 filaments of
+    N = 15 segments in the centre plane of a periodic 141 dL x 141 dL x 8.8 dL box, the
+    force-coupling method on a 1024 x 1024 x 64 grid (Gaussians truncated at 4.5 widths,
+    where their tails fall below the 1e-4 tolerance), B = 1000, dt = T/300, gravity in the
+    plane; bad Broyden against JFNK (J0, time-step preconditioners) and JFB-g (J0)."""
+    from paper_1903_12609_amd import synth
+    w = synth.periodic_monolayer(M=256, N=15, seed=1006)
+    per = (w.extra["box"], w.extra["grid"], cut)
+    return solver_comparison(w, steps=steps, warmup=warmup, names=("ejb_b", "jfnk_j0", "jfnk_pdt", "jfb_g_j0"),
+                             periodic=per,
+                             workload="periodic monolayer 256 x 15 (S=3840), FCM 1024x1024x64 over 141dL x 141dL x "
+                                      "8.8dL, cut 4.5 widths, B=1e3, dt=T/300, tolerances 1e-4")
 
 
 def fcm_apply_bench(reps=5):
@@ -259,6 +280,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-solvers", action="store_true", help="skip the Broyden vs Newton-Krylov comparison")
     ap.add_argument("--fcm-only", action="store_true", help="only the FCM applies (for profiling)")
+    ap.add_argument("--fcm-steps-only", action="store_true",
+                    help="only the solver comparison on the periodic FCM monolayer (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: runs on several GPUs are not part of this implementation",
@@ -268,6 +291,9 @@ def main():
     from paper_1903_12609_amd import synth
     if args.fcm_only:
         print(json.dumps({"fcm_apply": fcm_apply_bench()}))
+        return
+    if args.fcm_steps_only:
+        print(json.dumps({"fcm_monolayer_solvers": fcm_monolayer_steps()}))
         return
 
     w = synth.sediment_suspension(M=100, N=20, side=200.0, seed=1002, dt_over_T=1 / 30)
@@ -313,6 +339,7 @@ def main():
         res["fcm_apply"] = fcm_apply_bench()
     if not args.no_solvers:
         res["solver_comparison"] = solver_comparison(w)
+        res["fcm_monolayer_solvers"] = fcm_monolayer_steps()
     if not args.no_learned:
         res["learned_warm_start"] = learned_gain(log)
     if not args.no_cpu:

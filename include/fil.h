@@ -75,8 +75,11 @@ int fil_rpy_mobility_apply(int64_t S, const double* Y, const double* F, const do
  * -1/2 T_m x grad Theta_m (widths sigma_D = a / sqrt(pi), sigma_T = a / (6 sqrt(pi))^(1/3),
  * truncated at distance cut * sigma), the equations are solved spectrally on a regular
  * grid, and V_n, Omega_n are the Gaussian-weighted averages of the velocity and half the
- * vorticity (trapezoidal rule).  The zero mode and the Nyquist planes of even axes are
- * dropped.  The mean force is not balanced: the result is the periodic mobility.
+ * vorticity (trapezoidal rule), the latter integrated by parts over the box,
+ * Omega_n = 1/2 sum (r x u) Theta_n / sigma_T^2 dV (r = x - Y_n): the exact adjoint of the
+ * rotlet spreading, equal to the vorticity average up to the grid's discretisation error.
+ * The zero mode and the Nyquist planes of even axes are dropped.  The mean force is not
+ * balanced: the result is the periodic mobility.
  *   box   HOST double[3]: box lengths (positions are wrapped into [0, L))
  *   grid  HOST int32[3]: grid points per axis (4 .. 4096); the support 2 ceil(cut sigma_D
  *         / h) + 1 must fit in the grid and in 65 points

@@ -1,9 +1,16 @@
 // Force-coupling-method mobility (Sec. 2.7.2) on a periodic grid:
 //   f(x) = sum_m F_m Delta_m(x) - 1/2 sum_m T_m x grad Theta_m(x)   (Gaussians of widths
 //   sigma_D = a / sqrt(pi), sigma_T = a / (6 sqrt(pi))^(1/3), truncated at cut * sigma),
-//   u_k = (I - k k^T / k^2) f_k / (eta k^2), w_k = i k x u_k (u_0 = 0; the Nyquist planes
-//   of even axes dropped, where the spectral curl of a real field is undefined),
-//   V_n = sum_grid u Delta_n dV,  Omega_n = 1/2 sum_grid w Theta_n dV  (trapezoidal rule).
+//   u_k = (I - k k^T / k^2) f_k / (eta k^2) (u_0 = 0; the Nyquist planes of even axes
+//   dropped, where the spectral derivative of a real field is undefined),
+//   V_n = sum_grid u Delta_n dV  (trapezoidal rule),
+//   Omega_n = 1/2 int (curl u) Theta_n dV = 1/2 int u x grad Theta_n dV
+//           = 1/2 sum_grid (r x u) Theta_n / sigma_T^2 dV,  r = x - Y_n,
+//   the vorticity average integrated by parts over the periodic box: only the three
+//   velocity components are transformed back, and the averaging is the exact adjoint of
+//   the rotlet spreading (a symmetric discrete mobility).  It differs from averaging the
+//   spectral vorticity by the grid's discretisation error, which falls spectrally with
+//   the spacing (below 1e-9 of the rotation at h = 0.3a).
 // Spreading adds each segment's Gaussian into the grid with atomics (one workgroup per
 // segment, the separable 1D factors in LDS); the transforms are hipFFT's; averaging is a
 // gather, one workgroup per segment, summed in a fixed order.
@@ -97,8 +104,8 @@ __global__ void __launch_bounds__(kFcmBlock) fcm_zero_kernel(int64_t n, double* 
     if (i < n) f[i] = 0.0;
 }
 
-// Fourier space: fk [3][Nc] -> uk [6][Nc] (velocity, vorticity), scaled by 1/N for the
-// unnormalised inverse transform
+// Fourier space: fk [3][Nc] -> uk [3][Nc], scaled by 1/N for the unnormalised inverse
+// transform
 __global__ void __launch_bounds__(kFcmBlock) fcm_solve_kernel(FcmGrid g, const hipfftDoubleComplex* __restrict__ fk,
                                                               hipfftDoubleComplex* __restrict__ uk) {
     const int64_t e = (int64_t)blockIdx.x * kFcmBlock + threadIdx.x;
@@ -129,16 +136,9 @@ __global__ void __launch_bounds__(kFcmBlock) fcm_solve_kernel(FcmGrid g, const h
         }
     }
     for (int c = 0; c < 3; c++) uk[c * g.Nc + e] = hipfftDoubleComplex{ur[c], ui[c]};
-    // w = i k x u: (i k x u)_c = i (k_a u_b - k_b u_a)
-    const int A[3] = {1, 2, 0}, B[3] = {2, 0, 1};
-    for (int c = 0; c < 3; c++) {
-        const double cr = k[A[c]] * ur[B[c]] - k[B[c]] * ur[A[c]];
-        const double ci = k[A[c]] * ui[B[c]] - k[B[c]] * ui[A[c]];
-        uk[(3 + c) * g.Nc + e] = hipfftDoubleComplex{-ci, cr};
-    }
 }
 
-// V_n = sum u Delta_n dV, Omega_n = 1/2 sum w Theta_n dV; u [6][N] (velocity, vorticity)
+// V_n = sum u Delta_n dV, Omega_n = 1/2 sum (r x u) Theta_n / sigma_T^2 dV; u [3][N]
 __global__ void __launch_bounds__(kFcmBlock) fcm_average_kernel(FcmGrid g, int64_t S, const double* __restrict__ Y,
                                                                 const double* __restrict__ u, double* __restrict__ V,
                                                                 double* __restrict__ W) {
@@ -161,10 +161,15 @@ __global__ void __launch_bounds__(kFcmBlock) fcm_average_kernel(FcmGrid g, int64
         if (r2 >= rcD) continue;
         const int64_t gi = ((int64_t)fa.idx[0][ax] * g.n[1] + fa.idx[1][ay]) * g.n[2] + fa.idx[2][az];
         const double gD = nD * fa.eD[0][ax] * fa.eD[1][ay] * fa.eD[2][az];
-        for (int c = 0; c < 3; c++) acc[c] = fma(u[c * g.N + gi], gD, acc[c]);
+        const double u0 = u[gi], u1 = u[g.N + gi], u2 = u[2 * g.N + gi];
+        acc[0] = fma(u0, gD, acc[0]);
+        acc[1] = fma(u1, gD, acc[1]);
+        acc[2] = fma(u2, gD, acc[2]);
         if (r2 < rcT) {
             const double gT = nT * fa.eT[0][ax] * fa.eT[1][ay] * fa.eT[2][az];
-            for (int c = 0; c < 3; c++) acc[3 + c] = fma(u[(3 + c) * g.N + gi], gT, acc[3 + c]);
+            acc[3] = fma(ry * u2 - rz * u1, gT, acc[3]);
+            acc[4] = fma(rz * u0 - rx * u2, gT, acc[4]);
+            acc[5] = fma(rx * u1 - ry * u0, gT, acc[5]);
         }
     }
     for (int c = 0; c < 6; c++) red[c][threadIdx.x] = acc[c];
@@ -177,9 +182,10 @@ __global__ void __launch_bounds__(kFcmBlock) fcm_average_kernel(FcmGrid g, int64
     }
     if (threadIdx.x == 0) {
         const double dv = g.h[0] * g.h[1] * g.h[2];
+        const double wsc = 0.5 * dv / (g.sT * g.sT);
         for (int c = 0; c < 3; c++) {
             V[c * S + m] = red[c][0] * dv;
-            W[c * S + m] = 0.5 * red[3 + c][0] * dv;
+            W[c * S + m] = red[3 + c][0] * wsc;
         }
     }
 }
@@ -194,8 +200,8 @@ struct fil_fcm {
     bool fwd_ok = false, inv_ok = false;
     double* f = nullptr;                  // [3][N] body force
     hipfftDoubleComplex* fk = nullptr;    // [3][Nc]
-    hipfftDoubleComplex* uk = nullptr;    // [6][Nc]
-    double* u = nullptr;                  // [6][N] velocity and vorticity
+    hipfftDoubleComplex* uk = nullptr;    // [3][Nc]
+    double* u = nullptr;                  // [3][N] velocity
 };
 
 namespace {
@@ -246,8 +252,8 @@ int fil_fcm_create(const double* box, const int32_t* grid, double a, double eta,
     g.Nc = (int64_t)g.n[0] * g.n[1] * (g.n[2] / 2 + 1);
     if (hipMalloc(&s->f, 3 * g.N * sizeof(double)) != hipSuccess ||
         hipMalloc(&s->fk, 3 * g.Nc * sizeof(hipfftDoubleComplex)) != hipSuccess ||
-        hipMalloc(&s->uk, 6 * g.Nc * sizeof(hipfftDoubleComplex)) != hipSuccess ||
-        hipMalloc(&s->u, 6 * g.N * sizeof(double)) != hipSuccess) {
+        hipMalloc(&s->uk, 3 * g.Nc * sizeof(hipfftDoubleComplex)) != hipSuccess ||
+        hipMalloc(&s->u, 3 * g.N * sizeof(double)) != hipSuccess) {
         fcm_free(s);
         set_error("fil_fcm_create: device allocation of the grids failed");
         return FIL_ENOMEM;
@@ -259,7 +265,7 @@ int fil_fcm_create(const double* box, const int32_t* grid, double a, double eta,
         return FIL_EHIP;
     }
     s->fwd_ok = true;
-    if (hipfftPlanMany(&s->inv, 3, n, nullptr, 1, (int)g.Nc, nullptr, 1, (int)g.N, HIPFFT_Z2D, 6) != HIPFFT_SUCCESS) {
+    if (hipfftPlanMany(&s->inv, 3, n, nullptr, 1, (int)g.Nc, nullptr, 1, (int)g.N, HIPFFT_Z2D, 3) != HIPFFT_SUCCESS) {
         fcm_free(s);
         set_error("fil_fcm_create: hipFFT inverse plan failed");
         return FIL_EHIP;

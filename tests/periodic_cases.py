@@ -58,4 +58,5 @@ def small_monolayer(dt_over_T=1 / 30, tol=1e-8):
 
 
 def periodic(cut=7.5):
-    return dict(box=BOX, grid=GRID, cut=cut)
+    """The oracle's periodic set-up; the rotation averaged by parts, as on the GPU."""
+    return dict(box=BOX, grid=GRID, cut=cut, omega="by_parts")
