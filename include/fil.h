@@ -70,6 +70,22 @@ int64_t fil_rpy_workspace_bytes(int64_t S, int prec);
 int fil_rpy_mobility_apply(int64_t S, const double* Y, const double* F, const double* T, double a, double eta,
                            int prec, double* V, double* Omega, void* work, int64_t work_bytes, void* stream);
 
+/* RPY mobility of the segments above a no-slip plane wall z = 0 (the half-space tensor
+ * the paper uses for its cilia, Sec. 2.7.1 and Sec. 5.3): the unbounded tensor of
+ * fil_rpy_mobility_apply (same overlap forms) plus the wall's image part, Blake's image
+ * system for a point force above a wall under the Faxen operators of both spheres
+ *   tt = (1 + a^2/6 lap_x)(1 + a^2/6 lap_y) G^im,  rt = 1/2 curl_x (1 + a^2/6 lap_y) G^im,
+ *   tr = 1/2 curl_y (1 + a^2/6 lap_x) G^im,  rr = 1/4 curl_x curl_y G^im   (over 8 pi eta),
+ * whose self terms are the Rotne-Prager-Blake wall corrections (e.g. 1 - 9a/16h + a^3/8h^3
+ * - a^5/16h^5 for translation parallel to the wall).  Valid for centres at z >= a (spheres
+ * not crossing the wall); smaller heights are evaluated with the same formulas.
+ *   S, Y, F, T, a, eta, V, Omega  as fil_rpy_mobility_apply (FP64 only)
+ *   work   device scratch of fil_rpy_wall_workspace_bytes(S) bytes (NULL when 0)
+ * Deterministic: the partial sums over source chunks are added in a fixed order. */
+int64_t fil_rpy_wall_workspace_bytes(int64_t S);
+int fil_rpy_wall_apply(int64_t S, const double* Y, const double* F, const double* T, double a, double eta,
+                       double* V, double* Omega, void* work, int64_t work_bytes, void* stream);
+
 /* Force-coupling-method mobility (Sec. 2.7.2) in a periodic box: the forces and
  * torques enter the Stokes equations as Gaussian monopoles F_m Delta_m and rotlets
  * -1/2 T_m x grad Theta_m (widths sigma_D = a / sqrt(pi), sigma_T = a / (6 sqrt(pi))^(1/3),
@@ -191,6 +207,14 @@ int fil_set_external_forces(fil_sim* sim, const double* Fext);
  * The mobility timing of fil_set_timing then times whole FCM applies.  FIL_EINVAL on a
  * bad argument, and fil_fcm_create's errors. */
 int fil_set_periodic_fcm(fil_sim* sim, const double* box, const int32_t* grid, double cut);
+
+/* The suspension above a no-slip plane wall at z = 0: every residual evaluation applies
+ * the wall-bounded RPY mobility of fil_rpy_wall_apply in place of the unbounded one (the
+ * steric barrier and everything else unchanged; no wall repulsion, so segments must stay
+ * above z = a).  Only before the first step, for one suspension in FIL_PREC_F64, and not
+ * with fil_set_periodic_fcm.  Graph blocks and the Newton-Krylov steps use it too.
+ * FIL_EINVAL on a bad call, FIL_ENOMEM if the workspace cannot be allocated. */
+int fil_set_wall(fil_sim* sim);
 
 /* One time step: warm start, J0 and its inverse, Broyden iterations on the
  * device (one mobility apply each), then q^{j+1} = exp(u) . q^j, the robot-arm

@@ -98,10 +98,29 @@ def wall_matrix(Y, a, eta):
     return M
 
 
-def wall_rpy_apply(Y, F, T, a, eta):
-    """(V, Omega) [S, 3] of spheres at Y above the wall with forces F and torques T [S, 3]."""
+def wall_rpy_apply(Y, F, T, a, eta, targets=None):
+    """(V, Omega) [S, 3] of spheres at Y above the wall with forces F and torques T [S, 3];
+    with targets (indices) only those rows, [len(targets), 3]."""
     Y = np.asarray(Y, dtype=np.float64).reshape(-1, 3)
+    F = np.asarray(F, dtype=np.float64).reshape(-1, 3)
+    T = np.asarray(T, dtype=np.float64).reshape(-1, 3)
     S = Y.shape[0]
-    M = wall_matrix(Y, a, eta)
-    u = M @ np.concatenate([np.asarray(F, dtype=np.float64).ravel(), np.asarray(T, dtype=np.float64).ravel()])
-    return u[:3 * S].reshape(S, 3), u[3 * S:].reshape(S, 3)
+    if targets is None:
+        M = wall_matrix(Y, a, eta)
+        u = M @ np.concatenate([F.ravel(), T.ravel()])
+        return u[:3 * S].reshape(S, 3), u[3 * S:].reshape(S, 3)
+    from . import rpy_apply_targets
+    idx = np.asarray(targets, dtype=np.int64)
+    V, W = rpy_apply_targets(Y, F, T, a, eta, idx)
+    fn = _image_functions()
+    n = len(idx)
+    xi = [np.repeat(Y[idx, k], S) for k in range(3)]
+    yj = [np.tile(Y[:, k], n) for k in range(3)]
+    c = 1.0 / (8.0 * np.pi * eta)
+    for name, out, src in (("tt", V, F), ("tr", V, T), ("rt", W, F), ("rr", W, T)):
+        vals = fn[name](*xi, *yj, a)
+        for e in range(9):
+            i, j = divmod(e, 3)
+            v = np.broadcast_to(np.asarray(vals[e], dtype=np.float64), (n * S,)).reshape(n, S)
+            out[:, i] += c * (v @ src[:, j])
+    return V, W

@@ -12,6 +12,7 @@ import os
 from ._native import FilError, PREC, check, lib  # noqa: F401
 
 __all__ = ["FilError", "MLP", "Sim", "rpy_mobility_apply", "rpy_mobility_apply_batched", "rpy_workspace_bytes",
+           "rpy_wall_apply",
            "filament_internal_forces"]
 
 
@@ -48,6 +49,23 @@ def rpy_mobility_apply(Y, F, T, a=1.0, eta=1.0, prec="f64", V=None, W=None, work
         work = torch.empty(max(nb, 1), dtype=torch.uint8, device=Y.device)
     check(lib().fil_rpy_mobility_apply(S, _ptr(Y), _ptr(F), _ptr(T), float(a), float(eta), PREC[prec], _ptr(V),
                                        _ptr(W), _ptr(work), work.numel(), _stream()))
+    return V, W
+
+
+def rpy_wall_apply(Y, F, T, a=1.0, eta=1.0, V=None, W=None, work=None):
+    """(V, Omega) = RPY mobility above the no-slip wall z = 0 applied to forces F and
+    torques T at positions Y; float64 CUDA tensors of shape (3, S)."""
+    import torch
+    S = Y.shape[1]
+    for n, t in (("Y", Y), ("F", F), ("T", T)):
+        _check_soa(n, t, 3, S)
+    V = torch.empty_like(Y) if V is None else V
+    W = torch.empty_like(Y) if W is None else W
+    nb = int(lib().fil_rpy_wall_workspace_bytes(S))
+    if work is None or work.numel() < nb:
+        work = torch.empty(max(nb, 1), dtype=torch.uint8, device=Y.device)
+    check(lib().fil_rpy_wall_apply(S, _ptr(Y), _ptr(F), _ptr(T), float(a), float(eta), _ptr(V), _ptr(W), _ptr(work),
+                                   work.numel(), _stream()))
     return V, W
 
 
@@ -202,6 +220,10 @@ class Sim:
             return
         a = np.ascontiguousarray(np.asarray(F, dtype=np.float64).reshape(self.S, 3))
         check(lib().fil_set_external_forces(self._h, a.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_wall(self):
+        """No-slip plane wall at z = 0 (wall-bounded RPY mobility); before the first step."""
+        check(lib().fil_set_wall(self._h))
 
     def set_periodic_fcm(self, box, grid, cut=7.5):
         """Periodic box of lengths box [3] with the force-coupling-method mobility on a grid

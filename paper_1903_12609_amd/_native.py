@@ -76,6 +76,10 @@ def _declare(L):
         L.fil_set_suspension_params.argtypes = [_vp, _vp, _vp, _vp]
         L.fil_set_external_forces.argtypes = [_vp, _vp]
         L.fil_set_periodic_fcm.argtypes = [_vp, _vp, _vp, _d]
+        L.fil_set_wall.argtypes = [_vp]
+        L.fil_rpy_wall_workspace_bytes.argtypes = [_i64]
+        L.fil_rpy_wall_workspace_bytes.restype = _i64
+        L.fil_rpy_wall_apply.argtypes = [_i64, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp, _i64, _vp]
         L.fil_fcm_create.argtypes = [_vp, _vp, _d, _d, _d, _vp]
         L.fil_fcm_apply.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
         L.fil_fcm_destroy.argtypes = [_vp]

@@ -67,6 +67,9 @@ struct fil_sim {
     // force-coupling-method mobility of a periodic box (null: the unbounded RPY mobility);
     // its iterations run host-driven (the FFTs are not captured)
     fil_fcm* fcm = nullptr;
+    // the RPY mobility above a no-slip wall at z = 0 in place of the unbounded one
+    bool wall = false;
+    void* wall_work = nullptr;
     // Newton-Krylov workspace (allocated on first use): Krylov basis [(m+1)][6S], residuals
     // at the Newton point and a perturbed point, work vectors, P^{-1} diagonal, dot partials
     int kry_m = 0;
@@ -232,6 +235,10 @@ int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipE
     if (s->fcm) {
         if (e0) FIL_HIP_TRY(hipEventRecord(e0, s->st));
         TRY(fil_fcm_apply(s->fcm, s->S, s->Yc, s->F, s->T, s->V, s->W, s->st));
+        if (e1) FIL_HIP_TRY(hipEventRecord(e1, s->st));
+    } else if (s->wall) {
+        if (e0) FIL_HIP_TRY(hipEventRecord(e0, s->st));
+        TRY(rpy_wall_launch(s->S, s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->wall_work, s->st));
         if (e1) FIL_HIP_TRY(hipEventRecord(e1, s->st));
     } else if (s->batched) {
         TRY(rpy_batch_launch(s->bplan[c], s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->rpy_work[c], s->st, e0, e1,
@@ -850,6 +857,23 @@ int fil_set_periodic_fcm(fil_sim* s, const double* box, const int32_t* grid, dou
     s->fcm = f;
     for (int c = 0; c < 3; c++) s->d.per[c] = box[c];
     s->d.periodic = 1;
+    return FIL_OK;
+}
+
+int fil_set_wall(fil_sim* s) {
+    FIL_CHECK_ARG(s, "fil_set_wall: null sim");
+    FIL_CHECK_ARG(s->step == 0, "fil_set_wall: only before the first step");
+    FIL_CHECK_ARG(!s->wall, "fil_set_wall: the wall is already set");
+    FIL_CHECK_ARG(!s->fcm, "fil_set_wall: the suspension is in a periodic box");
+    FIL_CHECK_ARG(s->nsusp == 1, "fil_set_wall: one suspension per wall");
+    FIL_CHECK_ARG(s->p.prec == FIL_PREC_F64, "fil_set_wall: needs FIL_PREC_F64");
+    const int64_t nb = wall_workspace_bytes(s->S);
+    if (nb > 0) {
+        double* w = nullptr;
+        TRY(dalloc(s, &w, (size_t)(nb / (int64_t)sizeof(double))));
+        s->wall_work = w;
+    }
+    s->wall = true;
     return FIL_OK;
 }
 

@@ -55,6 +55,10 @@ struct SimDev {
 // tt: device pointer to the time t^{j+1} of the step
 int state_forces_launch(const SimDev& d, const double* X, const double* qj, const double* tt, const int32_t* active,
                         double* Yc, double* qc, double* F, double* T, double* box, hipStream_t st);
+// RPY mobility above the no-slip wall z = 0 (rpy_wall.hip); work of wall_workspace_bytes(S)
+int64_t wall_workspace_bytes(int64_t S);
+int rpy_wall_launch(int64_t S, const double* Y, const double* F, const double* T, double a, double eta, double* V,
+                    double* W, void* work, hipStream_t st);
 // adds the steric barrier into F and writes the mobility source records (precision prec)
 int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, const int32_t* active, double* F,
                        const double* T, int prec, void* pk, hipStream_t st);

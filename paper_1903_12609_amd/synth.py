@@ -211,15 +211,16 @@ def periodic_monolayer(M=256, N=15, box=MONOLAYER_BOX, grid=MONOLAYER_GRID, seed
                     np.concatenate(qs), params, extra=dict(T=T, box=tuple(box), grid=tuple(grid)))
 
 
-def active_array(nx=40, ny=25, N=32, spacing=20.0, seed=1003, tol=1e-6, kmax=100, steps_per_beat=100):
+def active_array(nx=40, ny=25, N=32, spacing=20.0, seed=1003, tol=1e-6, kmax=100, steps_per_beat=100, base_z=0.0):
     """Base-clamped filaments on a square lattice, initially straight along +z,
     driven by kappa_nu(s,t) = K0 sin(k s - omega t + phi) with K0 = 10.61/L,
-    k = 2 pi / L and (4 pi omega eta / K_B)^(1/4) L = 10 (Sec. 5.3 parameters)."""
+    k = 2 pi / L and (4 pi omega eta / K_B)^(1/4) L = 10 (Sec. 5.3 parameters).
+    The base segments sit at height base_z (above a wall at z = 0: base_z >= a)."""
     rng = np.random.default_rng(seed)
     L = N * DL
     M = nx * ny
     qz = _axis_angle_quat((0.0, 1.0, 0.0), -math.pi / 2)   # e_x -> e_z
-    base = np.array([[i * spacing, j * spacing, 0.0] for i in range(nx) for j in range(ny)])
+    base = np.array([[i * spacing, j * spacing, base_z] for i in range(nx) for j in range(ny)])
     Y = np.concatenate([b + np.outer(np.arange(N) * DL, [0, 0, 1.0]) for b in base])
     q = np.tile(qz, (M * N, 1))
     omega = 1e4 * KB / (4 * math.pi * ETA * L ** 4)
