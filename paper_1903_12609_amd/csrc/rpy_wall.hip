@@ -133,14 +133,15 @@ __global__ void __launch_bounds__(256) rpy_wall_sum_kernel(int64_t S, int K, con
     else W[(c - 3) * S + n] = s;
 }
 
-// source chunks: enough workgroups to fill 256 CUs several times over, chunks of at least
-// four tiles
+// source chunks: about 4096 single-wave workgroups (the kernel holds one wave per SIMD,
+// 1024 SIMDs), chunks of at least 16 sources, at most 256 chunks.  A chunk past the end
+// of the sources is empty and writes zeros.
 int wall_chunks(int64_t S) {
     const int64_t tb = ceil_div(S, (int64_t)kWallBlock);
-    int64_t K = ceil_div((int64_t)2048, tb);
-    const int64_t maxK = ceil_div(S, (int64_t)(4 * kWallBlock));
+    int64_t K = ceil_div((int64_t)4096, tb);
+    const int64_t maxK = ceil_div(S, (int64_t)16);
     if (K > maxK) K = maxK;
-    if (K > 64) K = 64;
+    if (K > 256) K = 256;
     return (int)(K < 1 ? 1 : K);
 }
 

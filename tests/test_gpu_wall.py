@@ -32,7 +32,7 @@ def test_wall_apply_matches_oracle(S, side):
 
 
 def test_wall_apply_sampled_targets_large():
-    """S = 4000 (64 source chunks): 40 sampled targets against the oracle's rows."""
+    """S = 4000 (66 source chunks): 40 sampled targets against the oracle's rows."""
     import paper_1903_12609_amd as fil
     S = 4000
     Y, F, T = _cloud(S, 31, 60.0)
