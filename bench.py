@@ -234,6 +234,55 @@ def fcm_apply_bench(reps=5):
     return out
 
 
+WALL_FLOP_PER_PAIR = 1740  # FP64 flops of one pair of the wall kernel (FMA = 2), from its instruction count
+
+
+def wall_mobility_bench(reps=5):
+    """The RPY mobility above a no-slip wall: applies at S = 2000, 16000, 32000 (lattices of
+    32-segment filaments standing on the wall, bases one segment spacing above it), and the
+    implicit steps of the paper's cilia-array size (6 x 6 clamped filaments of N = 20 at
+    spacing 20a, curvature-driven, dt = period/100) with the wall; without it the same
+    array's first step does not converge."""
+    import numpy as np
+    import torch
+    import paper_1903_12609_amd as fil
+    from paper_1903_12609_amd import synth
+    out = {"apply": []}
+    for S in (2000, 16000, 32000):
+        Y, F, T = synth.rpy_throughput_inputs(S)
+        Y = Y.copy()
+        Y[:, 2] += synth.DL
+        d = lambda x: torch.from_numpy(np.ascontiguousarray(x.T)).cuda()
+        Yd, Fd, Td = d(Y), d(F), d(T)
+        V, W = fil.rpy_wall_apply(Yd, Fd, Td)
+        ms = _time_applies(lambda: fil.rpy_wall_apply(Yd, Fd, Td, V=V, W=W), reps if S > 10000 else 20) * 1e3
+        tf = WALL_FLOP_PER_PAIR * float(S) ** 2 / (ms * 1e-3) / 1e12
+        out["apply"].append(dict(S=S, ms=ms, pairs_per_s=float(S) ** 2 / (ms * 1e-3), tflops=tf,
+                                 frac_of_peak=tf / PEAK_FP64_TFLOPS))
+        log("wall apply", out["apply"][-1])
+    w = synth.active_array(nx=6, ny=6, N=20, spacing=20.0, seed=1003, base_z=synth.DL)
+    res = {}
+    for wall in (True, False):
+        sim = fil.Sim(w.fil_off, w.Y, w.q, w.params, graph=GRAPH_ITERS)
+        if wall:
+            sim.set_wall()
+        its, t0, ok = [], time.perf_counter(), True
+        for _ in range(10):
+            r = sim.step(raise_on_fail=False)
+            rep = r[1][0] if isinstance(r, tuple) else r[0]
+            its.append(rep["iters"])
+            if not rep["converged"]:
+                ok = False
+                break
+        torch.cuda.synchronize()
+        res["wall" if wall else "unbounded"] = dict(converged=ok, iters=its,
+                                                    ms_per_step=(time.perf_counter() - t0) / len(its) * 1e3)
+        sim.close()
+        log("cilia-size array", res)
+    out["array_6x6x20_steps"] = res
+    return out
+
+
 def traffic_per_launch():
     """HBM bytes per launch of the FP64 pair kernel from the committed rocprofv3
     counter summary, or None when the kernel source changed since it was taken."""
@@ -337,6 +386,7 @@ def main():
         res["rpy_apply_batched"] = rpy_batched()
     if not args.no_sweep:
         res["fcm_apply"] = fcm_apply_bench()
+        res["wall_mobility"] = wall_mobility_bench()
     if not args.no_solvers:
         res["solver_comparison"] = solver_comparison(w)
         res["fcm_monolayer_solvers"] = fcm_monolayer_steps()
