@@ -234,7 +234,7 @@ def fcm_apply_bench(reps=5):
     return out
 
 
-WALL_FLOP_PER_PAIR = 1740  # FP64 flops of one pair of the wall kernel (FMA = 2), from its instruction count
+WALL_FLOP_PER_PAIR = 1640  # FP64 flops of one pair of the wall kernel (FMA = 2), from its instruction count
 
 
 def wall_mobility_bench(reps=5):

@@ -24,6 +24,7 @@ import sympy as sp
 from sympy.printing.c import C99CodePrinter
 
 R1, R2, R3, h, a = sp.symbols("R1 R2 R3 h a", real=True)
+ir = sp.Symbol("ir", positive=True)  # 1 / |R|
 Rv = [R1, R2, R3]
 Rn = sp.sqrt(R1 ** 2 + R2 ** 2 + R3 ** 2)
 
@@ -98,11 +99,16 @@ def main():
                for (jj, m, n), c2 in EPS.items() if jj == j) / 4 for j in range(3)] for i in range(3)]
     blocks = {"tt": tt, "tr": tr, "rt": rt, "rr": rr}
     names, exprs = [], []
+    rho2 = R1 ** 2 + R2 ** 2 + R3 ** 2
     for b, M in blocks.items():
         for i in range(3):
             for j in range(3):
                 names.append("%s[%d][%d]" % (b, i, j))
-                exprs.append(M[i][j])
+                # every power of |R| in terms of ir = 1/|R|: products instead of divisions
+                e = M[i][j].subs(rho2, 1 / ir ** 2)
+                left = [q for q in e.atoms(sp.Pow) if q.base.is_Add and q.base.has(R1) and q.exp.is_negative]
+                assert not left, "a negative power of |R| was left"
+                exprs.append(e)
     print("derived in %.1f s" % (time.time() - t0), flush=True)
     reps, red = sp.cse(exprs, symbols=sp.numbered_symbols("t"), optimizations="basic")
     print("cse in %.1f s: %d temporaries" % (time.time() - t0, len(reps)), flush=True)
@@ -117,11 +123,11 @@ def main():
     with open(out, "w") as f:
         f.write("// Generated by gen_wall_image.py: the image part of the Rotne-Prager-Blake mobility\n"
                 "// blocks times 8 pi eta, in the variables R = x - y* (y* the mirror image of the\n"
-                "// source) and h = source height; a the radius.  Do not edit.\n"
+                "// source), ir = 1/|R| and h = source height; a the radius.  Do not edit.\n"
                 "#pragma once\n\n"
                 "namespace fil {\n\n"
-                "__device__ __host__ inline void wall_image_blocks(double R1, double R2, double R3, double h, "
-                "double a,\n"
+                "__device__ __host__ inline void wall_image_blocks(double R1, double R2, double R3, double ir, "
+                "double h, double a,\n"
                 "                                                  double tt[3][3], double tr[3][3], "
                 "double rt[3][3], double rr[3][3]) {\n"
                 + body + "\n}\n\n}  // namespace fil\n")

@@ -23,28 +23,46 @@ struct WallArgs {
     double a, eta;
 };
 
+// per-launch constants of the free-space blocks
+struct FreeConst {
+    double a2, ia, c8, c16, c6a, c8a3, c16a2;
+};
+
+__device__ __forceinline__ FreeConst free_const(double a, double eta) {
+    FreeConst k;
+    k.a2 = a * a;
+    k.ia = 1.0 / a;
+    k.c8 = 1.0 / (8.0 * kPi * eta);
+    k.c16 = 0.5 * k.c8;
+    k.c6a = 1.0 / (6.0 * kPi * eta * a);
+    k.c8a3 = k.c8 * k.ia * k.ia * k.ia;
+    k.c16a2 = k.c16 * k.ia * k.ia;
+    return k;
+}
+
 // free-space RPY blocks of the pair with separation r = target - source (not the self pair)
-__device__ __forceinline__ void free_pair(double rx, double ry, double rz, double a, double eta, const double* Fm,
-                                          const double* Tm, double* v, double* w) {
+__device__ __forceinline__ void free_pair(double rx, double ry, double rz, double a, const FreeConst& k,
+                                          const double* Fm, const double* Tm, double* v, double* w) {
     const double d2 = rx * rx + ry * ry + rz * rz;
-    const double d = sqrt(d2);
-    const double id = 1.0 / d;
+    const double id = 1.0 / sqrt(d2);
+    const double d = d2 * id;
     const double hx = rx * id, hy = ry * id, hz = rz * id;
     double ctt_i, ctt_r, crr_i, crr_r, ctr;
     if (d >= 2.0 * a) {
-        const double c = 1.0 / (8.0 * kPi * eta * d);
-        ctt_i = c * (1.0 + 2.0 * a * a / (3.0 * d2));
-        ctt_r = c * (1.0 - 2.0 * a * a / d2);
-        crr_i = -1.0 / (16.0 * kPi * eta * d2 * d);
-        crr_r = 3.0 / (16.0 * kPi * eta * d2 * d);
-        ctr = 1.0 / (8.0 * kPi * eta * d2);
+        const double id2 = id * id;
+        const double c = k.c8 * id;
+        ctt_i = c * (1.0 + (2.0 / 3.0) * k.a2 * id2);
+        ctt_r = c * (1.0 - 2.0 * k.a2 * id2);
+        crr_i = -k.c16 * id2 * id;
+        crr_r = 3.0 * k.c16 * id2 * id;
+        ctr = k.c8 * id2;
     } else {
-        const double x = d / a;
-        ctt_i = (1.0 - 9.0 * x / 32.0) / (6.0 * kPi * eta * a);
-        ctt_r = (3.0 * x / 32.0) / (6.0 * kPi * eta * a);
-        crr_i = (1.0 - 27.0 * x / 32.0 + 5.0 * x * x * x / 64.0) / (8.0 * kPi * eta * a * a * a);
-        crr_r = (9.0 * x / 32.0 - 3.0 * x * x * x / 64.0) / (8.0 * kPi * eta * a * a * a);
-        ctr = (x - 3.0 * x * x / 8.0) / (16.0 * kPi * eta * a * a);
+        const double x = d * k.ia;
+        ctt_i = (1.0 - (9.0 / 32.0) * x) * k.c6a;
+        ctt_r = ((3.0 / 32.0) * x) * k.c6a;
+        crr_i = (1.0 - (27.0 / 32.0) * x + (5.0 / 64.0) * x * x * x) * k.c8a3;
+        crr_r = ((9.0 / 32.0) * x - (3.0 / 64.0) * x * x * x) * k.c8a3;
+        ctr = (x - 0.375 * x * x) * k.c16a2;
     }
     const double hF = hx * Fm[0] + hy * Fm[1] + hz * Fm[2];
     const double hT = hx * Tm[0] + hy * Tm[1] + hz * Tm[2];
@@ -70,6 +88,7 @@ __global__ void __launch_bounds__(kWallBlock) rpy_wall_kernel(WallArgs g, int64_
     const int64_t m1 = m0 + chunk < S ? m0 + chunk : S;
     double v[3] = {0, 0, 0}, w[3] = {0, 0, 0};
     double vi[3] = {0, 0, 0}, wi[3] = {0, 0, 0};  // image part, scaled by 1/(8 pi eta) at the end
+    const FreeConst kc = free_const(g.a, g.eta);
     for (int64_t t0 = m0; t0 < m1; t0 += kWallBlock) {
         __syncthreads();
         const int64_t m = t0 + threadIdx.x;
@@ -86,16 +105,16 @@ __global__ void __launch_bounds__(kWallBlock) rpy_wall_kernel(WallArgs g, int64_
             const double Tm[3] = {st[0][q], st[1][q], st[2][q]};
             const double y0 = sy[0][q], y1 = sy[1][q], y2 = sy[2][q];
             if (t0 + q == nn) {
-                const double ct = 1.0 / (6.0 * kPi * g.eta * g.a), cr = 1.0 / (8.0 * kPi * g.eta * g.a * g.a * g.a);
                 for (int c = 0; c < 3; c++) {
-                    v[c] += ct * Fm[c];
-                    w[c] += cr * Tm[c];
+                    v[c] += kc.c6a * Fm[c];
+                    w[c] += kc.c8a3 * Tm[c];
                 }
             } else {
-                free_pair(x0 - y0, x1 - y1, x2 - y2, g.a, g.eta, Fm, Tm, v, w);
+                free_pair(x0 - y0, x1 - y1, x2 - y2, g.a, kc, Fm, Tm, v, w);
             }
             double tt[3][3], tr[3][3], rt[3][3], rr[3][3];
-            wall_image_blocks(x0 - y0, x1 - y1, x2 + y2, y2, g.a, tt, tr, rt, rr);
+            const double Rx = x0 - y0, Ry = x1 - y1, Rz = x2 + y2;
+            wall_image_blocks(Rx, Ry, Rz, 1.0 / sqrt(Rx * Rx + Ry * Ry + Rz * Rz), y2, g.a, tt, tr, rt, rr);
             for (int i = 0; i < 3; i++) {
                 vi[i] += tt[i][0] * Fm[0] + tt[i][1] * Fm[1] + tt[i][2] * Fm[2] + tr[i][0] * Tm[0] + tr[i][1] * Tm[1] +
                          tr[i][2] * Tm[2];
@@ -105,11 +124,10 @@ __global__ void __launch_bounds__(kWallBlock) rpy_wall_kernel(WallArgs g, int64_
         }
     }
     if (!valid) return;
-    const double ci = 1.0 / (8.0 * kPi * g.eta);
     double out[6];
     for (int c = 0; c < 3; c++) {
-        out[c] = v[c] + ci * vi[c];
-        out[3 + c] = w[c] + ci * wi[c];
+        out[c] = v[c] + kc.c8 * vi[c];
+        out[3 + c] = w[c] + kc.c8 * wi[c];
     }
     if (part) {
         double* p = part + (int64_t)blockIdx.y * 6 * S;
