@@ -329,6 +329,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-solvers", action="store_true", help="skip the Broyden vs Newton-Krylov comparison")
     ap.add_argument("--fcm-only", action="store_true", help="only the FCM applies (for profiling)")
+    ap.add_argument("--wall-only", action="store_true", help="only the wall-bounded mobility (for profiling)")
     ap.add_argument("--fcm-steps-only", action="store_true",
                     help="only the solver comparison on the periodic FCM monolayer (for profiling)")
     args = ap.parse_args()
@@ -340,6 +341,9 @@ def main():
     from paper_1903_12609_amd import synth
     if args.fcm_only:
         print(json.dumps({"fcm_apply": fcm_apply_bench()}))
+        return
+    if args.wall_only:
+        print(json.dumps({"wall_mobility": wall_mobility_bench()}))
         return
     if args.fcm_steps_only:
         print(json.dumps({"fcm_monolayer_solvers": fcm_monolayer_steps()}))
