@@ -57,7 +57,7 @@ class Params(C.Structure):
         ("dt", C.c_double), ("tol", C.c_double), ("kmax", C.c_int64),
         ("K0", C.c_double), ("kw", C.c_double), ("omega", C.c_double), ("phase", _dp),
         ("tether", _i32p), ("base", _dp), ("nthreads", C.c_int64), ("drag_only", C.c_int64),
-        ("fext", _dp), ("Lper", _dp), ("mobility", C.c_void_p), ("mob_ctx", C.c_void_p),
+        ("fext", _dp), ("text", _dp), ("Lper", _dp), ("mobility", C.c_void_p), ("mob_ctx", C.c_void_p),
     ]
 
 
@@ -223,8 +223,9 @@ class Sim:
     ``fil_off`` [M+1] segment offsets; ``Y0`` [S,3] and ``q0`` [S,4] the initial
     configuration (from the shared synthetic generators).  Keyword parameters
     mirror the method's: a, eta, dL, KB, KT, chi, FS, grav, dt, tol, kmax, K0,
-    kw, omega, phase [M], tether [M] (0/1), base [M,3], fext [S,3] (a further external
-    force on each segment), nthreads; periodic = dict(box [3], grid [3], cut, omega) puts the
+    kw, omega, phase [M], tether [M] (0 free, 1 clamped, 2 pinned: base position held,
+    rotation free), base [M,3], fext [S,3] and text [S,3] (further external forces and
+    torques on each segment), nthreads; periodic = dict(box [3], grid [3], cut, omega) puts the
     suspension in a periodic box with the force-coupling-method mobility (Sec. 2.7.2) and
     nearest-image steric forces; mobility = callable (Y, F, T) -> (V, W) over [S, 3] arrays
     replaces the RPY apply otherwise.
@@ -271,6 +272,11 @@ class Sim:
             fx = _f64(fx, (S, 3))
             self._keep.append(fx)
             P.fext = _p(fx)
+        tx = kw.get("text")
+        if tx is not None:
+            tx = _f64(tx, (S, 3))
+            self._keep.append(tx)
+            P.text = _p(tx)
         P.nthreads = kw.get("nthreads", 0)
         P.drag_only = int(kw.get("drag_only", 0))
         per = kw.get("periodic")

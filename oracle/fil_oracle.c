@@ -15,7 +15,9 @@
  *   X_f = [ Y_1 (3) | u_1 .. u_N (3N) | Lambda_{3/2} .. Lambda_{N-1/2} (3(N-1)) ]
  * and the global X concatenates filaments, filament f starting at 6*fil_off[f].
  * A clamped (tethered) filament stores the tether multipliers lambda_1,
- * lambda_2 in the Y_1 and u_1 slots (Sec. 5.2.1, tethering constraints).
+ * lambda_2 in the Y_1 and u_1 slots (Sec. 5.2.1, tethering constraints).  A pinned
+ * filament (base position held, its rotation free, as the cilia bases of Sec. 5.3)
+ * stores lambda_1 in the Y_1 slot and keeps u_1 as an unknown.
  *
  * Parity: every function below is pinned by a CPU test (tests/test_oracle_*.py)
  * except where its comment says "parity unpinned".
@@ -350,11 +352,12 @@ typedef struct {
     /* preferred curvature kappa_nu(s,t) = K0 sin(kw s - omega t + phase[f]) (Sec. 5.3) */
     double K0, kw, omega;
     const double* phase;     /* [M] or NULL for no preferred curvature */
-    const int32_t* tether;   /* [M], 1 = base clamped (Sec. 5.2.1); NULL: all free */
+    const int32_t* tether;   /* [M], 1 = base clamped (Sec. 5.2.1), 2 = base pinned; NULL: all free */
     const double* base;      /* [M][3] clamped base positions */
     int64_t nthreads;        /* OpenMP threads for the RPY target loop (0: default) */
     int64_t drag_only;       /* 1: diagonal drag mobility, no steric, no gravity: the f0 of Sec. 3.2.1 */
     const double* fext;      /* [S][3] further external force on each segment (Sec. 2.5), or NULL */
+    const double* text;      /* [S][3] further external torque on each segment (Sec. 2.5), or NULL */
     /* periodic box (Sec. 2.7.2): its lengths [3] for the steric barrier's nearest images
      * (NULL: unbounded), and a mobility (V, W) = M(Y) (F, T) over [S][3] arrays that takes
      * the place of the unbounded RPY apply (NULL: RPY) */
@@ -382,6 +385,8 @@ typedef struct {
 
 static int64_t total_segments(const or_params* P) { return P->fil_off[P->M]; }
 static int is_tethered(const or_params* P, int64_t f) { return P->tether && P->tether[f]; }
+/* the base orientation is held too (u_1 = 0, lambda_2 in its slot) */
+static int is_clamped(const or_params* P, int64_t f) { return P->tether && P->tether[f] == 1; }
 
 /* BDF coefficients: y - a1 y^j - a2 y^{j-1} - b dt v = 0,  u - g u^j - b dt dexpinv(Omega) = 0.
  * The first step is BDF1 (reading R7), every later one BDF2 (Sec. 2.9.3). */
@@ -406,7 +411,7 @@ void or_reconstruct(const or_params* P, const double* qj, const double* X, doubl
         const double* Xf = X + 6 * s0;
         for (int64_t n = 0; n < N; n++) {
             double u[3] = {Xf[3 + 3 * n], Xf[4 + 3 * n], Xf[5 + 3 * n]}, e[4];
-            if (n == 0 && is_tethered(P, f)) { u[0] = u[1] = u[2] = 0; }
+            if (n == 0 && is_clamped(P, f)) { u[0] = u[1] = u[2] = 0; }
             or_qexp(u, e);
             or_qmul(e, qj + 4 * (s0 + n), qo + 4 * (s0 + n));
         }
@@ -447,10 +452,11 @@ void or_forces(const or_params* P, const double* Y, const double* q, const doubl
         }
         or_internal_forces(N, q + 4 * s0, Lam, kap, P->dL, P->KB, P->KT, F + 3 * s0, T + 3 * s0);
         if (is_tethered(P, f)) {
-            /* clamped base with u_1^j = 0: F^C_1 += lambda_1, T^C_1 += lambda_2 (Sec. 5.2.1) */
+            /* tethered base, Y_1 held: F^C_1 += lambda_1; clamped (u_1^j = 0) also
+             * T^C_1 += lambda_2 (Sec. 5.2.1) */
             for (int i = 0; i < 3; i++) {
                 F[3 * s0 + i] += X[6 * s0 + i];
-                T[3 * s0 + i] += X[6 * s0 + 3 + i];
+                if (is_clamped(P, f)) T[3 * s0 + i] += X[6 * s0 + 3 + i];
             }
         }
         free(Lam);
@@ -458,6 +464,8 @@ void or_forces(const or_params* P, const double* Y, const double* q, const doubl
     }
     for (int64_t n = 0; n < S; n++)
         for (int i = 0; i < 3; i++) F[3 * n + i] += P->grav[i] + (P->fext ? P->fext[3 * n + i] : 0.0);
+    if (P->text)
+        for (int64_t n = 0; n < 3 * S; n++) T[n] += P->text[n];
     if (P->FS != 0.0) {
         int64_t* seg_fil = (int64_t*)malloc(S * sizeof(int64_t));
         for (int64_t f = 0; f < P->M; f++)
@@ -488,7 +496,7 @@ double or_residual(const or_params* P, const or_state* St, const double* X, doub
     if (P->drag_only) {
         /* f0: M replaced by diag(M) and no steric or external forces (Sec. 3.2.1) */
         or_params P0 = *P;
-        P0.FS = 0; P0.grav[0] = P0.grav[1] = P0.grav[2] = 0; P0.fext = NULL;
+        P0.FS = 0; P0.grav[0] = P0.grav[1] = P0.grav[2] = 0; P0.fext = NULL; P0.text = NULL;
         or_forces(&P0, Y, q, X, tt, F, T);
         for (int64_t i = 0; i < 3 * S; i++) {
             V[i] = F[i] / (6.0 * PI * P->eta * P->a);
@@ -512,7 +520,7 @@ double or_residual(const or_params* P, const or_state* St, const double* X, doub
         for (int64_t n = 0; n < N; n++) {
             double u[3] = {Xf[3 + 3 * n], Xf[4 + 3 * n], Xf[5 + 3 * n]};
             double uj[3] = {Xj[3 + 3 * n], Xj[4 + 3 * n], Xj[5 + 3 * n]}, d[3];
-            if (n == 0 && is_tethered(P, f)) { u[0] = u[1] = u[2] = 0; uj[0] = uj[1] = uj[2] = 0; }
+            if (n == 0 && is_clamped(P, f)) { u[0] = u[1] = u[2] = 0; uj[0] = uj[1] = uj[2] = 0; }
             or_dexpinv(u, W + 3 * (s0 + n), d);
             for (int i = 0; i < 3; i++) ff[3 + 3 * n + i] = u[i] - g * uj[i] - b * P->dt * d[i];
         }
@@ -559,12 +567,13 @@ static void dM_du(const double t0[3], const double m0[3], const double n0[3], co
 /* Explicit block-diagonal approximate Jacobian J0 of one filament (Sec. 3.2.2,
  * Appendix B.2), evaluated at the configuration (q, Lambda, u) of X.  J is
  * (6N) x (6N) row-major.  cT = b dt/(6 pi eta a), cR = b dt/(8 pi eta a^3).
- * Clamped filaments replace the Y_1, u_1 columns by lambda_1, lambda_2 (reading R11).
+ * Clamped filaments replace the Y_1, u_1 columns by lambda_1, lambda_2 (reading R11);
+ * pinned ones only the Y_1 column, by lambda_1.
  * Reading R12: the torque T_m in the J22 diagonal is the internal torque T^C + T^E. */
 void or_j0_filament(const or_params* P, int64_t f, int64_t step, const double* q, const double* X, double tt,
                     double* J) {
     int64_t s0 = P->fil_off[f], N = P->fil_off[f + 1] - s0, n6 = 6 * N;
-    int teth = is_tethered(P, f);
+    int teth = is_tethered(P, f), clamp = is_clamped(P, f);
     double a1, a2, b, g;
     bdf_coeffs(step, &a1, &a2, &b, &g);
     double cT = b * P->dt / (6.0 * PI * P->eta * P->a);
@@ -601,7 +610,7 @@ void or_j0_filament(const or_params* P, int64_t f, int64_t step, const double* q
         SET(ROW_F3(m), IDX_L(m - 1), I3, cT);
         if (m + 1 < N) { SET(ROW_F3(m), IDX_L(m), I3, -cT); }
         for (int64_t n = 0; n <= m; n++) {
-            if (n == 0 && teth) continue;
+            if (n == 0 && clamp) continue;
             double w = (n == 0 || n == m) ? 1.0 : 2.0;
             double A[9];
             rskew(t + 3 * n, A);
@@ -611,7 +620,7 @@ void or_j0_filament(const or_params* P, int64_t f, int64_t step, const double* q
     /* f^2 rows */
     for (int64_t m = 0; m < N; m++) {
         double um[3] = {Xf[IDX_U(m)], Xf[IDX_U(m) + 1], Xf[IDX_U(m) + 2]};
-        if (m == 0 && teth) { um[0] = um[1] = um[2] = 0; }
+        if (m == 0 && clamp) { um[0] = um[1] = um[2] = 0; }
         double U[9], U2[9], Tay[9];
         skew(um, U);
         mat_mul(U, U, U2);
@@ -639,9 +648,9 @@ void or_j0_filament(const or_params* P, int64_t f, int64_t step, const double* q
         }
         /* off-diagonal u columns */
         if (m + 1 < N) { mat_mul(Tay, dMp_up, A); SET(r, IDX_U(m + 1), A, -cR); }
-        if (m >= 1 && !(m == 1 && teth)) { mat_mul(Tay, dMm_uprev, A); SET(r, IDX_U(m - 1), A, cR); }
+        if (m >= 1 && !(m == 1 && clamp)) { mat_mul(Tay, dMm_uprev, A); SET(r, IDX_U(m - 1), A, cR); }
         /* diagonal block */
-        if (m == 0 && teth) {
+        if (m == 0 && clamp) {
             SET(r, IDX_U(0), I3, -cR); /* lambda_2 column */
         } else {
             double ls[3] = {0, 0, 0};
@@ -718,7 +727,7 @@ void or_initial_guess(const or_params* P, const or_state* St, double* X0) {
             continue;
         }
         for (int64_t i = 0; i < 6 * N; i++) {
-            int is_u = (i >= 3 && i < 3 + 3 * N) && !(teth && i < 6);
+            int is_u = (i >= 3 && i < 3 + 3 * N) && !(is_clamped(P, f) && i < 6);
             if (is_u) x[i] = xj[i];
             else if (i < 3 && !teth) x[i] = 2.0 * St->Y[3 * s0 + i] - St->Yprev[3 * s0 + i];
             else x[i] = (St->step >= 2) ? 2.0 * xj[i] - xp[i] : xj[i];

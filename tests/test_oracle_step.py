@@ -183,3 +183,41 @@ def test_second_order_in_time():
     errs = [np.abs(run(h, 1e-11) - ref).max() for h in (1 / 8, 1 / 16, 1 / 32)]
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5, errs
+
+
+def test_j0_pinned_equals_drag_jacobian_at_straight_state():
+    """Pinned base (position held, rotation free, as the cilia bases of Sec. 5.3):
+    lambda_1 in the Y_1 slot, u_1 an ordinary unknown."""
+    N = 5
+    q0 = np.array([math.cos(-math.pi / 4), 0, math.sin(-math.pi / 4), 0])
+    q = np.tile(q0, (N, 1))
+    Y = synth.chain(np.array([1.0, 2.0, 0.0]), q)
+    sim = oracle.Sim([0, N], Y, q, dt=2.0, drag_only=1, tether=[2], base=Y[:1])
+    sim.St.step = 2
+    rng = np.random.default_rng(7)
+    X = np.zeros(6 * N)
+    X[:3] = rng.standard_normal(3)
+    X[3 + 3 * N:] = rng.standard_normal(3 * (N - 1))
+    J0 = sim.j0_filament(0, X)
+    Jfd = fd_jacobian(lambda x: sim.residual(x)[0], X)
+    assert np.allclose(J0, Jfd, rtol=0, atol=1e-7 * np.abs(Jfd).max())
+
+
+def test_pinned_filament_hangs_below_its_pin():
+    """A pinned filament started 60 degrees from the vertical swings down under gravity
+    and comes to rest hanging straight below the pin (the base never moves)."""
+    N = 8
+    th = math.radians(60.0)
+    # tangent e_x rotated to (sin th, 0, -cos th): about y by -(pi/2 - th)
+    q0 = np.array([math.cos(-(math.pi / 2 - th) / 2), 0, math.sin(-(math.pi / 2 - th) / 2), 0])
+    q = np.tile(q0, (N, 1))
+    Y = synth.chain(np.array([0.0, 0.0, 50.0]), q)
+    params, T = synth.sedimentation_params(N, 10.0, 1.0, 1e-10, 200, steric=False)
+    sim = oracle.Sim([0, N], Y, q, tether=[2], base=Y[:1], **params)
+    for _ in range(60):
+        rc, rep = sim.step()
+        assert rc == 0
+    t = np.array([oracle.qrot(qq)[:, 0] for qq in sim.q])
+    assert np.abs(sim.Y[0] - Y[0]).max() == 0.0
+    assert np.abs(t - np.array([0.0, 0.0, -1.0])).max() <= 1e-3
+    assert abs(sim.Y[-1, 2] - (50.0 - (N - 1) * params["dL"])) <= 1e-2
