@@ -14,7 +14,8 @@
  *     [ Y_1 (3) | u_1 .. u_N (3N) | Lambda_{3/2} .. Lambda_{N-1/2} (3(N-1)) ]
  *     (reduced system of Sec. 2.9.3), filament f starting at 6*fil_off[f].
  *     A base-clamped filament keeps its tether multipliers lambda_1, lambda_2
- *     in the Y_1 and u_1 slots (tethering constraints of Sec. 5.2.1).
+ *     in the Y_1 and u_1 slots (tethering constraints of Sec. 5.2.1); a pinned one
+ *     keeps lambda_1 in the Y_1 slot and its u_1.
  *   - `stream` is a hipStream_t (NULL = default stream).  Calls only enqueue
  *     work on it; nothing is synchronised unless the entry point says so.
  *   - Every function returns a fil_status.  Argument errors are detected on the
@@ -174,7 +175,9 @@ typedef struct fil_sim fil_sim;
  *   fil_seg_off  int64[M+1]       segments of filament f (M = susp_fil_off[nsusp])
  *   Y0  double[S][3], q0 double[S][4]   initial positions (constraints met) and unit quaternions
  *   phase  double[M] or NULL      per-filament phase of the preferred curvature
- *   tether int32[M] or NULL       1 = base clamped at its initial Y_1 and q_1
+ *   tether int32[M] or NULL       1 = base clamped at its initial Y_1 and q_1; 2 = base
+ *                                 pinned at its initial Y_1, its rotation free (the cilia
+ *                                 bases of Sec. 5.3): lambda_1 in the Y_1 slot, u_1 kept
  * The library allocates all device state and workspace here (FIL_ENOMEM on failure). */
 int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, const int64_t* fil_seg_off,
                const double* Y0, const double* q0, const double* phase, const int32_t* tether, fil_sim** out);
@@ -207,6 +210,22 @@ int fil_set_external_forces(fil_sim* sim, const double* Fext);
  * The mobility timing of fil_set_timing then times whole FCM applies.  FIL_EINVAL on a
  * bad argument, and fil_fcm_create's errors. */
 int fil_set_periodic_fcm(fil_sim* sim, const double* box, const int32_t* grid, double cut);
+
+/* Geometric-switch driving torque of model cilia (Sec. 5.3) on every pinned filament
+ * (tether 2): a torque about the unit axis drives the base until the angle theta between
+ * the unit wall normal and the base tangent (signed about the axis, atan2 form) reaches
+ * +theta_max or -theta_max, where it reverses; its magnitude is tau_pos while driving
+ * towards +theta_max and tau_neg towards -theta_max.  At a switch the torque passes to
+ * the new value along a logistic curve over n_transition steps (0: at once).  Decided at
+ * the start of each step (and of each Newton-Krylov step) from the committed base
+ * orientation; a step that fails keeps the switch state it started with advanced.  All
+ * filaments start driving towards +theta_max at tau_pos.  axis, normal: HOST double[3],
+ * orthogonal unit vectors.  Only before the first step.  FIL_EINVAL on a bad argument.
+ * fil_read_switch copies each filament's direction (+1 / -1) into HOST int32[M]
+ * (synchronising). */
+int fil_set_geometric_switch(fil_sim* sim, const double* axis, const double* normal, double theta_max,
+                             double tau_pos, double tau_neg, int n_transition);
+int fil_read_switch(fil_sim* sim, int32_t* dir);
 
 /* The suspension above a no-slip plane wall at z = 0: every residual evaluation applies
  * the wall-bounded RPY mobility of fil_rpy_wall_apply in place of the unbounded one (the

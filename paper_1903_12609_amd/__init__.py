@@ -221,6 +221,24 @@ class Sim:
         a = np.ascontiguousarray(np.asarray(F, dtype=np.float64).reshape(self.S, 3))
         check(lib().fil_set_external_forces(self._h, a.ctypes.data_as(ctypes.c_void_p)))
 
+    def set_geometric_switch(self, axis, normal, theta_max, tau_pos, tau_neg, n_transition=10):
+        """Geometric-switch base torques of the pinned filaments (Sec. 5.3); before the first step."""
+        import ctypes
+        import numpy as np
+        ax = np.ascontiguousarray(np.asarray(axis, dtype=np.float64).reshape(3))
+        nm = np.ascontiguousarray(np.asarray(normal, dtype=np.float64).reshape(3))
+        check(lib().fil_set_geometric_switch(self._h, ax.ctypes.data_as(ctypes.c_void_p),
+                                             nm.ctypes.data_as(ctypes.c_void_p), float(theta_max), float(tau_pos),
+                                             float(tau_neg), int(n_transition)))
+
+    def read_switch(self):
+        """Switch direction (+1 / -1) of every filament, int32 [M] (synchronising)."""
+        import ctypes
+        import numpy as np
+        out = np.zeros(self.M, dtype=np.int32)
+        check(lib().fil_read_switch(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
     def set_wall(self):
         """No-slip plane wall at z = 0 (wall-bounded RPY mobility); before the first step."""
         check(lib().fil_set_wall(self._h))

@@ -67,6 +67,10 @@ struct fil_sim {
     // force-coupling-method mobility of a periodic box (null: the unbounded RPY mobility);
     // its iterations run host-driven (the FFTs are not captured)
     fil_fcm* fcm = nullptr;
+    // geometric-switch base torques of pinned filaments (their state on the device)
+    bool sw = false;
+    SwitchArgs swa{};
+    double* text_d = nullptr;  // [3][S] external torques the switch writes
     // the RPY mobility above a no-slip wall at z = 0 in place of the unbounded one
     bool wall = false;
     void* wall_work = nullptr;
@@ -566,6 +570,9 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     for (int64_t i = 0; i < nsusp; i++)
         FIL_CHECK_ARG(susp_fil_off[i + 1] > susp_fil_off[i], "fil_create: every suspension needs >= 1 filament");
     const int64_t M = susp_fil_off[nsusp];
+    if (tether)
+        for (int64_t f = 0; f < M; f++)
+            FIL_CHECK_ARG(tether[f] >= 0 && tether[f] <= 2, "fil_create: tether values are 0, 1 (clamped) or 2 (pinned)");
     FIL_CHECK_ARG(fil_seg_off[0] == 0, "fil_create: fil_seg_off[0] must be 0");
     for (int64_t f = 0; f < M; f++) {
         const int64_t N = fil_seg_off[f + 1] - fil_seg_off[f];
@@ -591,7 +598,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     susp_seg_off[nsusp] = S;
     for (int64_t f = 0; f < M; f++) {
         for (int64_t x = seg_off[f]; x < seg_off[f + 1]; x++) seg_fil[x] = (int32_t)f;
-        if (tether) teth[f] = tether[f] ? 1 : 0;
+        if (tether) teth[f] = tether[f];
     }
     s->seg_uniform = (int)(seg_off[1] - seg_off[0]);
     for (int64_t f = 0; f < M; f++)
@@ -860,6 +867,57 @@ int fil_set_periodic_fcm(fil_sim* s, const double* box, const int32_t* grid, dou
     return FIL_OK;
 }
 
+int fil_set_geometric_switch(fil_sim* s, const double* axis, const double* normal, double theta_max,
+                             double tau_pos, double tau_neg, int n_transition) {
+    FIL_CHECK_ARG(s, "fil_set_geometric_switch: null sim");
+    FIL_CHECK_ARG(s->step == 0, "fil_set_geometric_switch: only before the first step");
+    FIL_CHECK_ARG(!s->sw, "fil_set_geometric_switch: already set");
+    FIL_CHECK_ARG(axis && normal, "fil_set_geometric_switch: null axis or normal");
+    FIL_CHECK_ARG(std::isfinite(theta_max) && theta_max > 0 && theta_max < kPi,
+                  "fil_set_geometric_switch: theta_max in (0, pi)");
+    FIL_CHECK_ARG(std::isfinite(tau_pos) && std::isfinite(tau_neg) && tau_pos >= 0 && tau_neg >= 0,
+                  "fil_set_geometric_switch: torque magnitudes >= 0");
+    FIL_CHECK_ARG(n_transition >= 0 && n_transition <= 100000, "fil_set_geometric_switch: n_transition in [0, 1e5]");
+    double na = 0, nn = 0, an = 0;
+    for (int c = 0; c < 3; c++) {
+        na += axis[c] * axis[c];
+        nn += normal[c] * normal[c];
+        an += axis[c] * normal[c];
+    }
+    FIL_CHECK_ARG(std::fabs(na - 1.0) < 1e-12 && std::fabs(nn - 1.0) < 1e-12 && std::fabs(an) < 1e-12,
+                  "fil_set_geometric_switch: axis and normal must be orthogonal unit vectors");
+    const int64_t M = s->M;
+    TRY(dalloc(s, &s->text_d, (size_t)(3 * s->S)));
+    TRY(dalloc(s, &s->swa.dir, (size_t)M));
+    TRY(dalloc(s, &s->swa.age, (size_t)M));
+    TRY(dalloc(s, &s->swa.tau0, (size_t)M));
+    std::vector<int32_t> dir(M, 1), age(M, n_transition);
+    std::vector<double> tau0(M, tau_pos);
+    TRY(upload(s->swa.dir, dir));
+    TRY(upload(s->swa.age, age));
+    TRY(upload(s->swa.tau0, tau0));
+    FIL_HIP_TRY(hipMemset(s->text_d, 0, 3 * s->S * sizeof(double)));
+    for (int c = 0; c < 3; c++) {
+        s->swa.axis[c] = axis[c];
+        s->swa.normal[c] = normal[c];
+    }
+    s->swa.theta_max = theta_max;
+    s->swa.tau_pos = tau_pos;
+    s->swa.tau_neg = tau_neg;
+    s->swa.n_tr = n_transition;
+    s->d.text = s->text_d;
+    s->sw = true;
+    return FIL_OK;
+}
+
+int fil_read_switch(fil_sim* s, int32_t* dir) {
+    FIL_CHECK_ARG(s && dir, "fil_read_switch: null argument");
+    FIL_CHECK_ARG(s->sw, "fil_read_switch: no geometric switch set");
+    FIL_HIP_TRY(hipStreamSynchronize(s->st));
+    FIL_HIP_TRY(hipMemcpy(dir, s->swa.dir, s->M * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return FIL_OK;
+}
+
 int fil_set_wall(fil_sim* s) {
     FIL_CHECK_ARG(s, "fil_set_wall: null sim");
     FIL_CHECK_ARG(s->step == 0, "fil_set_wall: only before the first step");
@@ -886,6 +944,7 @@ int fil_bdf2_step(fil_sim* s, fil_step_report* report) {
         TRY(collect_timing(s));
     }
     for (int64_t i = 0; i < ns; i++) s->active_h[i] = 1;
+    if (s->sw) TRY(switch_torque_launch(s->d, s->swa, s->qj, s->text_d, s->st));
     // one kernel starts the step: first iterate and its copy, every suspension running,
     // the device log cleared, the time t^{j+1}
     TRY(initial_guess_launch(s->d, s->step, s->Yj, s->Yjm1, s->Xj, s->Xjm1, s->X, s->X0p, s->active_d, s->log_d,
@@ -1316,6 +1375,7 @@ int eval_f0(fil_sim* s, const double* X, double* fout) {
     SimDev d0 = s->d;
     d0.spar = s->kry_spar0;
     d0.fext = nullptr;
+    d0.text = nullptr;
     TRY(state_forces_launch(d0, X, s->qj, s->time_d, s->active_d, s->Yc, s->qc, s->F, s->T, s->box, s->st));
     TRY(diag_mobility_launch(d0, s->F, s->T, s->V, s->W, s->st));
     unsigned long long* rb = s->kry_rb + 2 * s->kry_rbi * s->nsusp;
@@ -1341,6 +1401,7 @@ int kry_begin(fil_sim* s, const char* who, int precond, double krylov_tol, doubl
     FIL_CHECK_ARG(krylov_max >= 1 && krylov_max <= 100000, std::string(who) + ": krylov_max in [1, 100000]");
     const int64_t n6 = 6 * s->S;
     TRY(kry_ensure(s, std::min(krylov_max, 100)));
+    if (s->sw) TRY(switch_torque_launch(s->d, s->swa, s->qj, s->text_d, s->st));
     s->bc = coefs(s->step);
     s->cur = 0;
     s->active_h[0] = 1;

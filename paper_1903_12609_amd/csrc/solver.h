@@ -38,6 +38,7 @@ struct SimDev {
     int max_dots;                  // dot products per Broyden update at most (kmax + 2)
     const double* spar;            // [nsusp][5] per suspension: dt, gravity force (3), steric strength F^S
     const double* fext;            // [3][S] further external force per segment, or null
+    const double* text;            // [3][S] further external torque per segment, or null
     // periodic box lengths of the steric pass (minimum-image distances); periodic == 0:
     // unbounded
     double per[3];
@@ -55,6 +56,19 @@ struct SimDev {
 // tt: device pointer to the time t^{j+1} of the step
 int state_forces_launch(const SimDev& d, const double* X, const double* qj, const double* tt, const int32_t* active,
                         double* Yc, double* qc, double* F, double* T, double* box, hipStream_t st);
+// geometric-switch base torques of pinned filaments (cilia.hip): per filament the switch
+// direction and the steps since the last switch, updated from the committed base
+// orientations qj at the start of a step; writes the base torques into text
+struct SwitchArgs {
+    double axis[3], normal[3];
+    double theta_max, tau_pos, tau_neg;
+    int n_tr;
+    int32_t* dir;   // [M] +1 / -1
+    int32_t* age;   // [M] steps since the last switch
+    double* tau0;   // [M] signed torque before the last switch
+};
+int switch_torque_launch(const SimDev& d, const SwitchArgs& a, const double* qj, double* text, hipStream_t st);
+
 // RPY mobility above the no-slip wall z = 0 (rpy_wall.hip); work of wall_workspace_bytes(S)
 int64_t wall_workspace_bytes(int64_t S);
 int rpy_wall_launch(int64_t S, const double* Y, const double* F, const double* T, double a, double eta, double* V,

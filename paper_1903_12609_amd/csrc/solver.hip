@@ -152,7 +152,7 @@ __device__ void filament_state(const SimDev& d, int64_t f, const double* Xf, Q4 
     const bool seg = n < N;
     if (seg) {
         V3 u = ldx(Xf, 3 + 3 * n);
-        if (teth && n == 0) u = v3(0, 0, 0);
+        if (teth == 1 && n == 0) u = v3(0, 0, 0);  // clamped base: u_1 = 0
         const Q4 q = qmul(qexp(u), qjn);
         stq(qc, S, s0 + n, q);
         sq[n][0] = q.w; sq[n][1] = q.x; sq[n][2] = q.y; sq[n][3] = q.z;
@@ -209,9 +209,10 @@ __device__ void filament_state(const SimDev& d, int64_t f, const double* Xf, Q4 
     V3 fc = lp - lm + v3(sp[1], sp[2], sp[3]);
     if (d.fext) fc = fc + ld3(d.fext, S, s0 + n);
     V3 tc = (0.5 * d.dL) * cross(v3(st[n][0], st[n][1], st[n][2]), lp + lm) + (mp - mm);
+    if (d.text) tc = tc + ld3(d.text, S, s0 + n);
     if (teth && n == 0) {
-        fc = fc + ldx(Xf, 0);
-        tc = tc + ldx(Xf, 3);
+        fc = fc + ldx(Xf, 0);                   // lambda_1 of a held base
+        if (teth == 1) tc = tc + ldx(Xf, 3);    // lambda_2 of a clamped one
     }
     st3(F, S, s0 + n, fc);
     st3(T, S, s0 + n, tc);
@@ -389,6 +390,59 @@ int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, con
     return FIL_OK;
 }
 
+// ---------------------------------------------------------------- geometric switch
+// Geometric-switch driving torque of model cilia (Sec. 5.3): a torque about a fixed axis
+// drives the base of every pinned filament until the angle theta between the wall normal
+// and the base tangent (signed about the axis) reaches +theta_max or -theta_max, where
+// the drive reverses, its magnitude switching between tau_pos (driving towards
+// +theta_max) and tau_neg (towards -theta_max).  For the stability of the implicit
+// steps the torque passes from the old value to the new one along a logistic curve over
+// n_tr steps.  The switch is decided once per step from the committed configuration.
+__device__ __forceinline__ double switch_torque(const SwitchArgs& a, int dir, int age, double tau0) {
+    const double tau1 = dir > 0 ? a.tau_pos : -a.tau_neg;
+    if (age >= a.n_tr) return tau1;
+    const double x = (double)age / (double)a.n_tr - 0.5;
+    const double sg = 1.0 / (1.0 + exp(-12.0 * x));
+    return tau0 + (tau1 - tau0) * sg;
+}
+
+// one thread per filament
+__global__ void __launch_bounds__(64) switch_torque_kernel(SimDev d, SwitchArgs a, const double* __restrict__ qj,
+                                                           double* __restrict__ text) {
+    const int64_t f = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (f >= d.M) return;
+    const int64_t S = d.S, s0 = d.seg_off[f], N = d.seg_off[f + 1] - s0;
+    for (int64_t n = 0; n < N; n++)
+        for (int c = 0; c < 3; c++) text[c * S + s0 + n] = 0.0;
+    if (d.tether[f] != 2) return;
+    const Q4 q = ldq(qj, S, s0);
+    const V3 t = frame_t(q);
+    const V3 nrm = v3(a.normal[0], a.normal[1], a.normal[2]), ax = v3(a.axis[0], a.axis[1], a.axis[2]);
+    const double theta = atan2(dot(cross(nrm, t), ax), dot(nrm, t));
+    int dir = a.dir[f], age = a.age[f];
+    double tau0 = a.tau0[f];
+    if (dir * theta >= a.theta_max) {
+        tau0 = switch_torque(a, dir, age, tau0);
+        dir = -dir;
+        age = 0;
+    } else if (age < a.n_tr) {
+        age++;
+    }
+    const double tau = switch_torque(a, dir, age, tau0);
+    for (int c = 0; c < 3; c++) text[c * S + s0] = tau * a.axis[c];
+    a.dir[f] = dir;
+    a.age[f] = age;
+    a.tau0[f] = tau0;
+}
+
+int switch_torque_launch(const SimDev& d, const SwitchArgs& a, const double* qj, double* text, hipStream_t st) {
+    if (d.M == 0) return FIL_OK;
+    switch_torque_kernel<<<(unsigned)ceil_div(d.M, (int64_t)64), 64, 0, st>>>(d, a, qj, text);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
+}
+
+
 // ---------------------------------------------------------------- residual
 // f^1 = Y_1 - a1 Y_1^j - a2 Y_1^{j-1} - b dt V_1
 // f^2_n = u_n - g u_n^j - b dt dexpinv_{u_n}(Omega_n)
@@ -534,7 +588,7 @@ __global__ void __launch_bounds__(NT) residual_kernel(SimDev d, BdfCoef bc, cons
             const V3 om = v3(sv[3][n], sv[4][n], sv[5][n]);
             const V3 yres = ycur - bc.a1 * yold - bc.a2 * yold2 - bdt * vel;
             V3 u = uu;
-            if (teth && n == 0) u = uj = v3(0, 0, 0);
+            if (teth == 1 && n == 0) u = uj = v3(0, 0, 0);
             const V3 dom = dexpinv(u, om);
             const V3 ures = u - bc.g * uj - bdt * dom;
             vmax = fabs(bdt) * fmax(fmax(fmax(fabs(vel.x), fabs(vel.y)), fmax(fabs(vel.z), fabs(dom.x))),
@@ -657,7 +711,7 @@ __global__ void __launch_bounds__(256) initial_guess_kernel(SimDev d, int64_t st
         } else {
             if (n == 0 && !teth) x0 = 2.0 * Yj[i * d.S + s] - Yjm1[i * d.S + s];
             else x0 = step >= 2 ? 2.0 * Xj[r0 + i] - Xjm1[r0 + i] : Xj[r0 + i];
-            if (n == 0 && teth) x1 = step >= 2 ? 2.0 * Xj[r1 + i] - Xjm1[r1 + i] : Xj[r1 + i];
+            if (n == 0 && teth == 1) x1 = step >= 2 ? 2.0 * Xj[r1 + i] - Xjm1[r1 + i] : Xj[r1 + i];
             else x1 = Xj[r1 + i];
         }
         X0[r0 + i] = X0c[r0 + i] = x0;
@@ -780,8 +834,9 @@ __device__ __forceinline__ SegFrame frame_at(const J0Ctx& c, int n) {
 
 // Block (I, J) of the explicit approximate Jacobian (Appendix B.2) in the
 // original ordering.  Row blocks: 0 -> f^1, 1..N -> f^2_m (m = I-1), N+1..2N-1 ->
-// f^3_m (m = I-N).  Column blocks: 0 -> Y_1 (lambda_1 when clamped), 1..N -> u_n
-// (n = J-1; lambda_2 for n = 0 when clamped), N+1..2N-1 -> Lambda of joint J-N-1.
+// f^3_m (m = I-N).  Column blocks: 0 -> Y_1 (lambda_1 when the base is held: tether 1
+// clamped or 2 pinned), 1..N -> u_n (n = J-1; lambda_2 for n = 0 when clamped),
+// N+1..2N-1 -> Lambda of joint J-N-1.
 // cT = b dt/(6 pi eta a), cR = b dt/(8 pi eta a^3).
 __device__ M33 j0_block(const SimDev& d, const J0Ctx& c, int I, int Jb) {
     const int N = c.N;
@@ -796,7 +851,7 @@ __device__ M33 j0_block(const SimDev& d, const J0Ctx& c, int I, int Jb) {
             if (!teth) B = meye(1.0);
         } else if (Jb <= N) {
             const int n = Jb - 1;
-            if (n <= m && !(n == 0 && teth)) {
+            if (n <= m && !(n == 0 && teth == 1)) {
                 const double w = (n == 0 || n == m) ? 1.0 : 2.0;
                 B = mscale(mskew(-1.0 * frame_at(c, n).t), 0.5 * d.dL * w);
             }
@@ -820,12 +875,12 @@ __device__ M33 j0_block(const SimDev& d, const J0Ctx& c, int I, int Jb) {
             if (n == m + 1 && m + 1 < N) {
                 const M33 dM = dmoment_du(fm, frame_at(c, m + 1), joint_kappa(d, c.f, m, c.tt), d.dL, d.KB, d.KT, true);
                 B = mscale(mmul(Tay, dM), -c.cR);
-            } else if (n == m - 1 && !(m == 1 && teth)) {
+            } else if (n == m - 1 && !(m == 1 && teth == 1)) {
                 const M33 dM =
                     dmoment_du(frame_at(c, m - 1), fm, joint_kappa(d, c.f, m - 1, c.tt), d.dL, d.KB, d.KT, false);
                 B = mscale(mmul(Tay, dM), c.cR);
             } else if (n == m) {
-                if (teth && m == 0) {
+                if (teth == 1 && m == 0) {
                     B = meye(-c.cR);
                 } else {
                     V3 ls = v3(0, 0, 0);
@@ -887,7 +942,7 @@ __global__ void __launch_bounds__(256) j0_band_assemble_kernel(SimDev d, BdfCoef
         const Q4 q = ldq(qc, S, s0 + n);
         const V3 t = frame_t(q), mu = frame_mu(q), nu = frame_nu(q);
         V3 u = ldx(Xf, 3 + 3 * n);
-        if (teth && n == 0) u = v3(0, 0, 0);
+        if (teth == 1 && n == 0) u = v3(0, 0, 0);
         const V3 Tm = ld3(Tint, S, s0 + n);
         const double v[15] = {t.x, t.y, t.z, mu.x, mu.y, mu.z, nu.x, nu.y, nu.z, u.x, u.y, u.z, Tm.x, Tm.y, Tm.z};
         for (int i = 0; i < 15; i++) sh[n][i] = v[i];

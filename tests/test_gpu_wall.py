@@ -116,3 +116,56 @@ def test_set_wall_refusals():
     g3.step()
     with pytest.raises(FilError):
         g3.set_wall()
+
+
+def test_pinned_filament_parity():
+    """Pinned base (position held, rotation free) in free space: a filament swinging down
+    under gravity, 10 steps, against the oracle."""
+    import math
+    import paper_1903_12609_amd as fil
+    N = 8
+    th = math.radians(60.0)
+    q0 = np.array([math.cos(-(math.pi / 2 - th) / 2), 0, math.sin(-(math.pi / 2 - th) / 2), 0])
+    q = np.tile(q0, (N, 1))
+    Y = synth.chain(np.array([0.0, 0.0, 50.0]), q)
+    params, _ = synth.sedimentation_params(N, 10.0, 1.0, 1e-10, 200, steric=False)
+    params.update(tether=np.array([2], dtype=np.int32), base=Y[:1].copy())
+    o = oracle.Sim([0, N], Y, q, **params)
+    g = fil.Sim(np.array([0, N], dtype=np.int64), Y, q, params, graph=8)
+    for j in range(10):
+        rc, rep = o.step()
+        assert rc == 0
+        r = g.step()[0]
+        assert r["iters"] == rep.iters, (j, r["iters"], rep.iters)
+    Yg, qg, _ = g.read_state()
+    assert rel_l2(Yg, o.Y) <= 1e-9 and rel_l2(qg, o.q) <= 1e-9, (rel_l2(Yg, o.Y), rel_l2(qg, o.q))
+    assert np.abs(Yg[0] - Y[0]).max() == 0.0
+
+
+def test_cilia_on_the_wall_parity(steps=20):
+    """Two pinned cilia on the wall driven by the geometric switch (Sec. 5.3): per step
+    the same iteration count and switch directions as the oracle, positions to 1e-8."""
+    import paper_1903_12609_amd as fil
+    from oracle import cilia
+    import cilia_cases as cc
+    fo, Y, q, p = cc.pair()
+    text = np.zeros((Y.shape[0], 3))
+    o = oracle.Sim(fo, Y, q, text=text, mobility=lambda Y_, F, T: owall.wall_rpy_apply(Y_, F, T, 1.0, 1.0), **p)
+    sw = cilia.GeometricSwitch(fo, p["tether"], cc.AXIS, cc.NORMAL, cc.THETA_MAX, cc.TAU_POS, cc.TAU_NEG, cc.N_TR)
+    g = fil.Sim(fo, Y, q, p, graph=8)
+    g.set_wall()
+    g.set_geometric_switch(cc.AXIS, cc.NORMAL, cc.THETA_MAX, cc.TAU_POS, cc.TAU_NEG, cc.N_TR)
+    flips = 0
+    for j in range(steps):
+        sw.update(o.q, text)
+        rc, rep = o.step()
+        assert rc == 0
+        r = g.step()[0]
+        assert r["iters"] == rep.iters, (j, r["iters"], rep.iters)
+        d = g.read_switch()
+        assert np.array_equal(d, sw.dir), (j, d, sw.dir)
+        flips += int(j > 0 and d[0] != prev)
+        prev = d[0]
+    assert flips >= 1
+    Yg, qg, _ = g.read_state()
+    assert rel_l2(Yg, o.Y) <= 1e-8 and rel_l2(qg, o.q) <= 1e-8, (rel_l2(Yg, o.Y), rel_l2(qg, o.q))
