@@ -280,7 +280,56 @@ def wall_mobility_bench(reps=5):
         sim.close()
         log("cilia-size array", res)
     out["array_6x6x20_steps"] = res
+    out["cilia_6x6x20_switch"] = cilia_array_steps()
     return out
+
+
+def cilia_array_steps(steps=40, dt=25000.0, n_tr=10, tau=0.02):
+    """Model cilia of Sec. 5.3 at the paper's array size: 6 x 6 pinned filaments of N = 20
+    on the wall (base-to-base spacing L in both directions, bases one segment spacing
+    above the wall), each driven by the geometric switch about y (theta_max = 2 pi / 5,
+    torque ratio 3: tau_pos = 3 tau, tau_neg = tau = 0.02 K_B, 10-step transition),
+    dt = 25000, tol 1e-6; all start upright and in phase.  (tau = 0.05 needs dt <= 5000:
+    at larger steps the reversal's first step does not converge.)"""
+    import math
+    import numpy as np
+    import torch
+    import paper_1903_12609_amd as fil
+    from paper_1903_12609_amd import synth
+    N, nc = 20, 6
+    L = N * synth.DL
+    qz = np.array([math.cos(-math.pi / 4), 0.0, math.sin(-math.pi / 4), 0.0])
+    bases = np.array([[i * L, j * L, synth.DL] for i in range(nc) for j in range(nc)])
+    Y = np.concatenate([b + np.outer(np.arange(N) * synth.DL, [0, 0, 1.0]) for b in bases])
+    q = np.tile(qz, (nc * nc * N, 1))
+    fo = np.arange(0, nc * nc * N + 1, N, dtype=np.int64)
+    p = dict(a=1.0, eta=1.0, dL=synth.DL, KB=1.0, KT=1.0, chi=1.1, FS=1e3 / L ** 2, grav=(0.0, 0.0, 0.0),
+             dt=dt, tol=1e-6, kmax=100, tether=np.full(nc * nc, 2, dtype=np.int32), base=bases)
+    sim = fil.Sim(fo, Y, q, p, graph=GRAPH_ITERS)
+    sim.set_wall()
+    sim.set_geometric_switch((0.0, 1.0, 0.0), (0.0, 0.0, 1.0), 2 * math.pi / 5, 3 * tau, tau, n_tr)
+    its, flips, ok = [], 0, True
+    prev = sim.read_switch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = sim.step(raise_on_fail=False)
+        rep = r[1][0] if isinstance(r, tuple) else r[0]
+        its.append(rep["iters"])
+        if not rep["converged"]:
+            ok = False
+            break
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    d = sim.read_switch()
+    Yf = sim.read_state()[0]
+    sim.close()
+    res = dict(converged=ok, steps=len(its), ms_per_step=el / len(its) * 1e3, iters_per_step=float(np.mean(its)),
+               drive_down=int((d < 0).sum()), min_height=float(Yf[:, 2].min()),
+               workload="6 x 6 pinned cilia of N = 20 on a wall, geometric switch (theta_max 2 pi/5, tau_neg %g, "
+                        "ratio 3, %d-step transition), dt = %g, tol 1e-6" % (tau, n_tr, dt))
+    log("cilia array", res)
+    return res
 
 
 def traffic_per_launch():
