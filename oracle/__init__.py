@@ -56,7 +56,8 @@ class Params(C.Structure):
         ("chi", C.c_double), ("FS", C.c_double), ("grav", C.c_double * 3),
         ("dt", C.c_double), ("tol", C.c_double), ("kmax", C.c_int64),
         ("K0", C.c_double), ("kw", C.c_double), ("omega", C.c_double), ("phase", _dp),
-        ("tether", _i32p), ("base", _dp), ("nthreads", C.c_int64), ("drag_only", C.c_int64),
+        ("tether", _i32p), ("motor_d0", C.c_double), ("motor_w", C.c_double), ("base", _dp),
+        ("nthreads", C.c_int64), ("drag_only", C.c_int64),
         ("fext", _dp), ("text", _dp), ("Lper", _dp), ("mobility", C.c_void_p), ("mob_ctx", C.c_void_p),
     ]
 
@@ -89,7 +90,7 @@ def _declare(L):
     L.or_steric.argtypes = [C.c_int64, _dp, _i64p, C.c_double, C.c_double, C.c_double, _dp, _dp]
     L.or_moment.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
     L.or_internal_forces.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp, _dp]
-    L.or_reconstruct.argtypes = [C.POINTER(Params), _dp, _dp, _dp, _dp]
+    L.or_reconstruct.argtypes = [C.POINTER(Params), _dp, _dp, C.c_double, _dp, _dp]
     L.or_forces.argtypes = [C.POINTER(Params), _dp, _dp, _dp, C.c_double, _dp, _dp]
     L.or_residual.argtypes = [C.POINTER(Params), C.POINTER(State), _dp, _dp, _dp, _dp]
     L.or_residual.restype = C.c_double
@@ -224,7 +225,7 @@ class Sim:
     configuration (from the shared synthetic generators).  Keyword parameters
     mirror the method's: a, eta, dL, KB, KT, chi, FS, grav, dt, tol, kmax, K0,
     kw, omega, phase [M], tether [M] (0 free, 1 clamped, 2 pinned: base position held,
-    rotation free), base [M,3], fext [S,3] and text [S,3] (further external forces and
+    rotation free, 3 on a rotating motor: motor_d0, motor_w), base [M,3], fext [S,3] and text [S,3] (further external forces and
     torques on each segment), nthreads; periodic = dict(box [3], grid [3], cut, omega) puts the
     suspension in a periodic box with the force-coupling-method mobility (Sec. 2.7.2) and
     nearest-image steric forces; mobility = callable (Y, F, T) -> (V, W) over [S, 3] arrays
@@ -267,6 +268,8 @@ class Sim:
             self._keep += [th, base]
             P.tether = th.ctypes.data_as(_i32p)
             P.base = _p(base)
+        P.motor_d0 = kw.get("motor_d0", 0.0)
+        P.motor_w = kw.get("motor_w", 0.0)
         fx = kw.get("fext")
         if fx is not None:
             fx = _f64(fx, (S, 3))
@@ -343,7 +346,7 @@ class Sim:
     def reconstruct(self, X):
         X = _f64(X).copy()
         Y, q = np.zeros((self.S, 3)), np.zeros((self.S, 4))
-        lib().or_reconstruct(C.byref(self.P), _p(self.q), _p(X), _p(Y), _p(q))
+        lib().or_reconstruct(C.byref(self.P), _p(self.q), _p(X), self.St.t + self.P.dt, _p(Y), _p(q))
         return Y, q
 
     def forces(self, X, Y=None, q=None, tt=None):

@@ -352,7 +352,9 @@ typedef struct {
     /* preferred curvature kappa_nu(s,t) = K0 sin(kw s - omega t + phase[f]) (Sec. 5.3) */
     double K0, kw, omega;
     const double* phase;     /* [M] or NULL for no preferred curvature */
-    const int32_t* tether;   /* [M], 1 = base clamped (Sec. 5.2.1), 2 = base pinned; NULL: all free */
+    const int32_t* tether;   /* [M], 1 = base clamped (Sec. 5.2.1), 2 = base pinned, 3 = base on a
+                              * rotating motor (Sec. 5.2); NULL: all free */
+    double motor_d0, motor_w; /* the motor: base distance from its z axis and rotation rate */
     const double* base;      /* [M][3] clamped base positions */
     int64_t nthreads;        /* OpenMP threads for the RPY target loop (0: default) */
     int64_t drag_only;       /* 1: diagonal drag mobility, no steric, no gravity: the f0 of Sec. 3.2.1 */
@@ -385,8 +387,18 @@ typedef struct {
 
 static int64_t total_segments(const or_params* P) { return P->fil_off[P->M]; }
 static int is_tethered(const or_params* P, int64_t f) { return P->tether && P->tether[f]; }
-/* the base orientation is held too (u_1 = 0, lambda_2 in its slot) */
-static int is_clamped(const or_params* P, int64_t f) { return P->tether && P->tether[f] == 1; }
+/* the base orientation is prescribed too (lambda_2 in the u_1 slot): held (1) or turned by the motor (3) */
+static int is_clamped(const or_params* P, int64_t f) { return P->tether && (P->tether[f] == 1 || P->tether[f] == 3); }
+static int is_motor(const or_params* P, int64_t f) { return P->tether && P->tether[f] == 3; }
+/* the motor's prescribed base rotation per step, u_1 = (0, 0, omega dt) */
+static void motor_u(const or_params* P, double u[3]) { u[0] = 0; u[1] = 0; u[2] = P->motor_w * P->dt; }
+/* the motor's base position at time tt: on the circle of radius d0 about the z axis through
+ * base - (d0, 0, 0) (base = the initial Y_1), at angle omega tt */
+static void motor_base(const or_params* P, int64_t f, double tt, double y[3]) {
+    y[0] = P->base[3 * f] - P->motor_d0 + P->motor_d0 * cos(P->motor_w * tt);
+    y[1] = P->base[3 * f + 1] + P->motor_d0 * sin(P->motor_w * tt);
+    y[2] = P->base[3 * f + 2];
+}
 
 /* BDF coefficients: y - a1 y^j - a2 y^{j-1} - b dt v = 0,  u - g u^j - b dt dexpinv(Omega) = 0.
  * The first step is BDF1 (reading R7), every later one BDF2 (Sec. 2.9.3). */
@@ -405,18 +417,20 @@ static void joint_kappa(const or_params* P, int64_t f, int64_t k, double tt, dou
 /* Rebuild the configuration from X: q_n = exp(u_n) . q_n^j, t_n = R(q_n) e_x and the
  * robot-arm positions Y_n = Y_1 + dL/2 sum_{m=2}^{n} (t_{m-1} + t_m) (Sec. 2.9.3).
  * A clamped filament keeps Y_1 = base and u_1 = 0. */
-void or_reconstruct(const or_params* P, const double* qj, const double* X, double* Yo, double* qo) {
+void or_reconstruct(const or_params* P, const double* qj, const double* X, double tt, double* Yo, double* qo) {
     for (int64_t f = 0; f < P->M; f++) {
         int64_t s0 = P->fil_off[f], N = P->fil_off[f + 1] - s0;
         const double* Xf = X + 6 * s0;
         for (int64_t n = 0; n < N; n++) {
             double u[3] = {Xf[3 + 3 * n], Xf[4 + 3 * n], Xf[5 + 3 * n]}, e[4];
             if (n == 0 && is_clamped(P, f)) { u[0] = u[1] = u[2] = 0; }
+            if (n == 0 && is_motor(P, f)) motor_u(P, u);
             or_qexp(u, e);
             or_qmul(e, qj + 4 * (s0 + n), qo + 4 * (s0 + n));
         }
         double y[3];
-        if (is_tethered(P, f)) memcpy(y, P->base + 3 * f, sizeof y);
+        if (is_motor(P, f)) motor_base(P, f, tt, y);
+        else if (is_tethered(P, f)) memcpy(y, P->base + 3 * f, sizeof y);
         else memcpy(y, Xf, sizeof y);
         memcpy(Yo + 3 * s0, y, sizeof y);
         double tprev[3];
@@ -456,7 +470,19 @@ void or_forces(const or_params* P, const double* Y, const double* q, const doubl
              * T^C_1 += lambda_2 (Sec. 5.2.1) */
             for (int i = 0; i < 3; i++) {
                 F[3 * s0 + i] += X[6 * s0 + i];
-                if (is_clamped(P, f)) T[3 * s0 + i] += X[6 * s0 + 3 + i];
+                if (is_clamped(P, f) && !is_motor(P, f)) T[3 * s0 + i] += X[6 * s0 + 3 + i];
+            }
+            if (is_motor(P, f)) {
+                /* T^C_1 += D^T lambda_2 with D v = dexpinv_{u_1}(v) = v - 1/2 u x v + c u x (u x v)
+                 * (Sec. 5.2), so D^T v = v + 1/2 u x v + c u x (u x v), c as in or_dexpinv */
+                double u[3], l[3] = {X[6 * s0 + 3], X[6 * s0 + 4], X[6 * s0 + 5]}, ul[3], uul[3];
+                motor_u(P, u);
+                cross3(u, l, ul);
+                cross3(u, ul, uul);
+                double x = norm3(u);
+                double c = x < 1e-3 ? 1.0 / 12.0 + x * x / 720.0 + x * x * x * x / 30240.0
+                                    : -(x / tan(0.5 * x) - 2.0) / (2.0 * x * x);
+                for (int i = 0; i < 3; i++) T[3 * s0 + i] += l[i] + 0.5 * ul[i] + c * uul[i];
             }
         }
         free(Lam);
@@ -492,7 +518,7 @@ double or_residual(const or_params* P, const or_state* St, const double* X, doub
     double* T = (double*)malloc(3 * S * sizeof(double));
     double* V = (double*)malloc(3 * S * sizeof(double));
     double* W = (double*)malloc(3 * S * sizeof(double));
-    or_reconstruct(P, St->q, X, Y, q);
+    or_reconstruct(P, St->q, X, St->t + P->dt, Y, q);
     if (P->drag_only) {
         /* f0: M replaced by diag(M) and no steric or external forces (Sec. 3.2.1) */
         or_params P0 = *P;
@@ -521,6 +547,7 @@ double or_residual(const or_params* P, const or_state* St, const double* X, doub
             double u[3] = {Xf[3 + 3 * n], Xf[4 + 3 * n], Xf[5 + 3 * n]};
             double uj[3] = {Xj[3 + 3 * n], Xj[4 + 3 * n], Xj[5 + 3 * n]}, d[3];
             if (n == 0 && is_clamped(P, f)) { u[0] = u[1] = u[2] = 0; uj[0] = uj[1] = uj[2] = 0; }
+            if (n == 0 && is_motor(P, f)) { motor_u(P, u); motor_u(P, uj); }
             or_dexpinv(u, W + 3 * (s0 + n), d);
             for (int i = 0; i < 3; i++) ff[3 + 3 * n + i] = u[i] - g * uj[i] - b * P->dt * d[i];
         }
@@ -744,7 +771,7 @@ int or_broyden(const or_params* P, const or_state* St, double* X, or_report* rep
     /* J0 at X0, factorised per filament */
     double* Yc = (double*)malloc(3 * S * sizeof(double));
     double* qc = (double*)malloc(4 * S * sizeof(double));
-    or_reconstruct(P, St->q, X, Yc, qc);
+    or_reconstruct(P, St->q, X, St->t + P->dt, Yc, qc);
     double** LU = (double**)malloc(P->M * sizeof(double*));
     int64_t** piv = (int64_t**)malloc(P->M * sizeof(int64_t*));
     int bad = 0;
@@ -814,7 +841,7 @@ int or_bdf2_step(const or_params* P, or_state* St, or_report* rep) {
     if (rc == 0) {
         double* Yn = (double*)malloc(3 * S * sizeof(double));
         double* qn = (double*)malloc(4 * S * sizeof(double));
-        or_reconstruct(P, St->q, X, Yn, qn);
+        or_reconstruct(P, St->q, X, St->t + P->dt, Yn, qn);
         memcpy(St->Yprev, St->Y, 3 * S * sizeof(double));
         memcpy(St->Y, Yn, 3 * S * sizeof(double));
         memcpy(St->q, qn, 4 * S * sizeof(double));

@@ -221,3 +221,37 @@ def test_pinned_filament_hangs_below_its_pin():
     assert np.abs(sim.Y[0] - Y[0]).max() == 0.0
     assert np.abs(t - np.array([0.0, 0.0, -1.0])).max() <= 1e-3
     assert abs(sim.Y[-1, 2] - (50.0 - (N - 1) * params["dL"])) <= 1e-2
+
+
+def _motor_filament(Sp, N=10, d0=4.5977, tilt_deg=15.0):
+    """A filament on a rotating motor (Sec. 5.2): base d0 from the z axis, tilted 15 degrees
+    away from it; omega from the Sperm number Sp = zeta_perp omega L^4 / K_B, 0.05 rad per
+    step."""
+    tilt = math.radians(tilt_deg)
+    phi = -(math.pi / 2 - tilt)
+    q = np.tile([math.cos(phi / 2), 0, math.sin(phi / 2), 0], (N, 1))
+    Y = synth.chain(np.array([d0, 0.0, 0.0]), q)
+    L = N * synth.DL
+    w = Sp / (4 * math.pi / (math.log(L) + 0.5) * L ** 4)
+    sim = oracle.Sim([0, N], Y, q, dt=0.05 / w, tol=1e-10, kmax=100, tether=[3], base=Y[:1], motor_d0=d0,
+                     motor_w=w)
+    return sim, Y, (d0 + (N - 1) * synth.DL * math.sin(tilt))
+
+
+def test_motor_filament_limits():
+    """Low Sp: nearly rigid rotation, the free end at d0 + L sin(15 deg) from the axis; high
+    Sp: the filament collapses towards the axis.  The base follows the motor's circle."""
+    sim, Y, d_rigid = _motor_filament(0.1)
+    for _ in range(20):
+        rc, rep = sim.step()
+        assert rc == 0
+    assert abs(math.hypot(*sim.Y[-1, :2]) / d_rigid - 1.0) <= 1e-3
+    assert abs(math.hypot(*sim.Y[0, :2]) - 4.5977) <= 1e-12
+    assert abs(math.atan2(sim.Y[0, 1], sim.Y[0, 0]) - 20 * 0.05) <= 1e-12
+    sim, Y, d_rigid = _motor_filament(300.0)
+    ds = []
+    for _ in range(40):
+        rc, rep = sim.step()
+        assert rc == 0
+        ds.append(math.hypot(*sim.Y[-1, :2]) / d_rigid)
+    assert ds[-1] < 0.9 and ds[-1] < ds[19]
