@@ -177,7 +177,8 @@ typedef struct fil_sim fil_sim;
  *   phase  double[M] or NULL      per-filament phase of the preferred curvature
  *   tether int32[M] or NULL       1 = base clamped at its initial Y_1 and q_1; 2 = base
  *                                 pinned at its initial Y_1, its rotation free (the cilia
- *                                 bases of Sec. 5.3): lambda_1 in the Y_1 slot, u_1 kept
+ *                                 bases of Sec. 5.3): lambda_1 in the Y_1 slot, u_1 kept; 3 = base on
+ *                                 the rotating motor of fil_set_motor (Sec. 5.2)
  * The library allocates all device state and workspace here (FIL_ENOMEM on failure). */
 int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, const int64_t* fil_seg_off,
                const double* Y0, const double* q0, const double* phase, const int32_t* tether, fil_sim** out);
@@ -210,6 +211,14 @@ int fil_set_external_forces(fil_sim* sim, const double* Fext);
  * The mobility timing of fil_set_timing then times whole FCM applies.  FIL_EINVAL on a
  * bad argument, and fil_fcm_create's errors. */
 int fil_set_periodic_fcm(fil_sim* sim, const double* box, const int32_t* grid, double cut);
+
+/* The rotating motor of Sec. 5.2 for every tether-3 filament: its base moves on the circle
+ * of radius d0 about the z axis through (initial Y_1) - (d0, 0, 0), at angle omega t, and
+ * turns by u_1 = (0, 0, omega dt) per step; lambda_1, lambda_2 fill the Y_1, u_1 slots and
+ * act on the first segment as F^C = lambda_1, T^C = D^T lambda_2 (D = dexpinv at u_1).  J0
+ * keeps the clamped base's rows.  Only before the first step.  FIL_EINVAL on d0 < 0 or a
+ * non-finite value. */
+int fil_set_motor(fil_sim* sim, double d0, double omega);
 
 /* Geometric-switch driving torque of model cilia (Sec. 5.3) on every pinned filament
  * (tether 2): a torque about the unit axis drives the base until the angle theta between

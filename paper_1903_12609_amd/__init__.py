@@ -239,6 +239,10 @@ class Sim:
         check(lib().fil_read_switch(self._h, out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
+    def set_motor(self, d0, omega):
+        """Rotating motor of the tether-3 bases (Sec. 5.2); before the first step."""
+        check(lib().fil_set_motor(self._h, float(d0), float(omega)))
+
     def set_wall(self):
         """No-slip plane wall at z = 0 (wall-bounded RPY mobility); before the first step."""
         check(lib().fil_set_wall(self._h))

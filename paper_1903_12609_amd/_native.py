@@ -77,6 +77,7 @@ def _declare(L):
         L.fil_set_external_forces.argtypes = [_vp, _vp]
         L.fil_set_periodic_fcm.argtypes = [_vp, _vp, _vp, _d]
         L.fil_set_wall.argtypes = [_vp]
+        L.fil_set_motor.argtypes = [_vp, _d, _d]
         L.fil_set_geometric_switch.argtypes = [_vp, _vp, _vp, _d, _d, _d, _i]
         L.fil_read_switch.argtypes = [_vp, _vp]
         L.fil_rpy_wall_workspace_bytes.argtypes = [_i64]

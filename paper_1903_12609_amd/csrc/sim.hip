@@ -572,7 +572,8 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     const int64_t M = susp_fil_off[nsusp];
     if (tether)
         for (int64_t f = 0; f < M; f++)
-            FIL_CHECK_ARG(tether[f] >= 0 && tether[f] <= 2, "fil_create: tether values are 0, 1 (clamped) or 2 (pinned)");
+            FIL_CHECK_ARG(tether[f] >= 0 && tether[f] <= 3,
+                          "fil_create: tether values are 0, 1 (clamped), 2 (pinned) or 3 (rotating motor)");
     FIL_CHECK_ARG(fil_seg_off[0] == 0, "fil_create: fil_seg_off[0] must be 0");
     for (int64_t f = 0; f < M; f++) {
         const int64_t N = fil_seg_off[f + 1] - fil_seg_off[f];
@@ -915,6 +916,15 @@ int fil_read_switch(fil_sim* s, int32_t* dir) {
     FIL_CHECK_ARG(s->sw, "fil_read_switch: no geometric switch set");
     FIL_HIP_TRY(hipStreamSynchronize(s->st));
     FIL_HIP_TRY(hipMemcpy(dir, s->swa.dir, s->M * sizeof(int32_t), hipMemcpyDeviceToHost));
+    return FIL_OK;
+}
+
+int fil_set_motor(fil_sim* s, double d0, double omega) {
+    FIL_CHECK_ARG(s, "fil_set_motor: null sim");
+    FIL_CHECK_ARG(s->step == 0, "fil_set_motor: only before the first step");
+    FIL_CHECK_ARG(std::isfinite(d0) && d0 >= 0 && std::isfinite(omega), "fil_set_motor: d0 >= 0 and finite omega");
+    s->d.motor_d0 = d0;
+    s->d.motor_w = omega;
     return FIL_OK;
 }
 

@@ -39,6 +39,9 @@ struct SimDev {
     const double* spar;            // [nsusp][5] per suspension: dt, gravity force (3), steric strength F^S
     const double* fext;            // [3][S] further external force per segment, or null
     const double* text;            // [3][S] further external torque per segment, or null
+    // rotating motor of tether-3 bases: distance of the base from the motor's z axis and its
+    // rotation rate (the axis passes through the initial base position minus (d0, 0, 0))
+    double motor_d0, motor_w;
     // periodic box lengths of the steric pass (minimum-image distances); periodic == 0:
     // unbounded
     double per[3];

@@ -139,6 +139,17 @@ __device__ __forceinline__ V3 joint_kappa(const SimDev& d, int64_t f, int64_t k,
 // barrier); lane n of the first wave owns segment n (N <= 64) and passes q^j_n (read
 // by the caller, possibly well before).  Nothing may follow it in the caller that
 // needs a barrier.
+// the rotating motor of a tether-3 base (Sec. 5.2): the prescribed rotation per step
+// u_1 = (0, 0, omega dt) and the base on its circle at time tt
+__device__ __forceinline__ V3 motor_u(const SimDev& d, int64_t f) {
+    return v3(0.0, 0.0, d.motor_w * d.spar[kSpar * d.fil_susp[f]]);
+}
+__device__ __forceinline__ V3 motor_base(const SimDev& d, int64_t f, double tt) {
+    double s, c;
+    sincos(d.motor_w * tt, &s, &c);
+    return v3(d.base[3 * f] - d.motor_d0 + d.motor_d0 * c, d.base[3 * f + 1] + d.motor_d0 * s, d.base[3 * f + 2]);
+}
+
 __device__ void filament_state(const SimDev& d, int64_t f, const double* Xf, Q4 qjn, double tt,
                                double* __restrict__ Yc, double* __restrict__ qc, double* __restrict__ F,
                                double* __restrict__ T, double* __restrict__ box) {
@@ -153,6 +164,7 @@ __device__ void filament_state(const SimDev& d, int64_t f, const double* Xf, Q4 
     if (seg) {
         V3 u = ldx(Xf, 3 + 3 * n);
         if (teth == 1 && n == 0) u = v3(0, 0, 0);  // clamped base: u_1 = 0
+        if (teth == 3 && n == 0) u = motor_u(d, f);  // base turned by the motor
         const Q4 q = qmul(qexp(u), qjn);
         stq(qc, S, s0 + n, q);
         sq[n][0] = q.w; sq[n][1] = q.x; sq[n][2] = q.y; sq[n][3] = q.z;
@@ -165,7 +177,8 @@ __device__ void filament_state(const SimDev& d, int64_t f, const double* Xf, Q4 
         // wave prefix sum of the half-segment steps, then the bounding box
         double e[3];
         if (n == 0) {
-            const V3 y1 = teth ? v3(d.base[3 * f], d.base[3 * f + 1], d.base[3 * f + 2]) : ldx(Xf, 0);
+            const V3 y1 = teth == 3 ? motor_base(d, f, tt)
+                          : teth ? v3(d.base[3 * f], d.base[3 * f + 1], d.base[3 * f + 2]) : ldx(Xf, 0);
             e[0] = y1.x;
             e[1] = y1.y;
             e[2] = y1.z;
@@ -213,6 +226,10 @@ __device__ void filament_state(const SimDev& d, int64_t f, const double* Xf, Q4 
     if (teth && n == 0) {
         fc = fc + ldx(Xf, 0);                   // lambda_1 of a held base
         if (teth == 1) tc = tc + ldx(Xf, 3);    // lambda_2 of a clamped one
+        if (teth == 3) {                        // D^T lambda_2 on the motor's base, D = dexpinv_{u_1}
+            const V3 um = motor_u(d, f), l2 = ldx(Xf, 3);
+            tc = tc + dexpinv(um, l2) + cross(um, l2);
+        }
     }
     st3(F, S, s0 + n, fc);
     st3(T, S, s0 + n, tc);
@@ -589,6 +606,7 @@ __global__ void __launch_bounds__(NT) residual_kernel(SimDev d, BdfCoef bc, cons
             const V3 yres = ycur - bc.a1 * yold - bc.a2 * yold2 - bdt * vel;
             V3 u = uu;
             if (teth == 1 && n == 0) u = uj = v3(0, 0, 0);
+            if (teth == 3 && n == 0) u = uj = motor_u(d, f);
             const V3 dom = dexpinv(u, om);
             const V3 ures = u - bc.g * uj - bdt * dom;
             vmax = fabs(bdt) * fmax(fmax(fmax(fabs(vel.x), fabs(vel.y)), fmax(fabs(vel.z), fabs(dom.x))),
@@ -711,7 +729,7 @@ __global__ void __launch_bounds__(256) initial_guess_kernel(SimDev d, int64_t st
         } else {
             if (n == 0 && !teth) x0 = 2.0 * Yj[i * d.S + s] - Yjm1[i * d.S + s];
             else x0 = step >= 2 ? 2.0 * Xj[r0 + i] - Xjm1[r0 + i] : Xj[r0 + i];
-            if (n == 0 && teth == 1) x1 = step >= 2 ? 2.0 * Xj[r1 + i] - Xjm1[r1 + i] : Xj[r1 + i];
+            if (n == 0 && (teth == 1 || teth == 3)) x1 = step >= 2 ? 2.0 * Xj[r1 + i] - Xjm1[r1 + i] : Xj[r1 + i];
             else x1 = Xj[r1 + i];
         }
         X0[r0 + i] = X0c[r0 + i] = x0;
@@ -841,6 +859,8 @@ __device__ __forceinline__ SegFrame frame_at(const J0Ctx& c, int n) {
 __device__ M33 j0_block(const SimDev& d, const J0Ctx& c, int I, int Jb) {
     const int N = c.N;
     const int teth = c.teth;
+    // base orientation prescribed (held, or turned by the motor: the same drag-model rows)
+    const bool clamped = teth == 1 || teth == 3;
     M33 B = mzero();
     if (I == 0) {  // f^1
         if (Jb == 0) B = meye(teth ? -c.cT : 1.0);
@@ -851,7 +871,7 @@ __device__ M33 j0_block(const SimDev& d, const J0Ctx& c, int I, int Jb) {
             if (!teth) B = meye(1.0);
         } else if (Jb <= N) {
             const int n = Jb - 1;
-            if (n <= m && !(n == 0 && teth == 1)) {
+            if (n <= m && !(n == 0 && clamped)) {
                 const double w = (n == 0 || n == m) ? 1.0 : 2.0;
                 B = mscale(mskew(-1.0 * frame_at(c, n).t), 0.5 * d.dL * w);
             }
@@ -875,12 +895,12 @@ __device__ M33 j0_block(const SimDev& d, const J0Ctx& c, int I, int Jb) {
             if (n == m + 1 && m + 1 < N) {
                 const M33 dM = dmoment_du(fm, frame_at(c, m + 1), joint_kappa(d, c.f, m, c.tt), d.dL, d.KB, d.KT, true);
                 B = mscale(mmul(Tay, dM), -c.cR);
-            } else if (n == m - 1 && !(m == 1 && teth == 1)) {
+            } else if (n == m - 1 && !(m == 1 && clamped)) {
                 const M33 dM =
                     dmoment_du(frame_at(c, m - 1), fm, joint_kappa(d, c.f, m - 1, c.tt), d.dL, d.KB, d.KT, false);
                 B = mscale(mmul(Tay, dM), c.cR);
             } else if (n == m) {
-                if (teth == 1 && m == 0) {
+                if (clamped && m == 0) {
                     B = meye(-c.cR);
                 } else {
                     V3 ls = v3(0, 0, 0);
@@ -942,7 +962,7 @@ __global__ void __launch_bounds__(256) j0_band_assemble_kernel(SimDev d, BdfCoef
         const Q4 q = ldq(qc, S, s0 + n);
         const V3 t = frame_t(q), mu = frame_mu(q), nu = frame_nu(q);
         V3 u = ldx(Xf, 3 + 3 * n);
-        if (teth == 1 && n == 0) u = v3(0, 0, 0);
+        if ((teth == 1 || teth == 3) && n == 0) u = v3(0, 0, 0);
         const V3 Tm = ld3(Tint, S, s0 + n);
         const double v[15] = {t.x, t.y, t.z, mu.x, mu.y, mu.z, nu.x, nu.y, nu.z, u.x, u.y, u.z, Tm.x, Tm.y, Tm.z};
         for (int i = 0; i < 15; i++) sh[n][i] = v[i];

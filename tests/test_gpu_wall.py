@@ -169,3 +169,33 @@ def test_cilia_on_the_wall_parity(steps=20):
     assert flips >= 1
     Yg, qg, _ = g.read_state()
     assert rel_l2(Yg, o.Y) <= 1e-8 and rel_l2(qg, o.q) <= 1e-8, (rel_l2(Yg, o.Y), rel_l2(qg, o.q))
+
+
+def test_motor_filament_parity():
+    """A filament on the rotating motor of Sec. 5.2 (Sp = 30: visibly bent), 15 steps:
+    iteration counts and positions against the oracle; the base follows the circle."""
+    import math
+    import paper_1903_12609_amd as fil
+    from paper_1903_12609_amd._native import FilError
+    N, d0, tilt = 10, 4.5977, math.radians(15.0)
+    phi = -(math.pi / 2 - tilt)
+    q = np.tile([math.cos(phi / 2), 0, math.sin(phi / 2), 0], (N, 1))
+    Y = synth.chain(np.array([d0, 0.0, 0.0]), q)
+    L = N * synth.DL
+    w = 30.0 / (4 * math.pi / (math.log(L) + 0.5) * L ** 4)
+    params = dict(a=1.0, eta=1.0, dL=synth.DL, KB=1.0, KT=1.0, chi=1.1, FS=0.0, grav=(0.0, 0.0, 0.0), dt=0.05 / w,
+                  tol=1e-10, kmax=100, tether=np.array([3], dtype=np.int32), base=Y[:1].copy())
+    o = oracle.Sim([0, N], Y, q, motor_d0=d0, motor_w=w, **params)
+    g = fil.Sim(np.array([0, N], dtype=np.int64), Y, q, params, graph=8)
+    g.set_motor(d0, w)
+    for j in range(15):
+        rc, rep = o.step()
+        assert rc == 0
+        r = g.step()[0]
+        assert r["iters"] == rep.iters, (j, r["iters"], rep.iters)
+    Yg, qg, _ = g.read_state()
+    assert rel_l2(Yg, o.Y) <= 1e-9 and rel_l2(qg, o.q) <= 1e-9, (rel_l2(Yg, o.Y), rel_l2(qg, o.q))
+    assert abs(math.hypot(Yg[0, 0], Yg[0, 1]) - d0) <= 1e-12
+    bad = dict(params, tether=np.array([4], dtype=np.int32))
+    with pytest.raises(FilError):
+        fil.Sim(np.array([0, N], dtype=np.int64), Y, q, bad)
