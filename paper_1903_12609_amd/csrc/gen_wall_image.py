@@ -10,7 +10,7 @@ the free Stokeslet at y plus an image system at y* = (y1, y2, -h):
 part G^im = G - S(x - y) under the Faxen operators of both spheres:
     tt = (1 + a^2/6 lap_x)(1 + a^2/6 lap_y) G^im / (8 pi eta)
     rt = 1/2 curl_x (1 + a^2/6 lap_y) G^im / (8 pi eta)     (rotation at x, force at y)
-    tr = 1/2 curl_y (1 + a^2/6 lap_x) G^im                  (translation at x, torque at y)
+    tr = 1/2 curl_y (1 + a^2/6 lap_x) G^im / (8 pi eta)     (translation at x, torque at y)
     rr = 1/4 curl_x curl_y G^im / (8 pi eta)
 Here the image part is written in the variables R = x - y* and h = y_3 (x_3 = R_3 - h),
 d/dx = d/dR at fixed h, d/dy_1,2 = -d/dR_1,2 and d/dy_3 = d/dh + d/dR_3 (R_3 = x_3 + y_3).
