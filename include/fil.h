@@ -153,7 +153,10 @@ typedef struct {
     int32_t prec;               /* fil_prec of the mobility apply */
     int32_t j0_mode;            /* how J0^{-1} is applied: 0 auto (explicit inverse up to 256 MB),
                                    1 banded LU sweeps, 2 explicit inverse */
-    int32_t pad0;
+    int32_t j0_factor;          /* form of the banded LU kernel: 0 auto (rows staged in LDS while a
+                                   filament size class fits in four rounds of resident workgroups,
+                                   else without LDS), 1 always without LDS.  Both give the same
+                                   factor; 1 exists to check the large-ensemble form on small cases */
     double K0, kw, omega;       /* kappa_nu(s,t) = K0 sin(kw s - omega t + phase_f) */
 } fil_params;
 
@@ -325,12 +328,16 @@ int fil_get_state(fil_sim* sim, const double** Y, const double** q, const double
 int fil_read_state(fil_sim* sim, double* Y, double* q, double* Xj);
 
 /* Checkpoint of the committed state (time, step count, Y^j, Y^{j-1}, q^j, X^j,
- * X^{j-1}, X^{j-2} and the per-suspension parameters) to a file (HOST path), and
- * its restore into a simulation created with the same filament and suspension
- * layout; a restored simulation continues exactly as the saved one would (Broyden
- * histories do not outlive a step).  Synchronises the stream.  FIL_EINVAL when the
- * file cannot be opened, written or read, is not a checkpoint, belongs to another
- * layout or holds non-finite values; the simulation is then unchanged. */
+ * X^{j-1}, X^{j-2}, the per-suspension parameters and, when fil_set_geometric_switch
+ * was called, each filament's switch direction, steps since its last switch and torque
+ * at that switch) to a file (HOST path), and its restore into a simulation created with
+ * the same filament and suspension layout and the same settings (wall, motor, switch,
+ * external forces: they are not in the file); a restored simulation continues exactly as
+ * the saved one would (Broyden histories do not outlive a step).  Synchronises the
+ * stream.  FIL_EINVAL when the file cannot be opened, written or read, is not a
+ * checkpoint, belongs to another layout, holds switch state the simulation has no switch
+ * for (or lacks the state of its switch) or holds non-finite values; the simulation is
+ * then unchanged. */
 int fil_checkpoint(fil_sim* sim, const char* path);
 int fil_restore(fil_sim* sim, const char* path);
 

@@ -158,9 +158,12 @@ class Sim:
     params: a, eta, dL, KB, KT, chi, FS, grav, dt, tol, kmax, K0, kw, omega and
     optional phase [M], tether [M]; susp_fil_off [nsusp+1] groups filaments
     into suspensions (default: one suspension).  prec: "f64" or "f32tile".
+    j0_mode: "auto", "banded" or "dense"; j0_factor: "auto" or "unstaged" (the band LU
+    kernel without LDS staging, the form large ensembles take).
     """
 
-    def __init__(self, fil_off, Y0, q0, params, susp_fil_off=None, prec="f64", j0_mode="auto", graph=0):
+    def __init__(self, fil_off, Y0, q0, params, susp_fil_off=None, prec="f64", j0_mode="auto", graph=0,
+                 j0_factor="auto"):
         import ctypes
         import numpy as np
         from ._native import Params
@@ -179,6 +182,7 @@ class Sim:
         P.dt, P.tol, P.kmax = params["dt"], params.get("tol", 1e-6), int(params.get("kmax", 100))
         P.prec = PREC[prec]
         P.j0_mode = {"auto": 0, "banded": 1, "dense": 2}[j0_mode]
+        P.j0_factor = {"auto": 0, "unstaged": 1}[j0_factor]
         P.K0, P.kw, P.omega = params.get("K0", 0.0), params.get("kw", 0.0), params.get("omega", 0.0)
         self.params = P
         Y0 = np.ascontiguousarray(Y0, dtype=np.float64).reshape(self.S, 3)

@@ -32,7 +32,7 @@ _i = C.c_int
 class Params(C.Structure):
     _fields_ = [("a", _d), ("eta", _d), ("dL", _d), ("KB", _d), ("KT", _d), ("chi", _d), ("FS", _d),
                 ("grav", _d * 3), ("dt", _d), ("tol", _d), ("kmax", C.c_int32), ("prec", C.c_int32),
-                ("j0_mode", C.c_int32), ("pad0", C.c_int32),
+                ("j0_mode", C.c_int32), ("j0_factor", C.c_int32),
                 ("K0", _d), ("kw", _d), ("omega", _d)]
 
 

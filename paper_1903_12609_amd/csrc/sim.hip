@@ -108,6 +108,8 @@ struct fil_sim {
     BdfCoef bc{};
     std::vector<int64_t> susp_seg_off;
     std::vector<int64_t> fil_seg_off_h;  // filament offsets (host copy, for checkpoint checks)
+    bool has_motor = false;   // some filament's base sits on the rotating motor (tether 3)
+    bool dt_differ = false;   // fil_set_suspension_params gave a suspension its own time step
     // optional timing of the main mobility kernel: one event pair per apply of a step
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -181,6 +183,15 @@ int collect_timing(fil_sim* s) {
     }
     s->nev = 0;
     return FIL_OK;
+}
+
+// Forgets the captured graph blocks: they hold the device view and the mobility path as
+// they were when captured, so every setter that changes either drops them.
+void drop_graphs(fil_sim* s) {
+    for (auto& kv : s->graphs)
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    s->graphs.clear();
+    s->pred_iters = 0;
 }
 
 void free_sim(fil_sim* s) {
@@ -565,6 +576,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     FIL_CHECK_ARG(p->kmax >= 1 && p->kmax < kMaxIter, "fil_create: kmax must be in [1, 255]");
     FIL_CHECK_ARG(p->prec == FIL_PREC_F64 || p->prec == FIL_PREC_F32TILE, "fil_create: unknown precision");
     FIL_CHECK_ARG(p->j0_mode >= 0 && p->j0_mode <= 2, "fil_create: j0_mode must be 0, 1 or 2");
+    FIL_CHECK_ARG(p->j0_factor == 0 || p->j0_factor == 1, "fil_create: j0_factor must be 0 or 1");
     FIL_CHECK_ARG(p->FS == 0.0 || p->chi > 1.0, "fil_create: the steric range chi must exceed 1");
     FIL_CHECK_ARG(susp_fil_off[0] == 0, "fil_create: susp_fil_off[0] must be 0");
     for (int64_t i = 0; i < nsusp; i++)
@@ -588,6 +600,8 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     s->S = S;
     s->M = M;
     s->nsusp = nsusp;
+    if (tether)
+        for (int64_t f = 0; f < M; f++) s->has_motor |= tether[f] == 3;
     // ---- host-side index lists
     std::vector<int64_t> seg_off(fil_seg_off, fil_seg_off + M + 1);
     std::vector<int32_t> fil_susp(M), seg_fil(S), teth(M, 0);
@@ -772,6 +786,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     d.spar = s->spar;
     d.cls_fil = d_cls_fil;
     d.ncls = kMaxCls;
+    d.factor_unstaged = p->j0_factor;
     for (int k = 0; k <= kMaxCls; k++) d.cls_off[k] = cls_off[k];
     for (int k = 0; k < kMaxCls; k++) d.cls_n[k] = cls_n[k];
     d.K0 = p->K0;
@@ -816,8 +831,14 @@ int fil_set_suspension_params(fil_sim* s, const double* dt, const double* grav, 
             sp[kSpar * i + 4] = FS[i];
         }
     }
+    for (int64_t i = 0; i < ns; i++) differ |= sp[kSpar * i] != s->p.dt;  // also from an earlier call
     FIL_CHECK_ARG(!differ || s->p.K0 == 0.0,
                   "fil_set_suspension_params: per-suspension dt needs a time-independent preferred curvature (K0 = 0)");
+    FIL_CHECK_ARG(!differ || !s->has_motor || s->d.motor_w == 0.0,
+                  "fil_set_suspension_params: per-suspension dt with a turning motor (the motor's angle follows one "
+                  "global time)");
+    s->dt_differ = differ;
+    drop_graphs(s);
     FIL_HIP_TRY(hipMemcpy(s->spar, sp.data(), sp.size() * sizeof(double), hipMemcpyHostToDevice));
     return FIL_OK;
 }
@@ -825,6 +846,7 @@ int fil_set_suspension_params(fil_sim* s, const double* dt, const double* grav, 
 int fil_set_external_forces(fil_sim* s, const double* Fext) {
     FIL_CHECK_ARG(s, "fil_set_external_forces: null sim");
     FIL_CHECK_ARG(s->step == 0, "fil_set_external_forces: only before the first step");
+    drop_graphs(s);
     if (!Fext) {
         s->d.fext = nullptr;
         return FIL_OK;
@@ -865,6 +887,7 @@ int fil_set_periodic_fcm(fil_sim* s, const double* box, const int32_t* grid, dou
     s->fcm = f;
     for (int c = 0; c < 3; c++) s->d.per[c] = box[c];
     s->d.periodic = 1;
+    drop_graphs(s);
     return FIL_OK;
 }
 
@@ -908,6 +931,7 @@ int fil_set_geometric_switch(fil_sim* s, const double* axis, const double* norma
     s->swa.n_tr = n_transition;
     s->d.text = s->text_d;
     s->sw = true;
+    drop_graphs(s);
     return FIL_OK;
 }
 
@@ -923,8 +947,11 @@ int fil_set_motor(fil_sim* s, double d0, double omega) {
     FIL_CHECK_ARG(s, "fil_set_motor: null sim");
     FIL_CHECK_ARG(s->step == 0, "fil_set_motor: only before the first step");
     FIL_CHECK_ARG(std::isfinite(d0) && d0 >= 0 && std::isfinite(omega), "fil_set_motor: d0 >= 0 and finite omega");
+    FIL_CHECK_ARG(omega == 0.0 || !s->has_motor || !s->dt_differ,
+                  "fil_set_motor: the suspensions have their own time steps; the motor turns with one global time");
     s->d.motor_d0 = d0;
     s->d.motor_w = omega;
+    drop_graphs(s);
     return FIL_OK;
 }
 
@@ -942,6 +969,7 @@ int fil_set_wall(fil_sim* s) {
         s->wall_work = w;
     }
     s->wall = true;
+    drop_graphs(s);
     return FIL_OK;
 }
 
@@ -1136,13 +1164,17 @@ int fil_read_state(fil_sim* s, double* Y, double* q, double* Xj) {
 }
 
 // ---------------------------------------------------------------- checkpoint / restore
-// File layout (native byte order): "FILSIM01", int64 S, M, nsusp, step, double t,
+// File layout (native byte order): "FILSIM02", int64 S, M, nsusp, step, double t,
 // int64 fil_seg_off[M+1], int64 susp_fil_off[nsusp+1], double spar[nsusp][5],
-// then Y^j, Y^{j-1} [3][S], q^j [4][S], X^j, X^{j-1}, X^{j-2} [6S].
+// then Y^j, Y^{j-1} [3][S], q^j [4][S], X^j, X^{j-1}, X^{j-2} [6S], then int64 sw
+// (1 when a geometric switch drives the bases) followed, when sw = 1, by its state:
+// int32 dir[M], int32 age[M], double tau0[M].  "FILSIM01" files (no switch block) are
+// still read, into simulations without a switch.
 }  // extern "C"
 
 namespace {
-constexpr char kSimMagic[8] = {'F', 'I', 'L', 'S', 'I', 'M', '0', '1'};
+constexpr char kSimMagic[8] = {'F', 'I', 'L', 'S', 'I', 'M', '0', '2'};
+constexpr char kSimMagicV1[8] = {'F', 'I', 'L', 'S', 'I', 'M', '0', '1'};
 
 struct FileCloser {
     FILE* f;
@@ -1183,6 +1215,19 @@ int fil_checkpoint(fil_sim* s, const char* path) {
         FIL_HIP_TRY(hipMemcpy(buf.data(), a.first, a.second * sizeof(double), hipMemcpyDeviceToHost));
         ok = fwrite(buf.data(), sizeof(double), a.second, fc.f) == a.second;
     }
+    // the geometric switch's state: without it a restored run would restart every switch
+    const int64_t sw = s->sw ? 1 : 0;
+    ok = ok && fwrite(&sw, sizeof(int64_t), 1, fc.f) == 1;
+    if (ok && sw) {
+        const size_t M = (size_t)s->M;
+        std::vector<int32_t> dir(M), age(M);
+        std::vector<double> tau0(M);
+        FIL_HIP_TRY(hipMemcpy(dir.data(), s->swa.dir, M * sizeof(int32_t), hipMemcpyDeviceToHost));
+        FIL_HIP_TRY(hipMemcpy(age.data(), s->swa.age, M * sizeof(int32_t), hipMemcpyDeviceToHost));
+        FIL_HIP_TRY(hipMemcpy(tau0.data(), s->swa.tau0, M * sizeof(double), hipMemcpyDeviceToHost));
+        ok = fwrite(dir.data(), sizeof(int32_t), M, fc.f) == M && fwrite(age.data(), sizeof(int32_t), M, fc.f) == M &&
+             fwrite(tau0.data(), sizeof(double), M, fc.f) == M;
+    }
     ok = ok && fflush(fc.f) == 0;
     FIL_CHECK_ARG(ok, std::string("fil_checkpoint: write to ") + path + " failed");
     return FIL_OK;
@@ -1195,7 +1240,9 @@ int fil_restore(fil_sim* s, const char* path) {
     char magic[8];
     int64_t hdr[4];
     double t = 0.0;
-    FIL_CHECK_ARG(fread(magic, 1, 8, fc.f) == 8 && std::memcmp(magic, kSimMagic, 8) == 0 &&
+    const bool magic_ok = fread(magic, 1, 8, fc.f) == 8;
+    const bool v1 = magic_ok && std::memcmp(magic, kSimMagicV1, 8) == 0;
+    FIL_CHECK_ARG(magic_ok && (v1 || std::memcmp(magic, kSimMagic, 8) == 0) &&
                       fread(hdr, sizeof(int64_t), 4, fc.f) == 4 && fread(&t, sizeof(double), 1, fc.f) == 1,
                   "fil_restore: not a simulation checkpoint");
     FIL_CHECK_ARG(hdr[0] == s->S && hdr[1] == s->M && hdr[2] == s->nsusp && hdr[3] >= 0,
@@ -1217,6 +1264,23 @@ int fil_restore(fil_sim* s, const char* path) {
                       "fil_restore: truncated checkpoint");
         for (double v : data.back()) FIL_CHECK_ARG(std::isfinite(v), "fil_restore: non-finite state");
     }
+    int64_t sw = 0;
+    if (!v1) FIL_CHECK_ARG(fread(&sw, sizeof(int64_t), 1, fc.f) == 1 && (sw == 0 || sw == 1),
+                           "fil_restore: truncated checkpoint");
+    FIL_CHECK_ARG((sw == 1) == s->sw,
+                  sw ? "fil_restore: the checkpoint holds a geometric switch's state and the simulation has none"
+                     : "fil_restore: the simulation has a geometric switch and the checkpoint holds no state of it");
+    const size_t M = (size_t)s->M;
+    std::vector<int32_t> dir(sw ? M : 0), age(sw ? M : 0);
+    std::vector<double> tau0(sw ? M : 0);
+    if (sw) {
+        FIL_CHECK_ARG(fread(dir.data(), sizeof(int32_t), M, fc.f) == M && fread(age.data(), sizeof(int32_t), M, fc.f) == M &&
+                          fread(tau0.data(), sizeof(double), M, fc.f) == M,
+                      "fil_restore: truncated checkpoint");
+        for (size_t f = 0; f < M; f++)
+            FIL_CHECK_ARG((dir[f] == 1 || dir[f] == -1) && age[f] >= 0 && std::isfinite(tau0[f]),
+                          "fil_restore: invalid geometric-switch state");
+    }
     // everything read and checked: the simulation is changed only now
     FIL_HIP_TRY(hipStreamSynchronize(s->st));
     FIL_HIP_TRY(hipMemcpy(s->spar, spar.data(), spar.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -1224,6 +1288,11 @@ int fil_restore(fil_sim* s, const char* path) {
     for (size_t i = 0; i < arrays.size(); i++)
         FIL_HIP_TRY(hipMemcpy(arrays[i].first, data[i].data(), arrays[i].second * sizeof(double),
                               hipMemcpyHostToDevice));
+    if (sw) {
+        FIL_HIP_TRY(hipMemcpy(s->swa.dir, dir.data(), M * sizeof(int32_t), hipMemcpyHostToDevice));
+        FIL_HIP_TRY(hipMemcpy(s->swa.age, age.data(), M * sizeof(int32_t), hipMemcpyHostToDevice));
+        FIL_HIP_TRY(hipMemcpy(s->swa.tau0, tau0.data(), M * sizeof(double), hipMemcpyHostToDevice));
+    }
     s->t = t;
     s->step = hdr[3];
     s->pred_iters = 0;

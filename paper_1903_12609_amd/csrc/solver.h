@@ -50,6 +50,7 @@ struct SimDev {
     // cls_fil[cls_off[k] .. cls_off[k+1]), all with 6N <= cls_n[k]
     const int32_t* cls_fil;
     int ncls;
+    int factor_unstaged;           // 1: the band LU never stages rows in LDS (fil_params.j0_factor)
     int64_t cls_off[kMaxCls + 1];
     int cls_n[kMaxCls];
     double a, eta, dL, KB, KT, chi, K0, kw, omega;

@@ -1533,7 +1533,7 @@ int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const 
         // resident at once)
         const size_t fl = factor_lds_bytes(nc);
         const int64_t per_cu = std::min<int64_t>(kFacWavesPerCU, (int64_t)(kLdsPerCU / fl));
-        if (per_cu > 0 && cnt <= kFacStagedRounds * kNumCU * per_cu) {
+        if (!d.factor_unstaged && per_cu > 0 && cnt <= kFacStagedRounds * kNumCU * per_cu) {
             if (int rc = allow_lds(j0_band_factor_kernel<true>, fl)) return rc;
             j0_band_factor_kernel<true><<<(unsigned)cnt, 64, fl, st>>>(d, active, AB, ipiv, rdiag, flag, coff);
         } else {

@@ -78,3 +78,78 @@ def test_network_file_round_trip(tmp_path):
         m3.load(path)
     for m in (m1, m2, m3):
         m.close()
+
+
+def _cilia(graph):
+    import paper_1903_12609_amd as fil
+    import cilia_cases as cc
+    fo, Y, q, p = cc.pair()
+    g = fil.Sim(fo, Y, q, p, graph=graph)
+    g.set_wall()
+    g.set_geometric_switch(cc.AXIS, cc.NORMAL, cc.THETA_MAX, cc.TAU_POS, cc.TAU_NEG, cc.N_TR)
+    return g
+
+
+@pytest.mark.parametrize("graph", [0, 8])
+def test_restore_continues_switch_driven_cilia(tmp_path, graph):
+    """Two pinned cilia on the wall driven by the geometric switch: the checkpoint is taken
+    one step after the first reversal, inside the torque's transition, so the restored run
+    matches only if the switch's direction, age and torque come back with the state."""
+    print("case checkpoint cilia graph", graph, flush=True)
+    a = _cilia(graph)
+    for j in range(60):
+        a.step()
+        if (a.read_switch() < 0).any():
+            break
+    assert (a.read_switch() < 0).any(), "no reversal within 60 steps"
+    a.step()
+    path = tmp_path / "cilia.ckpt"
+    a.checkpoint(path)
+    ra = [a.step()[0]["iters"] for _ in range(8)]
+    da = a.read_switch()
+    Ya, qa, Xa = a.read_state()
+    b = _cilia(graph)
+    b.restore(path)
+    rb = [b.step()[0]["iters"] for _ in range(8)]
+    assert ra == rb
+    assert np.array_equal(da, b.read_switch())
+    Yb, qb, Xb = b.read_state()
+    assert np.array_equal(Ya, Yb) and np.array_equal(qa, qb) and np.array_equal(Xa, Xb)
+    # a simulation without the switch refuses the file, and a switch-driven one refuses a
+    # file without switch state; neither is changed
+    import paper_1903_12609_amd as fil
+    import cilia_cases as cc
+    fo, Y, q, p = cc.pair()
+    c = fil.Sim(fo, Y, q, p)
+    c.set_wall()
+    with pytest.raises(fil.FilError):
+        c.restore(path)
+    c.checkpoint(tmp_path / "plain.ckpt")
+    with pytest.raises(fil.FilError):
+        b.restore(tmp_path / "plain.ckpt")
+    assert np.array_equal(Yb, b.read_state()[0])
+    for s in (a, b, c):
+        s.close()
+
+
+def test_setter_after_failed_first_step_drops_captured_blocks():
+    """The 6 x 6 array of clamped, curvature-driven filaments fails its first step in
+    unbounded fluid (the block-diagonal J0 misses the tether monopoles' coupling) and
+    converges above the wall.  A first step that fails with graph blocks captured, then
+    fil_set_wall, then steps: the blocks captured with the unbounded mobility must not be
+    replayed, so the run equals one that set the wall before stepping."""
+    import paper_1903_12609_amd as fil
+    w = synth.active_array(nx=6, ny=6, N=20, spacing=20.0, seed=1003, base_z=synth.DL)
+    a = fil.Sim(w.fil_off, w.Y, w.q, w.params, graph=8)
+    r = a.step(raise_on_fail=False)
+    assert isinstance(r, tuple) and not r[1][0]["converged"]
+    a.set_wall()
+    c = fil.Sim(w.fil_off, w.Y, w.q, w.params, graph=0)
+    c.set_wall()
+    for j in range(3):
+        ra, rc_ = a.step()[0], c.step()[0]
+        assert ra["iters"] == rc_["iters"] and ra["converged"], (j, ra, rc_)
+    assert np.array_equal(a.read_state()[0], c.read_state()[0])
+    assert np.array_equal(a.read_state()[2], c.read_state()[2])
+    a.close()
+    c.close()

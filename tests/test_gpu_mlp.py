@@ -89,23 +89,73 @@ def test_adam_first_step_closed_form():
     assert np.max(np.abs(P1 - ref)) <= 1e-6 * max(1.0, np.max(np.abs(P)))
 
 
-def test_training_reduces_loss():
-    """Targets that are a fixed smooth function of the inputs are learned."""
+def test_training_matches_fp64_training():
+    """Training on the GPU (BF16 MFMA forward and backward, FP32 Adam) follows exact
+    training: the same network, initial weights (seeded on the host), minibatches and
+    cosine learning-rate schedule trained by the FP64 oracle network reaches a validation
+    loss within 1.3x of it.  The task (targets a fixed smooth function tanh(X A) of the
+    inputs) is learnable: the FP64 training itself ends below 0.15 of the initial loss.
+    (Its last validation loss is 0.13 of its first epoch's, so a 0.1x criterion against the
+    first epoch would fail even in exact arithmetic.)"""
+    import math
     import torch
     import paper_1903_12609_amd as fil
     m = fil.MLP(4, width=64, depth=2, max_batch=256, seed=3)
+    n_in, n_out = m.n_in, m.n_out
     rng = np.random.default_rng(4)
     n = 2048
-    X = rng.standard_normal((n, m.n_in))
-    A = rng.standard_normal((m.n_in, m.n_out)) / np.sqrt(m.n_in)
+    X = rng.standard_normal((n, n_in))
+    A = rng.standard_normal((n_in, n_out)) / np.sqrt(n_in)
     T = np.tanh(X @ A)
-    feat = torch.from_numpy(X.astype(np.float32)).cuda()
-    targ = torch.from_numpy(T.astype(np.float32)).cuda()
-    from paper_1903_12609_amd import learned
-    hist = learned.train(m, feat, targ, epochs=60, batch=256, lr=3e-3)
-    print("loss: first epoch %.4f -> last %.4f (validation %.4f -> %.4f)" % (hist[0][0], hist[-1][0], hist[0][1],
-                                                                          hist[-1][1]))
-    assert hist[-1][1] < 0.3 * hist[0][1]
+    Xs = np.zeros((n, m.n_in_pad))
+    Xs[:, :n_in] = (X - X.mean(0)) / X.std(0)
+    Ts = np.zeros((n, m.n_out_pad))
+    Ts[:, :n_out] = (T - T.mean(0)) / T.std(0)
+    # He-uniform initial weights drawn on the host, padding rows and columns zero
+    ir = np.random.default_rng(5)
+    params = []
+    for l, (din, dout) in enumerate(m.layer_dims):
+        W = ir.uniform(-1.0, 1.0, (dout, din)) * math.sqrt(6.0 / din)
+        if l == 0:
+            W[:, n_in:] = 0.0
+        if l + 1 == len(m.layer_dims):
+            W[n_out:, :] = 0.0
+        params.append((W, np.zeros(dout)))
+    m.set_params(OM.flatten(params).astype(np.float32))
+    params = OM.unflatten(OM.flatten(params).astype(np.float32).astype(np.float64), m.layer_dims)
+    # the data are already standardised: identity normalisation on the GPU
+    m.set_norm(np.concatenate([np.zeros(m.n_in_pad), np.ones(m.n_in_pad), np.zeros(m.n_out_pad),
+                               np.ones(m.n_out_pad)]))
+    xb, t = m.standardize(torch.from_numpy(Xs[:, :n_in].astype(np.float32)).cuda(),
+                          torch.from_numpy(Ts[:, :n_out].astype(np.float32)).cuda())
+    perm = np.random.default_rng(7).permutation(n)
+    va, tr = np.sort(perm[:205]), np.sort(perm[205:])
+    va_d = torch.from_numpy(va.astype(np.int32)).cuda()
+    batch, epochs, lr = 256, 60, 3e-3
+    spe = len(tr) // batch
+    total = epochs * spe
+    mo, vo = OM.zeros_like(params), OM.zeros_like(params)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    l0_or = OM.loss(params, Xs[va], Ts[va], n_out)
+    l0_gpu = m.backward(xb, t, rows=va_d)[0].item()
+    order_rng = np.random.default_rng(8)
+    k = 0
+    for ep in range(epochs):
+        order = tr[order_rng.permutation(len(tr))]
+        for b in range(spe):
+            rows = order[b * batch:(b + 1) * batch]
+            lr_k = 0.5 * lr * (1.0 + math.cos(math.pi * k / total))
+            m.train_step(xb, t, torch.from_numpy(rows.astype(np.int32)).cuda(), lr_k, loss)
+            _, g = OM.gradients(params, Xs[rows], Ts[rows], n_out)
+            k += 1
+            params = OM.adam_step(params, g, mo, vo, k, lr_k)
+    l_or = OM.loss(params, Xs[va], Ts[va], n_out)
+    l_gpu = m.backward(xb, t, rows=va_d)[0].item()
+    m.close()
+    print("validation loss: FP64 %.4f -> %.4f, GPU %.4f -> %.4f" % (l0_or, l_or, l0_gpu, l_gpu))
+    assert abs(l0_gpu - l0_or) <= 2e-2 * l0_or
+    assert l_or <= 0.15 * l0_or
+    assert l_gpu <= 1.3 * l_or
 
 
 def _small_run(steps=5):

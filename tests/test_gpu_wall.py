@@ -199,3 +199,29 @@ def test_motor_filament_parity():
     bad = dict(params, tether=np.array([4], dtype=np.int32))
     with pytest.raises(FilError):
         fil.Sim(np.array([0, N], dtype=np.int64), Y, q, bad)
+
+
+def test_motor_refuses_per_suspension_time_steps():
+    """The motor's angle follows one global time (omega t^{j+1}) while its turn per step is
+    omega dt: suspensions with their own dt cannot share it, in either call order."""
+    import math
+    import paper_1903_12609_amd as fil
+    from paper_1903_12609_amd._native import FilError
+    N = 6
+    q = np.tile([math.cos(-math.pi / 4), 0, math.sin(-math.pi / 4), 0], (2 * N, 1))
+    Y = np.concatenate([synth.chain(np.array([3.0 + 40.0 * i, 0.0, 0.0]), q[:N]) for i in range(2)])
+    params = dict(a=1.0, eta=1.0, dL=synth.DL, KB=1.0, KT=1.0, chi=1.1, FS=0.0, grav=(0.0, 0.0, 0.0), dt=1.0,
+                  tol=1e-8, kmax=100, tether=np.array([3, 3], dtype=np.int32), base=Y[[0, N]].copy())
+    fo, sfo = np.array([0, N, 2 * N], dtype=np.int64), np.array([0, 1, 2], dtype=np.int64)
+    g = fil.Sim(fo, Y, q, params, susp_fil_off=sfo)
+    g.set_motor(3.0, 0.01)
+    with pytest.raises(FilError):
+        g.set_suspension_params(dt=[1.0, 2.0])
+    g.set_suspension_params(dt=[1.0, 1.0])        # equal steps stay allowed
+    g.close()
+    g = fil.Sim(fo, Y, q, params, susp_fil_off=sfo)
+    g.set_suspension_params(dt=[1.0, 2.0])
+    with pytest.raises(FilError):
+        g.set_motor(3.0, 0.01)
+    g.set_motor(3.0, 0.0)                         # a motor that does not turn is allowed
+    g.close()

@@ -255,3 +255,37 @@ def test_motor_filament_limits():
         assert rc == 0
         ds.append(math.hypot(*sim.Y[-1, :2]) / d_rigid)
     assert ds[-1] < 0.9 and ds[-1] < ds[19]
+
+
+@pytest.mark.parametrize("tether", [0, 1])
+def test_j0_with_preferred_curvature_equals_drag_jacobian_at_straight_state(tether):
+    """Appendix B.2 with a preferred curvature: the moment carries -R(q_{n+1/2}) D kappa,
+    whose derivative in u is taken from the rotation of the frame vectors.  At u = 0 on a
+    straight, untwisted filament the midpoint frame turns by exactly half of each
+    neighbour's rotation to first order, so J0 (its kappa_nu entries included) must equal
+    the drag-only Jacobian there, free and clamped, with the drive of Sec. 5.3 at a set
+    phase and time (reading R5: kappa_nu only)."""
+    N = 6
+    L = N * synth.DL
+    q0 = np.array([math.cos(-math.pi / 4), 0, math.sin(-math.pi / 4), 0]) if tether else \
+        synth.random_unit_quaternion(np.random.default_rng(14))
+    q = np.tile(q0, (N, 1))
+    Y = synth.chain(np.array([0.5, -1.0, 2.0]), q)
+    extra = dict(tether=[1], base=Y[:1]) if tether else {}
+    sim = oracle.Sim([0, N], Y, q, dt=1.7, drag_only=1, KB=1.2, KT=0.8, K0=10.61 / L, kw=2 * math.pi / L,
+                     omega=0.37, phase=[1.1], **extra)
+    sim.St.step = 3
+    sim.St.t = 2.9
+    rng = np.random.default_rng(15 + tether)
+    X = np.zeros(6 * N)
+    X[:3] = rng.standard_normal(3) if tether else Y[0] + rng.standard_normal(3)
+    if tether:
+        X[3:6] = rng.standard_normal(3)
+    X[3 + 3 * N:] = rng.standard_normal(3 * (N - 1))
+    J0 = sim.j0_filament(0, X)
+    Jfd = fd_jacobian(lambda x: sim.residual(x)[0], X)
+    # the drive is large: without the kappa terms of dM/du this test must fail
+    sim0 = oracle.Sim([0, N], Y, q, dt=1.7, drag_only=1, KB=1.2, KT=0.8, **extra)
+    sim0.St.step, sim0.St.t = 3, 2.9
+    assert np.abs(sim0.j0_filament(0, X) - Jfd).max() > 1e-3 * np.abs(Jfd).max()
+    assert np.allclose(J0, Jfd, rtol=0, atol=1e-7 * np.abs(Jfd).max())
