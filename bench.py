@@ -1,19 +1,21 @@
-"""Benchmark: implicit filament steps on one MI355X.
+"""Benchmark: the RPY mobility apply and the implicit filament steps on one MI355X.
 
-Workload: the sedimenting suspension of 100 filaments x 20 segments (2,000
-segments), every segment under gravity, steric barrier on, RPY hydrodynamics,
-BDF2 steps solved by bad Broyden with the explicit block-diagonal J0 to a
-1e-6 residual (max|f|/a).  One "step" is one full implicit time step (warm
-start, J0 and its inverse, every Broyden iteration with its mobility apply,
-finalisation); the FP64 iterations run in captured HIP-graph blocks.
+Headline workload: the mobility apply of the active array's size and layout, 1000
+filaments x 32 segments (S = 32,000) on a 40 x 25 lattice of spacing 20a, bent as planar
+arcs, F, T ~ N(0, 1), with FP32 pair tiles and FP64 per-target accumulation.  One "step"
+is one apply (source packing, the pair kernel over all S^2 ordered pairs, the fixed-order
+reduction of the split-K partials), inputs resident on the GPU.
 
-Prints one JSON line: value = RPY pair-interactions per second of whole-step
-wall time (mobility applies x S^2 / elapsed), ms_per_step, the roofline of
-the mobility pair kernel (its duration measured with HIP events on the stream
-it runs on, inside the timed steps), the same steps with FP32 pair tiles, the
-stand-alone mobility apply at the workload sizes (FP64 and FP32 tiles, and the
-ragged 256-suspension batch), the learned warm start against plain Broyden on
-the 500 x 32 suspension, and the CPU oracle's rate on a bounded sample.
+Prints one JSON line: value = pair interactions per second of the FP32-tile apply
+(S^2 / wall time per apply), ms_per_step = wall ms per apply, the roofline of the pair
+kernel (its duration stamped by HIP events at the kernel's own start and end, on the
+stream it runs on, in every timed apply), the same apply in FP64 beside it, and, unless
+switched off: the implicit steps of the sedimenting suspension (100 x 20) in FP64 and
+with FP32 tiles, stand-alone applies at other sizes and the ragged 256-suspension batch,
+the 256-suspension ensemble's implicit steps, the force-coupling and wall mobilities,
+the solver comparison, the learned warm start against plain Broyden, and the CPU
+oracle's rate on a bounded sample of the headline apply (all host cores and one core)
+with the GPU results' error against it.
 """
 from __future__ import annotations
 
@@ -32,7 +34,10 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector peak
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (packed)
 PEAK_HBM_GBS = 8000.0
 GRAPH_ITERS = 32            # Broyden iterations per captured graph block (at most)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rpy_f64_sediment2000_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rpy_f32_active32000_traffic.json")
+HEADLINE_WORKLOAD = ("RPY mobility apply, active-array layout: 1000 filaments x 32 segments (S=32000) on a 40 x 25 "
+                     "lattice of spacing 20a, planar arcs (bend <= 0.05 rad per segment), F, T ~ N(0,1); FP32 pair "
+                     "tiles with FP64 per-target accumulation")
 
 
 def log(*a):
@@ -52,6 +57,38 @@ def _time_applies(fn, reps):
     e1.record(st)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def apply_headline(steps, warmup):
+    """K timed applies (after W untimed ones) of the active array's mobility in FP32 tiles
+    and in FP64: wall time per apply between synchronisations, and the pair kernel's own
+    duration from HIP events the library stamps at its start and end."""
+    import torch
+    import paper_1903_12609_amd as fil
+    from paper_1903_12609_amd import synth
+    Y, F, T = synth.active_array_mobility_inputs()
+    S = Y.shape[0]
+    d = lambda a: torch.from_numpy(a.T.copy()).cuda()
+    Yd, Fd, Td = d(Y), d(F), d(T)
+    out = {}
+    for prec in ("f32tile", "f64"):
+        V, W = torch.empty_like(Yd), torch.empty_like(Yd)
+        work = torch.empty(fil.rpy_workspace_bytes(S, prec), dtype=torch.uint8, device="cuda")
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for _ in range(warmup):
+            fil.rpy_mobility_apply(Yd, Fd, Td, 1.0, 1.0, prec, V, W, work)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            fil.rpy_mobility_apply(Yd, Fd, Td, 1.0, 1.0, prec, V, W, work, events=evs[i])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kern_ms = [a.elapsed_time(b) for a, b in evs]
+        out[prec] = dict(S=S, wall_s=el, ms_per_apply=el / steps * 1e3, pairs_per_s=float(S) ** 2 * steps / el,
+                         kernel_avg_us=sum(kern_ms) / steps * 1e3, kernel_min_us=min(kern_ms) * 1e3,
+                         V=V.cpu().numpy().T.copy(), W=W.cpu().numpy().T.copy())
+        log("headline apply", prec, {k: v for k, v in out[prec].items() if k not in ("V", "W")})
+    return out, (Y, F, T)
 
 
 def rpy_sweep(sizes=(2000, 16000, 32000), reps=10):
@@ -94,7 +131,10 @@ def rpy_batched(reps=5):
     pairs = float(sum(n * n for n in sizes))
     for prec in ("f64", "f32tile"):
         V, W = torch.empty_like(Yd), torch.empty_like(Yd)
-        t = _time_applies(lambda: fil.rpy_mobility_apply_batched(off, Yd, Fd, Td, 1.0, 1.0, prec, V, W), reps)
+        plan = fil.RpyBatch(off, prec)     # the work list is built once; applies only enqueue
+        work = torch.empty(max(plan.work_bytes, 1), dtype=torch.uint8, device="cuda")
+        t = _time_applies(lambda: plan.apply(Yd, Fd, Td, 1.0, 1.0, V, W, work), reps)
+        plan.close()
         peak = PEAK_FP64_TFLOPS if prec == "f64" else PEAK_FP32_TFLOPS
         out.append(dict(suspensions=256, segments=S, pairs=pairs, prec=prec, ms=round(t * 1e3, 4),
                         pairs_per_s=pairs / t, tflops=FLOP_PER_PAIR * pairs / t / 1e12,
@@ -333,8 +373,8 @@ def cilia_array_steps(steps=40, dt=25000.0, n_tr=10, tau=0.02):
 
 
 def traffic_per_launch():
-    """HBM bytes per launch of the FP64 pair kernel from the committed rocprofv3
-    counter summary, or None when the kernel source changed since it was taken."""
+    """HBM bytes per launch of the FP32-tile pair kernel from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -347,22 +387,63 @@ def traffic_per_launch():
         return None
 
 
-def cpu_baseline(w, budget_s=12.0):
-    """The FP64 oracle on the host cores, on a bounded sample of the same workload
-    (whole steps until about budget_s seconds have passed)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(inputs, gpu):
+    """The FP64 oracle on a bounded sample of the headline apply: all S targets against all
+    S sources on every host core, and 1000 targets on one core (both in pairs/s), and the
+    GPU results' relative L2 error against the oracle's on those targets."""
+    import numpy as np
     import oracle
+    Y, F, T = inputs
+    S = Y.shape[0]
     nthreads = len(os.sched_getaffinity(0))
-    sim = oracle.Sim(w.fil_off, w.Y, w.q, nthreads=nthreads, **w.params)
-    applies, steps = 0, 0
     t0 = time.perf_counter()
-    while steps < 2 or time.perf_counter() - t0 < budget_s:
-        rc, rep = sim.step()
-        applies += rep.applies
-        steps += 1
-    dt = time.perf_counter() - t0
-    return dict(value=applies * float(w.S) ** 2 / dt, unit="pairs/s", cores=nthreads, kind="oracle",
-                sample="first %d implicit steps (%d mobility applies) of the %d-segment suspension, %.1f s" %
-                       (steps, applies, w.S, dt), ms_per_step=dt / steps * 1e3)
+    V0, W0 = oracle.rpy_apply(Y, F, T, 1.0, 1.0, nthreads=nthreads)
+    t_all = time.perf_counter() - t0
+    idx = np.sort(np.random.default_rng(5).choice(S, 1000, replace=False))
+    t0 = time.perf_counter()
+    oracle.rpy_apply_targets(Y, F, T, 1.0, 1.0, idx, nthreads=1)
+    t_one = time.perf_counter() - t0
+    err = lambda x, r: float(np.linalg.norm(x - r) / np.linalg.norm(r))
+    errors = {prec: {"V_rel_l2": err(gpu[prec]["V"], V0), "Omega_rel_l2": err(gpu[prec]["W"], W0)}
+              for prec in gpu}
+    log("cpu baseline: all cores %.2f s, one core %.2f s; errors %s" % (t_all, t_one, errors))
+    return dict(value=float(S) ** 2 / t_all, unit="pairs/s", cores=nthreads, kind="oracle", cpu_model=_cpu_model(),
+                sample="one FP64 apply of the headline workload (all %d targets x %d sources), %.1f s on %d threads"
+                       % (S, S, t_all, nthreads),
+                one_core={"value": 1000.0 * S / t_one, "unit": "pairs/s", "cores": 1,
+                          "sample": "1000 sampled targets x %d sources, %.1f s" % (S, t_one)},
+                gpu_error_vs_oracle=errors)
+
+
+def sediment_steps(steps, warmup, graph):
+    """Implicit steps of the sedimenting suspension (100 x 20, S = 2000) in FP64 and with FP32
+    tiles: ms per step, iterations, pair-kernel time inside the steps."""
+    from paper_1903_12609_amd import synth
+    w = synth.sediment_suspension(M=100, N=20, side=200.0, seed=1002, dt_over_T=1 / 30)
+    S = w.S
+    out = {"workload": "sedimenting suspension, 100 filaments x 20 segments (S=2000), B=1e3, dt=T/30, tol 1e-6, "
+                       "steric on, unbounded RPY; Broyden iterations in graph blocks of %d" % graph}
+    for prec in ("f64", "f32tile"):
+        el, applies, iters, tm = run_steps(w, prec, steps, warmup, graph)
+        ms, nl = tm[prec]
+        kern_s = ms * 1e-3 / max(nl, 1)
+        out[prec] = {"ms_per_step": el / steps * 1e3, "pairs_per_s": applies * float(S) ** 2 / el,
+                     "iters_per_step": iters / steps, "mobility_applies_per_step": applies / steps,
+                     "pair_kernel_avg_us": kern_s * 1e6, "pair_kernel_launches_timed": nl,
+                     "pair_kernel_tflops": FLOP_PER_PAIR * float(S) ** 2 / kern_s / 1e12}
+        log("sediment steps", prec, out[prec])
+    return out, w
 
 
 def main():
@@ -379,6 +460,8 @@ def main():
     ap.add_argument("--no-solvers", action="store_true", help="skip the Broyden vs Newton-Krylov comparison")
     ap.add_argument("--fcm-only", action="store_true", help="only the FCM applies (for profiling)")
     ap.add_argument("--wall-only", action="store_true", help="only the wall-bounded mobility (for profiling)")
+    ap.add_argument("--rpy-only", action="store_true", help="only the stand-alone mobility applies (for profiling)")
+    ap.add_argument("--headline-only", action="store_true", help="only the headline applies (for profiling)")
     ap.add_argument("--fcm-steps-only", action="store_true",
                     help="only the solver comparison on the periodic FCM monolayer (for profiling)")
     args = ap.parse_args()
@@ -391,6 +474,9 @@ def main():
     if args.fcm_only:
         print(json.dumps({"fcm_apply": fcm_apply_bench()}))
         return
+    if args.rpy_only:
+        print(json.dumps({"rpy_apply": rpy_sweep(), "rpy_apply_batched": rpy_batched()}))
+        return
     if args.wall_only:
         print(json.dumps({"wall_mobility": wall_mobility_bench()}))
         return
@@ -398,55 +484,50 @@ def main():
         print(json.dumps({"fcm_monolayer_solvers": fcm_monolayer_steps()}))
         return
 
-    w = synth.sediment_suspension(M=100, N=20, side=200.0, seed=1002, dt_over_T=1 / 30)
-    S = w.S
-    el, applies, iters, tm = run_steps(w, "f64", args.steps, args.warmup, args.graph)
-    rpy_ms, nl = tm["f64"]
-    kern_s = rpy_ms * 1e-3 / max(nl, 1)
+    head, inputs = apply_headline(args.steps, args.warmup)
+    h32, h64 = head["f32tile"], head["f64"]
+    S = h32["S"]
     flop = FLOP_PER_PAIR * float(S) ** 2
-    achieved = flop / kern_s / 1e12
-    traffic = traffic_per_launch()
+    achieved = flop / (h32["kernel_avg_us"] * 1e-6) / 1e12
     res = {
         "metric": "RPY pair-interactions/s (fp64 vs fp32) + ms/step to tol, plain vs learned",
-        "value": applies * float(S) ** 2 / el,
+        "value": h32["pairs_per_s"],
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
+        "ms_per_step": h32["ms_per_apply"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "sedimenting suspension, 100 filaments x 20 segments (S=2000), B=1e3, "
-                               "dt=T/30, tol 1e-6, steric on, unbounded RPY", "segments": S,
-                   "precision": "f64", "graph_iters": args.graph},
-        "iters_per_step": iters / args.steps,
-        "mobility_applies_per_step": applies / args.steps,
-        "roofline": {"bound": "alu", "kernel": "rpy_f64_kernel", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "avg_kernel_us": kern_s * 1e6, "launches": nl, "flop_per_launch": flop},
+        "config": {"workload": HEADLINE_WORKLOAD, "segments": S, "pairs_per_apply": float(S) ** 2,
+                   "precision": "f32tile", "step": "one mobility apply"},
+        "roofline": {"bound": "alu", "kernel": "rpy_f32_kernel<2,1>", "achieved": achieved,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": traffic_per_launch(), "avg_kernel_us": h32["kernel_avg_us"], "launches": args.steps,
+                     "flop_per_launch": flop, "flop_per_pair": FLOP_PER_PAIR},
+        "f64_apply": {"ms_per_apply": h64["ms_per_apply"], "pairs_per_s": h64["pairs_per_s"],
+                      "kernel_avg_us": h64["kernel_avg_us"],
+                      "kernel_tflops": flop / (h64["kernel_avg_us"] * 1e-6) / 1e12,
+                      "frac_of_fp64_peak": flop / (h64["kernel_avg_us"] * 1e-6) / 1e12 / PEAK_FP64_TFLOPS},
+        "f32_over_f64_time": h64["ms_per_apply"] / h32["ms_per_apply"],
     }
-    el32, ap32, it32, tm32 = run_steps(w, "f32tile", args.steps, args.warmup, args.graph)
-    ms32, n32 = tm32["f32tile"]
-    res["f32tile_steps"] = {"value": ap32 * float(S) ** 2 / el32, "ms_per_step": el32 / args.steps * 1e3,
-                            "iters_per_step": it32 / args.steps, "mobility_applies_per_step": ap32 / args.steps,
-                            "f32_kernel_avg_us": ms32 * 1e3 / max(n32, 1)}
-    log("f32tile steps", res["f32tile_steps"])
-    if not args.no_sweep:
-        res["rpy_apply"] = rpy_sweep()
-        res["rpy_apply_batched"] = rpy_batched()
-    if not args.no_sweep:
-        res["fcm_apply"] = fcm_apply_bench()
-        res["wall_mobility"] = wall_mobility_bench()
-    if not args.no_solvers:
-        res["solver_comparison"] = solver_comparison(w)
-        res["fcm_monolayer_solvers"] = fcm_monolayer_steps()
-    if not args.no_learned:
-        res["learned_warm_start"] = learned_gain(log)
+    if not args.headline_only:
+        res["sediment2000_steps"], w = sediment_steps(args.steps, args.warmup, args.graph)
+        if not args.no_sweep:
+            res["rpy_apply"] = rpy_sweep()
+            res["rpy_apply_batched"] = rpy_batched()
+            res["fcm_apply"] = fcm_apply_bench()
+            res["wall_mobility"] = wall_mobility_bench()
+        if not args.no_solvers:
+            res["solver_comparison"] = solver_comparison(w)
+            res["fcm_monolayer_solvers"] = fcm_monolayer_steps()
+        if not args.no_learned:
+            res["learned_warm_start"] = learned_gain(log)
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(w)
+        res["cpu_baseline"] = cpu_baseline(inputs, head)
     print(json.dumps(res))
 
 

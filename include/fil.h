@@ -71,6 +71,14 @@ int64_t fil_rpy_workspace_bytes(int64_t S, int prec);
 int fil_rpy_mobility_apply(int64_t S, const double* Y, const double* F, const double* T, double a, double eta,
                            int prec, double* V, double* Omega, void* work, int64_t work_bytes, void* stream);
 
+/* The same apply with its main pair kernel bracketed by two caller-created HIP events
+ * (hipEvent_t, NULL for none): ev_start is stamped when the pair kernel starts and ev_end
+ * when it ends (extended launch), so hipEventElapsedTime(ev_start, ev_end) is that kernel's
+ * own duration; for profiling.  Arguments and errors otherwise as fil_rpy_mobility_apply. */
+int fil_rpy_mobility_apply_timed(int64_t S, const double* Y, const double* F, const double* T, double a, double eta,
+                                 int prec, double* V, double* Omega, void* work, int64_t work_bytes, void* ev_start,
+                                 void* ev_end, void* stream);
+
 /* RPY mobility of the segments above a no-slip plane wall z = 0 (the half-space tensor
  * the paper uses for its cilia, Sec. 2.7.1 and Sec. 5.3): the unbounded tensor of
  * fil_rpy_mobility_apply (same overlap forms) plus the wall's image part, Blake's image
@@ -113,13 +121,27 @@ int fil_fcm_apply(fil_fcm* fcm, int64_t S, const double* Y, const double* F, con
 void fil_fcm_destroy(fil_fcm* fcm);
 
 /* Batched form: nsusp independent suspensions in one launch; suspension i owns
- * segments susp_off[i] .. susp_off[i+1]-1 and interacts only with itself.
- * susp_off is a HOST int64[nsusp+1] (non-decreasing, susp_off[0] = 0);
- * arrays as above over S = susp_off[nsusp] segments. */
-int64_t fil_rpy_batched_workspace_bytes(int64_t nsusp, const int64_t* susp_off, int prec);
-int fil_rpy_mobility_apply_batched(int64_t nsusp, const int64_t* susp_off, const double* Y, const double* F,
-                                   const double* T, double a, double eta, int prec, double* V, double* Omega,
-                                   void* work, int64_t work_bytes, void* stream);
+ * segments susp_off[i] .. susp_off[i+1]-1 and interacts only with itself.  A plan holds
+ * the work list of one set of offsets and one precision: fil_rpy_batch_create builds and
+ * sorts it on the host, allocates its device copy on the current device and copies it there
+ * (synchronously; FIL_ENOMEM, FIL_EHIP on failure).  The apply then only enqueues work on
+ * `stream`: no allocation, no host copy and no synchronisation.
+ *   susp_off   HOST int64[nsusp+1], non-decreasing, susp_off[0] = 0 (copied)
+ *   prec       FIL_PREC_F64 or FIL_PREC_F32TILE
+ * fil_rpy_batch_workspace_bytes: device scratch of one apply (source records, FP32 tile
+ *   records, split-K partials), -1 for a null plan.
+ * fil_rpy_mobility_apply_batched: Y, F, T, a, eta, V, Omega as fil_rpy_mobility_apply over
+ *   S = susp_off[nsusp] segments, on the device the plan was created on; work of at least
+ *   fil_rpy_batch_workspace_bytes(plan) bytes (NULL when 0).  Applies in flight may share a
+ *   plan but not a workspace.  Deterministic.
+ * fil_rpy_batch_destroy frees the plan (after the applies that use it have completed). */
+typedef struct fil_rpy_batch fil_rpy_batch;
+int fil_rpy_batch_create(int64_t nsusp, const int64_t* susp_off, int prec, fil_rpy_batch** out);
+int64_t fil_rpy_batch_workspace_bytes(const fil_rpy_batch* plan);
+int fil_rpy_mobility_apply_batched(const fil_rpy_batch* plan, const double* Y, const double* F, const double* T,
+                                   double a, double eta, double* V, double* Omega, void* work, int64_t work_bytes,
+                                   void* stream);
+void fil_rpy_batch_destroy(fil_rpy_batch* plan);
 
 /* ------------------------------------------------------------------------ */
 /* Filament mechanics                                                        */

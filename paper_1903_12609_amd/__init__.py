@@ -35,9 +35,10 @@ def rpy_workspace_bytes(S, prec="f64"):
     return int(lib().fil_rpy_workspace_bytes(int(S), PREC[prec]))
 
 
-def rpy_mobility_apply(Y, F, T, a=1.0, eta=1.0, prec="f64", V=None, W=None, work=None):
+def rpy_mobility_apply(Y, F, T, a=1.0, eta=1.0, prec="f64", V=None, W=None, work=None, events=None):
     """(V, Omega) = RPY mobility (Sec. 2.7.1) applied to forces F and torques T at
-    positions Y; all float64 CUDA tensors of shape (3, S)."""
+    positions Y; all float64 CUDA tensors of shape (3, S).  events: optional pair of
+    torch.cuda.Event (enable_timing) stamped at the start and end of the pair kernel."""
     import torch
     S = Y.shape[1]
     for n, t in (("Y", Y), ("F", F), ("T", T)):
@@ -47,8 +48,14 @@ def rpy_mobility_apply(Y, F, T, a=1.0, eta=1.0, prec="f64", V=None, W=None, work
     nb = rpy_workspace_bytes(S, prec)
     if work is None or work.numel() < nb:
         work = torch.empty(max(nb, 1), dtype=torch.uint8, device=Y.device)
-    check(lib().fil_rpy_mobility_apply(S, _ptr(Y), _ptr(F), _ptr(T), float(a), float(eta), PREC[prec], _ptr(V),
-                                       _ptr(W), _ptr(work), work.numel(), _stream()))
+    evs = (None, None)
+    if events is not None:
+        for e in events:
+            if not e.cuda_event:  # torch creates the event at its first record
+                e.record()
+        evs = (events[0].cuda_event, events[1].cuda_event)
+    check(lib().fil_rpy_mobility_apply_timed(S, _ptr(Y), _ptr(F), _ptr(T), float(a), float(eta), PREC[prec],
+                                             _ptr(V), _ptr(W), _ptr(work), work.numel(), evs[0], evs[1], _stream()))
     return V, W
 
 
@@ -89,23 +96,55 @@ def filament_internal_forces(fil_off, q, Lam, kappa, dL, KB, KT, F, T):
     return F, T
 
 
+class RpyBatch:
+    """Plan of the batched mobility apply for suspensions at the host offsets susp_off
+    [nsusp+1] in one precision; its applies only enqueue work."""
+
+    def __init__(self, susp_off, prec="f64"):
+        import ctypes
+        import numpy as np
+        off = np.ascontiguousarray(susp_off, dtype=np.int64)
+        self.S = int(off[-1])
+        h = ctypes.c_void_p()
+        check(lib().fil_rpy_batch_create(len(off) - 1, off.ctypes.data_as(ctypes.c_void_p), PREC[prec],
+                                         ctypes.byref(h)))
+        self._h = h
+        self.work_bytes = int(lib().fil_rpy_batch_workspace_bytes(h))
+
+    def apply(self, Y, F, T, a=1.0, eta=1.0, V=None, W=None, work=None):
+        import torch
+        for n, t in (("Y", Y), ("F", F), ("T", T)):
+            _check_soa(n, t, 3, self.S)
+        V = torch.empty_like(Y) if V is None else V
+        W = torch.empty_like(Y) if W is None else W
+        if work is None:
+            work = torch.empty(max(self.work_bytes, 1), dtype=torch.uint8, device=Y.device)
+        check(lib().fil_rpy_mobility_apply_batched(self._h, _ptr(Y), _ptr(F), _ptr(T), float(a), float(eta), _ptr(V),
+                                                   _ptr(W), _ptr(work), work.numel(), _stream()))
+        return V, W
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fil_rpy_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def rpy_mobility_apply_batched(susp_off, Y, F, T, a=1.0, eta=1.0, prec="f64", V=None, W=None):
-    """Independent suspensions in one persistent launch; susp_off: host int sequence [nsusp+1]."""
-    import ctypes
-    import numpy as np
-    import torch
-    off = np.ascontiguousarray(susp_off, dtype=np.int64)
-    S = int(off[-1])
-    for n, t in (("Y", Y), ("F", F), ("T", T)):
-        _check_soa(n, t, 3, S)
-    V = torch.empty_like(Y) if V is None else V
-    W = torch.empty_like(Y) if W is None else W
-    nb = int(lib().fil_rpy_batched_workspace_bytes(len(off) - 1, off.ctypes.data_as(ctypes.c_void_p), PREC[prec]))
-    work = torch.empty(max(nb, 1), dtype=torch.uint8, device=Y.device)
-    check(lib().fil_rpy_mobility_apply_batched(len(off) - 1, off.ctypes.data_as(ctypes.c_void_p), _ptr(Y), _ptr(F),
-                                               _ptr(T), float(a), float(eta), PREC[prec], _ptr(V), _ptr(W),
-                                               _ptr(work), work.numel(), _stream()))
-    return V, W
+    """Independent suspensions in one persistent launch; susp_off: host int sequence [nsusp+1]
+    (builds a plan for this one call)."""
+    plan = RpyBatch(susp_off, prec)
+    try:
+        return plan.apply(Y, F, T, a, eta, V, W)
+    finally:
+        import torch
+        torch.cuda.current_stream().synchronize()  # the plan is freed after the apply has run
+        plan.close()
 
 
 class _DevView:

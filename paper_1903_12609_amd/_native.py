@@ -51,14 +51,14 @@ def _declare(L):
     L.fil_rpy_workspace_bytes.argtypes = [_i64, _i]
     L.fil_rpy_workspace_bytes.restype = _i64
     L.fil_rpy_mobility_apply.argtypes = [_i64, _vp, _vp, _vp, _d, _d, _i, _vp, _vp, _vp, _i64, _vp]
+    L.fil_rpy_mobility_apply_timed.argtypes = [_i64, _vp, _vp, _vp, _d, _d, _i, _vp, _vp, _vp, _i64, _vp, _vp, _vp]
     L.fil_filament_internal_forces.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _d, _d, _d, _vp, _vp, _vp]
-    for name in ("fil_rpy_batched_workspace_bytes",):
-        if hasattr(L, name):
-            getattr(L, name).argtypes = [_i64, _vp, _i]
-            getattr(L, name).restype = _i64
-    if hasattr(L, "fil_rpy_mobility_apply_batched"):
-        L.fil_rpy_mobility_apply_batched.argtypes = [_i64, _vp, _vp, _vp, _vp, _d, _d, _i, _vp, _vp, _vp, _i64,
-                                                     _vp]
+    L.fil_rpy_batch_create.argtypes = [_i64, _vp, _i, C.POINTER(_vp)]
+    L.fil_rpy_batch_workspace_bytes.argtypes = [_vp]
+    L.fil_rpy_batch_workspace_bytes.restype = _i64
+    L.fil_rpy_mobility_apply_batched.argtypes = [_vp, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp, _i64, _vp]
+    L.fil_rpy_batch_destroy.argtypes = [_vp]
+    L.fil_rpy_batch_destroy.restype = None
     if hasattr(L, "fil_create"):
         L.fil_create.argtypes = [C.POINTER(Params), _i64, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)]
         L.fil_destroy.argtypes = [_vp]

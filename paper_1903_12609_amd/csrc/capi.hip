@@ -26,6 +26,13 @@ int64_t fil_rpy_workspace_bytes(int64_t S, int prec) {
 
 int fil_rpy_mobility_apply(int64_t S, const double* Y, const double* F, const double* T, double a, double eta,
                            int prec, double* V, double* Omega, void* work, int64_t work_bytes, void* stream) {
+    return fil_rpy_mobility_apply_timed(S, Y, F, T, a, eta, prec, V, Omega, work, work_bytes, nullptr, nullptr,
+                                        stream);
+}
+
+int fil_rpy_mobility_apply_timed(int64_t S, const double* Y, const double* F, const double* T, double a, double eta,
+                                 int prec, double* V, double* Omega, void* work, int64_t work_bytes, void* ev_start,
+                                 void* ev_end, void* stream) {
     FIL_CHECK_ARG(S >= 0, "fil_rpy_mobility_apply: S < 0");
     FIL_CHECK_ARG(prec == FIL_PREC_F64 || prec == FIL_PREC_F32TILE, "fil_rpy_mobility_apply: unknown precision");
     FIL_CHECK_ARG(std::isfinite(a) && a > 0 && std::isfinite(eta) && eta > 0,
@@ -37,41 +44,75 @@ int fil_rpy_mobility_apply(int64_t S, const double* Y, const double* F, const do
     const RpyPlan p = rpy_plan(S, prec);
     FIL_CHECK_ARG(work_bytes >= (int64_t)p.total() && (work || p.total() == 0),
                   "fil_rpy_mobility_apply: workspace smaller than fil_rpy_workspace_bytes()");
-    return rpy_launch(p, Y, F, T, a, eta, V, Omega, work, (hipStream_t)stream);
+    return rpy_launch(p, Y, F, T, a, eta, V, Omega, work, (hipStream_t)stream, (hipEvent_t)ev_start,
+                      (hipEvent_t)ev_end);
 }
 
-int64_t fil_rpy_batched_workspace_bytes(int64_t nsusp, const int64_t* susp_off, int prec) {
-    if (nsusp < 1 || !susp_off || susp_off[0] != 0 || (prec != FIL_PREC_F64 && prec != FIL_PREC_F32TILE)) return -1;
+}  // extern "C"
+
+struct fil_rpy_batch {
+    RpyBatchPlan p;
+    void* lists = nullptr;  // device copy of the work list
+};
+
+extern "C" {
+
+int fil_rpy_batch_create(int64_t nsusp, const int64_t* susp_off, int prec, fil_rpy_batch** out) {
+    FIL_CHECK_ARG(out, "fil_rpy_batch_create: out is null");
+    *out = nullptr;
+    FIL_CHECK_ARG(nsusp >= 1 && susp_off && susp_off[0] == 0, "fil_rpy_batch_create: bad offsets");
     for (int64_t i = 0; i < nsusp; i++)
-        if (susp_off[i + 1] < susp_off[i]) return -1;
-    return (int64_t)rpy_batch_plan(nsusp, susp_off, prec).total();
+        FIL_CHECK_ARG(susp_off[i + 1] >= susp_off[i], "fil_rpy_batch_create: offsets must not decrease");
+    FIL_CHECK_ARG(susp_off[nsusp] <= ((int64_t)1 << 31) - 1, "fil_rpy_batch_create: more than 2^31 - 1 segments");
+    FIL_CHECK_ARG(prec == FIL_PREC_F64 || prec == FIL_PREC_F32TILE, "fil_rpy_batch_create: unknown precision");
+    fil_rpy_batch* b = new fil_rpy_batch();
+    b->p = rpy_batch_plan(nsusp, susp_off, prec);
+    const size_t nb = b->p.lists_bytes();
+    if (nb > 0) {
+        if (hipMalloc(&b->lists, nb) != hipSuccess) {
+            delete b;
+            set_error("fil_rpy_batch_create: out of device memory");
+            return FIL_ENOMEM;
+        }
+        int rc = rpy_batch_upload(b->p, b->lists, nullptr);
+        if (rc == FIL_OK && hipStreamSynchronize(nullptr) != hipSuccess) {
+            set_error("fil_rpy_batch_create: copy of the work list failed");
+            rc = FIL_EHIP;
+        }
+        if (rc) {
+            (void)hipFree(b->lists);
+            delete b;
+            return rc;
+        }
+    }
+    *out = b;
+    return FIL_OK;
 }
 
-int fil_rpy_mobility_apply_batched(int64_t nsusp, const int64_t* susp_off, const double* Y, const double* F,
-                                   const double* T, double a, double eta, int prec, double* V, double* Omega,
-                                   void* work, int64_t work_bytes, void* stream) {
-    FIL_CHECK_ARG(nsusp >= 1 && susp_off && susp_off[0] == 0, "fil_rpy_mobility_apply_batched: bad offsets");
-    for (int64_t i = 0; i < nsusp; i++)
-        FIL_CHECK_ARG(susp_off[i + 1] >= susp_off[i], "fil_rpy_mobility_apply_batched: offsets must not decrease");
-    FIL_CHECK_ARG(prec == FIL_PREC_F64 || prec == FIL_PREC_F32TILE,
-                  "fil_rpy_mobility_apply_batched: unknown precision");
+int64_t fil_rpy_batch_workspace_bytes(const fil_rpy_batch* plan) {
+    return plan ? (int64_t)plan->p.work_bytes() : -1;
+}
+
+int fil_rpy_mobility_apply_batched(const fil_rpy_batch* plan, const double* Y, const double* F, const double* T,
+                                   double a, double eta, double* V, double* Omega, void* work, int64_t work_bytes,
+                                   void* stream) {
+    FIL_CHECK_ARG(plan, "fil_rpy_mobility_apply_batched: null plan");
     FIL_CHECK_ARG(std::isfinite(a) && a > 0 && std::isfinite(eta) && eta > 0,
                   "fil_rpy_mobility_apply_batched: a and eta must be finite and > 0");
-    const int64_t S = susp_off[nsusp];
-    if (S == 0) return FIL_OK;
+    const RpyBatchPlan& p = plan->p;
+    if (p.Sg == 0) return FIL_OK;
     FIL_CHECK_ARG(Y && F && T && V && Omega, "fil_rpy_mobility_apply_batched: null array");
     FIL_CHECK_ARG(V != Omega && V != Y && V != F && V != T && Omega != Y && Omega != F && Omega != T,
                   "fil_rpy_mobility_apply_batched: outputs alias inputs");
-    const RpyBatchPlan p = rpy_batch_plan(nsusp, susp_off, prec);
-    FIL_CHECK_ARG(work && work_bytes >= (int64_t)p.total(),
-                  "fil_rpy_mobility_apply_batched: workspace smaller than fil_rpy_batched_workspace_bytes()");
-    int rc = rpy_batch_upload(p, work, (hipStream_t)stream);
-    if (rc) return rc;
-    rc = rpy_batch_launch(p, Y, F, T, a, eta, V, Omega, work, (hipStream_t)stream);
-    if (rc) return rc;
-    // the host-side lists must outlive the asynchronous upload
-    FIL_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-    return FIL_OK;
+    FIL_CHECK_ARG(work_bytes >= (int64_t)p.work_bytes() && (work || p.work_bytes() == 0),
+                  "fil_rpy_mobility_apply_batched: workspace smaller than fil_rpy_batch_workspace_bytes()");
+    return rpy_batch_launch(p, plan->lists, Y, F, T, a, eta, V, Omega, work, (hipStream_t)stream);
+}
+
+void fil_rpy_batch_destroy(fil_rpy_batch* plan) {
+    if (!plan) return;
+    if (plan->lists) (void)hipFree(plan->lists);
+    delete plan;
 }
 
 int fil_filament_internal_forces(int64_t M, int64_t S, const int64_t* fil_off, const double* q,

@@ -15,9 +15,14 @@
 //     which leaves 21 FMA-class accumulators per target and ~43 VALU
 //     operations per pair.  The coefficient 2a^2/3 s^3 F_m of M^tt is folded
 //     into the s^3 F_m accumulator, -1/2 s^3 T_m of M^rr into s^3 T_m.
-//   * FP32-tile path: r = Y_n - Y_m is formed in double and rounded once, the
-//     pair arithmetic runs in float and each tile of sources is accumulated in
-//     float and then added into double accumulators.
+//   * FP32-tile path: sources come in tiles of 16 (by global index) with an FP64
+//     origin each; a source record holds its FP32 offset from that origin.  A wave's
+//     targets are contiguous, and for a tile far from all of them (minimum pair
+//     distance >= 2 a + twice the tile radius) each target's offset from the tile
+//     origin is rounded once per tile and r = y' - s' is formed in float: three
+//     roundings of sizes below 3 |r| ulp.  Tiles near the wave take r = Y_n - Y_m in
+//     double, rounded once, with the overlap test.  The pair arithmetic runs in
+//     float, each tile is accumulated in float and then added into double.
 //   * Overlapping pairs (r < 2a) take a rarely executed branch with the regularised
 //     forms; the far-field weights are zeroed there.  The self pair (r = 0) is taken in
 //     its closed form 4/(3a) F, T/a^3 (in the FP32-tile path: in double, per target).
@@ -34,13 +39,57 @@ constexpr int kRpyBlock = 256;
 constexpr int kMaxChunkSmall = 256;  // most sources per block on the small-size path (64 per wave)
 
 // ------------------------------------------------------------------ packing
-__global__ void __launch_bounds__(256) rpy_pack(int64_t S, int prec, const double* __restrict__ Y,
-                                               const double* __restrict__ F, const double* __restrict__ T,
-                                               void* __restrict__ pk) {
+__global__ void __launch_bounds__(256) rpy_pack_f64(int64_t S, const double* __restrict__ Y,
+                                                   const double* __restrict__ F, const double* __restrict__ T,
+                                                   double* __restrict__ pk) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= S) return;
-    rpy_pack_record(prec, pk, m, Y[m], Y[S + m], Y[2 * S + m], F[m], F[S + m], F[2 * S + m], T[m], T[S + m],
-                    T[2 * S + m]);
+    rpy_pack_record_f64(pk, m, Y[m], Y[S + m], Y[2 * S + m], F[m], F[S + m], F[2 * S + m], T[m], T[S + m],
+                        T[2 * S + m]);
+}
+
+// FP32-tile records: one thread per source; the 16 lanes of a tile (tiles start at global
+// indices that are multiples of 16, and so do the lane groups of every wave) reduce their
+// bounding box with lane exchanges, take its centre as the tile origin and write their
+// offsets from it.  active: optional flag of the single suspension (0: nothing to do).
+__global__ void __launch_bounds__(256) rpy_tile_pack(int64_t S, const double* __restrict__ Y,
+                                                    const double* __restrict__ F, const double* __restrict__ T,
+                                                    SrcF32* __restrict__ pk, TileF32* __restrict__ tiles,
+                                                    const int32_t* __restrict__ active) {
+    static_assert(kF32Tile == 16 || kF32Tile == 32, "lane groups of 16 or 32 within a wave");
+    if (active && !active[0]) return;
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t mm = m < S ? m : S - 1;  // lanes past the end repeat the last source
+    double y[3], lo[3], hi[3];
+    for (int i = 0; i < 3; i++) y[i] = lo[i] = hi[i] = Y[i * S + mm];
+    for (int off = 1; off < kF32Tile; off <<= 1)
+        for (int i = 0; i < 3; i++) {
+            lo[i] = fmin(lo[i], __shfl_xor(lo[i], off));
+            hi[i] = fmax(hi[i], __shfl_xor(hi[i], off));
+        }
+    if (m >= S) return;
+    double o[3], d2 = 0.0;
+    for (int i = 0; i < 3; i++) {
+        o[i] = 0.5 * (lo[i] + hi[i]);
+        d2 = fma(hi[i] - lo[i], hi[i] - lo[i], d2);
+    }
+    SrcF32 r;
+    for (int i = 0; i < 3; i++) {
+        const double t = T[i * S + m];
+        r.sp[i] = (float)(y[i] - o[i]);
+        r.f[i] = (float)F[i * S + m];
+        r.t[i] = (float)t;
+        r.t15[i] = (float)(1.5 * t);
+        r.tm[i] = (float)(-0.5 * t);
+    }
+    r.pad = 0.f;
+    pk[m] = r;
+    if (m % kF32Tile == 0) {
+        TileF32 tr;
+        for (int i = 0; i < 3; i++) tr.o[i] = o[i];
+        tr.rad = 0.5 * sqrt(d2);
+        tiles[m / kF32Tile] = tr;
+    }
 }
 
 // ------------------------------------------------------------------ FP64 pair
@@ -299,46 +348,48 @@ __global__ void __launch_bounds__(kRpyBlock) rpy_f64_items_kernel(const RpyItem*
 // ------------------------------------------------------------------ FP32-tile pair
 // Accumulates (V, Omega) / c of one pair in float.  With q = s^3 r:
 //   v += (s + 2a^2/3 s^3) F + (1 - 2a^2 s^2)(r.F) q + T x q
-//   w += -1/2 s^3 T + 3/2 s^2 (r.T) q + F x q
-// (53 VALU operations per pair).
+//   w += s^3 (-1/2 T) + s^2 (r.(3/2 T)) q + F x q
+// (46 VALU operations per pair, r included).  NEAR: the overlap test and its branch.
 struct SrcRegF32 {
-    double y[3];
-    float f[3], t[3];
+    float sp[3], f[3], t[3], t15[3], tm[3];
 };
+// the whole 64-byte record in one scalar load (it is wave-uniform)
 __device__ __forceinline__ SrcRegF32 load_src_f32(const SrcF32* __restrict__ s) {
+    const float4* p = reinterpret_cast<const float4*>(s);
+    const float4 a = p[0], b = p[1], c = p[2], d = p[3];
     SrcRegF32 r;
-    for (int i = 0; i < 3; i++) {
-        r.y[i] = s->y[i];
-        r.f[i] = s->f[i];
-        r.t[i] = s->t[i];
-    }
+    r.sp[0] = a.x; r.sp[1] = a.y; r.sp[2] = a.z;
+    r.f[0] = a.w;  r.f[1] = b.x;  r.f[2] = b.y;
+    r.t[0] = b.z;  r.t[1] = b.w;  r.t[2] = c.x;
+    r.t15[0] = c.y; r.t15[1] = c.z; r.t15[2] = c.w;
+    r.tm[0] = d.x; r.tm[1] = d.y; r.tm[2] = d.z;
     return r;
 }
-__device__ __forceinline__ void rpy_pair_f32(const double y[3], const SrcRegF32& s, float a, float four_a2,
-                                             float two_a2, float c23, float v[3], float w[3]) {
-    const float rx = (float)(y[0] - s.y[0]);
-    const float ry = (float)(y[1] - s.y[1]);
-    const float rz = (float)(y[2] - s.y[2]);
+template <bool NEAR>
+__device__ __forceinline__ void rpy_pair_f32(float rx, float ry, float rz, const SrcRegF32& s, float a,
+                                             float four_a2, float two_a2, float c23, float v[3], float w[3]) {
     const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
-    const bool near = r2 < four_a2;
     float sv = __builtin_amdgcn_rsqf(r2);
-    sv = near ? 0.f : sv;
+    bool near = false;
+    if (NEAR) {
+        near = r2 < four_a2;
+        sv = near ? 0.f : sv;
+    }
     const float s2 = sv * sv, s3 = s2 * sv;
     const float qx = s3 * rx, qy = s3 * ry, qz = s3 * rz;
     const float Fx = s.f[0], Fy = s.f[1], Fz = s.f[2], Tx = s.t[0], Ty = s.t[1], Tz = s.t[2];
     const float rF = fmaf(rx, Fx, fmaf(ry, Fy, rz * Fz));
-    const float rT = fmaf(rx, Tx, fmaf(ry, Ty, rz * Tz));
-    const float A = fmaf(c23, s3, sv);                 // s + 2a^2/3 s^3
-    const float B = fmaf(-two_a2, s2, 1.f) * rF;       // (1 - 2a^2 s^2) (r.F)
-    const float D = (1.5f * s2) * rT;                  // 3/2 s^2 (r.T)
-    const float E = -0.5f * s3;
+    const float rT = fmaf(rx, s.t15[0], fmaf(ry, s.t15[1], rz * s.t15[2]));  // 3/2 r.T
+    const float A = fmaf(c23, s3, sv);            // s + 2a^2/3 s^3
+    const float B = fmaf(-two_a2, s2, 1.f) * rF;  // (1 - 2a^2 s^2) (r.F)
+    const float D = s2 * rT;                      // 3/2 s^2 (r.T)
     v[0] = fmaf(A, Fx, fmaf(B, qx, fmaf(Ty, qz, fmaf(-Tz, qy, v[0]))));
     v[1] = fmaf(A, Fy, fmaf(B, qy, fmaf(Tz, qx, fmaf(-Tx, qz, v[1]))));
     v[2] = fmaf(A, Fz, fmaf(B, qz, fmaf(Tx, qy, fmaf(-Ty, qx, v[2]))));
-    w[0] = fmaf(E, Tx, fmaf(D, qx, fmaf(Fy, qz, fmaf(-Fz, qy, w[0]))));
-    w[1] = fmaf(E, Ty, fmaf(D, qy, fmaf(Fz, qx, fmaf(-Fx, qz, w[1]))));
-    w[2] = fmaf(E, Tz, fmaf(D, qz, fmaf(Fx, qy, fmaf(-Fy, qx, w[2]))));
-    if (near && r2 > 0.f) {  // the self pair (r = 0) is added per target, in double, after the loop
+    w[0] = fmaf(s3, s.tm[0], fmaf(D, qx, fmaf(Fy, qz, fmaf(-Fz, qy, w[0]))));
+    w[1] = fmaf(s3, s.tm[1], fmaf(D, qy, fmaf(Fz, qx, fmaf(-Fx, qz, w[1]))));
+    w[2] = fmaf(s3, s.tm[2], fmaf(D, qz, fmaf(Fx, qy, fmaf(-Fy, qx, w[2]))));
+    if (NEAR && near && r2 > 0.f) {  // the self pair (r = 0) is added per target, in double, after the loop
         const Ovl<float> o = rpy_overlap<float>(rx, ry, rz, r2, Fx, Fy, Fz, Tx, Ty, Tz, a);
         for (int i = 0; i < 3; i++) {
             v[i] += o.v[i];
@@ -347,54 +398,106 @@ __device__ __forceinline__ void rpy_pair_f32(const double y[3], const SrcRegF32&
     }
 }
 
-constexpr int kF32Tile = 16;  // sources accumulated in float before the double flush
+// a wave-uniform double as such (both halves through readfirstlane)
+__device__ __forceinline__ double uniform_f64(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
+// One work item of the FP32-tile path: as rpy_item_f64, but the lanes of a wave own
+// 64 x TPL consecutive targets (lane + 64 j), so that the wave's targets are close together
+// and most tiles are far from all of them.
 template <int TPL, int WS>
 __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg, int64_t tb, int k, int K,
                                              int64_t chunk, const SrcF32* __restrict__ pk,
-                                             const double* __restrict__ Y, double a, double c, const RpyOut& out) {
+                                             const TileF32* __restrict__ tiles, const double* __restrict__ Y,
+                                             double a, double c, const RpyOut& out) {
     constexpr int kTgtPerBlock = kRpyBlock / WS;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int tid = WS == 1 ? (int)threadIdx.x : (int)(threadIdx.x % 64);
+    const int lane = (int)(threadIdx.x % 64);
     int64_t m0 = (int64_t)k * chunk;
     int64_t m1 = min(S, m0 + chunk);
     if (WS > 1) {
-        const int64_t sub = (m1 - m0 + WS - 1) / WS;
+        const int64_t sub = ((m1 - m0 + WS - 1) / WS + kF32Tile - 1) / kF32Tile * kF32Tile;
         const int64_t a0 = m0 + wave * sub;
         m1 = min(m1, a0 + sub);
         m0 = min(a0, m1);
     }
     const float af = (float)a, four_a2 = (float)(4.0 * a * a), two_a2 = (float)(2.0 * a * a);
     const float c23 = (float)(2.0 * a * a / 3.0);
+    const int64_t t_first = tb * (kTgtPerBlock * TPL) + (WS == 1 ? (int64_t)wave * 64 * TPL : 0);
     int64_t n[TPL];
     double y[TPL][3], vd[TPL][3], wd[TPL][3];
+    double lo[3], hi[3];
 #pragma unroll
     for (int j = 0; j < TPL; j++) {
-        n[j] = tb * (kTgtPerBlock * TPL) + j * kTgtPerBlock + tid;
+        n[j] = t_first + j * 64 + lane;
         const int64_t nn = base + (n[j] < S ? n[j] : S - 1);
         for (int i = 0; i < 3; i++) {
             y[j][i] = Y[i * Sg + nn];
             vd[j][i] = wd[j][i] = 0.0;
+            lo[i] = j ? fmin(lo[i], y[j][i]) : y[j][i];
+            hi[i] = j ? fmax(hi[i], y[j][i]) : y[j][i];
         }
     }
-    const SrcF32* src = pk + base;
-    for (int64_t t0 = m0; t0 < m1; t0 += kF32Tile) {
-        const int64_t t1 = min(m1, t0 + kF32Tile);
+    // bounding box of the wave's targets: centre cw and radius rw, wave-uniform
+    for (int off = 32; off >= 1; off >>= 1)
+        for (int i = 0; i < 3; i++) {
+            lo[i] = fmin(lo[i], __shfl_xor(lo[i], off));
+            hi[i] = fmax(hi[i], __shfl_xor(hi[i], off));
+        }
+    double cw[3], rw2 = 0.0;
+    for (int i = 0; i < 3; i++) {
+        cw[i] = uniform_f64(0.5 * (lo[i] + hi[i]));
+        rw2 = fma(hi[i] - lo[i], hi[i] - lo[i], rw2);
+    }
+    const double rw = uniform_f64(0.5 * sqrt(rw2));
+    for (int64_t t0 = m0; t0 < m1;) {
+        const int64_t g = base + t0;
+        const int64_t tile = g / kF32Tile;
+        const int64_t t1 = min(m1, (tile + 1) * kF32Tile - base);
+        const int cnt = (int)(t1 - t0);
+        const TileF32 tr = tiles[tile];
+        const double dx = cw[0] - tr.o[0], dy = cw[1] - tr.o[1], dz = cw[2] - tr.o[2];
+        const double reach = rw + 3.0 * tr.rad + 2.0 * a;  // |C_w - O| >= reach: every pair >= 2a + 2 rad apart
+        const int far = __builtin_amdgcn_readfirstlane((int)(fma(dx, dx, fma(dy, dy, dz * dz)) >= reach * reach));
         float v[TPL][3], w[TPL][3];
 #pragma unroll
         for (int j = 0; j < TPL; j++)
             for (int i = 0; i < 3; i++) v[j][i] = w[j][i] = 0.f;
         // the next record is requested before the current one is used (latency overlap);
         // 32-bit, wave-uniform loop arithmetic stays on the scalar unit
-        const SrcF32* ts = src + t0;
-        const int cnt = (int)(t1 - t0);
+        const SrcF32* ts = pk + g;
         SrcRegF32 cur = load_src_f32(ts);
-        for (int i = 0; i < cnt; ++i) {
-            const SrcRegF32 nxt = load_src_f32(ts + (i + 1 < cnt ? i + 1 : i));
+        if (far) {
+            float yt[TPL][3];
 #pragma unroll
             for (int j = 0; j < TPL; j++)
-                rpy_pair_f32(y[j], cur, af, four_a2, two_a2, c23, v[j], w[j]);
-            cur = nxt;
+                for (int i = 0; i < 3; i++) yt[j][i] = (float)(y[j][i] - tr.o[i]);
+            auto pairs = [&](const SrcRegF32& sr) {
+#pragma unroll
+                for (int j = 0; j < TPL; j++)
+                    rpy_pair_f32<false>(yt[j][0] - sr.sp[0], yt[j][1] - sr.sp[1], yt[j][2] - sr.sp[2], sr, af,
+                                        four_a2, two_a2, c23, v[j], w[j]);
+            };
+            for (int i = 0; i < cnt; ++i) {
+                const SrcRegF32 nxt = load_src_f32(ts + (i + 1 < cnt ? i + 1 : i));
+                pairs(cur);
+                cur = nxt;
+            }
+        } else {
+            for (int i = 0; i < cnt; ++i) {
+                const SrcRegF32 nxt = load_src_f32(ts + (i + 1 < cnt ? i + 1 : i));
+                const int64_t gm = g + i;
+                const double s0 = Y[gm], s1 = Y[Sg + gm], s2 = Y[2 * Sg + gm];
+#pragma unroll
+                for (int j = 0; j < TPL; j++)
+                    rpy_pair_f32<true>((float)(y[j][0] - s0), (float)(y[j][1] - s1), (float)(y[j][2] - s2), cur, af,
+                                       four_a2, two_a2, c23, v[j], w[j]);
+                cur = nxt;
+            }
         }
 #pragma unroll
         for (int j = 0; j < TPL; j++)
@@ -402,16 +505,17 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
                 vd[j][i] += (double)v[j][i];
                 wd[j][i] += (double)w[j][i];
             }
+        t0 = t1;
     }
     // the self pair (r = 0 in the overlap forms): 4/(3a) F and T / a^3, in double
 #pragma unroll
     for (int j = 0; j < TPL; j++)
         if (n[j] >= m0 && n[j] < m1) {
             const SrcF32& sr = pk[base + n[j]];
-            const double cv = 4.0 / (3.0 * a), cw = 1.0 / (a * a * a);
+            const double cv = 4.0 / (3.0 * a), cw3 = 1.0 / (a * a * a);
             for (int i = 0; i < 3; i++) {
                 vd[j][i] = fma(cv, (double)sr.f[i], vd[j][i]);
-                wd[j][i] = fma(cw, (double)sr.t[i], wd[j][i]);
+                wd[j][i] = fma(cw3, (double)sr.t[i], wd[j][i]);
             }
         }
     double vw[TPL][6];
@@ -427,17 +531,19 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
 template <int TPL, int WS>
 __global__ void __launch_bounds__(kRpyBlock) rpy_f32_kernel(int64_t S, int64_t chunk, int K,
                                                           const SrcF32* __restrict__ pk,
+                                                          const TileF32* __restrict__ tiles,
                                                           const double* __restrict__ Y, double a, double c,
                                                           RpyOut out) {
     if (out.active && !out.active[0]) return;
     const int k = (int)(blockIdx.x % (unsigned)K);
     const int64_t tb = blockIdx.x / (unsigned)K;
-    rpy_item_f32<TPL, WS>(0, S, S, tb, k, K, chunk, pk, Y, a, c, out);
+    rpy_item_f32<TPL, WS>(0, S, S, tb, k, K, chunk, pk, tiles, Y, a, c, out);
 }
 
 template <int TPL>
 __global__ void __launch_bounds__(kRpyBlock) rpy_f32_items_kernel(const RpyItem* __restrict__ items, int64_t nitems,
                                                                 int64_t Sg, const SrcF32* __restrict__ pk,
+                                                                const TileF32* __restrict__ tiles,
                                                                 const double* __restrict__ Y, double a, double c,
                                                                 RpyOut out) {
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -445,7 +551,7 @@ __global__ void __launch_bounds__(kRpyBlock) rpy_f32_items_kernel(const RpyItem*
         if (out.active && !out.active[w.susp]) continue;
         RpyOut o = out;
         o.part = out.part + w.part;
-        rpy_item_f32<TPL, 1>(w.base, w.S, Sg, w.tb, w.k, w.K, w.chunk, pk, Y, a, c, o);
+        rpy_item_f32<TPL, 1>(w.base, w.S, Sg, w.tb, w.k, w.K, w.chunk, pk, tiles, Y, a, c, o);
     }
 }
 
@@ -509,7 +615,8 @@ RpyPlan rpy_plan(int64_t S, int prec) {
     p.S = S;
     p.prec = prec;
     const bool small = S < kSmallS;
-    p.tpl = small ? 1 : (prec == FIL_PREC_F64 ? kTplF64 : kTplF32);
+    const bool f32 = prec == FIL_PREC_F32TILE;
+    p.tpl = small ? 1 : (f32 ? kTplF32 : kTplF64);
     p.ws = small ? 4 : 1;
     if (S <= 0) return p;
     p.tb = ceil_div(S, (int64_t)(kRpyBlock / p.ws) * p.tpl);
@@ -520,9 +627,11 @@ RpyPlan rpy_plan(int64_t S, int prec) {
     if (small) K = std::max<int64_t>(K, ceil_div(S, kMaxChunkSmall));
     if (K >= 8) K = ceil_div(K, 8) * 8;
     p.chunk = ceil_div(S, K);
+    if (f32) p.chunk = ceil_div(p.chunk, kF32Tile) * kF32Tile;  // chunks start on tile boundaries
     p.K = (int)ceil_div(S, p.chunk);
-    p.pack_bytes = (size_t)S * (prec == FIL_PREC_F64 ? 16 * sizeof(double) : sizeof(SrcF32));
+    p.pack_bytes = (size_t)S * (f32 ? sizeof(SrcF32) : 16 * sizeof(double));
     p.pack_bytes = (p.pack_bytes + 255) & ~(size_t)255;
+    p.tile_bytes = f32 ? ((size_t)ceil_div(S, kF32Tile) * sizeof(TileF32) + 255) & ~(size_t)255 : 0;
     p.part_bytes = p.K > 1 ? (size_t)p.K * 6 * S * sizeof(double) : 0;
     return p;
 }
@@ -532,22 +641,25 @@ int rpy_launch(const RpyPlan& p, const double* Y, const double* F, const double*
                const int32_t* active) {
     if (p.S <= 0) return FIL_OK;
     char* base = static_cast<char*>(work);
-    RpyOut out{reinterpret_cast<double*>(base + p.pack_bytes), V, W, active};
+    RpyOut out{reinterpret_cast<double*>(base + p.pack_bytes + p.tile_bytes), V, W, active};
     const double c = 1.0 / (8.0 * kPi * eta);
     const unsigned grid = (unsigned)(p.tb * p.K);
     const unsigned pgrid = (unsigned)ceil_div(p.S, 256);
     if (p.prec == FIL_PREC_F64) {
         double* pk = reinterpret_cast<double*>(base);
-        if (!packed) rpy_pack<<<pgrid, 256, 0, st>>>(p.S, p.prec, Y, F, T, pk);
+        if (!packed) rpy_pack_f64<<<pgrid, 256, 0, st>>>(p.S, Y, F, T, pk);
         const double* src = pk;
         if (p.ws == 4) launch_pair(rpy_f64_kernel<1, 4>, grid, st, ev0, ev1, p.S, p.chunk, p.K, src, Y, a, c, out);
         else launch_pair(rpy_f64_kernel<kTplF64, 1>, grid, st, ev0, ev1, p.S, p.chunk, p.K, src, Y, a, c, out);
     } else {
         SrcF32* pk = reinterpret_cast<SrcF32*>(base);
-        if (!packed) rpy_pack<<<pgrid, 256, 0, st>>>(p.S, p.prec, Y, F, T, pk);
+        TileF32* tiles = reinterpret_cast<TileF32*>(base + p.pack_bytes);
+        rpy_tile_pack<<<pgrid, 256, 0, st>>>(p.S, Y, F, T, pk, tiles, active);
         const SrcF32* src = pk;
-        if (p.ws == 4) launch_pair(rpy_f32_kernel<1, 4>, grid, st, ev0, ev1, p.S, p.chunk, p.K, src, Y, a, c, out);
-        else launch_pair(rpy_f32_kernel<kTplF32, 1>, grid, st, ev0, ev1, p.S, p.chunk, p.K, src, Y, a, c, out);
+        const TileF32* tl = tiles;
+        if (p.ws == 4)
+            launch_pair(rpy_f32_kernel<1, 4>, grid, st, ev0, ev1, p.S, p.chunk, p.K, src, tl, Y, a, c, out);
+        else launch_pair(rpy_f32_kernel<kTplF32, 1>, grid, st, ev0, ev1, p.S, p.chunk, p.K, src, tl, Y, a, c, out);
     }
     if (p.K > 1 && reduce) rpy_reduce<<<(unsigned)ceil_div(6 * p.S, 256), 256, 0, st>>>(p.S, p.K, out.part, V, W);
     FIL_HIP_TRY(hipGetLastError());
@@ -562,7 +674,8 @@ RpyBatchPlan rpy_batch_plan(int64_t nsusp, const int64_t* susp_off, int prec) {
     RpyBatchPlan p;
     p.prec = prec;
     p.Sg = susp_off[nsusp];
-    const int tpl = prec == FIL_PREC_F64 ? kTplF64 : kTplF32;
+    const bool f32 = prec == FIL_PREC_F32TILE;
+    const int tpl = f32 ? kTplF32 : kTplF64;
     int64_t part = 0;
     p.sus.resize(nsusp);
     p.seg_susp.resize(p.Sg);
@@ -597,7 +710,8 @@ RpyBatchPlan rpy_batch_plan(int64_t nsusp, const int64_t* susp_off, int prec) {
     std::stable_sort(p.items.begin(), p.items.end(),
                      [&](const RpyItem& x, const RpyItem& y) { return cost(x) > cost(y); });
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    p.pack_bytes = al((size_t)p.Sg * (prec == FIL_PREC_F64 ? 16 * sizeof(double) : sizeof(SrcF32)));
+    p.pack_bytes = al((size_t)p.Sg * (f32 ? sizeof(SrcF32) : 16 * sizeof(double)));
+    p.tile_bytes = f32 ? al((size_t)ceil_div(p.Sg, kF32Tile) * sizeof(TileF32)) : 0;
     p.part_bytes = al((size_t)part * sizeof(double));
     p.items_bytes = al(p.items.size() * sizeof(RpyItem));
     p.sus_bytes = al(p.sus.size() * sizeof(RpySusp));
@@ -605,8 +719,8 @@ RpyBatchPlan rpy_batch_plan(int64_t nsusp, const int64_t* susp_off, int prec) {
     return p;
 }
 
-int rpy_batch_upload(const RpyBatchPlan& p, void* work, hipStream_t st) {
-    char* base = static_cast<char*>(work) + p.pack_bytes + p.part_bytes;
+int rpy_batch_upload(const RpyBatchPlan& p, void* lists, hipStream_t st) {
+    char* base = static_cast<char*>(lists);
     if (!p.items.empty())
         FIL_HIP_TRY(hipMemcpyAsync(base, p.items.data(), p.items.size() * sizeof(RpyItem), hipMemcpyHostToDevice, st));
     base += p.items_bytes;
@@ -619,30 +733,33 @@ int rpy_batch_upload(const RpyBatchPlan& p, void* work, hipStream_t st) {
     return FIL_OK;
 }
 
-int rpy_batch_launch(const RpyBatchPlan& p, const double* Y, const double* F, const double* T, double a, double eta,
-                     double* V, double* W, void* work, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, bool packed,
-                     const int32_t* active) {
+int rpy_batch_launch(const RpyBatchPlan& p, const void* lists, const double* Y, const double* F, const double* T,
+                     double a, double eta, double* V, double* W, void* work, hipStream_t st, hipEvent_t ev0,
+                     hipEvent_t ev1, bool packed, const int32_t* active) {
     if (p.Sg <= 0) return FIL_OK;
     char* base = static_cast<char*>(work);
-    RpyOut out{reinterpret_cast<double*>(base + p.pack_bytes), V, W, active};
-    const RpyItem* items = reinterpret_cast<const RpyItem*>(base + p.pack_bytes + p.part_bytes);
-    const RpySusp* sus = reinterpret_cast<const RpySusp*>(base + p.pack_bytes + p.part_bytes + p.items_bytes);
-    const int32_t* segs =
-        reinterpret_cast<const int32_t*>(base + p.pack_bytes + p.part_bytes + p.items_bytes + p.sus_bytes);
+    RpyOut out{reinterpret_cast<double*>(base + p.pack_bytes + p.tile_bytes), V, W, active};
+    const char* lb = static_cast<const char*>(lists);
+    const RpyItem* items = reinterpret_cast<const RpyItem*>(lb);
+    const RpySusp* sus = reinterpret_cast<const RpySusp*>(lb + p.items_bytes);
+    const int32_t* segs = reinterpret_cast<const int32_t*>(lb + p.items_bytes + p.sus_bytes);
     const double c = 1.0 / (8.0 * kPi * eta);
     const int64_t nitems = (int64_t)p.items.size();
     const unsigned grid = (unsigned)std::min<int64_t>(nitems, kPersistentBlocks);
     const unsigned pgrid = (unsigned)ceil_div(p.Sg, 256);
     if (p.prec == FIL_PREC_F64) {
         double* pk = reinterpret_cast<double*>(base);
-        if (!packed) rpy_pack<<<pgrid, 256, 0, st>>>(p.Sg, p.prec, Y, F, T, pk);
+        if (!packed) rpy_pack_f64<<<pgrid, 256, 0, st>>>(p.Sg, Y, F, T, pk);
         const double* src = pk;
         if (nitems) launch_pair(rpy_f64_items_kernel<kTplF64>, grid, st, ev0, ev1, items, nitems, p.Sg, src, Y, a, c, out);
     } else {
         SrcF32* pk = reinterpret_cast<SrcF32*>(base);
-        if (!packed) rpy_pack<<<pgrid, 256, 0, st>>>(p.Sg, p.prec, Y, F, T, pk);
+        TileF32* tiles = reinterpret_cast<TileF32*>(base + p.pack_bytes);
+        rpy_tile_pack<<<pgrid, 256, 0, st>>>(p.Sg, Y, F, T, pk, tiles, nullptr);
         const SrcF32* src = pk;
-        if (nitems) launch_pair(rpy_f32_items_kernel<kTplF32>, grid, st, ev0, ev1, items, nitems, p.Sg, src, Y, a, c, out);
+        const TileF32* tl = tiles;
+        if (nitems)
+            launch_pair(rpy_f32_items_kernel<kTplF32>, grid, st, ev0, ev1, items, nitems, p.Sg, src, tl, Y, a, c, out);
     }
     if (!nitems) {  // nothing launched: the timing events still mark this point
         if (ev0) FIL_HIP_TRY(hipEventRecord(ev0, st));

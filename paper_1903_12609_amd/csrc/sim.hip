@@ -48,6 +48,7 @@ struct fil_sim {
     unsigned long long* resbits_h = nullptr;
     // mobility plans and workspaces: [0] FP64, [1] FP32-tile (only when prec is FP32-tile)
     void* rpy_work[2] = {nullptr, nullptr};
+    void* rpy_lists[2] = {nullptr, nullptr};  // device work lists of the batched plans
     RpyPlan rplan[2]{};
     RpyBatchPlan bplan[2];
     int cur = 0;  // plan of the next residual evaluation
@@ -256,8 +257,8 @@ int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipE
         TRY(rpy_wall_launch(s->S, s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->wall_work, s->st));
         if (e1) FIL_HIP_TRY(hipEventRecord(e1, s->st));
     } else if (s->batched) {
-        TRY(rpy_batch_launch(s->bplan[c], s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->rpy_work[c], s->st, e0, e1,
-                             true, s->active_d));
+        TRY(rpy_batch_launch(s->bplan[c], s->rpy_lists[c], s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W,
+                             s->rpy_work[c], s->st, e0, e1, true, s->active_d));
     } else {
         // the split-K partials are summed inside the residual kernel
         TRY(rpy_launch(s->rplan[c], s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->rpy_work[c], s->st, e0, e1,
@@ -703,7 +704,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         size_t wbytes;
         if (s->batched) {
             s->bplan[c] = rpy_batch_plan(nsusp, susp_seg_off.data(), pr);
-            wbytes = s->bplan[c].total();
+            wbytes = s->bplan[c].work_bytes() + s->bplan[c].lists_bytes();
         } else {
             s->rplan[c] = rpy_plan(S, pr);
             wbytes = s->rplan[c].total();
@@ -714,6 +715,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
             return rc;
         }
         s->rpy_work[c] = wk;
+        if (s->batched) s->rpy_lists[c] = wk + s->bplan[c].work_bytes();
     }
     // ---- uploads
     std::vector<double> Ysoa(3 * S), qsoa(4 * S);
@@ -753,7 +755,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         TRY(upload(s->X, zeros));
         TRY(upload(s->resbits_d, std::vector<unsigned long long>(4 * nsusp, 0ull)));
         if (s->batched) {
-            for (int c = 0; c < nplan; c++) TRY(rpy_batch_upload(s->bplan[c], s->rpy_work[c], nullptr));
+            for (int c = 0; c < nplan; c++) TRY(rpy_batch_upload(s->bplan[c], s->rpy_lists[c], nullptr));
             FIL_HIP_TRY(hipDeviceSynchronize());
         }
         return FIL_OK;

@@ -396,7 +396,9 @@ __global__ void __launch_bounds__(64 * kStericWaves) steric_pack_kernel(SimDev d
     F[sn] = fx;
     F[S + sn] = fy;
     F[2 * S + sn] = fz;
-    rpy_pack_record(prec, pk, sn, y0, y1, y2, fx, fy, fz, Tp[0], Tp[1], Tp[2]);
+    // FP64 source records here; the FP32-tile records need the tile origins and are written
+    // by the mobility launch itself
+    if (prec == FIL_PREC_F64) rpy_pack_record_f64(static_cast<double*>(pk), sn, y0, y1, y2, fx, fy, fz, Tp[0], Tp[1], Tp[2]);
 }
 
 int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, const int32_t* active, double* F,

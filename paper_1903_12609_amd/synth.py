@@ -270,6 +270,23 @@ def rpy_throughput_inputs(S, seed=7, structured=True):
     return Y, F, T
 
 
+def active_array_mobility_inputs(nx=40, ny=25, N=32, spacing=20.0, seed=7, bend=0.05, base_z=0.0):
+    """Mobility inputs at the active array's size and layout: nx x ny filaments of N segments
+    (S = 32000 by default) standing on a square lattice of spacing 20a, each a planar arc
+    bent by a seed-random angle in [-bend, bend] per segment (the shape of a beating
+    filament), with F, T ~ N(0, 1) per component.  Filament-major order, row by row."""
+    rng = np.random.default_rng(seed)
+    qz = _axis_angle_quat((0.0, 1.0, 0.0), -math.pi / 2)   # e_x -> e_z
+    Ys = []
+    for i in range(nx):
+        for j in range(ny):
+            q = bent_quaternions(qz, N, bend * rng.uniform(-1, 1))
+            Ys.append(chain(np.array([i * spacing, j * spacing, base_z]), q))
+    Y = np.concatenate(Ys)
+    S = Y.shape[0]
+    return Y, rng.standard_normal((S, 3)), rng.standard_normal((S, 3))
+
+
 def random_cloud(S, seed, side, min_sep=None):
     """Uniform random points in a cube (optionally with a minimum separation)."""
     rng = np.random.default_rng(seed)
