@@ -79,6 +79,22 @@ int fil_rpy_mobility_apply_timed(int64_t S, const double* Y, const double* F, co
                                  int prec, double* V, double* Omega, void* work, int64_t work_bytes, void* ev_start,
                                  void* ev_end, void* stream);
 
+/* The same apply for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): no workspace argument,
+ * no hipMalloc, hipFree or allocating library call.  Its scratch (source records, FP32
+ * tile records, split-K partials) is a static device array of 64 MiB, one per GPU, held by
+ * each GPU the library runs on until the process ends (fil_rpy_noalloc_scratch_bytes
+ * returns its size).  Every S up to 40,000 fits in both precisions; an S whose
+ * fil_rpy_workspace_bytes exceeds the array is refused with FIL_EINVAL.  Nothing in the
+ * array needs to start at zero: every apply writes what it reads.  All calls on one GPU
+ * share the array, so calls that overlap on one GPU (other streams, other threads) race;
+ * calls on one stream are ordered.  The first call on a device looks up the array's device
+ * address (FIL_EHIP if that fails).  Other arguments and errors as fil_rpy_mobility_apply;
+ * bitwise the same result. */
+int fil_rpy_mobility_apply_noalloc(int64_t S, const double* Y, const double* F, const double* T, double a,
+                                   double eta, int prec, double* V, double* Omega, void* stream);
+int64_t fil_rpy_noalloc_scratch_bytes(void);
+
 /* RPY mobility of the segments above a no-slip plane wall z = 0 (the half-space tensor
  * the paper uses for its cilia, Sec. 2.7.1 and Sec. 5.3): the unbounded tensor of
  * fil_rpy_mobility_apply (same overlap forms) plus the wall's image part, Blake's image

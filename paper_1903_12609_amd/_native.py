@@ -51,6 +51,9 @@ def _declare(L):
     L.fil_rpy_workspace_bytes.argtypes = [_i64, _i]
     L.fil_rpy_workspace_bytes.restype = _i64
     L.fil_rpy_mobility_apply.argtypes = [_i64, _vp, _vp, _vp, _d, _d, _i, _vp, _vp, _vp, _i64, _vp]
+    L.fil_rpy_mobility_apply_noalloc.argtypes = [_i64, _vp, _vp, _vp, _d, _d, _i, _vp, _vp, _vp]
+    L.fil_rpy_noalloc_scratch_bytes.argtypes = []
+    L.fil_rpy_noalloc_scratch_bytes.restype = _i64
     L.fil_rpy_mobility_apply_timed.argtypes = [_i64, _vp, _vp, _vp, _d, _d, _i, _vp, _vp, _vp, _i64, _vp, _vp, _vp]
     L.fil_filament_internal_forces.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _d, _d, _d, _vp, _vp, _vp]
     L.fil_rpy_batch_create.argtypes = [_i64, _vp, _i, C.POINTER(_vp)]

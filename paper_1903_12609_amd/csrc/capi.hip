@@ -1,6 +1,8 @@
 // extern "C" entry points of the filament library: argument checking, workspace
 // sizing and dispatch to the kernels' launchers.
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "common.h"
@@ -47,6 +49,58 @@ int fil_rpy_mobility_apply_timed(int64_t S, const double* Y, const double* F, co
     return rpy_launch(p, Y, F, T, a, eta, V, Omega, work, (hipStream_t)stream, (hipEvent_t)ev_start,
                       (hipEvent_t)ev_end);
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free apply
+// The workspace of fil_rpy_mobility_apply_noalloc: a static device array, one copy per GPU
+// (each GPU holds it until the process ends).  Host code never passes the array's name to a
+// kernel: it uses the device address hipGetSymbolAddress returns, looked up once per device.
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+
+int scratch_address(void** out) {
+    int dev = 0;
+    FIL_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        FIL_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        it = g_scratch_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return FIL_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int fil_rpy_mobility_apply_noalloc(int64_t S, const double* Y, const double* F, const double* T, double a,
+                                   double eta, int prec, double* V, double* Omega, void* stream) {
+    FIL_CHECK_ARG(S >= 0, "fil_rpy_mobility_apply_noalloc: S < 0");
+    FIL_CHECK_ARG(prec == FIL_PREC_F64 || prec == FIL_PREC_F32TILE,
+                  "fil_rpy_mobility_apply_noalloc: unknown precision");
+    FIL_CHECK_ARG(std::isfinite(a) && a > 0 && std::isfinite(eta) && eta > 0,
+                  "fil_rpy_mobility_apply_noalloc: a and eta must be finite and > 0");
+    if (S == 0) return FIL_OK;
+    FIL_CHECK_ARG(Y && F && T && V && Omega, "fil_rpy_mobility_apply_noalloc: null array");
+    FIL_CHECK_ARG(V != Omega && V != Y && V != F && V != T && Omega != Y && Omega != F && Omega != T,
+                  "fil_rpy_mobility_apply_noalloc: outputs alias inputs");
+    const RpyPlan p = rpy_plan(S, prec);
+    FIL_CHECK_ARG(p.total() <= kNoAllocScratchBytes,
+                  "fil_rpy_mobility_apply_noalloc: S = " + std::to_string(S) + " needs " +
+                      std::to_string(p.total()) + " bytes of scratch; the static buffer holds " +
+                      std::to_string(kNoAllocScratchBytes) + " (use fil_rpy_mobility_apply with a workspace)");
+    void* ptr = nullptr;
+    if (int rc = scratch_address(&ptr)) return rc;
+    return rpy_launch(p, Y, F, T, a, eta, V, Omega, ptr, (hipStream_t)stream);
+}
+
+int64_t fil_rpy_noalloc_scratch_bytes(void) { return (int64_t)kNoAllocScratchBytes; }
 
 }  // extern "C"
 
