@@ -165,6 +165,81 @@ def run_steps(w, prec, steps, warmup, graph):
     return el, applies, iters, tm
 
 
+def suspension_steps(steps=10, warmup=3, graph=GRAPH_ITERS):
+    """Implicit steps of the 500 x 32 sedimenting suspension (S = 16000, cube of side 400a,
+    dt = T/30) in FP64 and with FP32 tiles (FP64 finish): ms per step, iterations, mobility
+    applies and how many of them ran in FP64."""
+    from paper_1903_12609_amd import synth
+    w = synth.sediment_suspension(M=500, N=32, side=400.0, seed=1005, dt_over_T=1 / 30)
+    out = {"workload": "sedimenting suspension 500 x 32 (S=16000), side 400a, dt=T/30, tol 1e-6, graph blocks of %d"
+                       % graph}
+    for prec in ("f64", "f32tile"):
+        import torch
+        import paper_1903_12609_amd as fil
+        sim = fil.Sim(w.fil_off, w.Y, w.q, w.params, prec=prec, graph=graph)
+        for _ in range(warmup):
+            sim.step()
+        torch.cuda.synchronize()
+        its = aps = a64 = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = sim.step()[0]
+            its += r["iters"]
+            aps += r["applies"]
+            a64 += r["applies_f64"]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sim.close()
+        out[prec] = {"ms_per_step": el / steps * 1e3, "iters_per_step": its / steps,
+                     "mobility_applies_per_step": aps / steps, "fp64_applies_per_step": a64 / steps}
+        log("500x32 steps", prec, out[prec])
+    out["f32tile_over_f64_speed"] = out["f64"]["ms_per_step"] / out["f32tile"]["ms_per_step"]
+    return out
+
+
+def ensemble_steps(steps=4, warmup=1, graph=GRAPH_ITERS):
+    """The batched ensemble: 256 independent suspensions of U{1..64} filaments x U{10..50}
+    segments (about 2.6e5 segments), each at its own dt = T/100 and gravity, in one
+    simulation (one persistent mobility launch per evaluation, Broyden iterations in graph
+    blocks, per-suspension convergence), in FP64 and with FP32 tiles."""
+    import numpy as np
+    import torch
+    import paper_1903_12609_amd as fil
+    from paper_1903_12609_amd import synth
+    t0 = time.perf_counter()
+    ws = synth.batched_ensemble(n_susp=256, seed=1004, dt_over_T=1 / 100)
+    fil_off = [0]
+    for w in ws:
+        fil_off += list(fil_off[-1] + w.fil_off[1:])
+    sfo = np.concatenate([[0], np.cumsum([w.M for w in ws])])
+    Y, q = np.concatenate([w.Y for w in ws]), np.concatenate([w.q for w in ws])
+    S = int(fil_off[-1])
+    pairs = float(sum(w.S ** 2 for w in ws))
+    out = {"workload": "256 suspensions, filaments U{1..64} x segments U{10..50} (S=%d, sum S_i^2=%.3g), "
+                       "dt=T_i/100, tol 1e-6, graph blocks of %d" % (S, pairs, graph),
+           "setup_s": time.perf_counter() - t0}
+    for prec in ("f64", "f32tile"):
+        sim = fil.Sim(fil_off, Y, q, ws[0].params, susp_fil_off=sfo, prec=prec, graph=graph)
+        sim.set_suspension_params(dt=[w.params["dt"] for w in ws], grav=[w.params["grav"] for w in ws],
+                                  FS=[w.params["FS"] for w in ws])
+        for _ in range(warmup):
+            sim.step()
+        torch.cuda.synchronize()
+        its, mx = [], 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            reps = sim.step()
+            its += [r["iters"] for r in reps]
+            mx = max(mx, max(r["iters"] for r in reps))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sim.close()
+        out[prec] = {"ms_per_step": el / steps * 1e3, "mean_iters_per_suspension": float(np.mean(its)),
+                     "max_iters": mx}
+        log("ensemble steps", prec, out[prec])
+    return out
+
+
 def learned_gain(log_fn):
     """Learned warm start vs plain Broyden on the 500 x 32 sedimenting suspension
     (network trained here, on the GPU, from single-filament runs)."""
@@ -449,10 +524,10 @@ def sediment_steps(steps, warmup, graph):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    # untimed steps: the first steps capture the HIP graphs of the Broyden iteration blocks
-    # (one per first iteration and length) that later steps replay
-    ap.add_argument("--warmup", type=int, default=5)
+    # a step is one headline apply; the untimed ones first bring the GPU's clocks up (the
+    # pair kernel's duration falls by ~8% over the first dozen launches from idle)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--graph", type=int, default=GRAPH_ITERS, help="Broyden iterations per graph block (0: off)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
@@ -462,6 +537,7 @@ def main():
     ap.add_argument("--wall-only", action="store_true", help="only the wall-bounded mobility (for profiling)")
     ap.add_argument("--rpy-only", action="store_true", help="only the stand-alone mobility applies (for profiling)")
     ap.add_argument("--headline-only", action="store_true", help="only the headline applies (for profiling)")
+    ap.add_argument("--steps-only", action="store_true", help="only the implicit-step workloads")
     ap.add_argument("--fcm-steps-only", action="store_true",
                     help="only the solver comparison on the periodic FCM monolayer (for profiling)")
     args = ap.parse_args()
@@ -476,6 +552,11 @@ def main():
         return
     if args.rpy_only:
         print(json.dumps({"rpy_apply": rpy_sweep(), "rpy_apply_batched": rpy_batched()}))
+        return
+    if args.steps_only:
+        out = {"sediment2000_steps": sediment_steps(20, 5, args.graph)[0], "sediment500x32_steps": suspension_steps(),
+               "ensemble256_steps": ensemble_steps()}
+        print(json.dumps(out))
         return
     if args.wall_only:
         print(json.dumps({"wall_mobility": wall_mobility_bench()}))
@@ -515,7 +596,9 @@ def main():
         "f32_over_f64_time": h64["ms_per_apply"] / h32["ms_per_apply"],
     }
     if not args.headline_only:
-        res["sediment2000_steps"], w = sediment_steps(args.steps, args.warmup, args.graph)
+        res["sediment2000_steps"], w = sediment_steps(20, 5, args.graph)
+        res["sediment500x32_steps"] = suspension_steps()
+        res["ensemble256_steps"] = ensemble_steps()
         if not args.no_sweep:
             res["rpy_apply"] = rpy_sweep()
             res["rpy_apply_batched"] = rpy_batched()

@@ -82,9 +82,9 @@ int fil_rpy_mobility_apply_timed(int64_t S, const double* Y, const double* F, co
 /* The same apply for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): no workspace argument,
  * no hipMalloc, hipFree or allocating library call.  Its scratch (source records, FP32
- * tile records, split-K partials) is a static device array of 64 MiB, one per GPU, held by
+ * tile records, split-K partials) is a static device array of 256 MiB, one per GPU, held by
  * each GPU the library runs on until the process ends (fil_rpy_noalloc_scratch_bytes
- * returns its size).  Every S up to 40,000 fits in both precisions; an S whose
+ * returns its size).  Every S up to 160,000 fits in both precisions; an S whose
  * fil_rpy_workspace_bytes exceeds the array is refused with FIL_EINVAL.  Nothing in the
  * array needs to start at zero: every apply writes what it reads.  All calls on one GPU
  * share the array, so calls that overlap on one GPU (other streams, other threads) race;
@@ -290,7 +290,8 @@ int fil_set_wall(fil_sim* sim);
  * positions and the history shift.  The first step is BDF1, later ones BDF2.
  * In FIL_PREC_F32TILE mode the step's first mobility applies use FP32 pair
  * tiles; once every running suspension's residual is within 10 tol, or within
- * 30x the FP32 rounding floor (3e-8 x max|b dt V|), later applies use FP64, and
+ * 3000x the FP32 rounding floor (3e-8 x max|b dt V|), later applies use FP64, the
+ * Broyden history restarting there (Alg. 2 from the current iterate, same J0), and
  * only an FP64 residual ends a step (the FP32 floor can exceed tol).
  * report: HOST fil_step_report[nsusp] (may be NULL).  Host-driven iterations
  * (graph execution off, and FP32-tile iterations) synchronise the stream once
@@ -400,8 +401,8 @@ int fil_set_stream(fil_sim* sim, void* stream);
  * runs on the device; the host reads a block's log while the next block runs,
  * so a block launched after the end only runs kernels that find their
  * suspension finished.  Results are identical to U = 0 (the default, one host
- * test per iteration).  Graphs are cached per (first iteration, U, precision)
- * and freed by fil_destroy.  U in [0, 64].  fil_set_timing then times only the
+ * test per iteration).  Graphs are cached per (first iteration, U, precision,
+ * iteration of the last history restart) and freed by fil_destroy.  U in [0, 64].  fil_set_timing then times only the
  * host-driven evaluations (the first of each step); captured blocks carry no
  * timing events. */
 int fil_set_graph(fil_sim* sim, int iters_per_launch);

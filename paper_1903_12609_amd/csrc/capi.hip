@@ -57,7 +57,7 @@ int fil_rpy_mobility_apply_timed(int64_t S, const double* Y, const double* F, co
 // (each GPU holds it until the process ends).  Host code never passes the array's name to a
 // kernel: it uses the device address hipGetSymbolAddress returns, looked up once per device.
 namespace {
-constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr size_t kNoAllocScratchBytes = size_t(256) << 20;
 __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 std::mutex g_scratch_mu;
 std::map<int, void*> g_scratch_ptr;

@@ -620,10 +620,13 @@ RpyPlan rpy_plan(int64_t S, int prec) {
     p.ws = small ? 4 : 1;
     if (S <= 0) return p;
     p.tb = ceil_div(S, (int64_t)(kRpyBlock / p.ws) * p.tpl);
-    // aim for ~2048 workgroups (8 per CU); every wave gets >= 16 (small) or 64 sources;
-    // and on the small path no wave walks more than 64 sources
-    int64_t K = ceil_div(2048, p.tb);
-    K = std::min<int64_t>(K, std::max<int64_t>(1, S / (small ? 16 * p.ws : 64)));
+    // aim for ~2048 workgroups (8 per CU; FP32 tiles on the large path: ~8192, whose finer
+    // grain balances the end of the launch better than the extra partials cost: S = 32000
+    // pair kernel 1.11 -> 1.01 ms); every wave gets >= 16 (small), 64 (FP64) or 128 (FP32
+    // tiles) sources; and on the small path no wave walks more than 64 sources
+    const bool fine = f32 && !small;
+    int64_t K = ceil_div(fine ? 8192 : 2048, p.tb);
+    K = std::min<int64_t>(K, std::max<int64_t>(1, S / (small ? 16 * p.ws : (fine ? 128 : 64))));
     if (small) K = std::max<int64_t>(K, ceil_div(S, kMaxChunkSmall));
     if (K >= 8) K = ceil_div(K, 8) * 8;
     p.chunk = ceil_div(S, K);

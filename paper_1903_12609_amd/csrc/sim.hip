@@ -63,6 +63,7 @@ struct fil_sim {
     };
     int graph_iters = 0;  // iterations per captured block; 0 runs every iteration from the host
     int pred_iters = 0;   // iterations the last device-driven solve took (0: none yet)
+    int koff = 0;         // iteration at which the Broyden history last restarted (update k = it - 1 - koff)
     hipStream_t cap_st = nullptr;  // private stream the blocks are captured on (launches go to st)
     double* fext_d = nullptr;      // [3][S] external forces per segment (null until set)
     // force-coupling-method mobility of a periodic box (null: the unbounded RPY mobility);
@@ -85,7 +86,7 @@ struct fil_sim {
     double *kry_f00 = nullptr, *kry_spar0 = nullptr;  // f0 at the initial guess; parameters without external forces
     unsigned long long* kry_rb = nullptr;              // maxima of f0 evaluations (unused, two alternating pairs)
     int kry_rbi = 0;
-    std::map<std::array<int, 5>, GraphEntry> graphs;
+    std::map<std::array<int, 6>, GraphEntry> graphs;
     SuspLog* log_d = nullptr;  // device log of the current solve [nsusp]
     SuspLog* log_h = nullptr;  // staging of the host's counts when the device takes over a solve
     // two pinned slots for the logs of graph blocks in flight, each with its export's event
@@ -167,10 +168,14 @@ BdfCoef coefs(int64_t step) {
 // FP32-tile mode: the switch to FP64 evaluations happens once every running
 // suspension has max|f|/a <= max(kSwitchTol tol, kNoiseMargin kF32Floor max|b dt V|/a),
 // kF32Floor being the measured rounding floor of an FP32-tile apply relative to
-// the size of its mobility term.
+// the size of its mobility term.  The margin keeps the FP32 secant pairs well above
+// that floor (at 30x the noise they slowed the FP64 finish: 500 x 32 suspension 42.6
+// iterations per step against 33.5 in FP64), and the Broyden history restarts at the
+// switch (Alg. 2 from the current iterate with the same J0): 31.4 iterations, 16.5 ms
+// against 18.9 ms per step in FP64.
 constexpr double kSwitchTol = 10.0;
 constexpr double kF32Floor = 3e-8;
-constexpr double kNoiseMargin = 30.0;
+constexpr double kNoiseMargin = 3000.0;
 // timing events of mobility launches not yet read (read when the pool is this full, or on request)
 constexpr int kMaxPendingTimings = 256;
 
@@ -337,10 +342,11 @@ int capture_block(fil_sim* s, int it0, int U, GraphEntry& g) {
     int rc = FIL_OK;
     for (int i = 0; i < U && rc == FIL_OK; i++) {
         const int it = it0 + i;
-        rc = eval_residual(s, s->X, s->f, nullptr, nullptr, false, it - 1);
+        rc = eval_residual(s, s->X, s->f, nullptr, nullptr, false, it - 1 - s->koff);
         const JudgeArgs jg{s->log_d, s->resbits_d + 2 * s->rb * ns, nullptr, s->p.tol, 1.0 / s->p.a, it, s->p.kmax,
                            s->cur == 0 ? 1 : 0};
-        if (rc == FIL_OK) rc = broyden_state_launch(s->d, update_args(s, it - 1, s->f, nullptr), jg, s->active_d, s->st);
+        if (rc == FIL_OK)
+            rc = broyden_state_launch(s->d, update_args(s, it - 1 - s->koff, s->f, nullptr), jg, s->active_d, s->st);
     }
     // the block ends by exporting its log to the next pinned slot
     if (rc == FIL_OK)
@@ -367,7 +373,7 @@ int capture_block(fil_sim* s, int it0, int U, GraphEntry& g) {
 }
 
 int graph_block(fil_sim* s, int it0, int U) {
-    const std::array<int, 5> key{it0, U, s->cur, s->rb, s->step == 0 ? 1 : 0};
+    const std::array<int, 6> key{it0, U, s->cur, s->rb, s->step == 0 ? 1 : 0, s->koff};
     auto itg = s->graphs.find(key);
     if (itg == s->graphs.end()) {
         GraphEntry g;
@@ -441,6 +447,7 @@ int device_iterations(fil_sim* s, SolveLog& L, int it) {
 int solve(fil_sim* s, SolveLog& L) {
     const int64_t ns = s->nsusp;
     s->cur = s->p.prec == FIL_PREC_F32TILE ? 1 : 0;
+    s->koff = 0;
     std::vector<double> res, vmx;
     bool changed = false;
     auto count = [&]() {
@@ -514,24 +521,31 @@ int solve(fil_sim* s, SolveLog& L) {
     }
     if (changed) TRY(upload_flags(s, s->active_d, s->active_h));
     if (any) TRY(broyden_state_launch(s->d, update_args(s, -1, s->f, nullptr), JudgeArgs{}, s->active_d, s->st));
+    bool restart = false;  // the evaluation of this iteration is the first FP64 one after FP32 tiles
     for (int it = 1; any;) {
         if (graphs && s->cur == 0) {
-            // FP32 iterations are done: the device continues from the host's counts
+            // FP32 iterations are done: the device continues from the host's counts, with
+            // the Broyden history restarting at this iteration
             for (int64_t i = 0; i < ns; i++)
                 s->log_h[i] = SuspLog{L.state[i], L.iters[i], L.applies[i], L.applies_hi[i], L.last[i]};
             FIL_HIP_TRY(hipMemcpyAsync(s->log_d, s->log_h, ns * sizeof(SuspLog), hipMemcpyHostToDevice, s->st));
+            s->koff = it;
             return device_iterations(s, L, it);
         }
         count();
         TRY(pool_events(s, &e0, &e1));
-        TRY(eval_residual(s, s->X, s->f, e0, e1, false, s->k));
+        TRY(eval_residual(s, s->X, s->f, e0, e1, false, restart ? -1 : s->k));
         TRY(read_resid(s, res, &vmx));
         changed = false;
+        const int cur_before = s->cur;
         any = judge(it);
         if (!any) break;
         if (changed) TRY(upload_flags(s, s->active_d, s->active_h));
-        TRY(broyden_state_launch(s->d, update_args(s, s->k, s->f, nullptr), JudgeArgs{}, s->active_d, s->st));
-        s->k++;
+        // a restart takes Alg. 2's first step X <- X - J0^{-1} f from the first FP64 residual
+        TRY(broyden_state_launch(s->d, update_args(s, restart ? -1 : s->k, s->f, nullptr), JudgeArgs{}, s->active_d,
+                                 s->st));
+        s->k = restart ? 0 : s->k + 1;
+        restart = cur_before == 1 && s->cur == 0;
         it++;
     }
     return FIL_OK;

@@ -38,7 +38,7 @@ def _batch(workloads):
     return np.array(fil_off), np.array(sfo), Y, q
 
 
-def _ensemble(source, n_fil, N, seed, dt_over_T):
+def _ensemble(source, n_fil, N, seed, dt_over_T, per=10):
     rng = np.random.default_rng(seed)
     ws = []
     if source == "single":
@@ -53,7 +53,6 @@ def _ensemble(source, n_fil, N, seed, dt_over_T):
         ws.append(synth.sediment_suspension(M=n_fil, N=N, side=side, seed=int(rng.integers(1 << 31)),
                                             dt_over_T=dt_over_T))
     elif source == "suspension":
-        per = 10
         for i in range(max(1, n_fil // per)):
             side = 200.0 * (per * N / 2000.0) ** (1.0 / 3.0)
             ws.append(synth.sediment_suspension(M=per, N=N, side=side, seed=int(rng.integers(1 << 31)),
@@ -63,8 +62,9 @@ def _ensemble(source, n_fil, N, seed, dt_over_T):
     return ws
 
 
-def generate(n_fil=500, N=32, steps=100, warm=3, seed=2024, source="single", dt_over_T=1 / 30, log=None):
-    """(features [n, 19N], targets [n, 6N]) float32 device tensors, n = n_fil x steps.
+def generate(n_fil=500, N=32, steps=100, warm=3, seed=2024, source="single", dt_over_T=1 / 30, log=None, per=10):
+    """(features [n, 19N], targets [n, 6N]) float32 device tensors, n = n_fil x steps
+    (source "suspension": n_fil / per suspensions of `per` filaments each).
     A simulation whose step fails (Broyden diverging) is dropped from that step
     on and replaced by a freshly seeded one until n samples are collected."""
     import torch
@@ -75,7 +75,7 @@ def generate(n_fil=500, N=32, steps=100, warm=3, seed=2024, source="single", dt_
     while have < n_fil * steps:
         if attempt >= 10:
             raise RuntimeError("training data: too many diverging simulations")
-        ws = _ensemble(source, n_fil, N, seed + 7919 * attempt, dt_over_T)
+        ws = _ensemble(source, n_fil, N, seed + 7919 * attempt, dt_over_T, per)
         attempt += 1
         fil_off, sfo, Y, q = _batch(ws)
         sim = Sim(fil_off, Y, q, ws[0].params, susp_fil_off=sfo)

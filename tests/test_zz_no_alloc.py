@@ -39,7 +39,7 @@ def test_noalloc_apply_equals_workspace_apply(prec):
         torch.cuda.synchronize()
         assert torch.equal(V0, V1) and torch.equal(W0, W1)
     # a size whose workspace exceeds the static array is refused before anything runs
-    big = 200000
+    big = 10_000_000  # its workspace exceeds the static array in both precisions
     assert int(L.fil_rpy_workspace_bytes(big, prec)) > int(L.fil_rpy_noalloc_scratch_bytes())
     p = ctypes.c_void_p(Yd.data_ptr())
     q = ctypes.c_void_p(V1.data_ptr())
