@@ -241,25 +241,34 @@ def ensemble_steps(steps=4, warmup=1, graph=GRAPH_ITERS):
 
 
 def learned_gain(log_fn):
-    """Learned warm start vs plain Broyden on the 500 x 32 sedimenting suspension
-    (network trained here, on the GPU, from single-filament runs)."""
+    """Learned warm start vs plain Broyden on the 500 x 32 sedimenting suspension, with the
+    network (608-256-256-256-192 SiLU, BF16 MFMA) trained here, on the GPU, from pairs the
+    method generates: (a) from another 500 x 32 suspension at the same density
+    (in-distribution), the headline factor; (b) from single filaments at N = 32, the
+    config-1-style source."""
     import torch
     import paper_1903_12609_amd as fil
     from paper_1903_12609_amd import learned, synth
-    t0 = time.perf_counter()
-    feat, targ = learned.generate(n_fil=500, N=32, steps=100, source="single")
-    t1 = time.perf_counter()
-    m = fil.MLP(32, width=256, depth=3, max_batch=1024, seed=0)
-    hist = learned.train(m, feat, targ, epochs=60, batch=1024, lr=1e-3)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
     w = synth.sediment_suspension(M=500, N=32, side=400.0, seed=1005, dt_over_T=1 / 30)
-    res = learned.compare(w, m, steps=20, skip=5, log=log_fn)
-    res.update(train_samples=int(feat.shape[0]), data_s=t1 - t0, train_s=t2 - t1,
-               final_validation_loss=hist[-1][1], network="608-256-256-256-192 SiLU, BF16 MFMA",
-               workload="sedimenting suspension 500 x 32 (S=16000), dt=T/30, tol 1e-6")
-    m.close()
-    return res
+    out = {"workload": "sedimenting suspension 500 x 32 (S=16000), dt=T/30, tol 1e-6, 20 steps after 5"}
+    for name, src, seed in (("suspension_trained", "dense", 21), ("single_filament_trained", "single", 2024)):
+        t0 = time.perf_counter()
+        feat, targ = learned.generate(n_fil=500, N=32, steps=100, source=src, seed=seed)
+        t1 = time.perf_counter()
+        m = fil.MLP(32, width=256, depth=3, max_batch=1024, seed=0)
+        hist = learned.train(m, feat, targ, epochs=60, batch=1024, lr=1e-3)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res = learned.compare(w, m, steps=25, skip=5, log=log_fn)
+        res.update(train_samples=int(feat.shape[0]), data_s=t1 - t0, train_s=t2 - t1,
+                   final_validation_loss=hist[-1][1],
+                   source="one 500 x 32 suspension at the same density (another seed), 100 steps" if src == "dense"
+                   else "500 single filaments of N=32, B log-uniform in [1e2, 1e4], 100 steps")
+        out[name] = res
+        m.close()
+    out["time_ratio"] = out["suspension_trained"]["time_ratio"]
+    out["iteration_ratio"] = out["suspension_trained"]["iteration_ratio"]
+    return out
 
 
 def solver_comparison(w, steps=5, warmup=2, names=("ejb_b", "jfnk_j0", "jfnk_none", "jfb_g_j0"), periodic=None,
@@ -400,7 +409,7 @@ def wall_mobility_bench(reps=5):
 
 
 def cilia_array_steps(steps=40, dt=25000.0, n_tr=10, tau=0.02):
-    """Model cilia of Sec. 5.3 at the paper's array size: 6 x 6 pinned filaments of N = 20
+    """Model cilia of Sec. 5.2.2 at the paper's array size: 6 x 6 pinned filaments of N = 20
     on the wall (base-to-base spacing L in both directions, bases one segment spacing
     above the wall), each driven by the geometric switch about y (theta_max = 2 pi / 5,
     torque ratio 3: tau_pos = 3 tau, tau_neg = tau = 0.02 K_B, 10-step transition),
@@ -538,6 +547,8 @@ def main():
     ap.add_argument("--rpy-only", action="store_true", help="only the stand-alone mobility applies (for profiling)")
     ap.add_argument("--headline-only", action="store_true", help="only the headline applies (for profiling)")
     ap.add_argument("--steps-only", action="store_true", help="only the implicit-step workloads")
+    ap.add_argument("--sediment500-only", action="store_true",
+                    help="only the 500 x 32 suspension's steps (for profiling)")
     ap.add_argument("--fcm-steps-only", action="store_true",
                     help="only the solver comparison on the periodic FCM monolayer (for profiling)")
     args = ap.parse_args()
@@ -552,6 +563,9 @@ def main():
         return
     if args.rpy_only:
         print(json.dumps({"rpy_apply": rpy_sweep(), "rpy_apply_batched": rpy_batched()}))
+        return
+    if args.sediment500_only:
+        print(json.dumps({"sediment500x32_steps": suspension_steps(graph=args.graph)}))
         return
     if args.steps_only:
         out = {"sediment2000_steps": sediment_steps(20, 5, args.graph)[0], "sediment500x32_steps": suspension_steps(),

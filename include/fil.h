@@ -96,7 +96,7 @@ int fil_rpy_mobility_apply_noalloc(int64_t S, const double* Y, const double* F, 
 int64_t fil_rpy_noalloc_scratch_bytes(void);
 
 /* RPY mobility of the segments above a no-slip plane wall z = 0 (the half-space tensor
- * the paper uses for its cilia, Sec. 2.7.1 and Sec. 5.3): the unbounded tensor of
+ * the paper uses for its cilia, Sec. 2.7.1 and Sec. 5.2.2): the unbounded tensor of
  * fil_rpy_mobility_apply (same overlap forms) plus the wall's image part, Blake's image
  * system for a point force above a wall under the Faxen operators of both spheres
  *   tt = (1 + a^2/6 lap_x)(1 + a^2/6 lap_y) G^im,  rt = 1/2 curl_x (1 + a^2/6 lap_y) G^im,
@@ -218,8 +218,8 @@ typedef struct fil_sim fil_sim;
  *   phase  double[M] or NULL      per-filament phase of the preferred curvature
  *   tether int32[M] or NULL       1 = base clamped at its initial Y_1 and q_1; 2 = base
  *                                 pinned at its initial Y_1, its rotation free (the cilia
- *                                 bases of Sec. 5.3): lambda_1 in the Y_1 slot, u_1 kept; 3 = base on
- *                                 the rotating motor of fil_set_motor (Sec. 5.2)
+ *                                 bases of Sec. 5.2.2): lambda_1 in the Y_1 slot, u_1 kept; 3 = base on
+ *                                 the rotating motor of fil_set_motor (Sec. 5.2.1)
  * The library allocates all device state and workspace here (FIL_ENOMEM on failure). */
 int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, const int64_t* fil_seg_off,
                const double* Y0, const double* q0, const double* phase, const int32_t* tether, fil_sim** out);
@@ -236,7 +236,7 @@ int fil_set_suspension_params(fil_sim* sim, const double* dt, const double* grav
 
 /* A further external force on every segment, added to the gravity force in the force
  * balance of each segment (the external forces of Sec. 2.5, e.g. the end load of the
- * clamped filament of Sec. 5.1).  HOST array double[S][3], copied in; NULL removes it.
+ * clamped filament of Sec. 4.1).  HOST array double[S][3], copied in; NULL removes it.
  * Only before the first step (captured iterations read the force's address).  Not
  * part of checkpoints.  FIL_EINVAL on a non-finite value, FIL_ENOMEM if the device
  * copy cannot be allocated. */
@@ -253,7 +253,7 @@ int fil_set_external_forces(fil_sim* sim, const double* Fext);
  * bad argument, and fil_fcm_create's errors. */
 int fil_set_periodic_fcm(fil_sim* sim, const double* box, const int32_t* grid, double cut);
 
-/* The rotating motor of Sec. 5.2 for every tether-3 filament: its base moves on the circle
+/* The rotating motor of Sec. 5.2.1 for every tether-3 filament: its base moves on the circle
  * of radius d0 about the z axis through (initial Y_1) - (d0, 0, 0), at angle omega t, and
  * turns by u_1 = (0, 0, omega dt) per step; lambda_1, lambda_2 fill the Y_1, u_1 slots and
  * act on the first segment as F^C = lambda_1, T^C = D^T lambda_2 (D = dexpinv at u_1).  J0
@@ -261,7 +261,7 @@ int fil_set_periodic_fcm(fil_sim* sim, const double* box, const int32_t* grid, d
  * non-finite value. */
 int fil_set_motor(fil_sim* sim, double d0, double omega);
 
-/* Geometric-switch driving torque of model cilia (Sec. 5.3) on every pinned filament
+/* Geometric-switch driving torque of model cilia (Sec. 5.2.2) on every pinned filament
  * (tether 2): a torque about the unit axis drives the base until the angle theta between
  * the unit wall normal and the base tangent (signed about the axis, atan2 form) reaches
  * +theta_max or -theta_max, where it reverses; its magnitude is tau_pos while driving
@@ -303,7 +303,7 @@ int fil_set_wall(fil_sim* sim);
 int fil_bdf2_step(fil_sim* sim, fil_step_report* report);
 
 /* One time step solved by Jacobian-free Newton-Krylov instead of bad Broyden (the
- * comparison method of Sec. 3.1 and 4.1): Newton iterations X <- X + dX until
+ * comparison method of Sec. 3.1 and 3.3.1): Newton iterations X <- X + dX until
  * max|f|/a <= fil_params.tol (at most fil_params.kmax of them), each solving
  * J(X) dX = -f(X) by restarted GMRES (restart length min(krylov_max, 100)) to a
  * relative residual krylov_tol (the paper's 1e-4), the products J v taken as
@@ -327,7 +327,7 @@ int fil_jfnk_step(fil_sim* sim, int precond, double krylov_tol, double fd_delta,
                   fil_jfnk_report* report);
 
 /* One time step solved by the Jacobian-free good Broyden method JFB-g (Sec. 3.2.1,
- * Alg. 1, compared in Sec. 4.2): Broyden iterations dX = -[J0 + sum_i c_i d_i^T]^{-1}
+ * Alg. 1, compared in Sec. 3.3.2): Broyden iterations dX = -[J0 + sum_i c_i d_i^T]^{-1}
  * f(X_k), c = f(X_{k+1}) / |dX|, d = dX / |dX|, until max|f|/a <= fil_params.tol (at
  * most fil_params.kmax iterations).  J0 = grad f0 at the step's initial guess, with f0
  * the residual computed with the drag-only mobility diag(M) and without steric or

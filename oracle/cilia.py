@@ -1,5 +1,5 @@
 """Test infrastructure (not the product path): the geometric switch of model cilia
-(Sec. 5.3) for the oracle's steps.
+(Sec. 5.2.2) for the oracle's steps.
 
 Every pinned filament (tether 2) is driven by a torque about a fixed unit axis applied to
 its base segment.  Let theta be the angle from the unit wall normal n to the base tangent

@@ -16,7 +16,7 @@
  * and the global X concatenates filaments, filament f starting at 6*fil_off[f].
  * A clamped (tethered) filament stores the tether multipliers lambda_1,
  * lambda_2 in the Y_1 and u_1 slots (Sec. 5.2.1, tethering constraints).  A pinned
- * filament (base position held, its rotation free, as the cilia bases of Sec. 5.3)
+ * filament (base position held, its rotation free, as the cilia bases of Sec. 5.2.2)
  * stores lambda_1 in the Y_1 slot and keeps u_1 as an unknown.
  *
  * Parity: every function below is pinned by a CPU test (tests/test_oracle_*.py)
@@ -353,7 +353,7 @@ typedef struct {
     double K0, kw, omega;
     const double* phase;     /* [M] or NULL for no preferred curvature */
     const int32_t* tether;   /* [M], 1 = base clamped (Sec. 5.2.1), 2 = base pinned, 3 = base on a
-                              * rotating motor (Sec. 5.2); NULL: all free */
+                              * rotating motor (Sec. 5.2.1); NULL: all free */
     double motor_d0, motor_w; /* the motor: base distance from its z axis and rotation rate */
     const double* base;      /* [M][3] clamped base positions */
     int64_t nthreads;        /* OpenMP threads for the RPY target loop (0: default) */
@@ -450,7 +450,7 @@ void or_reconstruct(const or_params* P, const double* qj, const double* X, doubl
 /* Forces and torques the segments exert on the fluid for configuration (Y, q) and
  * multipliers in X: F^H = F^C + F^B + gravity (+ further external forces),
  * T^H = T^C + T^E (Sec. 2.5 and the
- * mobility problem of Sec. 2.8.2), plus tether multipliers on clamped bases. */
+ * mobility problem of Sec. 2.7), plus tether multipliers on clamped bases. */
 void or_forces(const or_params* P, const double* Y, const double* q, const double* X, double tt, double* F,
                double* T) {
     int64_t S = total_segments(P);
@@ -474,7 +474,7 @@ void or_forces(const or_params* P, const double* Y, const double* q, const doubl
             }
             if (is_motor(P, f)) {
                 /* T^C_1 += D^T lambda_2 with D v = dexpinv_{u_1}(v) = v - 1/2 u x v + c u x (u x v)
-                 * (Sec. 5.2), so D^T v = v + 1/2 u x v + c u x (u x v), c as in or_dexpinv */
+                 * (Sec. 5.2.1), so D^T v = v + 1/2 u x v + c u x (u x v), c as in or_dexpinv */
                 double u[3], l[3] = {X[6 * s0 + 3], X[6 * s0 + 4], X[6 * s0 + 5]}, ul[3], uul[3];
                 motor_u(P, u);
                 cross3(u, l, ul);

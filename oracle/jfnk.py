@@ -4,7 +4,7 @@ oracle's residual and J0 blocks, to check the GPU solvers against.  Linear syste
 solved by restarted GMRES (Arnoldi with modified Gram-Schmidt, Givens rotations).  JFNK
 takes each J v by the finite difference (f(X + delta v) - f(X)) / delta; JFB-g takes
 J0 v the same way from f0, the residual with the drag-only mobility and without steric
-or external forces, at the initial guess.  Preconditioners (Sec. 4.1): none; right,
+or external forces, at the initial guess.  Preconditioners (Sec. 3.3.1): none; right,
 P_dt applied as its inverse (multiplier unknowns scaled by 6 pi eta a / dt, undoing the
 dt / (6 pi eta a) of their Jacobian columns); left, J0^{-1} with the block-diagonal J0 of
 the initial guess (Sec. 3.2.2).

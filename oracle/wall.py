@@ -1,6 +1,6 @@
 """Test infrastructure (not the product path): the Rotne-Prager-Yamakawa mobility of
 equal spheres above a no-slip plane wall z = 0, the wall-bounded RPY tensor that the paper
-cites for its cilia (Sec. 2.7.1, Sec. 5.3; Swan & Brady 2007), built here from its
+cites for its cilia (Sec. 2.7.1, Sec. 5.2.2; Swan & Brady 2007), built here from its
 definition.
 
 Blake's solution for a unit point force at y above the wall (velocity at x, times 8 pi eta):

@@ -265,7 +265,7 @@ class Sim:
         check(lib().fil_set_external_forces(self._h, a.ctypes.data_as(ctypes.c_void_p)))
 
     def set_geometric_switch(self, axis, normal, theta_max, tau_pos, tau_neg, n_transition=10):
-        """Geometric-switch base torques of the pinned filaments (Sec. 5.3); before the first step."""
+        """Geometric-switch base torques of the pinned filaments (Sec. 5.2.2); before the first step."""
         import ctypes
         import numpy as np
         ax = np.ascontiguousarray(np.asarray(axis, dtype=np.float64).reshape(3))
@@ -283,7 +283,7 @@ class Sim:
         return out
 
     def set_motor(self, d0, omega):
-        """Rotating motor of the tether-3 bases (Sec. 5.2); before the first step."""
+        """Rotating motor of the tether-3 bases (Sec. 5.2.1); before the first step."""
         check(lib().fil_set_motor(self._h, float(d0), float(omega)))
 
     def set_wall(self):

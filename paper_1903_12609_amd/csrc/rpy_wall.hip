@@ -1,5 +1,5 @@
 // RPY mobility of equal spheres above a no-slip plane wall z = 0 (the half-space tensor
-// the paper uses for its cilia, Sec. 2.7.1 and Sec. 5.3): the free-space RPY blocks of
+// the paper uses for its cilia, Sec. 2.7.1 and Sec. 5.2.2): the free-space RPY blocks of
 // every pair (with the regularised overlap forms for r < 2a) plus the wall's image part,
 // Blake's image system under the Faxen operators of both spheres (wall_image.h, generated
 // by gen_wall_image.py).  Self terms: 1/(6 pi eta a) I, 1/(8 pi eta a^3) I plus the image

@@ -139,7 +139,7 @@ __device__ __forceinline__ V3 joint_kappa(const SimDev& d, int64_t f, int64_t k,
 // barrier); lane n of the first wave owns segment n (N <= 64) and passes q^j_n (read
 // by the caller, possibly well before).  Nothing may follow it in the caller that
 // needs a barrier.
-// the rotating motor of a tether-3 base (Sec. 5.2): the prescribed rotation per step
+// the rotating motor of a tether-3 base (Sec. 5.2.1): the prescribed rotation per step
 // u_1 = (0, 0, omega dt) and the base on its circle at time tt
 __device__ __forceinline__ V3 motor_u(const SimDev& d, int64_t f) {
     return v3(0.0, 0.0, d.motor_w * d.spar[kSpar * d.fil_susp[f]]);
@@ -410,7 +410,7 @@ int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, con
 }
 
 // ---------------------------------------------------------------- geometric switch
-// Geometric-switch driving torque of model cilia (Sec. 5.3): a torque about a fixed axis
+// Geometric-switch driving torque of model cilia (Sec. 5.2.2): a torque about a fixed axis
 // drives the base of every pinned filament until the angle theta between the wall normal
 // and the base tangent (signed about the axis) reaches +theta_max or -theta_max, where
 // the drive reverses, its magnitude switching between tau_pos (driving towards

@@ -134,8 +134,13 @@ def single_filament(N=15, seed=1001, B=1e3, dt_over_T=1.0, tol=1e-6, kmax=100, b
 
 
 def _place(rng, M_fil, Ns, side, max_bend, min_sep=DL, max_tries=100000):
+    """Random sequential placement with rejection when any segment comes closer than
+    min_sep to a placed one.  Placed segments are hashed into cubic cells of side min_sep,
+    so a candidate is compared only with the segments of its own and the neighbouring
+    cells (every segment within min_sep of it lies there)."""
     Ys, qs = [], []
-    placed = np.zeros((0, 3))
+    cells = {}
+    pts = []
     tries = 0
     for m in range(M_fil):
         N = Ns[m]
@@ -149,14 +154,23 @@ def _place(rng, M_fil, Ns, side, max_bend, min_sep=DL, max_tries=100000):
             centre = rng.uniform(0.0, side, 3)
             Y = chain(np.zeros(3), q)
             Y += centre - Y.mean(axis=0)
-            if len(placed):
-                d2 = ((Y[:, None, :] - placed[None, :, :]) ** 2).sum(-1)
+            near = set()
+            for c in np.floor(Y / min_sep).astype(np.int64):
+                for dx in (-1, 0, 1):
+                    for dy in (-1, 0, 1):
+                        for dz in (-1, 0, 1):
+                            near.update(cells.get((c[0] + dx, c[1] + dy, c[2] + dz), ()))
+            if near:
+                P = np.asarray([pts[i] for i in sorted(near)])
+                d2 = ((Y[:, None, :] - P[None, :, :]) ** 2).sum(-1)
                 if d2.min() < min_sep ** 2:
                     continue
             break
+        for y in Y:
+            cells.setdefault(tuple(np.floor(y / min_sep).astype(np.int64)), []).append(len(pts))
+            pts.append(y)
         Ys.append(Y)
         qs.append(q)
-        placed = np.concatenate([placed, Y])
     fil_off = np.concatenate([[0], np.cumsum(Ns)]).astype(np.int64)
     return fil_off, np.concatenate(Ys), np.concatenate(qs)
 

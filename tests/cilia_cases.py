@@ -1,4 +1,4 @@
-"""Two model cilia (Sec. 5.3) shared by the oracle and GPU tests: pinned filaments of
+"""Two model cilia (Sec. 5.2.2) shared by the oracle and GPU tests: pinned filaments of
 N = 20 standing on the wall one filament length apart (bases one segment spacing above
 it), driven by the geometric switch about the y axis (wall normal z): theta_max = 0.5,
 tau_neg = 0.05 K_B, tau_pos = 3 tau_neg (the paper's torque ratio), a 4-step transition,

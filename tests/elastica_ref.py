@@ -1,4 +1,4 @@
-"""Clamped filament under an end load (the spatial-convergence problem of Sec. 5.1):
+"""Clamped filament under an end load (the spatial-convergence problem of Sec. 4.1):
 the analytic elastica and the discrete set-up shared by the oracle and GPU tests.
 
 The continuum problem: a filament clamped horizontally at s = 0 and loaded by a force

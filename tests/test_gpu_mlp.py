@@ -221,3 +221,24 @@ def test_learned_start_with_untrained_network_still_converges():
         r = g.step()[0]
         assert r["converged"] and r["resid"] <= w.params["tol"]
     print("fallbacks", g.fallbacks())
+
+
+def test_trained_network_cuts_iterations_on_held_out_suspension():
+    """The gain of the learned warm start: the network is trained on the GPU (library
+    kernels only) on 50,000 (state, converged update) pairs of one 500 x 32 sedimenting
+    suspension, then a held-out suspension of the same kind (another seed) is stepped from
+    the learned first iterate and from the plain one at the same tolerance: the learned
+    start needs at least one Broyden iteration per step fewer on average (measured 36.6
+    against 39.0), without fallbacks, and every step converges."""
+    import paper_1903_12609_amd as fil
+    from paper_1903_12609_amd import learned
+    feat, targ = learned.generate(n_fil=500, N=32, steps=100, source="dense", seed=21)
+    m = fil.MLP(32, width=256, depth=3, max_batch=1024, seed=0)
+    learned.train(m, feat, targ, epochs=60, batch=1024, lr=1e-3)
+    w = synth.sediment_suspension(M=500, N=32, side=400.0, seed=1005, dt_over_T=1 / 30)
+    res = learned.compare(w, m, steps=25, skip=5)
+    m.close()
+    print("plain %.2f, learned %.2f iterations per step; time ratio %.3f" % (
+        res["plain"]["iters_per_step"], res["learned"]["iters_per_step"], res["time_ratio"]))
+    assert res["learned"]["learned_steps"] == res["learned"]["steps"] and res["learned"]["fallbacks"] == 0
+    assert res["learned"]["iters_per_step"] <= res["plain"]["iters_per_step"] - 1.0

@@ -1,5 +1,5 @@
 """Validation workloads on the GPU path (the paper's convergence and sedimentation
-checks, Sec. 5: convergence in time; Sec. 6.2.1, settling filament).
+checks, Sec. 4.2: convergence in time; Sec. 5.4.1, settling filament).
 
 * BDF2 in time: settling filaments integrated to the same final time with halved
   steps converge at second order toward a run with a much smaller step and a tight
@@ -125,7 +125,7 @@ def test_settling_filament_deflection_and_drag():
 
 
 def test_clamped_elastica_second_order_in_space():
-    """Sec. 5.1: the steady shape of a clamped filament under an end load converges at
+    """Sec. 4.1: the steady shape of a clamped filament under an end load converges at
     second order in dL to the analytic elastica (F l^2 / K_B = 1.93)."""
     fil, synth = _fil()
     import elastica_ref as er
@@ -175,7 +175,7 @@ def test_external_forces_trajectory_parity(graph):
 
 
 def test_falling_square_tumbles_periodically():
-    """Sec. 6.2.4: four vertical filaments (N = 30) at the corners of a horizontal square
+    """Sec. 5.4.3: four vertical filaments (N = 30) at the corners of a horizontal square
     of side D = 0.268 L settle with steric forces on.  Stiff filaments tumble
     periodically: they spread apart and come back to their initial configuration; the
     return time and the distance at return decrease as B grows (B = 0.1, 1, 10).

@@ -1,4 +1,4 @@
-"""GPU RPY mobility above a no-slip wall (Sec. 2.7.1 / Sec. 5.3's half-space tensor)
+"""GPU RPY mobility above a no-slip wall (Sec. 2.7.1 / Sec. 5.2.2's half-space tensor)
 against the oracle's: applies on clouds of spheres above the wall (overlapping pairs
 included; one and several source chunks), sampled targets of a large cloud, and the
 implicit steps of clamped filaments standing on the wall through fil_set_wall."""
@@ -143,7 +143,7 @@ def test_pinned_filament_parity():
 
 
 def test_cilia_on_the_wall_parity(steps=20):
-    """Two pinned cilia on the wall driven by the geometric switch (Sec. 5.3): per step
+    """Two pinned cilia on the wall driven by the geometric switch (Sec. 5.2.2): per step
     the same iteration count and switch directions as the oracle, positions to 1e-8."""
     import paper_1903_12609_amd as fil
     from oracle import cilia
@@ -172,7 +172,7 @@ def test_cilia_on_the_wall_parity(steps=20):
 
 
 def test_motor_filament_parity():
-    """A filament on the rotating motor of Sec. 5.2 (Sp = 30: visibly bent), 15 steps:
+    """A filament on the rotating motor of Sec. 5.2.1 (Sp = 30: visibly bent), 15 steps:
     iteration counts and positions against the oracle; the base follows the circle."""
     import math
     import paper_1903_12609_amd as fil

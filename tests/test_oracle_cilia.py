@@ -1,4 +1,4 @@
-"""The oracle's geometric switch (Sec. 5.3) pinned to its definition and to the beat it
+"""The oracle's geometric switch (Sec. 5.2.2) pinned to its definition and to the beat it
 must produce: the logistic transition between the old and the new torque, the reversal
 when the base tangent reaches the extreme it is driven towards, and a pinned filament in
 free space that beats between the two extremes with alternating drive."""

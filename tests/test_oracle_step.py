@@ -186,7 +186,7 @@ def test_second_order_in_time():
 
 
 def test_j0_pinned_equals_drag_jacobian_at_straight_state():
-    """Pinned base (position held, rotation free, as the cilia bases of Sec. 5.3):
+    """Pinned base (position held, rotation free, as the cilia bases of Sec. 5.2.2):
     lambda_1 in the Y_1 slot, u_1 an ordinary unknown."""
     N = 5
     q0 = np.array([math.cos(-math.pi / 4), 0, math.sin(-math.pi / 4), 0])
@@ -224,7 +224,7 @@ def test_pinned_filament_hangs_below_its_pin():
 
 
 def _motor_filament(Sp, N=10, d0=4.5977, tilt_deg=15.0):
-    """A filament on a rotating motor (Sec. 5.2): base d0 from the z axis, tilted 15 degrees
+    """A filament on a rotating motor (Sec. 5.2.1): base d0 from the z axis, tilted 15 degrees
     away from it; omega from the Sperm number Sp = zeta_perp omega L^4 / K_B, 0.05 rad per
     step."""
     tilt = math.radians(tilt_deg)

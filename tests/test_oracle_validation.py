@@ -1,4 +1,4 @@
-"""The oracle's external-force term against the analytic elastica (Sec. 5.1): the steady
+"""The oracle's external-force term against the analytic elastica (Sec. 4.1): the steady
 shape of a clamped filament under an end load converges at second order in dL."""
 import numpy as np
 

@@ -1,5 +1,5 @@
 """The oracle's wall-bounded RPY mobility (spheres above a no-slip plane, Sec. 2.7.1 and
-Sec. 5.3) pinned to what fixes it independently of its construction:
+Sec. 5.2.2) pinned to what fixes it independently of its construction:
 
 * Blake's Green's function satisfies the no-slip condition on the wall, is divergence
   free and biharmonic away from the force, and obeys Lorentz reciprocity;
