@@ -456,6 +456,42 @@ def cilia_array_steps(steps=40, dt=25000.0, n_tr=10, tau=0.02):
     return res
 
 
+def array_wall_sweep(steps=10, beats=(100, 300, 1000)):
+    """The full active array above a no-slip wall: 40 x 25 base-clamped filaments of N = 32
+    (spacing 20a, bases one segment spacing above the wall), driven by the swimmers'
+    travelling curvature wave from straight, dt = period/100, /300, /1000; up to `steps`
+    steps each, a dt stopping at its first step that does not converge.  Reports the
+    iterations, applies and time of every step tried."""
+    import torch
+    import paper_1903_12609_amd as fil
+    from paper_1903_12609_amd import synth
+    out = []
+    for spb in beats:
+        w = synth.active_array(nx=40, ny=25, N=32, spacing=20.0, seed=1003, base_z=synth.DL, steps_per_beat=spb)
+        sim = fil.Sim(w.fil_off, w.Y, w.q, w.params, graph=GRAPH_ITERS)
+        sim.set_wall()
+        rec = dict(steps_per_beat=spb, dt=w.params["dt"], iters=[], applies=[], ms=[], converged=True)
+        for j in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = sim.step(raise_on_fail=False)
+            torch.cuda.synchronize()
+            rep = r[1][0] if isinstance(r, tuple) else r[0]
+            rec["iters"].append(rep["iters"])
+            rec["applies"].append(rep["applies"])
+            rec["ms"].append((time.perf_counter() - t0) * 1e3)
+            log("wall array dt = period/%d, step %d: %d iterations, converged %s, residual %.2e" %
+                (spb, j, rep["iters"], rep["converged"], rep["resid"]))
+            if not rep["converged"]:
+                rec["converged"] = False
+                rec["final_residual"] = rep["resid"]
+                break
+        sim.close()
+        out.append(rec)
+    return {"workload": "40 x 25 clamped filaments, N = 32, spacing 20a, bases 2.2a above a no-slip wall, "
+                        "travelling curvature wave from straight, tol 1e-6", "sweep": out}
+
+
 def traffic_per_launch():
     """HBM bytes per launch of the FP32-tile pair kernel from the committed rocprofv3 counter
     summary, or None when the kernel source changed since it was taken."""
@@ -549,6 +585,8 @@ def main():
     ap.add_argument("--steps-only", action="store_true", help="only the implicit-step workloads")
     ap.add_argument("--sediment500-only", action="store_true",
                     help="only the 500 x 32 suspension's steps (for profiling)")
+    ap.add_argument("--array-wall-sweep", action="store_true",
+                    help="only the dt sweep of the 40 x 25 x 32 active array above a wall")
     ap.add_argument("--fcm-steps-only", action="store_true",
                     help="only the solver comparison on the periodic FCM monolayer (for profiling)")
     args = ap.parse_args()
@@ -574,6 +612,9 @@ def main():
         return
     if args.wall_only:
         print(json.dumps({"wall_mobility": wall_mobility_bench()}))
+        return
+    if args.array_wall_sweep:
+        print(json.dumps({"array_wall_sweep": array_wall_sweep()}, default=float))
         return
     if args.fcm_steps_only:
         print(json.dumps({"fcm_monolayer_solvers": fcm_monolayer_steps()}))
