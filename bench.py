@@ -358,7 +358,10 @@ def fcm_apply_bench(reps=5):
     return out
 
 
-WALL_FLOP_PER_PAIR = 1640  # FP64 flops of one pair of the wall kernel (FMA = 2), from its instruction count
+# FP64 flops of one pair of the wall kernel (FMA = 2): the free-space blocks as in the unbounded
+# count (85), R and 1/|R| (14), the 18 image coefficients (153) and their application to F and
+# T (98), as written in wall_image.h
+WALL_FLOP_PER_PAIR = 350
 
 
 def wall_mobility_bench(reps=5):

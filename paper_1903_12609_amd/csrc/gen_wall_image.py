@@ -15,7 +15,13 @@ part G^im = G - S(x - y) under the Faxen operators of both spheres:
 Here the image part is written in the variables R = x - y* and h = y_3 (x_3 = R_3 - h),
 d/dx = d/dR at fixed h, d/dy_1,2 = -d/dR_1,2 and d/dy_3 = d/dh + d/dR_3 (R_3 = x_3 + y_3).
 
-Run:  python gen_wall_image.py   (writes wall_image.h beside it; needs sympy)
+Output form.  The image system is symmetric about the wall normal e, so each block is a
+combination of a few tensors built from R, e and c = R x e whose scalar coefficients depend
+on |R|, R_3, h and a only (see coefficients()).  The header evaluates those 18 coefficients
+(common subexpressions shared) and applies the blocks to F and T through the dot products
+R.F, c.F, R.T, c.T: a few hundred flops per pair instead of the 36 explicit entries.
+
+Run:  python gen_wall_image.py   (writes wall_image.h beside it; needs sympy and mpmath)
 """
 import os
 import time
@@ -83,8 +89,8 @@ class _Printer(C99CodePrinter):
         return super()._print_Pow(e)
 
 
-def main():
-    t0 = time.time()
+def blocks():
+    """The four image blocks (times 8 pi eta) as 3 x 3 lists of sympy expressions."""
     G = [[Gim(i, j) for j in range(3)] for i in range(3)]
     Ly = [[G[i][j] + a ** 2 / 6 * lapy(G[i][j]) for j in range(3)] for i in range(3)]
     tt = [[Ly[i][j] + a ** 2 / 6 * lapx(Ly[i][j]) for j in range(3)] for i in range(3)]
@@ -97,41 +103,150 @@ def main():
     rr = [[sum(c1 * c2 * dx(dy(G[l][n], m), k)
                for (ii, k, l), c1 in EPS.items() if ii == i
                for (jj, m, n), c2 in EPS.items() if jj == j) / 4 for j in range(3)] for i in range(3)]
-    blocks = {"tt": tt, "tr": tr, "rt": rt, "rr": rr}
-    names, exprs = [], []
+    return {"tt": tt, "tr": tr, "rt": rt, "rr": rr}
+
+
+def _div(e, d):
+    q, r = sp.div(sp.Poly(sp.expand(e), R1), sp.Poly(d, R1))
+    assert r.is_zero, "a basis coefficient is not polynomial"
+    return q.as_expr()
+
+
+def _even_r1(e):
+    """R1 enters a coefficient only through R1^2 = 1/ir^2 - R3^2 (the coefficients are
+    functions of |R|, R3, h and a alone: the image system is symmetric about the wall normal)."""
+    out = 0
+    for (k,), c in sp.Poly(sp.expand(e), R1).terms():
+        assert k % 2 == 0, "odd power of R1 in a coefficient"
+        out += c * (1 / ir ** 2 - R3 ** 2) ** (k // 2)
+    return sp.expand(out)
+
+
+def coefficients(B):
+    """Each block on a basis of tensors built from R, the wall normal e = (0, 0, 1) and
+    c = R x e = (R2, -R1, 0), with scalar coefficients in ir, R3, h and a:
+        true tensors (tt, rr):   A I + B R R^T + C R e^T + D e R^T + E e e^T
+        pseudo-tensors (tr, rt): beta [e]x + gamma (c R^T + R c^T) + eps c e^T + zeta e c^T
+    ([e]x v = e x v).  Read off in the plane R2 = 0, where the basis is independent."""
     rho2 = R1 ** 2 + R2 ** 2 + R3 ** 2
-    for b, M in blocks.items():
-        for i in range(3):
-            for j in range(3):
-                names.append("%s[%d][%d]" % (b, i, j))
-                # every power of |R| in terms of ir = 1/|R|: products instead of divisions
-                e = M[i][j].subs(rho2, 1 / ir ** 2)
-                left = [q for q in e.atoms(sp.Pow) if q.base.is_Add and q.base.has(R1) and q.exp.is_negative]
-                assert not left, "a negative power of |R| was left"
-                exprs.append(e)
-    print("derived in %.1f s" % (time.time() - t0), flush=True)
+    E = {b: [[sp.expand(M[i][j].subs(rho2, 1 / ir ** 2).subs(R2, 0)) for j in range(3)] for i in range(3)]
+         for b, M in B.items()}
+    co = {}
+    for b in ("tt", "rr"):
+        M = E[b]
+        assert all(sp.expand(M[i][j]) == 0 for i, j in ((0, 1), (1, 0), (1, 2), (2, 1)))
+        A = M[1][1]
+        Bc = _div(M[0][0] - M[1][1], R1 ** 2)
+        C = _div(M[0][2], R1) - Bc * R3
+        D = _div(M[2][0], R1) - Bc * R3
+        Ec = M[2][2] - A - Bc * R3 ** 2 - (C + D) * R3
+        co[b] = [_even_r1(x) for x in (A, Bc, C, D, Ec)]
+    for b in ("tr", "rt"):
+        P = E[b]
+        assert all(sp.expand(P[i][j]) == 0 for i, j in ((0, 0), (0, 2), (1, 1), (2, 0), (2, 2)))
+        beta = -(P[0][1] - P[1][0]) / 2
+        gam = _div(-(P[0][1] + P[1][0]) / 2, R1 ** 2)
+        eps = _div(-P[1][2], R1) - gam * R3
+        zet = _div(-P[2][1], R1) - gam * R3
+        co[b] = [_even_r1(x) for x in (beta, gam, eps, zet)]
+    return co
+
+
+def check(B, co, trials=20):
+    """The basis form against the full blocks at random points, in 30-digit arithmetic."""
+    import random
+    import mpmath
+    mpmath.mp.dps = 30
+    full = {b: sp.lambdify((R1, R2, R3, h, a), sp.Matrix(M), "mpmath") for b, M in B.items()}
+    cf = {b: sp.lambdify((ir, R3, h, a), co[b], "mpmath") for b in co}
+    rng = random.Random(1)
+    worst = 0
+    for _ in range(trials):
+        r = [mpmath.mpf(rng.uniform(-20, 20)), mpmath.mpf(rng.uniform(-20, 20)), mpmath.mpf(rng.uniform(2.5, 40))]
+        hh, aa = mpmath.mpf(rng.uniform(1.2, float(r[2]) - 1.0)), mpmath.mpf(rng.choice([1.0, 0.7]))
+        irr = 1 / mpmath.sqrt(r[0] ** 2 + r[1] ** 2 + r[2] ** 2)
+        e, c = [0, 0, 1], [r[1], -r[0], 0]
+        ex = [[0, -1, 0], [1, 0, 0], [0, 0, 0]]
+        for b in B:
+            M, k = full[b](r[0], r[1], r[2], hh, aa), cf[b](irr, r[2], hh, aa)
+            sc = max(abs(M[i, j]) for i in range(3) for j in range(3))
+            for i in range(3):
+                for j in range(3):
+                    if b in ("tt", "rr"):
+                        rec = (k[0] * (i == j) + k[1] * r[i] * r[j] + k[2] * r[i] * e[j] + k[3] * e[i] * r[j] +
+                               k[4] * e[i] * e[j])
+                    else:
+                        rec = k[0] * ex[i][j] + k[1] * (c[i] * r[j] + r[i] * c[j]) + k[2] * c[i] * e[j] + k[3] * e[i] * c[j]
+                    worst = max(worst, abs(rec - M[i, j]) / sc)
+    assert worst < 1e-25, worst
+    return worst
+
+
+TEMPLATE = """// Generated by gen_wall_image.py: the image part of the Rotne-Prager-Blake mobility
+// (Blake's image system under the Faxen operators of both spheres) applied to one source's
+// force and torque.  Variables: R = x - y* (y* the mirror image of the source), ir = 1/|R|,
+// h = source height, a the radius; e = (0, 0, 1) the wall normal and c = R x e.  Each block
+// (times 8 pi eta) is written on a basis of tensors built from R, e and c:
+//   tt, rr = A I + B R R^T + C R e^T + D e R^T + E e e^T
+//   tr, rt = beta [e]x + gamma (c R^T + R c^T) + eps c e^T + zeta e c^T
+// with coefficients that depend on ir, R3, h and a only.  Do not edit.
+#pragma once
+
+namespace fil {
+
+// vi += (tt F + tr T), wi += (rt F + rr T), all times 8 pi eta
+__device__ __host__ inline void wall_image_apply(double R1, double R2, double R3, double ir, double h, double a,
+                                                 const double F[3], const double T[3], double vi[3], double wi[3]) {
+%(body)s
+    const double c1 = R2, c2 = -R1;
+    const double rF = R1 * F[0] + R2 * F[1] + R3 * F[2], rT = R1 * T[0] + R2 * T[1] + R3 * T[2];
+    const double cF = c1 * F[0] + c2 * F[1], cT = c1 * T[0] + c2 * T[1];
+    // tt F
+    double k = tt_B * rF + tt_C * F[2];
+    vi[0] += tt_A * F[0] + k * R1;
+    vi[1] += tt_A * F[1] + k * R2;
+    vi[2] += tt_A * F[2] + k * R3 + tt_D * rF + tt_E * F[2];
+    // tr T
+    k = tr_gamma * rT + tr_eps * T[2];
+    vi[0] += -tr_beta * T[1] + k * c1 + tr_gamma * cT * R1;
+    vi[1] += tr_beta * T[0] + k * c2 + tr_gamma * cT * R2;
+    vi[2] += tr_gamma * cT * R3 + tr_zeta * cT;
+    // rt F
+    k = rt_gamma * rF + rt_eps * F[2];
+    wi[0] += -rt_beta * F[1] + k * c1 + rt_gamma * cF * R1;
+    wi[1] += rt_beta * F[0] + k * c2 + rt_gamma * cF * R2;
+    wi[2] += rt_gamma * cF * R3 + rt_zeta * cF;
+    // rr T
+    k = rr_B * rT + rr_C * T[2];
+    wi[0] += rr_A * T[0] + k * R1;
+    wi[1] += rr_A * T[1] + k * R2;
+    wi[2] += rr_A * T[2] + k * R3 + rr_D * rT + rr_E * T[2];
+}
+
+}  // namespace fil
+"""
+
+
+def main():
+    t0 = time.time()
+    B = blocks()
+    co = coefficients(B)
+    print("basis coefficients in %.1f s; reconstruction error %.1e" % (time.time() - t0, check(B, co)), flush=True)
+    names = {"tt": ["A", "B", "C", "D", "E"], "rr": ["A", "B", "C", "D", "E"],
+             "tr": ["beta", "gamma", "eps", "zeta"], "rt": ["beta", "gamma", "eps", "zeta"]}
+    outs, exprs = [], []
+    for b in ("tt", "tr", "rt", "rr"):
+        for n, e in zip(names[b], co[b]):
+            outs.append("%s_%s" % (b, n))
+            exprs.append(e)
     reps, red = sp.cse(exprs, symbols=sp.numbered_symbols("t"), optimizations="basic")
-    print("cse in %.1f s: %d temporaries" % (time.time() - t0, len(reps)), flush=True)
-    lines = []
     pr = _Printer()
-    for s_, e in reps:
-        lines.append("    const double %s = %s;" % (s_, pr.doprint(e)))
-    for n, e in zip(names, red):
-        lines.append("    %s = %s;" % (n, pr.doprint(e)))
-    body = "\n".join(lines)
+    lines = ["    const double %s = %s;" % (s_, pr.doprint(e)) for s_, e in reps]
+    lines += ["    const double %s = %s;" % (n, pr.doprint(e)) for n, e in zip(outs, red)]
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "wall_image.h")
     with open(out, "w") as f:
-        f.write("// Generated by gen_wall_image.py: the image part of the Rotne-Prager-Blake mobility\n"
-                "// blocks times 8 pi eta, in the variables R = x - y* (y* the mirror image of the\n"
-                "// source), ir = 1/|R| and h = source height; a the radius.  Do not edit.\n"
-                "#pragma once\n\n"
-                "namespace fil {\n\n"
-                "__device__ __host__ inline void wall_image_blocks(double R1, double R2, double R3, double ir, "
-                "double h, double a,\n"
-                "                                                  double tt[3][3], double tr[3][3], "
-                "double rt[3][3], double rr[3][3]) {\n"
-                + body + "\n}\n\n}  // namespace fil\n")
-    print("wrote", out, "(%d lines)" % len(lines))
+        f.write(TEMPLATE % {"body": "\n".join(lines)})
+    print("wrote", out, "(%d temporaries)" % len(reps))
 
 
 if __name__ == "__main__":
