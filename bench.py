@@ -495,6 +495,46 @@ def array_wall_sweep(steps=10, beats=(100, 300, 1000)):
                         "travelling curvature wave from straight, tol 1e-6", "sweep": out}
 
 
+def array_wall_steps(steps=200, spacing=40.0, spb=100):
+    """The 40 x 25 array of base-clamped filaments of N = 32 (32,000 segments) above a no-slip
+    wall at lattice spacing 40a (at 20a the first step diverges: the coupling of neighbouring
+    filaments through the fluid, which the block-diagonal J0 does not carry, is too strong for
+    filaments of this length), driven by the travelling curvature wave from straight,
+    dt = period/spb, FP64, tol 1e-6: iterations, mobility applies and wall time of every step."""
+    import numpy as np
+    import torch
+    import paper_1903_12609_amd as fil
+    from paper_1903_12609_amd import synth
+    w = synth.active_array(nx=40, ny=25, N=32, spacing=spacing, seed=1003, base_z=synth.DL, steps_per_beat=spb)
+    sim = fil.Sim(w.fil_off, w.Y, w.q, w.params, graph=GRAPH_ITERS)
+    sim.set_wall()
+    rec = dict(iters=[], applies=[], ms=[], converged=True)
+    for j in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sim.step(raise_on_fail=False)
+        torch.cuda.synchronize()
+        rep = r[1][0] if isinstance(r, tuple) else r[0]
+        rec["iters"].append(rep["iters"])
+        rec["applies"].append(rep["applies"])
+        rec["ms"].append((time.perf_counter() - t0) * 1e3)
+        if not rep["converged"]:
+            rec["converged"] = False
+            log("array on the wall: step %d did not converge (residual %.2e)" % (j, rep["resid"]))
+            break
+        if (j + 1) % 10 == 0:
+            log("array on the wall: step %d, %.1f iterations and %.1f ms per step over the last 10" %
+                (j + 1, np.mean(rec["iters"][-10:]), np.mean(rec["ms"][-10:])))
+    Yf = sim.read_state()[0]
+    sim.close()
+    rec.update(workload="40 x 25 clamped filaments, N = 32 (S = 32000), spacing %ga, bases 2.2a above a no-slip "
+                        "wall, travelling curvature wave from straight, dt = period/%d, FP64, tol 1e-6" % (spacing, spb),
+               steps=len(rec["iters"]), mean_iters=float(np.mean(rec["iters"])),
+               mean_applies=float(np.mean(rec["applies"])), mean_ms=float(np.mean(rec["ms"][1:] or rec["ms"])),
+               min_height=float(Yf[:, 2].min()))
+    return rec
+
+
 def traffic_per_launch():
     """HBM bytes per launch of the FP32-tile pair kernel from the committed rocprofv3 counter
     summary, or None when the kernel source changed since it was taken."""
@@ -590,6 +630,8 @@ def main():
                     help="only the 500 x 32 suspension's steps (for profiling)")
     ap.add_argument("--array-wall-sweep", action="store_true",
                     help="only the dt sweep of the 40 x 25 x 32 active array above a wall")
+    ap.add_argument("--array-wall-steps", action="store_true",
+                    help="only the 200 steps of the 40 x 25 x 32 active array above a wall (spacing 40a)")
     ap.add_argument("--fcm-steps-only", action="store_true",
                     help="only the solver comparison on the periodic FCM monolayer (for profiling)")
     args = ap.parse_args()
@@ -618,6 +660,9 @@ def main():
         return
     if args.array_wall_sweep:
         print(json.dumps({"array_wall_sweep": array_wall_sweep()}, default=float))
+        return
+    if args.array_wall_steps:
+        print(json.dumps({"array_wall_steps": array_wall_steps()}, default=float))
         return
     if args.fcm_steps_only:
         print(json.dumps({"fcm_monolayer_solvers": fcm_monolayer_steps()}))
@@ -657,6 +702,7 @@ def main():
         res["sediment2000_steps"], w = sediment_steps(20, 5, args.graph)
         res["sediment500x32_steps"] = suspension_steps()
         res["ensemble256_steps"] = ensemble_steps()
+        res["array_wall_steps"] = array_wall_steps()
         if not args.no_sweep:
             res["rpy_apply"] = rpy_sweep()
             res["rpy_apply_batched"] = rpy_batched()
