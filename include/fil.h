@@ -413,9 +413,12 @@ int fil_set_graph(fil_sim* sim, int iters_per_launch);
 /* converged unknowns of step j+1 (Y_1, the Lie-algebra increments u_n and  */
 /* the multipliers Lambda) lie from the extrapolated first iterate of the    */
 /* warm start (Sec. 3.3.3 notes that the iteration count depends on that     */
-/* guess).  The prediction is added to the guess; if Broyden then fails, the */
-/* step is re-solved from the plain guess, and convergence is always judged  */
-/* by the same residual tolerance.                                           */
+/* guess).  The network works around a base guess: the extrapolated first   */
+/* iterate plus the last step's own correction (its converged unknowns minus */
+/* its extrapolation: second differences of Y_1 and Lambda, first            */
+/* differences of u).  The prediction is added to that base; if Broyden then */
+/* fails, the step is re-solved from the plain guess, and convergence is     */
+/* always judged by the same residual tolerance.                             */
 /*                                                                           */
 /* Network: 19N inputs -> `depth` SiLU hidden layers of `width` -> 6N        */
 /* outputs for filaments of N segments; BF16 weights and activations with    */
@@ -472,7 +475,9 @@ int fil_mlp_train_step(fil_mlp* mlp, int32_t B, const int32_t* rows, const uint1
  * fil_sim_features: the 19N raw features of every filament at the committed
  *   state (DEVICE float[M][19N]); valid after at least one step.
  * fil_sim_step_target: the scaled difference between the converged unknowns of
- *   the last step and its extrapolated first iterate (DEVICE float[M][6N]).
+ *   the last step and the base of its learned first iterate (the extrapolated
+ *   first iterate plus, from the fourth step on, the correction of the step
+ *   before), scaled like the last 6N features (DEVICE float[M][6N]).
  * fil_sim_set_mlp: use the network for the first iterate of every step from
  *   the fourth on (it needs three committed steps of history); tethered
  *   filaments keep the plain guess.  The network must outlive its use and have

@@ -15,8 +15,10 @@ order [Y_1 | u_1..u_N | Lambda_{3/2}..Lambda_{N-1/2}]):
     last changes of the unknowns:                        6N
        Y_1 and Lambda: X^j - 2 X^{j-1} + X^{j-2}, u: X^j - X^{j-1},
        scaled by 1/dL (Y_1), 1 (u), 1/F_s (Lambda)
-  target (6N): (X* - X0) with the same slot scales,
-  first iterate: X0 + prediction * scales,
+  base (6N): X0 plus the last step's correction X^j - X0^j, which is the unscaled
+     last-changes group (from the fourth step on, free filaments only),
+  target (6N): (X* - base) with the same slot scales,
+  first iterate: base + prediction * scales,
 with F_s the magnitude of the gravity force per segment, or K_B / dL^2 when
 there is none.
 """
@@ -62,21 +64,42 @@ def features(fil_off, Y, q, F, V, Xj, Xjm1, Xjm2, dL, dt, grav, KB):
     return out
 
 
-def target(fil_off, Xstar, X0, dL, grav, KB):
+def base(fil_off, X0, Xj, Xjm1, Xjm2, step, tether=None):
+    """X0 plus the last step's correction for every free filament when three committed
+    steps of history exist (step >= 3), else X0.  The correction of step j is its
+    converged X^j minus its extrapolated first iterate: X^j - 2 X^{j-1} + X^{j-2} for
+    Y_1 and Lambda, u^j - u^{j-1} for u."""
+    fil_off = np.asarray(fil_off)
+    Xb = np.array(X0, dtype=np.float64)
+    if step < 3:
+        return Xb
+    for f in range(len(fil_off) - 1):
+        if tether is not None and tether[f]:
+            continue
+        a, b = 6 * fil_off[f], 6 * fil_off[f + 1]
+        N = int(fil_off[f + 1] - fil_off[f])
+        d = Xj[a:b] - 2.0 * Xjm1[a:b] + Xjm2[a:b]
+        d[3:3 + 3 * N] = Xj[a + 3:a + 3 + 3 * N] - Xjm1[a + 3:a + 3 + 3 * N]
+        Xb[a:b] += d
+    return Xb
+
+
+def target(fil_off, Xstar, Xb, dL, grav, KB):
+    """(X* - Xb) / slot scales per filament, Xb the base (see base())."""
     fil_off = np.asarray(fil_off)
     M = len(fil_off) - 1
     N = int(fil_off[1] - fil_off[0])
     sc = slot_scales(N, dL, force_scale(grav, KB, dL))
-    return np.stack([(Xstar[6 * fil_off[f]:6 * fil_off[f + 1]] - X0[6 * fil_off[f]:6 * fil_off[f + 1]]) / sc
+    return np.stack([(Xstar[6 * fil_off[f]:6 * fil_off[f + 1]] - Xb[6 * fil_off[f]:6 * fil_off[f + 1]]) / sc
                      for f in range(M)])
 
 
-def first_iterate(fil_off, X0, pred, dL, grav, KB):
-    """X0 + pred * scales for every filament (pred [M, 6N], de-standardised)."""
+def first_iterate(fil_off, Xb, pred, dL, grav, KB):
+    """Xb + pred * scales for every filament (pred [M, 6N], de-standardised)."""
     fil_off = np.asarray(fil_off)
     N = int(fil_off[1] - fil_off[0])
     sc = slot_scales(N, dL, force_scale(grav, KB, dL))
-    X = np.array(X0, dtype=np.float64)
+    X = np.array(Xb, dtype=np.float64)
     for f in range(len(fil_off) - 1):
         X[6 * fil_off[f]:6 * fil_off[f + 1]] += pred[f] * sc
     return X

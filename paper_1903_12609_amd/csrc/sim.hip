@@ -36,6 +36,7 @@ struct fil_sim {
     SimDev d{};
     double *Yj = nullptr, *Yjm1 = nullptr, *qj = nullptr, *Xj = nullptr, *Xjm1 = nullptr, *Xjm2 = nullptr;
     double* X0p = nullptr;  // extrapolated first iterate of the last step (the plain warm start)
+    double* Xb = nullptr;   // base of the learned first iterate of the last step
     double *X = nullptr, *f = nullptr, *fprev = nullptr;
     double *Yc = nullptr, *qc = nullptr, *F = nullptr, *T = nullptr, *V = nullptr, *W = nullptr;
     double *AB = nullptr, *AinvT = nullptr, *Chist = nullptr, *Dhist = nullptr, *part = nullptr;
@@ -562,7 +563,7 @@ int ensure_learned_buffers(fil_sim* s, int in_pad, int out_pad) {
     return FIL_OK;
 }
 
-// X = X0 + the network's prediction for every free filament (X0p holds X0)
+// X = Xb + the network's prediction for every free filament (Xb: X0 plus the last step's correction)
 int learned_guess(fil_sim* s) {
     fil_mlp* m = s->mlp;
     const int N = s->seg_uniform;
@@ -571,7 +572,7 @@ int learned_guess(fil_sim* s) {
     TRY(mlp_forward_rows(m, (int)s->M, s->featb, s->pred, s->st));
     const float* nrm = mlp_norm(m);
     const float* mu = nrm + 2 * mlp_in_pad(m);
-    TRY(learned_apply_launch(s->d, N, mlp_out_pad(m), s->pred, mu, mu + mlp_out_pad(m), s->active_d, s->X0p, s->X,
+    TRY(learned_apply_launch(s->d, N, mlp_out_pad(m), s->pred, mu, mu + mlp_out_pad(m), s->active_d, s->Xb, s->X,
                              s->st));
     return FIL_OK;
 }
@@ -681,7 +682,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     A(d_fil_susp, M) A(d_seg_fil, S) A(d_teth, M) A(d_cls_fil, M)
     A(d_base, 3 * M)
     if (phase) A(d_phase, M)
-    A(s->Yj, 3 * S) A(s->Yjm1, 3 * S) A(s->qj, 4 * S) A(s->Xj, n6) A(s->Xjm1, n6) A(s->Xjm2, n6) A(s->X0p, n6)
+    A(s->Yj, 3 * S) A(s->Yjm1, 3 * S) A(s->qj, 4 * S) A(s->Xj, n6) A(s->Xjm1, n6) A(s->Xjm2, n6) A(s->X0p, n6) A(s->Xb, n6)
     A(s->X, n6) A(s->f, n6) A(s->fprev, n6)
     A(s->Yc, 3 * S) A(s->qc, 4 * S) A(s->F, 3 * S) A(s->T, 3 * S) A(s->V, 3 * S) A(s->W, 3 * S)
     A(s->AB, n6 * kBandW) A(s->ipiv, n6) A(s->rdiag, n6)
@@ -765,6 +766,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
         TRY(upload(s->Xjm1, zeros));
         TRY(upload(s->Xjm2, zeros));
         TRY(upload(s->X0p, zeros));
+        TRY(upload(s->Xb, zeros));
         TRY(upload(s->exports_d, std::vector<int64_t>(1, 0)));
         TRY(upload(s->X, zeros));
         TRY(upload(s->resbits_d, std::vector<unsigned long long>(4 * nsusp, 0ull)));
@@ -1001,8 +1003,8 @@ int fil_bdf2_step(fil_sim* s, fil_step_report* report) {
     if (s->sw) TRY(switch_torque_launch(s->d, s->swa, s->qj, s->text_d, s->st));
     // one kernel starts the step: first iterate and its copy, every suspension running,
     // the device log cleared, the time t^{j+1}
-    TRY(initial_guess_launch(s->d, s->step, s->Yj, s->Yjm1, s->Xj, s->Xjm1, s->X, s->X0p, s->active_d, s->log_d,
-                             s->time_d, s->t + s->p.dt, s->st));
+    TRY(initial_guess_launch(s->d, s->step, s->Yj, s->Yjm1, s->Xj, s->Xjm1, s->Xjm2, s->X, s->X0p, s->Xb,
+                             s->active_d, s->log_d, s->time_d, s->t + s->p.dt, s->st));
     bool learned = s->use_mlp && s->mlp && s->step >= 3;
     if (learned) TRY(learned_guess(s));
     SolveLog L(ns);
@@ -1082,7 +1084,7 @@ int fil_sim_step_target(fil_sim* s, float* out) {
     FIL_CHECK_ARG(s && out, "fil_sim_step_target: null argument");
     FIL_CHECK_ARG(s->seg_uniform > 0, "fil_sim_step_target: filaments of different lengths");
     FIL_CHECK_ARG(s->step >= 1, "fil_sim_step_target: no step taken yet");
-    return learned_target_launch(s->d, s->seg_uniform, s->Xj, s->X0p, out, s->st);
+    return learned_target_launch(s->d, s->seg_uniform, s->Xj, s->Xb, out, s->st);
 }
 
 int fil_sim_fallbacks(fil_sim* s, int64_t* n) {
@@ -1500,8 +1502,8 @@ int kry_begin(fil_sim* s, const char* who, int precond, double krylov_tol, doubl
     s->bc = coefs(s->step);
     s->cur = 0;
     s->active_h[0] = 1;
-    TRY(initial_guess_launch(s->d, s->step, s->Yj, s->Yjm1, s->Xj, s->Xjm1, s->X, s->X0p, s->active_d, s->log_d,
-                             s->time_d, s->t + s->p.dt, s->st));
+    TRY(initial_guess_launch(s->d, s->step, s->Yj, s->Yjm1, s->Xj, s->Xjm1, s->Xjm2, s->X, s->X0p, s->Xb,
+                             s->active_d, s->log_d, s->time_d, s->t + s->p.dt, s->st));
     std::vector<double> sp(kSpar * s->nsusp);
     FIL_HIP_TRY(hipMemcpy(sp.data(), s->spar, sp.size() * sizeof(double), hipMemcpyDeviceToHost));
     if (precond == 1) {

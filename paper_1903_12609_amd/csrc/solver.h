@@ -135,11 +135,12 @@ struct UpdateArgs {
     double *Yc, *qc, *F, *T, *box;
 };
 int broyden_state_launch(const SimDev& d, const UpdateArgs& u, const JudgeArgs& jg, int32_t* active, hipStream_t st);
-// Start of a step: the first iterate X0 (and its copy X0c) for every suspension, every
-// suspension marked running, the device log cleared and the device time set to tt.
+// Start of a step: the first iterate X0 (and its copy X0c) for every suspension, the base
+// of the learned first iterate Xb (X0 plus the last step's correction, from step 3 on),
+// every suspension marked running, the device log cleared and the device time set to tt.
 int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const double* Yjm1, const double* Xj,
-                         const double* Xjm1, double* X0, double* X0c, int32_t* active, SuspLog* log, double* time_d,
-                         double tt, hipStream_t st);
+                         const double* Xjm1, const double* Xjm2, double* X0, double* X0c, double* Xb, int32_t* active,
+                         SuspLog* log, double* time_d, double tt, hipStream_t st);
 // copies the device log to pinned host slot (*counter mod 2) and advances *counter
 int log_export_launch(const SuspLog* log, int64_t ns, SuspLog* slot0, SuspLog* slot1, int64_t* counter,
                       hipStream_t st);

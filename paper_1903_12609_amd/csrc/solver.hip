@@ -704,10 +704,11 @@ int residual_launch(const SimDev& d, const BdfCoef& bc, const double* X, const d
 __global__ void __launch_bounds__(256) initial_guess_kernel(SimDev d, int64_t step, const double* __restrict__ Yj,
                                                           const double* __restrict__ Yjm1,
                                                           const double* __restrict__ Xj,
-                                                          const double* __restrict__ Xjm1, double* __restrict__ X0,
-                                                          double* __restrict__ X0c, int32_t* __restrict__ active,
-                                                          SuspLog* __restrict__ log, double* __restrict__ time_d,
-                                                          double tt) {
+                                                          const double* __restrict__ Xjm1,
+                                                          const double* __restrict__ Xjm2, double* __restrict__ X0,
+                                                          double* __restrict__ X0c, double* __restrict__ Xb,
+                                                          int32_t* __restrict__ active, SuspLog* __restrict__ log,
+                                                          double* __restrict__ time_d, double tt) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (blockIdx.x == 0) {
         for (int64_t i = threadIdx.x; i < d.nsusp; i += blockDim.x) {
@@ -736,14 +737,20 @@ __global__ void __launch_bounds__(256) initial_guess_kernel(SimDev d, int64_t st
         }
         X0[r0 + i] = X0c[r0 + i] = x0;
         X0[r1 + i] = X0c[r1 + i] = x1;
+        // base of the learned first iterate: the extrapolation plus the last step's own
+        // correction (its converged unknowns minus its extrapolation: the second difference
+        // of Y_1 and Lambda, the first difference of u), for free filaments from step 3 on
+        const bool hist = step >= 3 && !teth;
+        Xb[r0 + i] = hist ? x0 + (Xj[r0 + i] - 2.0 * Xjm1[r0 + i] + Xjm2[r0 + i]) : x0;
+        Xb[r1 + i] = hist ? x1 + (Xj[r1 + i] - Xjm1[r1 + i]) : x1;
     }
 }
 
 int initial_guess_launch(const SimDev& d, int64_t step, const double* Yj, const double* Yjm1, const double* Xj,
-                         const double* Xjm1, double* X0, double* X0c, int32_t* active, SuspLog* log, double* time_d,
-                         double tt, hipStream_t st) {
+                         const double* Xjm1, const double* Xjm2, double* X0, double* X0c, double* Xb, int32_t* active,
+                         SuspLog* log, double* time_d, double tt, hipStream_t st) {
     initial_guess_kernel<<<(unsigned)std::max<int64_t>(1, ceil_div(d.S, 256)), 256, 0, st>>>(
-        d, step, Yj, Yjm1, Xj, Xjm1, X0, X0c, active, log, time_d, tt);
+        d, step, Yj, Yjm1, Xj, Xjm1, Xjm2, X0, X0c, Xb, active, log, time_d, tt);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }

@@ -6,6 +6,10 @@ feature/target kernels, the BF16 MFMA network and its Adam update); this
 module only sequences the calls, draws seeded permutations and holds device
 tensors.
 
+What the network predicts: the converged unknowns of a step minus a base guess, the
+extrapolated first iterate plus the last step's own correction (the step target of
+`Sim.step_target`); the prediction is added back to that base.
+
 Training data ("single filament" source): independent sedimenting filaments
 of N segments, each its own suspension in one batched simulation, with the
 gravity number B log-uniform in [1e2, 1e4], isotropic orientations and a

@@ -127,3 +127,28 @@ def test_target_and_first_iterate_are_inverse():
     assert np.allclose(OL.first_iterate(fil_off, X0, t, **kw), Xs, atol=1e-12)
     # the multiplier slots are measured in units of the gravity force per segment
     assert np.isclose(t[0, -1], (Xs[6 * 5 - 1] - X0[6 * 5 - 1]) / 2.0)
+
+
+def test_base_is_extrapolation_plus_last_correction():
+    """The learned start's base is X0 plus the unscaled last-changes features; it is X0
+    before three steps of history and for tethered filaments, and a history linear in time
+    adds nothing to Y_1 and Lambda."""
+    rng = np.random.default_rng(6)
+    fil_off, Y, q, F, V, (Xj, X1, X2) = _fake_state(rng)
+    X0 = rng.standard_normal(Xj.shape)
+    kw = dict(dL=2.2, dt=0.7, grav=(0, 0, -2.0), KB=1.0)
+    N = 5
+    feats = OL.features(fil_off, Y, q, F, V, Xj, X1, X2, **kw)
+    sc = OL.slot_scales(N, kw["dL"], OL.force_scale(kw["grav"], kw["KB"], kw["dL"]))
+    Xb = OL.base(fil_off, X0, Xj, X1, X2, step=3)
+    for f in range(3):
+        assert np.allclose(Xb[30 * f:30 * (f + 1)] - X0[30 * f:30 * (f + 1)], feats[f, 13 * N:] * sc, atol=1e-12)
+    assert np.array_equal(OL.base(fil_off, X0, Xj, X1, X2, step=2), X0)
+    Xt = OL.base(fil_off, X0, Xj, X1, X2, step=3, tether=[0, 1, 0])
+    assert np.array_equal(Xt[30:60], X0[30:60]) and np.array_equal(Xt[:30], Xb[:30])
+    Xl = OL.base(fil_off, X0, Xj, Xj - 0.3 * X1, Xj - 0.6 * X1, step=5)
+    for f in range(3):
+        a = 30 * f
+        assert np.allclose(Xl[a:a + 3], X0[a:a + 3], atol=1e-12)
+        assert np.allclose(Xl[a + 3 + 3 * N:a + 30], X0[a + 3 + 3 * N:a + 30], atol=1e-12)
+        assert np.allclose(Xl[a + 3:a + 3 + 3 * N] - X0[a + 3:a + 3 + 3 * N], 0.3 * X1[a + 3:a + 3 + 3 * N])
