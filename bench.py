@@ -643,6 +643,8 @@ def main():
     ap.add_argument("--array-wall-steps", action="store_true",
                     help="only the 200 steps of the 40 x 25 x 32 active array above a wall (spacing 40a)")
     ap.add_argument("--learned-only", action="store_true", help="only the learned warm start comparison")
+    ap.add_argument("--sediment2000-only", action="store_true",
+                    help="only the 100 x 20 suspension's steps (for profiling)")
     ap.add_argument("--fcm-steps-only", action="store_true",
                     help="only the solver comparison on the periodic FCM monolayer (for profiling)")
     args = ap.parse_args()
@@ -674,6 +676,9 @@ def main():
         return
     if args.array_wall_steps:
         print(json.dumps({"array_wall_steps": array_wall_steps()}, default=float))
+        return
+    if args.sediment2000_only:
+        print(json.dumps({"sediment2000_steps": sediment_steps(20, 5, args.graph)[0]}))
         return
     if args.learned_only:
         print(json.dumps({"learned_warm_start": learned_gain(log)}))
