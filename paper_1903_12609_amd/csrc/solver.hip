@@ -1549,17 +1549,19 @@ int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const 
             j0_band_factor_kernel<false><<<(unsigned)cnt, 64, 0, st>>>(d, active, AB, ipiv, rdiag, flag, coff);
         }
         if (!AinvT) continue;
-        // one thread per inverse column; a block's columns (64, 32 or 16, so that its
-        // band, pivots and forward results fit in LDS) share the staged factor
+        // one thread per inverse column; a block's columns (the most of 64, 32 or 16 whose
+        // band, pivots and forward results fit in one CU's LDS: a block holds one CU either
+        // way, so the widest block does the most columns per CU; 500 x 32 suspension: 64
+        // columns 0.40 ms against 0.72 ms for 32) share the staged factor
         auto lds = [nc](int cb) {
             return ((size_t)(nc + kInvPadLo + kInvPadHi) * kBandW + (size_t)nc * (cb + 2)) * sizeof(double) +
                    (size_t)nc * sizeof(int);
         };
-        if (nc <= 128) {
+        if (lds(64) <= kLdsPerCU) {
             const dim3 grid((unsigned)cnt, (unsigned)ceil_div(nc, 64));
             if (int rc = allow_lds(j0_inverse_cols_kernel<64>, lds(64))) return rc;
             j0_inverse_cols_kernel<64><<<grid, 64, lds(64), st>>>(d, AB, ipiv, rdiag, active, AinvT, coff);
-        } else if (nc <= 256) {
+        } else if (lds(32) <= kLdsPerCU) {
             const dim3 grid((unsigned)cnt, (unsigned)ceil_div(nc, 32));
             if (int rc = allow_lds(j0_inverse_cols_kernel<32>, lds(32))) return rc;
             j0_inverse_cols_kernel<32><<<grid, 64, lds(32), st>>>(d, AB, ipiv, rdiag, active, AinvT, coff);

@@ -73,6 +73,24 @@ def test_first_quasi_newton_step(name, j0_mode):
     assert rel_l2(g.iterate().cpu().numpy(), X1) <= 1e-11
 
 
+@pytest.mark.parametrize("N", [32, 48, 64])
+def test_first_quasi_newton_step_long_filaments(N):
+    """The explicit inverse of long filaments' blocks: 192, 288 and 384 unknowns take the
+    inverse kernel's 64-, 32- and 16-column forms (the widest whose LDS fits a CU)."""
+    print("case N", N, flush=True)
+    w = synth.sediment_suspension(M=3, N=N, side=40.0 + 3.0 * N, seed=23 + N, dt_over_T=1 / 30)
+    o, g = _pair(w, "dense")
+    X0 = o.initial_guess()
+    f0, _ = o.residual(X0)
+    X1 = X0.copy()
+    for f in range(w.M):
+        a, b = 6 * w.fil_off[f], 6 * w.fil_off[f + 1]
+        X1[a:b] -= np.linalg.solve(o.j0_filament(f, X0), f0[a:b])
+    f0_gpu = g.broyden_begin(_to_dev(X0)).cpu().numpy()
+    assert rel_l2(f0_gpu, f0) <= 1e-12
+    assert rel_l2(g.iterate().cpu().numpy(), X1) <= 1e-11
+
+
 @pytest.mark.parametrize("j0_mode", ["banded", "dense"])
 @pytest.mark.parametrize("name", list(WL))
 def test_every_broyden_iterate(name, j0_mode):
