@@ -643,6 +643,7 @@ def main():
     ap.add_argument("--array-wall-steps", action="store_true",
                     help="only the 200 steps of the 40 x 25 x 32 active array above a wall (spacing 40a)")
     ap.add_argument("--learned-only", action="store_true", help="only the learned warm start comparison")
+    ap.add_argument("--ensemble-only", action="store_true", help="only the 256-suspension ensemble's steps")
     ap.add_argument("--sediment2000-only", action="store_true",
                     help="only the 100 x 20 suspension's steps (for profiling)")
     ap.add_argument("--fcm-steps-only", action="store_true",
@@ -676,6 +677,9 @@ def main():
         return
     if args.array_wall_steps:
         print(json.dumps({"array_wall_steps": array_wall_steps()}, default=float))
+        return
+    if args.ensemble_only:
+        print(json.dumps({"ensemble256_steps": ensemble_steps()}))
         return
     if args.sediment2000_only:
         print(json.dumps({"sediment2000_steps": sediment_steps(20, 5, args.graph)[0]}))

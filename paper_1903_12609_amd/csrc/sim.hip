@@ -40,6 +40,7 @@ struct fil_sim {
     double *X = nullptr, *f = nullptr, *fprev = nullptr;
     double *Yc = nullptr, *qc = nullptr, *F = nullptr, *T = nullptr, *V = nullptr, *W = nullptr;
     double *AB = nullptr, *AinvT = nullptr, *Chist = nullptr, *Dhist = nullptr, *part = nullptr;
+    double* gsolve = nullptr;  // J0^{-1} f formed before the update (band path, many filaments)
     double* rdiag = nullptr;  // reciprocal pivots of the band factor [6S]
     double* box = nullptr;
     double* spar = nullptr;  // [nsusp][kSpar]
@@ -179,6 +180,10 @@ constexpr double kF32Floor = 3e-8;
 constexpr double kNoiseMargin = 3000.0;
 // timing events of mobility launches not yet read (read when the pool is this full, or on request)
 constexpr int kMaxPendingTimings = 256;
+// from this many filaments on, the band path forms J0^{-1} f in a kernel of its own before
+// the update (inside the update kernel the sweeps run six per CU, a latency-bound chain of
+// ~570 cycles per row: 256-suspension ensemble, 8684 filaments, 580 us per update)
+constexpr int64_t kLaneSolveMinFil = 256;
 
 // adds the recorded mobility-kernel durations (stream already synchronised)
 int collect_timing(fil_sim* s) {
@@ -284,7 +289,7 @@ int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipE
 // Broyden update k (k < 0: the first step) from the residual fnew, then the state at the new X
 UpdateArgs update_args(fil_sim* s, int k, const double* fnew, double* dXout) {
     return UpdateArgs{k,     s->AB,    s->ipiv, s->rdiag, s->AinvT, s->part, s->Chist, s->Dhist, fnew, s->fprev,
-                      s->X,  dXout,    s->qj,   s->time_d, s->Yc,   s->qc,   s->F,     s->T,     s->box};
+                      s->X,  dXout,    s->qj,   s->time_d, s->Yc,   s->qc,   s->F,     s->T,     s->box, s->gsolve};
 }
 
 // max|f|/a and max|b dt (V, dexpinv Omega)| per suspension of the last evaluation
@@ -687,6 +692,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     A(s->Yc, 3 * S) A(s->qc, 4 * S) A(s->F, 3 * S) A(s->T, 3 * S) A(s->V, 3 * S) A(s->W, 3 * S)
     A(s->AB, n6 * kBandW) A(s->ipiv, n6) A(s->rdiag, n6)
     if (dense) { A(s->AinvT, dense_tot) A(d_dense_off, M) }
+    if (!dense && M >= kLaneSolveMinFil) { A(s->gsolve, n6) }
     A(s->Chist, (size_t)p->kmax * n6) A(s->Dhist, (size_t)p->kmax * n6) A(s->part, (size_t)M * max_dots)
     A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->time_d, 1) A(s->log_d, nsusp) A(s->exports_d, 1)
     A(s->active_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 4 * nsusp)

@@ -133,6 +133,9 @@ struct UpdateArgs {
     const double* qj;      // state at the new X, as state_forces_launch
     const double* tt;
     double *Yc, *qc, *F, *T, *box;
+    // band path with many filaments: J0^{-1} fnew is formed first by a kernel of one wave
+    // per filament into gsolve [6S] (X layout); null: the update kernel's own sweeps
+    double* gsolve;
 };
 int broyden_state_launch(const SimDev& d, const UpdateArgs& u, const JudgeArgs& jg, int32_t* active, hipStream_t st);
 // Start of a step: the first iterate X0 (and its copy X0c) for every suspension, the base

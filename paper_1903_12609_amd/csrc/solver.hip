@@ -1736,6 +1736,8 @@ __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs 
             for (int p = 1; p < P; p++) acc += red[p * n + i];
             sg[i] = acc;
         }
+    } else if (u.gsolve) {
+        for (int i = t; i < n; i += NT) sg[i] = u.gsolve[e0 + i];
     } else {
         // L f in the interleaved order, then the sweeps through the band factor
         __shared__ double y[6 * kMaxSeg], rd[6 * kMaxSeg];
@@ -1808,8 +1810,39 @@ __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs 
     filament_state(d, f, sx, qjn, *u.tt, u.Yc, u.qc, u.F, u.T, u.box);
 }
 
+// J0^{-1} f for many filaments at once: one single-wave workgroup per filament running the
+// band sweeps, before the update kernel.  Inside the update kernel the sweeps occupy one of
+// its four waves and its LDS allows six workgroups per CU, so a CU runs six sweeps; here a
+// CU holds up to twenty (7.7 KB of LDS each), which hides the sweeps' per-row latency.
+__global__ void __launch_bounds__(64) band_solve_kernel(SimDev d, const double* __restrict__ AB,
+                                                        const int32_t* __restrict__ ipiv,
+                                                        const double* __restrict__ rdiag,
+                                                        const int32_t* __restrict__ active,
+                                                        const double* __restrict__ fX, double* __restrict__ g) {
+    const int64_t f = blockIdx.x;
+    if (!active[d.fil_susp[f]]) return;
+    const int64_t s0 = d.seg_off[f];
+    const int N = (int)(d.seg_off[f + 1] - s0);
+    const int n = 6 * N;
+    const int64_t e0 = 6 * s0;
+    const int lane = threadIdx.x;
+    __shared__ double y[6 * kMaxSeg], rd[6 * kMaxSeg];
+    __shared__ int ip[6 * kMaxSeg];
+    for (int i = lane; i < n; i += 64) {
+        y[i] = diff_rhs(fX + e0, i, N);
+        rd[i] = rdiag[e0 + i];
+        ip[i] = ipiv[e0 + i];
+    }
+    __syncthreads();
+    band_sweeps(AB + e0 * kBandW, ip, rd, y, n, lane);
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) g[e0 + slot_of(i / 3, N) + i % 3] = y[i];
+}
+
 int broyden_state_launch(const SimDev& d, const UpdateArgs& u, const JudgeArgs& jg, int32_t* active, hipStream_t st) {
     if (d.M == 0) return FIL_OK;
+    if (u.gsolve && !u.AinvT)
+        band_solve_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, u.AB, u.ipiv, u.rdiag, active, u.fnew, u.gsolve);
     if (fil_threads(d) == 1024) broyden_state_kernel<1024><<<(unsigned)d.M, 1024, 0, st>>>(d, u, jg, active);
     else broyden_state_kernel<256><<<(unsigned)d.M, 256, 0, st>>>(d, u, jg, active);
     FIL_HIP_TRY(hipGetLastError());

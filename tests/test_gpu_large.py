@@ -108,3 +108,27 @@ def test_batched_suspensions_over_256_filaments():
     g.close()
     assert rel_l2(Yg, np.concatenate([o.Y for o in os_])) <= 1e-8
     assert rel_l2(qg, np.concatenate([o.q for o in os_])) <= 1e-8
+
+
+def test_band_solve_kernel_mixed_lengths():
+    """Band path with 300 filaments of 2 to 50 segments: J0^{-1} f is formed by the band
+    solve kernel of its own (one wave per filament) before the update, and
+    X1 = X0 - J0^{-1} f(X0) matches the oracle's dense LU solve."""
+    import paper_1903_12609_amd as fil
+    print("case band solve kernel", flush=True)
+    rng = np.random.default_rng(91)
+    Ns = [int(n) for n in rng.integers(2, 51, 300)]
+    base = synth.sediment_suspension(M=2, N=10, seed=91)
+    fil_off, Y, q = synth._place(rng, 300, Ns, 260.0, 0.02)
+    o = oracle.Sim(fil_off, Y, q, nthreads=8, **base.params)
+    X0 = o.initial_guess()
+    f0, _ = o.residual(X0)
+    X1 = X0.copy()
+    for f in range(300):
+        a, b = 6 * fil_off[f], 6 * fil_off[f + 1]
+        X1[a:b] -= np.linalg.solve(o.j0_filament(f, X0), f0[a:b])
+    g = fil.Sim(fil_off, Y, q, base.params, j0_mode="banded")
+    g.broyden_begin(_to_dev(X0))
+    X1g = g.iterate().cpu().numpy()
+    g.close()
+    assert rel_l2(X1g, X1) <= 1e-11, rel_l2(X1g, X1)
