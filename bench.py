@@ -391,12 +391,15 @@ def wall_mobility_bench(reps=5):
         Y[:, 2] += synth.DL
         d = lambda x: torch.from_numpy(np.ascontiguousarray(x.T)).cuda()
         Yd, Fd, Td = d(Y), d(F), d(T)
-        V, W = fil.rpy_wall_apply(Yd, Fd, Td)
-        ms = _time_applies(lambda: fil.rpy_wall_apply(Yd, Fd, Td, V=V, W=W), reps if S > 10000 else 20) * 1e3
-        tf = WALL_FLOP_PER_PAIR * float(S) ** 2 / (ms * 1e-3) / 1e12
-        out["apply"].append(dict(S=S, ms=ms, pairs_per_s=float(S) ** 2 / (ms * 1e-3), tflops=tf,
-                                 frac_of_peak=tf / PEAK_FP64_TFLOPS))
-        log("wall apply", out["apply"][-1])
+        for prec in ("f64", "f32tile"):
+            V, W = fil.rpy_wall_apply(Yd, Fd, Td, prec=prec)
+            ms = _time_applies(lambda: fil.rpy_wall_apply(Yd, Fd, Td, prec=prec, V=V, W=W),
+                               reps if S > 10000 else 20) * 1e3
+            tf = WALL_FLOP_PER_PAIR * float(S) ** 2 / (ms * 1e-3) / 1e12
+            pk = PEAK_FP64_TFLOPS if prec == "f64" else PEAK_FP32_TFLOPS
+            out["apply"].append(dict(S=S, prec=prec, ms=ms, pairs_per_s=float(S) ** 2 / (ms * 1e-3), tflops=tf,
+                                     frac_of_peak=tf / pk))
+            log("wall apply", out["apply"][-1])
     w = synth.active_array(nx=6, ny=6, N=20, spacing=20.0, seed=1003, base_z=synth.DL)
     res = {}
     for wall in (True, False):
@@ -505,20 +508,21 @@ def array_wall_sweep(steps=10, beats=(100, 300, 1000)):
                         "travelling curvature wave from straight, tol 1e-6", "sweep": out}
 
 
-def array_wall_steps(steps=200, spacing=40.0, spb=100):
+def array_wall_steps(steps=200, spacing=40.0, spb=100, prec="f32tile"):
     """The 40 x 25 array of base-clamped filaments of N = 32 (32,000 segments) above a no-slip
     wall at lattice spacing 40a (at 20a the first step diverges: the coupling of neighbouring
     filaments through the fluid, which the block-diagonal J0 does not carry, is too strong for
     filaments of this length), driven by the travelling curvature wave from straight,
-    dt = period/spb, FP64, tol 1e-6: iterations, mobility applies and wall time of every step."""
+    dt = period/spb, tol 1e-6, FP32 tiles with an FP64 finish (or FP64): iterations,
+    mobility applies and wall time of every step."""
     import numpy as np
     import torch
     import paper_1903_12609_amd as fil
     from paper_1903_12609_amd import synth
     w = synth.active_array(nx=40, ny=25, N=32, spacing=spacing, seed=1003, base_z=synth.DL, steps_per_beat=spb)
-    sim = fil.Sim(w.fil_off, w.Y, w.q, w.params, graph=GRAPH_ITERS)
+    sim = fil.Sim(w.fil_off, w.Y, w.q, w.params, graph=GRAPH_ITERS, prec=prec)
     sim.set_wall()
-    rec = dict(iters=[], applies=[], ms=[], converged=True)
+    rec = dict(iters=[], applies=[], applies_f64=[], ms=[], converged=True)
     for j in range(steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -527,21 +531,22 @@ def array_wall_steps(steps=200, spacing=40.0, spb=100):
         rep = r[1][0] if isinstance(r, tuple) else r[0]
         rec["iters"].append(rep["iters"])
         rec["applies"].append(rep["applies"])
+        rec["applies_f64"].append(rep["applies_f64"])
         rec["ms"].append((time.perf_counter() - t0) * 1e3)
         if not rep["converged"]:
             rec["converged"] = False
-            log("array on the wall: step %d did not converge (residual %.2e)" % (j, rep["resid"]))
+            log("array on the wall (%s): step %d did not converge (residual %.2e)" % (prec, j, rep["resid"]))
             break
         if (j + 1) % 10 == 0:
-            log("array on the wall: step %d, %.1f iterations and %.1f ms per step over the last 10" %
-                (j + 1, np.mean(rec["iters"][-10:]), np.mean(rec["ms"][-10:])))
+            log("array on the wall (%s): step %d, %.1f iterations and %.1f ms per step over the last 10" %
+                (prec, j + 1, np.mean(rec["iters"][-10:]), np.mean(rec["ms"][-10:])))
     Yf = sim.read_state()[0]
     sim.close()
     rec.update(workload="40 x 25 clamped filaments, N = 32 (S = 32000), spacing %ga, bases 2.2a above a no-slip "
-                        "wall, travelling curvature wave from straight, dt = period/%d, FP64, tol 1e-6" % (spacing, spb),
+                        "wall, travelling curvature wave from straight, dt = period/%d, %s, tol 1e-6" % (spacing, spb, prec),
                steps=len(rec["iters"]), mean_iters=float(np.mean(rec["iters"])),
-               mean_applies=float(np.mean(rec["applies"])), mean_ms=float(np.mean(rec["ms"][1:] or rec["ms"])),
-               min_height=float(Yf[:, 2].min()))
+               mean_applies=float(np.mean(rec["applies"])), mean_applies_f64=float(np.mean(rec["applies_f64"])),
+               mean_ms=float(np.mean(rec["ms"][1:] or rec["ms"])), min_height=float(Yf[:, 2].min()))
     return rec
 
 
@@ -676,7 +681,8 @@ def main():
         print(json.dumps({"array_wall_sweep": array_wall_sweep()}, default=float))
         return
     if args.array_wall_steps:
-        print(json.dumps({"array_wall_steps": array_wall_steps()}, default=float))
+        print(json.dumps({"array_wall_steps": {"f32tile": array_wall_steps(),
+                                               "f64": array_wall_steps(steps=50, prec="f64")}}, default=float))
         return
     if args.ensemble_only:
         print(json.dumps({"ensemble256_steps": ensemble_steps()}))
@@ -725,7 +731,7 @@ def main():
         res["sediment2000_steps"], w = sediment_steps(20, 5, args.graph)
         res["sediment500x32_steps"] = suspension_steps()
         res["ensemble256_steps"] = ensemble_steps()
-        res["array_wall_steps"] = array_wall_steps()
+        res["array_wall_steps"] = {"f32tile": array_wall_steps(), "f64": array_wall_steps(steps=50, prec="f64")}
         if not args.no_sweep:
             res["rpy_apply"] = rpy_sweep()
             res["rpy_apply_batched"] = rpy_batched()

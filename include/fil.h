@@ -104,11 +104,16 @@ int64_t fil_rpy_noalloc_scratch_bytes(void);
  * whose self terms are the Rotne-Prager-Blake wall corrections (e.g. 1 - 9a/16h + a^3/8h^3
  * - a^5/16h^5 for translation parallel to the wall).  Valid for centres at z >= a (spheres
  * not crossing the wall); smaller heights are evaluated with the same formulas.
- *   S, Y, F, T, a, eta, V, Omega  as fil_rpy_mobility_apply (FP64 only)
- *   work   device scratch of fil_rpy_wall_workspace_bytes(S) bytes (NULL when 0)
- * Deterministic: the partial sums over source chunks are added in a fixed order. */
+ *   S, Y, F, T, a, eta, V, Omega  as fil_rpy_mobility_apply
+ *   prec   FIL_PREC_F64, or FIL_PREC_F32TILE: the pair arithmetic (free-space and image
+ *          parts) in float on coordinates relative to an FP64 origin per 16 sources, float
+ *          sums of each 16 added to FP64 sums per target; self terms in FP64
+ *   work   device scratch of fil_rpy_wall_workspace_bytes(S) bytes (NULL when 0; the same
+ *          for both precisions)
+ * Deterministic: the partial sums over source chunks are added in a fixed order.
+ * FIL_EINVAL on a bad argument or precision, or a workspace too small. */
 int64_t fil_rpy_wall_workspace_bytes(int64_t S);
-int fil_rpy_wall_apply(int64_t S, const double* Y, const double* F, const double* T, double a, double eta,
+int fil_rpy_wall_apply(int64_t S, const double* Y, const double* F, const double* T, double a, double eta, int prec,
                        double* V, double* Omega, void* work, int64_t work_bytes, void* stream);
 
 /* Force-coupling-method mobility (Sec. 2.7.2) in a periodic box: the forces and
@@ -280,8 +285,9 @@ int fil_read_switch(fil_sim* sim, int32_t* dir);
 /* The suspension above a no-slip plane wall at z = 0: every residual evaluation applies
  * the wall-bounded RPY mobility of fil_rpy_wall_apply in place of the unbounded one (the
  * steric barrier and everything else unchanged; no wall repulsion, so segments must stay
- * above z = a).  Only before the first step, for one suspension in FIL_PREC_F64, and not
- * with fil_set_periodic_fcm.  Graph blocks and the Newton-Krylov steps use it too.
+ * above z = a).  Only before the first step, for one suspension, and not with
+ * fil_set_periodic_fcm.  In FIL_PREC_F32TILE the evaluations before the FP64 finish use
+ * the wall apply's FP32-tile form.  Graph blocks and the Newton-Krylov steps use it too.
  * FIL_EINVAL on a bad call, FIL_ENOMEM if the workspace cannot be allocated. */
 int fil_set_wall(fil_sim* sim);
 

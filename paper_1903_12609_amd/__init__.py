@@ -59,9 +59,10 @@ def rpy_mobility_apply(Y, F, T, a=1.0, eta=1.0, prec="f64", V=None, W=None, work
     return V, W
 
 
-def rpy_wall_apply(Y, F, T, a=1.0, eta=1.0, V=None, W=None, work=None):
+def rpy_wall_apply(Y, F, T, a=1.0, eta=1.0, prec="f64", V=None, W=None, work=None):
     """(V, Omega) = RPY mobility above the no-slip wall z = 0 applied to forces F and
-    torques T at positions Y; float64 CUDA tensors of shape (3, S)."""
+    torques T at positions Y; float64 CUDA tensors of shape (3, S).  prec: "f64" or
+    "f32tile"."""
     import torch
     S = Y.shape[1]
     for n, t in (("Y", Y), ("F", F), ("T", T)):
@@ -71,8 +72,8 @@ def rpy_wall_apply(Y, F, T, a=1.0, eta=1.0, V=None, W=None, work=None):
     nb = int(lib().fil_rpy_wall_workspace_bytes(S))
     if work is None or work.numel() < nb:
         work = torch.empty(max(nb, 1), dtype=torch.uint8, device=Y.device)
-    check(lib().fil_rpy_wall_apply(S, _ptr(Y), _ptr(F), _ptr(T), float(a), float(eta), _ptr(V), _ptr(W), _ptr(work),
-                                   work.numel(), _stream()))
+    check(lib().fil_rpy_wall_apply(S, _ptr(Y), _ptr(F), _ptr(T), float(a), float(eta), PREC[prec], _ptr(V), _ptr(W),
+                                   _ptr(work), work.numel(), _stream()))
     return V, W
 
 

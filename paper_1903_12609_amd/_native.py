@@ -85,7 +85,7 @@ def _declare(L):
         L.fil_read_switch.argtypes = [_vp, _vp]
         L.fil_rpy_wall_workspace_bytes.argtypes = [_i64]
         L.fil_rpy_wall_workspace_bytes.restype = _i64
-        L.fil_rpy_wall_apply.argtypes = [_i64, _vp, _vp, _vp, _d, _d, _vp, _vp, _vp, _i64, _vp]
+        L.fil_rpy_wall_apply.argtypes = [_i64, _vp, _vp, _vp, _d, _d, _i, _vp, _vp, _vp, _i64, _vp]
         L.fil_fcm_create.argtypes = [_vp, _vp, _d, _d, _d, _vp]
         L.fil_fcm_apply.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
         L.fil_fcm_destroy.argtypes = [_vp]

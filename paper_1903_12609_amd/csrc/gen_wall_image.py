@@ -89,6 +89,19 @@ class _Printer(C99CodePrinter):
         return super()._print_Pow(e)
 
 
+class _PrinterF32(_Printer):
+    """As _Printer, with single-precision literals (no promotion to double)."""
+
+    def _print_Rational(self, e):
+        return "(%d.0f/%d.0f)" % (e.p, e.q)
+
+    def _print_Float(self, e):
+        return repr(float(e)) + "f"
+
+    def _print_Pow(self, e):
+        return super()._print_Pow(e).replace("1.0/", "1.0f/").replace('"1.0"', '"1.0f"')
+
+
 def blocks():
     """The four image blocks (times 8 pi eta) as 3 x 3 lists of sympy expressions."""
     G = [[Gim(i, j) for j in range(3)] for i in range(3)]
@@ -182,27 +195,30 @@ def check(B, co, trials=20):
     return worst
 
 
-TEMPLATE = """// Generated by gen_wall_image.py: the image part of the Rotne-Prager-Blake mobility
+HEADER = """// Generated by gen_wall_image.py: the image part of the Rotne-Prager-Blake mobility
 // (Blake's image system under the Faxen operators of both spheres) applied to one source's
 // force and torque.  Variables: R = x - y* (y* the mirror image of the source), ir = 1/|R|,
 // h = source height, a the radius; e = (0, 0, 1) the wall normal and c = R x e.  Each block
 // (times 8 pi eta) is written on a basis of tensors built from R, e and c:
 //   tt, rr = A I + B R R^T + C R e^T + D e R^T + E e e^T
 //   tr, rt = beta [e]x + gamma (c R^T + R c^T) + eps c e^T + zeta e c^T
-// with coefficients that depend on ir, R3, h and a only.  Do not edit.
+// with coefficients that depend on ir, R3, h and a only.  Two forms: double, and float
+// (single-precision literals throughout).  Do not edit.
 #pragma once
 
 namespace fil {
+"""
 
+TEMPLATE = """
 // vi += (tt F + tr T), wi += (rt F + rr T), all times 8 pi eta
-__device__ __host__ inline void wall_image_apply(double R1, double R2, double R3, double ir, double h, double a,
-                                                 const double F[3], const double T[3], double vi[3], double wi[3]) {
+__device__ __host__ inline void %(name)s(%(T)s R1, %(T)s R2, %(T)s R3, %(T)s ir, %(T)s h, %(T)s a,
+                                         const %(T)s F[3], const %(T)s T[3], %(T)s vi[3], %(T)s wi[3]) {
 %(body)s
-    const double c1 = R2, c2 = -R1;
-    const double rF = R1 * F[0] + R2 * F[1] + R3 * F[2], rT = R1 * T[0] + R2 * T[1] + R3 * T[2];
-    const double cF = c1 * F[0] + c2 * F[1], cT = c1 * T[0] + c2 * T[1];
+    const %(T)s c1 = R2, c2 = -R1;
+    const %(T)s rF = R1 * F[0] + R2 * F[1] + R3 * F[2], rT = R1 * T[0] + R2 * T[1] + R3 * T[2];
+    const %(T)s cF = c1 * F[0] + c2 * F[1], cT = c1 * T[0] + c2 * T[1];
     // tt F
-    double k = tt_B * rF + tt_C * F[2];
+    %(T)s k = tt_B * rF + tt_C * F[2];
     vi[0] += tt_A * F[0] + k * R1;
     vi[1] += tt_A * F[1] + k * R2;
     vi[2] += tt_A * F[2] + k * R3 + tt_D * rF + tt_E * F[2];
@@ -222,8 +238,6 @@ __device__ __host__ inline void wall_image_apply(double R1, double R2, double R3
     wi[1] += rr_A * T[1] + k * R2;
     wi[2] += rr_A * T[2] + k * R3 + rr_D * rT + rr_E * T[2];
 }
-
-}  // namespace fil
 """
 
 
@@ -240,12 +254,15 @@ def main():
             outs.append("%s_%s" % (b, n))
             exprs.append(e)
     reps, red = sp.cse(exprs, symbols=sp.numbered_symbols("t"), optimizations="basic")
-    pr = _Printer()
-    lines = ["    const double %s = %s;" % (s_, pr.doprint(e)) for s_, e in reps]
-    lines += ["    const double %s = %s;" % (n, pr.doprint(e)) for n, e in zip(outs, red)]
+    text = HEADER
+    for name, T, pr in (("wall_image_apply", "double", _Printer()), ("wall_image_apply_f32", "float", _PrinterF32())):
+        lines = ["    const %s %s = %s;" % (T, s_, pr.doprint(e)) for s_, e in reps]
+        lines += ["    const %s %s = %s;" % (T, n, pr.doprint(e)) for n, e in zip(outs, red)]
+        text += TEMPLATE % {"name": name, "T": T, "body": "\n".join(lines)}
+    text += "\n}  // namespace fil\n"
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "wall_image.h")
     with open(out, "w") as f:
-        f.write(TEMPLATE % {"body": "\n".join(lines)})
+        f.write(text)
     print("wrote", out, "(%d temporaries)" % len(reps))
 
 

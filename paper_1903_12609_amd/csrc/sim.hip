@@ -265,7 +265,8 @@ int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipE
         if (e1) FIL_HIP_TRY(hipEventRecord(e1, s->st));
     } else if (s->wall) {
         if (e0) FIL_HIP_TRY(hipEventRecord(e0, s->st));
-        TRY(rpy_wall_launch(s->S, s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->wall_work, s->st));
+        TRY(rpy_wall_launch(s->S, s->Yc, s->F, s->T, s->p.a, s->p.eta, c ? FIL_PREC_F32TILE : FIL_PREC_F64, s->V,
+                            s->W, s->wall_work, s->st));
         if (e1) FIL_HIP_TRY(hipEventRecord(e1, s->st));
     } else if (s->batched) {
         TRY(rpy_batch_launch(s->bplan[c], s->rpy_lists[c], s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W,
@@ -985,7 +986,6 @@ int fil_set_wall(fil_sim* s) {
     FIL_CHECK_ARG(!s->wall, "fil_set_wall: the wall is already set");
     FIL_CHECK_ARG(!s->fcm, "fil_set_wall: the suspension is in a periodic box");
     FIL_CHECK_ARG(s->nsusp == 1, "fil_set_wall: one suspension per wall");
-    FIL_CHECK_ARG(s->p.prec == FIL_PREC_F64, "fil_set_wall: needs FIL_PREC_F64");
     const int64_t nb = wall_workspace_bytes(s->S);
     if (nb > 0) {
         double* w = nullptr;

@@ -75,8 +75,8 @@ int switch_torque_launch(const SimDev& d, const SwitchArgs& a, const double* qj,
 
 // RPY mobility above the no-slip wall z = 0 (rpy_wall.hip); work of wall_workspace_bytes(S)
 int64_t wall_workspace_bytes(int64_t S);
-int rpy_wall_launch(int64_t S, const double* Y, const double* F, const double* T, double a, double eta, double* V,
-                    double* W, void* work, hipStream_t st);
+int rpy_wall_launch(int64_t S, const double* Y, const double* F, const double* T, double a, double eta, int prec,
+                    double* V, double* W, void* work, hipStream_t st);
 // adds the steric barrier into F and, when prec is FIL_PREC_F64, writes the mobility source records
 int steric_pack_launch(const SimDev& d, const double* Yc, const double* box, const int32_t* active, double* F,
                        const double* T, int prec, void* pk, hipStream_t st);

@@ -43,6 +43,36 @@ def test_wall_apply_sampled_targets_large():
     assert rel_l2(V[idx], Vo) <= 1e-12 and rel_l2(W[idx], Wo) <= 1e-12, (rel_l2(V[idx], Vo), rel_l2(W[idx], Wo))
 
 
+@pytest.mark.parametrize("S,side", [(7, 6.0), (150, 20.0), (300, 30.0)])
+def test_wall_apply_f32tile_error_bound(S, side):
+    """FP32 tiles (float pair arithmetic on tile-relative coordinates, FP64 sums): the
+    error against the oracle's FP64 apply is reported and bounded by 1e-5 (relative L2)."""
+    import paper_1903_12609_amd as fil
+    print("case wall f32tile", S, side, flush=True)
+    Y, F, T = _cloud(S, 20 + S, side)
+    Vo, Wo = owall.wall_rpy_apply(Y, F, T, 1.0, 1.0)
+    V, W = fil.rpy_wall_apply(dev(Y), dev(F), dev(T), 1.0, 1.0, prec="f32tile")
+    V, W = host(V), host(W)
+    print("f32tile rel L2 V %.3e W %.3e" % (rel_l2(V, Vo), rel_l2(W, Wo)))
+    assert np.isfinite(V).all() and np.isfinite(W).all()
+    assert rel_l2(V, Vo) <= 1e-5 and rel_l2(W, Wo) <= 1e-5
+
+
+def test_wall_apply_f32tile_lattice_sampled():
+    """The active-array layout above the wall (S = 4000: 125 filaments of 32 segments,
+    bases one spacing above it, far-away tiles included) with FP32 tiles, on 40 sampled
+    targets against the oracle's rows."""
+    import paper_1903_12609_amd as fil
+    Y, F, T = synth.active_array_mobility_inputs(nx=25, ny=5, N=32, base_z=synth.DL)
+    S = Y.shape[0]
+    V, W = fil.rpy_wall_apply(dev(Y), dev(F), dev(T), 1.0, 1.0, prec="f32tile")
+    V, W = host(V), host(W)
+    idx = np.random.default_rng(3).choice(S, 40, replace=False)
+    Vo, Wo = owall.wall_rpy_apply(Y, F, T, 1.0, 1.0, targets=idx)
+    print("f32tile sampled rel L2 V %.3e W %.3e" % (rel_l2(V[idx], Vo), rel_l2(W[idx], Wo)))
+    assert rel_l2(V[idx], Vo) <= 1e-5 and rel_l2(W[idx], Wo) <= 1e-5
+
+
 def test_wall_apply_refusals():
     import torch
     import paper_1903_12609_amd as fil
@@ -54,7 +84,10 @@ def test_wall_apply_refusals():
     V, W = torch.empty_like(Y), torch.empty_like(Y)
     assert lib().fil_rpy_wall_workspace_bytes(300) > 0
     with pytest.raises(FilError):  # workspace too small, through the C-ABI
-        check(lib().fil_rpy_wall_apply(300, Y.data_ptr(), F.data_ptr(), T.data_ptr(), 1.0, 1.0, V.data_ptr(),
+        check(lib().fil_rpy_wall_apply(300, Y.data_ptr(), F.data_ptr(), T.data_ptr(), 1.0, 1.0, 0, V.data_ptr(),
+                                       W.data_ptr(), None, 0, None))
+    with pytest.raises(FilError):  # unknown precision
+        check(lib().fil_rpy_wall_apply(300, Y.data_ptr(), F.data_ptr(), T.data_ptr(), 1.0, 1.0, 7, V.data_ptr(),
                                        W.data_ptr(), None, 0, None))
 
 
@@ -71,6 +104,29 @@ def _pair(graph=8):
     g = fil.Sim(w.fil_off, w.Y, w.q, p, graph=graph)
     g.set_wall()
     return w, o, g
+
+
+def test_wall_f32tile_steps_finish_in_fp64():
+    """FP32-tile mode on the wall: evaluations start with the FP32-tile wall apply and every
+    step ends on an FP64 residual within tol, so the clamped array's trajectory stays within
+    the tolerance of the FP64 oracle's."""
+    import paper_1903_12609_amd as fil
+    w = _array()
+    p = dict(w.params)
+    o = oracle.Sim(w.fil_off, w.Y, w.q, mobility=lambda Y, F, T: owall.wall_rpy_apply(Y, F, T, p["a"], p["eta"]),
+                   **p)
+    g = fil.Sim(w.fil_off, w.Y, w.q, p, prec="f32tile", graph=8)
+    g.set_wall()
+    for j in range(6):
+        r = g.step()[0]
+        rc, rep = o.step()
+        assert rc == 0 and r["converged"] and r["resid"] <= p["tol"]
+        assert 1 <= r["applies_f64"] < r["applies"], r
+    Yg, _, _ = g.read_state()
+    g.close()
+    err = rel_l2(Yg, o.Y)
+    print("wall f32tile trajectory vs FP64 oracle after 6 steps: rel L2 %.3e" % err)
+    assert err <= 1e-6
 
 
 def test_wall_residual_parity():
@@ -109,9 +165,6 @@ def test_set_wall_refusals():
     g.set_wall()
     with pytest.raises(FilError):
         g.set_wall()
-    g2 = fil.Sim(w.fil_off, w.Y, w.q, w.params, prec="f32tile")
-    with pytest.raises(FilError):
-        g2.set_wall()
     g3 = fil.Sim(w.fil_off, w.Y, w.q, w.params)
     g3.step()
     with pytest.raises(FilError):
