@@ -300,9 +300,9 @@ int fil_set_wall(fil_sim* sim);
  * Broyden history restarting there (Alg. 2 from the current iterate, same J0), and
  * only an FP64 residual ends a step (the FP32 floor can exceed tol).
  * report: HOST fil_step_report[nsusp] (may be NULL).  Host-driven iterations
- * (graph execution off, and FP32-tile iterations) synchronise the stream once
- * per iteration to test convergence; see fil_set_graph for the device-driven
- * form.  On success the commit of the new state may still be running when the
+ * (graph execution off) synchronise the stream once per iteration to test
+ * convergence; see fil_set_graph for the device-driven form, in which the switch
+ * to FP64 applies is decided on the device as well.  On success the commit of the new state may still be running when the
  * call returns: work on the simulation's stream is ordered after it, other
  * streams synchronise first (fil_read_state does).  Returns FIL_ENOCONV or
  * FIL_ENONFINITE if a suspension failed; its state is then left at step j. */
@@ -406,11 +406,14 @@ int fil_set_stream(fil_sim* sim, void* stream);
  * replayed on the simulation's stream.  Every test, the first included, then
  * runs on the device; the host reads a block's log while the next block runs,
  * so a block launched after the end only runs kernels that find their
- * suspension finished.  Results are identical to U = 0 (the default, one host
- * test per iteration).  Graphs are cached per (first iteration, U, precision,
- * iteration of the last history restart) and freed by fil_destroy.  U in [0, 64].  fil_set_timing then times only the
- * host-driven evaluations (the first of each step); captured blocks carry no
- * timing events. */
+ * suspension finished.  In FIL_PREC_F32TILE mode the FP32-tile iterations run in
+ * blocks too: a one-workgroup kernel before each decides the switch to FP64 from
+ * the previous test and stops the suspensions there; FP64 blocks continue from
+ * that iteration.  Results are identical to U = 0 (the default, one host test
+ * per iteration).  Graphs are cached per (first iteration, U, precision,
+ * iteration of the last history restart) and freed by fil_destroy.  U in [0, 64].
+ * fil_set_timing then times only the host-driven evaluations (the first of each
+ * step); captured blocks carry no timing events. */
 int fil_set_graph(fil_sim* sim, int iters_per_launch);
 
 /* ------------------------------------------------------------------------ */

@@ -65,6 +65,8 @@ struct fil_sim {
     };
     int graph_iters = 0;  // iterations per captured block; 0 runs every iteration from the host
     int pred_iters = 0;   // iterations the last device-driven solve took (0: none yet)
+    int pred_iters32 = 0;  // the same for the FP32-tile iterations of FP32-tile mode
+    int* notnear_d = nullptr;  // FP32-tile iterations: running suspensions not near the switch
     int koff = 0;         // iteration at which the Broyden history last restarted (update k = it - 1 - koff)
     hipStream_t cap_st = nullptr;  // private stream the blocks are captured on (launches go to st)
     double* fext_d = nullptr;      // [3][S] external forces per segment (null until set)
@@ -203,7 +205,7 @@ void drop_graphs(fil_sim* s) {
     for (auto& kv : s->graphs)
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
     s->graphs.clear();
-    s->pred_iters = 0;
+    s->pred_iters = s->pred_iters32 = 0;
 }
 
 void free_sim(fil_sim* s) {
@@ -293,6 +295,23 @@ UpdateArgs update_args(fil_sim* s, int k, const double* fnew, double* dXout) {
                       s->X,  dXout,    s->qj,   s->time_d, s->Yc,   s->qc,   s->F,     s->T,     s->box, s->gsolve};
 }
 
+// the device-side test of iteration it (jflag: singular-J0 flags, first iteration only);
+// FP32-tile evaluations cannot end a step and count the suspensions not yet near the switch
+JudgeArgs judge_args(fil_sim* s, int it, const int32_t* jflag) {
+    const bool f32 = s->cur == 1;
+    return JudgeArgs{s->log_d,
+                     s->resbits_d + 2 * s->rb * s->nsusp,
+                     jflag,
+                     s->p.tol,
+                     1.0 / s->p.a,
+                     it,
+                     s->p.kmax,
+                     f32 ? 0 : 1,
+                     f32 ? s->notnear_d : nullptr,
+                     kSwitchTol * s->p.tol,
+                     kNoiseMargin * kF32Floor};
+}
+
 // max|f|/a and max|b dt (V, dexpinv Omega)| per suspension of the last evaluation
 int read_resid(fil_sim* s, std::vector<double>& res, std::vector<double>* vmax = nullptr) {
     const int64_t ns = s->nsusp;
@@ -349,9 +368,10 @@ int capture_block(fil_sim* s, int it0, int U, GraphEntry& g) {
     int rc = FIL_OK;
     for (int i = 0; i < U && rc == FIL_OK; i++) {
         const int it = it0 + i;
-        rc = eval_residual(s, s->X, s->f, nullptr, nullptr, false, it - 1 - s->koff);
-        const JudgeArgs jg{s->log_d, s->resbits_d + 2 * s->rb * ns, nullptr, s->p.tol, 1.0 / s->p.a, it, s->p.kmax,
-                           s->cur == 0 ? 1 : 0};
+        // FP32-tile iterations: the switch to FP64 is decided on the device before each
+        if (s->cur == 1) rc = f32_switch_launch(s->active_d, s->log_d, s->notnear_d, ns, it, s->p.kmax, s->st);
+        if (rc == FIL_OK) rc = eval_residual(s, s->X, s->f, nullptr, nullptr, false, it - 1 - s->koff);
+        const JudgeArgs jg = judge_args(s, it, nullptr);
         if (rc == FIL_OK)
             rc = broyden_state_launch(s->d, update_args(s, it - 1 - s->koff, s->f, nullptr), jg, s->active_d, s->st);
     }
@@ -405,9 +425,9 @@ struct SolveLog {
 // the end runs only kernels that find their suspension finished.  Blocks are full
 // up to the iteration count of the previous solve and single iterations beyond it,
 // which bounds that waste.
-int device_iterations(fil_sim* s, SolveLog& L, int it) {
+int device_iterations(fil_sim* s, SolveLog& L, int it, int& pred_out) {
     const int64_t ns = s->nsusp;
-    const int pred = s->pred_iters;
+    const int pred = pred_out;
     int pending = 0;
     int rslot = (int)(s->exports_h & 1);
     for (;;) {
@@ -439,18 +459,19 @@ int device_iterations(fil_sim* s, SolveLog& L, int it) {
         pending--;
         if (!any) break;
     }
-    s->pred_iters = *std::max_element(L.iters.begin(), L.iters.end());
+    pred_out = *std::max_element(L.iters.begin(), L.iters.end());
     return FIL_OK;
 }
 
 // Alg. 2 from the iterate in s->X for every active suspension: f_0 = f(X_0), J0
 // at X_0 and its inverse, X_1 = X_0 - J0^{-1} f_0, then one evaluation and one
 // bad-Broyden update per iteration until every suspension has converged or failed.
-// FP64 iterations run in captured graph blocks when enabled, with every test on the
-// device (the first one included) and no host round trip between blocks.  In
-// FP32-tile mode the evaluations start in FP32, host-driven, and switch to FP64 once
-// every running suspension is near the tolerance or near the FP32 rounding floor;
-// only an FP64 residual can end a step.
+// The iterations run in captured graph blocks when enabled, with every test on the
+// device (the first one included) and no host round trip between blocks, or one by one
+// from the host.  In FP32-tile mode the evaluations start in FP32 and switch to FP64 once
+// every running suspension is near the tolerance or near the FP32 rounding floor (in
+// graph blocks the switch is decided on the device before each iteration and the FP64
+// blocks take over from the host at the switch); only an FP64 residual can end a step.
 int solve(fil_sim* s, SolveLog& L) {
     const int64_t ns = s->nsusp;
     s->cur = s->p.prec == FIL_PREC_F32TILE ? 1 : 0;
@@ -499,13 +520,37 @@ int solve(fil_sim* s, SolveLog& L) {
     TRY(eval_residual(s, s->X, s->f, e0, e1, true, -1));
     TRY(begin_solve(s));
     const bool graphs = s->graph_iters > 0 && !s->fcm;
-    if (graphs && s->cur == 0) {
+    if (graphs) {
         // the first test runs in the first-step kernel (the log was cleared at the start
         // of the step), which also fails a suspension with a singular J0 block
-        const JudgeArgs jg{s->log_d, s->resbits_d + 2 * s->rb * ns, s->jflag_d, s->p.tol, 1.0 / s->p.a, 0,
-                           s->p.kmax, 1};
-        TRY(broyden_state_launch(s->d, update_args(s, -1, s->f, nullptr), jg, s->active_d, s->st));
-        TRY(device_iterations(s, L, 1));
+        if (s->cur == 1) TRY(f32_switch_launch(s->active_d, s->log_d, s->notnear_d, ns, -1, s->p.kmax, s->st));
+        TRY(broyden_state_launch(s->d, update_args(s, -1, s->f, nullptr), judge_args(s, 0, s->jflag_d), s->active_d,
+                                 s->st));
+        if (s->cur == 1) {
+            // FP32-tile iterations until the device switches; the switched suspensions then
+            // continue with FP64 evaluations from the next iteration, the Broyden history
+            // restarting there (as in the host-driven loop below)
+            TRY(device_iterations(s, L, 1, s->pred_iters32));
+            int its = -1;
+            for (int64_t i = 0; i < ns; i++)
+                if (L.state[i] == 2) {
+                    its = L.iters[i] + 1;
+                    L.state[i] = 0;
+                }
+            if (its > 0) {
+                for (int64_t i = 0; i < ns; i++) {
+                    s->active_h[i] = L.state[i] == 0;
+                    s->log_h[i] = SuspLog{L.state[i], L.iters[i], L.applies[i], L.applies_hi[i], L.last[i]};
+                }
+                FIL_HIP_TRY(hipMemcpyAsync(s->log_d, s->log_h, ns * sizeof(SuspLog), hipMemcpyHostToDevice, s->st));
+                TRY(upload_flags(s, s->active_d, s->active_h));
+                s->cur = 0;
+                s->koff = its;
+                TRY(device_iterations(s, L, its, s->pred_iters));
+            }
+        } else {
+            TRY(device_iterations(s, L, 1, s->pred_iters));
+        }
         for (int64_t i = 0; i < ns; i++)
             if (L.state[i] == -2) {
                 set_error("fil_bdf2_step: an approximate Jacobian block of suspension " + std::to_string(i) +
@@ -530,15 +575,6 @@ int solve(fil_sim* s, SolveLog& L) {
     if (any) TRY(broyden_state_launch(s->d, update_args(s, -1, s->f, nullptr), JudgeArgs{}, s->active_d, s->st));
     bool restart = false;  // the evaluation of this iteration is the first FP64 one after FP32 tiles
     for (int it = 1; any;) {
-        if (graphs && s->cur == 0) {
-            // FP32 iterations are done: the device continues from the host's counts, with
-            // the Broyden history restarting at this iteration
-            for (int64_t i = 0; i < ns; i++)
-                s->log_h[i] = SuspLog{L.state[i], L.iters[i], L.applies[i], L.applies_hi[i], L.last[i]};
-            FIL_HIP_TRY(hipMemcpyAsync(s->log_d, s->log_h, ns * sizeof(SuspLog), hipMemcpyHostToDevice, s->st));
-            s->koff = it;
-            return device_iterations(s, L, it);
-        }
         count();
         TRY(pool_events(s, &e0, &e1));
         TRY(eval_residual(s, s->X, s->f, e0, e1, false, restart ? -1 : s->k));
@@ -696,7 +732,7 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     if (!dense && M >= kLaneSolveMinFil) { A(s->gsolve, n6) }
     A(s->Chist, (size_t)p->kmax * n6) A(s->Dhist, (size_t)p->kmax * n6) A(s->part, (size_t)M * max_dots)
     A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->time_d, 1) A(s->log_d, nsusp) A(s->exports_d, 1)
-    A(s->active_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 4 * nsusp)
+    A(s->active_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 4 * nsusp) A(s->notnear_d, 1)
 #undef A
     if (rc == FIL_OK) rc = halloc(s, &s->active_h, nsusp);
     if (rc == FIL_OK) rc = halloc(s, &s->jflag_h, M);
@@ -1319,7 +1355,7 @@ int fil_restore(fil_sim* s, const char* path) {
     }
     s->t = t;
     s->step = hdr[3];
-    s->pred_iters = 0;
+    s->pred_iters = s->pred_iters32 = 0;
     return FIL_OK;
 }
 
@@ -1327,7 +1363,7 @@ int fil_restore(fil_sim* s, const char* path) {
 
 // ---------------------------------------------------------------- Newton-Krylov and JFB steps
 // Two steps whose linear systems are solved by restarted GMRES with Jacobian-free
-// products (Sec. 3.1, 3.2.1, 4.1, 4.2):
+// products (Sec. 3.1, 3.2.1; compared in Sec. 3.3.1, 3.3.2):
 //  * Newton-Krylov: X <- X + dX with J(X) dX = -f(X), J v = (f(X + delta v) - f(X)) / delta
 //    (one mobility apply per Krylov iteration);
 //  * JFB-g, good Broyden (Alg. 1) with J0 = grad f0 taken the same way from f0, the

@@ -101,7 +101,8 @@ int update_dots_launch(const SimDev& d, const double* fnew, const int32_t* activ
                        hipStream_t st);
 // Per-suspension record of a solve run by the device
 struct SuspLog {
-    int32_t state;     // 0 running, 1 converged, -1 failed, -2 failed on a singular J0 block
+    int32_t state;     // 0 running, 1 converged, -1 failed, -2 failed on a singular J0 block,
+                       // 2 done with FP32-tile evaluations (to continue in FP64)
     int32_t it;        // last iteration tested
     int32_t evals;     // residual evaluations (mobility applies)
     int32_t evals_hi;  // of which in FP64
@@ -115,7 +116,16 @@ struct JudgeArgs {
     const int32_t* jflag;  // [M] singular-J0 flags (first step only; null: not checked): fail the suspension
     double tol, inv_a;
     int it, kmax, can_converge;
+    // FP32-tile evaluations (notnear non-null): a running suspension whose max|f|/a exceeds
+    // max(near_tol, near_coef max|b dt (V, dexpinv Omega)|/a) adds one to *notnear
+    int* notnear;
+    double near_tol, near_coef;
 };
+// Before FP32-tile iteration `it` of captured blocks: when no running suspension counted
+// itself not near after iteration it - 1 (or 2 (it - 1) >= kmax), every running suspension
+// stops (active 0, log state 2) to continue with FP64 evaluations; *notnear is cleared.
+// it < 0: only the clearing.
+int f32_switch_launch(int32_t* active, SuspLog* log, int* notnear, int64_t nsusp, int it, int kmax, hipStream_t st);
 // Broyden update k (k < 0: first step X <- X - J0^{-1} f) and the state at the new X
 struct UpdateArgs {
     int k;

@@ -1673,6 +1673,10 @@ __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs 
             L.last = r;
             if (state && L.state == 0) L.state = state;
             if (state) active[isus] = 0;
+            if (!state && jg.notnear) {
+                const double vm = __longlong_as_double((long long)jg.resbits[d.nsusp + isus]) * jg.inv_a;
+                if (!(r <= fmax(jg.near_tol, jg.near_coef * vm))) atomicAdd(jg.notnear, 1);
+            }
         }
         if (state) return;
     }
@@ -1837,6 +1841,25 @@ __global__ void __launch_bounds__(64) band_solve_kernel(SimDev d, const double* 
     band_sweeps(AB + e0 * kBandW, ip, rd, y, n, lane);
     __syncthreads();
     for (int i = lane; i < n; i += 64) g[e0 + slot_of(i / 3, N) + i % 3] = y[i];
+}
+
+__global__ void __launch_bounds__(256) f32_switch_kernel(int32_t* __restrict__ active, SuspLog* __restrict__ log,
+                                                       int* __restrict__ notnear, int64_t ns, int it, int kmax) {
+    const int cnt = *notnear;
+    __syncthreads();  // every thread has read the count before it is cleared
+    if (threadIdx.x == 0) *notnear = 0;
+    if (it < 0 || !(cnt == 0 || 2 * (it - 1) >= kmax)) return;
+    for (int64_t i = threadIdx.x; i < ns; i += blockDim.x)
+        if (active[i]) {
+            active[i] = 0;
+            log[i].state = 2;
+        }
+}
+
+int f32_switch_launch(int32_t* active, SuspLog* log, int* notnear, int64_t nsusp, int it, int kmax, hipStream_t st) {
+    f32_switch_kernel<<<1, 256, 0, st>>>(active, log, notnear, nsusp, it, kmax);
+    FIL_HIP_TRY(hipGetLastError());
+    return FIL_OK;
 }
 
 int broyden_state_launch(const SimDev& d, const UpdateArgs& u, const JudgeArgs& jg, int32_t* active, hipStream_t st) {
