@@ -293,28 +293,44 @@ def solver_comparison(w, steps=5, warmup=2, names=("ejb_b", "jfnk_j0", "jfnk_non
     import paper_1903_12609_amd as fil
     out = {}
     for name in names:
-        sim = fil.Sim(w.fil_off, w.Y, w.q, dict(w.params, tol=1e-4), graph=GRAPH_ITERS)
+        # the Krylov methods get at most 30 outer iterations of at most 400 GMRES iterations
+        # each per step, so that a stagnating step ends in bounded time
+        kmax = w.params["kmax"] if name == "ejb_b" else min(w.params["kmax"], 30)
+        sim = fil.Sim(w.fil_off, w.Y, w.q, dict(w.params, tol=1e-4, kmax=kmax), graph=GRAPH_ITERS)
         if periodic is not None:
             sim.set_periodic_fcm(*periodic)
         if name == "ejb_b":
             run = lambda: sim.step()[0]
         elif name.startswith("jfnk"):
-            run = lambda: sim.jfnk_step(precond=name[5:], krylov_tol=1e-4, fd_delta=1e-7)
+            run = lambda: sim.jfnk_step(precond=name[5:], krylov_tol=1e-4, fd_delta=1e-7, krylov_max=400,
+                                        raise_on_fail=False)
         else:
-            run = lambda: sim.jfb_step(precond=name[6:], krylov_tol=1e-4, fd_delta=1e-7)
+            run = lambda: sim.jfb_step(precond=name[6:], krylov_tol=1e-4, fd_delta=1e-7, krylov_max=400,
+                                       raise_on_fail=False)
+        failed = 0
         for _ in range(warmup):
-            run()
+            failed += isinstance(run(), tuple)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         applies = krylov = 0
-        for _ in range(steps):
+        for j in range(steps):
+            t1 = time.perf_counter()
             r = run()
+            if isinstance(r, tuple):  # (error code, report): the step did not converge
+                failed += 1
+                r = r[1]
             applies += r["applies"]
             krylov += r.get("krylov", 0)
+            if periodic is not None:
+                torch.cuda.synchronize()
+                log("solver %s step %d: %.1f ms, %d applies" % (name, j, (time.perf_counter() - t1) * 1e3,
+                                                               r["applies"]))
         torch.cuda.synchronize()
         out[name] = {"ms_per_step": (time.perf_counter() - t0) / steps * 1e3, "mobility_applies_per_step": applies / steps}
         if name != "ejb_b":
             out[name]["krylov_iters_per_step"] = krylov / steps
+        if failed:
+            out[name]["steps_not_converged"] = failed
         sim.close()
         log("solver", name, out[name])
     for name in names:

@@ -29,6 +29,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -319,7 +320,7 @@ __device__ __forceinline__ void rpy_item_f64(int64_t base, int64_t S, int64_t Sg
 // k = bid % K); chunks adjacent in k land on different XCDs, so each XCD's L2
 // holds ~K/8 of the sources.
 template <int TPL, int WS>
-__global__ void __launch_bounds__(kRpyBlock) rpy_f64_kernel(int64_t S, int64_t chunk, int K,
+__global__ void __launch_bounds__(kRpyBlock) __attribute__((amdgpu_waves_per_eu(3))) rpy_f64_kernel(int64_t S, int64_t chunk, int K,
                                                           const double* __restrict__ pk,
                                                           const double* __restrict__ Y, double a, double c,
                                                           RpyOut out) {
@@ -332,7 +333,7 @@ __global__ void __launch_bounds__(kRpyBlock) rpy_f64_kernel(int64_t S, int64_t c
 // Many suspensions in one persistent launch: a fixed grid walks a work list
 // sorted by cost (largest first), item i handled by block i mod gridDim.
 template <int TPL>
-__global__ void __launch_bounds__(kRpyBlock) rpy_f64_items_kernel(const RpyItem* __restrict__ items, int64_t nitems,
+__global__ void __launch_bounds__(kRpyBlock) __attribute__((amdgpu_waves_per_eu(3))) rpy_f64_items_kernel(const RpyItem* __restrict__ items, int64_t nitems,
                                                                 int64_t Sg, const double* __restrict__ pk,
                                                                 const double* __restrict__ Y, double a, double c,
                                                                 RpyOut out) {
@@ -408,7 +409,7 @@ __device__ __forceinline__ double uniform_f64(double x) {
 
 // One work item of the FP32-tile path: as rpy_item_f64, but the lanes of a wave own
 // 64 x TPL consecutive targets (lane + 64 j), so that the wave's targets are close together
-// and most tiles are far from all of them.
+// and most tiles are far enough from all of them to skip the overlap test.
 template <int TPL, int WS>
 __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg, int64_t tb, int k, int K,
                                              int64_t chunk, const SrcF32* __restrict__ pk,
@@ -461,44 +462,36 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
         const int cnt = (int)(t1 - t0);
         const TileF32 tr = tiles[tile];
         const double dx = cw[0] - tr.o[0], dy = cw[1] - tr.o[1], dz = cw[2] - tr.o[2];
-        const double reach = rw + 3.0 * tr.rad + 2.0 * a;  // |C_w - O| >= reach: every pair >= 2a + 2 rad apart
+        // |C_w - O| >= reach: every pair of this tile is at least 2a apart (no overlap test)
+        const double reach = rw + tr.rad + 2.0 * a;
         const int far = __builtin_amdgcn_readfirstlane((int)(fma(dx, dx, fma(dy, dy, dz * dz)) >= reach * reach));
         float v[TPL][3], w[TPL][3];
 #pragma unroll
         for (int j = 0; j < TPL; j++)
             for (int i = 0; i < 3; i++) v[j][i] = w[j][i] = 0.f;
+        // r in float from the target's offset to the tile origin (rounded once per tile) and the
+        // source's stored offset: its error is a few float ulps of |r| + 2 rad
+        float yt[TPL][3];
+#pragma unroll
+        for (int j = 0; j < TPL; j++)
+            for (int i = 0; i < 3; i++) yt[j][i] = (float)(y[j][i] - tr.o[i]);
         // the next record is requested before the current one is used (latency overlap);
         // 32-bit, wave-uniform loop arithmetic stays on the scalar unit
         const SrcF32* ts = pk + g;
         SrcRegF32 cur = load_src_f32(ts);
-        if (far) {
-            float yt[TPL][3];
-#pragma unroll
-            for (int j = 0; j < TPL; j++)
-                for (int i = 0; i < 3; i++) yt[j][i] = (float)(y[j][i] - tr.o[i]);
-            auto pairs = [&](const SrcRegF32& sr) {
-#pragma unroll
-                for (int j = 0; j < TPL; j++)
-                    rpy_pair_f32<false>(yt[j][0] - sr.sp[0], yt[j][1] - sr.sp[1], yt[j][2] - sr.sp[2], sr, af,
-                                        four_a2, two_a2, c23, v[j], w[j]);
-            };
+        auto sweep = [&](auto near) {
             for (int i = 0; i < cnt; ++i) {
                 const SrcRegF32 nxt = load_src_f32(ts + (i + 1 < cnt ? i + 1 : i));
-                pairs(cur);
-                cur = nxt;
-            }
-        } else {
-            for (int i = 0; i < cnt; ++i) {
-                const SrcRegF32 nxt = load_src_f32(ts + (i + 1 < cnt ? i + 1 : i));
-                const int64_t gm = g + i;
-                const double s0 = Y[gm], s1 = Y[Sg + gm], s2 = Y[2 * Sg + gm];
 #pragma unroll
                 for (int j = 0; j < TPL; j++)
-                    rpy_pair_f32<true>((float)(y[j][0] - s0), (float)(y[j][1] - s1), (float)(y[j][2] - s2), cur, af,
-                                       four_a2, two_a2, c23, v[j], w[j]);
+                    rpy_pair_f32<decltype(near)::value>(yt[j][0] - cur.sp[0], yt[j][1] - cur.sp[1],
+                                                        yt[j][2] - cur.sp[2], cur, af, four_a2, two_a2, c23, v[j],
+                                                        w[j]);
                 cur = nxt;
             }
-        }
+        };
+        if (far) sweep(std::false_type{});
+        else sweep(std::true_type{});
 #pragma unroll
         for (int j = 0; j < TPL; j++)
             for (int i = 0; i < 3; i++) {
@@ -541,7 +534,7 @@ __global__ void __launch_bounds__(kRpyBlock) rpy_f32_kernel(int64_t S, int64_t c
 }
 
 template <int TPL>
-__global__ void __launch_bounds__(kRpyBlock) rpy_f32_items_kernel(const RpyItem* __restrict__ items, int64_t nitems,
+__global__ void __launch_bounds__(kRpyBlock) __attribute__((amdgpu_waves_per_eu(5))) rpy_f32_items_kernel(const RpyItem* __restrict__ items, int64_t nitems,
                                                                 int64_t Sg, const SrcF32* __restrict__ pk,
                                                                 const TileF32* __restrict__ tiles,
                                                                 const double* __restrict__ Y, double a, double c,
