@@ -41,6 +41,7 @@ struct fil_sim {
     double *Yc = nullptr, *qc = nullptr, *F = nullptr, *T = nullptr, *V = nullptr, *W = nullptr;
     double *AB = nullptr, *AinvT = nullptr, *Chist = nullptr, *Dhist = nullptr, *part = nullptr;
     double* gsolve = nullptr;  // J0^{-1} f formed before the update (band path, many filaments)
+    double* BC = nullptr;      // the band factor's column records for that solve
     double* rdiag = nullptr;  // reciprocal pivots of the band factor [6S]
     double* box = nullptr;
     double* spar = nullptr;  // [nsusp][kSpar]
@@ -292,7 +293,7 @@ int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipE
 // Broyden update k (k < 0: the first step) from the residual fnew, then the state at the new X
 UpdateArgs update_args(fil_sim* s, int k, const double* fnew, double* dXout) {
     return UpdateArgs{k,     s->AB,    s->ipiv, s->rdiag, s->AinvT, s->part, s->Chist, s->Dhist, fnew, s->fprev,
-                      s->X,  dXout,    s->qj,   s->time_d, s->Yc,   s->qc,   s->F,     s->T,     s->box, s->gsolve};
+                      s->X,  dXout,    s->qj,   s->time_d, s->Yc,   s->qc,   s->F,     s->T,     s->box, s->gsolve, s->BC};
 }
 
 // the device-side test of iteration it (jflag: singular-J0 flags, first iteration only);
@@ -342,7 +343,7 @@ int upload_flags(fil_sim* s, int32_t* dst, const int32_t* src) {
 int begin_solve(fil_sim* s) {
     const double tt = s->t + s->p.dt;
     TRY(j0_factor_launch(s->d, s->bc, s->X, s->qc, s->T, tt, s->active_d, s->AB, s->ipiv, s->rdiag, s->jflag_d,
-                         s->AinvT, s->st));
+                         s->AinvT, s->BC, s->st));
     s->k = 0;
     return FIL_OK;
 }
@@ -729,11 +730,20 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
     A(s->Yc, 3 * S) A(s->qc, 4 * S) A(s->F, 3 * S) A(s->T, 3 * S) A(s->V, 3 * S) A(s->W, 3 * S)
     A(s->AB, n6 * kBandW) A(s->ipiv, n6) A(s->rdiag, n6)
     if (dense) { A(s->AinvT, dense_tot) A(d_dense_off, M) }
-    if (!dense && M >= kLaneSolveMinFil) { A(s->gsolve, n6) }
+    if (!dense && M >= kLaneSolveMinFil) { A(s->gsolve, n6) A(s->BC, (n6 + 2 * kBcPad) * kBcW) }
     A(s->Chist, (size_t)p->kmax * n6) A(s->Dhist, (size_t)p->kmax * n6) A(s->part, (size_t)M * max_dots)
     A(s->box, 6 * M) A(s->spar, kSpar * nsusp) A(s->time_d, 1) A(s->log_d, nsusp) A(s->exports_d, 1)
     A(s->active_d, nsusp) A(s->jflag_d, M) A(s->resbits_d, 4 * nsusp) A(s->notnear_d, 1)
 #undef A
+    // the column records' zero pads (a sweep of a shorter filament beside a longer one reads
+    // past its own records); the records themselves are rewritten at every factorisation
+    if (rc == FIL_OK && s->BC) {
+        if (hipMemset(s->BC, 0, (n6 + 2 * kBcPad) * kBcW * sizeof(double)) != hipSuccess) {
+            set_error("fil_create: clearing the band records failed");
+            rc = FIL_EHIP;
+        }
+        s->BC += kBcPad * kBcW;
+    }
     if (rc == FIL_OK) rc = halloc(s, &s->active_h, nsusp);
     if (rc == FIL_OK) rc = halloc(s, &s->jflag_h, M);
     if (rc == FIL_OK) rc = halloc(s, &s->resbits_h, 2 * nsusp);
@@ -1565,7 +1575,7 @@ int kry_begin(fil_sim* s, const char* who, int precond, double krylov_tol, doubl
     TRY(state_forces_launch(s->d, s->X, s->qj, s->time_d, s->active_d, s->Yc, s->qc, s->F, s->T, s->box, s->st));
     if (precond == 2) {
         TRY(j0_factor_launch(s->d, s->bc, s->X, s->qc, s->T, s->t + s->p.dt, s->active_d, s->AB, s->ipiv, s->rdiag,
-                             s->jflag_d, s->AinvT, s->st));
+                             s->jflag_d, s->AinvT, nullptr, s->st));
         FIL_HIP_TRY(hipMemcpyAsync(s->jflag_h, s->jflag_d, s->M * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
     }
     TRY(eval_residual(s, s->X, s->kry_f0, nullptr, nullptr, false, -1));

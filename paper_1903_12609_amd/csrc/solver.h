@@ -8,6 +8,12 @@ constexpr int kMaxSeg = 64;       // segments per filament (one lane per segment
 constexpr int kKL = 8;            // sub-diagonals of the row-differenced J0 in interleaved order
 constexpr int kKU = 8;            // super-diagonals (kKL + kKU after pivoting fill-in)
 constexpr int kBandW = 2 * kKL + kKU + 1;
+// column records of the band factor (many-filament path), 32 doubles per column: two
+// halves of 16 slots, the multipliers below the diagonal and the entries of U above it,
+// each rotated by the column index (see band_columns_kernel); kBcPad records of zeros
+// before and after the 6S records
+constexpr int kBcW = 32;
+constexpr int64_t kBcPad = 512;
 // explicit J0^{-1} used up to this total size: streaming it in each update beats the
 // banded sweeps (latency-bound, 6N sequential steps) up to a few hundred MB
 constexpr size_t kDenseInvBytes = size_t(256) << 20;
@@ -143,9 +149,11 @@ struct UpdateArgs {
     const double* qj;      // state at the new X, as state_forces_launch
     const double* tt;
     double *Yc, *qc, *F, *T, *box;
-    // band path with many filaments: J0^{-1} fnew is formed first by a kernel of one wave
-    // per filament into gsolve [6S] (X layout); null: the update kernel's own sweeps
+    // band path with many filaments: J0^{-1} fnew is formed first by a kernel of four
+    // filaments per wave into gsolve [6S] (X layout) from the column records BC
+    // [6S x kBcW]; null: the update kernel's own sweeps
     double* gsolve;
+    const double* BC;
 };
 int broyden_state_launch(const SimDev& d, const UpdateArgs& u, const JudgeArgs& jg, int32_t* active, hipStream_t st);
 // Start of a step: the first iterate X0 (and its copy X0c) for every suspension, the base
@@ -159,10 +167,11 @@ int log_export_launch(const SuspLog* log, int64_t ns, SuspLog* slot0, SuspLog* s
                       hipStream_t st);
 // J0 at X in row-differenced banded form (6N x kBandW per filament at 6*seg_off[f]*kBandW),
 // factorised with partial pivoting (ipiv at 6*seg_off[f]); flag[f] = 1 for a zero pivot
-// When AinvT is non-null the explicit inverse is also built (transposed, at dense_off[f]).
+// When AinvT is non-null the explicit inverse is also built (transposed, at dense_off[f]);
+// when BC is non-null the column records of the factor are written there (6S x kBcW).
 int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* qc, const double* Tint,
                      double tt, const int32_t* active, double* AB, int32_t* ipiv, double* rdiag, int32_t* flag,
-                     double* AinvT, hipStream_t st);
+                     double* AinvT, double* BC, hipStream_t st);
 // commits the step of the suspensions flagged in commit (null: all): Y, q from the
 // converged state; X history shifted (Xjm2 may be null)
 int finalize_launch(const SimDev& d, const int32_t* commit, const double* Yc, const double* qc, const double* X,

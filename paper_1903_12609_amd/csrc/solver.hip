@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "solver.h"
 
@@ -65,12 +66,22 @@ enum : int {
     kDppHalfMirror = 0x141,
     kDppRowMirror = 0x140,
     kDppRowShr = 0x110,  // + shift (1..15)
+    kDppRowBcast = 0x150,  // + lane (0..15): every lane of a row receives that lane of its row
 };
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
+}
+// one 64-bit DPP move (the row broadcast is the one control 64-bit DPP takes)
+template <int CTRL>
+__device__ __forceinline__ double dpp64_f64(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, true);
 }
 template <int CTRL>
 __device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
@@ -1527,9 +1538,44 @@ int allow_lds(Kernel kernel, size_t bytes) {
     return FIL_OK;
 }
 
+// Column records of the band factor for the grouped sweeps (kBcW doubles per column).
+// The first half of record i holds the lane of the pivot row ip[i] in a row of 16 lanes (4 x
+// (ip[i] mod 16) in the low word, at position i mod 16) and the multipliers of column i, L(i + off, i) for off = 1 .. kKL, at position
+// (i + off) mod 16 (zeros elsewhere); the second half holds the entries of U in column i
+// divided by the pivot, U(i - 1 - k, i) / U(i, i) for k = 0 .. 15, at position (i - 1 - k)
+// mod 16; zero outside the filament.  With these rotations the lane of a sweep that holds
+// row r of the 16-row window (lane r mod 16) reads the same position of every record, so
+// one address per lane serves every step with an immediate offset.
+__global__ void __launch_bounds__(256) band_columns_kernel(SimDev d, const int32_t* __restrict__ active,
+                                                          const double* __restrict__ AB,
+                                                          const int32_t* __restrict__ ipiv,
+                                                          const double* __restrict__ rdiag, double* __restrict__ BC) {
+    static_assert(kKL + kKU == 16 && kKL < 16 && kBcW == 32, "two 16-slot halves");
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= 6 * d.S * kBcW) return;
+    const int64_t e = t / kBcW;
+    const int k = (int)(t - e * kBcW);
+    const int64_t f = d.seg_fil[e / 6];
+    if (!active[d.fil_susp[f]]) return;
+    const int64_t e0 = 6 * d.seg_off[f];
+    const int n = 6 * (int)(d.seg_off[f + 1] - d.seg_off[f]);
+    const int i = (int)(e - e0);
+    const double* ab = AB + e0 * kBandW;
+    double v = 0.0;
+    if (k < 16) {
+        const int off = (k - i) & 15;  // L(i + off, i) at column offset -off of row i + off
+        if (off == 0) v = __hiloint2double(0, (ipiv[e] & 15) << 2);  // the pivot row's lane, as a byte offset
+        else if (off <= kKL && i + off < n) v = ab[(int64_t)(i + off) * kBandW + (kKL - off)];
+    } else {
+        const int off = ((i - (k - 16) - 1) & 15) + 1;  // U(i - off, i) at column offset off of row i - off
+        if (i - off >= 0) v = ab[(int64_t)(i - off) * kBandW + (kKL + off)] * rdiag[e];
+    }
+    BC[t] = v;
+}
+
 int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const double* qc, const double* Tint,
                      double tt, const int32_t* active, double* AB, int32_t* ipiv, double* rdiag, int32_t* flag,
-                     double* AinvT, hipStream_t st) {
+                     double* AinvT, double* BC, hipStream_t st) {
     if (d.M == 0) return FIL_OK;
     j0_band_assemble_kernel<<<(unsigned)d.M, 256, 0, st>>>(d, bc, X, qc, Tint, tt, active, AB);
     // filaments grouped by size so that each launch's LDS fits its own largest filament
@@ -1571,6 +1617,9 @@ int j0_factor_launch(const SimDev& d, const BdfCoef& bc, const double* X, const 
             j0_inverse_cols_kernel<16><<<grid, 64, lds(16), st>>>(d, AB, ipiv, rdiag, active, AinvT, coff);
         }
     }
+    if (BC)
+        band_columns_kernel<<<(unsigned)ceil_div(6 * d.S * kBcW, (int64_t)256), 256, 0, st>>>(d, active, AB, ipiv,
+                                                                                           rdiag, BC);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }
@@ -1814,33 +1863,155 @@ __global__ void __launch_bounds__(NT) broyden_state_kernel(SimDev d, UpdateArgs 
     filament_state(d, f, sx, qjn, *u.tt, u.Yc, u.qc, u.F, u.T, u.box);
 }
 
-// J0^{-1} f for many filaments at once: one single-wave workgroup per filament running the
-// band sweeps, before the update kernel.  Inside the update kernel the sweeps occupy one of
-// its four waves and its LDS allows six workgroups per CU, so a CU runs six sweeps; here a
-// CU holds up to twenty (7.7 KB of LDS each), which hides the sweeps' per-row latency.
-__global__ void __launch_bounds__(64) band_solve_kernel(SimDev d, const double* __restrict__ AB,
-                                                        const int32_t* __restrict__ ipiv,
+// compile-time loop over the 16 lanes of a row (the DPP lane selects are immediates)
+template <int H = 0, class Fn>
+__device__ __forceinline__ void for_row_lanes(Fn&& fn) {
+    if constexpr (H < 16) {
+        fn(std::integral_constant<int, H>{});
+        for_row_lanes<H + 1>(fn);
+    }
+}
+
+// the right-hand side row i of L v (as diff_rhs) with both loads issued unconditionally
+__device__ __forceinline__ double diff_rhs_nobranch(const double* vf, int i, int N) {
+    const int R = i / 3, a = i % 3, m = R / 2;
+    const bool plain = R == 0 || (R & 1);
+    const int i1 = plain ? slot_of(R, N) + a : 3 + 3 * N + 3 * (m - 1) + a;
+    const int i2 = plain ? i1 : (m == 1 ? a : 3 + 3 * N + 3 * (m - 2) + a);
+    const double v1 = vf[i1], v2 = vf[i2];
+    return plain ? v1 : v1 - v2;
+}
+
+// J0^{-1} f for many filaments at once: four filaments per wave, one per row of 16 lanes,
+// the rows stepping together through the forward sweep (the factor's row interchanges and
+// its kKL multipliers per column) and the backward sweep (U, kKL + kKU entries above the
+// diagonal).  Each sweep keeps a 16-row window of the right-hand side in registers, row r
+// in lane r mod 16 of its row: a step broadcasts the head row inside the row of lanes
+// (DPP), updates the rows below (above) it with one multiply-add from the column record,
+// and the freed lane takes the row that enters the window.  Each lane reads one slot of
+// every record (band_columns_kernel rotates them so), into a ring of 16 registers: the
+// slot for step s + 16 is requested as soon as step s has used its own, so loads have 16
+// steps to arrive.  Records past either end of a filament (the next ones, or the zero pads)
+// are read but only ever multiply rows outside it, which are zero and never written out.
+// A wave's rows of lanes with shorter filaments (or finished suspensions) step along on
+// zero rows; in the backward sweep they are aligned at the top, so every row of lanes has
+// the same head lane.  The backward sweep leaves U(i, i) x_i, scaled at the output.
+__global__ void __launch_bounds__(64) band_solve_kernel(SimDev d, const double* __restrict__ BC,
                                                         const double* __restrict__ rdiag,
                                                         const int32_t* __restrict__ active,
                                                         const double* __restrict__ fX, double* __restrict__ g) {
-    const int64_t f = blockIdx.x;
-    if (!active[d.fil_susp[f]]) return;
-    const int64_t s0 = d.seg_off[f];
-    const int N = (int)(d.seg_off[f + 1] - s0);
-    const int n = 6 * N;
+    static_assert(kKL + kKU == 16 && kKL < 16 && kBcW == 32, "16-row windows, two 16-slot halves");
+    constexpr int kRows = 6 * kMaxSeg;
+    const int lane = threadIdx.x, gl = lane & 15, grp = lane >> 4, gb = lane & 48;
+    const int64_t f = (int64_t)blockIdx.x * 4 + grp;
+    const int64_t fc = f < d.M ? f : d.M - 1;
+    const bool on = f < d.M && active[d.fil_susp[fc]];
+    const int64_t s0 = d.seg_off[fc];
+    const int N = (int)(d.seg_off[fc + 1] - s0);
+    const int n = on ? 6 * N : 0;
+    const int nl = 6 * N - 1;  // last row of the (clamped) filament
     const int64_t e0 = 6 * s0;
-    const int lane = threadIdx.x;
-    __shared__ double y[6 * kMaxSeg], rd[6 * kMaxSeg];
-    __shared__ int ip[6 * kMaxSeg];
-    for (int i = lane; i < n; i += 64) {
-        y[i] = diff_rhs(fX + e0, i, N);
-        rd[i] = rdiag[e0 + i];
-        ip[i] = ipiv[e0 + i];
+    const int nmax = max(max(__builtin_amdgcn_readlane(n, 0), __builtin_amdgcn_readlane(n, 16)),
+                         max(__builtin_amdgcn_readlane(n, 32), __builtin_amdgcn_readlane(n, 48)));
+    if (nmax == 0) return;
+    const double* col = BC + e0 * kBcW;
+    // the first 16 forward records, requested before the right-hand side is staged
+    const double* pf = col + gl;  // position gl of every record's first half
+    double R[16];
+#pragma unroll
+    for (int h = 0; h < 16; h++) R[h] = pf[h * kBcW];
+    // the right-hand side (every load issued before the first is used) into the window store
+    __shared__ double ys[4][kRows + 16];  // a spare tail for the last block's rows past nmax
+    double* y = ys[grp];
+    constexpr int kPer = kRows / 32;  // rows per lane in each of two rounds
+#pragma unroll
+    for (int r0 = 0; r0 < kRows; r0 += 16 * kPer) {
+        double sv[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) sv[q] = diff_rhs_nobranch(fX + e0, min(r0 + gl + 16 * q, nl), N);
+#pragma unroll
+        for (int q = 0; q < kPer; q++)
+            if (r0 + gl + 16 * q < n) y[r0 + gl + 16 * q] = sv[q];
     }
     __syncthreads();
-    band_sweeps(AB + e0 * kBandW, ip, rd, y, n, lane);
+
+    // ---- forward sweep; step j: rows j .. j+15 in the window, head lane j mod 16.  Rows
+    // past n are zero (their multipliers are zero), so steps past n move and add zeros; a
+    // lane keeps the row it heads (yo) until the end of the block.
+    const int gl4 = gl << 2, gb4 = gb << 2;
+    double w = y[min(gl, kRows - 1)];
+    w = gl < n ? w : 0.0;
+    double yo = 0.0;
+    for (int jb = 0; jb < nmax; jb += 16) {
+        const int ie = jb + 16 + gl;  // the row that enters this lane at its step
+        const double yr = y[min(ie, kRows - 1)];
+        const double ye = ie < n ? yr : 0.0;
+        const double* pn = pf + (int64_t)(jb + 16) * kBcW;
+        for_row_lanes([&](auto hc) {
+            constexpr int h = decltype(hc)::value;
+            if (jb + h < nmax) {
+                // lane h's slot of the record holds the pivot's lane; its multiply-add is discarded
+                const int p4 = dpp_i32<kDppRowBcast + h>(__double2loint(R[h])) & 60;
+                const double vh = dpp64_f64<kDppRowBcast + h>(w);
+                const int a = gb4 | p4;
+                const double vp = __hiloint2double(__builtin_amdgcn_ds_bpermute(a, __double2hiint(w)),
+                                                   __builtin_amdgcn_ds_bpermute(a, __double2loint(w)));
+                const bool head = gl == h;
+                w = gl4 == p4 ? vh : w;  // row interchange
+                w = fma(-R[h], vp, w);
+                yo = head ? vp : yo;
+                w = head ? ye : w;
+            }
+            R[h] = pn[h * kBcW];
+        });
+        y[jb + gl] = yo;  // rows past n land in the store's spare tail or are never read
+    }
+
+    // ---- backward sweep in virtual rows v = i + dl (dl = nmax - n): head lane v mod 16
+    const int dl = nmax - n;
+    {
+        const int r = n - 16 + ((gl - nmax) & 15);  // rows n-16 .. n-1
+        const double yr = y[max(r, 0)];
+        w = r >= 0 ? yr : 0.0;
+    }
+    // position (gl - dl) mod 16 of the second halves: this lane's U entry at every step
+    const double* pb = col + 16 + ((gl - dl) & 15) - (int64_t)dl * kBcW;
+    int kb = (nmax - 1) >> 4;
+    {
+        const double* pk = pb + (int64_t)16 * kb * kBcW;
+#pragma unroll
+        for (int h = 0; h < 16; h++) R[h] = pk[h * kBcW];
+    }
+    for (; kb >= 0; kb--) {
+        const int ie = 16 * kb + gl - dl - 16;  // the row that enters this lane at its step
+        const double yr = y[max(ie, 0)];
+        const double ye = ie >= 0 ? yr : 0.0;
+        const double* pn = pb + (int64_t)16 * (kb - 1) * kBcW;
+        for_row_lanes([&](auto sc) {
+            constexpr int h = 15 - decltype(sc)::value;
+            if (16 * kb + h < nmax) {
+                const double wi = dpp64_f64<kDppRowBcast + h>(w);  // U(i, i) x_i of the head row i
+                const bool head = gl == h;
+                yo = head ? wi : yo;
+                w = fma(-R[h], wi, head ? ye : w);
+            }
+            R[h] = pn[h * kBcW];
+        });
+        const int i = 16 * kb + gl - dl;  // the row this lane headed
+        if (i >= 0 && 16 * kb + gl < nmax) y[i] = yo;
+    }
     __syncthreads();
-    for (int i = lane; i < n; i += 64) g[e0 + slot_of(i / 3, N) + i % 3] = y[i];
+#pragma unroll
+    for (int r0 = 0; r0 < kRows; r0 += 16 * kPer) {
+        double rv[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) rv[q] = rdiag[e0 + min(r0 + gl + 16 * q, nl)];
+#pragma unroll
+        for (int q = 0; q < kPer; q++) {
+            const int i = r0 + gl + 16 * q;
+            if (i < n) g[e0 + slot_of(i / 3, N) + i % 3] = y[i] * rv[q];
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256) f32_switch_kernel(int32_t* __restrict__ active, SuspLog* __restrict__ log,
@@ -1865,7 +2036,8 @@ int f32_switch_launch(int32_t* active, SuspLog* log, int* notnear, int64_t nsusp
 int broyden_state_launch(const SimDev& d, const UpdateArgs& u, const JudgeArgs& jg, int32_t* active, hipStream_t st) {
     if (d.M == 0) return FIL_OK;
     if (u.gsolve && !u.AinvT)
-        band_solve_kernel<<<(unsigned)d.M, 64, 0, st>>>(d, u.AB, u.ipiv, u.rdiag, active, u.fnew, u.gsolve);
+        band_solve_kernel<<<(unsigned)ceil_div(d.M, (int64_t)4), 64, 0, st>>>(d, u.BC, u.rdiag, active, u.fnew,
+                                                                            u.gsolve);
     if (fil_threads(d) == 1024) broyden_state_kernel<1024><<<(unsigned)d.M, 1024, 0, st>>>(d, u, jg, active);
     else broyden_state_kernel<256><<<(unsigned)d.M, 256, 0, st>>>(d, u, jg, active);
     FIL_HIP_TRY(hipGetLastError());
