@@ -150,7 +150,8 @@ void fil_fcm_destroy(fil_fcm* fcm);
  *   susp_off   HOST int64[nsusp+1], non-decreasing, susp_off[0] = 0 (copied)
  *   prec       FIL_PREC_F64 or FIL_PREC_F32TILE
  * fil_rpy_batch_workspace_bytes: device scratch of one apply (source records, FP32 tile
- *   records, split-K partials), -1 for a null plan.
+ *   records, split-K partials and the counter its workgroups take work items from, which
+ *   the apply clears first), -1 for a null plan.
  * fil_rpy_mobility_apply_batched: Y, F, T, a, eta, V, Omega as fil_rpy_mobility_apply over
  *   S = susp_off[nsusp] segments, on the device the plan was created on; work of at least
  *   fil_rpy_batch_workspace_bytes(plan) bytes (NULL when 0).  Applies in flight may share a

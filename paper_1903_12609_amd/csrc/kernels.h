@@ -68,9 +68,10 @@ struct RpyBatchPlan {
     std::vector<RpySusp> sus;
     std::vector<int32_t> seg_susp;
     size_t pack_bytes = 0, tile_bytes = 0, part_bytes = 0;
+    size_t ctr_bytes = 256;  // the work-item counter of one apply (cleared at its start)
     size_t items_bytes = 0, sus_bytes = 0, segs_bytes = 0;
     bool any_reduce = false;
-    size_t work_bytes() const { return pack_bytes + tile_bytes + part_bytes; }
+    size_t work_bytes() const { return pack_bytes + tile_bytes + part_bytes + ctr_bytes; }
     size_t lists_bytes() const { return items_bytes + sus_bytes + segs_bytes; }
 };
 RpyBatchPlan rpy_batch_plan(int64_t nsusp, const int64_t* susp_off, int prec);

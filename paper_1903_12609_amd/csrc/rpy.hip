@@ -332,12 +332,28 @@ __global__ void __launch_bounds__(kRpyBlock) __attribute__((amdgpu_waves_per_eu(
 
 // Many suspensions in one persistent launch: a fixed grid walks a work list
 // sorted by cost (largest first), item i handled by block i mod gridDim.
+// The next work item of a persistent workgroup: taken from a counter shared by the launch
+// (items are listed largest first, so taking them in order balances the workgroups)
+__device__ __forceinline__ int64_t next_item(int* next, int& take) {
+    __syncthreads();  // every thread has read the previous item's index
+    if (threadIdx.x == 0) take = atomicAdd(next, 1);
+    __syncthreads();
+    return take;
+}
+
+__global__ void __launch_bounds__(32) rpy_items_reset(int* __restrict__ next) {
+    if (threadIdx.x == 0) *next = 0;
+}
+
 template <int TPL>
 __global__ void __launch_bounds__(kRpyBlock) __attribute__((amdgpu_waves_per_eu(3))) rpy_f64_items_kernel(const RpyItem* __restrict__ items, int64_t nitems,
                                                                 int64_t Sg, const double* __restrict__ pk,
                                                                 const double* __restrict__ Y, double a, double c,
-                                                                RpyOut out) {
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+                                                                RpyOut out, int* __restrict__ next) {
+    __shared__ int take;
+    for (;;) {
+        const int64_t it = next_item(next, take);
+        if (it >= nitems) break;
         const RpyItem w = items[it];
         if (out.active && !out.active[w.susp]) continue;
         RpyOut o = out;
@@ -538,8 +554,11 @@ __global__ void __launch_bounds__(kRpyBlock) __attribute__((amdgpu_waves_per_eu(
                                                                 int64_t Sg, const SrcF32* __restrict__ pk,
                                                                 const TileF32* __restrict__ tiles,
                                                                 const double* __restrict__ Y, double a, double c,
-                                                                RpyOut out) {
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+                                                                RpyOut out, int* __restrict__ next) {
+    __shared__ int take;
+    for (;;) {
+        const int64_t it = next_item(next, take);
+        if (it >= nitems) break;
         const RpyItem w = items[it];
         if (out.active && !out.active[w.susp]) continue;
         RpyOut o = out;
@@ -697,7 +716,7 @@ RpyBatchPlan rpy_batch_plan(int64_t nsusp, const int64_t* susp_off, int prec) {
         }
         p.sus[i] = u;
     }
-    // largest items first: with a static round-robin walk this balances the blocks
+    // largest items first: workgroups taking them in order from a shared counter balance
     auto cost = [tpl](const RpyItem& w) {
         const int64_t nt = std::min<int64_t>((int64_t)kRpyBlock * tpl, w.S - (int64_t)w.tb * kRpyBlock * tpl);
         const int64_t ns = std::min<int64_t>(w.chunk, w.S - (int64_t)w.k * w.chunk);
@@ -743,11 +762,14 @@ int rpy_batch_launch(const RpyBatchPlan& p, const void* lists, const double* Y, 
     const int64_t nitems = (int64_t)p.items.size();
     const unsigned grid = (unsigned)std::min<int64_t>(nitems, kPersistentBlocks);
     const unsigned pgrid = (unsigned)ceil_div(p.Sg, 256);
+    int* next = reinterpret_cast<int*>(base + p.pack_bytes + p.tile_bytes + p.part_bytes);
+    if (nitems) rpy_items_reset<<<1, 32, 0, st>>>(next);
     if (p.prec == FIL_PREC_F64) {
         double* pk = reinterpret_cast<double*>(base);
         if (!packed) rpy_pack_f64<<<pgrid, 256, 0, st>>>(p.Sg, Y, F, T, pk);
         const double* src = pk;
-        if (nitems) launch_pair(rpy_f64_items_kernel<kTplF64>, grid, st, ev0, ev1, items, nitems, p.Sg, src, Y, a, c, out);
+        if (nitems)
+            launch_pair(rpy_f64_items_kernel<kTplF64>, grid, st, ev0, ev1, items, nitems, p.Sg, src, Y, a, c, out, next);
     } else {
         SrcF32* pk = reinterpret_cast<SrcF32*>(base);
         TileF32* tiles = reinterpret_cast<TileF32*>(base + p.pack_bytes);
@@ -755,7 +777,8 @@ int rpy_batch_launch(const RpyBatchPlan& p, const void* lists, const double* Y, 
         const SrcF32* src = pk;
         const TileF32* tl = tiles;
         if (nitems)
-            launch_pair(rpy_f32_items_kernel<kTplF32>, grid, st, ev0, ev1, items, nitems, p.Sg, src, tl, Y, a, c, out);
+            launch_pair(rpy_f32_items_kernel<kTplF32>, grid, st, ev0, ev1, items, nitems, p.Sg, src, tl, Y, a, c, out,
+                        next);
     }
     if (!nitems) {  // nothing launched: the timing events still mark this point
         if (ev0) FIL_HIP_TRY(hipEventRecord(ev0, st));

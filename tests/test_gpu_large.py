@@ -81,12 +81,15 @@ def test_unstaged_factor_first_quasi_newton_step(name, j0_mode):
     assert np.array_equal(out["unstaged"], out["auto"])
 
 
-def test_batched_suspensions_over_256_filaments():
+@pytest.mark.parametrize("j0_mode", ["dense", "banded"])
+def test_batched_suspensions_over_256_filaments(j0_mode):
     """Three suspensions of 120, 100 and 90 filaments (310 together) in one simulation: the
     ragged mobility work list, the 256-thread per-filament kernels and per-suspension
-    convergence; each matches its own oracle run."""
+    convergence; each matches its own oracle run.  Banded: J0^{-1} f by the band solve
+    kernel, whose waves then hold filaments of different lengths and of suspensions that
+    have already converged."""
     import paper_1903_12609_amd as fil
-    print("case batched-310", flush=True)
+    print("case batched-310", j0_mode, flush=True)
     ws = [synth.sediment_suspension(M=m, N=n, side=s, seed=80 + m, dt_over_T=1 / 15)
           for m, n, s in ((120, 5, 70.0), (100, 6, 70.0), (90, 4, 60.0))]
     fil_off = [0]
@@ -95,7 +98,7 @@ def test_batched_suspensions_over_256_filaments():
     sfo = np.concatenate([[0], np.cumsum([w.M for w in ws])])
     assert sfo[-1] > 256
     g = fil.Sim(fil_off, np.concatenate([w.Y for w in ws]), np.concatenate([w.q for w in ws]), ws[0].params,
-                susp_fil_off=sfo, graph=8)
+                susp_fil_off=sfo, graph=8, j0_mode=j0_mode)
     g.set_suspension_params(dt=[w.params["dt"] for w in ws], grav=[w.params["grav"] for w in ws],
                             FS=[w.params["FS"] for w in ws])
     os_ = [oracle.Sim(w.fil_off, w.Y, w.q, nthreads=8, **w.params) for w in ws]
@@ -112,7 +115,8 @@ def test_batched_suspensions_over_256_filaments():
 
 def test_band_solve_kernel_mixed_lengths():
     """Band path with 300 filaments of 2 to 50 segments: J0^{-1} f is formed by the band
-    solve kernel of its own (one wave per filament) before the update, and
+    solve kernel of its own (four filaments of different lengths per wave) before the
+    update, and
     X1 = X0 - J0^{-1} f(X0) matches the oracle's dense LU solve."""
     import paper_1903_12609_amd as fil
     print("case band solve kernel", flush=True)
