@@ -78,9 +78,14 @@ RpyBatchPlan rpy_batch_plan(int64_t nsusp, const int64_t* susp_off, int prec);
 // copies the plan's lists into `lists` (device, lists_bytes()), host -> device on `st`; the
 // plan's host vectors must stay alive until the copy has completed
 int rpy_batch_upload(const RpyBatchPlan& p, void* lists, hipStream_t st);
+// counter_clear: the work-item counter in `work` is known to be zero (cleared when the
+// workspace was made and by every apply of a plan that sums partials); else it is cleared first
 int rpy_batch_launch(const RpyBatchPlan& p, const void* lists, const double* Y, const double* F, const double* T,
                      double a, double eta, double* V, double* W, void* work, hipStream_t st, hipEvent_t ev0 = nullptr,
-                     hipEvent_t ev1 = nullptr, bool packed = false, const int32_t* active = nullptr);
+                     hipEvent_t ev1 = nullptr, bool packed = false, const int32_t* active = nullptr,
+                     bool counter_clear = false);
+// byte offset of the work-item counter in an apply's workspace
+inline size_t rpy_batch_counter_offset(const RpyBatchPlan& p) { return p.pack_bytes + p.tile_bytes + p.part_bytes; }
 
 struct RpyPlan {
     int64_t S;

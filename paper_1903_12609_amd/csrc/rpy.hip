@@ -593,7 +593,8 @@ __global__ void __launch_bounds__(256) rpy_reduce(int64_t S, int K, const double
 __global__ void __launch_bounds__(256) rpy_reduce_items(int64_t Sg, const int32_t* __restrict__ seg_susp,
                                                        const RpySusp* __restrict__ sus, const double* __restrict__ part,
                                                        double* __restrict__ V, double* __restrict__ W,
-                                                       const int32_t* __restrict__ active) {
+                                                       const int32_t* __restrict__ active, int* __restrict__ next) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *next = 0;  // the items kernel has finished: clear its counter
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= 6 * Sg) return;
     const int64_t c = e / Sg, s = e - c * Sg;
@@ -750,7 +751,7 @@ int rpy_batch_upload(const RpyBatchPlan& p, void* lists, hipStream_t st) {
 
 int rpy_batch_launch(const RpyBatchPlan& p, const void* lists, const double* Y, const double* F, const double* T,
                      double a, double eta, double* V, double* W, void* work, hipStream_t st, hipEvent_t ev0,
-                     hipEvent_t ev1, bool packed, const int32_t* active) {
+                     hipEvent_t ev1, bool packed, const int32_t* active, bool counter_clear) {
     if (p.Sg <= 0) return FIL_OK;
     char* base = static_cast<char*>(work);
     RpyOut out{reinterpret_cast<double*>(base + p.pack_bytes + p.tile_bytes), V, W, active};
@@ -763,7 +764,9 @@ int rpy_batch_launch(const RpyBatchPlan& p, const void* lists, const double* Y, 
     const unsigned grid = (unsigned)std::min<int64_t>(nitems, kPersistentBlocks);
     const unsigned pgrid = (unsigned)ceil_div(p.Sg, 256);
     int* next = reinterpret_cast<int*>(base + p.pack_bytes + p.tile_bytes + p.part_bytes);
-    if (nitems) rpy_items_reset<<<1, 32, 0, st>>>(next);
+    // the counter starts at zero: cleared here, or (counter_clear, a plan with partials to sum)
+    // by the previous apply's sum of the partials
+    if (nitems && !(counter_clear && p.any_reduce)) rpy_items_reset<<<1, 32, 0, st>>>(next);
     if (p.prec == FIL_PREC_F64) {
         double* pk = reinterpret_cast<double*>(base);
         if (!packed) rpy_pack_f64<<<pgrid, 256, 0, st>>>(p.Sg, Y, F, T, pk);
@@ -785,7 +788,8 @@ int rpy_batch_launch(const RpyBatchPlan& p, const void* lists, const double* Y, 
         if (ev1) FIL_HIP_TRY(hipEventRecord(ev1, st));
     }
     if (p.any_reduce)
-        rpy_reduce_items<<<(unsigned)ceil_div(6 * p.Sg, 256), 256, 0, st>>>(p.Sg, segs, sus, out.part, V, W, active);
+        rpy_reduce_items<<<(unsigned)ceil_div(6 * p.Sg, 256), 256, 0, st>>>(p.Sg, segs, sus, out.part, V, W, active,
+                                                                            next);
     FIL_HIP_TRY(hipGetLastError());
     return FIL_OK;
 }

@@ -273,7 +273,7 @@ int eval_residual(fil_sim* s, const double* X, double* fout, hipEvent_t e0, hipE
         if (e1) FIL_HIP_TRY(hipEventRecord(e1, s->st));
     } else if (s->batched) {
         TRY(rpy_batch_launch(s->bplan[c], s->rpy_lists[c], s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W,
-                             s->rpy_work[c], s->st, e0, e1, true, s->active_d));
+                             s->rpy_work[c], s->st, e0, e1, true, s->active_d, true));
     } else {
         // the split-K partials are summed inside the residual kernel
         TRY(rpy_launch(s->rplan[c], s->Yc, s->F, s->T, s->p.a, s->p.eta, s->V, s->W, s->rpy_work[c], s->st, e0, e1,
@@ -783,7 +783,15 @@ int fil_create(const fil_params* p, int64_t nsusp, const int64_t* susp_fil_off, 
             return rc;
         }
         s->rpy_work[c] = wk;
-        if (s->batched) s->rpy_lists[c] = wk + s->bplan[c].work_bytes();
+        if (s->batched) {
+            s->rpy_lists[c] = wk + s->bplan[c].work_bytes();
+            // the work-item counter starts at zero; every apply that sums partials clears it again
+            if (hipMemset(wk + rpy_batch_counter_offset(s->bplan[c]), 0, s->bplan[c].ctr_bytes) != hipSuccess) {
+                set_error("fil_create: clearing the mobility work counter failed");
+                free_sim(s);
+                return FIL_EHIP;
+            }
+        }
     }
     // ---- uploads
     std::vector<double> Ysoa(3 * S), qsoa(4 * S);
