@@ -145,33 +145,44 @@ __global__ void __launch_bounds__(256) gather_kernel(int B, int Bp, int nin, int
     for (int c = threadIdx.x; c < nout; c += blockDim.x) T[(int64_t)r * nout + c] = src >= 0 ? Tall[src * nout + c] : 0.f;
 }
 
-// dY = 2 (Y - T) / (B n_out) on the valid block (zero elsewhere), in both
-// layouts, and the loss (mean squared error) by one fixed-order block reduction.
+// dY = 2 (Y - T) / (B n_out) on the valid block (zero elsewhere), in both layouts, and
+// the squared errors summed per workgroup (rows blockIdx.x, blockIdx.x + kLossBlocks, ...)
+// by a fixed-order block reduction; loss_sum_kernel adds the workgroups' sums in order.
+constexpr int kLossBlocks = 64;
 __global__ void __launch_bounds__(256) loss_kernel(int B, int Bp, int nout, int nout_pad, const float* __restrict__ Y,
                                                    const float* __restrict__ T, uint16_t* __restrict__ dY,
-                                                   uint16_t* __restrict__ dYT, double* __restrict__ loss) {
+                                                   uint16_t* __restrict__ dYT, double* __restrict__ part) {
     __shared__ double red[256];
     double acc = 0.0;
     const float scale = 2.f / ((float)B * (float)nout);
-    for (int64_t e = threadIdx.x; e < (int64_t)Bp * nout_pad; e += blockDim.x) {
-        const int r = (int)(e / nout_pad), c = (int)(e % nout_pad);
-        float g = 0.f;
-        if (r < B && c < nout) {
-            const float d = Y[e] - T[e];
-            acc += (double)d * d;
-            g = scale * d;
+    for (int r = blockIdx.x; r < Bp; r += gridDim.x)
+        for (int c = threadIdx.x; c < nout_pad; c += blockDim.x) {
+            const int64_t e = (int64_t)r * nout_pad + c;
+            float g = 0.f;
+            if (r < B && c < nout) {
+                const float d = Y[e] - T[e];
+                acc += (double)d * d;
+                g = scale * d;
+            }
+            const uint16_t h = to_bf16(g);
+            dY[e] = h;
+            dYT[(int64_t)c * Bp + r] = h;
         }
-        const uint16_t h = to_bf16(g);
-        dY[e] = h;
-        dYT[(int64_t)c * Bp + r] = h;
-    }
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && loss) *loss = red[0] / ((double)B * nout);
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(64) loss_sum_kernel(int n, const double* __restrict__ part, double inv,
+                                                      double* __restrict__ loss) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; i++) s += part[i];
+    *loss = s * inv;
 }
 
 // db[n] = sum over the batch of dZ[b][n], from the transposed BF16 copy; one wave per n.
@@ -286,6 +297,7 @@ struct fil_mlp {
     float *Y = nullptr, *T = nullptr;
     uint16_t *dZ[2] = {nullptr, nullptr}, *dZT[2] = {nullptr, nullptr};
     double* loss = nullptr;
+    double* lpart = nullptr;  // per-workgroup squared-error sums of the loss kernel
     int64_t adam_t = 0;
     bool has_grad = false;
     std::vector<void*> allocs;
@@ -340,7 +352,9 @@ int backward(fil_mlp* m, int B, double* loss, hipStream_t st) {
     const int Bp = m->Bp;
     int rc = forward(m, Bp, m->X, m->Y, true, st);
     if (rc) return rc;
-    loss_kernel<<<1, 256, 0, st>>>(B, Bp, m->n_out, m->n_out_pad, m->Y, m->T, m->dZ[0], m->dZT[0], loss);
+    loss_kernel<<<kLossBlocks, 256, 0, st>>>(B, Bp, m->n_out, m->n_out_pad, m->Y, m->T, m->dZ[0], m->dZT[0],
+                                             m->lpart);
+    if (loss) loss_sum_kernel<<<1, 64, 0, st>>>(kLossBlocks, m->lpart, 1.0 / ((double)B * m->n_out), loss);
     FIL_HIP_TRY(hipGetLastError());
     int cur = 0;
     for (int l = m->L - 1; l >= 0; l--) {
@@ -442,7 +456,7 @@ int fil_mlp_create(int32_t n_seg, int32_t width, int32_t depth, int32_t max_batc
     if (rc == FIL_OK) rc = dalloc(m, &(ptr), (n));
     A(m->P, m->nparams) A(m->Mo, m->nparams) A(m->Ve, m->nparams) A(m->G, m->nparams)
     A(m->norm, 2 * (size_t)(m->n_in_pad + m->n_out_pad)) A(m->X, Bp * m->n_in_pad) A(m->XT, Bp * m->n_in_pad)
-    A(m->Y, Bp * m->n_out_pad) A(m->T, Bp * m->n_out_pad) A(m->loss, 1)
+    A(m->Y, Bp * m->n_out_pad) A(m->T, Bp * m->n_out_pad) A(m->loss, 1) A(m->lpart, kLossBlocks)
     const size_t wmax = std::max(width, m->n_out_pad);
     for (int i = 0; i < 2; i++) { A(m->dZ[i], Bp * wmax) A(m->dZT[i], Bp * wmax) }
     m->Wb.resize(m->L);
