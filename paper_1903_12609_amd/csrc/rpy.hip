@@ -248,16 +248,21 @@ __device__ __forceinline__ void rpy_finish(const RpyOut& out, int64_t base, int6
 // results go to part[(k*6 + c) * S + n] (suspension-local n) when K > 1.
 // WS = 1: the block's four waves own 4 x 64 x TPL different targets.  WS = 4 (small
 // sizes): the four waves share 64 x TPL targets and split the chunk's sources
-// four ways; their results are combined through LDS in wave order.
-template <int TPL, int WS>
+// four ways; their results are combined through LDS in wave order.  SKIP (WS = 1, many
+// suspensions of any size): each wave owns 64 x TPL consecutive targets and a wave whose
+// targets all lie past the end of the suspension returns at once.
+template <int TPL, int WS, bool SKIP = false>
 __device__ __forceinline__ void rpy_item_f64(int64_t base, int64_t S, int64_t Sg, int64_t tb, int k, int K,
                                              int64_t chunk, const double* __restrict__ pk,
                                              const double* __restrict__ Y, double a, double c, const RpyOut& out) {
+    static_assert(!SKIP || WS == 1, "waves that share targets cannot skip");
     constexpr int kTgtPerBlock = kRpyBlock / WS;  // targets per j-slice
     // the wave index is made visibly wave-uniform so that the source range, the
     // loop and the source addresses stay on the scalar unit
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int tid = WS == 1 ? (int)threadIdx.x : (int)(threadIdx.x % 64);
+    const int64_t t_wave = tb * (kTgtPerBlock * TPL) + (int64_t)wave * 64 * TPL;  // SKIP: the wave's first target
+    if (SKIP && t_wave >= S) return;
     int64_t m0 = (int64_t)k * chunk;
     int64_t m1 = min(S, m0 + chunk);
     if (WS > 1) {
@@ -272,7 +277,7 @@ __device__ __forceinline__ void rpy_item_f64(int64_t base, int64_t S, int64_t Sg
     AccF64 A[TPL];
 #pragma unroll
     for (int j = 0; j < TPL; j++) {
-        n[j] = tb * (kTgtPerBlock * TPL) + j * kTgtPerBlock + tid;
+        n[j] = SKIP ? t_wave + j * 64 + (tid & 63) : tb * (kTgtPerBlock * TPL) + j * kTgtPerBlock + tid;
         const int64_t nn = base + (n[j] < S ? n[j] : S - 1);
         y[j][0] = Y[nn];
         y[j][1] = Y[Sg + nn];
@@ -358,7 +363,7 @@ __global__ void __launch_bounds__(kRpyBlock) __attribute__((amdgpu_waves_per_eu(
         if (out.active && !out.active[w.susp]) continue;
         RpyOut o = out;
         o.part = out.part + w.part;
-        rpy_item_f64<TPL, 1>(w.base, w.S, Sg, w.tb, w.k, w.K, w.chunk, pk, Y, a, c, o);
+        rpy_item_f64<TPL, 1, true>(w.base, w.S, Sg, w.tb, w.k, w.K, w.chunk, pk, Y, a, c, o);
     }
 }
 
@@ -426,11 +431,12 @@ __device__ __forceinline__ double uniform_f64(double x) {
 // One work item of the FP32-tile path: as rpy_item_f64, but the lanes of a wave own
 // 64 x TPL consecutive targets (lane + 64 j), so that the wave's targets are close together
 // and most tiles are far enough from all of them to skip the overlap test.
-template <int TPL, int WS>
+template <int TPL, int WS, bool SKIP = false>
 __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg, int64_t tb, int k, int K,
                                              int64_t chunk, const SrcF32* __restrict__ pk,
                                              const TileF32* __restrict__ tiles, const double* __restrict__ Y,
                                              double a, double c, const RpyOut& out) {
+    static_assert(!SKIP || WS == 1, "waves that share targets cannot skip");
     constexpr int kTgtPerBlock = kRpyBlock / WS;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x % 64);
@@ -445,6 +451,7 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
     const float af = (float)a, four_a2 = (float)(4.0 * a * a), two_a2 = (float)(2.0 * a * a);
     const float c23 = (float)(2.0 * a * a / 3.0);
     const int64_t t_first = tb * (kTgtPerBlock * TPL) + (WS == 1 ? (int64_t)wave * 64 * TPL : 0);
+    if (SKIP && t_first >= S) return;  // no target of this wave inside the suspension
     int64_t n[TPL];
     double y[TPL][3], vd[TPL][3], wd[TPL][3];
     double lo[3], hi[3];
@@ -563,7 +570,7 @@ __global__ void __launch_bounds__(kRpyBlock) __attribute__((amdgpu_waves_per_eu(
         if (out.active && !out.active[w.susp]) continue;
         RpyOut o = out;
         o.part = out.part + w.part;
-        rpy_item_f32<TPL, 1>(w.base, w.S, Sg, w.tb, w.k, w.K, w.chunk, pk, tiles, Y, a, c, o);
+        rpy_item_f32<TPL, 1, true>(w.base, w.S, Sg, w.tb, w.k, w.K, w.chunk, pk, tiles, Y, a, c, o);
     }
 }
 
