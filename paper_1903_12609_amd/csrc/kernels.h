@@ -7,15 +7,16 @@
 namespace fil {
 
 // FP32-tile source record (64 B, all float): the source's offset from the origin of its
-// tile (kF32Tile consecutive sources by global index), its force, its torque and the torque
-// scaled by 3/2 and by -1/2 (the factors of the rotation terms, applied once per source)
+// tile (kF32Tile consecutive sources by global index), its force, its torque, and the cross
+// products of torque and force with that offset (the parts of T x r and F x r that do not
+// depend on the target, formed once per source)
 constexpr int kF32Tile = 16;
 struct alignas(16) SrcF32 {
     float sp[3];   // fl(Y_m - O_tile)
     float f[3];    // F_m
     float t[3];    // T_m
-    float t15[3];  // 3/2 T_m
-    float tm[3];   // -1/2 T_m
+    float ct[3];   // T_m x sp
+    float cf[3];   // 2/3 F_m x sp
     float pad;
 };
 static_assert(sizeof(SrcF32) == 64, "SrcF32 must be 64 bytes");

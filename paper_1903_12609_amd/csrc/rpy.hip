@@ -75,13 +75,19 @@ __global__ void __launch_bounds__(256) rpy_tile_pack(int64_t S, const double* __
         d2 = fma(hi[i] - lo[i], hi[i] - lo[i], d2);
     }
     SrcF32 r;
+    double sp[3], f[3], t[3];
     for (int i = 0; i < 3; i++) {
-        const double t = T[i * S + m];
         r.sp[i] = (float)(y[i] - o[i]);
-        r.f[i] = (float)F[i * S + m];
-        r.t[i] = (float)t;
-        r.t15[i] = (float)(1.5 * t);
-        r.tm[i] = (float)(-0.5 * t);
+        sp[i] = (double)r.sp[i];  // the cross products below use the offset as stored
+        f[i] = F[i * S + m];
+        t[i] = T[i * S + m];
+        r.f[i] = (float)f[i];
+        r.t[i] = (float)t[i];
+    }
+    for (int i = 0; i < 3; i++) {
+        const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+        r.ct[i] = (float)(t[i1] * sp[i2] - t[i2] * sp[i1]);
+        r.cf[i] = (float)((2.0 / 3.0) * (f[i1] * sp[i2] - f[i2] * sp[i1]));
     }
     r.pad = 0.f;
     pk[m] = r;
@@ -368,12 +374,23 @@ __global__ void __launch_bounds__(kRpyBlock) __attribute__((amdgpu_waves_per_eu(
 }
 
 // ------------------------------------------------------------------ FP32-tile pair
-// Accumulates (V, Omega) / c of one pair in float.  With q = s^3 r:
-//   v += (s + 2a^2/3 s^3) F + (1 - 2a^2 s^2)(r.F) q + T x q
-//   w += s^3 (-1/2 T) + s^2 (r.(3/2 T)) q + F x q
-// (46 VALU operations per pair, r included).  NEAR: the overlap test and its branch.
+// Sums over the sources of one tile, per target, in float.  With r = y_t - s_p (y_t the
+// target's and s_p the source's offset from the tile origin), s = 1/|r|:
+//   V  += s F + (1 - 2a^2 s^2)(r.F) s^3 r - s^3 (T x s_p)
+//   R  += s^3 F
+//   P  += s^3 T
+//   W  += s^5 (r.T) r - 2/3 s^3 (F x s_p)
+// (41 VALU operations per pair, r included; T x s_p and 2/3 F x s_p are stored in the
+// source record).  Once per tile the target's (V, Omega) / c take
+//   v = V + 2a^2/3 R + P x y_t,   w = R x y_t + 3/2 W - 1/2 P,
+// which is s F + 2a^2/3 s^3 F + (1 - 2a^2 s^2)(r.F) s^3 r + s^3 T x r for v and
+// s^3 F x r + 3/2 s^5 (r.T) r - 1/2 s^3 T for w, summed over the tile.  NEAR: the overlap
+// test and its branch.
 struct SrcRegF32 {
-    float sp[3], f[3], t[3], t15[3], tm[3];
+    float sp[3], f[3], t[3], ct[3], cf[3];
+};
+struct AccF32 {
+    float V[3], R[3], P[3], W[3];
 };
 // the whole 64-byte record in one scalar load (it is wave-uniform)
 __device__ __forceinline__ SrcRegF32 load_src_f32(const SrcF32* __restrict__ s) {
@@ -383,13 +400,13 @@ __device__ __forceinline__ SrcRegF32 load_src_f32(const SrcF32* __restrict__ s) 
     r.sp[0] = a.x; r.sp[1] = a.y; r.sp[2] = a.z;
     r.f[0] = a.w;  r.f[1] = b.x;  r.f[2] = b.y;
     r.t[0] = b.z;  r.t[1] = b.w;  r.t[2] = c.x;
-    r.t15[0] = c.y; r.t15[1] = c.z; r.t15[2] = c.w;
-    r.tm[0] = d.x; r.tm[1] = d.y; r.tm[2] = d.z;
+    r.ct[0] = c.y; r.ct[1] = c.z; r.ct[2] = c.w;
+    r.cf[0] = d.x; r.cf[1] = d.y; r.cf[2] = d.z;
     return r;
 }
 template <bool NEAR>
 __device__ __forceinline__ void rpy_pair_f32(float rx, float ry, float rz, const SrcRegF32& s, float a,
-                                             float four_a2, float two_a2, float c23, float v[3], float w[3]) {
+                                             float four_a2, float two_a2, AccF32& A) {
     const float r2 = fmaf(rx, rx, fmaf(ry, ry, rz * rz));
     float sv = __builtin_amdgcn_rsqf(r2);
     bool near = false;
@@ -398,24 +415,28 @@ __device__ __forceinline__ void rpy_pair_f32(float rx, float ry, float rz, const
         sv = near ? 0.f : sv;
     }
     const float s2 = sv * sv, s3 = s2 * sv;
-    const float qx = s3 * rx, qy = s3 * ry, qz = s3 * rz;
     const float Fx = s.f[0], Fy = s.f[1], Fz = s.f[2], Tx = s.t[0], Ty = s.t[1], Tz = s.t[2];
     const float rF = fmaf(rx, Fx, fmaf(ry, Fy, rz * Fz));
-    const float rT = fmaf(rx, s.t15[0], fmaf(ry, s.t15[1], rz * s.t15[2]));  // 3/2 r.T
-    const float A = fmaf(c23, s3, sv);            // s + 2a^2/3 s^3
-    const float B = fmaf(-two_a2, s2, 1.f) * rF;  // (1 - 2a^2 s^2) (r.F)
-    const float D = s2 * rT;                      // 3/2 s^2 (r.T)
-    v[0] = fmaf(A, Fx, fmaf(B, qx, fmaf(Ty, qz, fmaf(-Tz, qy, v[0]))));
-    v[1] = fmaf(A, Fy, fmaf(B, qy, fmaf(Tz, qx, fmaf(-Tx, qz, v[1]))));
-    v[2] = fmaf(A, Fz, fmaf(B, qz, fmaf(Tx, qy, fmaf(-Ty, qx, v[2]))));
-    w[0] = fmaf(s3, s.tm[0], fmaf(D, qx, fmaf(Fy, qz, fmaf(-Fz, qy, w[0]))));
-    w[1] = fmaf(s3, s.tm[1], fmaf(D, qy, fmaf(Fz, qx, fmaf(-Fx, qz, w[1]))));
-    w[2] = fmaf(s3, s.tm[2], fmaf(D, qz, fmaf(Fx, qy, fmaf(-Fy, qx, w[2]))));
+    const float rT = fmaf(rx, Tx, fmaf(ry, Ty, rz * Tz));
+    const float Bs3 = fmaf(-two_a2, s2, 1.f) * rF * s3;  // (1 - 2a^2 s^2)(r.F) s^3
+    const float Ds5 = s2 * s3 * rT;                       // s^5 (r.T)
+    A.V[0] = fmaf(sv, Fx, fmaf(Bs3, rx, fmaf(-s3, s.ct[0], A.V[0])));
+    A.V[1] = fmaf(sv, Fy, fmaf(Bs3, ry, fmaf(-s3, s.ct[1], A.V[1])));
+    A.V[2] = fmaf(sv, Fz, fmaf(Bs3, rz, fmaf(-s3, s.ct[2], A.V[2])));
+    A.R[0] = fmaf(s3, Fx, A.R[0]);
+    A.R[1] = fmaf(s3, Fy, A.R[1]);
+    A.R[2] = fmaf(s3, Fz, A.R[2]);
+    A.P[0] = fmaf(s3, Tx, A.P[0]);
+    A.P[1] = fmaf(s3, Ty, A.P[1]);
+    A.P[2] = fmaf(s3, Tz, A.P[2]);
+    A.W[0] = fmaf(Ds5, rx, fmaf(-s3, s.cf[0], A.W[0]));
+    A.W[1] = fmaf(Ds5, ry, fmaf(-s3, s.cf[1], A.W[1]));
+    A.W[2] = fmaf(Ds5, rz, fmaf(-s3, s.cf[2], A.W[2]));
     if (NEAR && near && r2 > 0.f) {  // the self pair (r = 0) is added per target, in double, after the loop
         const Ovl<float> o = rpy_overlap<float>(rx, ry, rz, r2, Fx, Fy, Fz, Tx, Ty, Tz, a);
         for (int i = 0; i < 3; i++) {
-            v[i] += o.v[i];
-            w[i] += o.w[i];
+            A.V[i] += o.v[i];
+            A.W[i] = fmaf(2.f / 3.f, o.w[i], A.W[i]);
         }
     }
 }
@@ -488,10 +509,10 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
         // |C_w - O| >= reach: every pair of this tile is at least 2a apart (no overlap test)
         const double reach = rw + tr.rad + 2.0 * a;
         const int far = __builtin_amdgcn_readfirstlane((int)(fma(dx, dx, fma(dy, dy, dz * dz)) >= reach * reach));
-        float v[TPL][3], w[TPL][3];
+        AccF32 acc[TPL];
 #pragma unroll
         for (int j = 0; j < TPL; j++)
-            for (int i = 0; i < 3; i++) v[j][i] = w[j][i] = 0.f;
+            for (int i = 0; i < 3; i++) acc[j].V[i] = acc[j].R[i] = acc[j].P[i] = acc[j].W[i] = 0.f;
         // r in float from the target's offset to the tile origin (rounded once per tile) and the
         // source's stored offset: its error is a few float ulps of |r| + 2 rad
         float yt[TPL][3];
@@ -508,19 +529,24 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
 #pragma unroll
                 for (int j = 0; j < TPL; j++)
                     rpy_pair_f32<decltype(near)::value>(yt[j][0] - cur.sp[0], yt[j][1] - cur.sp[1],
-                                                        yt[j][2] - cur.sp[2], cur, af, four_a2, two_a2, c23, v[j],
-                                                        w[j]);
+                                                        yt[j][2] - cur.sp[2], cur, af, four_a2, two_a2, acc[j]);
                 cur = nxt;
             }
         };
         if (far) sweep(std::false_type{});
         else sweep(std::true_type{});
 #pragma unroll
-        for (int j = 0; j < TPL; j++)
+        for (int j = 0; j < TPL; j++) {
+            const AccF32& A = acc[j];
+            const float* u = yt[j];
             for (int i = 0; i < 3; i++) {
-                vd[j][i] += (double)v[j][i];
-                wd[j][i] += (double)w[j][i];
+                const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+                const float v = fmaf(A.P[i1], u[i2], fmaf(-A.P[i2], u[i1], fmaf(c23, A.R[i], A.V[i])));
+                const float w = fmaf(A.R[i1], u[i2], fmaf(-A.R[i2], u[i1], fmaf(1.5f, A.W[i], -0.5f * A.P[i])));
+                vd[j][i] += (double)v;
+                wd[j][i] += (double)w;
             }
+        }
         t0 = t1;
     }
     // the self pair (r = 0 in the overlap forms): 4/(3a) F and T / a^3, in double
@@ -545,7 +571,7 @@ __device__ __forceinline__ void rpy_item_f32(int64_t base, int64_t S, int64_t Sg
 }
 
 template <int TPL, int WS>
-__global__ void __launch_bounds__(kRpyBlock) rpy_f32_kernel(int64_t S, int64_t chunk, int K,
+__global__ void __launch_bounds__(kRpyBlock) __attribute__((amdgpu_waves_per_eu(5))) rpy_f32_kernel(int64_t S, int64_t chunk, int K,
                                                           const SrcF32* __restrict__ pk,
                                                           const TileF32* __restrict__ tiles,
                                                           const double* __restrict__ Y, double a, double c,
