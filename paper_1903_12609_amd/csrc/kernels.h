@@ -28,18 +28,19 @@ struct alignas(16) TileF32 {
 };
 static_assert(sizeof(TileF32) == 32, "TileF32 must be 32 bytes");
 
-// Writes the FP64 mobility source record of segment m: 16 doubles [Y, F, T, T x Y, F x Y, 0].
+// Writes the FP64 mobility source record of segment m: 16 doubles [Y, F, T, T x Y, 2/3 F x Y, 0].
 __device__ __forceinline__ void rpy_pack_record_f64(double* pk, int64_t m, double y0, double y1, double y2,
                                                     double f0, double f1, double f2, double t0, double t1, double t2) {
     double2* o = reinterpret_cast<double2*>(pk + 16 * m);
+    constexpr double k23 = 2.0 / 3.0;
     o[0] = make_double2(y0, y1);
     o[1] = make_double2(y2, f0);
     o[2] = make_double2(f1, f2);
     o[3] = make_double2(t0, t1);
     o[4] = make_double2(t2, t1 * y2 - t2 * y1);
     o[5] = make_double2(t2 * y0 - t0 * y2, t0 * y1 - t1 * y0);
-    o[6] = make_double2(f1 * y2 - f2 * y1, f2 * y0 - f0 * y2);
-    o[7] = make_double2(f0 * y1 - f1 * y0, 0.0);
+    o[6] = make_double2(k23 * (f1 * y2 - f2 * y1), k23 * (f2 * y0 - f0 * y2));
+    o[7] = make_double2(k23 * (f0 * y1 - f1 * y0), 0.0);
 }
 
 // Work item of the persistent RPY launch: a target block x source chunk of one suspension.

@@ -100,14 +100,14 @@ __global__ void __launch_bounds__(256) rpy_tile_pack(int64_t S, const double* __
 }
 
 // ------------------------------------------------------------------ FP64 pair
+// Per target, with r = y - Y_m and s = 1/|r| (V, Omega below are divided by c):
+//   V += s F + (1 - 2a^2 s^2)(r.F) s^3 r - s^3 (T x Y_m)   (+ overlap V)
+//   R += s^3 F,   P += s^3 T
+//   W += s^5 (r.T) r - 2/3 s^3 (F x Y_m)                   (+ 2/3 overlap Omega)
+// and at the end V = V + 2a^2/3 R + P x y, Omega = R x y + 3/2 W - 1/2 P (T x Y_m and
+// 2/3 F x Y_m come with the source record).
 struct AccF64 {
-    double G[3];   // sum s F                     (M^tt, 1/r part)
-    double R[3];   // sum s^3 F                   (M^tt a^2 part, M^rt)
-    double P[3];   // sum s^3 T                   (M^tr, M^rr)
-    double Q[3];   // sum s^3 (T x Y_m)           (M^tr)
-    double U[3];   // sum s^3 (F x Y_m) - overlap Omega / c
-    double Hv[3];  // sum s^3 (1 - 2a^2 s^2)(r.F) r
-    double Hw[3];  // sum s^5 (r.T) r
+    double V[3], R[3], P[3], W[3];
 };
 
 // Overlap (r < 2a) contribution divided by c = 1/(8 pi eta).  Equal-radius
@@ -153,46 +153,37 @@ __device__ __forceinline__ void rpy_pair_f64(const double y[3], const double (&s
     const double Fx = s[3], Fy = s[4], Fz = s[5], Tx = s[6], Ty = s[7], Tz = s[8];
     const double rF = fma(rx, Fx, fma(ry, Fy, rz * Fz));
     const double rT = fma(rx, Tx, fma(ry, Ty, rz * Tz));
-    A.G[0] = fma(sv, Fx, A.G[0]);
-    A.G[1] = fma(sv, Fy, A.G[1]);
-    A.G[2] = fma(sv, Fz, A.G[2]);
+    const double Br = s3 * fma(-two_a2, s2, 1.0) * rF;
+    A.V[0] = fma(sv, Fx, fma(Br, rx, fma(-s3, s[9], A.V[0])));
+    A.V[1] = fma(sv, Fy, fma(Br, ry, fma(-s3, s[10], A.V[1])));
+    A.V[2] = fma(sv, Fz, fma(Br, rz, fma(-s3, s[11], A.V[2])));
     A.R[0] = fma(s3, Fx, A.R[0]);
     A.R[1] = fma(s3, Fy, A.R[1]);
     A.R[2] = fma(s3, Fz, A.R[2]);
     A.P[0] = fma(s3, Tx, A.P[0]);
     A.P[1] = fma(s3, Ty, A.P[1]);
     A.P[2] = fma(s3, Tz, A.P[2]);
-    A.Q[0] = fma(s3, s[9], A.Q[0]);
-    A.Q[1] = fma(s3, s[10], A.Q[1]);
-    A.Q[2] = fma(s3, s[11], A.Q[2]);
-    A.U[0] = fma(s3, s[12], A.U[0]);
-    A.U[1] = fma(s3, s[13], A.U[1]);
-    A.U[2] = fma(s3, s[14], A.U[2]);
-    const double Br = s3 * fma(-two_a2, s2, 1.0) * rF;
-    A.Hv[0] = fma(Br, rx, A.Hv[0]);
-    A.Hv[1] = fma(Br, ry, A.Hv[1]);
-    A.Hv[2] = fma(Br, rz, A.Hv[2]);
     const double D = s3 * s2 * rT;
-    A.Hw[0] = fma(D, rx, A.Hw[0]);
-    A.Hw[1] = fma(D, ry, A.Hw[1]);
-    A.Hw[2] = fma(D, rz, A.Hw[2]);
+    A.W[0] = fma(D, rx, fma(-s3, s[12], A.W[0]));
+    A.W[1] = fma(D, ry, fma(-s3, s[13], A.W[1]));
+    A.W[2] = fma(D, rz, fma(-s3, s[14], A.W[2]));
     if (near) {
-        // overlap: added to G (velocity), subtracted from U (angular velocity).  At r = 0
-        // (the self pair) the overlap forms reduce to 4/(3a) F and T/a^3, taken directly
+        // overlap: added to V and (times 2/3) to W.  At r = 0 (the self pair) the overlap
+        // forms reduce to 4/(3a) F and T/a^3, taken directly
         if (r2 > 0.0) {
             const Ovl<double> o = rpy_overlap<double>(rx, ry, rz, r2, Fx, Fy, Fz, Tx, Ty, Tz, a);
             for (int i = 0; i < 3; i++) {
-                A.G[i] += o.v[i];
-                A.U[i] -= o.w[i];
+                A.V[i] += o.v[i];
+                A.W[i] = fma(2.0 / 3.0, o.w[i], A.W[i]);
             }
         } else {
-            const double cv = 4.0 / (3.0 * a), cw = 1.0 / (a * a * a);
-            A.G[0] = fma(cv, Fx, A.G[0]);
-            A.G[1] = fma(cv, Fy, A.G[1]);
-            A.G[2] = fma(cv, Fz, A.G[2]);
-            A.U[0] = fma(-cw, Tx, A.U[0]);
-            A.U[1] = fma(-cw, Ty, A.U[1]);
-            A.U[2] = fma(-cw, Tz, A.U[2]);
+            const double cv = 4.0 / (3.0 * a), cw = 2.0 / (3.0 * a * a * a);
+            A.V[0] = fma(cv, Fx, A.V[0]);
+            A.V[1] = fma(cv, Fy, A.V[1]);
+            A.V[2] = fma(cv, Fz, A.V[2]);
+            A.W[0] = fma(cw, Tx, A.W[0]);
+            A.W[1] = fma(cw, Ty, A.W[1]);
+            A.W[2] = fma(cw, Tz, A.W[2]);
         }
     }
 }
@@ -288,8 +279,7 @@ __device__ __forceinline__ void rpy_item_f64(int64_t base, int64_t S, int64_t Sg
         y[j][0] = Y[nn];
         y[j][1] = Y[Sg + nn];
         y[j][2] = Y[2 * Sg + nn];
-        for (int i = 0; i < 3; i++)
-            A[j].G[i] = A[j].R[i] = A[j].P[i] = A[j].Q[i] = A[j].U[i] = A[j].Hv[i] = A[j].Hw[i] = 0.0;
+        for (int i = 0; i < 3; i++) A[j].V[i] = A[j].R[i] = A[j].P[i] = A[j].W[i] = 0.0;
     }
     {
         // the next source record is requested before the current one is used, so
@@ -316,13 +306,13 @@ __device__ __forceinline__ void rpy_item_f64(int64_t base, int64_t S, int64_t Sg
     for (int j = 0; j < TPL; j++) {
         const AccF64& B = A[j];
         const double* yy = y[j];
-        // V = c [G + 2a^2/3 R + Hv + P x y - Q];  Omega = c [R x y - U + 3/2 Hw - 1/2 P]
-        vw[j][0] = c * (B.G[0] + c23 * B.R[0] + B.Hv[0] + (B.P[1] * yy[2] - B.P[2] * yy[1]) - B.Q[0]);
-        vw[j][1] = c * (B.G[1] + c23 * B.R[1] + B.Hv[1] + (B.P[2] * yy[0] - B.P[0] * yy[2]) - B.Q[1]);
-        vw[j][2] = c * (B.G[2] + c23 * B.R[2] + B.Hv[2] + (B.P[0] * yy[1] - B.P[1] * yy[0]) - B.Q[2]);
-        vw[j][3] = c * ((B.R[1] * yy[2] - B.R[2] * yy[1]) - B.U[0] + 1.5 * B.Hw[0] - 0.5 * B.P[0]);
-        vw[j][4] = c * ((B.R[2] * yy[0] - B.R[0] * yy[2]) - B.U[1] + 1.5 * B.Hw[1] - 0.5 * B.P[1]);
-        vw[j][5] = c * ((B.R[0] * yy[1] - B.R[1] * yy[0]) - B.U[2] + 1.5 * B.Hw[2] - 0.5 * B.P[2]);
+        // V = c [V + 2a^2/3 R + P x y];  Omega = c [R x y + 3/2 W - 1/2 P]
+        vw[j][0] = c * (B.V[0] + c23 * B.R[0] + (B.P[1] * yy[2] - B.P[2] * yy[1]));
+        vw[j][1] = c * (B.V[1] + c23 * B.R[1] + (B.P[2] * yy[0] - B.P[0] * yy[2]));
+        vw[j][2] = c * (B.V[2] + c23 * B.R[2] + (B.P[0] * yy[1] - B.P[1] * yy[0]));
+        vw[j][3] = c * ((B.R[1] * yy[2] - B.R[2] * yy[1]) + 1.5 * B.W[0] - 0.5 * B.P[0]);
+        vw[j][4] = c * ((B.R[2] * yy[0] - B.R[0] * yy[2]) + 1.5 * B.W[1] - 0.5 * B.P[1]);
+        vw[j][5] = c * ((B.R[0] * yy[1] - B.R[1] * yy[0]) + 1.5 * B.W[2] - 0.5 * B.P[2]);
     }
     rpy_finish<TPL, WS>(out, base, S, Sg, K, k, n, vw);
 }
