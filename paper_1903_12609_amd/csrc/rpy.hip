@@ -10,19 +10,21 @@
 //     and broadcast to the VALU for free.  No LDS staging is needed.
 //   * Each lane owns TPL targets (register blocking amortises loop overhead).
 //   * FP64 path: the cross-product terms are expanded so that per-source
-//     constants (T_m x Y_m, F_m x Y_m) are precomputed:
+//     constants (T_m x Y_m, 2/3 F_m x Y_m) are precomputed:
 //         sum_m s^3 T_m x (Y_n - Y_m) = (sum_m s^3 T_m) x Y_n - sum_m s^3 (T_m x Y_m)
-//     which leaves 21 FMA-class accumulators per target and ~43 VALU
-//     operations per pair.  The coefficient 2a^2/3 s^3 F_m of M^tt is folded
-//     into the s^3 F_m accumulator, -1/2 s^3 T_m of M^rr into s^3 T_m.
+//     and the terms that enter V (or Omega) with a fixed coefficient share one sum,
+//     which leaves four 3-vector sums per target and ~50 VALU operations per pair.
+//     The coefficient 2a^2/3 of s^3 F_m in M^tt and -1/2 of s^3 T_m in M^rr are
+//     applied once per target at the end.
 //   * FP32-tile path: sources come in tiles of 16 (by global index) with an FP64
-//     origin each; a source record holds its FP32 offset from that origin.  A wave's
-//     targets are contiguous, and for a tile far from all of them (minimum pair
-//     distance >= 2 a + twice the tile radius) each target's offset from the tile
-//     origin is rounded once per tile and r = y' - s' is formed in float: three
-//     roundings of sizes below 3 |r| ulp.  Tiles near the wave take r = Y_n - Y_m in
-//     double, rounded once, with the overlap test.  The pair arithmetic runs in
-//     float, each tile is accumulated in float and then added into double.
+//     origin each; a source record holds its FP32 offset s' from that origin and the
+//     cross products of its torque and force with s'.  A wave's targets are
+//     contiguous; each target's offset y' from the tile origin is rounded once per
+//     tile and r = y' - s' is formed in float (an error of a few float ulps of
+//     |r| + 2 x tile radius).  The pair arithmetic runs in float, the parts of T x r
+//     and F x r that depend on y' are completed once per tile, and each tile's sums
+//     are added into double.  Only tiles that may hold a pair closer than 2a to one of
+//     the wave's targets take the overlap test.
 //   * Overlapping pairs (r < 2a) take a rarely executed branch with the regularised
 //     forms; the far-field weights are zeroed there.  The self pair (r = 0) is taken in
 //     its closed form 4/(3a) F, T/a^3 (in the FP32-tile path: in double, per target).
