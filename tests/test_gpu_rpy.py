@@ -88,6 +88,33 @@ def test_rpy_deterministic_and_empty():
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32tile"])
+def test_rpy_batched_wave_and_item_boundaries(prec):
+    """Suspension sizes around the batched work item's boundaries (a wave owns 128
+    consecutive targets, an item 512): every target of every suspension, the last ones
+    included, equals its own oracle apply, whether its wave is full, partly filled, or
+    (past the suspension's end) skips the item."""
+    import paper_1903_12609_amd as fil
+    rng = np.random.default_rng(23)
+    sizes = [127, 128, 129, 255, 383, 384, 385, 511, 512, 513, 640, 2]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    Y = np.concatenate([synth.rpy_throughput_inputs(n, seed=40 + i)[0] for i, n in enumerate(sizes)])
+    F, T = rng.standard_normal((off[-1], 3)), rng.standard_normal((off[-1], 3))
+    plan = fil.RpyBatch(off, prec)
+    V, W = plan.apply(dev(Y), dev(F), dev(T), 1.0, 1.0)
+    V, W = host(V), host(W)
+    plan.close()
+    tol = F64_TOL if prec == "f64" else F32_TOL
+    for i in range(len(sizes)):
+        a, b = off[i], off[i + 1]
+        V0, W0 = oracle.rpy_apply(Y[a:b], F[a:b], T[a:b], 1.0, 1.0, nthreads=8)
+        ev, ew = rel_l2(V[a:b], V0), rel_l2(W[a:b], W0)
+        # the last target alone (the end of the suspension's last wave)
+        el = max(rel_l2(V[b - 1:b], V0[-1:]), rel_l2(W[b - 1:b], W0[-1:]))
+        print("suspension %d (S=%d): rel L2 V %.3e W %.3e, last target %.3e" % (i, b - a, ev, ew, el))
+        assert ev <= tol and ew <= tol and el <= 10 * tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32tile"])
 def test_rpy_batched_matches_separate_applies(prec):
     """Ragged suspensions in one persistent launch (a plan built once, applied twice): each
     suspension's velocities equal its own oracle apply (FP64 to 1e-12, FP32 tiles within the
