@@ -72,6 +72,33 @@ def test_rpy_full_size_sampled(S):
     assert rel_l2(V[idx], v0) <= F32_TOL and rel_l2(W[idx], w0) <= F32_TOL
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32tile"])
+def test_rpy_large_path_overlaps(prec):
+    """The large-size kernels (S >= 12,000: two targets per lane) and the batched items on a
+    dense cloud where many pairs overlap (mean spacing ~1.7a < 2a): sampled targets against
+    the oracle, so the overlap branch of those kernel forms is exercised."""
+    import paper_1903_12609_amd as fil
+    S = 12288
+    rng = np.random.default_rng(31)
+    Y = rng.uniform(0.0, 40.0, (S, 3))
+    F, T = rng.standard_normal((S, 3)), rng.standard_normal((S, 3))
+    idx = np.unique(np.concatenate([[0, 1, S // 2, S - 1], rng.integers(0, S, 60)]))
+    v0, w0 = oracle.rpy_apply_targets(Y, F, T, 1.0, 1.0, idx, nthreads=8)
+    tol = F64_TOL if prec == "f64" else F32_TOL
+    V, W = _apply(Y, F, T, prec)
+    ev, ew = rel_l2(V[idx], v0), rel_l2(W[idx], w0)
+    print("%s stand-alone sampled rel L2 V %.3e W %.3e" % (prec, ev, ew))
+    assert ev <= tol and ew <= tol
+    off = np.array([0, S], dtype=np.int64)
+    plan = fil.RpyBatch(off, prec)
+    Vb, Wb = plan.apply(dev(Y), dev(F), dev(T), 1.0, 1.0)
+    Vb, Wb = host(Vb), host(Wb)
+    plan.close()
+    ev, ew = rel_l2(Vb[idx], v0), rel_l2(Wb[idx], w0)
+    print("%s batched sampled rel L2 V %.3e W %.3e" % (prec, ev, ew))
+    assert ev <= tol and ew <= tol
+
+
 def test_rpy_deterministic_and_empty():
     import torch
     import paper_1903_12609_amd as fil
