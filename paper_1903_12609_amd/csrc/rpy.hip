@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(kRpyBlock) __attribute__((amdgpu_waves_per_eu(
 //   R  += s^3 F
 //   P  += s^3 T
 //   W  += s^5 (r.T) r - 2/3 s^3 (F x s_p)
-// (41 VALU operations per pair, r included; T x s_p and 2/3 F x s_p are stored in the
+// (40 VALU operations per pair, r included; T x s_p and 2/3 F x s_p are stored in the
 // source record).  Once per tile the target's (V, Omega) / c take
 //   v = V + 2a^2/3 R + P x y_t,   w = R x y_t + 3/2 W - 1/2 P,
 // which is s F + 2a^2/3 s^3 F + (1 - 2a^2 s^2)(r.F) s^3 r + s^3 T x r for v and
@@ -410,8 +410,9 @@ __device__ __forceinline__ void rpy_pair_f32(float rx, float ry, float rz, const
     const float Fx = s.f[0], Fy = s.f[1], Fz = s.f[2], Tx = s.t[0], Ty = s.t[1], Tz = s.t[2];
     const float rF = fmaf(rx, Fx, fmaf(ry, Fy, rz * Fz));
     const float rT = fmaf(rx, Tx, fmaf(ry, Ty, rz * Tz));
-    const float Bs3 = fmaf(-two_a2, s2, 1.f) * rF * s3;  // (1 - 2a^2 s^2)(r.F) s^3
-    const float Ds5 = s2 * s3 * rT;                       // s^5 (r.T)
+    const float s5 = s2 * s3;
+    const float Bs3 = fmaf(-two_a2, s5, s3) * rF;  // (1 - 2a^2 s^2)(r.F) s^3
+    const float Ds5 = s5 * rT;                      // s^5 (r.T)
     A.V[0] = fmaf(sv, Fx, fmaf(Bs3, rx, fmaf(-s3, s.ct[0], A.V[0])));
     A.V[1] = fmaf(sv, Fy, fmaf(Bs3, ry, fmaf(-s3, s.ct[1], A.V[1])));
     A.V[2] = fmaf(sv, Fz, fmaf(Bs3, rz, fmaf(-s3, s.ct[2], A.V[2])));
